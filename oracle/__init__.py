@@ -1,0 +1,418 @@
+"""FP64 CPU oracle of the adaptive probe-update path (ctypes wrapper).
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package. It shares no code with
+the GPU library ``paper_2301_05125_amd``; the two meet only on the seeded
+inputs of ``scenes``.
+
+The arithmetic lives in ``adgi_oracle.c`` (plain C, double precision, OpenMP
+over rays/probes); this module only marshals numpy arrays and sequences the
+per-frame steps in the order of the paper's frame: pilot rays and change
+detection (Sec. 4.1-4.4), the ray budget, then trace + shade + moving-average
+update of each probe's texels (Alg. ApproxAlgo, Alg. MovingAvgUpdate).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "adgi_oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Tol(C.Structure):
+    _fields_ = [("hit_rel", C.c_double), ("edge_rel", C.c_double), ("edge_abs", C.c_double),
+                ("graze", C.c_double), ("bin_eps", C.c_double), ("q10_rel", C.c_double),
+                ("q10_abs", C.c_double), ("cos_eps", C.c_double)]
+
+
+class Hit(C.Structure):
+    _fields_ = [("t", C.c_double), ("tri", C.c_int32), ("front", C.c_int32), ("tie", C.c_int32)]
+
+
+class Ray(C.Structure):
+    _fields_ = [("rgb", C.c_double * 3), ("t", C.c_double), ("tri", C.c_int32),
+                ("front", C.c_int32), ("shadow", C.c_uint8), ("hit_tie", C.c_int32),
+                ("shadow_tie", C.c_int32)]
+
+
+class Counts(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "hit_ties", "shadow_ties", "bin_ties", "q10_ties",
+        "hit_mismatch", "shadow_mismatch", "bin_mismatch", "q10_mismatch",
+        "rays", "shadow_rays")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class Grid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+                ("dims", C.c_int32 * 3), ("s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        d3 = C.POINTER(C.c_double)
+        L.orc_splitmix64.restype = C.c_uint64
+        L.orc_splitmix64.argtypes = [C.c_uint64]
+        L.orc_key.restype = C.c_uint64
+        L.orc_key.argtypes = [C.c_uint64] * 5
+        L.orc_uniform.restype = C.c_double
+        L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_frame_rotation.argtypes = [C.c_uint64, C.c_int32, P]
+        L.orc_sf_dir.argtypes = [C.c_int32, C.c_int32, P, P]
+        L.orc_pilot_dir.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, P]
+        L.orc_oct_encode.argtypes = [P, P]
+        L.orc_oct_decode.argtypes = [P, P]
+        L.orc_oct_bin.restype = C.c_int32
+        L.orc_oct_bin.argtypes = [P, C.c_int32, C.c_double, P]
+        L.orc_border_source.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.orc_fold_tile.argtypes = [P, C.c_int32, C.c_int32, P]
+        L.orc_default_tol.argtypes = [P]
+        L.orc_scene_new.restype = P
+        L.orc_scene_new.argtypes = [C.c_int32, P, C.c_int32, P, P, C.c_int32]
+        L.orc_scene_free.argtypes = [P]
+        L.orc_scene_set_positions.argtypes = [P, P]
+        L.orc_scene_set_lights.argtypes = [P, C.c_int32, P, P, P]
+        L.orc_scene_bvh_depth.restype = C.c_int32
+        L.orc_scene_bvh_depth.argtypes = [P]
+        L.orc_closest_hit.argtypes = [P, P, P, P, P]
+        L.orc_closest_hit_brute.argtypes = [P, P, P, P, P]
+        L.orc_occluded.restype = C.c_int32
+        L.orc_occluded.argtypes = [P, P, P, C.c_double, P, P]
+        L.orc_shade_ray.argtypes = [P, P, P, C.c_double, P, C.c_int32, C.c_int32, P, P, P]
+        L.orc_grid_init.argtypes = [P, P, P, P]
+        L.orc_probe_pos.argtypes = [P, C.c_int32, P]
+        L.orc_pilots.argtypes = [P, P, C.c_uint64, C.c_int32, C.c_double, P, P, P, P, P, P]
+        L.orc_detect.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_allocate.restype = C.c_int32
+        L.orc_allocate.argtypes = [C.c_int32, P, C.c_int64, C.c_int32, C.c_int32, P, P, P]
+        L.orc_probe_frame.argtypes = [P, P, C.c_int32, C.c_int32, P, P, C.c_int32, C.c_int32,
+                                      C.c_double, C.c_double, C.c_int32] + [P] * 14
+        L.orc_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32,
+                                       C.c_double, C.c_double, C.c_int32] + [P] * 14
+        L.orc_blend_alpha.restype = C.c_double
+        L.orc_blend_alpha.argtypes = [C.c_int32, C.c_double]
+        L.orc_round_half.restype = C.c_double
+        L.orc_round_half.argtypes = [C.c_double]
+        L.orc_num_threads.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"], "arrays passed to the oracle must be contiguous"
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def default_tol() -> Tol:
+    t = Tol()
+    lib().orc_default_tol(C.byref(t))
+    return t
+
+
+# ------------------------------------------------------------ primitives
+
+def splitmix64(x: int) -> int:
+    return lib().orc_splitmix64(x & 0xFFFFFFFFFFFFFFFF)
+
+
+def frame_rotation(seed: int, frame: int) -> np.ndarray:
+    R = np.zeros(9, np.float32)
+    lib().orc_frame_rotation(seed & 0xFFFFFFFFFFFFFFFF, frame, _p(R))
+    return R.reshape(3, 3)
+
+
+def sf_dirs(n: int, R: np.ndarray) -> np.ndarray:
+    R = np.ascontiguousarray(R, np.float32).reshape(9)
+    out = np.zeros((n, 3))
+    d = np.zeros(3)
+    for j in range(n):
+        lib().orc_sf_dir(j, n, _p(R), _p(d))
+        out[j] = d
+    return out
+
+
+def pilot_dir(seed: int, probe: int, k: int, pair: int) -> np.ndarray:
+    d = np.zeros(3)
+    lib().orc_pilot_dir(seed & 0xFFFFFFFFFFFFFFFF, probe, k, pair, _p(d))
+    return d
+
+
+def oct_encode(d) -> np.ndarray:
+    d = np.ascontiguousarray(d, np.float64)
+    uv = np.zeros(2)
+    lib().orc_oct_encode(_p(d), _p(uv))
+    return uv
+
+
+def oct_decode(uv) -> np.ndarray:
+    uv = np.ascontiguousarray(uv, np.float64)
+    d = np.zeros(3)
+    lib().orc_oct_decode(_p(uv), _p(d))
+    return d
+
+
+def oct_bin(d, r: int, eps: float = 0.0):
+    d = np.ascontiguousarray(d, np.float64)
+    tie = C.c_int32(0)
+    k = lib().orc_oct_bin(_p(d), r, eps, C.byref(tie))
+    return int(k), bool(tie.value)
+
+
+def border_source(X: int, Y: int, r: int):
+    sx, sy = C.c_int32(), C.c_int32()
+    lib().orc_border_source(X, Y, r, C.byref(sx), C.byref(sy))
+    return sx.value, sy.value
+
+
+def fold_tile(interior: np.ndarray, r: int, c: int) -> np.ndarray:
+    interior = np.ascontiguousarray(interior, np.float64)
+    tile = np.zeros(((r + 2) * (r + 2) * c,))
+    lib().orc_fold_tile(_p(interior), r, c, _p(tile))
+    return tile.reshape(r + 2, r + 2, c)
+
+
+def blend_alpha(n: int, h: float) -> float:
+    return lib().orc_blend_alpha(n, h)
+
+
+def round_half(x: float) -> float:
+    return lib().orc_round_half(x)
+
+
+def allocate(score: np.ndarray, budget: int, n_min: int, n_max: int):
+    """Integer budget allocation. Returns (n[P] int32, offsets[P+1] int64, lambda*)."""
+    score = np.ascontiguousarray(score, np.int64)
+    P = score.shape[0]
+    n = np.zeros(P, np.int32)
+    off = np.zeros(P + 1, np.int64)
+    lam = C.c_uint32(0)
+    rc = lib().orc_allocate(P, _p(score), int(budget), n_min, n_max, _p(n), _p(off), C.byref(lam))
+    if rc != 0:
+        raise ValueError("budget below P * n_min or bad bounds")
+    return n, off, int(lam.value)
+
+
+class OracleScene:
+    """Triangles + lights in FP64 with the oracle's own BVH (or brute force)."""
+
+    def __init__(self, positions, indices, albedo, use_bvh: bool = True):
+        self.positions = np.ascontiguousarray(positions, np.float32)
+        self.indices = np.ascontiguousarray(indices, np.int32)
+        self.albedo = np.ascontiguousarray(albedo, np.float32)
+        self.ptr = lib().orc_scene_new(self.positions.shape[0], _p(self.positions),
+                                       self.indices.shape[0], _p(self.indices), _p(self.albedo),
+                                       1 if use_bvh else 0)
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().orc_scene_free(self.ptr)
+            self.ptr = None
+
+    def set_positions(self, positions):
+        self.positions = np.ascontiguousarray(positions, np.float32)
+        lib().orc_scene_set_positions(self.ptr, _p(self.positions))
+
+    def set_lights(self, lpos, lint, sky):
+        self._lp = np.ascontiguousarray(lpos, np.float32).reshape(-1, 3)
+        self._li = np.ascontiguousarray(lint, np.float32).reshape(-1, 3)
+        self._sky = np.ascontiguousarray(sky, np.float32).reshape(3)
+        lib().orc_scene_set_lights(self.ptr, self._lp.shape[0], _p(self._lp), _p(self._li),
+                                   _p(self._sky))
+
+    @property
+    def bvh_depth(self) -> int:
+        return lib().orc_scene_bvh_depth(self.ptr)
+
+    def closest_hit(self, o, d, tol: Optional[Tol] = None, brute: bool = False) -> Hit:
+        o = np.ascontiguousarray(o, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        h = Hit()
+        fn = lib().orc_closest_hit_brute if brute else lib().orc_closest_hit
+        fn(self.ptr, _p(o), _p(d), C.byref(tol) if tol is not None else None, C.byref(h))
+        return h
+
+    def occluded(self, o, d, tmax: float, tol: Optional[Tol] = None):
+        o = np.ascontiguousarray(o, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        tie = C.c_int32(0)
+        r = lib().orc_occluded(self.ptr, _p(o), _p(d), tmax,
+                               C.byref(tol) if tol is not None else None, C.byref(tie))
+        return bool(r), bool(tie.value)
+
+    def shade(self, o, d, spacing_diag: float, tol: Optional[Tol] = None) -> Ray:
+        o = np.ascontiguousarray(o, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        r = Ray()
+        lib().orc_shade_ray(self.ptr, _p(o), _p(d), spacing_diag,
+                            C.byref(tol) if tol is not None else None, -2, -1, C.byref(r),
+                            None, None)
+        return r
+
+
+def make_grid(origin, spacing, dims) -> Grid:
+    g = Grid()
+    o = np.ascontiguousarray(origin, np.float32)
+    s = np.ascontiguousarray(spacing, np.float32)
+    d = np.ascontiguousarray(dims, np.int32)
+    lib().orc_grid_init(C.byref(g), _p(o), _p(s), _p(d))
+    return g
+
+
+TAU_MAX = (math.exp(5.0) - 1.0) / 15.0
+
+
+class OracleVolume:
+    """The per-frame probe update in FP64, state kept for a set of probes.
+
+    ``probes`` selects which probes' texels are tracked (all by default);
+    detection and allocation always cover the whole grid because the budget
+    couples every probe.
+    """
+
+    def __init__(self, scene, irr_res: int = 8, depth_res: int = 16,
+                 hysteresis: float = 0.97, tau_max: float = TAU_MAX, seed: int = 1,
+                 fp16: bool = False, probes: Optional[np.ndarray] = None,
+                 use_bvh: bool = True, tol: Optional[Tol] = None):
+        self.sc = scene
+        self.scene = OracleScene(scene.positions, scene.indices, scene.albedo, use_bvh=use_bvh)
+        self.grid = make_grid(scene.grid_origin, scene.grid_spacing, scene.grid_dims)
+        self.P = int(np.prod(scene.grid_dims.astype(np.int64)))
+        self.irr_res, self.depth_res = irr_res, depth_res
+        # parameters arrive as FP32 and are promoted
+        self.h = float(np.float32(hysteresis))
+        self.tau_max = float(np.float32(tau_max))
+        self.seed = seed
+        self.fp16 = bool(fp16)
+        self.tol = tol if tol is not None else default_tol()
+        self.probes = (np.arange(self.P, dtype=np.int32) if probes is None
+                       else np.ascontiguousarray(probes, np.int32))
+        nq = self.probes.shape[0]
+        ri, rd = irr_res - 2, depth_res - 2
+        self.irr = np.zeros((nq, ri * ri * 3))
+        self.irr_n = np.zeros((nq, ri * ri), np.uint8)
+        self.dep = np.zeros((nq, rd * rd * 2))
+        self.dep_n = np.zeros((nq, rd * rd), np.uint8)
+        self.qv_prev = np.zeros(self.P * 8, np.uint16)
+        self.qr_prev = np.zeros(self.P * 8, np.uint16)
+        self.tv = np.zeros(self.P * 8, np.int32)
+        self.tr = np.zeros(self.P * 8, np.int32)
+        self.score = np.zeros(self.P, np.int64)
+        self.counts = Counts()
+
+    def set_frame_inputs(self, frame: int):
+        sc = self.sc
+        if sc.anim_vertices and frame > 0:
+            self.scene.set_positions(sc.positions_at(frame))
+        self.scene.set_lights(sc.light_positions(frame), sc.light_intensity, sc.sky)
+
+    def pilots(self, frame: int, beta: float = 5.0, hint_qv=None, hint_qr=None):
+        qv = np.zeros(self.P * 8, np.uint16)
+        qr = np.zeros(self.P * 8, np.uint16)
+        lib().orc_pilots(self.scene.ptr, C.byref(self.grid), self.seed & 0xFFFFFFFFFFFFFFFF,
+                         frame, float(np.float32(beta)), C.byref(self.tol),
+                         _p(hint_qv), _p(hint_qr), _p(qv), _p(qr), C.byref(self.counts))
+        return qv, qr
+
+    def detect(self, frame: int, qv, qr, theta: int = 8, mu: int = 2):
+        lib().orc_detect(C.byref(self.grid), frame, theta, mu, _p(qv), _p(qr),
+                         _p(self.qv_prev), _p(self.qr_prev), _p(self.tv), _p(self.tr),
+                         _p(self.score))
+        return self.score.copy()
+
+    def update(self, frame: int, adaptive: bool, budget: int = 0, n_min: int = 8,
+               n_max: int = 2048, n_uniform: int = 64, beta: float = 5.0, mu: int = 2,
+               theta: int = 8, hints: Optional[dict] = None, keep_rays: bool = False) -> dict:
+        """One frame. ``hints`` holds the GPU's discrete decisions (lockstep)."""
+        hints = hints or {}
+        self.set_frame_inputs(frame)
+        out = {}
+        if adaptive:
+            qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"))
+            score = self.detect(frame, qv, qr, theta, mu)
+            n, off, lam = allocate(score, budget, n_min, n_max)
+            out.update(qv=qv, qr=qr, score=score, lam=lam)
+        else:
+            n = np.full(self.P, n_uniform, np.int32)
+            off = np.concatenate([[0], np.cumsum(n, dtype=np.int64)])
+        out.update(n=n, offsets=off)
+        R = frame_rotation(self.seed, frame)
+        out["R"] = R
+        Rf = np.ascontiguousarray(R.reshape(9), np.float32)
+        nq = self.probes.shape[0]
+        n_sel = np.ascontiguousarray(n[self.probes], np.int32)
+        base_global = off[self.probes]
+        # outputs and hints are addressed in a compact per-subset ray space
+        local_base = np.concatenate([[0], np.cumsum(n_sel, dtype=np.int64)])
+        total = int(local_base[-1])
+        ray_base = np.ascontiguousarray(local_base[:-1], np.int64)
+
+        def gather(name, dtype):
+            a = hints.get(name)
+            if a is None:
+                return None
+            a = np.asarray(a)
+            idx = np.concatenate([np.arange(b, b + k, dtype=np.int64)
+                                  for b, k in zip(base_global, n_sel)]) if total else np.zeros(0, np.int64)
+            return np.ascontiguousarray(a[idx], dtype)
+
+        h_tri = gather("hit_tri", np.int32)
+        h_sh = gather("shadow_bits", np.uint8)
+        h_ib = gather("irr_bin", np.uint16)
+        h_db = gather("depth_bin", np.uint16)
+        rays = np.zeros((max(total, 1), 4)) if keep_rays else None
+        tri = np.zeros(max(total, 1), np.int32) if keep_rays else None
+        sh = np.zeros(max(total, 1), np.uint8) if keep_rays else None
+        ib = np.zeros(max(total, 1), np.uint16) if keep_rays else None
+        db = np.zeros(max(total, 1), np.uint16) if keep_rays else None
+        cnt = Counts()
+        lib().orc_probes_frame(
+            self.scene.ptr, C.byref(self.grid), nq, _p(self.probes), _p(n_sel), _p(ray_base),
+            _p(Rf), C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
+            1 if self.fp16 else 0, _p(h_tri), _p(h_sh), _p(h_ib), _p(h_db),
+            _p(self.irr), _p(self.irr_n), _p(self.dep), _p(self.dep_n),
+            _p(rays), _p(tri), _p(sh), _p(ib), _p(db), C.byref(cnt))
+        for name, _ in Counts._fields_:
+            setattr(self.counts, name, getattr(self.counts, name) + getattr(cnt, name))
+        out["counts"] = cnt.as_dict()
+        if keep_rays:
+            out.update(rays=rays[:total], tri=tri[:total], shadow=sh[:total], irr_bin=ib[:total],
+                       depth_bin=db[:total], ray_base=ray_base)
+        return out
+
+    # views in the library's readback layout
+    def irradiance_tiles(self) -> np.ndarray:
+        ri = self.irr_res - 2
+        return np.stack([fold_tile(t, ri, 3) for t in self.irr])
+
+    def depth_tiles(self) -> np.ndarray:
+        rd = self.depth_res - 2
+        return np.stack([fold_tile(t, rd, 2) for t in self.dep])

@@ -1,0 +1,177 @@
+/* adgi_oracle.h - FP64 CPU oracle for the adaptive probe-update path.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. It shares no code,
+ * header, table or constant generator with the GPU library; the two are
+ * written independently from the paper and meet only on the seeded inputs.
+ *
+ * The oracle is the method's steps written out plainly in double precision:
+ *   - octahedral direction map and its border fold,
+ *   - counter-based random numbers, per-frame rotation, spherical Fibonacci
+ *     ray sets and octant-stratified pilot directions,
+ *   - closest-hit and any-hit queries (Moller-Trumbore, brute force or a
+ *     median-split BVH of its own),
+ *   - direct-light shading with shadow rays,
+ *   - change detection (probe visibility f_v = exp(-2t/s), eq. ProbeVis;
+ *     incoming radiance f_r = min(r, beta)/beta, Sec. 4.1.3; temporal
+ *     gradients, eq. tempGradVis / tempGradIrr; temporal trigger and 5x5x5
+ *     spatial sum, Sec. 4.1.4-4.1.5; dynamic composition, eq. priorDynamic),
+ *   - integer ray-budget allocation,
+ *   - the per-sample moving average of Alg. MovingAvgUpdate applied to the
+ *     texel containing each sample (Alg. ApproxAlgo).
+ *
+ * Ties: where FP32 (GPU) and FP64 (oracle) arithmetic can legitimately take
+ * different discrete decisions (which triangle is hit, whether a shadow ray
+ * is blocked, which texel a direction falls in, which 10-bit code a value
+ * quantises to), the oracle flags the decision as a tie. Callers may pass
+ * the GPU's decisions as hints; on a tie the oracle adopts the hint and
+ * counts it, and a differing hint that is not a tie counts as a mismatch.
+ */
+#ifndef ADGI_ORACLE_H
+#define ADGI_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- counter-based random numbers (splitmix64, Steele, Lea & Flood 2014) */
+uint64_t orc_splitmix64(uint64_t x);
+uint64_t orc_key(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t c);
+double   orc_uniform(uint64_t key, uint64_t q);   /* top 24 bits of mix(key^q) * 2^-24 */
+#define ORC_TAG_ROTATION 0x524F54ull  /* "ROT" */
+#define ORC_TAG_PILOT    0x50494Cull  /* "PIL" */
+
+/* Per-frame rotation (Shoemake, Graphics Gems III 1992), FP64 -> FP32. */
+void orc_frame_rotation(uint64_t seed, int32_t frame, float R[9]);
+/* Spherical Fibonacci direction j of n, rotated by R (FP64). */
+void orc_sf_dir(int32_t j, int32_t n, const float R[9], double d[3]);
+/* Pilot direction: probe, octant k (bit0 -x, bit1 -y, bit2 -z), pair m. */
+void orc_pilot_dir(uint64_t seed, int32_t probe, int32_t k, int32_t pair, double d[3]);
+
+/* ---- octahedral map (Cigolle et al. 2014) */
+void orc_oct_encode(const double d[3], double uv[2]);
+void orc_oct_decode(const double uv[2], double d[3]);
+/* interior bin k = iy*r + ix; *tie set when a cell edge is within eps */
+int32_t orc_oct_bin(const double d[3], int32_t r, double eps, int32_t* tie);
+/* source interior coordinate (1..r) of tile coordinate (X,Y) in 0..r+1 */
+void orc_border_source(int32_t X, int32_t Y, int32_t r, int32_t* sx, int32_t* sy);
+/* interior [r*r*c] -> full tile [(r+2)*(r+2)*c] with border fold */
+void orc_fold_tile(const double* interior, int32_t r, int32_t c, double* tile);
+
+/* ---- tolerances that define ties */
+typedef struct {
+  double hit_rel;     /* another surface within hit_rel*t of the closest hit   */
+  double edge_rel;    /* world margin = edge_abs + edge_rel*(|o|_inf + t + |v|) */
+  double edge_abs;
+  double graze;       /* |cos(ray, plane normal)| below this is a tie          */
+  double bin_eps;     /* bin coordinate within bin_eps of a cell edge          */
+  double q10_rel;     /* code coordinate within q10_abs + q10_rel*x*1024 ...   */
+  double q10_abs;
+  double cos_eps;     /* light cosine within cos_eps of 0                       */
+} orc_tol;
+void orc_default_tol(orc_tol* tol);
+
+/* ---- scene */
+typedef struct orc_scene orc_scene;
+orc_scene* orc_scene_new(int32_t nv, const float* pos, int32_t nt, const int32_t* idx,
+                         const float* albedo, int32_t use_bvh);
+void orc_scene_free(orc_scene* s);
+void orc_scene_set_positions(orc_scene* s, const float* pos);  /* rebuilds the BVH */
+void orc_scene_set_lights(orc_scene* s, int32_t nl, const float* lpos, const float* lint,
+                          const float sky[3]);
+int32_t orc_scene_bvh_depth(const orc_scene* s);
+
+typedef struct {
+  double t;        /* hit distance, INFINITY on a miss */
+  int32_t tri;     /* -1 on a miss */
+  int32_t front;   /* 1 if (v1-v0)x(v2-v0) . d < 0 */
+  int32_t tie;     /* decision is within the tie tolerance */
+} orc_hit;
+
+/* exact closest hit: brute force over all triangles, or the oracle's BVH */
+void orc_closest_hit(const orc_scene* s, const double o[3], const double d[3],
+                     const orc_tol* tol, orc_hit* out);
+void orc_closest_hit_brute(const orc_scene* s, const double o[3], const double d[3],
+                           const orc_tol* tol, orc_hit* out);
+/* any hit on (0, tmax); *tie set when ambiguous */
+int32_t orc_occluded(const orc_scene* s, const double o[3], const double d[3], double tmax,
+                     const orc_tol* tol, int32_t* tie);
+
+/* ---- one probe ray: trace + shade (O3, O4) */
+typedef struct {
+  double rgb[3];
+  double t;
+  int32_t tri;
+  int32_t front;
+  uint8_t shadow;       /* bit l: light l lit the hit point (cos > 0 and unblocked) */
+  int32_t hit_tie, shadow_tie;
+} orc_ray;
+/* hint_tri: GPU hit triangle or -2 for none; hint_shadow: GPU light bits */
+void orc_shade_ray(const orc_scene* s, const double o[3], const double d[3], double spacing_diag,
+                   const orc_tol* tol, int32_t hint_tri, int32_t hint_shadow, orc_ray* out,
+                   int64_t* ties, int64_t* mismatches);
+
+typedef struct {
+  int64_t hit_ties, shadow_ties, bin_ties, q10_ties;
+  int64_t hit_mismatch, shadow_mismatch, bin_mismatch, q10_mismatch;
+  int64_t rays, shadow_rays;
+} orc_counts;
+
+/* ---- grid */
+typedef struct {
+  double origin[3], spacing[3];
+  int32_t dims[3];
+  double s;            /* ||spacing||_2 : voxel (cage) diagonal */
+} orc_grid;
+void orc_grid_init(orc_grid* g, const float origin[3], const float spacing[3], const int32_t dims[3]);
+void orc_probe_pos(const orc_grid* g, int32_t i, double p[3]);
+
+/* ---- detection (O5): pilots for every probe, Q10 codes with ties.
+ * hint_qv/hint_qr may be NULL; otherwise tied codes adopt the hint. */
+void orc_pilots(const orc_scene* s, const orc_grid* g, uint64_t seed, int32_t frame,
+                double beta, const orc_tol* tol, const uint16_t* hint_qv, const uint16_t* hint_qr,
+                uint16_t* qv, uint16_t* qr, orc_counts* counts);
+/* state arrays are [P*8]; score is [P]. Updates the state for frame t. */
+void orc_detect(const orc_grid* g, int32_t frame, int32_t theta, int32_t mu,
+                const uint16_t* qv, const uint16_t* qr, uint16_t* qv_prev, uint16_t* qr_prev,
+                int32_t* tv, int32_t* tr, int64_t* score);
+
+/* ---- allocation (O6). Returns 0 or -1 (budget below P*n_min). */
+int32_t orc_allocate(int32_t P, const int64_t* score, int64_t budget, int32_t n_min, int32_t n_max,
+                     int32_t* n, int64_t* offsets, uint32_t* lambda_out);
+
+/* ---- one probe's frame: trace its n rays, blend them (O2-O4, O7).
+ * irr[36*3], irr_n[36], dep[196*2], dep_n[196] are the interior state in
+ * FP64 (updated in place). Optional hints are indexed by ray j. Optional
+ * outputs: rays[n*4] (rgb, t), tri[n], shadow[n], ibin[n], dbin[n]. */
+void orc_probe_frame(const orc_scene* s, const orc_grid* g, int32_t probe, int32_t n,
+                     const float R[9], const orc_tol* tol,
+                     int32_t irr_r, int32_t dep_r, double hysteresis, double tau_max, int32_t fp16,
+                     const int32_t* hint_tri, const uint8_t* hint_shadow,
+                     const uint16_t* hint_ibin, const uint16_t* hint_dbin,
+                     double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
+                     double* rays, int32_t* tri, uint8_t* shadow, uint16_t* ibin, uint16_t* dbin,
+                     orc_counts* counts);
+/* many probes in parallel (OpenMP); state arrays indexed by position in list;
+ * hints/outputs indexed by ray offset ray_base[q] + j */
+void orc_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
+                      const int32_t* n, const int64_t* ray_base, const float R[9], const orc_tol* tol,
+                      int32_t irr_r, int32_t dep_r, double hysteresis, double tau_max, int32_t fp16,
+                      const int32_t* hint_tri, const uint8_t* hint_shadow,
+                      const uint16_t* hint_ibin, const uint16_t* hint_dbin,
+                      double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
+                      double* rays, int32_t* tri, uint8_t* shadow, uint16_t* ibin, uint16_t* dbin,
+                      orc_counts* counts);
+
+/* single moving-average step of Alg. MovingAvgUpdate with real N_max */
+double orc_blend_alpha(int32_t n, double hysteresis);
+/* binary16 round-to-nearest-even of a double */
+double orc_round_half(double x);
+
+int32_t orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,647 @@
+"""Pins of the FP64 oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle against a closed form, a published test vector,
+a number printed in the paper, brute force on tiny inputs, or an invariant of
+the mathematics, chosen so that a plausible slip (a dropped term, a wrong
+sign or index, a transposed operand) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+G64 = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# --------------------------------------------------------------- O2: RNG
+
+def test_splitmix64_published_vectors():
+    for seed, k, out in _read_golden("splitmix64.txt"):
+        state = (int(seed) + int(k) * G64) & M64
+        assert oracle.splitmix64(state) == int(out)
+
+
+def test_uniforms_are_24_bit_and_in_range():
+    L = oracle.lib()
+    for k in range(200):
+        key = L.orc_key(1, 2, k, 3, 4)
+        u = L.orc_uniform(key, 1)
+        assert 0.0 <= u < 1.0
+        assert (u * 2 ** 24) == int(u * 2 ** 24)
+
+
+# ----------------------------------------------------- O2: rotations, SF
+
+def test_frame_rotation_is_orthonormal_fp32():
+    for t in range(50):
+        R = oracle.frame_rotation(12345, t).astype(np.float64)
+        assert np.abs(R.T @ R - np.eye(3)).max() < 1e-6
+        assert abs(np.linalg.det(R) - 1.0) < 1e-6
+    # distinct frames give distinct rotations
+    assert not np.array_equal(oracle.frame_rotation(1, 0), oracle.frame_rotation(1, 1))
+
+
+def test_frame_rotation_uniform_on_so3():
+    # For a Haar-random rotation E[R] = 0 and E[trace R] = 0.
+    Rs = np.stack([oracle.frame_rotation(99, t).astype(np.float64) for t in range(4000)])
+    assert np.abs(Rs.mean(axis=0)).max() < 0.05
+    assert abs(np.trace(Rs, axis1=1, axis2=2).mean()) < 0.1
+
+
+@pytest.mark.parametrize("n", [8, 64, 257, 1024])
+def test_spherical_fibonacci_properties(n):
+    I = np.eye(3, dtype=np.float32)
+    d = oracle.sf_dirs(n, I)
+    # z_j = 1 - (2j+1)/n exactly (identity rotation)
+    j = np.arange(n)
+    assert np.array_equal(d[:, 2], 1.0 - (2.0 * j + 1.0) / n)
+    assert np.abs(np.linalg.norm(d, axis=1) - 1.0).max() < 1e-15
+    # near-uniform: the mean direction is O(1/n)
+    assert np.linalg.norm(d.mean(axis=0)) < 2.0 / n
+    # equal-area in z (Archimedes): each z-band of the sphere holds its share
+    counts, _ = np.histogram(d[:, 2], bins=4, range=(-1, 1))
+    assert np.all(np.abs(counts - n / 4) <= 1)
+    # golden-angle azimuth: successive points differ by 2*pi*(1 - 1/phi)
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    dphi = np.mod(phi[1:] - phi[:-1], 2 * np.pi)
+    golden = 2 * np.pi * (2 - (1 + 5 ** 0.5) / 2)
+    assert np.allclose(np.minimum(dphi, 2 * np.pi - dphi), golden, atol=1e-9)
+
+
+def test_sf_rotation_applies_matrix():
+    R = oracle.frame_rotation(5, 3)
+    d0 = oracle.sf_dirs(33, np.eye(3, dtype=np.float32))
+    d1 = oracle.sf_dirs(33, R)
+    assert np.abs(d1 - d0 @ R.astype(np.float64).T).max() < 1e-14
+
+
+def test_pilot_directions_in_octant_and_pair_stable():
+    for probe in range(20):
+        for k in range(8):
+            for pair in range(3):
+                d = oracle.pilot_dir(7, probe, k, pair)
+                assert abs(np.linalg.norm(d) - 1.0) < 1e-12
+                sx = -1 if k & 1 else 1
+                sy = -1 if k & 2 else 1
+                sz = -1 if k & 4 else 1
+                assert d[0] * sx >= 0 and d[1] * sy >= 0 and d[2] * sz >= 0
+            # same pair -> same direction; the frame index only enters via pair
+    assert np.array_equal(oracle.pilot_dir(7, 3, 2, 5), oracle.pilot_dir(7, 3, 2, 5))
+    assert not np.array_equal(oracle.pilot_dir(7, 3, 2, 5), oracle.pilot_dir(7, 3, 2, 6))
+
+
+def test_pilot_directions_uniform_within_octant():
+    # Folded uniform sphere points: each |component| has mean 1/2.
+    ds = np.array([np.abs(oracle.pilot_dir(11, p, 0, 0)) for p in range(6000)])
+    assert np.abs(ds.mean(axis=0) - 0.5).max() < 0.02
+
+
+# -------------------------------------------------------- O1: octahedral
+
+def test_octahedral_axes_closed_form():
+    cases = {(1, 0, 0): (1, 0), (-1, 0, 0): (-1, 0), (0, 1, 0): (0, 1), (0, -1, 0): (0, -1),
+             (0, 0, 1): (0, 0)}
+    for d, uv in cases.items():
+        assert np.allclose(oracle.oct_encode(np.array(d, float)), uv, atol=1e-15)
+    # the south pole sits at the four corners
+    assert np.allclose(np.abs(oracle.oct_encode(np.array([0.0, 0.0, -1.0]))), [1, 1])
+    for c in [(1, 1), (-1, 1), (1, -1), (-1, -1)]:
+        assert np.allclose(oracle.oct_decode(np.array(c, float)), [0, 0, -1], atol=1e-15)
+
+
+def test_octahedral_round_trip():
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(20000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    for v in d:
+        uv = oracle.oct_encode(v)
+        assert abs(uv[0]) <= 1 and abs(uv[1]) <= 1
+        if v[2] >= 0:
+            assert abs(uv[0]) + abs(uv[1]) <= 1 + 1e-15
+        assert np.abs(oracle.oct_decode(uv) - v).max() < 1e-15
+
+
+@pytest.mark.parametrize("r", [6, 14])
+def test_octahedral_bins_centres_and_coverage(r):
+    # decode(centre of texel k) falls in texel k; encode(decode(centre)) = centre
+    for iy in range(r):
+        for ix in range(r):
+            c = np.array([(ix + 0.5) / r * 2 - 1, (iy + 0.5) / r * 2 - 1])
+            d = oracle.oct_decode(c)
+            assert np.abs(oracle.oct_encode(d) - c).max() < 1e-14
+            k, tie = oracle.oct_bin(d, r, 1e-6)
+            assert k == iy * r + ix and not tie
+    # every texel receives directions; solid angles of cells add up to 4*pi
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=(60000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    ks = np.array([oracle.oct_bin(v, r)[0] for v in d])
+    cnt = np.bincount(ks, minlength=r * r)
+    assert cnt.shape[0] == r * r and cnt.min() > 0
+    # the map is not equal-area: cell solid angles vary (about 1.85x at 6x6)
+    ratio = cnt.max() / cnt.min()
+    assert 1.3 < ratio < 6.0
+
+
+def test_octahedral_edge_identification():
+    # (u,+-1) ~ (-u,+-1) and (+-1,v) ~ (+-1,-v) decode to the same direction
+    for u in np.linspace(-1, 1, 41):
+        for s in (-1.0, 1.0):
+            assert np.abs(oracle.oct_decode([u, s]) - oracle.oct_decode([-u, s])).max() < 1e-15
+            assert np.abs(oracle.oct_decode([s, u]) - oracle.oct_decode([s, -u])).max() < 1e-15
+
+
+@pytest.mark.parametrize("r", [6, 14])
+def test_border_fold_is_edge_mirror(r):
+    """The source of a border texel is the mirror image, across the map edge,
+    of the interior texel next to the border: the direction of the source's
+    centre equals the adjacent texel's with x negated (top/bottom edge, which
+    maps to the plane x = 0), y negated (left/right, plane y = 0) or both
+    (corners, the south pole)."""
+    def centre_dir(X, Y):
+        return oracle.oct_decode([(X - 0.5) / r * 2 - 1, (Y - 0.5) / r * 2 - 1])
+    w = r + 2
+    for Y in range(w):
+        for X in range(w):
+            bx, by = X in (0, r + 1), Y in (0, r + 1)
+            if not (bx or by):
+                continue
+            sx, sy = oracle.border_source(X, Y, r)
+            assert 1 <= sx <= r and 1 <= sy <= r
+            ax, ay = min(max(X, 1), r), min(max(Y, 1), r)  # adjacent interior texel
+            m = np.array([-1.0 if by else 1.0, -1.0 if bx else 1.0, 1.0])
+            assert np.abs(centre_dir(sx, sy) - m * centre_dir(ax, ay)).max() < 1e-14, (X, Y)
+    # fold of a tile copies interior texels unchanged
+    interior = np.arange(r * r * 2, dtype=np.float64)
+    tile = oracle.fold_tile(interior, r, 2)
+    assert np.array_equal(tile[1:r + 1, 1:r + 1].reshape(-1), interior)
+
+
+# ------------------------------------------------------ O3: intersection
+
+def _quad(x0, x1, y0, y1, z):
+    pos = np.array([[x0, y0, z], [x1, y0, z], [x1, y1, z], [x0, y1, z]], np.float32)
+    idx = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    return pos, idx
+
+
+def test_axis_aligned_exact_t():
+    pos, idx = _quad(-1, 1, -1, 1, 2.5)
+    sc = oracle.OracleScene(pos, idx, np.ones((2, 3), np.float32), use_bvh=False)
+    h = sc.closest_hit([0.25, 0.5, 0.0], [0.0, 0.0, 1.0], brute=True)
+    assert h.t == 2.5 and h.tri in (0, 1)
+    assert h.front == 0  # winding gives normal +z; ray along +z sees the back
+    h = sc.closest_hit([0.25, 0.5, 5.0], [0.0, 0.0, -1.0], brute=True)
+    assert h.t == 2.5 and h.front == 1
+    h = sc.closest_hit([3.0, 0.0, 0.0], [0.0, 0.0, 1.0], brute=True)
+    assert h.tri == -1 and math.isinf(h.t)
+
+
+def test_bvh_equals_brute_force_on_tiny_scenes():
+    rng = np.random.default_rng(3)
+    tol = oracle.default_tol()
+    for trial in range(8):
+        nt = int(rng.integers(1, 65))
+        pos = rng.uniform(-2, 2, size=(3 * nt, 3)).astype(np.float32)
+        idx = np.arange(3 * nt, dtype=np.int32).reshape(nt, 3)
+        alb = np.ones((nt, 3), np.float32)
+        bvh = oracle.OracleScene(pos, idx, alb, use_bvh=True)
+        for _ in range(300):
+            o = rng.uniform(-3, 3, 3)
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            a = bvh.closest_hit(o, d, tol)
+            b = bvh.closest_hit(o, d, tol, brute=True)
+            assert (a.tri, a.t, a.front, a.tie) == (b.tri, b.t, b.front, b.tie)
+
+
+def test_closest_hit_ties_break_to_lowest_index():
+    pos1, idx1 = _quad(-1, 1, -1, 1, 1.0)
+    pos = np.concatenate([pos1, pos1])
+    idx = np.concatenate([idx1, idx1 + 4])[[2, 0, 3, 1]]  # duplicates, shuffled
+    sc = oracle.OracleScene(pos, idx, np.ones((4, 3), np.float32), use_bvh=False)
+    h = sc.closest_hit([0.3, -0.2, 0.0], [0.0, 0.0, 1.0], oracle.default_tol())
+    assert h.t == 1.0 and h.tri == min(t for t in range(4) if True and t in (0, 1, 2, 3)
+                                        and _contains(pos, idx[t], 0.3, -0.2))
+    assert h.tie  # a second surface at the same depth is a tie
+
+
+def _contains(pos, tri, x, y):
+    a, b, c = pos[tri][:, :2].astype(np.float64)
+    def s(p, q, r):
+        return (p[0] - r[0]) * (q[1] - r[1]) - (q[0] - r[0]) * (p[1] - r[1])
+    p = np.array([x, y])
+    d1, d2, d3 = s(p, a, b), s(p, b, c), s(p, c, a)
+    return not ((d1 < 0 or d2 < 0 or d3 < 0) and (d1 > 0 or d2 > 0 or d3 > 0))
+
+
+def test_edge_and_near_miss_rays_are_ties():
+    pos, idx = _quad(-1, 1, -1, 1, 1.0)
+    sc = oracle.OracleScene(pos, idx, np.ones((2, 3), np.float32), use_bvh=False)
+    tol = oracle.default_tol()
+    # interior: no tie; on the shared diagonal: tie; just outside: tie
+    assert not sc.closest_hit([0.5, -0.3, 0.0], [0, 0, 1.0], tol).tie
+    assert sc.closest_hit([0.3, 0.3, 0.0], [0, 0, 1.0], tol).tie
+    h = sc.closest_hit([1.0 + 1e-9, 0.0, 0.0], [0, 0, 1.0], tol)
+    assert h.tri == -1 and h.tie
+    h = sc.closest_hit([1.1, 0.0, 0.0], [0, 0, 1.0], tol)
+    assert h.tri == -1 and not h.tie
+
+
+# ----------------------------------------------------------- O4: shading
+
+def test_pin1_uniform_sky_empty_scene():
+    """Uniform sky, no triangles: every sampled texel holds the sky radiance
+    exactly, depth texels hold tau_max and tau_max^2, counts = samples."""
+    sc = scenes.cornell()
+    empty = scenes.Scene(
+        name="empty", positions=np.zeros((0, 3), np.float32), indices=np.zeros((0, 3), np.int32),
+        albedo=np.zeros((0, 3), np.float32), light_a=np.zeros((0, 3), np.float32),
+        light_b=np.zeros((0, 3), np.float32), light_intensity=np.zeros((0, 3), np.float32),
+        sky=np.array([0.7, 1.3, 2.0], np.float32), grid_origin=sc.grid_origin,
+        grid_spacing=sc.grid_spacing, grid_dims=np.array([2, 2, 2], np.int32), frames=4)
+    vol = oracle.OracleVolume(empty, seed=5)
+    total = np.zeros((8, 36))
+    for f in range(3):
+        out = vol.update(f, adaptive=False, n_uniform=97, keep_rays=True)
+        for q in range(8):
+            b = out["ray_base"][q]
+            total[q] += np.bincount(out["irr_bin"][b:b + 97], minlength=36)
+    sky = np.float32([0.7, 1.3, 2.0]).astype(np.float64)
+    ri = vol.irr.reshape(8, 36, 3)
+    hit = vol.irr_n > 0
+    assert np.array_equal(vol.irr_n, np.minimum(total, 255).astype(np.uint8))
+    assert np.all(ri[hit] == sky)
+    dep = vol.dep.reshape(8, 196, 2)
+    dh = vol.dep_n > 0
+    assert np.all(dep[dh][:, 0] == vol.tau_max)
+    assert np.all(dep[dh][:, 1] == vol.tau_max ** 2)
+    # untouched texels keep their initial value 0
+    assert np.all(ri[~hit] == 0) and np.all(dep[~dh] == 0)
+
+
+def _plane_light_scene(H, rho, I, half=None):
+    half = half if half is not None else 200.0 * H
+    pos, idx = _quad(-half, half, -half, half, 0.0)  # normal +z (faces the light)
+    sc = oracle.OracleScene(pos, idx, np.full((2, 3), rho, np.float32), use_bvh=False)
+    sc.set_lights(np.array([[0.0, 0.0, H]], np.float32), np.full((1, 3), I, np.float32),
+                  np.zeros(3, np.float32))
+    return sc
+
+
+def _downward_irradiance(sc, probe, s=1.0, n_theta=96, n_phi=6):
+    # E = int L(w) cos(theta) dw over the lower hemisphere, Gauss-Legendre in
+    # cos(theta), midpoint in phi (the setup is rotationally symmetric).
+    x, w = np.polynomial.legendre.leggauss(n_theta)
+    mu = 0.5 * (x + 1.0)
+    wm = 0.5 * w
+    E = 0.0
+    for m, wt in zip(mu, wm):
+        st = math.sqrt(max(0.0, 1 - m * m))
+        acc = 0.0
+        for k in range(n_phi):
+            ph = 2 * math.pi * (k + 0.5) / n_phi
+            d = np.array([st * math.cos(ph), st * math.sin(ph), -m])
+            acc += sc.shade(probe, d, s).rgb[0]
+        E += wt * m * (acc / n_phi) * 2 * math.pi
+    return E
+
+
+@pytest.mark.parametrize("H", [1.0, 2.0])
+def test_pin2_point_light_over_plane_colocated(H):
+    """Probe at the light, plane below: E = 2 rho I / (5 H^2)."""
+    rho, I = 0.75, 3.0
+    sc = _plane_light_scene(H, rho, I)
+    E = _downward_irradiance(sc, np.array([0.0, 0.0, H]))
+    exact = 2 * float(np.float32(rho)) * I / (5 * H * H)
+    assert abs(E - exact) / exact < 1e-6
+
+
+@pytest.mark.parametrize("h", [0.5, 3.0])
+def test_pin2_point_light_over_plane_general_height(h):
+    """Probe at height h, light at H: E = rho I H h^2 int du/((u+H^2)^1.5 (u+h^2)^2)."""
+    rho, I, H = 0.5, 2.0, 1.5
+    sc = _plane_light_scene(H, rho, I, half=400.0)
+    E = _downward_irradiance(sc, np.array([0.0, 0.0, h]), n_theta=160)
+    f = lambda u: 1.0 / ((u + H * H) ** 1.5 * (u + h * h) ** 2)
+    integral, _ = integrate.quad(f, 0.0, np.inf, epsabs=0, epsrel=1e-12)
+    exact = float(np.float32(rho)) * I * H * h * h * integral
+    assert abs(E - exact) / exact < 1e-5
+
+
+def test_pin9_direct_light_one_triangle_and_blocker():
+    pos = np.array([[-5, 0, -5], [5, 0, -5], [0, 0, 5]], np.float32)  # y = 0 plane
+    idx = np.array([[0, 2, 1]], np.int32)
+    v = pos.astype(np.float64)
+    n = np.cross(v[2] - v[0], v[1] - v[0])
+    assert n[1] > 0  # normal +y
+    sc = oracle.OracleScene(pos, idx, np.array([[0.6, 0.3, 0.9]], np.float32), use_bvh=False)
+    lp = np.array([1.0, 2.0, 0.5])
+    I = np.array([2.0, 4.0, 8.0])
+    sc.set_lights(lp[None].astype(np.float32), I[None].astype(np.float32), np.zeros(3, np.float32))
+    o = np.array([0.0, 1.0, 0.0])
+    d = np.array([0.3, -1.0, 0.2])
+    d /= np.linalg.norm(d)
+    r = sc.shade(o, d, 1.0)
+    x = o + (1.0 / -d[1]) * d
+    L = lp - x
+    cos = L[1] / np.linalg.norm(L)
+    rho = np.array([0.6, 0.3, 0.9], np.float32).astype(np.float64)
+    expect = rho / math.pi * I * cos / (L @ L)
+    assert np.allclose(np.array(r.rgb), expect, rtol=1e-13, atol=0)
+    assert r.shadow == 1 and r.front == 1
+    # add a blocker between the hit point and the light
+    bpos = np.concatenate([pos, np.array([[-9, 1.5, -9], [9, 1.5, -9], [0, 1.5, 9]], np.float32)])
+    bidx = np.array([[0, 2, 1], [3, 4, 5]], np.int32)
+    sc2 = oracle.OracleScene(bpos, bidx, np.ones((2, 3), np.float32), use_bvh=False)
+    sc2.set_lights(lp[None].astype(np.float32), I[None].astype(np.float32), np.zeros(3, np.float32))
+    r2 = sc2.shade(o, d, 1.0)
+    assert r2.tri == 0 and r2.shadow == 0 and list(r2.rgb) == [0.0, 0.0, 0.0]
+    # back face: zero radiance, distance kept
+    r3 = sc.shade(np.array([0.0, -1.0, 0.0]), np.array([0.0, 1.0, 0.0]), 1.0)
+    assert r3.front == 0 and r3.t == 1.0 and list(r3.rgb) == [0.0, 0.0, 0.0]
+    # light below the surface: no contribution
+    sc.set_lights(np.array([[0.0, -2.0, 0.0]], np.float32), I[None].astype(np.float32),
+                  np.zeros(3, np.float32))
+    assert list(sc.shade(o, d, 1.0).rgb) == [0.0, 0.0, 0.0]
+
+
+# ------------------------------------------------------------- O7: blend
+
+def test_pin6_hysteresis_matches_printed_table():
+    """Alg. MovingAvgUpdate with N_max saturates at N_max/(N_max+1); the
+    paper's table prints these as 0.98 (63) and 0.91 (10). With the real-valued
+    N_max = h/(1-h), the saturated step 1-h reproduces that weight."""
+    for name, nmax, printed in _read_golden("cache_hysteresis.txt"):
+        nmax = int(nmax)
+        h = nmax / (nmax + 1.0)
+        assert round(h, 2) == float(printed)
+        # past saturation the new sample's weight is 1/(N_max+1) = 1-h
+        assert abs(oracle.blend_alpha(10 ** 6, h) - (1 - h)) < 1e-15
+        # before saturation it is the running-mean weight 1/(n+1)
+        assert oracle.blend_alpha(0, h) == 1.0
+        assert oracle.blend_alpha(nmax - 1, h) == 1.0 / nmax
+    # the prose reading (N_max-1)/N_max would print 0.90 for N_max=10, not 0.91
+    assert round(9 / 10, 2) != 0.91
+
+
+def _sky_scene(value, dims=(1, 1, 1)):
+    return scenes.Scene(
+        name="sky", positions=np.zeros((0, 3), np.float32), indices=np.zeros((0, 3), np.int32),
+        albedo=np.zeros((0, 3), np.float32), light_a=np.zeros((0, 3), np.float32),
+        light_b=np.zeros((0, 3), np.float32), light_intensity=np.zeros((0, 3), np.float32),
+        sky=np.array(value, np.float32), grid_origin=np.zeros(3, np.float32),
+        grid_spacing=np.ones(3, np.float32), grid_dims=np.array(dims, np.int32), frames=2)
+
+
+def test_pin6_running_mean_then_step_response():
+    # Cornell room, 1 frame, <=33 samples per texel from empty: exact mean.
+    vol = oracle.OracleVolume(scenes.cornell(), seed=3)
+    out = vol.update(0, adaptive=False, n_uniform=200, keep_rays=True)
+    for q in (0, 21, 42, 63):
+        b = out["ray_base"][q]
+        bins = out["irr_bin"][b:b + 200]
+        rgb = out["rays"][b:b + 200, :3]
+        for k in range(36):
+            sel = bins == k
+            if 0 < sel.sum() <= 33:
+                assert np.allclose(vol.irr[q].reshape(36, 3)[k], rgb[sel].mean(axis=0),
+                                   rtol=1e-12, atol=1e-15)
+    # saturated step response: after a texel has >= 34 samples of 0, switch
+    # the sky to 1; after k more samples the texel holds 1 - h^k.
+    vol = oracle.OracleVolume(_sky_scene([0.0, 0.0, 0.0]), seed=1)
+    for f in range(6):
+        vol.update(f, adaptive=False, n_uniform=400)
+    assert vol.irr_n.min() >= 34
+    n0 = vol.irr_n.copy().astype(np.int64)
+    vol.sc.sky = np.ones(3, np.float32)
+    out = vol.update(6, adaptive=False, n_uniform=400, keep_rays=True)
+    k = np.bincount(out["irr_bin"], minlength=36)
+    expect = 1.0 - vol.h ** k
+    assert np.allclose(vol.irr.reshape(36, 3)[:, 0], expect, rtol=1e-12)
+    assert np.array_equal(vol.irr_n[0], np.minimum(n0[0] + k, 255))
+
+
+def test_fp16_rounding_is_rne():
+    # exactly representable values are unchanged; halfway cases go to even
+    assert oracle.round_half(1.0) == 1.0
+    assert oracle.round_half(1.0 + 2 ** -11) == 1.0          # halfway, to even (1.0)
+    assert oracle.round_half(1.0 + 3 * 2 ** -11) == 1.0 + 2 ** -9  # halfway, to even
+    assert oracle.round_half(65504.0) == 65504.0
+    assert math.isinf(oracle.round_half(65520.0))
+    assert oracle.round_half(2 ** -25) == 0.0                 # halfway to 0 (even)
+    assert oracle.round_half(3 * 2 ** -25) == 2 ** -23
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-100, 100, 5000)
+    ref = x.astype(np.float16).astype(np.float64)  # numpy converts directly with RNE
+    assert np.array_equal(np.array([oracle.round_half(v) for v in x]), ref)
+
+
+# --------------------------------------------------------- O5: detection
+
+def _grid(dims):
+    return oracle.make_grid(np.zeros(3, np.float32), np.ones(3, np.float32),
+                            np.array(dims, np.int32))
+
+
+def _detect_run(dims, frames_q, theta=8, mu=2):
+    import ctypes as C
+    L = oracle.lib()
+    g = _grid(dims)
+    P = int(np.prod(dims))
+    st = dict(qvp=np.zeros(P * 8, np.uint16), qrp=np.zeros(P * 8, np.uint16),
+              tv=np.zeros(P * 8, np.int32), tr=np.zeros(P * 8, np.int32),
+              s=np.zeros(P, np.int64))
+    scores = []
+    for f, (qv, qr) in enumerate(frames_q):
+        qv = np.ascontiguousarray(qv, np.uint16)
+        qr = np.ascontiguousarray(qr, np.uint16)
+        L.orc_detect(C.byref(g), f, theta, mu, oracle._p(qv), oracle._p(qr), oracle._p(st["qvp"]),
+                     oracle._p(st["qrp"]), oracle._p(st["tv"]), oracle._p(st["tr"]),
+                     oracle._p(st["s"]))
+        scores.append(st["s"].copy())
+    return scores, st
+
+
+def test_pin7_static_scene_scores_zero():
+    rng = np.random.default_rng(0)
+    dims = (5, 3, 4)
+    P = 60
+    q = (rng.integers(0, 1024, P * 8), rng.integers(0, 1024, P * 8))
+    scores, _ = _detect_run(dims, [q, q, q, q])
+    assert all(np.all(s == 0) for s in scores)
+    n, off, _ = oracle.allocate(scores[-1], 64 * P + 17, 8, 512)
+    assert np.all(n[:17] == 65) and np.all(n[17:] == 64)
+
+
+def test_pin7_box_sum_identity_and_locality():
+    rng = np.random.default_rng(1)
+    dims = (7, 6, 9)
+    P = int(np.prod(dims))
+    qv0 = rng.integers(0, 1024, P * 8)
+    qr0 = rng.integers(0, 1024, P * 8)
+    qr1 = rng.integers(0, 1024, P * 8)
+    ones = np.ones(P * 8)
+    scores, st = _detect_run(dims, [(qv0, qr0), (ones, qr1)], mu=3)
+    tv, tr = st["tv"].astype(np.int64), st["tr"].astype(np.int64)
+    assert np.array_equal(tv, np.abs(1 - qv0)) and np.array_equal(tr, np.abs(qr1 - qr0))
+    # sum_i score_i = sum_j (Tv_j + mu Tr_j) * #{grid probes in the 5x5x5 box at j}
+    def span(x, D):
+        return min(x + 2, D - 1) - max(x - 2, 0) + 1
+    mult = np.zeros(P, np.int64)
+    for z in range(dims[2]):
+        for y in range(dims[1]):
+            for x in range(dims[0]):
+                mult[x + dims[0] * (y + dims[1] * z)] = span(x, dims[0]) * span(y, dims[1]) * span(z, dims[2])
+    rhs = ((tv + 3 * tr).reshape(P, 8).sum(axis=1) * mult).sum()
+    assert scores[1].sum() == rhs
+    # a single pulse reaches exactly the 5x5x5 neighbourhood
+    dims = (9, 9, 9)
+    P = 729
+    z0 = np.zeros(P * 8)
+    qv = np.full(P * 8, 3)
+    pulse = z0.copy()
+    c = 4 + 9 * (4 + 9 * 4)
+    pulse[c * 8 + 5] = 100
+    scores, _ = _detect_run(dims, [(qv, z0), (qv, pulse)])
+    s = scores[1].reshape(9, 9, 9)
+    assert np.all(s[2:7, 2:7, 2:7] == 3 * 2 * 100)
+    s[2:7, 2:7, 2:7] = 0
+    assert np.all(s == 0)
+
+
+def test_pin7_trigger_decays_to_zero():
+    dims = (1, 1, 1)
+    z = np.zeros(8)
+    pulse = np.zeros(8)
+    pulse[0] = 1023
+    qv = np.ones(8)
+    frames = [(qv, z), (qv, pulse)] + [(qv, pulse)] * 30
+    scores, _ = _detect_run(dims, frames, theta=8)
+    odd = [s[0] for f, s in enumerate(scores) if f % 2 == 1]
+    delta = math.ceil(1023 / 8)
+    # T = 1023, 1023-d, ... then 0 after ceil(1023/delta) = 8 detection steps
+    assert odd[0] == 2 * 1023
+    assert odd[1:9] == [2 * max(0, 1023 - k * delta) for k in range(1, 9)]
+    assert odd[8] == 0 and all(v == 0 for v in odd[8:])
+
+
+def test_pin7_light_switched_on_changes_only_lit_pilots():
+    sc = scenes.cornell()
+    sc.light_intensity = np.zeros((1, 3), np.float32)
+    vol = oracle.OracleVolume(sc, seed=2)
+    vol.set_frame_inputs(0)
+    qv0, qr0 = vol.pilots(0)
+    assert np.all(qr0 == 0)
+    vol.sc.light_intensity = np.full((1, 3), 5.0, np.float32)
+    vol.set_frame_inputs(1)
+    qv1, qr1 = vol.pilots(1)
+    assert np.array_equal(qv0, qv1)  # same directions within a pair, static geometry
+    changed = qr1 != qr0
+    assert changed.any()
+    score = vol.detect(0, qv0, qr0)
+    score = vol.detect(1, qv1, qr1)
+    assert np.all(vol.tv == 0) and np.array_equal(vol.tr > 0, changed)
+
+
+# -------------------------------------------------------- O6: allocation
+
+def _brute_lambda(w, E, Bp):
+    """lambda* by scanning every breakpoint of the step function."""
+    cands = {0, 1 << 31}
+    for wi in w:
+        if wi == 0:
+            continue
+        for m in range(1, E + 1):
+            lam = -(-(m << 32) // wi)  # ceil(m*2^32 / w)
+            if lam <= (1 << 31):
+                cands.add(lam)
+    best = 0
+    for lam in sorted(cands):
+        tot = sum(min(E, (lam * wi) >> 32) for wi in w)
+        if tot <= Bp:
+            best = max(best, lam)
+    # lambda* is the last integer before the next breakpoint that overflows
+    nxt = [c for c in sorted(cands) if c > best]
+    for c in nxt:
+        tot = sum(min(E, (c * wi) >> 32) for wi in w)
+        if tot > Bp:
+            return c - 1
+        best = c
+    return 1 << 31
+
+
+def _weights(score):
+    mx = int(max(score))
+    if mx == 0:
+        return [1 << 31] * len(score)
+    b = mx.bit_length()
+    return [(int(s) << (32 - b)) if b <= 32 else (int(s) >> (b - 32)) for s in score]
+
+
+def test_pin8_allocation_matches_breakpoint_scan():
+    rng = np.random.default_rng(4)
+    for trial in range(60):
+        P = int(rng.integers(1, 9))
+        n_min = int(rng.integers(1, 5))
+        n_max = n_min + int(rng.integers(0, 12))
+        score = rng.integers(0, 3000, P)
+        if trial % 7 == 0:
+            score[:] = 0
+        if trial % 11 == 0:
+            score = rng.integers(0, 2 ** 40, P)
+        budget = P * n_min + int(rng.integers(0, P * (n_max - n_min) + 3))
+        n, off, lam = oracle.allocate(score, budget, n_min, n_max)
+        w = _weights(score)
+        E = n_max - n_min
+        Bp = budget - P * n_min
+        assert lam == _brute_lambda(w, E, Bp)
+        e0 = [min(E, (lam * wi) >> 32) for wi in w]
+        R = Bp - sum(e0)
+        bonus = [0] * P
+        for i in range(P):
+            if R > 0 and min(E, ((lam + 1) * w[i]) >> 32) > e0[i]:
+                bonus[i] = 1
+                R -= 1
+        assert list(n) == [n_min + e0[i] + bonus[i] for i in range(P)]
+        assert np.all(n >= n_min) and np.all(n <= n_max)
+        assert off[0] == 0 and np.array_equal(np.diff(off), n)
+        if sum(min(E, (((1 << 31) + 1) * wi) >> 32) for wi in w) > Bp:
+            assert n.sum() == budget  # not saturated: the budget is spent exactly
+
+
+def test_pin8_allocation_properties():
+    rng = np.random.default_rng(5)
+    P = 2048
+    score = rng.integers(0, 10 ** 6, P)
+    B = 2 ** 19
+    n, off, lam = oracle.allocate(score, B, 32, 1024)
+    assert n.sum() == B and n.min() >= 32 and n.max() <= 1024
+    # monotone in a score while the normalisation shift is unchanged
+    i = int(np.argmin(score))
+    s2 = score.copy()
+    s2[i] += 1000
+    n2, _, _ = oracle.allocate(s2, B, 32, 1024)
+    assert n2[i] >= n[i]
+    # all-zero scores: uniform, remainder to the lowest indices
+    n3, _, _ = oracle.allocate(np.zeros(P, np.int64), B + 5, 32, 1024)
+    assert np.all(n3[:5] == 257) and np.all(n3[5:] == 256)
+    with pytest.raises(ValueError):
+        oracle.allocate(score, 32 * P - 1, 32, 1024)
