@@ -1,0 +1,224 @@
+/* adgi.h - C ABI of the MI355X probe-update library.
+ *
+ * The library keeps a uniform grid of light probes up to date each frame, as
+ * in the adaptive probe update of "Adaptive Dynamic Global Illumination"
+ * (Datta, Goli & Zhang, arXiv 2301.05125):
+ *
+ *   1. pilot rays, one per octant of every probe, measure probe visibility
+ *      f_v = exp(-2t/s) (eq. ProbeVis) and incoming radiance
+ *      f_r = min(lum, beta)/beta (Sec. 4.1.3); their temporal change, passed
+ *      through a decaying trigger and a 5x5x5 spatial sum (Sec. 4.1.4-4.1.5),
+ *      is composed as f_v (f_dv + mu f_dr) (eq. priorDynamic) into an integer
+ *      score per probe;
+ *   2. a user-set total ray budget is split over the probes in proportion to
+ *      their scores (the paper fixes the samples per frame and lets its guide
+ *      place them, Sec. 3.3), each probe getting between n_min and n_max rays;
+ *   3. every probe traces its rays (a randomly rotated spherical Fibonacci
+ *      set, as DDGI's rotated spiral, Sec. 3.1) against a triangle BVH, with
+ *      direct light and shadow rays at each hit;
+ *   4. each sample updates the octahedral irradiance texel and the
+ *      depth-moment (visibility) texel it falls in with the moving average of
+ *      Alg. MovingAvgUpdate (Alg. ApproxAlgo, Sec. 4.5-4.7).
+ * With adaptive = 0 every probe traces n_uniform rays and steps 1-2 are
+ * skipped (the uniform DDGI-style update).
+ *
+ * Conventions
+ *   - Probe i sits at origin + (x, y, z) * spacing with
+ *     i = x + dims[0] * (y + dims[1] * z).
+ *   - s = |spacing|_2 is the voxel diagonal (the length eq. ProbeVis
+ *     normalises distances by); depth texels store tau = min(t/s, tau_max)
+ *     and tau^2.
+ *   - Texel tiles are res x res with a one-texel border copied across the
+ *     octahedral map's edges; the interior is (res-2) x (res-2). Direction d
+ *     falls in the interior texel of its octahedral coordinates (Cigolle et
+ *     al. 2014), row = v, column = u.
+ *   - All functions return an adgi_status; on any error nothing has been
+ *     enqueued, the volume and every output are unchanged, and
+ *     adgi_last_error() describes the failure. A device error is sticky: every
+ *     later call on that volume returns ADGI_ERR_DEVICE until it is destroyed.
+ *   - A volume is not thread-safe. Distinct volumes may be used from distinct
+ *     threads and overlap on the device.
+ *   - Pointers marked "host" are CPU memory owned by the caller and only read
+ *     or written during the call. All device memory belongs to the library.
+ */
+#ifndef ADGI_H
+#define ADGI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adgi_volume adgi_volume;
+
+typedef enum {
+  ADGI_OK = 0,
+  ADGI_ERR_INVALID_ARG = -1,   /* a descriptor or argument is out of range        */
+  ADGI_ERR_OUT_OF_MEMORY = -2, /* the allocator returned NULL                     */
+  ADGI_ERR_BUDGET = -3,        /* budget < P*n_min, n_min < 1 or n_max < n_min,
+                                  or the rays would exceed max_rays_per_frame     */
+  ADGI_ERR_NO_SCENE = -4,      /* update_probes before any update_scene           */
+  ADGI_ERR_TOPOLOGY = -5,      /* REFIT with a different vertex/triangle count    */
+  ADGI_ERR_DEVICE = -6         /* a HIP call failed; sticky until destroy         */
+} adgi_status;
+
+enum { ADGI_FP32 = 0, ADGI_FP16 = 1 };                       /* texel storage */
+enum { ADGI_SCENE_REBUILD = 0, ADGI_SCENE_REFIT = 1 };      /* scene update mode */
+enum { ADGI_DEBUG_ARRAYS = 1u << 0 };                        /* volume flags */
+enum { ADGI_MAX_LIGHTS = 8 };
+
+/* Device memory provider. alloc returns device memory of at least `bytes`
+ * (256-byte aligned) or NULL; free releases it. Both are called only from
+ * create/update_scene/destroy and from adgi_autotune. NULL allocator = hipMalloc. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} adgi_allocator;
+
+typedef struct {
+  float origin[3];            /* centre of probe (0,0,0), world units            */
+  float spacing[3];           /* > 0                                             */
+  int32_t dims[3];            /* >= 1 each; P = product, P <= 2^24               */
+  int32_t irr_res;            /* irradiance tile side incl. border, 3..34 (8)    */
+  int32_t depth_res;          /* depth tile side incl. border, 3..34 (16)        */
+  int32_t storage;            /* ADGI_FP32 or ADGI_FP16                           */
+  float hysteresis;           /* h in [0, 1): step = max(1/(N+1), 1-h) (0.97)    */
+  float tau_max;              /* depth clamp in units of s ((e^5-1)/15)          */
+  int64_t max_rays_per_frame; /* capacity of the per-frame ray buffers, < 2^31   */
+  uint64_t seed;              /* seeds the frame rotation and the pilot rays     */
+  uint32_t flags;             /* ADGI_DEBUG_ARRAYS keeps per-ray decisions       */
+} adgi_volume_desc;
+
+typedef struct {
+  const float* positions;     /* host [num_vertices][3]                           */
+  int32_t num_vertices;
+  const int32_t* indices;     /* host [num_triangles][3], 0 <= index < V          */
+  int32_t num_triangles;      /* >= 0 (0 = empty scene: every ray sees the sky)   */
+  const float* albedo;        /* host [num_triangles][3]; ignored by REFIT        */
+  const float* light_pos;     /* host [num_lights][3]                              */
+  const float* light_intensity;/* host [num_lights][3] RGB                         */
+  int32_t num_lights;         /* 0..ADGI_MAX_LIGHTS                                */
+  float sky[3];               /* radiance of rays that leave the scene            */
+  int32_t mode;               /* REBUILD: new triangles, host SAH build.
+                                 REFIT: same V and T, positions[vbegin, vend)
+                                 changed; boxes are refitted on the device.       */
+  int32_t refit_vertex_begin; /* REFIT only; [0, V]                                */
+  int32_t refit_vertex_end;   /* REFIT only; [begin, V]                            */
+} adgi_scene_desc;
+
+typedef struct {
+  int32_t frame;              /* frame index t >= 0; consecutive frames form pairs
+                                 (2m, 2m+1) that share pilot directions           */
+  int32_t adaptive;           /* 0: n_uniform rays per probe; 1: budgeted          */
+  int64_t budget;             /* adaptive: total rays B this frame                 */
+  int32_t n_min, n_max;       /* adaptive: per-probe bounds                        */
+  int32_t n_uniform;          /* uniform: rays per probe, >= 1                     */
+  float beta;                 /* f_r dynamic range (5)                              */
+  int32_t mu;                 /* weight of radiance change vs visibility change (2) */
+  int32_t theta;              /* trigger decays to 0 in theta detection steps (8)  */
+  int32_t sync;               /* 1: wait for completion and fill stats             */
+} adgi_update_params;
+
+typedef struct {
+  int64_t primary_rays;       /* rays traced from probes this frame               */
+  int64_t pilot_rays;         /* 8 * P in adaptive mode                            */
+  int64_t shadow_rays;        /* shadow rays of primary + pilot hits               */
+  int64_t budget_used;        /* sum of rays per probe                             */
+  uint32_t lambda;            /* allocation multiplier lambda*                      */
+  int32_t n_min_seen, n_max_seen;
+  float ms_total;             /* device time of the frame (sync = 1)               */
+  float ms_stage[8];          /* reserved                                          */
+  int64_t ties[4];            /* reserved                                          */
+} adgi_update_stats;
+
+/* Readback destinations (host). NULL fields are skipped. Texel arrays are
+ * FP32 whatever the storage (FP16 is widened exactly). Debug arrays need
+ * ADGI_DEBUG_ARRAYS and hold the last frame. */
+typedef struct {
+  float* irradiance;          /* [P][irr_res][irr_res][3]                          */
+  float* depth;               /* [P][depth_res][depth_res][2] (tau, tau^2)         */
+  uint8_t* irr_count;         /* [P][irr_res-2][irr_res-2] samples, saturating 255 */
+  uint8_t* depth_count;       /* [P][depth_res-2][depth_res-2]                      */
+  int32_t* rays_per_probe;    /* [P] n_i of the last frame                          */
+  int64_t* score;             /* [P] detection score                                */
+  int64_t* ray_offsets;       /* [P+1] exclusive prefix sum of rays_per_probe       */
+  /* debug: per primary ray r = ray_offsets[i] + j of the last frame */
+  int32_t* hit_tri;           /* [R] closest triangle, -1 for a miss               */
+  uint8_t* shadow_bits;       /* [R] bit l: light l lit the hit point              */
+  uint16_t* irr_bin;          /* [R] interior irradiance texel (row*(res-2)+col)   */
+  uint16_t* depth_bin;        /* [R] interior depth texel                           */
+  float* ray_record;          /* [R][4] radiance RGB, hit distance (inf = miss)    */
+  uint16_t* q10_vis;          /* [P][8] pilot visibility code of the last frame    */
+  uint16_t* q10_rad;          /* [P][8] pilot radiance code of the last frame      */
+  float* frame_rotation;      /* [9] row-major rotation of the last frame          */
+  int64_t num_rays;           /* out: R of the last frame                           */
+} adgi_probe_readback;
+
+/* Create a volume. desc/alloc are host, copied. hip_stream (hipStream_t or
+ * NULL) is the caller's stream: every call orders its device work after the
+ * work already on that stream and makes that stream wait for it. Texels and
+ * counts start at zero. *out receives the handle. */
+adgi_status adgi_create_volume(const adgi_volume_desc* desc, const adgi_allocator* alloc,
+                               void* hip_stream, adgi_volume** out);
+
+/* Upload or change the scene (triangles, albedo, lights, sky). REBUILD
+ * builds a binned-SAH BVH on the host and uploads it; REFIT uploads the
+ * changed vertex range and refits the boxes on the device. Lights and sky
+ * are taken on every call. Asynchronous w.r.t. the device; the host arrays
+ * may be reused on return. */
+adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* scene);
+
+/* One probe-update frame (pilots, detection, allocation, trace, shade,
+ * blend), enqueued as one HIP graph launch. Errors: ADGI_ERR_NO_SCENE,
+ * ADGI_ERR_BUDGET, ADGI_ERR_INVALID_ARG. stats may be NULL; it is filled only
+ * when params->sync is 1. */
+adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* params,
+                               adgi_update_stats* stats);
+
+/* Wait for the volume's work and copy state into caller buffers. */
+adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out);
+
+/* Complete pending work and release every device allocation. NULL is a no-op. */
+void adgi_destroy_volume(adgi_volume* vol);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* adgi_last_error(void);
+
+/* ---- launch tuning -------------------------------------------------------
+ * How the frame is launched; results are bitwise identical for every valid
+ * setting. Defaults: graph on, persistent traversal, autotuned sizes. */
+typedef struct {
+  int32_t use_graph;          /* 1: capture the frame as a hipGraph; 0: eager     */
+  int32_t persistent;         /* 1: work-stealing persistent traversal;
+                                 0: one thread per ray, grid sized to the rays    */
+  int32_t trace_block;        /* threads per traversal workgroup: 64..1024, x64   */
+  int32_t trace_waves_per_cu; /* persistent grid = CUs * this / (block/64), 1..32 */
+  int32_t blend_chunk;        /* rays staged in LDS per blend step: 64..2048, x64 */
+  int32_t lds_top_nodes;      /* BVH nodes staged in LDS per workgroup: 0..1024   */
+} adgi_tuning;
+
+adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);
+adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t);
+/* Time candidate launch shapes on the current scene and frame parameters
+ * and keep the fastest. Runs the traversal and the blend several times on
+ * scratch copies: the volume's state is unchanged. The choice is cached per
+ * (device, shape class) in memory for the process. */
+adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* params, adgi_tuning* chosen);
+
+/* ---- state snapshot (checkpoint / eviction) ------------------------------
+ * The complete temporal state: texels, counts, detection codes and triggers,
+ * scores and the last frame's allocation. Restoring a snapshot into a volume
+ * created with the same desc resumes bit-identically. */
+size_t adgi_state_size(const adgi_volume* vol);
+adgi_status adgi_save_state(adgi_volume* vol, void* host_dst, size_t bytes);
+adgi_status adgi_restore_state(adgi_volume* vol, const void* host_src, size_t bytes);
+/* Device bytes the volume holds now (state + scene + frame buffers). */
+size_t adgi_device_bytes(const adgi_volume* vol);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

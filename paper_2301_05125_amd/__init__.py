@@ -1,0 +1,333 @@
+"""Python binding of the gfx950 probe-update library (ctypes, marshalling only).
+
+Every step of the probe update runs in the HIP kernels of ``libadgi.so``;
+this module only converts numpy arrays and Python values to the C ABI of
+``include/adgi.h``. PyTorch provides device memory (its caching allocator, as
+the library's allocator callbacks) and the caller's stream. The import fails
+loudly when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadgi.so")
+
+ADGI_OK = 0
+STATUS = {0: "ADGI_OK", -1: "ADGI_ERR_INVALID_ARG", -2: "ADGI_ERR_OUT_OF_MEMORY",
+          -3: "ADGI_ERR_BUDGET", -4: "ADGI_ERR_NO_SCENE", -5: "ADGI_ERR_TOPOLOGY",
+          -6: "ADGI_ERR_DEVICE"}
+ADGI_FP32, ADGI_FP16 = 0, 1
+ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
+ADGI_DEBUG_ARRAYS = 1
+MAX_LIGHTS = 8
+TAU_MAX = (math.exp(5.0) - 1.0) / 15.0
+
+
+class AdgiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class VolumeDesc(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("dims", C.c_int32 * 3),
+                ("irr_res", C.c_int32), ("depth_res", C.c_int32), ("storage", C.c_int32),
+                ("hysteresis", C.c_float), ("tau_max", C.c_float),
+                ("max_rays_per_frame", C.c_int64), ("seed", C.c_uint64), ("flags", C.c_uint32)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("positions", C.c_void_p), ("num_vertices", C.c_int32), ("indices", C.c_void_p),
+                ("num_triangles", C.c_int32), ("albedo", C.c_void_p), ("light_pos", C.c_void_p),
+                ("light_intensity", C.c_void_p), ("num_lights", C.c_int32), ("sky", C.c_float * 3),
+                ("mode", C.c_int32), ("refit_vertex_begin", C.c_int32),
+                ("refit_vertex_end", C.c_int32)]
+
+
+class UpdateParams(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("adaptive", C.c_int32), ("budget", C.c_int64),
+                ("n_min", C.c_int32), ("n_max", C.c_int32), ("n_uniform", C.c_int32),
+                ("beta", C.c_float), ("mu", C.c_int32), ("theta", C.c_int32), ("sync", C.c_int32)]
+
+
+class UpdateStats(C.Structure):
+    _fields_ = [("primary_rays", C.c_int64), ("pilot_rays", C.c_int64), ("shadow_rays", C.c_int64),
+                ("budget_used", C.c_int64), ("lambda_", C.c_uint32), ("n_min_seen", C.c_int32),
+                ("n_max_seen", C.c_int32), ("ms_total", C.c_float), ("ms_stage", C.c_float * 8),
+                ("ties", C.c_int64 * 4)]
+
+    def as_dict(self):
+        return {"primary_rays": self.primary_rays, "pilot_rays": self.pilot_rays,
+                "shadow_rays": self.shadow_rays, "budget_used": self.budget_used,
+                "lambda": self.lambda_, "n_min_seen": self.n_min_seen,
+                "n_max_seen": self.n_max_seen, "ms_total": self.ms_total}
+
+
+class ProbeReadback(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "irradiance", "depth", "irr_count", "depth_count", "rays_per_probe", "score",
+        "ray_offsets", "hit_tri", "shadow_bits", "irr_bin", "depth_bin", "ray_record",
+        "q10_vis", "q10_rad", "frame_rotation")] + [("num_rays", C.c_int64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("persistent", C.c_int32), ("trace_block", C.c_int32),
+                ("trace_waves_per_cu", C.c_int32), ("blend_chunk", C.c_int32),
+                ("lds_top_nodes", C.c_int32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libadgi.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(no CPU fallback exists)")
+        try:
+            import torch  # noqa: F401  (loads the HIP runtime torch uses)
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.adgi_last_error.restype = C.c_char_p
+        L.adgi_create_volume.argtypes = [P, P, P, P]
+        L.adgi_update_scene.argtypes = [P, P]
+        L.adgi_update_probes.argtypes = [P, P, P]
+        L.adgi_read_probes.argtypes = [P, P]
+        L.adgi_destroy_volume.argtypes = [P]
+        L.adgi_destroy_volume.restype = None
+        L.adgi_get_tuning.argtypes = [P, P]
+        L.adgi_set_tuning.argtypes = [P, P]
+        L.adgi_autotune.argtypes = [P, P, P]
+        L.adgi_state_size.argtypes = [P]
+        L.adgi_state_size.restype = C.c_size_t
+        L.adgi_save_state.argtypes = [P, P, C.c_size_t]
+        L.adgi_restore_state.argtypes = [P, P, C.c_size_t]
+        L.adgi_device_bytes.argtypes = [P]
+        L.adgi_device_bytes.restype = C.c_size_t
+        for name in ("adgi_create_volume", "adgi_update_scene", "adgi_update_probes",
+                     "adgi_read_probes", "adgi_get_tuning", "adgi_set_tuning", "adgi_autotune",
+                     "adgi_save_state", "adgi_restore_state"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != ADGI_OK:
+        raise AdgiError(status, lib().adgi_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _torch_allocator():
+    """Allocator callbacks backed by torch's caching allocator."""
+    import torch
+    dev = torch.cuda.current_device()
+    stream = torch.cuda.current_stream()
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+        except RuntimeError:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    return a
+
+
+def create_volume(origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
+                  hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
+                  debug=False, stream=None, allocator="torch") -> "Volume":
+    return Volume(origin, spacing, dims, irr_res, depth_res, storage, hysteresis, tau_max,
+                  max_rays_per_frame, seed, debug, stream, allocator)
+
+
+class Volume:
+    """A probe volume: device state, scene and the per-frame update."""
+
+    def __init__(self, origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
+                 hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
+                 debug=False, stream=None, allocator="torch"):
+        d = VolumeDesc()
+        d.origin[:] = [float(x) for x in origin]
+        d.spacing[:] = [float(x) for x in spacing]
+        d.dims[:] = [int(x) for x in dims]
+        d.irr_res, d.depth_res, d.storage = int(irr_res), int(depth_res), int(storage)
+        d.hysteresis, d.tau_max = float(hysteresis), float(tau_max)
+        d.max_rays_per_frame = int(max_rays_per_frame)
+        d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        d.flags = ADGI_DEBUG_ARRAYS if debug else 0
+        self.desc = d
+        self.P = int(np.prod([int(x) for x in dims]))
+        self._alloc = None
+        if allocator == "torch":
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream().cuda_stream
+            self._alloc = _torch_allocator()
+        elif allocator is not None:
+            self._alloc = allocator
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().adgi_create_volume(C.byref(d), C.byref(self._alloc) if self._alloc else None,
+                                        C.c_void_p(stream) if stream else None, C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        self.destroy_volume()
+
+    def destroy_volume(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().adgi_destroy_volume(self.h)
+            self.h = C.c_void_p()
+
+    def update_scene(self, positions, indices=None, albedo=None, light_pos=None,
+                     light_intensity=None, sky=(0.0, 0.0, 0.0), mode=ADGI_SCENE_REBUILD,
+                     refit_range=None):
+        pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
+        idx = None if indices is None else np.ascontiguousarray(indices, np.int32).reshape(-1, 3)
+        alb = None if albedo is None else np.ascontiguousarray(albedo, np.float32).reshape(-1, 3)
+        lp = np.ascontiguousarray(light_pos if light_pos is not None else np.zeros((0, 3)),
+                                  np.float32).reshape(-1, 3)
+        li = np.ascontiguousarray(light_intensity if light_intensity is not None
+                                  else np.zeros((0, 3)), np.float32).reshape(-1, 3)
+        s = SceneDesc()
+        s.positions = _ptr(pos)
+        s.num_vertices = pos.shape[0]
+        s.indices = _ptr(idx)
+        s.num_triangles = 0 if idx is None else idx.shape[0]
+        if mode == ADGI_SCENE_REFIT and idx is None:
+            s.num_triangles = self._nt
+        s.albedo = _ptr(alb)
+        s.light_pos = _ptr(lp)
+        s.light_intensity = _ptr(li)
+        s.num_lights = lp.shape[0]
+        s.sky[:] = [float(x) for x in sky]
+        s.mode = int(mode)
+        if refit_range is None:
+            refit_range = (0, pos.shape[0])
+        s.refit_vertex_begin, s.refit_vertex_end = int(refit_range[0]), int(refit_range[1])
+        _check(lib().adgi_update_scene(self.h, C.byref(s)))
+        if mode == ADGI_SCENE_REBUILD:
+            self._nt = s.num_triangles
+
+    def update_probes(self, frame, adaptive=False, budget=0, n_min=8, n_max=2048, n_uniform=64,
+                      beta=5.0, mu=2, theta=8, sync=True) -> dict:
+        p = UpdateParams(int(frame), 1 if adaptive else 0, int(budget), int(n_min), int(n_max),
+                         int(n_uniform), float(beta), int(mu), int(theta), 1 if sync else 0)
+        st = UpdateStats()
+        _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
+        return st.as_dict() if sync else {}
+
+    def read_probes(self, texels=True, debug=False, probes=None) -> dict:
+        d = self.desc
+        P = self.P
+        gi, gd = d.irr_res, d.depth_res
+        out = {}
+        rb = ProbeReadback()
+        if texels:
+            out["irradiance"] = np.zeros((P, gi, gi, 3), np.float32)
+            out["depth"] = np.zeros((P, gd, gd, 2), np.float32)
+            out["irr_count"] = np.zeros((P, gi - 2, gi - 2), np.uint8)
+            out["depth_count"] = np.zeros((P, gd - 2, gd - 2), np.uint8)
+        out["rays_per_probe"] = np.zeros(P, np.int32)
+        out["score"] = np.zeros(P, np.int64)
+        out["ray_offsets"] = np.zeros(P + 1, np.int64)
+        out["q10_vis"] = np.zeros(P * 8, np.uint16)
+        out["q10_rad"] = np.zeros(P * 8, np.uint16)
+        out["frame_rotation"] = np.zeros(9, np.float32)
+        for k, a in out.items():
+            setattr(rb, k, _ptr(a))
+        _check(lib().adgi_read_probes(self.h, C.byref(rb)))
+        if debug:
+            R = int(out["ray_offsets"][-1])
+            dbg = {"hit_tri": np.zeros(max(R, 1), np.int32),
+                   "shadow_bits": np.zeros(max(R, 1), np.uint8),
+                   "irr_bin": np.zeros(max(R, 1), np.uint16),
+                   "depth_bin": np.zeros(max(R, 1), np.uint16),
+                   "ray_record": np.zeros((max(R, 1), 4), np.float32)}
+            rb2 = ProbeReadback()
+            for k, a in dbg.items():
+                setattr(rb2, k, _ptr(a))
+            _check(lib().adgi_read_probes(self.h, C.byref(rb2)))
+            for k, a in dbg.items():
+                out[k] = a[:R]
+        out["num_rays"] = int(out["ray_offsets"][-1])
+        return out
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().adgi_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        _check(lib().adgi_get_tuning(self.h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(lib().adgi_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, frame, adaptive=False, budget=0, n_min=8, n_max=2048, n_uniform=64,
+                 beta=5.0, mu=2, theta=8) -> dict:
+        p = UpdateParams(int(frame), 1 if adaptive else 0, int(budget), int(n_min), int(n_max),
+                         int(n_uniform), float(beta), int(mu), int(theta), 1)
+        t = Tuning()
+        _check(lib().adgi_autotune(self.h, C.byref(p), C.byref(t)))
+        return t.as_dict()
+
+    def state_size(self) -> int:
+        return int(lib().adgi_state_size(self.h))
+
+    def save_state(self) -> np.ndarray:
+        buf = np.zeros(self.state_size(), np.uint8)
+        _check(lib().adgi_save_state(self.h, _ptr(buf), buf.nbytes))
+        return buf
+
+    def restore_state(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        _check(lib().adgi_restore_state(self.h, _ptr(buf), buf.nbytes))
+
+    def device_bytes(self) -> int:
+        return int(lib().adgi_device_bytes(self.h))
+
+
+def volume_for_scene(scene, storage=ADGI_FP32, max_rays=None, seed=1, debug=False,
+                     irr_res=8, depth_res=16, hysteresis=0.97, **kw) -> Volume:
+    """Create a volume on a ``scenes.Scene``'s grid and upload its frame-0 scene."""
+    if max_rays is None:
+        max_rays = 1 << 20
+    vol = Volume(scene.grid_origin, scene.grid_spacing, scene.grid_dims, irr_res=irr_res,
+                 depth_res=depth_res, storage=storage, hysteresis=hysteresis,
+                 max_rays_per_frame=max_rays, seed=seed, debug=debug, **kw)
+    vol.update_scene(scene.positions, scene.indices, scene.albedo, scene.light_positions(0),
+                     scene.light_intensity, scene.sky)
+    return vol

@@ -1,0 +1,77 @@
+// adgi_internal.hpp - kernel launchers and host-side helpers of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "adgi_device.hpp"
+#include "adgi_layout.hpp"
+
+namespace adgi {
+
+// trace.hip
+size_t trace_lds_bytes(int block, int ntop);
+hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
+                        int grid, int ntop);
+
+// detect.hip: trigger update and the separable 5x5x5 box sum -> scores
+hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s);
+hipError_t launch_detect(const VolumeView& v, hipStream_t s);
+
+// alloc.hip: integer budget split and exclusive scan
+hipError_t launch_alloc(const VolumeView& v, hipStream_t s);
+hipError_t launch_uniform_offsets(const VolumeView& v, hipStream_t s);
+
+// blend.hip: per-probe texel update and border fold
+struct BlendIO {
+  const void* irr_in;
+  const void* dep_in;
+  const uint8_t* irr_n_in;
+  const uint8_t* dep_n_in;
+  void* irr_out;
+  void* dep_out;
+  uint8_t* irr_n_out;
+  uint8_t* dep_n_out;
+};
+hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk);
+size_t blend_lds_bytes(const VolumeView& v, int chunk);
+
+// refit.hip
+struct RefitView {
+  const float* positions;    // [V][3]
+  const int32_t* indices;    // [T][3]
+  const int32_t* tri_order;  // slot -> original triangle
+  float4* tris;              // [T][3]
+  float4* nodes;             // [N][4]
+  const int32_t* leaf_slots; // (node << 1 | side) for every leaf child slot
+  int32_t num_leaf_slots;
+  uint32_t* arrive;          // [N] counters, zeroed by the launcher
+  int32_t num_tris;
+  int32_t num_nodes;
+  float pad_abs;
+};
+hipError_t launch_refit(const RefitView& r, hipStream_t s);
+
+// bvh_build.cpp: binned SAH on the host
+struct BvhHost {
+  std::vector<float4> nodes;       // 4 per node
+  std::vector<float4> tris;        // 3 per triangle slot
+  std::vector<int32_t> tri_order;  // slot -> original triangle
+  std::vector<int32_t> leaf_slots; // node << 1 | side
+  int32_t depth = 0;
+};
+bool build_bvh(const float* positions, int32_t nv, const int32_t* indices, int32_t nt, float pad_abs,
+               BvhHost& out, const char** err);
+// Conservative box padding (builder and refit): a few ulps of the coordinate
+// plus an absolute term tied to the scene's coordinate scale, so that FP32
+// slab tests from any ray origin in the scene never cull a box a hit lies in.
+__host__ __device__ __forceinline__ float pad_lo(float x, float pad_abs) {
+  return x - (fabsf(x) * 4.8e-7f + pad_abs);
+}
+__host__ __device__ __forceinline__ float pad_hi(float x, float pad_abs) {
+  return x + (fabsf(x) * 4.8e-7f + pad_abs);
+}
+
+}  // namespace adgi

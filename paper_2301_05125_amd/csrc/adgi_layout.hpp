@@ -1,0 +1,104 @@
+// adgi_layout.hpp - device data layout shared by the host runtime and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adgi {
+
+constexpr uint64_t kTagRotation = 0x524F54ull;  // "ROT"
+constexpr uint64_t kTagPilot = 0x50494Cull;     // "PIL"
+constexpr int kMaxLights = 8;
+constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
+constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
+constexpr int kStackLds = 16;                   // traversal stack entries kept in LDS
+constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
+constexpr float kShadowOffset = 1e-4f;          // shadow origin offset, units of s
+constexpr float kShadowShorten = 1e-6f;         // relative shortening of shadow rays
+
+// BVH2 node: the boxes of both children live in the parent (64 bytes).
+//   f[0] = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)
+//   f[1] = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
+//   f[2] = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)
+//   f[3] = (left, right, parent, side-in-parent) as int bits
+// A child c >= 0 is an internal node; c < 0 is a leaf with
+// ~c = (first triangle slot << 4) | (count - 1), count in 1..16.
+// Node 0 is the root and is always internal.
+constexpr int kLeafShift = 4;
+constexpr int kLeafMaxTris = 16;
+
+// Triangle record in leaf order (48 bytes): (v0, id bits), (e1, 0), (e2, 0).
+
+struct SceneParams {
+  float lpos[kMaxLights][4];
+  float lint[kMaxLights][4];
+  float sky[4];
+  int32_t num_lights;
+  int32_t num_tris;
+  int32_t num_nodes;
+  int32_t pad;
+};
+
+struct FrameParams {
+  float R[12];        // row-major rotation (9 used)
+  uint64_t seed;
+  int64_t budget;
+  int32_t frame;
+  int32_t adaptive;
+  int32_t n_min, n_max, n_uniform;
+  int32_t mu, theta;
+  float beta;
+  int32_t debug;
+  int32_t pad[3];
+};
+
+struct FrameStats {
+  uint32_t ray_counter;     // persistent work-stealing cursor (primary)
+  uint32_t pilot_counter;   // persistent cursor (pilots)
+  uint64_t shadow_rays;
+  uint64_t max_score;
+  uint32_t lambda;
+  int32_t n_min_seen, n_max_seen;
+  int32_t pad;
+  uint64_t budget_used;
+  uint64_t sums[4][kAllocCandidates];
+};
+
+// Everything a kernel needs, passed by value.
+struct VolumeView {
+  // grid
+  float ox, oy, oz;
+  float sx, sy, sz;
+  int32_t dx, dy, dz;
+  int32_t P;
+  float s_diag;
+  int32_t irr_res, dep_res;
+  float one_minus_h;
+  float tau_max;
+  // scene
+  const float4* nodes;
+  const float4* tris;
+  const float4* albedo;       // by original triangle index
+  const SceneParams* scene;
+  const FrameParams* fp;
+  FrameStats* stats;
+  // detection
+  uint16_t* qv[2];            // [P*8] pilot visibility codes, slot = frame & 1
+  uint16_t* qr[2];            // [P*8] pilot radiance codes
+  int2* trig;                 // [P*8] (Tv, Tr)
+  int2* box_a;                // [P*8] box-sum scratch
+  int2* box_b;
+  int64_t* score;             // [P]
+  // allocation
+  int32_t* n;                 // [P]
+  uint32_t* offsets;          // [P+1]
+  // trace / blend
+  float4* rec;                // [max_rays] radiance RGB, t
+  int32_t* dbg_tri;           // [max_rays] or null
+  uint8_t* dbg_shadow;
+  uint16_t* dbg_ibin;
+  uint16_t* dbg_dbin;
+  uint32_t max_rays;
+};
+
+}  // namespace adgi

@@ -1,0 +1,255 @@
+// blend.hip - per-probe texel update (one workgroup per probe).
+//
+// Every sample updates the texel that contains its direction ("the closest
+// entry", Alg. ApproxAlgo) with the moving average of Alg. MovingAvgUpdate:
+// V <- V + a (x - V), a = max(1/(N+1), 1-h), N <- min(N+1, 255): a running
+// mean while 1/(N+1) > 1-h, then an exponential average with hysteresis h.
+// Irradiance texels take the ray's radiance; depth texels take the moments
+// (tau, tau^2) of tau = min(t/s, tau_max) (Sec. 4.6). Samples of one texel are
+// applied in ascending ray order. The probe's texel tile is staged in LDS;
+// rays are processed in chunks: coalesced load of the chunk's 16-byte
+// records, octahedral bins recomputed from the ray index, an LDS counting
+// sort by texel (histogram, scan, scatter, then a short insertion sort of each
+// texel's list to restore ray order), and one thread per texel applying its
+// samples in sequence. The tile is written back with its one-texel border
+// folded across the octahedral map's edges. FP32 arithmetic throughout;
+// FP16 storage is widened on load and rounded to nearest-even on store.
+#include <hip/hip_fp16.h>
+
+#include "adgi_internal.hpp"
+
+namespace adgi {
+
+template <bool HALF>
+struct Store;
+template <>
+struct Store<false> {
+  using T = float;
+  __device__ static float load(const T* p) { return *p; }
+  __device__ static void store(T* p, float x) { *p = x; }
+};
+template <>
+struct Store<true> {
+  using T = __half;
+  __device__ static float load(const T* p) { return __half2float(*p); }
+  __device__ static void store(T* p, float x) { *p = __float2half_rn(x); }
+};
+
+__device__ uint32_t block_scan_u32(uint32_t x, uint32_t* sm, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t v = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(v, off);
+    if (lane >= off) v += y;
+  }
+  if (lane == 63) sm[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < nw; ++k) {
+      uint32_t t = sm[k];
+      sm[k] = acc;
+      acc += t;
+    }
+    sm[nw] = acc;
+  }
+  __syncthreads();
+  total = sm[nw];
+  uint32_t r = v - x + sm[wave];
+  __syncthreads();
+  return r;
+}
+
+struct BlendLds {
+  float* stI;
+  float* stD;
+  uint32_t* cnt;
+  uint32_t* hist;
+  uint32_t* start;
+  uint32_t* cursor;
+  uint32_t* scan;
+  float4* rec;
+  uint16_t* bins;
+  uint16_t* list;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t blend_layout(int irr_res, int dep_res, int chunk, BlendLds* L,
+                                               uint8_t* base) {
+  const int ri = irr_res - 2, rd = dep_res - 2, nI = ri * ri, nD = rd * rd, nT = nI + nD;
+  size_t o = 0;
+  size_t oStI = o; o += (size_t)nI * 3 * 4;
+  size_t oStD = o; o += (size_t)nD * 2 * 4;
+  size_t oCnt = o; o += (size_t)nT * 4;
+  size_t oHist = o; o += (size_t)nT * 4;
+  size_t oStart = o; o += (size_t)nT * 4;
+  size_t oCur = o; o += (size_t)nT * 4;
+  size_t oScan = o; o += 17 * 4;
+  o = align16(o);
+  size_t oRec = o; o += (size_t)chunk * 16;
+  size_t oBins = o; o += (size_t)chunk * 2 * 2;
+  size_t oList = o; o += (size_t)chunk * 2 * 2;
+  if (L) {
+    L->stI = (float*)(base + oStI);
+    L->stD = (float*)(base + oStD);
+    L->cnt = (uint32_t*)(base + oCnt);
+    L->hist = (uint32_t*)(base + oHist);
+    L->start = (uint32_t*)(base + oStart);
+    L->cursor = (uint32_t*)(base + oCur);
+    L->scan = (uint32_t*)(base + oScan);
+    L->rec = (float4*)(base + oRec);
+    L->bins = (uint16_t*)(base + oBins);
+    L->list = (uint16_t*)(base + oList);
+  }
+  return align16(o);
+}
+
+template <bool HALF>
+__global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, int chunk) {
+  using S = Store<HALF>;
+  using T = typename S::T;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  BlendLds L;
+  blend_layout(v.irr_res, v.dep_res, chunk, &L, smem);
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int gi = v.irr_res, gd = v.dep_res;
+  const int ri = gi - 2, rd = gd - 2, nI = ri * ri, nD = rd * rd, nT = nI + nD;
+  const FrameParams& fp = *v.fp;
+
+  // ---- load the interior of both tiles and the counts
+  const T* irr_in = (const T*)io.irr_in + (size_t)i * gi * gi * 3;
+  const T* dep_in = (const T*)io.dep_in + (size_t)i * gd * gd * 2;
+  for (int f = tid; f < nI * 3; f += nt) {
+    int k = f / 3, c = f - 3 * k, iy = k / ri, ix = k - iy * ri;
+    L.stI[f] = S::load(irr_in + ((iy + 1) * gi + ix + 1) * 3 + c);
+  }
+  for (int f = tid; f < nD * 2; f += nt) {
+    int k = f >> 1, c = f & 1, iy = k / rd, ix = k - iy * rd;
+    L.stD[f] = S::load(dep_in + ((iy + 1) * gd + ix + 1) * 2 + c);
+  }
+  for (int k = tid; k < nT; k += nt)
+    L.cnt[k] = k < nI ? io.irr_n_in[(size_t)i * nI + k] : io.dep_n_in[(size_t)i * nD + (k - nI)];
+
+  const uint32_t off = v.offsets[i];
+  const uint32_t n = v.offsets[i + 1] - off;
+  const float inv_s = 1.0f / v.s_diag;
+  for (uint32_t c0 = 0; c0 < n; c0 += (uint32_t)chunk) {
+    const int m = (int)min((uint32_t)chunk, n - c0);
+    for (int k = tid; k < nT; k += nt) L.hist[k] = 0u;
+    for (int j = tid; j < m; j += nt) L.rec[j] = v.rec[off + c0 + j];
+    __syncthreads();
+    for (int j = tid; j < m; j += nt) {
+      float3 d = sf_direction(c0 + (uint32_t)j, n, fp.R);
+      float2 uv = oct_encode(d);
+      uint32_t bI = oct_bin(uv, ri), bD = oct_bin(uv, rd);
+      L.bins[j] = (uint16_t)bI;
+      L.bins[chunk + j] = (uint16_t)(nI + bD);
+      atomicAdd(&L.hist[bI], 1u);
+      atomicAdd(&L.hist[nI + bD], 1u);
+      if (fp.debug) {
+        v.dbg_ibin[off + c0 + j] = (uint16_t)bI;
+        v.dbg_dbin[off + c0 + j] = (uint16_t)bD;
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the histogram over the combined texel space
+    const int seg = (nT + nt - 1) / nt, sb = tid * seg, se = min(nT, sb + seg);
+    uint32_t loc = 0;
+    for (int k = sb; k < se; ++k) loc += L.hist[k];
+    uint32_t tot;
+    uint32_t base = block_scan_u32(loc, L.scan, tot);
+    for (int k = sb; k < se; ++k) {
+      L.start[k] = base;
+      L.cursor[k] = base;
+      base += L.hist[k];
+    }
+    __syncthreads();
+    for (int j = tid; j < m; j += nt) {
+      uint32_t p = atomicAdd(&L.cursor[L.bins[j]], 1u);
+      L.list[p] = (uint16_t)j;
+      p = atomicAdd(&L.cursor[L.bins[chunk + j]], 1u);
+      L.list[p] = (uint16_t)j;
+    }
+    __syncthreads();
+    for (int k = tid; k < nT; k += nt) {
+      const uint32_t s = L.start[k], e = s + L.hist[k];
+      // restore ascending ray order within the texel
+      for (uint32_t a = s + 1; a < e; ++a) {
+        uint16_t key = L.list[a];
+        uint32_t b = a;
+        while (b > s && L.list[b - 1] > key) {
+          L.list[b] = L.list[b - 1];
+          --b;
+        }
+        L.list[b] = key;
+      }
+      uint32_t N = L.cnt[k];
+      if (k < nI) {
+        float V0 = L.stI[3 * k], V1 = L.stI[3 * k + 1], V2 = L.stI[3 * k + 2];
+        for (uint32_t a = s; a < e; ++a) {
+          float4 r = L.rec[L.list[a]];
+          float al = fmaxf(1.0f / (float)(N + 1u), v.one_minus_h);
+          V0 = fmaf(al, r.x - V0, V0);
+          V1 = fmaf(al, r.y - V1, V1);
+          V2 = fmaf(al, r.z - V2, V2);
+          N = min(N + 1u, 255u);
+        }
+        L.stI[3 * k] = V0;
+        L.stI[3 * k + 1] = V1;
+        L.stI[3 * k + 2] = V2;
+      } else {
+        const int kd = k - nI;
+        float V0 = L.stD[2 * kd], V1 = L.stD[2 * kd + 1];
+        for (uint32_t a = s; a < e; ++a) {
+          float t = L.rec[L.list[a]].w;
+          float tau = fminf(t * inv_s, v.tau_max);
+          float al = fmaxf(1.0f / (float)(N + 1u), v.one_minus_h);
+          V0 = fmaf(al, tau - V0, V0);
+          V1 = fmaf(al, tau * tau - V1, V1);
+          N = min(N + 1u, 255u);
+        }
+        L.stD[2 * kd] = V0;
+        L.stD[2 * kd + 1] = V1;
+      }
+      L.cnt[k] = N;
+    }
+    __syncthreads();
+  }
+
+  // ---- write both tiles with the border fold, then the counts
+  T* irr_out = (T*)io.irr_out + (size_t)i * gi * gi * 3;
+  T* dep_out = (T*)io.dep_out + (size_t)i * gd * gd * 2;
+  __syncthreads();
+  for (int f = tid; f < gi * gi * 3; f += nt) {
+    int t = f / 3, c = f - 3 * t, Y = t / gi, X = t - Y * gi, sx, sy;
+    border_source(X, Y, ri, sx, sy);
+    S::store(irr_out + f, L.stI[((sy - 1) * ri + (sx - 1)) * 3 + c]);
+  }
+  for (int f = tid; f < gd * gd * 2; f += nt) {
+    int t = f >> 1, c = f & 1, Y = t / gd, X = t - Y * gd, sx, sy;
+    border_source(X, Y, rd, sx, sy);
+    S::store(dep_out + f, L.stD[((sy - 1) * rd + (sx - 1)) * 2 + c]);
+  }
+  for (int k = tid; k < nT; k += nt) {
+    uint8_t c = (uint8_t)L.cnt[k];
+    if (k < nI) io.irr_n_out[(size_t)i * nI + k] = c;
+    else io.dep_n_out[(size_t)i * nD + (k - nI)] = c;
+  }
+}
+
+size_t blend_lds_bytes(const VolumeView& v, int chunk) {
+  return blend_layout(v.irr_res, v.dep_res, chunk, nullptr, nullptr);
+}
+
+hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk) {
+  size_t lds = blend_lds_bytes(v, chunk);
+  if (fp16)
+    hipLaunchKernelGGL(blend_kernel<true>, dim3(v.P), dim3(256), lds, s, v, io, chunk);
+  else
+    hipLaunchKernelGGL(blend_kernel<false>, dim3(v.P), dim3(256), lds, s, v, io, chunk);
+  return hipGetLastError();
+}
+
+}  // namespace adgi

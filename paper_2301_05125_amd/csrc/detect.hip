@@ -1,0 +1,115 @@
+// detect.hip - per-frame setup and change detection -> per-probe scores.
+//
+// On the second frame of each pair (odd t) the pilot codes of this frame and
+// the previous one give the temporal gradient d = |Q_t - Q_{t-1}| of probe
+// visibility and radiance (eq. tempGradVis, eq. tempGradIrr), the temporal
+// trigger T <- max(d, T - ceil(1023/theta)) turns a change into a linearly
+// decaying signal (Sec. 4.1.4), and an unnormalised 5x5x5 box sum over
+// probes, zero padded, spreads it in space (the spatial convolution of
+// Sec. 4.1.4-4.1.5; the directional part is per probe a constant and is
+// dropped). The score sum_k Qv (Cv + mu Cr) is the dynamic composition
+// f_v (f_dv + mu f_dr) of eq. priorDynamic, summed over the eight octants.
+// Everything after the 10-bit codes is integer arithmetic, so the result is
+// exact. The box sum is separable: three 5-tap passes along x, y and z.
+#include "adgi_internal.hpp"
+
+namespace adgi {
+
+__global__ void frame_begin_kernel(VolumeView v) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  FrameStats* st = v.stats;
+  if (tid < 4 * kAllocCandidates) (&st->sums[0][0])[tid] = 0ull;
+  if (tid == 0) {
+    st->ray_counter = 0u;
+    st->pilot_counter = 0u;
+    st->shadow_rays = 0ull;
+    st->max_score = 0ull;
+    st->lambda = 0u;
+    st->n_min_seen = 0;
+    st->n_max_seen = 0;
+    st->budget_used = 0ull;
+  }
+  if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;
+}
+
+__global__ void trigger_kernel(VolumeView v) {
+  const FrameParams& fp = *v.fp;
+  if (!fp.adaptive || (fp.frame & 1) == 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 8 * v.P) return;
+  const int delta = (1023 + fp.theta - 1) / fp.theta;
+  int dv = abs((int)v.qv[1][e] - (int)v.qv[0][e]);
+  int dr = abs((int)v.qr[1][e] - (int)v.qr[0][e]);
+  int2 t = v.trig[e];
+  t.x = max(dv, t.x - delta);
+  t.y = max(dr, t.y - delta);
+  v.trig[e] = t;
+}
+
+// 5-tap sum along one grid axis; element e = probe * 8 + octant.
+__global__ void box_pass_kernel(VolumeView v, const int2* __restrict__ src, int2* __restrict__ dst,
+                                int axis) {
+  const FrameParams& fp = *v.fp;
+  if (!fp.adaptive || (fp.frame & 1) == 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 8 * v.P) return;
+  const int i = e >> 3;
+  int c, D, stride;
+  if (axis == 0) {
+    c = i % v.dx;
+    D = v.dx;
+    stride = 8;
+  } else if (axis == 1) {
+    c = (i / v.dx) % v.dy;
+    D = v.dy;
+    stride = 8 * v.dx;
+  } else {
+    c = i / (v.dx * v.dy);
+    D = v.dz;
+    stride = 8 * v.dx * v.dy;
+  }
+  int sx = 0, sy = 0;
+  for (int o = -2; o <= 2; ++o) {
+    int cc = c + o;
+    if (cc < 0 || cc >= D) continue;
+    int2 t = src[e + o * stride];
+    sx += t.x;
+    sy += t.y;
+  }
+  dst[e] = make_int2(sx, sy);
+}
+
+__global__ void score_kernel(VolumeView v) {
+  const FrameParams& fp = *v.fp;
+  if (!fp.adaptive || (fp.frame & 1) == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.P) return;
+  const int64_t mu = fp.mu;
+  int64_t s = 0;
+  for (int k = 0; k < 8; ++k) {
+    int2 c = v.box_b[8 * i + k];
+    s += (int64_t)v.qv[1][8 * i + k] * ((int64_t)c.x + mu * (int64_t)c.y);
+  }
+  v.score[i] = s;
+}
+
+hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s) {
+  int n = v.P > 4 * kAllocCandidates ? v.P : 4 * kAllocCandidates;
+  hipLaunchKernelGGL(frame_begin_kernel, dim3((n + 255) / 256), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect(const VolumeView& v, hipStream_t s) {
+  const int n = 8 * v.P, g = (n + 255) / 256;
+  hipLaunchKernelGGL(trigger_kernel, dim3(g), dim3(256), 0, s, v);
+  // box: trig -> a (x) -> b (y) -> a (z) ; score reads b, so run z into b
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.trig, v.box_a, 0);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_a, v.box_b, 1);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_b, v.box_a, 2);
+  VolumeView w = v;
+  w.box_b = v.box_a;  // score reads the z-pass output
+  hipLaunchKernelGGL(score_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+}  // namespace adgi

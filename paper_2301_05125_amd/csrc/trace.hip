@@ -1,0 +1,337 @@
+// trace.hip - probe-ray and pilot-ray traversal, direct light and shadow rays.
+//
+// One kernel template serves both ray sources:
+//   KIND_PRIMARY: ray r of probe i is the j-th point of a rotated spherical
+//     Fibonacci set of n_i directions (r = offsets[i] + j); output one 16-byte
+//     record (radiance RGB, hit distance) per ray.
+//   KIND_PILOT:   ray r = 8i + k is the pilot of octant k (Sec. 4.1, 4.4);
+//     output the 10-bit codes of f_v = exp(-2t/s) (eq. ProbeVis) and
+//     f_r = min(lum, beta)/beta (Sec. 4.1.3).
+// Rays are handed out 64 at a time to waves from a global counter (persistent
+// work-stealing launch) or one per thread (plain launch). Traversal is a BVH2
+// while-while loop with a short per-lane stack in LDS (deeper entries in
+// private memory) and optionally the top nodes staged in LDS. Shadow rays of a
+// wave's front-face hits are compacted with ballot/prefix into a wave-local
+// LDS queue and traced by all 64 lanes together.
+#include "adgi_internal.hpp"
+
+namespace adgi {
+
+enum { KIND_PRIMARY = 0, KIND_PILOT = 1 };
+
+struct Stack {
+  int* lds;       // this lane's slot 0; entry k at lds[k * stride]
+  int stride;
+  int sp;
+  int deep[kStackMax - kStackLds];
+  __device__ __forceinline__ void push(int v) {
+    if (sp < kStackLds) lds[sp * stride] = v;
+    else deep[sp - kStackLds] = v;
+    ++sp;
+  }
+  __device__ __forceinline__ int pop() {
+    --sp;
+    return sp < kStackLds ? lds[sp * stride] : deep[sp - kStackLds];
+  }
+};
+
+struct NodeData {
+  float4 a, b, c;
+  int left, right;
+};
+
+__device__ __forceinline__ NodeData fetch_node(const float4* __restrict__ nodes,
+                                               const float4* top, int ntop, int idx) {
+  NodeData n;
+  const float4* src = idx < ntop ? top + 4 * idx : nodes + 4 * (size_t)idx;
+  n.a = src[0];
+  n.b = src[1];
+  n.c = src[2];
+  float4 d = src[3];
+  n.left = __float_as_int(d.x);
+  n.right = __float_as_int(d.y);
+  return n;
+}
+
+// Closest hit: smallest t in (0, inf); equal t resolves to the lowest
+// original triangle index. Returns the triangle slot or -1.
+__device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, const Ray& ray,
+                           Stack& st, float& t_best, bool& front_best, int& id_best) {
+  t_best = INFINITY;
+  id_best = 0x7fffffff;
+  int slot_best = -1;
+  front_best = false;
+  st.sp = 0;
+  int node = 0;
+  for (;;) {
+    while (node >= 0) {
+      NodeData nd = fetch_node(v.nodes, top, ntop, node);
+      float tl, tr;
+      bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, t_best, tl);
+      bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, t_best, tr);
+      if (hl && hr) {
+        bool lf = tl <= tr;
+        st.push(lf ? nd.right : nd.left);
+        node = lf ? nd.left : nd.right;
+      } else if (hl) {
+        node = nd.left;
+      } else if (hr) {
+        node = nd.right;
+      } else {
+        if (st.sp == 0) return slot_best;
+        node = st.pop();
+      }
+    }
+    int code = ~node;
+    int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+    for (int k = 0; k < count; ++k) {
+      const float4* tp = v.tris + 3 * (size_t)(first + k);
+      float4 a = tp[0], b = tp[1], c = tp[2];
+      float t;
+      bool fr;
+      if (tri_hit(ray, a, b, c, 0.0f, t_best, t, fr)) {
+        int id = __float_as_int(a.w);
+        if (t < t_best || id < id_best) {
+          t_best = t;
+          id_best = id;
+          slot_best = first + k;
+          front_best = fr;
+        }
+      }
+    }
+    if (st.sp == 0) return slot_best;
+    node = st.pop();
+  }
+}
+
+// Any hit on (0, tmax].
+__device__ bool any_hit(const VolumeView& v, const float4* top, int ntop, const Ray& ray,
+                        float tmax, Stack& st) {
+  st.sp = 0;
+  int node = 0;
+  for (;;) {
+    while (node >= 0) {
+      NodeData nd = fetch_node(v.nodes, top, ntop, node);
+      float tl, tr;
+      bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
+      bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
+      if (hl && hr) {
+        st.push(nd.right);
+        node = nd.left;
+      } else if (hl) {
+        node = nd.left;
+      } else if (hr) {
+        node = nd.right;
+      } else {
+        if (st.sp == 0) return false;
+        node = st.pop();
+      }
+    }
+    int code = ~node;
+    int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+    for (int k = 0; k < count; ++k) {
+      const float4* tp = v.tris + 3 * (size_t)(first + k);
+      float t;
+      bool fr;
+      if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
+    }
+    if (st.sp == 0) return false;
+    node = st.pop();
+  }
+}
+
+// First probe i with offsets[i+1] > r (offsets ascending, offsets[0] = 0).
+__device__ __forceinline__ int probe_of_ray(const uint32_t* __restrict__ off, int P, uint32_t r) {
+  int lo = 0, hi = P - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ float3 probe_position(const VolumeView& v, int i) {
+  int x = i % v.dx, y = (i / v.dx) % v.dy, z = i / (v.dx * v.dy);
+  return make_float3(fmaf((float)x, v.sx, v.ox), fmaf((float)y, v.sy, v.oy),
+                     fmaf((float)z, v.sz, v.oz));
+}
+
+template <int KIND>
+__device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Stack& st,
+                           uint16_t* queue, uint32_t* vis, uint32_t base, uint32_t total) {
+  const FrameParams& fp = *v.fp;
+  const SceneParams& sc = *v.scene;
+  const uint32_t lane = lane_id();
+  const uint32_t r = base + lane;
+  const bool active = r < total;
+
+  // ---- ray generation
+  float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
+  if (active) {
+    if (KIND == KIND_PRIMARY) {
+      int i = probe_of_ray(v.offsets, v.P, r);
+      uint32_t b = v.offsets[i], n = v.offsets[i + 1] - b;
+      o = probe_position(v, i);
+      d = sf_direction(r - b, n, fp.R);
+    } else {
+      uint32_t i = r >> 3, k = r & 7;
+      o = probe_position(v, (int)i);
+      d = pilot_direction(fp.seed, i, k, (uint32_t)fp.frame >> 1);
+    }
+  }
+
+  // ---- closest hit
+  float t = INFINITY;
+  bool front = false;
+  int id = -1, slot = -1;
+  if (active && sc.num_tris > 0) {
+    Ray ray = make_ray(o, d);
+    slot = closest_hit(v, top, ntop, ray, st, t, front, id);
+    if (slot < 0) {
+      id = -1;
+      t = INFINITY;
+    }
+  }
+
+  // ---- direct light at front-face hits, shadow rays compacted per wave
+  const bool lit_hit = active && slot >= 0 && front;
+  float3 x = make_float3(0.f, 0.f, 0.f), nrm = make_float3(0.f, 0.f, 0.f);
+  if (lit_hit) {
+    const float4* tp = v.tris + 3 * (size_t)slot;
+    float4 b = tp[1], c = tp[2];
+    float nx = b.y * c.z - b.z * c.y, ny = b.z * c.x - b.x * c.z, nz = b.x * c.y - b.y * c.x;
+    float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+    nrm = make_float3(nx * inv, ny * inv, nz * inv);
+    x = make_float3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
+  }
+  const int nl = sc.num_lights;
+  uint32_t qtotal = 0;
+  for (int l = 0; l < nl; ++l) {
+    bool need = false;
+    if (lit_hit) {
+      float lx = sc.lpos[l][0] - x.x, ly = sc.lpos[l][1] - x.y, lz = sc.lpos[l][2] - x.z;
+      need = nrm.x * lx + nrm.y * ly + nrm.z * lz > 0.0f;
+    }
+    uint64_t mask = ballot(need);
+    if (need) queue[qtotal + lanes_below(mask)] = (uint16_t)(lane | (l << 6));
+    qtotal += (uint32_t)__popcll(mask);
+  }
+  vis[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float off_len = kShadowOffset * v.s_diag;
+  for (uint32_t qb = 0; qb < qtotal; qb += 64) {
+    uint32_t q = qb + lane;
+    bool has = q < qtotal;
+    uint32_t e = has ? queue[q] : 0u;
+    int src = (int)(e & 63u), l = (int)(e >> 6);
+    float sx = __shfl(x.x, src), sy = __shfl(x.y, src), sz = __shfl(x.z, src);
+    float mx = __shfl(nrm.x, src), my = __shfl(nrm.y, src), mz = __shfl(nrm.z, src);
+    if (has) {
+      float3 so = make_float3(fmaf(off_len, mx, sx), fmaf(off_len, my, sy), fmaf(off_len, mz, sz));
+      float gx = sc.lpos[l][0] - so.x, gy = sc.lpos[l][1] - so.y, gz = sc.lpos[l][2] - so.z;
+      float len = sqrtf(gx * gx + gy * gy + gz * gz);
+      float il = 1.0f / len;
+      Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
+      bool blocked = any_hit(v, top, ntop, sray, len * (1.0f - kShadowShorten), st);
+      if (!blocked) atomicOr(&vis[src], 1u << l);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t bits = vis[lane];
+  if (lane == 0 && qtotal > 0) atomicAdd((unsigned long long*)&v.stats->shadow_rays, (unsigned long long)qtotal);
+
+  float3 L = make_float3(0.f, 0.f, 0.f);
+  if (active && slot < 0) {
+    L = make_float3(sc.sky[0], sc.sky[1], sc.sky[2]);
+  } else if (lit_hit) {
+    float er = 0.f, eg = 0.f, eb = 0.f;
+    for (int l = 0; l < nl; ++l) {
+      if (!((bits >> l) & 1u)) continue;
+      float lx = sc.lpos[l][0] - x.x, ly = sc.lpos[l][1] - x.y, lz = sc.lpos[l][2] - x.z;
+      float d2 = lx * lx + ly * ly + lz * lz;
+      float cs = (nrm.x * lx + nrm.y * ly + nrm.z * lz) / sqrtf(d2);
+      float w = fmaxf(cs, 0.0f) / d2;
+      er = fmaf(sc.lint[l][0], w, er);
+      eg = fmaf(sc.lint[l][1], w, eg);
+      eb = fmaf(sc.lint[l][2], w, eb);
+    }
+    float4 rho = v.albedo[id];
+    const float inv_pi = 0.318309886183790671538f;
+    L = make_float3(rho.x * inv_pi * er, rho.y * inv_pi * eg, rho.z * inv_pi * eb);
+  }
+
+  // ---- outputs
+  if (!active) return;
+  if (KIND == KIND_PRIMARY) {
+    v.rec[r] = make_float4(L.x, L.y, L.z, t);
+    if (fp.debug) {
+      v.dbg_tri[r] = id;
+      v.dbg_shadow[r] = (uint8_t)bits;
+    }
+  } else {
+    int qv = 0;
+    if (t < INFINITY) qv = min(1023, (int)floorf(1024.0f * expf(-2.0f * t / v.s_diag)));
+    float lum = 0.2126f * L.x + 0.7152f * L.y + 0.0722f * L.z;
+    int qr = min(1023, (int)floorf(1024.0f * (fminf(lum, fp.beta) / fp.beta)));
+    int slot_q = fp.frame & 1;
+    v.qv[slot_q][r] = (uint16_t)qv;
+    v.qr[slot_q][r] = (uint16_t)max(qr, 0);
+  }
+}
+
+template <int KIND>
+__global__ void trace_kernel(VolumeView v, int persistent, int ntop) {
+  extern __shared__ float4 smem[];
+  float4* top = smem;                                            // ntop * 4
+  int* stack_base = (int*)(smem + 4 * ntop);                     // kStackLds * blockDim
+  uint16_t* queues = (uint16_t*)(stack_base + kStackLds * blockDim.x);  // waves * 64 * kMaxLights
+  const int nwaves = blockDim.x >> 6;
+  uint32_t* vis_all = (uint32_t*)(queues + nwaves * 64 * kMaxLights);   // waves * 64
+  for (int k = threadIdx.x; k < 4 * ntop; k += blockDim.x) top[k] = v.nodes[k];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  Stack st;
+  st.lds = stack_base + threadIdx.x;
+  st.stride = blockDim.x;
+  st.sp = 0;
+  uint16_t* queue = queues + wave * 64 * kMaxLights;
+  uint32_t* vis = vis_all + wave * 64;
+  const uint32_t total = KIND == KIND_PRIMARY ? v.offsets[v.P] : 8u * (uint32_t)v.P;
+  if (persistent) {
+    uint32_t* counter = KIND == KIND_PRIMARY ? &v.stats->ray_counter : &v.stats->pilot_counter;
+    for (;;) {
+      uint32_t base = 0;
+      if (lane_id() == 0) base = atomicAdd(counter, 64u);
+      base = __shfl(base, 0);
+      if (base >= total) break;
+      trace_wave<KIND>(v, top, ntop, st, queue, vis, base, total);
+    }
+  } else {
+    uint32_t base = (blockIdx.x * blockDim.x) + (uint32_t)wave * 64u;
+    if (base < total) trace_wave<KIND>(v, top, ntop, st, queue, vis, base, total);
+  }
+}
+
+size_t trace_lds_bytes(int block, int ntop) {
+  return (size_t)ntop * 64 + (size_t)kStackLds * block * 4 + (size_t)(block / 64) * 64 * kMaxLights * 2 +
+         (size_t)(block / 64) * 64 * 4;
+}
+
+hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
+                        int grid, int ntop) {
+  size_t lds = trace_lds_bytes(block, ntop);
+  if (pilot)
+    hipLaunchKernelGGL(trace_kernel<KIND_PILOT>, dim3(grid), dim3(block), lds, s, v, persistent ? 1 : 0,
+                       ntop);
+  else
+    hipLaunchKernelGGL(trace_kernel<KIND_PRIMARY>, dim3(grid), dim3(block), lds, s, v,
+                       persistent ? 1 : 0, ntop);
+  return hipGetLastError();
+}
+
+}  // namespace adgi

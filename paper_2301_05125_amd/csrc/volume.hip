@@ -1,0 +1,950 @@
+// volume.hip - host runtime behind the C ABI declared in include/adgi.h.
+//
+// A volume owns one non-blocking HIP stream (default priority) and all device
+// state, allocated through the caller's allocator. A frame is the kernel
+// sequence frame_begin -> [pilot trace -> detect -> allocate | uniform
+// offsets] -> primary trace -> blend, captured once per mode as a hipGraph and
+// relaunched every frame; only the 128-byte parameter block is copied per
+// frame (outside the graph, from a ring of pinned host slots). All counts stay
+// on the device, so nothing is read back inside a frame.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <tuple>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/adgi.h"
+#include "adgi_internal.hpp"
+
+using namespace adgi;
+
+namespace {
+
+thread_local std::string g_err;
+
+adgi_status fail(adgi_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+adgi_status fail(adgi_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+constexpr int kParamSlots = 8;
+
+void* default_alloc(size_t bytes, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+void default_free(void* p, void*) { (void)hipFree(p); }
+
+// Per-frame rotation: Shoemake's uniform random rotation from three uniforms
+// of the counter-based stream (seed, "ROT", frame); FP64, rounded to FP32.
+uint64_t host_splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+void frame_rotation(uint64_t seed, int32_t frame, float R[9]) {
+  uint64_t h = host_splitmix64(seed ^ kTagRotation);
+  h = host_splitmix64(h ^ (uint64_t)(uint32_t)frame);
+  h = host_splitmix64(h ^ 0ull);
+  h = host_splitmix64(h ^ 0ull);
+  double u[3];
+  for (int q = 0; q < 3; ++q) u[q] = (double)(host_splitmix64(h ^ (uint64_t)(q + 1)) >> 40) * 0x1p-24;
+  const double twopi = 6.283185307179586476925286766559;
+  double s1 = std::sqrt(1.0 - u[0]), s2 = std::sqrt(u[0]);
+  double qx = s1 * std::sin(twopi * u[1]), qy = s1 * std::cos(twopi * u[1]);
+  double qz = s2 * std::sin(twopi * u[2]), qw = s2 * std::cos(twopi * u[2]);
+  double m[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qz * qw), 2.0 * (qx * qz + qy * qw),
+                 2.0 * (qx * qy + qz * qw), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qx * qw),
+                 2.0 * (qx * qz - qy * qw), 2.0 * (qy * qz + qx * qw), 1.0 - 2.0 * (qx * qx + qy * qy)};
+  for (int k = 0; k < 9; ++k) R[k] = (float)m[k];
+}
+
+float half_bits_to_float(uint16_t h) {
+  uint32_t sign = (uint32_t)(h >> 15) << 31, e = (h >> 10) & 31u, m = h & 1023u, bits;
+  if (e == 0) {
+    if (m == 0) {
+      bits = sign;
+    } else {  // subnormal: normalise
+      int sh = 0;
+      while (!(m & 1024u)) {
+        m <<= 1;
+        ++sh;
+      }
+      m &= 1023u;
+      bits = sign | ((uint32_t)(127 - 15 + 1 - sh) << 23) | (m << 13);
+    }
+  } else if (e == 31) {
+    bits = sign | 0x7F800000u | (m << 13);
+  } else {
+    bits = sign | ((e - 15 + 127) << 23) | (m << 13);
+  }
+  float f;
+  std::memcpy(&f, &bits, 4);
+  return f;
+}
+
+struct TuneKey {
+  int device, P_class, res, storage;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(device, P_class, res, storage) < std::tie(o.device, o.P_class, o.res, o.storage);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, adgi_tuning> g_tune_cache;
+
+}  // namespace
+
+struct adgi_volume {
+  adgi_volume_desc desc{};
+  adgi_allocator alloc{};
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_user = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  hipEvent_t ev_slot[kParamSlots] = {};
+  hipEvent_t ev_stage = nullptr;
+  int device = 0, num_cus = 256;
+  int32_t P = 0;
+  bool sticky = false;
+  std::vector<std::pair<void*, size_t>> allocs;
+  size_t dev_bytes = 0;
+  // pinned host
+  FrameParams* h_fp = nullptr;
+  FrameStats* h_stats = nullptr;
+  SceneParams* h_scene = nullptr;
+  float* h_stage = nullptr;  // vertex staging for refit uploads
+  size_t h_stage_floats = 0;
+  int slot = 0;
+  // device
+  VolumeView v{};
+  void *irr = nullptr, *dep = nullptr;
+  uint8_t *irr_n = nullptr, *dep_n = nullptr;
+  // scene
+  bool has_scene = false;
+  int32_t nv = 0, nt = 0, num_nodes = 0, num_leaf_slots = 0;
+  float* d_pos = nullptr;
+  int32_t* d_idx = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_leaf = nullptr;
+  uint32_t* d_arrive = nullptr;
+  float4* d_nodes = nullptr;
+  float4* d_tris = nullptr;
+  float4* d_albedo = nullptr;
+  std::vector<void*> scene_allocs;
+  float pad_abs = 0.f;
+  int bvh_depth = 0;
+  double last_build_ms = 0.0;
+  // frame
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  adgi_tuning tun{};
+  bool tuned = false;
+  int32_t last_frame = -1, last_adaptive = 0;
+  float last_R[9] = {};
+};
+
+namespace {
+
+#define HIP_TRY(vol, call)                                                                    \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      (vol)->sticky = true;                                                                   \
+      return fail(ADGI_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));            \
+    }                                                                                         \
+  } while (0)
+
+void* vol_alloc(adgi_volume* vol, size_t bytes, std::vector<void*>* group = nullptr) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes == 0) bytes = 256;
+  void* p = vol->alloc.alloc(bytes, vol->alloc.ctx);
+  if (!p) return nullptr;
+  vol->allocs.push_back({p, bytes});
+  vol->dev_bytes += bytes;
+  if (group) group->push_back(p);
+  return p;
+}
+
+void vol_free(adgi_volume* vol, void* p) {
+  if (!p) return;
+  for (size_t k = 0; k < vol->allocs.size(); ++k)
+    if (vol->allocs[k].first == p) {
+      vol->dev_bytes -= vol->allocs[k].second;
+      vol->allocs.erase(vol->allocs.begin() + k);
+      break;
+    }
+  vol->alloc.free(p, vol->alloc.ctx);
+}
+
+void drop_graphs(adgi_volume* vol) {
+  for (auto& e : vol->exec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+}
+
+int lds_top_nodes(const adgi_volume* vol) {
+  return std::min(vol->tun.lds_top_nodes, vol->num_nodes);
+}
+
+hipError_t enqueue_frame(adgi_volume* vol, bool adaptive) {
+  const adgi_tuning& t = vol->tun;
+  VolumeView& v = vol->v;
+  hipStream_t s = vol->stream;
+  hipError_t e;
+  const int ntop = lds_top_nodes(vol);
+  const int pgrid = std::max(1, vol->num_cus * t.trace_waves_per_cu / (t.trace_block / 64));
+  if ((e = launch_frame_begin(v, s)) != hipSuccess) return e;
+  if (adaptive) {
+    int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
+    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, ntop)) != hipSuccess) return e;
+    if ((e = launch_detect(v, s)) != hipSuccess) return e;
+    if ((e = launch_alloc(v, s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_uniform_offsets(v, s)) != hipSuccess) return e;
+  }
+  int grid = t.persistent ? pgrid
+                          : (int)((vol->desc.max_rays_per_frame + t.trace_block - 1) / t.trace_block);
+  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, ntop)) != hipSuccess) return e;
+  BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
+  return launch_blend(v, io, s, vol->desc.storage == ADGI_FP16, t.blend_chunk);
+}
+
+adgi_status order_after_user(adgi_volume* vol) {
+  if (vol->user_stream) {
+    HIP_TRY(vol, hipEventRecord(vol->ev_user, vol->user_stream));
+    HIP_TRY(vol, hipStreamWaitEvent(vol->stream, vol->ev_user, 0));
+  }
+  return ADGI_OK;
+}
+
+adgi_status order_user_after(adgi_volume* vol) {
+  HIP_TRY(vol, hipEventRecord(vol->ev_done, vol->stream));
+  if (vol->user_stream) HIP_TRY(vol, hipStreamWaitEvent(vol->user_stream, vol->ev_done, 0));
+  return ADGI_OK;
+}
+
+void free_scene(adgi_volume* vol) {
+  for (void* p : vol->scene_allocs) vol_free(vol, p);
+  vol->scene_allocs.clear();
+  vol->d_pos = nullptr;
+  vol->d_idx = vol->d_order = vol->d_leaf = nullptr;
+  vol->d_arrive = nullptr;
+  vol->d_nodes = vol->d_tris = vol->d_albedo = nullptr;
+  if (vol->h_stage) {
+    (void)hipHostFree(vol->h_stage);
+    vol->h_stage = nullptr;
+    vol->h_stage_floats = 0;
+  }
+}
+
+void release(adgi_volume* vol) {
+  if (vol->stream) (void)hipStreamSynchronize(vol->stream);
+  drop_graphs(vol);
+  free_scene(vol);
+  while (!vol->allocs.empty()) vol_free(vol, vol->allocs.back().first);
+  if (vol->h_fp) (void)hipHostFree(vol->h_fp);
+  if (vol->h_stats) (void)hipHostFree(vol->h_stats);
+  if (vol->h_scene) (void)hipHostFree(vol->h_scene);
+  for (auto& e : vol->ev_slot)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage})
+    if (e) (void)hipEventDestroy(e);
+  if (vol->stream) (void)hipStreamDestroy(vol->stream);
+}
+
+bool finite3(const float* x) { return std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]); }
+
+adgi_tuning default_tuning() {
+  adgi_tuning t;
+  t.use_graph = 1;
+  t.persistent = 1;
+  t.trace_block = 256;
+  t.trace_waves_per_cu = 16;
+  t.blend_chunk = 256;
+  t.lds_top_nodes = 0;
+  return t;
+}
+
+bool tuning_valid(const adgi_tuning& t) {
+  return (t.use_graph == 0 || t.use_graph == 1) && (t.persistent == 0 || t.persistent == 1) &&
+         t.trace_block >= 64 && t.trace_block <= 1024 && t.trace_block % 64 == 0 &&
+         t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 && t.blend_chunk >= 64 &&
+         t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0 && t.lds_top_nodes >= 0 &&
+         t.lds_top_nodes <= 1024;
+}
+
+}  // namespace
+
+namespace {
+// ---- snapshots
+struct Part {
+  void* dev;
+  size_t bytes;
+};
+std::vector<Part> state_parts(adgi_volume* vol) {
+  const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res, ri = gi - 2, rd = gd - 2;
+  const size_t el = vol->desc.storage == ADGI_FP16 ? 2 : 4;
+  return {{vol->irr, P * gi * gi * 3 * el}, {vol->dep, P * gd * gd * 2 * el}, {vol->irr_n, P * ri * ri},
+          {vol->dep_n, P * rd * rd},         {vol->v.qv[0], P * 16},           {vol->v.qv[1], P * 16},
+          {vol->v.qr[0], P * 16},            {vol->v.qr[1], P * 16},           {vol->v.trig, P * 64},
+          {vol->v.score, P * 8},             {vol->v.n, P * 4},                {vol->v.offsets, (P + 1) * 4}};
+}
+constexpr uint64_t kSnapMagic = 0x5041534E49474441ull;  // "ADGINSAP"
+struct SnapHeader {
+  uint64_t magic;
+  int32_t P, irr_res, depth_res, storage;
+  int32_t last_frame, last_adaptive;
+  float last_R[9];
+  int32_t pad;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* adgi_last_error(void) { return g_err.c_str(); }
+
+adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* alloc, void* hip_stream,
+                               adgi_volume** out) {
+  if (!d || !out) return fail(ADGI_ERR_INVALID_ARG, "desc and out must not be NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (d->dims[a] < 1) return fail(ADGI_ERR_INVALID_ARG, "dims[%d] = %d < 1", a, d->dims[a]);
+    if (!(d->spacing[a] > 0.f) || !std::isfinite(d->spacing[a]))
+      return fail(ADGI_ERR_INVALID_ARG, "spacing[%d] must be finite and > 0", a);
+  }
+  if (!finite3(d->origin)) return fail(ADGI_ERR_INVALID_ARG, "origin must be finite");
+  int64_t P = (int64_t)d->dims[0] * d->dims[1] * d->dims[2];
+  if (P > (1 << 24)) return fail(ADGI_ERR_INVALID_ARG, "P = %lld exceeds 2^24", (long long)P);
+  if (d->irr_res < 3 || d->irr_res > 34 || d->depth_res < 3 || d->depth_res > 34)
+    return fail(ADGI_ERR_INVALID_ARG, "irr_res/depth_res must be in [3, 34]");
+  if (d->storage != ADGI_FP32 && d->storage != ADGI_FP16)
+    return fail(ADGI_ERR_INVALID_ARG, "storage must be ADGI_FP32 or ADGI_FP16");
+  if (!(d->hysteresis >= 0.f && d->hysteresis < 1.f))
+    return fail(ADGI_ERR_INVALID_ARG, "hysteresis must be in [0, 1)");
+  if (!(d->tau_max > 0.f) || !std::isfinite(d->tau_max))
+    return fail(ADGI_ERR_INVALID_ARG, "tau_max must be finite and > 0");
+  if (d->max_rays_per_frame < 1 || d->max_rays_per_frame >= (int64_t)1 << 31)
+    return fail(ADGI_ERR_INVALID_ARG, "max_rays_per_frame must be in [1, 2^31)");
+  if (d->flags & ~(uint32_t)ADGI_DEBUG_ARRAYS) return fail(ADGI_ERR_INVALID_ARG, "unknown flags");
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(ADGI_ERR_INVALID_ARG, "allocator needs both alloc and free");
+
+  adgi_volume* vol = new adgi_volume();
+  vol->desc = *d;
+  vol->alloc = alloc ? *alloc : adgi_allocator{default_alloc, default_free, nullptr};
+  vol->user_stream = (hipStream_t)hip_stream;
+  vol->P = (int32_t)P;
+  vol->tun = default_tuning();
+  auto bail = [&](adgi_status s) {
+    release(vol);
+    delete vol;
+    return s;
+  };
+#define CREATE_TRY(call)                                                                        \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      adgi_status st_ = fail(ADGI_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
+      return bail(st_);                                                                         \
+    }                                                                                           \
+  } while (0)
+  CREATE_TRY(hipGetDevice(&vol->device));
+  CREATE_TRY(hipDeviceGetAttribute(&vol->num_cus, hipDeviceAttributeMultiprocessorCount, vol->device));
+  CREATE_TRY(hipStreamCreateWithFlags(&vol->stream, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_t0, &vol->ev_t1, &vol->ev_stage})
+    CREATE_TRY(hipEventCreate(e));
+  for (auto& e : vol->ev_slot) CREATE_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  CREATE_TRY(hipHostMalloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots, hipHostMallocDefault));
+  CREATE_TRY(hipHostMalloc((void**)&vol->h_stats, sizeof(FrameStats), hipHostMallocDefault));
+  CREATE_TRY(hipHostMalloc((void**)&vol->h_scene, sizeof(SceneParams), hipHostMallocDefault));
+  std::memset(vol->h_fp, 0, sizeof(FrameParams) * kParamSlots);
+  std::memset(vol->h_scene, 0, sizeof(SceneParams));
+
+  const size_t gi = d->irr_res, gd = d->depth_res, ri = gi - 2, rd = gd - 2;
+  const size_t el = d->storage == ADGI_FP16 ? 2 : 4;
+  const size_t R = (size_t)d->max_rays_per_frame;
+  const bool dbg = d->flags & ADGI_DEBUG_ARRAYS;
+  VolumeView& v = vol->v;
+  struct Req {
+    void** p;
+    size_t bytes;
+  };
+  std::vector<Req> reqs = {
+      {&vol->irr, (size_t)P * gi * gi * 3 * el},
+      {&vol->dep, (size_t)P * gd * gd * 2 * el},
+      {(void**)&vol->irr_n, (size_t)P * ri * ri},
+      {(void**)&vol->dep_n, (size_t)P * rd * rd},
+      {(void**)&v.fp, sizeof(FrameParams)},
+      {(void**)&v.scene, sizeof(SceneParams)},
+      {(void**)&v.stats, sizeof(FrameStats)},
+      {(void**)&v.qv[0], (size_t)P * 16},
+      {(void**)&v.qv[1], (size_t)P * 16},
+      {(void**)&v.qr[0], (size_t)P * 16},
+      {(void**)&v.qr[1], (size_t)P * 16},
+      {(void**)&v.trig, (size_t)P * 64},
+      {(void**)&v.box_a, (size_t)P * 64},
+      {(void**)&v.box_b, (size_t)P * 64},
+      {(void**)&v.score, (size_t)P * 8},
+      {(void**)&v.n, (size_t)P * 4},
+      {(void**)&v.offsets, (size_t)(P + 1) * 4},
+      {(void**)&v.rec, R * 16},
+  };
+  if (dbg) {
+    reqs.push_back({(void**)&v.dbg_tri, R * 4});
+    reqs.push_back({(void**)&v.dbg_shadow, R});
+    reqs.push_back({(void**)&v.dbg_ibin, R * 2});
+    reqs.push_back({(void**)&v.dbg_dbin, R * 2});
+  }
+  for (auto& r : reqs) {
+    *r.p = vol_alloc(vol, r.bytes);
+    if (!*r.p) {
+      g_err = "allocator returned NULL";
+      return bail(ADGI_ERR_OUT_OF_MEMORY);
+    }
+  }
+  // zero the temporal state
+  for (auto& r : reqs) CREATE_TRY(hipMemsetAsync(*r.p, 0, r.bytes, vol->stream));
+  CREATE_TRY(hipStreamSynchronize(vol->stream));
+#undef CREATE_TRY
+  v.ox = d->origin[0];
+  v.oy = d->origin[1];
+  v.oz = d->origin[2];
+  v.sx = d->spacing[0];
+  v.sy = d->spacing[1];
+  v.sz = d->spacing[2];
+  v.dx = d->dims[0];
+  v.dy = d->dims[1];
+  v.dz = d->dims[2];
+  v.P = (int32_t)P;
+  {
+    double s2 = 0.0;
+    for (int a = 0; a < 3; ++a) s2 += (double)d->spacing[a] * (double)d->spacing[a];
+    v.s_diag = (float)std::sqrt(s2);
+  }
+  v.irr_res = d->irr_res;
+  v.dep_res = d->depth_res;
+  v.one_minus_h = (float)(1.0 - (double)d->hysteresis);
+  v.tau_max = d->tau_max;
+  v.max_rays = (uint32_t)R;
+  *out = vol;
+  return ADGI_OK;
+}
+
+void adgi_destroy_volume(adgi_volume* vol) {
+  if (!vol) return;
+  release(vol);
+  delete vol;
+}
+
+adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
+  if (!vol || !sc) return fail(ADGI_ERR_INVALID_ARG, "volume and scene must not be NULL");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (sc->num_lights < 0 || sc->num_lights > ADGI_MAX_LIGHTS)
+    return fail(ADGI_ERR_INVALID_ARG, "num_lights must be in [0, %d]", ADGI_MAX_LIGHTS);
+  if (sc->num_lights > 0 && (!sc->light_pos || !sc->light_intensity))
+    return fail(ADGI_ERR_INVALID_ARG, "light arrays must not be NULL");
+  for (int l = 0; l < sc->num_lights; ++l)
+    if (!finite3(sc->light_pos + 3 * l) || !finite3(sc->light_intensity + 3 * l))
+      return fail(ADGI_ERR_INVALID_ARG, "light %d is not finite", l);
+  if (!finite3(sc->sky)) return fail(ADGI_ERR_INVALID_ARG, "sky must be finite");
+  if (sc->num_vertices < 0 || sc->num_triangles < 0)
+    return fail(ADGI_ERR_INVALID_ARG, "negative vertex or triangle count");
+  if (sc->num_triangles > (1 << 27) - 1)
+    return fail(ADGI_ERR_INVALID_ARG, "at most 2^27-1 triangles");
+  if (sc->num_vertices > 0 && !sc->positions) return fail(ADGI_ERR_INVALID_ARG, "positions is NULL");
+  if (sc->mode != ADGI_SCENE_REBUILD && sc->mode != ADGI_SCENE_REFIT)
+    return fail(ADGI_ERR_INVALID_ARG, "unknown scene mode");
+  const bool refit = sc->mode == ADGI_SCENE_REFIT;
+  if (refit) {
+    if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "REFIT before any REBUILD");
+    if (sc->num_vertices != vol->nv || sc->num_triangles != vol->nt)
+      return fail(ADGI_ERR_TOPOLOGY, "REFIT changes V (%d -> %d) or T (%d -> %d)", vol->nv,
+                  sc->num_vertices, vol->nt, sc->num_triangles);
+    if (sc->refit_vertex_begin < 0 || sc->refit_vertex_end < sc->refit_vertex_begin ||
+        sc->refit_vertex_end > sc->num_vertices)
+      return fail(ADGI_ERR_INVALID_ARG, "refit vertex range out of bounds");
+  } else {
+    if (sc->num_triangles > 0 && (!sc->indices || !sc->albedo))
+      return fail(ADGI_ERR_INVALID_ARG, "indices/albedo are NULL");
+    for (int64_t k = 0; k < 3 * (int64_t)sc->num_triangles; ++k)
+      if (sc->indices[k] < 0 || sc->indices[k] >= sc->num_vertices)
+        return fail(ADGI_ERR_INVALID_ARG, "index %lld out of range", (long long)k);
+  }
+  const int64_t vb = refit ? sc->refit_vertex_begin : 0, ve = refit ? sc->refit_vertex_end : sc->num_vertices;
+  for (int64_t k = 3 * vb; k < 3 * ve; ++k)
+    if (!std::isfinite(sc->positions[k])) return fail(ADGI_ERR_INVALID_ARG, "vertex %lld not finite", (long long)(k / 3));
+
+  adgi_status st = order_after_user(vol);
+  if (st != ADGI_OK) return st;
+  // scene constants: staged in pinned memory; the previous copy must be done
+  HIP_TRY(vol, hipEventSynchronize(vol->ev_stage));
+  SceneParams& hp = *vol->h_scene;
+  std::memset(&hp, 0, sizeof(hp));
+  for (int l = 0; l < sc->num_lights; ++l)
+    for (int a = 0; a < 3; ++a) {
+      hp.lpos[l][a] = sc->light_pos[3 * l + a];
+      hp.lint[l][a] = sc->light_intensity[3 * l + a];
+    }
+  for (int a = 0; a < 3; ++a) hp.sky[a] = sc->sky[a];
+  hp.num_lights = sc->num_lights;
+  hp.num_tris = sc->num_triangles;
+
+  if (!refit) {
+    // coordinate scale of the scene and the grid for conservative box padding
+    double scale = 0.0;
+    for (int64_t k = 0; k < 3 * (int64_t)sc->num_vertices; ++k) scale = std::max(scale, (double)std::fabs(sc->positions[k]));
+    for (int a = 0; a < 3; ++a) {
+      double far = std::fabs((double)vol->desc.origin[a]) +
+                   std::fabs((double)vol->desc.spacing[a]) * (vol->desc.dims[a] - 1);
+      scale = std::max(scale, far);
+    }
+    for (int l = 0; l < sc->num_lights; ++l)
+      for (int a = 0; a < 3; ++a) scale = std::max(scale, (double)std::fabs(sc->light_pos[3 * l + a]));
+    const float pad_abs = (float)(scale * 1e-6) + 1e-30f;
+    BvhHost bvh;
+    const char* err = "";
+    auto t0 = std::chrono::steady_clock::now();
+    if (!build_bvh(sc->positions, sc->num_vertices, sc->indices, sc->num_triangles, pad_abs, bvh, &err))
+      return fail(ADGI_ERR_INVALID_ARG, "BVH build failed: %s", err);
+    vol->last_build_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+    drop_graphs(vol);
+    free_scene(vol);
+    const int32_t nt = sc->num_triangles, nv = sc->num_vertices;
+    const int32_t nn = (int32_t)(bvh.nodes.size() / 4);
+    std::vector<void*>& g = vol->scene_allocs;
+    vol->d_pos = (float*)vol_alloc(vol, (size_t)nv * 12, &g);
+    vol->d_idx = (int32_t*)vol_alloc(vol, (size_t)nt * 12, &g);
+    vol->d_order = (int32_t*)vol_alloc(vol, (size_t)nt * 4, &g);
+    vol->d_leaf = (int32_t*)vol_alloc(vol, bvh.leaf_slots.size() * 4, &g);
+    vol->d_arrive = (uint32_t*)vol_alloc(vol, (size_t)nn * 4, &g);
+    vol->d_nodes = (float4*)vol_alloc(vol, bvh.nodes.size() * 16, &g);
+    vol->d_tris = (float4*)vol_alloc(vol, std::max<size_t>(bvh.tris.size(), 3) * 16, &g);
+    vol->d_albedo = (float4*)vol_alloc(vol, (size_t)std::max(nt, 1) * 16, &g);
+    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_leaf || !vol->d_arrive || !vol->d_nodes ||
+        !vol->d_tris || !vol->d_albedo) {
+      free_scene(vol);
+      vol->has_scene = false;
+      return fail(ADGI_ERR_OUT_OF_MEMORY, "allocator returned NULL for the scene");
+    }
+    std::vector<float4> alb((size_t)std::max(nt, 1), make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int32_t t = 0; t < nt; ++t) alb[t] = make_float4(sc->albedo[3 * t], sc->albedo[3 * t + 1], sc->albedo[3 * t + 2], 0.f);
+    // synchronous uploads (REBUILD is not on the per-frame path)
+    if (nv) HIP_TRY(vol, hipMemcpy(vol->d_pos, sc->positions, (size_t)nv * 12, hipMemcpyHostToDevice));
+    if (nt) {
+      HIP_TRY(vol, hipMemcpy(vol->d_idx, sc->indices, (size_t)nt * 12, hipMemcpyHostToDevice));
+      HIP_TRY(vol, hipMemcpy(vol->d_order, bvh.tri_order.data(), (size_t)nt * 4, hipMemcpyHostToDevice));
+      HIP_TRY(vol, hipMemcpy(vol->d_tris, bvh.tris.data(), bvh.tris.size() * 16, hipMemcpyHostToDevice));
+    }
+    if (!bvh.leaf_slots.empty())
+      HIP_TRY(vol, hipMemcpy(vol->d_leaf, bvh.leaf_slots.data(), bvh.leaf_slots.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(vol, hipMemcpy(vol->d_nodes, bvh.nodes.data(), bvh.nodes.size() * 16, hipMemcpyHostToDevice));
+    HIP_TRY(vol, hipMemcpy(vol->d_albedo, alb.data(), alb.size() * 16, hipMemcpyHostToDevice));
+    vol->nv = nv;
+    vol->nt = nt;
+    vol->num_nodes = nn;
+    vol->num_leaf_slots = (int32_t)bvh.leaf_slots.size();
+    vol->pad_abs = pad_abs;
+    vol->bvh_depth = bvh.depth;
+    vol->v.nodes = vol->d_nodes;
+    vol->v.tris = vol->d_tris;
+    vol->v.albedo = vol->d_albedo;
+    hp.num_nodes = nn;
+    HIP_TRY(vol, hipHostMalloc((void**)&vol->h_stage, std::max<size_t>((size_t)nv * 12, 16), hipHostMallocDefault));
+    vol->h_stage_floats = (size_t)nv * 3;
+  } else {
+    hp.num_nodes = vol->num_nodes;
+    const size_t cnt = (size_t)(ve - vb) * 3;
+    if (cnt) {
+      std::memcpy(vol->h_stage + 3 * vb, sc->positions + 3 * vb, cnt * 4);
+      HIP_TRY(vol, hipMemcpyAsync(vol->d_pos + 3 * vb, vol->h_stage + 3 * vb, cnt * 4,
+                                  hipMemcpyHostToDevice, vol->stream));
+      RefitView r{vol->d_pos, vol->d_idx, vol->d_order, vol->d_tris, vol->d_nodes, vol->d_leaf,
+                  vol->num_leaf_slots, vol->d_arrive, vol->nt, vol->num_nodes, vol->pad_abs};
+      HIP_TRY(vol, launch_refit(r, vol->stream));
+    }
+  }
+  HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice,
+                              vol->stream));
+  HIP_TRY(vol, hipEventRecord(vol->ev_stage, vol->stream));
+  vol->has_scene = true;
+  return order_user_after(vol);
+}
+
+adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, adgi_update_stats* stats) {
+  if (!vol || !p) return fail(ADGI_ERR_INVALID_ARG, "volume and params must not be NULL");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "update_probes before update_scene");
+  if (p->frame < 0) return fail(ADGI_ERR_INVALID_ARG, "frame must be >= 0");
+  if (p->adaptive != 0 && p->adaptive != 1) return fail(ADGI_ERR_INVALID_ARG, "adaptive must be 0 or 1");
+  const int64_t P = vol->P, cap = vol->desc.max_rays_per_frame;
+  if (p->adaptive) {
+    if (p->n_min < 1 || p->n_max < p->n_min) return fail(ADGI_ERR_BUDGET, "need 1 <= n_min <= n_max");
+    if (p->budget < P * p->n_min)
+      return fail(ADGI_ERR_BUDGET, "budget %lld < P*n_min = %lld", (long long)p->budget, (long long)(P * p->n_min));
+    if (p->budget > cap) return fail(ADGI_ERR_BUDGET, "budget exceeds max_rays_per_frame");
+    if (!(p->beta > 0.f) || !std::isfinite(p->beta)) return fail(ADGI_ERR_INVALID_ARG, "beta must be > 0");
+    if (p->theta < 1) return fail(ADGI_ERR_INVALID_ARG, "theta must be >= 1");
+    if (p->mu < 0 || p->mu > 1024) return fail(ADGI_ERR_INVALID_ARG, "mu must be in [0, 1024]");
+  } else {
+    if (p->n_uniform < 1) return fail(ADGI_ERR_BUDGET, "n_uniform must be >= 1");
+    if (P * p->n_uniform > cap) return fail(ADGI_ERR_BUDGET, "P*n_uniform exceeds max_rays_per_frame");
+  }
+  if (p->n_max > 65535 && p->adaptive) return fail(ADGI_ERR_BUDGET, "n_max must be <= 65535");
+
+  adgi_status st = order_after_user(vol);
+  if (st != ADGI_OK) return st;
+  // parameter block into the next pinned slot
+  const int slot = vol->slot;
+  vol->slot = (slot + 1) % kParamSlots;
+  HIP_TRY(vol, hipEventSynchronize(vol->ev_slot[slot]));
+  FrameParams& fp = vol->h_fp[slot];
+  std::memset(&fp, 0, sizeof(fp));
+  frame_rotation(vol->desc.seed, p->frame, fp.R);
+  fp.seed = vol->desc.seed;
+  fp.budget = p->budget;
+  fp.frame = p->frame;
+  fp.adaptive = p->adaptive;
+  fp.n_min = p->n_min;
+  fp.n_max = p->n_max;
+  fp.n_uniform = p->n_uniform;
+  fp.mu = p->mu;
+  fp.theta = p->theta;
+  fp.beta = p->beta;
+  fp.debug = (vol->desc.flags & ADGI_DEBUG_ARRAYS) ? 1 : 0;
+  HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.fp, &fp, sizeof(FrameParams), hipMemcpyHostToDevice, vol->stream));
+  HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
+  HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
+  const int mode = p->adaptive ? 1 : 0;
+  if (vol->tun.use_graph) {
+    if (!vol->exec[mode]) {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
+      hipError_t e = enqueue_frame(vol, p->adaptive != 0);
+      hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        vol->sticky = true;
+        return fail(ADGI_ERR_DEVICE, "frame capture failed: %s / %s", hipGetErrorString(e),
+                    hipGetErrorString(e2));
+      }
+      hipError_t e3 = hipGraphInstantiate(&vol->exec[mode], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e3 != hipSuccess) {
+        vol->sticky = true;
+        return fail(ADGI_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
+      }
+    }
+    HIP_TRY(vol, hipGraphLaunch(vol->exec[mode], vol->stream));
+  } else {
+    HIP_TRY(vol, enqueue_frame(vol, p->adaptive != 0));
+  }
+  HIP_TRY(vol, hipEventRecord(vol->ev_t1, vol->stream));
+  vol->last_frame = p->frame;
+  vol->last_adaptive = p->adaptive;
+  std::memcpy(vol->last_R, fp.R, sizeof(vol->last_R));
+  st = order_user_after(vol);
+  if (st != ADGI_OK) return st;
+  if (p->sync) {
+    HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+    if (stats) {
+      HIP_TRY(vol, hipMemcpy(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost));
+      uint32_t total = 0;
+      HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
+      std::memset(stats, 0, sizeof(*stats));
+      stats->primary_rays = total;
+      stats->pilot_rays = p->adaptive ? 8 * P : 0;
+      stats->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
+      stats->budget_used = (int64_t)vol->h_stats->budget_used;
+      stats->lambda = vol->h_stats->lambda;
+      stats->n_min_seen = vol->h_stats->n_min_seen;
+      stats->n_max_seen = vol->h_stats->n_max_seen;
+      float ms = 0.f;
+      HIP_TRY(vol, hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1));
+      stats->ms_total = ms;
+    }
+  }
+  return ADGI_OK;
+}
+
+adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
+  if (!vol || !out) return fail(ADGI_ERR_INVALID_ARG, "volume and out must not be NULL");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  const bool dbg = vol->desc.flags & ADGI_DEBUG_ARRAYS;
+  if (!dbg && (out->hit_tri || out->shadow_bits || out->irr_bin || out->depth_bin || out->ray_record))
+    return fail(ADGI_ERR_INVALID_ARG, "debug arrays need ADGI_DEBUG_ARRAYS");
+  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res, ri = gi - 2, rd = gd - 2;
+  const bool h = vol->desc.storage == ADGI_FP16;
+  auto copy_texels = [&](float* dst, const void* src, size_t count) -> hipError_t {
+    if (!h) return hipMemcpy(dst, src, count * 4, hipMemcpyDeviceToHost);
+    std::vector<uint16_t> tmp(count);
+    hipError_t e = hipMemcpy(tmp.data(), src, count * 2, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (size_t k = 0; k < count; ++k) dst[k] = half_bits_to_float(tmp[k]);
+    return hipSuccess;
+  };
+  if (out->irradiance) HIP_TRY(vol, copy_texels(out->irradiance, vol->irr, P * gi * gi * 3));
+  if (out->depth) HIP_TRY(vol, copy_texels(out->depth, vol->dep, P * gd * gd * 2));
+  if (out->irr_count) HIP_TRY(vol, hipMemcpy(out->irr_count, vol->irr_n, P * ri * ri, hipMemcpyDeviceToHost));
+  if (out->depth_count) HIP_TRY(vol, hipMemcpy(out->depth_count, vol->dep_n, P * rd * rd, hipMemcpyDeviceToHost));
+  if (out->rays_per_probe) HIP_TRY(vol, hipMemcpy(out->rays_per_probe, vol->v.n, P * 4, hipMemcpyDeviceToHost));
+  if (out->score) HIP_TRY(vol, hipMemcpy(out->score, vol->v.score, P * 8, hipMemcpyDeviceToHost));
+  std::vector<uint32_t> off(P + 1);
+  HIP_TRY(vol, hipMemcpy(off.data(), vol->v.offsets, (P + 1) * 4, hipMemcpyDeviceToHost));
+  if (out->ray_offsets)
+    for (size_t i = 0; i <= P; ++i) out->ray_offsets[i] = off[i];
+  const size_t R = vol->last_frame >= 0 ? off[P] : 0;
+  out->num_rays = (int64_t)R;
+  if (R) {
+    if (out->hit_tri) HIP_TRY(vol, hipMemcpy(out->hit_tri, vol->v.dbg_tri, R * 4, hipMemcpyDeviceToHost));
+    if (out->shadow_bits) HIP_TRY(vol, hipMemcpy(out->shadow_bits, vol->v.dbg_shadow, R, hipMemcpyDeviceToHost));
+    if (out->irr_bin) HIP_TRY(vol, hipMemcpy(out->irr_bin, vol->v.dbg_ibin, R * 2, hipMemcpyDeviceToHost));
+    if (out->depth_bin) HIP_TRY(vol, hipMemcpy(out->depth_bin, vol->v.dbg_dbin, R * 2, hipMemcpyDeviceToHost));
+    if (out->ray_record) HIP_TRY(vol, hipMemcpy(out->ray_record, vol->v.rec, R * 16, hipMemcpyDeviceToHost));
+  }
+  const int qs = vol->last_frame >= 0 ? (vol->last_frame & 1) : 0;
+  if (out->q10_vis) HIP_TRY(vol, hipMemcpy(out->q10_vis, vol->v.qv[qs], P * 16, hipMemcpyDeviceToHost));
+  if (out->q10_rad) HIP_TRY(vol, hipMemcpy(out->q10_rad, vol->v.qr[qs], P * 16, hipMemcpyDeviceToHost));
+  if (out->frame_rotation) std::memcpy(out->frame_rotation, vol->last_R, sizeof(vol->last_R));
+  return ADGI_OK;
+}
+
+adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out) {
+  if (!vol || !out) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  *out = vol->tun;
+  return ADGI_OK;
+}
+
+adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
+  if (!vol || !t) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (!tuning_valid(*t)) return fail(ADGI_ERR_INVALID_ARG, "tuning out of range");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  size_t lds = blend_lds_bytes(vol->v, t->blend_chunk);
+  if (lds > 65536) return fail(ADGI_ERR_INVALID_ARG, "blend_chunk needs %zu bytes of LDS", lds);
+  if (trace_lds_bytes(t->trace_block, t->lds_top_nodes) > 65536)
+    return fail(ADGI_ERR_INVALID_ARG, "trace LDS over 64 KiB");
+  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  drop_graphs(vol);
+  vol->tun = *t;
+  vol->tuned = true;
+  return ADGI_OK;
+}
+
+size_t adgi_device_bytes(const adgi_volume* vol) { return vol ? vol->dev_bytes : 0; }
+
+size_t adgi_state_size(const adgi_volume* vol) {
+  if (!vol) return 0;
+  size_t s = sizeof(SnapHeader);
+  for (const Part& p : state_parts(const_cast<adgi_volume*>(vol))) s += p.bytes;
+  return s;
+}
+
+adgi_status adgi_save_state(adgi_volume* vol, void* dst, size_t bytes) {
+  if (!vol || !dst) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (bytes < adgi_state_size(vol)) return fail(ADGI_ERR_INVALID_ARG, "buffer too small");
+  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  SnapHeader h{};
+  h.magic = kSnapMagic;
+  h.P = vol->P;
+  h.irr_res = vol->desc.irr_res;
+  h.depth_res = vol->desc.depth_res;
+  h.storage = vol->desc.storage;
+  h.last_frame = vol->last_frame;
+  h.last_adaptive = vol->last_adaptive;
+  std::memcpy(h.last_R, vol->last_R, sizeof(h.last_R));
+  uint8_t* o = (uint8_t*)dst;
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  for (const Part& p : state_parts(vol)) {
+    HIP_TRY(vol, hipMemcpy(o, p.dev, p.bytes, hipMemcpyDeviceToHost));
+    o += p.bytes;
+  }
+  return ADGI_OK;
+}
+
+adgi_status adgi_restore_state(adgi_volume* vol, const void* src, size_t bytes) {
+  if (!vol || !src) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (bytes < adgi_state_size(vol)) return fail(ADGI_ERR_INVALID_ARG, "snapshot too small");
+  SnapHeader h;
+  std::memcpy(&h, src, sizeof(h));
+  if (h.magic != kSnapMagic || h.P != vol->P || h.irr_res != vol->desc.irr_res ||
+      h.depth_res != vol->desc.depth_res || h.storage != vol->desc.storage)
+    return fail(ADGI_ERR_INVALID_ARG, "snapshot does not match this volume");
+  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  const uint8_t* o = (const uint8_t*)src + sizeof(h);
+  for (const Part& p : state_parts(vol)) {
+    HIP_TRY(vol, hipMemcpy(p.dev, o, p.bytes, hipMemcpyHostToDevice));
+    o += p.bytes;
+  }
+  vol->last_frame = h.last_frame;
+  vol->last_adaptive = h.last_adaptive;
+  std::memcpy(vol->last_R, h.last_R, sizeof(h.last_R));
+  return ADGI_OK;
+}
+
+
+// ---- autotuning: time candidate launch shapes of the two dominant kernels
+// on the current frame, then restore the state saved before.
+adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tuning* chosen) {
+  if (!vol || !p) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "autotune before update_scene");
+  const TuneKey key{vol->device, 32 - __builtin_clz((unsigned)vol->P), vol->desc.irr_res * 64 + vol->desc.depth_res,
+                    vol->desc.storage * 2 + p->adaptive};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      adgi_status st = adgi_set_tuning(vol, &it->second);
+      if (st == ADGI_OK && chosen) *chosen = it->second;
+      return st;
+    }
+  }
+  std::vector<uint8_t> snap(adgi_state_size(vol));
+  adgi_status st = adgi_save_state(vol, snap.data(), snap.size());
+  if (st != ADGI_OK) return st;
+  const adgi_tuning saved = vol->tun;
+  // run one frame eagerly so that offsets and counters are those of params
+  adgi_tuning t = saved;
+  t.use_graph = 0;
+  vol->tun = t;
+  adgi_update_params q = *p;
+  q.sync = 1;
+  drop_graphs(vol);
+  st = adgi_update_probes(vol, &q, nullptr);
+  if (st != ADGI_OK) {
+    vol->tun = saved;
+    return st;
+  }
+  // scratch outputs so the blend candidates leave the state alone
+  const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res;
+  const size_t el = vol->desc.storage == ADGI_FP16 ? 2 : 4;
+  std::vector<void*> scratch;
+  void* so_irr = vol_alloc(vol, P * gi * gi * 3 * el, &scratch);
+  void* so_dep = vol_alloc(vol, P * gd * gd * 2 * el, &scratch);
+  void* so_in = vol_alloc(vol, P * (gi - 2) * (gi - 2), &scratch);
+  void* so_dn = vol_alloc(vol, P * (gd - 2) * (gd - 2), &scratch);
+  auto cleanup = [&]() {
+    for (void* x : scratch) vol_free(vol, x);
+  };
+  if (!so_irr || !so_dep || !so_in || !so_dn) {
+    cleanup();
+    vol->tun = saved;
+    (void)adgi_restore_state(vol, snap.data(), snap.size());
+    return fail(ADGI_ERR_OUT_OF_MEMORY, "allocator returned NULL for tuning scratch");
+  }
+  hipStream_t s = vol->stream;
+  auto time_trace = [&](const adgi_tuning& c, float& best) -> hipError_t {
+    best = INFINITY;
+    const int ntop = std::min(c.lds_top_nodes, vol->num_nodes);
+    const int grid = c.persistent ? std::max(1, vol->num_cus * c.trace_waves_per_cu / (c.trace_block / 64))
+                                  : (int)((vol->desc.max_rays_per_frame + c.trace_block - 1) / c.trace_block);
+    for (int rep = 0; rep < 3; ++rep) {
+      hipError_t e;
+      if ((e = launch_frame_begin(vol->v, s)) != hipSuccess) return e;
+      if ((e = hipEventRecord(vol->ev_t0, s)) != hipSuccess) return e;
+      if ((e = launch_trace(vol->v, s, false, c.persistent != 0, c.trace_block, grid, ntop)) != hipSuccess) return e;
+      if ((e = hipEventRecord(vol->ev_t1, s)) != hipSuccess) return e;
+      if ((e = hipEventSynchronize(vol->ev_t1)) != hipSuccess) return e;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1)) != hipSuccess) return e;
+      best = std::min(best, ms);
+    }
+    return hipSuccess;
+  };
+  adgi_tuning best_t = saved;
+  float best_ms = INFINITY;
+  hipError_t err = hipSuccess;
+  const int blocks[] = {64, 128, 256};
+  const int waves[] = {8, 16, 24};
+  const int tops[] = {0, 256};
+  for (int b : blocks)
+    for (int w : waves)
+      for (int top : tops) {
+        adgi_tuning c = saved;
+        c.persistent = 1;
+        c.trace_block = b;
+        c.trace_waves_per_cu = w;
+        c.lds_top_nodes = top;
+        if (trace_lds_bytes(b, top) > 65536) continue;
+        float ms;
+        if ((err = time_trace(c, ms)) != hipSuccess) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_t = c;
+        }
+      }
+  if (err == hipSuccess) {
+    adgi_tuning c = best_t;
+    c.persistent = 0;
+    c.trace_block = 256;
+    float ms;
+    err = time_trace(c, ms);
+    if (err == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best_t = c;
+    }
+  }
+  float best_blend = INFINITY;
+  const int chunks[] = {128, 256, 512};
+  for (int ch : chunks) {
+    if (err != hipSuccess) break;
+    if (blend_lds_bytes(vol->v, ch) > 65536) continue;
+    BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, so_irr, so_dep, (uint8_t*)so_in, (uint8_t*)so_dn};
+    float bm = INFINITY;
+    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+      if ((err = hipEventRecord(vol->ev_t0, s)) != hipSuccess) break;
+      if ((err = launch_blend(vol->v, io, s, vol->desc.storage == ADGI_FP16, ch)) != hipSuccess) break;
+      if ((err = hipEventRecord(vol->ev_t1, s)) != hipSuccess) break;
+      if ((err = hipEventSynchronize(vol->ev_t1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((err = hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1)) != hipSuccess) break;
+      bm = std::min(bm, ms);
+    }
+    if (bm < best_blend) {
+      best_blend = bm;
+      best_t.blend_chunk = ch;
+    }
+  }
+  if (err != hipSuccess) {
+    vol->sticky = true;
+    return fail(ADGI_ERR_DEVICE, "autotune kernel failed: %s", hipGetErrorString(err));
+  }
+  (void)hipStreamSynchronize(s);
+  cleanup();
+  best_t.use_graph = saved.use_graph;
+  vol->tun = saved;
+  st = adgi_restore_state(vol, snap.data(), snap.size());
+  if (st != ADGI_OK) return st;
+  st = adgi_set_tuning(vol, &best_t);
+  if (st != ADGI_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best_t;
+  }
+  if (chosen) *chosen = best_t;
+  return ADGI_OK;
+}
+
+}  // extern "C"

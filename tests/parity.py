@@ -1,0 +1,117 @@
+"""Lockstep parity driver: GPU library vs. FP64 CPU oracle, frame by frame.
+
+Each frame the GPU runs ``adgi_update_probes`` with per-ray debug arrays on;
+the oracle then runs the same frame on the same seeded inputs. Where FP32 and
+FP64 can legitimately take different discrete decisions (a hit at a triangle
+edge, a shadow ray grazing an occluder, a direction on a texel edge, a value on
+a 10-bit code boundary), the oracle flags a tie and adopts the GPU's decision,
+so both sides keep the same state; every other discrete disagreement counts
+as a mismatch. Integer results (codes, scores, rays per probe, counts) must
+then agree exactly and texels within the FP32 tolerance.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import paper_2301_05125_amd as adgi
+
+
+def rel_err(g: np.ndarray, o: np.ndarray, per_probe_axis: int = 0) -> np.ndarray:
+    """|g-o| / max(|o|, 1e-3 * max over the probe's texels of |o|, 1e-8)."""
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    flat = np.abs(o).reshape(o.shape[0], -1)
+    floor = 1e-3 * flat.max(axis=1)
+    floor = floor.reshape((-1,) + (1,) * (o.ndim - 1))
+    den = np.maximum(np.maximum(np.abs(o), floor), 1e-8)
+    return np.abs(g - o) / den
+
+
+def gpu_scene_update(vol, scene, frame):
+    if scene.anim_vertices and frame > 0:
+        vol.update_scene(scene.positions_at(frame), light_pos=scene.light_positions(frame),
+                         light_intensity=scene.light_intensity, sky=scene.sky,
+                         mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, scene.anim_vertices))
+    else:
+        vol.update_scene(scene.positions, light_pos=scene.light_positions(frame),
+                         light_intensity=scene.light_intensity, sky=scene.sky,
+                         mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, 0))
+
+
+def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget: int = 0,
+                 n_min: int = 8, n_max: int = 2048, probes=None, storage=adgi.ADGI_FP32,
+                 seed: int = 0x5EED, max_rays=None, tuning=None, check_rays: bool = True,
+                 use_bvh: bool = True) -> dict:
+    P = scene.num_probes
+    if max_rays is None:
+        max_rays = max(budget, P * n_uniform, 1)
+    vol = adgi.volume_for_scene(scene, storage=storage, max_rays=max_rays, seed=seed, debug=True)
+    if tuning:
+        vol.set_tuning(**tuning)
+    fp16 = storage == adgi.ADGI_FP16
+    ora = oracle.OracleVolume(scene, seed=seed, fp16=fp16, probes=probes, use_bvh=use_bvh)
+    sel = ora.probes
+    res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "max_rel_ray": 0.0,
+           "ties": {}, "frames": frames, "rays": 0, "count_mismatch": 0, "score_mismatch": 0,
+           "alloc_mismatch": 0, "rotation_mismatch": 0}
+    for f in range(frames):
+        if f > 0:
+            gpu_scene_update(vol, scene, f)
+        st = vol.update_probes(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
+                               n_uniform=n_uniform, sync=True)
+        rb = vol.read_probes(texels=True, debug=True)
+        R = oracle.frame_rotation(seed, f).reshape(9)
+        if not np.array_equal(R, rb["frame_rotation"]):
+            res["rotation_mismatch"] += 1
+        hints = {"hit_tri": rb["hit_tri"], "shadow_bits": rb["shadow_bits"],
+                 "irr_bin": rb["irr_bin"], "depth_bin": rb["depth_bin"],
+                 "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
+        out = ora.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
+                         n_uniform=n_uniform, hints=hints, keep_rays=check_rays)
+        c = out["counts"]
+        mism = c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"]
+        if adaptive:
+            res["score_mismatch"] += int(np.count_nonzero(out["score"] != rb["score"]))
+        res["alloc_mismatch"] += int(np.count_nonzero(out["n"] != rb["rays_per_probe"]))
+        res["mismatches"] += mism
+        for k in ("hit_ties", "shadow_ties", "bin_ties"):
+            res["ties"][k] = res["ties"].get(k, 0) + c[k]
+        res["rays"] += c["rays"]
+        res["stats_last"] = st
+        # texels of the tracked probes
+        gi = rb["irradiance"][sel]
+        gd = rb["depth"][sel]
+        oi = ora.irradiance_tiles()
+        od = ora.depth_tiles()
+        res["max_rel_irr"] = max(res["max_rel_irr"], float(rel_err(gi, oi).max(initial=0.0)))
+        res["max_rel_depth"] = max(res["max_rel_depth"], float(rel_err(gd, od).max(initial=0.0)))
+        ri, rd = scene_res(vol)
+        cnt_i = rb["irr_count"][sel].reshape(len(sel), -1)
+        cnt_d = rb["depth_count"][sel].reshape(len(sel), -1)
+        res["count_mismatch"] += int(np.count_nonzero(cnt_i != ora.irr_n)) + \
+            int(np.count_nonzero(cnt_d != ora.dep_n))
+        if check_rays:
+            base = rb["ray_offsets"][sel]
+            n_sel = out["n"][sel]
+            idx = np.concatenate([np.arange(b, b + k) for b, k in zip(base, n_sel)])
+            g = rb["ray_record"][idx].astype(np.float64)
+            o = out["rays"]
+            same = rb["hit_tri"][idx] == out["tri"]
+            gt = np.where(np.isinf(g[:, 3]), 0.0, g[:, 3])
+            ot = np.where(np.isinf(o[:, 3]), 0.0, o[:, 3])
+            if np.any(np.isinf(g[:, 3]) != np.isinf(o[:, 3])):
+                res["mismatches"] += int(np.count_nonzero(np.isinf(g[:, 3]) != np.isinf(o[:, 3])))
+            e_rgb = np.abs(g[:, :3] - o[:, :3]) / np.maximum(np.abs(o[:, :3]), 1e-6)
+            e_t = np.abs(gt - ot) / np.maximum(np.abs(ot), 1e-6)
+            e = np.maximum(e_rgb.max(axis=1), e_t)[same]
+            res["max_rel_ray"] = max(res["max_rel_ray"], float(e.max(initial=0.0)))
+    res["irr_gpu"] = rb["irradiance"][sel]
+    res["irr_oracle"] = ora.irradiance_tiles()
+    res["oracle_counts"] = ora.counts.as_dict()
+    vol.destroy_volume()
+    return res
+
+
+def scene_res(vol):
+    return vol.desc.irr_res - 2, vol.desc.depth_res - 2

@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports what include/adgi.h declares (CPU only).
+
+No compute call is made here: only argument validation, which returns before
+any HIP call, is exercised.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2301_05125_amd as adgi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "adgi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(adgi_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_four_entry_points():
+    names = _declared()
+    for n in ("adgi_create_volume", "adgi_update_scene", "adgi_update_probes",
+              "adgi_read_probes", "adgi_destroy_volume", "adgi_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(adgi.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _desc(**kw):
+    d = adgi.VolumeDesc()
+    d.origin[:] = [0, 0, 0]
+    d.spacing[:] = [1, 1, 1]
+    d.dims[:] = [2, 2, 2]
+    d.irr_res, d.depth_res, d.storage = 8, 16, adgi.ADGI_FP32
+    d.hysteresis, d.tau_max, d.max_rays_per_frame, d.seed = 0.97, 9.8, 1024, 1
+    for k, v in kw.items():
+        if k in ("dims", "spacing", "origin"):
+            getattr(d, k)[:] = v
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("bad", [
+    {"dims": [0, 2, 2]}, {"spacing": [1, -1, 1]}, {"irr_res": 2}, {"depth_res": 35},
+    {"storage": 7}, {"hysteresis": 1.0}, {"tau_max": 0.0}, {"max_rays_per_frame": 0},
+    {"max_rays_per_frame": 1 << 31}, {"dims": [4096, 4096, 2]}, {"flags": 8},
+])
+def test_invalid_descriptor_rejected_before_any_device_call(bad):
+    L = adgi.lib()
+    h = C.c_void_p()
+    st = L.adgi_create_volume(C.byref(_desc(**bad)), None, None, C.byref(h))
+    assert st == -1
+    assert h.value is None
+    assert len(L.adgi_last_error()) > 0
+
+
+def test_null_arguments():
+    L = adgi.lib()
+    assert L.adgi_create_volume(None, None, None, None) == -1
+    assert L.adgi_update_scene(None, None) == -1
+    assert L.adgi_update_probes(None, None, None) == -1
+    assert L.adgi_read_probes(None, None) == -1
+    L.adgi_destroy_volume(None)  # no-op
+    assert L.adgi_state_size(None) == 0

@@ -1,0 +1,43 @@
+"""GPU vs. oracle parity through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import scenes
+from tests.parity import run_lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+def _assert_parity(res, tol=1e-4):
+    assert res["rotation_mismatch"] == 0, res
+    assert res["mismatches"] == 0, res
+    assert res["alloc_mismatch"] == 0, res
+    assert res["score_mismatch"] == 0, res
+    assert res["count_mismatch"] == 0, res
+    assert res["max_rel_irr"] <= tol, res
+    assert res["max_rel_depth"] <= tol, res
+    assert res["max_rel_ray"] <= 1e-4, res
+
+
+def test_cornell_uniform_8_frames():
+    """Cornell room, 64 rays/probe, FP32, 8 frames (three probes lie inside boxes)."""
+    res = run_lockstep(scenes.cornell(), frames=8, adaptive=False, n_uniform=64)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_parity(res)
+
+
+def test_cornell_ragged_ray_counts():
+    """Ray counts that are not multiples of the wave size or blend chunk."""
+    res = run_lockstep(scenes.cornell(), frames=3, adaptive=False, n_uniform=77,
+                       tuning={"blend_chunk": 64})
+    _assert_parity(res)
+
+
+def test_cornell_adaptive_budget():
+    """Adaptive mode on the Cornell room with a light that appears at frame 1."""
+    sc = scenes.cornell()
+    sc.light_a = np.array([[0.5, 0.95, 0.5]], np.float32)
+    sc.light_b = np.array([[0.2, 0.5, 0.3]], np.float32)
+    sc.frames = 6
+    res = run_lockstep(sc, frames=6, adaptive=True, budget=64 * 40, n_min=8, n_max=200)
+    _assert_parity(res)
