@@ -1,0 +1,291 @@
+#!/usr/bin/env python
+"""Probe-update benchmark on one MI355X: probe rays/s and p50/p99 update latency,
+adaptive vs uniform, with rooflines of the two dominant kernels and the CPU
+oracle timed beside it.
+
+A step is one whole frame of the hot path on the 1M-triangle box field
+(65,536 probes, 5% of the boxes animated, 3 moving lights): scene refit and
+light update, pilot rays, change detection, budget allocation (B = 2^23,
+8..2048 rays per probe), probe-ray trace with shadow rays, and the texel
+blend. ``value`` is probe (primary) rays per second over the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "probe rays/sec + p50/p99 probe-update ms/frame, adaptive vs uniform, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+# VALU issue rate of one MI355X without packed FP32: 256 CUs x 64 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# FP32 operations of the two traversal tests as written (adgi_device.hpp):
+# slab test of one child box = 6 fma + 6 min/max + 6 min/max + 1 compare = 19,
+# a node visit tests two child boxes; Moller-Trumbore = 2 crosses (12),
+# 4 dots (12), 3 subtractions, 2 sign products, 4 compares = 33.
+OPS_PER_NODE = 38
+OPS_PER_TRI = 33
+
+WORKLOADS = {
+    "box_field": dict(budget=1 << 23, n_min=8, n_max=2048, uniform_equal_b=128, uniform_equal_rays=136),
+    "tunnel": dict(budget=1 << 19, n_min=32, n_max=1024, uniform_equal_b=256, uniform_equal_rays=264),
+}
+
+
+def blend_bytes(P, R, fp16):
+    """Algorithmic HBM bytes of one blend launch: per probe read the interior
+    texels (36 x 12 + 196 x 8 B FP32), write full tiles (64 x 12 + 256 x 8 B),
+    read+write counts (2 x 232 B); FP16 halves the texel bytes; 16 B per ray."""
+    per_probe = 2872 if fp16 else 5280
+    return P * per_probe + 16 * R
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    f = math.floor(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2301_05125_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key, src_hash):
+    """HBM bytes per dispatch from a committed rocprofv3 counter summary,
+    valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def light_frame(frame, period=60):
+    """Lights go back and forth along their seeded paths."""
+    f = frame % (2 * period)
+    return f if f <= period else 2 * period - f
+
+
+def step_scene(vol, sc, frame, adgi):
+    vol.update_scene(sc.positions_at(frame), light_pos=sc.light_positions(light_frame(frame)),
+                     light_intensity=sc.light_intensity, sky=sc.sky, mode=adgi.ADGI_SCENE_REFIT,
+                     refit_range=(0, sc.anim_vertices))
+
+
+def run_mode(vol, sc, adgi, torch, frame0, steps, warmup, latency_frames, **p):
+    f = frame0
+    for _ in range(warmup):
+        step_scene(vol, sc, f, adgi)
+        vol.update_probes(f, sync=False, **p)
+        f += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_scene(vol, sc, f, adgi)
+        vol.update_probes(f, sync=False, **p)
+        f += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # latency: one synchronous frame at a time
+    host_ms, gpu_ms, rays, shadow = [], [], [], []
+    for _ in range(latency_frames):
+        step_scene(vol, sc, f, adgi)
+        a = time.perf_counter()
+        st = vol.update_probes(f, sync=True, **p)
+        host_ms.append((time.perf_counter() - a) * 1e3)
+        gpu_ms.append(st["ms_total"])
+        rays.append(st["primary_rays"])
+        shadow.append(st["shadow_rays"] + st["pilot_rays"])
+        f += 1
+    return dict(seconds=t1 - t0, frames_end=f, host_ms=host_ms, gpu_ms=gpu_ms,
+                rays_per_frame=sum(rays) / len(rays), extra_rays_per_frame=sum(shadow) / len(shadow))
+
+
+def stage_times(vol, sc, adgi, frame0, frames, **p):
+    """Per-kernel durations: eager launches with HIP events recorded between the
+    kernels on the volume's own stream (the stream the kernels run on)."""
+    tun = vol.get_tuning()
+    vol.set_tuning(use_graph=0)
+    acc = [0.0] * 6
+    f = frame0
+    for _ in range(frames):
+        step_scene(vol, sc, f, adgi)
+        st = vol.update_probes(f, sync=True, **p)
+        for k in range(6):
+            acc[k] += st["ms_stage"][k]
+        f += 1
+    vol.set_tuning(use_graph=tun["use_graph"])
+    return [a / frames for a in acc], f
+
+
+def cpu_baseline(sc, budget, n_min, n_max, sample_probes=512):
+    """The oracle as it stands on the host cores: all pilot rays of one pair
+    (two frames), detection, allocation, and the rays of 512 sampled probes."""
+    import numpy as np
+
+    import oracle
+    import scenes as S
+    probes = S.sample_probes(sc.num_probes, sample_probes)
+    vol = oracle.OracleVolume(sc, seed=7, probes=probes)
+    rays = 0
+    t0 = time.perf_counter()
+    for f in range(2):
+        out = vol.update(f, adaptive=True, budget=budget, n_min=n_min, n_max=n_max)
+        rays += out["counts"]["rays"]
+    t1 = time.perf_counter()
+    return {"value": rays / (t1 - t0), "unit": "rays/s", "cores": int(oracle.lib().orc_num_threads()),
+            "kind": "oracle",
+            "sample": f"2 frames of the box field: all {8 * sc.num_probes} pilot rays per frame "
+                      f"(+ shadow rays), detection, allocation of B={budget}, and the probe rays of "
+                      f"{len(probes)} sampled probes; {rays} rays in {t1 - t0:.1f} s (BVH build untimed)",
+            "seconds": t1 - t0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="box_field", choices=sorted(WORKLOADS))
+    ap.add_argument("--latency-frames", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2301_05125_amd as adgi
+    import scenes
+
+    torch.cuda.set_device(0)
+    cfg = WORKLOADS[args.workload]
+    sc = scenes.box_field() if args.workload == "box_field" else scenes.tunnel()
+    sc.frames = 61  # light_frame() walks frames 0..60 back and forth
+    fp16 = args.storage == "fp16"
+    storage = adgi.ADGI_FP16 if fp16 else adgi.ADGI_FP32
+    P = sc.num_probes
+    max_rays = max(cfg["budget"], P * cfg["uniform_equal_rays"])
+    print(f"[bench] workload={args.workload} P={P} tris={sc.num_triangles} B={cfg['budget']}",
+          file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    vol = adgi.volume_for_scene(sc, storage=storage, max_rays=max_rays, seed=11)
+    build_s = time.perf_counter() - t
+    ad = dict(adaptive=True, budget=cfg["budget"], n_min=cfg["n_min"], n_max=cfg["n_max"])
+    tuning = vol.get_tuning()
+    if not args.no_autotune:
+        tuning = vol.autotune(0, **ad)
+    print(f"[bench] scene build {build_s:.2f}s tuning={tuning}", file=sys.stderr, flush=True)
+
+    res_a = run_mode(vol, sc, adgi, torch, 0, args.steps, args.warmup, args.latency_frames, **ad)
+    print(f"[bench] adaptive done {res_a['seconds']:.3f}s", file=sys.stderr, flush=True)
+    stages_a, fnext = stage_times(vol, sc, adgi, res_a["frames_end"], 5, **ad)
+    tw = vol.measure_trace_work(fnext, **ad)
+
+    # uniform baselines on fresh volumes (same scene, same tuning)
+    uni = {}
+    for name, n in (("uniform_equal_budget", cfg["uniform_equal_b"]),
+                    ("uniform_equal_traced", cfg["uniform_equal_rays"])):
+        v2 = adgi.volume_for_scene(sc, storage=storage, max_rays=max_rays, seed=11)
+        v2.set_tuning(**tuning)
+        r = run_mode(v2, sc, adgi, torch, 0, args.steps, args.warmup, args.latency_frames,
+                     adaptive=False, n_uniform=n)
+        uni[name] = dict(
+            rays_per_probe=n,
+            rays_per_s=P * n * args.steps / r["seconds"],
+            ms_per_step=r["seconds"] / args.steps * 1e3,
+            p50_ms=pct(r["host_ms"], 50), p99_ms=pct(r["host_ms"], 99),
+            gpu_p50_ms=pct(r["gpu_ms"], 50), gpu_p99_ms=pct(r["gpu_ms"], 99))
+        v2.destroy_volume()
+        print(f"[bench] {name} done", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")  # 256 MiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    R = res_a["rays_per_frame"]
+    value = R * args.steps / res_a["seconds"]
+    ms_step = res_a["seconds"] / args.steps * 1e3
+    trace_ms, blend_ms = stages_a[4], stages_a[5]
+    ops = tw["node_tests"] * OPS_PER_NODE + tw["tri_tests"] * OPS_PER_TRI
+    trace_tops = ops / (trace_ms * 1e-3) / 1e12
+    bbytes = blend_bytes(P, R, fp16)
+    blend_gbs = bbytes / (blend_ms * 1e-3) / 1e9
+    h_trace = source_hash("trace.hip", "adgi_device.hpp")
+    h_blend = source_hash("blend.hip", "adgi_device.hpp")
+    roof_trace = {"bound": "alu", "kernel": "trace_kernel<primary>", "achieved": trace_tops,
+                  "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": trace_tops / VALU_PEAK_TOPS,
+                  "traffic": read_traffic("trace_boxfield", h_trace),
+                  "ms": trace_ms, "node_tests_per_ray": tw["node_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
+                  "tri_tests_per_ray": tw["tri_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
+                  "rays_incl_shadow": tw["primary_rays"] + tw["shadow_rays"]}
+    roof_blend = {"bound": "hbm", "kernel": "blend_kernel", "achieved": blend_gbs, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": blend_gbs / HBM_PEAK_GBS,
+                  "traffic": read_traffic("blend_boxfield", h_blend), "ms": blend_ms,
+                  "algorithmic_bytes": bbytes}
+    dominant = roof_trace if trace_ms >= blend_ms else roof_blend
+    out = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {sc.num_triangles} triangles, {P} probes "
+                               f"{tuple(int(x) for x in sc.grid_dims)}, adaptive B={cfg['budget']} "
+                               f"n in [{cfg['n_min']},{cfg['n_max']}], 8x8 irradiance + 16x16 depth "
+                               f"texels {args.storage}, 5% boxes refit per frame, "
+                               f"{sc.num_lights} moving lights",
+                   "parallelism": "1 GPU", "tuning": tuning},
+        "adaptive": {"rays_per_s": value, "probe_updates_per_s": P * args.steps / res_a["seconds"],
+                     "pilot_plus_shadow_rays_per_s": res_a["extra_rays_per_frame"] * args.steps / res_a["seconds"],
+                     "p50_ms": pct(res_a["host_ms"], 50), "p99_ms": pct(res_a["host_ms"], 99),
+                     "gpu_p50_ms": pct(res_a["gpu_ms"], 50), "gpu_p99_ms": pct(res_a["gpu_ms"], 99),
+                     "stage_ms": dict(zip(["setup", "pilot_trace", "detect", "allocate", "probe_trace",
+                                           "blend"], stages_a))},
+        **uni,
+        "roofline": dominant,
+        "roofline_trace": roof_trace,
+        "roofline_blend": roof_blend,
+        "scene_build_s": build_s,
+    }
+    vol.destroy_volume()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc, cfg["budget"], cfg["n_min"], cfg["n_max"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -130,7 +130,9 @@ typedef struct {
   uint32_t lambda;            /* allocation multiplier lambda*                      */
   int32_t n_min_seen, n_max_seen;
   float ms_total;             /* device time of the frame (sync = 1)               */
-  float ms_stage[8];          /* reserved                                          */
+  float ms_stage[8];          /* eager launches with sync = 1: frame setup, pilot
+                                 trace, detection, allocation, probe trace, blend
+                                 (ms each); zero when the frame ran as a graph    */
   int64_t ties[4];            /* reserved                                          */
 } adgi_update_stats;
 
@@ -207,6 +209,18 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t);
  * scratch copies: the volume's state is unchanged. The choice is cached per
  * (device, shape class) in memory for the process. */
 adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* params, adgi_tuning* chosen);
+
+/* ---- traversal work (for rooflines) --------------------------------------
+ * Runs the frame's pilot/detection/allocation steps and a counting variant of
+ * the probe-ray traversal (same rays, same kernel shape) on the current
+ * scene, then restores the volume's state. node_tests counts box-pair tests
+ * (one BVH2 node visit tests both child boxes), tri_tests ray/triangle tests,
+ * both over the probe rays and their shadow rays. */
+typedef struct {
+  int64_t primary_rays, shadow_rays, node_tests, tri_tests;
+} adgi_trace_work;
+adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* params,
+                                    adgi_trace_work* out);
 
 /* ---- state snapshot (checkpoint / eviction) ------------------------------
  * The complete temporal state: texels, counts, detection codes and triggers,

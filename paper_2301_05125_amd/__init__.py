@@ -74,7 +74,8 @@ class UpdateStats(C.Structure):
         return {"primary_rays": self.primary_rays, "pilot_rays": self.pilot_rays,
                 "shadow_rays": self.shadow_rays, "budget_used": self.budget_used,
                 "lambda": self.lambda_, "n_min_seen": self.n_min_seen,
-                "n_max_seen": self.n_max_seen, "ms_total": self.ms_total}
+                "n_max_seen": self.n_max_seen, "ms_total": self.ms_total,
+                "ms_stage": [float(x) for x in self.ms_stage[:6]]}
 
 
 class ProbeReadback(C.Structure):
@@ -82,6 +83,14 @@ class ProbeReadback(C.Structure):
         "irradiance", "depth", "irr_count", "depth_count", "rays_per_probe", "score",
         "ray_offsets", "hit_tri", "shadow_bits", "irr_bin", "depth_bin", "ray_record",
         "q10_vis", "q10_rad", "frame_rotation")] + [("num_rays", C.c_int64)]
+
+
+class TraceWork(C.Structure):
+    _fields_ = [("primary_rays", C.c_int64), ("shadow_rays", C.c_int64),
+                ("node_tests", C.c_int64), ("tri_tests", C.c_int64)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 class Tuning(C.Structure):
@@ -119,6 +128,7 @@ def lib():
         L.adgi_get_tuning.argtypes = [P, P]
         L.adgi_set_tuning.argtypes = [P, P]
         L.adgi_autotune.argtypes = [P, P, P]
+        L.adgi_measure_trace_work.argtypes = [P, P, P]
         L.adgi_state_size.argtypes = [P]
         L.adgi_state_size.restype = C.c_size_t
         L.adgi_save_state.argtypes = [P, P, C.c_size_t]
@@ -127,6 +137,7 @@ def lib():
         L.adgi_device_bytes.restype = C.c_size_t
         for name in ("adgi_create_volume", "adgi_update_scene", "adgi_update_probes",
                      "adgi_read_probes", "adgi_get_tuning", "adgi_set_tuning", "adgi_autotune",
+                     "adgi_measure_trace_work",
                      "adgi_save_state", "adgi_restore_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -303,6 +314,14 @@ class Volume:
         t = Tuning()
         _check(lib().adgi_autotune(self.h, C.byref(p), C.byref(t)))
         return t.as_dict()
+
+    def measure_trace_work(self, frame, adaptive=False, budget=0, n_min=8, n_max=2048,
+                           n_uniform=64, beta=5.0, mu=2, theta=8) -> dict:
+        p = UpdateParams(int(frame), 1 if adaptive else 0, int(budget), int(n_min), int(n_max),
+                         int(n_uniform), float(beta), int(mu), int(theta), 1)
+        w = TraceWork()
+        _check(lib().adgi_measure_trace_work(self.h, C.byref(p), C.byref(w)))
+        return w.as_dict()
 
     def state_size(self) -> int:
         return int(lib().adgi_state_size(self.h))

@@ -14,7 +14,7 @@ namespace adgi {
 // trace.hip
 size_t trace_lds_bytes(int block, int ntop);
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
-                        int grid, int ntop);
+                        int grid, int ntop, bool count = false);
 
 // detect.hip: trigger update and the separable 5x5x5 box sum -> scores
 hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s);

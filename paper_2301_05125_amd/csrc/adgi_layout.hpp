@@ -61,6 +61,8 @@ struct FrameStats {
   int32_t n_min_seen, n_max_seen;
   int32_t pad;
   uint64_t budget_used;
+  uint64_t node_tests;      // work-counting traversal only
+  uint64_t tri_tests;
   uint64_t sums[4][kAllocCandidates];
 };
 

@@ -28,6 +28,8 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->n_min_seen = 0;
     st->n_max_seen = 0;
     st->budget_used = 0ull;
+    st->node_tests = 0ull;
+    st->tri_tests = 0ull;
   }
   if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;
 }

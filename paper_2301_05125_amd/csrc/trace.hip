@@ -53,10 +53,16 @@ __device__ __forceinline__ NodeData fetch_node(const float4* __restrict__ nodes,
   return n;
 }
 
+// Work counters of the counting variant (node visits = box-pair tests).
+struct Work {
+  uint32_t nodes = 0, tris = 0;
+};
+
 // Closest hit: smallest t in (0, inf); equal t resolves to the lowest
 // original triangle index. Returns the triangle slot or -1.
+template <bool COUNT>
 __device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, const Ray& ray,
-                           Stack& st, float& t_best, bool& front_best, int& id_best) {
+                           Stack& st, float& t_best, bool& front_best, int& id_best, Work& w) {
   t_best = INFINITY;
   id_best = 0x7fffffff;
   int slot_best = -1;
@@ -66,6 +72,7 @@ __device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, con
   for (;;) {
     while (node >= 0) {
       NodeData nd = fetch_node(v.nodes, top, ntop, node);
+      if (COUNT) ++w.nodes;
       float tl, tr;
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, t_best, tl);
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, t_best, tr);
@@ -84,6 +91,7 @@ __device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, con
     }
     int code = ~node;
     int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+    if (COUNT) w.tris += count;
     for (int k = 0; k < count; ++k) {
       const float4* tp = v.tris + 3 * (size_t)(first + k);
       float4 a = tp[0], b = tp[1], c = tp[2];
@@ -105,13 +113,15 @@ __device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, con
 }
 
 // Any hit on (0, tmax].
+template <bool COUNT>
 __device__ bool any_hit(const VolumeView& v, const float4* top, int ntop, const Ray& ray,
-                        float tmax, Stack& st) {
+                        float tmax, Stack& st, Work& w) {
   st.sp = 0;
   int node = 0;
   for (;;) {
     while (node >= 0) {
       NodeData nd = fetch_node(v.nodes, top, ntop, node);
+      if (COUNT) ++w.nodes;
       float tl, tr;
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
@@ -133,6 +143,7 @@ __device__ bool any_hit(const VolumeView& v, const float4* top, int ntop, const 
       const float4* tp = v.tris + 3 * (size_t)(first + k);
       float t;
       bool fr;
+      if (COUNT) ++w.tris;
       if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
     }
     if (st.sp == 0) return false;
@@ -157,7 +168,7 @@ __device__ __forceinline__ float3 probe_position(const VolumeView& v, int i) {
                      fmaf((float)z, v.sz, v.oz));
 }
 
-template <int KIND>
+template <int KIND, bool COUNT>
 __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Stack& st,
                            uint16_t* queue, uint32_t* vis, uint32_t base, uint32_t total) {
   const FrameParams& fp = *v.fp;
@@ -185,9 +196,10 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
   float t = INFINITY;
   bool front = false;
   int id = -1, slot = -1;
+  Work w;
   if (active && sc.num_tris > 0) {
     Ray ray = make_ray(o, d);
-    slot = closest_hit(v, top, ntop, ray, st, t, front, id);
+    slot = closest_hit<COUNT>(v, top, ntop, ray, st, t, front, id, w);
     if (slot < 0) {
       id = -1;
       t = INFINITY;
@@ -235,7 +247,7 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
       float len = sqrtf(gx * gx + gy * gy + gz * gz);
       float il = 1.0f / len;
       Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
-      bool blocked = any_hit(v, top, ntop, sray, len * (1.0f - kShadowShorten), st);
+      bool blocked = any_hit<COUNT>(v, top, ntop, sray, len * (1.0f - kShadowShorten), st, w);
       if (!blocked) atomicOr(&vis[src], 1u << l);
     }
   }
@@ -243,6 +255,17 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   uint32_t bits = vis[lane];
+  if (COUNT) {
+    uint32_t n = w.nodes, tt = w.tris;
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      n += __shfl_xor(n, o2);
+      tt += __shfl_xor(tt, o2);
+    }
+    if (lane == 0) {
+      atomicAdd((unsigned long long*)&v.stats->node_tests, (unsigned long long)n);
+      atomicAdd((unsigned long long*)&v.stats->tri_tests, (unsigned long long)tt);
+    }
+  }
   if (lane == 0 && qtotal > 0) atomicAdd((unsigned long long*)&v.stats->shadow_rays, (unsigned long long)qtotal);
 
   float3 L = make_float3(0.f, 0.f, 0.f);
@@ -284,7 +307,7 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
   }
 }
 
-template <int KIND>
+template <int KIND, bool COUNT>
 __global__ void trace_kernel(VolumeView v, int persistent, int ntop) {
   extern __shared__ float4 smem[];
   float4* top = smem;                                            // ntop * 4
@@ -309,11 +332,11 @@ __global__ void trace_kernel(VolumeView v, int persistent, int ntop) {
       if (lane_id() == 0) base = atomicAdd(counter, 64u);
       base = __shfl(base, 0);
       if (base >= total) break;
-      trace_wave<KIND>(v, top, ntop, st, queue, vis, base, total);
+      trace_wave<KIND, COUNT>(v, top, ntop, st, queue, vis, base, total);
     }
   } else {
     uint32_t base = (blockIdx.x * blockDim.x) + (uint32_t)wave * 64u;
-    if (base < total) trace_wave<KIND>(v, top, ntop, st, queue, vis, base, total);
+    if (base < total) trace_wave<KIND, COUNT>(v, top, ntop, st, queue, vis, base, total);
   }
 }
 
@@ -323,14 +346,17 @@ size_t trace_lds_bytes(int block, int ntop) {
 }
 
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
-                        int grid, int ntop) {
+                        int grid, int ntop, bool count) {
   size_t lds = trace_lds_bytes(block, ntop);
-  if (pilot)
-    hipLaunchKernelGGL(trace_kernel<KIND_PILOT>, dim3(grid), dim3(block), lds, s, v, persistent ? 1 : 0,
-                       ntop);
+  const int pers = persistent ? 1 : 0;
+  if (pilot && count)
+    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, true>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
+  else if (pilot)
+    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, false>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
+  else if (count)
+    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, true>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
   else
-    hipLaunchKernelGGL(trace_kernel<KIND_PRIMARY>, dim3(grid), dim3(block), lds, s, v,
-                       persistent ? 1 : 0, ntop);
+    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, false>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
   return hipGetLastError();
 }
 

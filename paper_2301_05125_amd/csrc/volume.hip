@@ -119,6 +119,7 @@ struct adgi_volume {
   hipEvent_t ev_user = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_slot[kParamSlots] = {};
   hipEvent_t ev_stage = nullptr;
+  hipEvent_t ev_k[7] = {};
   int device = 0, num_cus = 256;
   int32_t P = 0;
   bool sticky = false;
@@ -203,27 +204,44 @@ int lds_top_nodes(const adgi_volume* vol) {
   return std::min(vol->tun.lds_top_nodes, vol->num_nodes);
 }
 
-hipError_t enqueue_frame(adgi_volume* vol, bool adaptive) {
+// Stage boundaries recorded into ev[0..6] when ev is non-null (eager only):
+// 0 start, 1 frame_begin, 2 pilot trace, 3 detect, 4 allocate, 5 probe trace, 6 blend.
+hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullptr,
+                         bool count_work = false) {
   const adgi_tuning& t = vol->tun;
   VolumeView& v = vol->v;
   hipStream_t s = vol->stream;
   hipError_t e;
   const int ntop = lds_top_nodes(vol);
   const int pgrid = std::max(1, vol->num_cus * t.trace_waves_per_cu / (t.trace_block / 64));
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  if ((e = mark(0)) != hipSuccess) return e;
   if ((e = launch_frame_begin(v, s)) != hipSuccess) return e;
+  if ((e = mark(1)) != hipSuccess) return e;
   if (adaptive) {
     int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
     if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, ntop)) != hipSuccess) return e;
+    if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_detect(v, s)) != hipSuccess) return e;
+    if ((e = mark(3)) != hipSuccess) return e;
     if ((e = launch_alloc(v, s)) != hipSuccess) return e;
   } else {
+    if ((e = mark(2)) != hipSuccess) return e;
+    if ((e = mark(3)) != hipSuccess) return e;
     if ((e = launch_uniform_offsets(v, s)) != hipSuccess) return e;
   }
+  if ((e = mark(4)) != hipSuccess) return e;
+  // the counting run starts the probe trace from clean counters
+  if (count_work && (e = launch_frame_begin(v, s)) != hipSuccess) return e;
   int grid = t.persistent ? pgrid
                           : (int)((vol->desc.max_rays_per_frame + t.trace_block - 1) / t.trace_block);
-  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, ntop)) != hipSuccess) return e;
+  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, ntop, count_work)) != hipSuccess)
+    return e;
+  if ((e = mark(5)) != hipSuccess) return e;
+  if (count_work) return hipSuccess;
   BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
-  return launch_blend(v, io, s, vol->desc.storage == ADGI_FP16, t.blend_chunk);
+  if ((e = launch_blend(v, io, s, vol->desc.storage == ADGI_FP16, t.blend_chunk)) != hipSuccess) return e;
+  return mark(6);
 }
 
 adgi_status order_after_user(adgi_volume* vol) {
@@ -263,6 +281,8 @@ void release(adgi_volume* vol) {
   if (vol->h_stats) (void)hipHostFree(vol->h_stats);
   if (vol->h_scene) (void)hipHostFree(vol->h_scene);
   for (auto& e : vol->ev_slot)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : vol->ev_k)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage})
     if (e) (void)hipEventDestroy(e);
@@ -371,6 +391,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_t0, &vol->ev_t1, &vol->ev_stage})
     CREATE_TRY(hipEventCreate(e));
   for (auto& e : vol->ev_slot) CREATE_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : vol->ev_k) CREATE_TRY(hipEventCreate(&e));
   CREATE_TRY(hipHostMalloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots, hipHostMallocDefault));
   CREATE_TRY(hipHostMalloc((void**)&vol->h_stats, sizeof(FrameStats), hipHostMallocDefault));
   CREATE_TRY(hipHostMalloc((void**)&vol->h_scene, sizeof(SceneParams), hipHostMallocDefault));
@@ -655,7 +676,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
     }
     HIP_TRY(vol, hipGraphLaunch(vol->exec[mode], vol->stream));
   } else {
-    HIP_TRY(vol, enqueue_frame(vol, p->adaptive != 0));
+    HIP_TRY(vol, enqueue_frame(vol, p->adaptive != 0, p->sync ? vol->ev_k : nullptr));
   }
   HIP_TRY(vol, hipEventRecord(vol->ev_t1, vol->stream));
   vol->last_frame = p->frame;
@@ -680,6 +701,9 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       float ms = 0.f;
       HIP_TRY(vol, hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1));
       stats->ms_total = ms;
+      if (!vol->tun.use_graph)
+        for (int k = 0; k < 6; ++k)
+          HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[k], vol->ev_k[k], vol->ev_k[k + 1]));
     }
   }
   return ADGI_OK;
@@ -803,6 +827,36 @@ adgi_status adgi_restore_state(adgi_volume* vol, const void* src, size_t bytes) 
   return ADGI_OK;
 }
 
+
+adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* p, adgi_trace_work* out) {
+  if (!vol || !p || !out) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "measure before update_scene");
+  std::vector<uint8_t> snap(adgi_state_size(vol));
+  adgi_status st = adgi_save_state(vol, snap.data(), snap.size());
+  if (st != ADGI_OK) return st;
+  // parameters as update_probes would set them
+  adgi_update_params q = *p;
+  q.sync = 1;
+  const adgi_tuning saved = vol->tun;
+  vol->tun.use_graph = 0;
+  st = adgi_update_probes(vol, &q, nullptr);  // validates and uploads the parameter block
+  vol->tun = saved;
+  if (st != ADGI_OK) {
+    (void)adgi_restore_state(vol, snap.data(), snap.size());
+    return st;
+  }
+  HIP_TRY(vol, enqueue_frame(vol, p->adaptive != 0, nullptr, true));
+  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  HIP_TRY(vol, hipMemcpy(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost));
+  uint32_t total = 0;
+  HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
+  out->primary_rays = total;
+  out->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
+  out->node_tests = (int64_t)vol->h_stats->node_tests;
+  out->tri_tests = (int64_t)vol->h_stats->tri_tests;
+  return adgi_restore_state(vol, snap.data(), snap.size());
+}
 
 // ---- autotuning: time candidate launch shapes of the two dominant kernels
 // on the current frame, then restore the state saved before.

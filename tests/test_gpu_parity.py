@@ -41,3 +41,35 @@ def test_cornell_adaptive_budget():
     sc.frames = 6
     res = run_lockstep(sc, frames=6, adaptive=True, budget=64 * 40, n_min=8, n_max=200)
     _assert_parity(res)
+
+
+def test_tunnel_adaptive_lockstep():
+    """Tunnel (~100k triangles, 2048 probes), adaptive B = 2^19, n in [32, 1024],
+    two moving lights, four frames (two detection pairs), 256 sampled probes."""
+    sc = scenes.tunnel()
+    probes = scenes.sample_probes(sc.num_probes, 256)
+    res = run_lockstep(sc, frames=4, adaptive=True, budget=1 << 19, n_min=32, n_max=1024,
+                       probes=probes)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_parity(res)
+
+
+def test_box_field_sampled_probes_with_refit():
+    """1M-triangle box field, 65,536 probes, B = 2^23, n in [8, 2048], animated
+    boxes refit on the device every frame; 128 sampled probes, three frames."""
+    sc = scenes.box_field()
+    probes = scenes.sample_probes(sc.num_probes, 128)
+    res = run_lockstep(sc, frames=3, adaptive=True, budget=1 << 23, n_min=8, n_max=2048,
+                       probes=probes)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_parity(res)
+
+
+def test_fp16_storage_against_fp16_emulating_oracle():
+    """FP16 texels (FP32 arithmetic, RNE store) vs. the oracle rounding to
+    binary16 at every frame store: <= 2e-3 relative."""
+    import paper_2301_05125_amd as adgi
+    res = run_lockstep(scenes.cornell(), frames=8, adaptive=False, n_uniform=64,
+                       storage=adgi.ADGI_FP16)
+    assert res["mismatches"] == 0 and res["count_mismatch"] == 0, res
+    assert res["max_rel_irr"] <= 2e-3 and res["max_rel_depth"] <= 2e-3, res

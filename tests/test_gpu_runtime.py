@@ -1,0 +1,138 @@
+"""Runtime behaviour of the library on the GPU: determinism across runs,
+launch shapes and graph/eager execution, snapshots, and error paths."""
+import numpy as np
+import pytest
+
+import paper_2301_05125_amd as adgi
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(sc, frames, adaptive, tuning=None, budget=0, n_min=8, n_max=256, n_uniform=64,
+         storage=adgi.ADGI_FP32, seed=3, vol=None, start=0):
+    own = vol is None
+    if own:
+        vol = adgi.volume_for_scene(sc, storage=storage, max_rays=max(budget, sc.num_probes * n_uniform),
+                                    seed=seed)
+    if tuning:
+        vol.set_tuning(**tuning)
+    for f in range(start, start + frames):
+        vol.update_scene(sc.positions_at(f), light_pos=sc.light_positions(f),
+                         light_intensity=sc.light_intensity, sky=sc.sky,
+                         mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, sc.anim_vertices))
+        vol.update_probes(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
+                          n_uniform=n_uniform, sync=True)
+    rb = vol.read_probes()
+    if own:
+        vol.destroy_volume()
+    return rb
+
+
+def _small_field():
+    return scenes.box_field(lattice=48, dims=(16, 4, 16), frames=8)
+
+
+def _same(a, b):
+    for k in ("irradiance", "depth", "irr_count", "depth_count", "rays_per_probe", "score"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_bitwise_determinism_across_runs():
+    sc = _small_field()
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    _same(_run(sc, 6, **kw), _run(sc, 6, **kw))
+
+
+@pytest.mark.parametrize("tuning", [
+    {"use_graph": 0},
+    {"persistent": 0},
+    {"trace_block": 64, "trace_waves_per_cu": 8},
+    {"trace_block": 128, "lds_top_nodes": 256},
+    {"blend_chunk": 64},
+    {"blend_chunk": 512},
+])
+def test_launch_shape_does_not_change_results(tuning):
+    sc = _small_field()
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    _same(_run(sc, 4, **kw), _run(sc, 4, tuning=tuning, **kw))
+
+
+def test_autotune_keeps_state_and_results():
+    sc = _small_field()
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    ref = _run(sc, 4, **kw)
+    vol = adgi.volume_for_scene(sc, max_rays=sc.num_probes * 40, seed=3)
+    _run(sc, 2, vol=vol, **kw)
+    before = vol.read_probes()
+    chosen = vol.autotune(2, **kw)
+    assert chosen["trace_block"] in (64, 128, 256)
+    after = vol.read_probes()
+    _same(before, after)
+    out = _run(sc, 2, vol=vol, start=2, **kw)
+    vol.destroy_volume()
+    _same(ref, out)
+
+
+def test_snapshot_resumes_bit_identically():
+    sc = _small_field()
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    ref = _run(sc, 6, **kw)
+    v1 = adgi.volume_for_scene(sc, max_rays=sc.num_probes * 40, seed=3)
+    _run(sc, 3, vol=v1, **kw)
+    snap = v1.save_state()
+    v1.destroy_volume()
+    v2 = adgi.volume_for_scene(sc, max_rays=sc.num_probes * 40, seed=3)
+    v2.restore_state(snap)
+    out = _run(sc, 3, vol=v2, start=3, **kw)
+    v2.destroy_volume()
+    _same(ref, out)
+
+
+def test_error_paths():
+    sc = scenes.cornell()
+    vol = adgi.Volume(sc.grid_origin, sc.grid_spacing, sc.grid_dims, max_rays_per_frame=64 * 64)
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_probes(0, adaptive=False, n_uniform=64)
+    assert e.value.status == -4  # no scene
+    vol.update_scene(sc.positions, sc.indices, sc.albedo, sc.light_positions(0),
+                     sc.light_intensity, sc.sky)
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_probes(0, adaptive=True, budget=64 * 8 - 1, n_min=8, n_max=64)
+    assert e.value.status == -3  # budget below P * n_min
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_probes(0, adaptive=False, n_uniform=65)
+    assert e.value.status == -3  # over max_rays_per_frame
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_scene(sc.positions[:-1], light_pos=sc.light_positions(0),
+                         light_intensity=sc.light_intensity, mode=adgi.ADGI_SCENE_REFIT)
+    assert e.value.status == -5  # topology change
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_scene(sc.positions, sc.indices, sc.albedo, np.zeros((9, 3)), np.ones((9, 3)))
+    assert e.value.status == -1  # too many lights
+    # the volume is unchanged and still works after every rejected call
+    vol.update_probes(0, adaptive=False, n_uniform=64)
+    rb = vol.read_probes()
+    assert rb["irr_count"].sum() > 0
+    vol.destroy_volume()
+
+
+def test_allocator_failure_reports_out_of_memory():
+    calls = {"n": 0}
+
+    def alloc(nbytes, ctx):
+        calls["n"] += 1
+        if calls["n"] > 5:
+            return None
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+    def free(ptr, ctx):
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = adgi.Allocator(adgi.ALLOC_FN(alloc), adgi.FREE_FN(free), None)
+    sc = scenes.cornell()
+    with pytest.raises(adgi.AdgiError) as e:
+        adgi.Volume(sc.grid_origin, sc.grid_spacing, sc.grid_dims, allocator=a)
+    assert e.value.status == -2
