@@ -8,9 +8,11 @@ loudly when the library has not been built: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -103,6 +105,14 @@ class Tuning(C.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_volumes():
+    """Release device state while torch (the allocator) is still alive."""
+    for v in list(_live):
+        v.destroy_volume()
 
 
 def lib():
@@ -169,7 +179,8 @@ def _torch_allocator():
             return None
 
     def _free(ptr, ctx):
-        torch.cuda.caching_allocator_delete(int(ptr))
+        if torch.cuda is not None:
+            torch.cuda.caching_allocator_delete(int(ptr))
 
     a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
     return a
@@ -212,6 +223,7 @@ class Volume:
         _check(lib().adgi_create_volume(C.byref(d), C.byref(self._alloc) if self._alloc else None,
                                         C.c_void_p(stream) if stream else None, C.byref(h)))
         self.h = h
+        _live.add(self)
 
     def __del__(self):
         self.destroy_volume()

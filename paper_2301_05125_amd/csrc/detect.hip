@@ -48,35 +48,28 @@ __global__ void trigger_kernel(VolumeView v) {
   v.trig[e] = t;
 }
 
-// 5-tap sum along one grid axis; element e = probe * 8 + octant.
+// 5-tap sum along one grid axis; element e = probe * 8 + octant. The axis is
+// given by its probe-index divisor (1, dx, dx*dy) and extent (dx, dy, dz), so
+// the kernel is straight-line code: the coordinate along the axis is
+// (i / div) % D and neighbours are 8 * div elements apart.
 __global__ void box_pass_kernel(VolumeView v, const int2* __restrict__ src, int2* __restrict__ dst,
-                                int axis) {
+                                int div, int D) {
   const FrameParams& fp = *v.fp;
   if (!fp.adaptive || (fp.frame & 1) == 0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 8 * v.P) return;
   const int i = e >> 3;
-  int c, D, stride;
-  if (axis == 0) {
-    c = i % v.dx;
-    D = v.dx;
-    stride = 8;
-  } else if (axis == 1) {
-    c = (i / v.dx) % v.dy;
-    D = v.dy;
-    stride = 8 * v.dx;
-  } else {
-    c = i / (v.dx * v.dy);
-    D = v.dz;
-    stride = 8 * v.dx * v.dy;
-  }
+  const int c = (i / div) % D;
+  const int stride = 8 * div;
   int sx = 0, sy = 0;
+#pragma unroll
   for (int o = -2; o <= 2; ++o) {
-    int cc = c + o;
-    if (cc < 0 || cc >= D) continue;
-    int2 t = src[e + o * stride];
-    sx += t.x;
-    sy += t.y;
+    const int cc = c + o;
+    if (cc >= 0 && cc < D) {
+      const int2 t = src[e + o * stride];
+      sx += t.x;
+      sy += t.y;
+    }
   }
   dst[e] = make_int2(sx, sy);
 }
@@ -104,10 +97,12 @@ hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s) {
 hipError_t launch_detect(const VolumeView& v, hipStream_t s) {
   const int n = 8 * v.P, g = (n + 255) / 256;
   hipLaunchKernelGGL(trigger_kernel, dim3(g), dim3(256), 0, s, v);
-  // box: trig -> a (x) -> b (y) -> a (z) ; score reads b, so run z into b
-  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.trig, v.box_a, 0);
-  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_a, v.box_b, 1);
-  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_b, v.box_a, 2);
+  // box sum: trig -> a (x) -> b (y) -> a (z); the score reads a
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.trig, v.box_a, 1, v.dx);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_a, v.box_b, v.dx,
+                     v.dy);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_b, v.box_a,
+                     v.dx * v.dy, v.dz);
   VolumeView w = v;
   w.box_b = v.box_a;  // score reads the z-pass output
   hipLaunchKernelGGL(score_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, w);
