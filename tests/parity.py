@@ -95,17 +95,29 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             base = rb["ray_offsets"][sel]
             n_sel = out["n"][sel]
             idx = np.concatenate([np.arange(b, b + k) for b, k in zip(base, n_sel)])
+            owner = np.repeat(np.arange(len(sel)), n_sel)
             g = rb["ray_record"][idx].astype(np.float64)
             o = out["rays"]
             same = rb["hit_tri"][idx] == out["tri"]
-            gt = np.where(np.isinf(g[:, 3]), 0.0, g[:, 3])
-            ot = np.where(np.isinf(o[:, 3]), 0.0, o[:, 3])
-            if np.any(np.isinf(g[:, 3]) != np.isinf(o[:, 3])):
-                res["mismatches"] += int(np.count_nonzero(np.isinf(g[:, 3]) != np.isinf(o[:, 3])))
-            e_rgb = np.abs(g[:, :3] - o[:, :3]) / np.maximum(np.abs(o[:, :3]), 1e-6)
-            e_t = np.abs(gt - ot) / np.maximum(np.abs(ot), 1e-6)
-            e = np.maximum(e_rgb.max(axis=1), e_t)[same]
-            res["max_rel_ray"] = max(res["max_rel_ray"], float(e.max(initial=0.0)))
+            miss_g, miss_o = np.isinf(g[:, 3]), np.isinf(o[:, 3])
+            res["mismatches"] += int(np.count_nonzero(miss_g != miss_o))
+            gt = np.where(miss_g, 0.0, g[:, 3])
+            ot = np.where(miss_o, 0.0, o[:, 3])
+            # per-probe floor as for texels: 1e-3 x the probe's largest value
+            peak_rgb = np.zeros(len(sel))
+            np.maximum.at(peak_rgb, owner, np.abs(o[:, :3]).max(axis=1))
+            peak_t = np.zeros(len(sel))
+            np.maximum.at(peak_t, owner, np.abs(ot))
+            den_rgb = np.maximum(np.maximum(np.abs(o[:, :3]), 1e-3 * peak_rgb[owner][:, None]), 1e-8)
+            den_t = np.maximum(np.maximum(np.abs(ot), 1e-3 * peak_t[owner]), 1e-8)
+            e = np.maximum((np.abs(g[:, :3] - o[:, :3]) / den_rgb).max(axis=1),
+                           np.abs(gt - ot) / den_t)
+            e = np.where(same, e, 0.0)
+            k = int(np.argmax(e)) if e.size else 0
+            if e.size and e[k] > res["max_rel_ray"]:
+                res["max_rel_ray"] = float(e[k])
+                res["worst_ray"] = {"gpu": g[k].tolist(), "oracle": o[k].tolist(),
+                                    "tri": int(out["tri"][k]), "frame": f}
     res["irr_gpu"] = rb["irradiance"][sel]
     res["irr_oracle"] = ora.irradiance_tiles()
     res["oracle_counts"] = ora.counts.as_dict()
