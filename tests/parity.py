@@ -54,7 +54,7 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
     sel = ora.probes
     res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "max_rel_ray": 0.0,
            "ties": {}, "frames": frames, "rays": 0, "count_mismatch": 0, "score_mismatch": 0,
-           "alloc_mismatch": 0, "rotation_mismatch": 0}
+           "alloc_mismatch": 0, "rotation_mismatch": 0, "max_rel_t": 0.0}
     for f in range(frames):
         if f > 0:
             gpu_scene_update(vol, scene, f)
@@ -110,9 +110,10 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             np.maximum.at(peak_t, owner, np.abs(ot))
             den_rgb = np.maximum(np.maximum(np.abs(o[:, :3]), 1e-3 * peak_rgb[owner][:, None]), 1e-8)
             den_t = np.maximum(np.maximum(np.abs(ot), 1e-3 * peak_t[owner]), 1e-8)
-            e = np.maximum((np.abs(g[:, :3] - o[:, :3]) / den_rgb).max(axis=1),
-                           np.abs(gt - ot) / den_t)
+            e = (np.abs(g[:, :3] - o[:, :3]) / den_rgb).max(axis=1)
             e = np.where(same, e, 0.0)
+            et = np.where(same, np.abs(gt - ot) / den_t, 0.0)
+            res["max_rel_t"] = max(res.get("max_rel_t", 0.0), float(et.max(initial=0.0)))
             k = int(np.argmax(e)) if e.size else 0
             if e.size and e[k] > res["max_rel_ray"]:
                 res["max_rel_ray"] = float(e[k])
