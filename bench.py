@@ -90,8 +90,16 @@ def light_frame(frame, period=60):
     return f if f <= period else 2 * period - f
 
 
+_POS = {}
+
+
 def step_scene(vol, sc, frame, adgi):
-    vol.update_scene(sc.positions_at(frame), light_pos=sc.light_positions(light_frame(frame)),
+    """Scene update of one step: animated vertex prefix and lights."""
+    pos = _POS.get(id(sc))
+    if pos is None:
+        pos = _POS[id(sc)] = sc.positions.copy()
+    sc.write_animated(frame, pos)
+    vol.update_scene(pos, light_pos=sc.light_positions(light_frame(frame)),
                      light_intensity=sc.light_intensity, sky=sc.sky, mode=adgi.ADGI_SCENE_REFIT,
                      refit_range=(0, sc.anim_vertices))
 

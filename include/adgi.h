@@ -198,7 +198,9 @@ typedef struct {
                                  0: one thread per ray, grid sized to the rays    */
   int32_t trace_block;        /* threads per traversal workgroup: 64..1024, x64   */
   int32_t trace_waves_per_cu; /* persistent grid = CUs * this / (block/64), 1..32 */
-  int32_t blend_chunk;        /* rays staged in LDS per blend step: 64..2048, x64 */
+  int32_t blend_chunk;        /* 0: wave-per-probe blend (tiles 8/16 or 16/16);
+                                 64..2048, x64: rays staged in LDS per step of the
+                                 workgroup-per-probe blend                        */
   int32_t lds_top_nodes;      /* BVH nodes staged in LDS per workgroup: 0..1024   */
 } adgi_tuning;
 

@@ -63,6 +63,7 @@ struct FrameStats {
   uint64_t budget_used;
   uint64_t node_tests;      // work-counting traversal only
   uint64_t tri_tests;
+  int64_t remainder;        // R = B' - sum e_i(lambda*)
   uint64_t sums[4][kAllocCandidates];
 };
 
@@ -94,6 +95,10 @@ struct VolumeView {
   // allocation
   int32_t* n;                 // [P]
   uint32_t* offsets;          // [P+1]
+  int64_t* blk_e;             // [ceil(P/256)] per-block sum of e_i(lambda*)
+  uint32_t* blk_el;           // per-block count of probes eligible for the top-up
+  uint32_t* blk_rank;         // per-block exclusive rank base among eligible probes
+  uint32_t* blk_off;          // per-block exclusive ray offset
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
   int32_t* dbg_tri;           // [max_rays] or null

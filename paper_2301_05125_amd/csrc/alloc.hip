@@ -12,8 +12,9 @@
 // the monotone sum at 255 candidates in parallel (one candidate per thread,
 // the block's weights staged in LDS) and accumulates per-candidate integer
 // sums with atomics; every block of the next pass replays the narrowing from
-// those sums, so no grid-wide synchronisation is needed. A single workgroup
-// then derives e_i, the top-up ranks and the exclusive scan of n_i.
+// those sums, so no grid-wide synchronisation is needed. The top-up ranks and
+// the exclusive scan of n_i then take three passes: per-block sums, a scan
+// over the blocks in one workgroup, and per-block local scans.
 #include "adgi_internal.hpp"
 
 namespace adgi {
@@ -121,73 +122,125 @@ __device__ int64_t block_exclusive_scan(int64_t x, int64_t* sm, int64_t& total) 
   return v - x + sm[wave];
 }
 
-__global__ __launch_bounds__(1024) void alloc_finalize_kernel(VolumeView v) {
+// Finalize in three parallel steps over blocks of 256 probes:
+//   F1 per block: e_i(lambda*), top-up eligibility, block sums;
+//   F2 one workgroup: R, exclusive rank bases and ray offsets of the blocks;
+//   F3 per block: local scans -> bonus_i, n_i and ray offsets.
+__global__ __launch_bounds__(256) void alloc_blocks_kernel(VolumeView v) {
+  const FrameParams& fp = *v.fp;
+  if (!fp.adaptive) return;
+  __shared__ uint32_t lam_s;
+  __shared__ int64_t red_e[4];
+  __shared__ uint32_t red_el[4];
+  const int64_t Bp = fp.budget - (int64_t)v.P * fp.n_min;
+  const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
+  if (threadIdx.x == 0) {
+    uint32_t lo, hi;
+    replay_interval(v.stats, kAllocPasses, Bp, lo, hi);
+    lam_s = lo;
+  }
+  __syncthreads();
+  const uint32_t lam = lam_s;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  int64_t e0 = 0;
+  uint32_t el = 0;
+  if (i < v.P) {
+    const uint32_t w = weight_of((uint64_t)v.score[i], v.stats->max_score);
+    const uint32_t a = extra_rays(lam, w, E), b = extra_rays(lam + 1u, w, E);
+    e0 = a;
+    el = b > a ? 1u : 0u;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    e0 += __shfl_xor(e0, o);
+    el += __shfl_xor(el, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red_e[threadIdx.x >> 6] = e0;
+    red_el[threadIdx.x >> 6] = el;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v.blk_e[blockIdx.x] = red_e[0] + red_e[1] + red_e[2] + red_e[3];
+    v.blk_el[blockIdx.x] = red_el[0] + red_el[1] + red_el[2] + red_el[3];
+    if (blockIdx.x == 0) v.stats->lambda = lam;
+  }
+}
+
+__global__ __launch_bounds__(1024) void alloc_scan_blocks_kernel(VolumeView v) {
   const FrameParams& fp = *v.fp;
   if (!fp.adaptive) return;
   __shared__ int64_t sm[17];
-  __shared__ int32_t mm[2][16];
-  const int P = v.P;
-  const int64_t Bp = fp.budget - (int64_t)P * fp.n_min;
-  const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
-  uint32_t lam, hi;
-  replay_interval(v.stats, kAllocPasses, Bp, lam, hi);
-  const uint64_t maxs = v.stats->max_score;
-  const int per = (P + blockDim.x - 1) / blockDim.x;
-  const int b = threadIdx.x * per, e = min(P, b + per);
-  int64_t se = 0, sel = 0;
-  for (int i = b; i < e; ++i) {
-    uint32_t w = weight_of((uint64_t)v.score[i], maxs);
-    uint32_t e0 = extra_rays(lam, w, E), e1 = extra_rays(lam + 1u, w, E);
-    se += e0;
-    sel += e1 > e0;
-  }
+  const int nb = (v.P + 255) / 256;
+  const int64_t Bp = fp.budget - (int64_t)v.P * fp.n_min;
+  // total extras -> remainder R
+  int64_t part = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) part += v.blk_e[b];
   int64_t tot_e;
-  block_exclusive_scan(se, sm, tot_e);
-  int64_t tot_el;
-  int64_t rank = block_exclusive_scan(sel, sm, tot_el);
+  block_exclusive_scan(part, sm, tot_e);
   const int64_t R = Bp - tot_e;
-  int64_t nsum = 0;
-  for (int i = b; i < e; ++i) {
-    uint32_t w = weight_of((uint64_t)v.score[i], maxs);
-    uint32_t e0 = extra_rays(lam, w, E), e1 = extra_rays(lam + 1u, w, E);
-    int bonus = 0;
-    if (e1 > e0) {
-      bonus = rank < R ? 1 : 0;
-      ++rank;
+  // exclusive scans over blocks, in tiles of blockDim with a running carry
+  int64_t carry_rank = 0, carry_off = 0;
+  for (int t0 = 0; t0 < nb; t0 += blockDim.x) {
+    const int b = t0 + threadIdx.x;
+    int64_t el = 0, nsum = 0;
+    if (b < nb) el = v.blk_el[b];
+    int64_t tot;
+    int64_t rank = carry_rank + block_exclusive_scan(el, sm, tot);
+    if (b < nb) {
+      const int cnt = min(256, v.P - b * 256);
+      int64_t bonus = R - rank;
+      bonus = bonus < 0 ? 0 : (bonus > el ? el : bonus);
+      nsum = (int64_t)cnt * fp.n_min + v.blk_e[b] + bonus;
     }
-    int n = fp.n_min + (int)e0 + bonus;
-    v.n[i] = n;
-    nsum += n;
+    carry_rank += tot;
+    int64_t tot_n;
+    int64_t off = carry_off + block_exclusive_scan(nsum, sm, tot_n);
+    carry_off += tot_n;
+    if (b < nb) {
+      v.blk_rank[b] = (uint32_t)rank;
+      v.blk_off[b] = (uint32_t)off;
+    }
   }
-  int64_t total;
-  int64_t off = block_exclusive_scan(nsum, sm, total);
+  if (threadIdx.x == 0) {
+    v.stats->remainder = R;
+    v.offsets[v.P] = (uint32_t)carry_off;
+    v.stats->budget_used = (uint64_t)carry_off;
+    v.stats->n_min_seen = 0x7fffffff;
+    v.stats->n_max_seen = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void alloc_write_kernel(VolumeView v) {
+  const FrameParams& fp = *v.fp;
+  if (!fp.adaptive) return;
+  __shared__ int64_t sm[17];
+  const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
+  const uint32_t lam = v.stats->lambda;
+  const int64_t R = v.stats->remainder;
+  const int b = blockIdx.x, i = b * 256 + threadIdx.x;
+  uint32_t e0 = 0, el = 0;
+  if (i < v.P) {
+    const uint32_t w = weight_of((uint64_t)v.score[i], v.stats->max_score);
+    e0 = extra_rays(lam, w, E);
+    el = extra_rays(lam + 1u, w, E) > e0 ? 1u : 0u;
+  }
+  int64_t tot;
+  const int64_t rank = (int64_t)v.blk_rank[b] + block_exclusive_scan((int64_t)el, sm, tot);
+  const int n = fp.n_min + (int)e0 + ((el && rank < R) ? 1 : 0);
+  const int64_t off = (int64_t)v.blk_off[b] + block_exclusive_scan(i < v.P ? (int64_t)n : 0, sm, tot);
   int nmin = 0x7fffffff, nmax = 0;
-  for (int i = b; i < e; ++i) {
+  if (i < v.P) {
+    v.n[i] = n;
     v.offsets[i] = (uint32_t)off;
-    int n = v.n[i];
-    off += n;
-    nmin = min(nmin, n);
-    nmax = max(nmax, n);
+    nmin = nmax = n;
   }
   for (int o = 32; o > 0; o >>= 1) {
     nmin = min(nmin, __shfl_xor(nmin, o));
     nmax = max(nmax, __shfl_xor(nmax, o));
   }
   if ((threadIdx.x & 63) == 0) {
-    mm[0][threadIdx.x >> 6] = nmin;
-    mm[1][threadIdx.x >> 6] = nmax;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-      nmin = min(nmin, mm[0][w]);
-      nmax = max(nmax, mm[1][w]);
-    }
-    v.offsets[P] = (uint32_t)total;
-    v.stats->lambda = lam;
-    v.stats->n_min_seen = nmin;
-    v.stats->n_max_seen = nmax;
-    v.stats->budget_used = (uint64_t)total;
+    atomicMin(&v.stats->n_min_seen, nmin);
+    atomicMax(&v.stats->n_max_seen, nmax);
   }
 }
 
@@ -210,7 +263,9 @@ hipError_t launch_alloc(const VolumeView& v, hipStream_t s) {
   hipLaunchKernelGGL(alloc_max_kernel, dim3(g < 1024 ? g : 1024), dim3(256), 0, s, v);
   for (int p = 0; p < kAllocPasses; ++p)
     hipLaunchKernelGGL(lambda_pass_kernel, dim3(g), dim3(256), 0, s, v, p);
-  hipLaunchKernelGGL(alloc_finalize_kernel, dim3(1), dim3(1024), 0, s, v);
+  hipLaunchKernelGGL(alloc_blocks_kernel, dim3(g), dim3(256), 0, s, v);
+  hipLaunchKernelGGL(alloc_scan_blocks_kernel, dim3(1), dim3(1024), 0, s, v);
+  hipLaunchKernelGGL(alloc_write_kernel, dim3(g), dim3(256), 0, s, v);
   return hipGetLastError();
 }
 

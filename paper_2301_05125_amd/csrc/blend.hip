@@ -239,11 +239,199 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-per-probe variant for the common tile sizes. One 64-lane wave owns one
+// probe: interior texel k lives in the registers of lane k % 64 (slot k / 64)
+// for the whole frame. Rays are taken 64 at a time, one per lane; each lane
+// ORs its lane bit into a 64-bit LDS mask of the irradiance texel and of the
+// depth texel its direction falls in, and every owner then walks the set bits
+// of its texels' masks from the lowest: that is ascending ray order, so no
+// sort is needed, and all synchronisation is within the wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int RI, int RD>
+struct WaveTile {
+  static constexpr int NI = RI * RI, ND = RD * RD, NT = NI + ND;
+  static constexpr int SI = (NI + 63) / 64, SD = (ND + 63) / 64;
+  static constexpr int GI = RI + 2, GD = RD + 2;
+  static constexpr size_t kChunkBytes = 64 * 16 + 8 * (size_t)NT;
+  static constexpr size_t kStageBytes = 4 * (3 * (size_t)NI + 2 * (size_t)ND) + NT;
+  static constexpr size_t kWaveBytes =
+      ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
+};
+
+template <int RI, int RD, bool HALF>
+__global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io) {
+  using S = Store<HALF>;
+  using T = typename S::T;
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= v.P) return;  // uniform per wave
+  uint8_t* wbase = smem + (size_t)wave * W::kWaveBytes;
+  float4* rec_s = (float4*)wbase;
+  unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
+  const FrameParams& fp = *v.fp;
+
+  // ---- owned interior texels into registers
+  const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
+  const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
+  float vi[SI][3], vd[SD][2];
+  uint32_t ni[SI], nd[SD];
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    vi[s][0] = vi[s][1] = vi[s][2] = 0.f;
+    ni[s] = 0u;
+    if (k < NI) {
+      const int iy = k / RI, ix = k - iy * RI;
+      const T* p = irr_in + ((iy + 1) * GI + ix + 1) * 3;
+      vi[s][0] = S::load(p);
+      vi[s][1] = S::load(p + 1);
+      vi[s][2] = S::load(p + 2);
+      ni[s] = io.irr_n_in[(size_t)i * NI + k];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    vd[s][0] = vd[s][1] = 0.f;
+    nd[s] = 0u;
+    if (k < ND) {
+      const int iy = k / RD, ix = k - iy * RD;
+      const T* p = dep_in + ((iy + 1) * GD + ix + 1) * 2;
+      vd[s][0] = S::load(p);
+      vd[s][1] = S::load(p + 1);
+      nd[s] = io.dep_n_in[(size_t)i * ND + k];
+    }
+  }
+
+  const uint32_t off = v.offsets[i];
+  const uint32_t n = v.offsets[i + 1] - off;
+  const float inv_s = 1.0f / v.s_diag;
+  const float omh = v.one_minus_h, tmax = v.tau_max;
+  for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
+    const uint32_t m = min(64u, n - c0);
+    for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
+    wave_sync();
+    if ((uint32_t)lane < m) {
+      const uint32_t j = c0 + (uint32_t)lane;
+      rec_s[lane] = v.rec[off + j];
+      const float2 uv = oct_encode(sf_direction(j, n, fp.R));
+      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
+      atomicOr(&mask[bI], 1ull << lane);
+      atomicOr(&mask[NI + bD], 1ull << lane);
+      if (fp.debug) {
+        v.dbg_ibin[off + j] = (uint16_t)bI;
+        v.dbg_dbin[off + j] = (uint16_t)bD;
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < SI; ++s) {
+      const int k = lane + 64 * s;
+      unsigned long long mk = k < NI ? mask[k] : 0ull;
+      while (mk) {
+        const int j = __ffsll((long long)mk) - 1;
+        mk &= mk - 1ull;
+        const float4 r = rec_s[j];
+        const float al = fmaxf(1.0f / (float)(ni[s] + 1u), omh);
+        vi[s][0] = fmaf(al, r.x - vi[s][0], vi[s][0]);
+        vi[s][1] = fmaf(al, r.y - vi[s][1], vi[s][1]);
+        vi[s][2] = fmaf(al, r.z - vi[s][2], vi[s][2]);
+        ni[s] = min(ni[s] + 1u, 255u);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SD; ++s) {
+      const int k = lane + 64 * s;
+      unsigned long long mk = k < ND ? mask[NI + k] : 0ull;
+      while (mk) {
+        const int j = __ffsll((long long)mk) - 1;
+        mk &= mk - 1ull;
+        const float tau = fminf(rec_s[j].w * inv_s, tmax);
+        const float al = fmaxf(1.0f / (float)(nd[s] + 1u), omh);
+        vd[s][0] = fmaf(al, tau - vd[s][0], vd[s][0]);
+        vd[s][1] = fmaf(al, tau * tau - vd[s][1], vd[s][1]);
+        nd[s] = min(nd[s] + 1u, 255u);
+      }
+    }
+    wave_sync();
+  }
+
+  // ---- stage the interior in LDS, then write both tiles with the border fold
+  float* stI = (float*)wbase;
+  float* stD = stI + 3 * NI;
+  uint8_t* stN = (uint8_t*)(stD + 2 * ND);
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    if (k < NI) {
+      stI[3 * k] = vi[s][0];
+      stI[3 * k + 1] = vi[s][1];
+      stI[3 * k + 2] = vi[s][2];
+      stN[k] = (uint8_t)ni[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    if (k < ND) {
+      stD[2 * k] = vd[s][0];
+      stD[2 * k + 1] = vd[s][1];
+      stN[NI + k] = (uint8_t)nd[s];
+    }
+  }
+  wave_sync();
+  T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
+  T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
+  for (int f = lane; f < GI * GI * 3; f += 64) {
+    const int t = f / 3, c = f - 3 * t, Y = t / GI, X = t - Y * GI;
+    int sx, sy;
+    border_source(X, Y, RI, sx, sy);
+    S::store(irr_out + f, stI[((sy - 1) * RI + (sx - 1)) * 3 + c]);
+  }
+  for (int f = lane; f < GD * GD * 2; f += 64) {
+    const int t = f >> 1, c = f & 1, Y = t / GD, X = t - Y * GD;
+    int sx, sy;
+    border_source(X, Y, RD, sx, sy);
+    S::store(dep_out + f, stD[((sy - 1) * RD + (sx - 1)) * 2 + c]);
+  }
+  for (int k = lane; k < NI; k += 64) io.irr_n_out[(size_t)i * NI + k] = stN[k];
+  for (int k = lane; k < ND; k += 64) io.dep_n_out[(size_t)i * ND + k] = stN[NI + k];
+}
+
+bool blend_wave_supported(const VolumeView& v) {
+  return (v.irr_res == 8 && v.dep_res == 16) || (v.irr_res == 16 && v.dep_res == 16);
+}
+
 size_t blend_lds_bytes(const VolumeView& v, int chunk) {
   return blend_layout(v.irr_res, v.dep_res, chunk, nullptr, nullptr);
 }
 
+template <int RI, int RD>
+static void launch_wave(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16) {
+  const size_t lds = 4 * WaveTile<RI, RD>::kWaveBytes;
+  const int grid = (v.P + 3) / 4;
+  if (fp16)
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
+  else
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
+}
+
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk) {
+  if (chunk == 0) {  // wave-per-probe kernel
+    if (v.irr_res == 8 && v.dep_res == 16) launch_wave<6, 14>(v, io, s, fp16);
+    else if (v.irr_res == 16 && v.dep_res == 16) launch_wave<14, 14>(v, io, s, fp16);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   size_t lds = blend_lds_bytes(v, chunk);
   if (fp16)
     hipLaunchKernelGGL(blend_kernel<true>, dim3(v.P), dim3(256), lds, s, v, io, chunk);

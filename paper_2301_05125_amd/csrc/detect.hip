@@ -30,6 +30,7 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->budget_used = 0ull;
     st->node_tests = 0ull;
     st->tri_tests = 0ull;
+    st->remainder = 0;
   }
   if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;
 }

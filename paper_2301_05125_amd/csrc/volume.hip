@@ -305,8 +305,9 @@ adgi_tuning default_tuning() {
 bool tuning_valid(const adgi_tuning& t) {
   return (t.use_graph == 0 || t.use_graph == 1) && (t.persistent == 0 || t.persistent == 1) &&
          t.trace_block >= 64 && t.trace_block <= 1024 && t.trace_block % 64 == 0 &&
-         t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 && t.blend_chunk >= 64 &&
-         t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0 && t.lds_top_nodes >= 0 &&
+         t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 &&
+         (t.blend_chunk == 0 || (t.blend_chunk >= 64 && t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0)) &&
+         t.lds_top_nodes >= 0 &&
          t.lds_top_nodes <= 1024;
 }
 
@@ -425,6 +426,10 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.score, (size_t)P * 8},
       {(void**)&v.n, (size_t)P * 4},
       {(void**)&v.offsets, (size_t)(P + 1) * 4},
+      {(void**)&v.blk_e, (size_t)((P + 255) / 256) * 8},
+      {(void**)&v.blk_el, (size_t)((P + 255) / 256) * 4},
+      {(void**)&v.blk_rank, (size_t)((P + 255) / 256) * 4},
+      {(void**)&v.blk_off, (size_t)((P + 255) / 256) * 4},
       {(void**)&v.rec, R * 16},
   };
   if (dbg) {
@@ -464,6 +469,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.one_minus_h = (float)(1.0 - (double)d->hysteresis);
   v.tau_max = d->tau_max;
   v.max_rays = (uint32_t)R;
+  if (blend_wave_supported(v)) vol->tun.blend_chunk = 0;
   *out = vol;
   return ADGI_OK;
 }
@@ -762,7 +768,9 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
   if (!vol || !t) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
   if (!tuning_valid(*t)) return fail(ADGI_ERR_INVALID_ARG, "tuning out of range");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
-  size_t lds = blend_lds_bytes(vol->v, t->blend_chunk);
+  if (t->blend_chunk == 0 && !blend_wave_supported(vol->v))
+    return fail(ADGI_ERR_INVALID_ARG, "blend_chunk 0 (wave kernel) needs tiles 8/16 or 16/16");
+  size_t lds = t->blend_chunk ? blend_lds_bytes(vol->v, t->blend_chunk) : 0;
   if (lds > 65536) return fail(ADGI_ERR_INVALID_ARG, "blend_chunk needs %zu bytes of LDS", lds);
   if (trace_lds_bytes(t->trace_block, t->lds_top_nodes) > 65536)
     return fail(ADGI_ERR_INVALID_ARG, "trace LDS over 64 KiB");
@@ -961,10 +969,11 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     }
   }
   float best_blend = INFINITY;
-  const int chunks[] = {128, 256, 512};
+  const int chunks[] = {0, 128, 256, 512};
   for (int ch : chunks) {
     if (err != hipSuccess) break;
-    if (blend_lds_bytes(vol->v, ch) > 65536) continue;
+    if (ch == 0 && !blend_wave_supported(vol->v)) continue;
+    if (ch != 0 && blend_lds_bytes(vol->v, ch) > 65536) continue;
     BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, so_irr, so_dep, (uint8_t*)so_in, (uint8_t*)so_dn};
     float bm = INFINITY;
     for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {

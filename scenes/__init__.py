@@ -70,6 +70,19 @@ class Scene:
         b = self.light_b.astype(np.float64)
         return (a + (b - a) * f).astype(np.float32)
 
+    def write_animated(self, frame: int, out: np.ndarray) -> None:
+        """Write the animated vertex prefix of ``frame`` into ``out`` (a full
+        [V,3] float32 buffer); vertices past the prefix are left untouched."""
+        if self.anim_vertices == 0:
+            return
+        t = frame / self.fps
+        dy = (self.anim_amp.astype(np.float64)
+              * np.sin(2.0 * math.pi * self.anim_freq.astype(np.float64) * t
+                       + self.anim_phase.astype(np.float64)))
+        dy = np.repeat(dy, self.anim_group)[: self.anim_vertices]
+        out[: self.anim_vertices, 1] = (
+            self.positions[: self.anim_vertices, 1].astype(np.float64) + dy).astype(np.float32)
+
     def positions_at(self, frame: int) -> np.ndarray:
         """Vertex positions at ``frame`` (animated prefix bobbing in y)."""
         if self.anim_vertices == 0:
