@@ -183,6 +183,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--tuning", default=None,
+                    help="JSON launch tuning to use instead of the autotuner")
+    ap.add_argument("--skip-uniform", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -212,7 +215,10 @@ def main():
     build_s = time.perf_counter() - t
     ad = dict(adaptive=True, budget=cfg["budget"], n_min=cfg["n_min"], n_max=cfg["n_max"])
     tuning = vol.get_tuning()
-    if not args.no_autotune:
+    if args.tuning:
+        vol.set_tuning(**json.loads(args.tuning))
+        tuning = vol.get_tuning()
+    elif not args.no_autotune:
         tuning = vol.autotune(0, **ad)
     print(f"[bench] scene build {build_s:.2f}s tuning={tuning}", file=sys.stderr, flush=True)
 
@@ -223,8 +229,9 @@ def main():
 
     # uniform baselines on fresh volumes (same scene, same tuning)
     uni = {}
-    for name, n in (("uniform_equal_budget", cfg["uniform_equal_b"]),
-                    ("uniform_equal_traced", cfg["uniform_equal_rays"])):
+    for name, n in (() if args.skip_uniform else
+                    (("uniform_equal_budget", cfg["uniform_equal_b"]),
+                     ("uniform_equal_traced", cfg["uniform_equal_rays"]))):
         v2 = adgi.volume_for_scene(sc, storage=storage, max_rays=max_rays, seed=11)
         v2.set_tuning(**tuning)
         r = run_mode(v2, sc, adgi, torch, 0, args.steps, args.warmup, args.latency_frames,

@@ -42,26 +42,26 @@ size_t blend_lds_bytes(const VolumeView& v, int chunk);
 
 // refit.hip
 struct RefitView {
-  const float* positions;    // [V][3]
-  const int32_t* indices;    // [T][3]
-  const int32_t* tri_order;  // slot -> original triangle
-  float4* tris;              // [T][3]
-  float4* nodes;             // [N][4]
-  const int32_t* leaf_slots; // (node << 1 | side) for every leaf child slot
-  int32_t num_leaf_slots;
-  uint32_t* arrive;          // [N] counters, zeroed by the launcher
+  const float* positions;      // [V][3]
+  const int32_t* indices;      // [T][3]
+  const int32_t* tri_order;    // slot -> original triangle
+  float4* tris;                // [T][3]
+  float4* nodes;               // [N][4]
+  const int32_t* level_nodes;  // node indices grouped by depth
   int32_t num_tris;
   int32_t num_nodes;
   float pad_abs;
 };
-hipError_t launch_refit(const RefitView& r, hipStream_t s);
+// level_offsets[d] .. level_offsets[d+1] index level_nodes for depth d
+hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s);
 
 // bvh_build.cpp: binned SAH on the host
 struct BvhHost {
   std::vector<float4> nodes;       // 4 per node
   std::vector<float4> tris;        // 3 per triangle slot
   std::vector<int32_t> tri_order;  // slot -> original triangle
-  std::vector<int32_t> leaf_slots; // node << 1 | side
+  std::vector<int32_t> level_nodes;   // internal nodes grouped by depth (root first)
+  std::vector<int32_t> level_offsets; // size depth+1
   int32_t depth = 0;
 };
 bool build_bvh(const float* positions, int32_t nv, const int32_t* indices, int32_t nt, float pad_abs,

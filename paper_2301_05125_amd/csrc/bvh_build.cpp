@@ -66,7 +66,8 @@ bool build_bvh(const float* pos, int32_t nv, const int32_t* idx, int32_t nt, flo
   out.nodes.clear();
   out.tris.clear();
   out.tri_order.clear();
-  out.leaf_slots.clear();
+  out.level_nodes.clear();
+  out.level_offsets.clear();
   out.depth = 0;
   if (nt == 0) {
     // a root whose children are never entered (the kernels skip traversal)
@@ -311,20 +312,30 @@ bool build_bvh(const float* pos, int32_t nv, const int32_t* idx, int32_t nt, flo
       lc = rc = ~((bn[0].start << kLeafShift) | (bn[0].count - 1));
       put(f, 0, bn[0].box);
       put(f, 1, bn[0].box);
-      out.leaf_slots.push_back(0);
-      out.leaf_slots.push_back(1);
     } else {
       lc = child_code(bn[n].left);
       rc = child_code(bn[n].right);
       put(f, 0, bn[bn[n].left].box);
       put(f, 1, bn[bn[n].right].box);
-      if (bn[bn[n].left].left < 0) out.leaf_slots.push_back((int)(g << 1));
-      if (bn[bn[n].right].left < 0) out.leaf_slots.push_back((int)(g << 1 | 1));
     }
     std::memcpy(&f[3].x, &lc, 4);
     std::memcpy(&f[3].y, &rc, 4);
     std::memcpy(&f[3].z, &par, 4);
     std::memcpy(&f[3].w, &side, 4);
+  }
+  // internal nodes grouped by depth, for the level-by-level refit
+  {
+    std::vector<std::vector<int32_t>> lv;
+    for (size_t g = 0; g < order.size(); ++g) {
+      int d = bn[order[g]].depth;
+      if ((int)lv.size() <= d) lv.resize(d + 1);
+      lv[d].push_back((int32_t)g);
+    }
+    out.level_offsets.push_back(0);
+    for (auto& l : lv) {
+      out.level_nodes.insert(out.level_nodes.end(), l.begin(), l.end());
+      out.level_offsets.push_back((int32_t)out.level_nodes.size());
+    }
   }
   // parent links
   for (size_t g = 0; g < order.size(); ++g) {

@@ -1,11 +1,11 @@
 // refit.hip - device BVH refit after vertex motion (same topology).
 //
 // 1. Rebuild every triangle record (v0, e1, e2) from the current positions.
-// 2. One thread per leaf child slot computes its leaf's box from the vertex
-//    positions, writes it (padded) into the parent node, and climbs: at each
-//    node an acquire/release arrival counter lets the second arriving child
-//    merge both child boxes into the grandparent's slot, so every node is
-//    finished exactly once without a launch per level.
+// 2. Refit the boxes level by level from the deepest internal nodes to the
+//    root, one launch per level: a node's child slot gets the (padded) bounds
+//    of its leaf triangles, or the union of the internal child's two slots,
+//    which the previous launch finished. Kernel boundaries order the levels,
+//    so no cross-workgroup atomics or cache maintenance are needed.
 #include "adgi_internal.hpp"
 
 namespace adgi {
@@ -23,79 +23,66 @@ __global__ void refit_tris_kernel(RefitView r) {
   r.tris[3 * (size_t)s + 2] = make_float4(v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2], 0.f);
 }
 
-__global__ void refit_clear_kernel(RefitView r) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < r.num_nodes) r.arrive[k] = 0u;
-}
-
 __device__ __forceinline__ void write_slot(float4* node, int side, const float* lo, const float* hi) {
   float* f = (float*)node;
-  if (side == 0) {
-    f[0] = lo[0];
-    f[1] = lo[1];
-    f[2] = lo[2];
-    f[3] = hi[0];
-    f[4] = hi[1];
-    f[5] = hi[2];
-  } else {
-    f[6] = lo[0];
-    f[7] = lo[1];
-    f[8] = lo[2];
-    f[9] = hi[0];
-    f[10] = hi[1];
-    f[11] = hi[2];
-  }
+  const int b = side ? 6 : 0;
+  f[b + 0] = lo[0];
+  f[b + 1] = lo[1];
+  f[b + 2] = lo[2];
+  f[b + 3] = hi[0];
+  f[b + 4] = hi[1];
+  f[b + 5] = hi[2];
 }
 
-__global__ void refit_nodes_kernel(RefitView r) {
+__global__ void refit_level_kernel(RefitView r, const int32_t* __restrict__ nodes_of_level, int count) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= r.num_leaf_slots) return;
-  const int slot = r.leaf_slots[q];
-  int node = slot >> 1;
-  const int side = slot & 1;
-  const int* meta = (const int*)(r.nodes + 4 * (size_t)node + 3);
-  const int code = ~meta[side];
-  const int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int k = 0; k < count; ++k) {
-    const int t = r.tri_order[first + k];
-    for (int c = 0; c < 3; ++c) {
-      const float* p = r.positions + 3 * (size_t)r.indices[3 * t + c];
+  if (q >= count) return;
+  const int g = nodes_of_level[q];
+  const int* meta = (const int*)(r.nodes + 4 * (size_t)g + 3);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int c = meta[side];
+    float lo[3], hi[3];
+    if (c < 0) {
+      const int code = ~c;
+      const int first = code >> kLeafShift, count_t = (code & (kLeafMaxTris - 1)) + 1;
+      lo[0] = lo[1] = lo[2] = INFINITY;
+      hi[0] = hi[1] = hi[2] = -INFINITY;
+      for (int k = 0; k < count_t; ++k) {
+        const int t = r.tri_order[first + k];
+        for (int v = 0; v < 3; ++v) {
+          const float* p = r.positions + 3 * (size_t)r.indices[3 * t + v];
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], p[a]);
+            hi[a] = fmaxf(hi[a], p[a]);
+          }
+        }
+      }
       for (int a = 0; a < 3; ++a) {
-        lo[a] = fminf(lo[a], p[a]);
-        hi[a] = fmaxf(hi[a], p[a]);
+        lo[a] = pad_lo(lo[a], r.pad_abs);
+        hi[a] = pad_hi(hi[a], r.pad_abs);
+      }
+    } else {
+      // union of the child's two (already padded) slots
+      const float* f = (const float*)(r.nodes + 4 * (size_t)c);
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(f[a], f[6 + a]);
+        hi[a] = fmaxf(f[3 + a], f[9 + a]);
       }
     }
-  }
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = pad_lo(lo[a], r.pad_abs);
-    hi[a] = pad_hi(hi[a], r.pad_abs);
-  }
-  write_slot(r.nodes + 4 * (size_t)node, side, lo, hi);
-  for (;;) {
-    uint32_t prev = __hip_atomic_fetch_add(&r.arrive[node], 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == 0u) return;  // the sibling finishes this node
-    const int* m = (const int*)(r.nodes + 4 * (size_t)node + 3);
-    const int parent = m[2], pside = m[3];
-    if (parent < 0) return;
-    const float* f = (const float*)(r.nodes + 4 * (size_t)node);
-    float blo[3], bhi[3];
-    for (int a = 0; a < 3; ++a) {
-      blo[a] = fminf(f[a], f[6 + a]);
-      bhi[a] = fmaxf(f[3 + a], f[9 + a]);
-    }
-    write_slot(r.nodes + 4 * (size_t)parent, pside, blo, bhi);
-    node = parent;
+    write_slot(r.nodes + 4 * (size_t)g, side, lo, hi);
   }
 }
 
-hipError_t launch_refit(const RefitView& r, hipStream_t s) {
-  if (r.num_tris > 0)
-    hipLaunchKernelGGL(refit_tris_kernel, dim3((r.num_tris + 255) / 256), dim3(256), 0, s, r);
-  hipLaunchKernelGGL(refit_clear_kernel, dim3((r.num_nodes + 255) / 256), dim3(256), 0, s, r);
-  if (r.num_leaf_slots > 0)
-    hipLaunchKernelGGL(refit_nodes_kernel, dim3((r.num_leaf_slots + 255) / 256), dim3(256), 0, s, r);
+hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s) {
+  if (r.num_tris == 0) return hipSuccess;
+  hipLaunchKernelGGL(refit_tris_kernel, dim3((r.num_tris + 255) / 256), dim3(256), 0, s, r);
+  for (int d = (int)level_offsets.size() - 2; d >= 0; --d) {
+    const int b = level_offsets[d], cnt = level_offsets[d + 1] - b;
+    if (cnt <= 0) continue;
+    hipLaunchKernelGGL(refit_level_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, r,
+                       r.level_nodes + b, cnt);
+  }
   return hipGetLastError();
 }
 

@@ -138,12 +138,13 @@ struct adgi_volume {
   uint8_t *irr_n = nullptr, *dep_n = nullptr;
   // scene
   bool has_scene = false;
-  int32_t nv = 0, nt = 0, num_nodes = 0, num_leaf_slots = 0;
+  int32_t nv = 0, nt = 0, num_nodes = 0;
   float* d_pos = nullptr;
   int32_t* d_idx = nullptr;
   int32_t* d_order = nullptr;
-  int32_t* d_leaf = nullptr;
-  uint32_t* d_arrive = nullptr;
+  int32_t* d_levels = nullptr;
+  std::vector<int32_t> level_offsets;
+  hipGraphExec_t refit_exec = nullptr;
   float4* d_nodes = nullptr;
   float4* d_tris = nullptr;
   float4* d_albedo = nullptr;
@@ -259,11 +260,15 @@ adgi_status order_user_after(adgi_volume* vol) {
 }
 
 void free_scene(adgi_volume* vol) {
+  if (vol->refit_exec) {
+    (void)hipGraphExecDestroy(vol->refit_exec);
+    vol->refit_exec = nullptr;
+  }
   for (void* p : vol->scene_allocs) vol_free(vol, p);
   vol->scene_allocs.clear();
   vol->d_pos = nullptr;
-  vol->d_idx = vol->d_order = vol->d_leaf = nullptr;
-  vol->d_arrive = nullptr;
+  vol->d_idx = vol->d_order = vol->d_levels = nullptr;
+  vol->level_offsets.clear();
   vol->d_nodes = vol->d_tris = vol->d_albedo = nullptr;
   if (vol->h_stage) {
     (void)hipHostFree(vol->h_stage);
@@ -561,12 +566,11 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
     vol->d_pos = (float*)vol_alloc(vol, (size_t)nv * 12, &g);
     vol->d_idx = (int32_t*)vol_alloc(vol, (size_t)nt * 12, &g);
     vol->d_order = (int32_t*)vol_alloc(vol, (size_t)nt * 4, &g);
-    vol->d_leaf = (int32_t*)vol_alloc(vol, bvh.leaf_slots.size() * 4, &g);
-    vol->d_arrive = (uint32_t*)vol_alloc(vol, (size_t)nn * 4, &g);
+    vol->d_levels = (int32_t*)vol_alloc(vol, bvh.level_nodes.size() * 4, &g);
     vol->d_nodes = (float4*)vol_alloc(vol, bvh.nodes.size() * 16, &g);
     vol->d_tris = (float4*)vol_alloc(vol, std::max<size_t>(bvh.tris.size(), 3) * 16, &g);
     vol->d_albedo = (float4*)vol_alloc(vol, (size_t)std::max(nt, 1) * 16, &g);
-    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_leaf || !vol->d_arrive || !vol->d_nodes ||
+    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_nodes ||
         !vol->d_tris || !vol->d_albedo) {
       free_scene(vol);
       vol->has_scene = false;
@@ -581,14 +585,15 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
       HIP_TRY(vol, hipMemcpy(vol->d_order, bvh.tri_order.data(), (size_t)nt * 4, hipMemcpyHostToDevice));
       HIP_TRY(vol, hipMemcpy(vol->d_tris, bvh.tris.data(), bvh.tris.size() * 16, hipMemcpyHostToDevice));
     }
-    if (!bvh.leaf_slots.empty())
-      HIP_TRY(vol, hipMemcpy(vol->d_leaf, bvh.leaf_slots.data(), bvh.leaf_slots.size() * 4, hipMemcpyHostToDevice));
+    if (!bvh.level_nodes.empty())
+      HIP_TRY(vol, hipMemcpy(vol->d_levels, bvh.level_nodes.data(), bvh.level_nodes.size() * 4,
+                             hipMemcpyHostToDevice));
+    vol->level_offsets = bvh.level_offsets;
     HIP_TRY(vol, hipMemcpy(vol->d_nodes, bvh.nodes.data(), bvh.nodes.size() * 16, hipMemcpyHostToDevice));
     HIP_TRY(vol, hipMemcpy(vol->d_albedo, alb.data(), alb.size() * 16, hipMemcpyHostToDevice));
     vol->nv = nv;
     vol->nt = nt;
     vol->num_nodes = nn;
-    vol->num_leaf_slots = (int32_t)bvh.leaf_slots.size();
     vol->pad_abs = pad_abs;
     vol->bvh_depth = bvh.depth;
     vol->v.nodes = vol->d_nodes;
@@ -604,9 +609,28 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
       std::memcpy(vol->h_stage + 3 * vb, sc->positions + 3 * vb, cnt * 4);
       HIP_TRY(vol, hipMemcpyAsync(vol->d_pos + 3 * vb, vol->h_stage + 3 * vb, cnt * 4,
                                   hipMemcpyHostToDevice, vol->stream));
-      RefitView r{vol->d_pos, vol->d_idx, vol->d_order, vol->d_tris, vol->d_nodes, vol->d_leaf,
-                  vol->num_leaf_slots, vol->d_arrive, vol->nt, vol->num_nodes, vol->pad_abs};
-      HIP_TRY(vol, launch_refit(r, vol->stream));
+      // the refit (one launch per BVH level) is captured once per build
+      if (!vol->refit_exec) {
+        RefitView r{vol->d_pos, vol->d_idx, vol->d_order, vol->d_tris, vol->d_nodes, vol->d_levels,
+                    vol->nt, vol->num_nodes, vol->pad_abs};
+        hipGraph_t graph = nullptr;
+        HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = launch_refit(r, vol->level_offsets, vol->stream);
+        hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          vol->sticky = true;
+          return fail(ADGI_ERR_DEVICE, "refit capture failed: %s / %s", hipGetErrorString(e),
+                      hipGetErrorString(e2));
+        }
+        hipError_t e3 = hipGraphInstantiate(&vol->refit_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+          vol->sticky = true;
+          return fail(ADGI_ERR_DEVICE, "refit graph instantiate failed: %s", hipGetErrorString(e3));
+        }
+      }
+      HIP_TRY(vol, hipGraphLaunch(vol->refit_exec, vol->stream));
     }
   }
   HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice,
