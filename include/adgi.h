@@ -202,6 +202,9 @@ typedef struct {
                                  64..2048, x64: rays staged in LDS per step of the
                                  workgroup-per-probe blend                        */
   int32_t lds_top_nodes;      /* BVH nodes staged in LDS per workgroup: 0..1024   */
+  int32_t blend_blocks_per_cu;/* scheduled blend: workgroups per CU, 1..32         */
+  int32_t blend_heavy_rays;   /* scheduled blend: probes with more rays are blended
+                                 by a whole workgroup, the rest one per wave      */
 } adgi_tuning;
 
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);

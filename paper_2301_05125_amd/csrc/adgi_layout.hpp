@@ -64,6 +64,10 @@ struct FrameStats {
   uint64_t node_tests;      // work-counting traversal only
   uint64_t tri_tests;
   int64_t remainder;        // R = B' - sum e_i(lambda*)
+  uint32_t blend_counter;   // heavy-probe blend queue cursor
+  uint32_t num_heavy;       // probes blended by a whole workgroup (set by allocation)
+  uint32_t num_light;
+  uint32_t blend_counter2;  // light-probe blend queue cursor
   uint64_t sums[4][kAllocCandidates];
 };
 
@@ -99,6 +103,8 @@ struct VolumeView {
   uint32_t* blk_el;           // per-block count of probes eligible for the top-up
   uint32_t* blk_rank;         // per-block exclusive rank base among eligible probes
   uint32_t* blk_off;          // per-block exclusive ray offset
+  int32_t* order;             // [P] blend order: heavy probes first, then light
+  int32_t heavy_rays;         // probes with more rays are blended by a workgroup
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
   int32_t* dbg_tri;           // [max_rays] or null

@@ -122,6 +122,25 @@ __device__ int64_t block_exclusive_scan(int64_t x, int64_t* sm, int64_t& total) 
   return v - x + sm[wave];
 }
 
+// Blend work order: heavy probes (more than heavy_rays rays) from the front of
+// order[], light ones from the back, one atomic per wave and list. The order
+// within each list depends on timing, which does not matter: every probe's
+// blend is independent of the others.
+__device__ void append_blend_order(const VolumeView& v, bool valid, int i, int n) {
+  const bool heavy = valid && n > v.heavy_rays, light = valid && !heavy;
+  const uint64_t mh = __ballot(heavy), ml = __ballot(light);
+  const uint32_t lane = __lane_id();
+  uint32_t bh = 0, bl = 0;
+  if (lane == 0) {
+    if (mh) bh = atomicAdd(&v.stats->num_heavy, (uint32_t)__popcll(mh));
+    if (ml) bl = atomicAdd(&v.stats->num_light, (uint32_t)__popcll(ml));
+  }
+  bh = __shfl(bh, 0);
+  bl = __shfl(bl, 0);
+  if (heavy) v.order[bh + lanes_below(mh)] = i;
+  if (light) v.order[v.P - 1 - (bl + lanes_below(ml))] = i;
+}
+
 // Finalize in three parallel steps over blocks of 256 probes:
 //   F1 per block: e_i(lambda*), top-up eligibility, block sums;
 //   F2 one workgroup: R, exclusive rank bases and ray offsets of the blocks;
@@ -202,6 +221,8 @@ __global__ __launch_bounds__(1024) void alloc_scan_blocks_kernel(VolumeView v) {
     }
   }
   if (threadIdx.x == 0) {
+    v.stats->num_heavy = 0u;
+    v.stats->num_light = 0u;
     v.stats->remainder = R;
     v.offsets[v.P] = (uint32_t)carry_off;
     v.stats->budget_used = (uint64_t)carry_off;
@@ -234,6 +255,7 @@ __global__ __launch_bounds__(256) void alloc_write_kernel(VolumeView v) {
     v.offsets[i] = (uint32_t)off;
     nmin = nmax = n;
   }
+  append_blend_order(v, i < v.P, i, n);
   for (int o = 32; o > 0; o >>= 1) {
     nmin = min(nmin, __shfl_xor(nmin, o));
     nmax = max(nmax, __shfl_xor(nmax, o));
@@ -249,9 +271,15 @@ __global__ void uniform_offsets_kernel(VolumeView v) {
   if (fp.adaptive) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = (uint32_t)fp.n_uniform;
-  if (i < v.P) v.n[i] = (int)n;
+  if (i < v.P) {
+    v.n[i] = (int)n;
+    v.order[i] = i;
+  }
   if (i <= v.P) v.offsets[i] = (uint32_t)i * n;
   if (i == 0) {
+    const bool heavy = (int)n > v.heavy_rays;
+    v.stats->num_heavy = heavy ? (uint32_t)v.P : 0u;
+    v.stats->num_light = heavy ? 0u : (uint32_t)v.P;
     v.stats->n_min_seen = (int)n;
     v.stats->n_max_seen = (int)n;
     v.stats->budget_used = (uint64_t)v.P * n;

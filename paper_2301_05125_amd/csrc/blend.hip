@@ -1,4 +1,4 @@
-// blend.hip - per-probe texel update (one workgroup per probe).
+// blend.hip - per-probe texel update.
 //
 // Every sample updates the texel that contains its direction ("the closest
 // entry", Alg. ApproxAlgo) with the moving average of Alg. MovingAvgUpdate:
@@ -6,7 +6,9 @@
 // mean while 1/(N+1) > 1-h, then an exponential average with hysteresis h.
 // Irradiance texels take the ray's radiance; depth texels take the moments
 // (tau, tau^2) of tau = min(t/s, tau_max) (Sec. 4.6). Samples of one texel are
-// applied in ascending ray order. The probe's texel tile is staged in LDS;
+// applied in ascending ray order. Two kernels: the general one (any tile
+// size, one workgroup per probe) and the scheduled one further below. In the
+// general kernel the probe's texel tile is staged in LDS;
 // rays are processed in chunks: coalesced load of the chunk's 16-byte
 // records, octahedral bins recomputed from the ray index, an LDS counting
 // sort by texel (histogram, scan, scatter, then a short insertion sort of each
@@ -240,13 +242,16 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
 }
 
 // ---------------------------------------------------------------------------
-// Wave-per-probe variant for the common tile sizes. One 64-lane wave owns one
-// probe: interior texel k lives in the registers of lane k % 64 (slot k / 64)
-// for the whole frame. Rays are taken 64 at a time, one per lane; each lane
-// ORs its lane bit into a 64-bit LDS mask of the irradiance texel and of the
-// depth texel its direction falls in, and every owner then walks the set bits
-// of its texels' masks from the lowest: that is ascending ray order, so no
-// sort is needed, and all synchronisation is within the wave.
+// Scheduled variant for the common tile sizes: the allocation writes a probe
+// order with the probes that have many rays first. A persistent kernel blends
+// those heavy probes, one whole 256-thread workgroup each, 256 rays per step,
+// one interior texel per thread; a second persistent kernel then blends the
+// light probes, one 64-lane wave each, 64 rays per step, every wave taking the
+// next probe from a queue. In
+// both cases each ray ORs its bit into a per-texel LDS mask (one 64-bit word
+// per wave of rays), and the texel's owner walks the set bits from the lowest
+// word and bit: that is ascending ray order, so no sort is needed. The next
+// step's records are loaded while the current step is applied.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -262,24 +267,66 @@ struct WaveTile {
   static constexpr size_t kStageBytes = 4 * (3 * (size_t)NI + 2 * (size_t)ND) + NT;
   static constexpr size_t kWaveBytes =
       ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
+  // heavy path over the whole workgroup: 256 records + 4 mask words per texel
+  static constexpr size_t kBlockChunk = 256 * 16 + 32 * (size_t)NT;
+  static constexpr size_t kBlockBytes =
+      ((kBlockChunk > 4 * kWaveBytes ? kBlockChunk : 4 * kWaveBytes) + 15) & ~(size_t)15;
 };
 
+// One texel update with the moving average of Alg. MovingAvgUpdate.
+__device__ __forceinline__ void blend_rgb(float* V, uint32_t& N, float4 r, float omh) {
+  const float al = fmaxf(1.0f / (float)(N + 1u), omh);
+  V[0] = fmaf(al, r.x - V[0], V[0]);
+  V[1] = fmaf(al, r.y - V[1], V[1]);
+  V[2] = fmaf(al, r.z - V[2], V[2]);
+  N = min(N + 1u, 255u);
+}
+__device__ __forceinline__ void blend_tau(float* V, uint32_t& N, float t, float inv_s, float tmax,
+                                          float omh) {
+  const float tau = fminf(t * inv_s, tmax);
+  const float al = fmaxf(1.0f / (float)(N + 1u), omh);
+  V[0] = fmaf(al, tau - V[0], V[0]);
+  V[1] = fmaf(al, tau * tau - V[1], V[1]);
+  N = min(N + 1u, 255u);
+}
+
+// Write the staged interior (stI, stD, stN in LDS) as full tiles with the border fold.
 template <int RI, int RD, bool HALF>
-__global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io) {
+__device__ void write_tiles(const VolumeView& v, const BlendIO& io, int i, const float* stI,
+                            const float* stD, const uint8_t* stN, int t0, int nthreads) {
+  using S = Store<HALF>;
+  using T = typename S::T;
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND, GI = W::GI, GD = W::GD;
+  T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
+  T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
+  for (int f = t0; f < GI * GI * 3; f += nthreads) {
+    const int t = f / 3, c = f - 3 * t, Y = t / GI, X = t - Y * GI;
+    int sx, sy;
+    border_source(X, Y, RI, sx, sy);
+    S::store(irr_out + f, stI[((sy - 1) * RI + (sx - 1)) * 3 + c]);
+  }
+  for (int f = t0; f < GD * GD * 2; f += nthreads) {
+    const int t = f >> 1, c = f & 1, Y = t / GD, X = t - Y * GD;
+    int sx, sy;
+    border_source(X, Y, RD, sx, sy);
+    S::store(dep_out + f, stD[((sy - 1) * RD + (sx - 1)) * 2 + c]);
+  }
+  for (int k = t0; k < NI; k += nthreads) io.irr_n_out[(size_t)i * NI + k] = stN[k];
+  for (int k = t0; k < ND; k += nthreads) io.dep_n_out[(size_t)i * ND + k] = stN[NI + k];
+}
+
+// Light probe: one wave.
+template <int RI, int RD, bool HALF>
+__device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
   constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
-  if (i >= v.P) return;  // uniform per wave
-  uint8_t* wbase = smem + (size_t)wave * W::kWaveBytes;
+  const int lane = threadIdx.x & 63;
   float4* rec_s = (float4*)wbase;
   unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
   const FrameParams& fp = *v.fp;
-
-  // ---- owned interior texels into registers
   const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
   const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
   float vi[SI][3], vd[SD][2];
@@ -311,18 +358,21 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
       nd[s] = io.dep_n_in[(size_t)i * ND + k];
     }
   }
-
   const uint32_t off = v.offsets[i];
   const uint32_t n = v.offsets[i + 1] - off;
   const float inv_s = 1.0f / v.s_diag;
   const float omh = v.one_minus_h, tmax = v.tau_max;
+  float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+  if ((uint32_t)lane < n) nxt = v.rec[off + lane];
   for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
     const uint32_t m = min(64u, n - c0);
+    const float4 cur = nxt;
+    if (c0 + 64u + (uint32_t)lane < n) nxt = v.rec[off + c0 + 64u + lane];
     for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
     wave_sync();
     if ((uint32_t)lane < m) {
       const uint32_t j = c0 + (uint32_t)lane;
-      rec_s[lane] = v.rec[off + j];
+      rec_s[lane] = cur;
       const float2 uv = oct_encode(sf_direction(j, n, fp.R));
       const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
       atomicOr(&mask[bI], 1ull << lane);
@@ -340,12 +390,7 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
       while (mk) {
         const int j = __ffsll((long long)mk) - 1;
         mk &= mk - 1ull;
-        const float4 r = rec_s[j];
-        const float al = fmaxf(1.0f / (float)(ni[s] + 1u), omh);
-        vi[s][0] = fmaf(al, r.x - vi[s][0], vi[s][0]);
-        vi[s][1] = fmaf(al, r.y - vi[s][1], vi[s][1]);
-        vi[s][2] = fmaf(al, r.z - vi[s][2], vi[s][2]);
-        ni[s] = min(ni[s] + 1u, 255u);
+        blend_rgb(vi[s], ni[s], rec_s[j], omh);
       }
     }
 #pragma unroll
@@ -355,17 +400,11 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
       while (mk) {
         const int j = __ffsll((long long)mk) - 1;
         mk &= mk - 1ull;
-        const float tau = fminf(rec_s[j].w * inv_s, tmax);
-        const float al = fmaxf(1.0f / (float)(nd[s] + 1u), omh);
-        vd[s][0] = fmaf(al, tau - vd[s][0], vd[s][0]);
-        vd[s][1] = fmaf(al, tau * tau - vd[s][1], vd[s][1]);
-        nd[s] = min(nd[s] + 1u, 255u);
+        blend_tau(vd[s], nd[s], rec_s[j].w, inv_s, tmax, omh);
       }
     }
     wave_sync();
   }
-
-  // ---- stage the interior in LDS, then write both tiles with the border fold
   float* stI = (float*)wbase;
   float* stD = stI + 3 * NI;
   uint8_t* stN = (uint8_t*)(stD + 2 * ND);
@@ -389,22 +428,145 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
     }
   }
   wave_sync();
-  T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
-  T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
-  for (int f = lane; f < GI * GI * 3; f += 64) {
-    const int t = f / 3, c = f - 3 * t, Y = t / GI, X = t - Y * GI;
-    int sx, sy;
-    border_source(X, Y, RI, sx, sy);
-    S::store(irr_out + f, stI[((sy - 1) * RI + (sx - 1)) * 3 + c]);
+  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, lane, 64);
+  wave_sync();
+}
+
+// Heavy probe: the whole workgroup; thread t owns texels t and t + 256.
+template <int RI, int RD, bool HALF>
+__device__ void blend_probe_block(const VolumeView& v, const BlendIO& io, int i, uint8_t* base) {
+  using S = Store<HALF>;
+  using T = typename S::T;
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND, NT = W::NT, GI = W::GI, GD = W::GD;
+  constexpr int SB = (NT + 255) / 256;
+  const int t = threadIdx.x;
+  float4* rec_s = (float4*)base;
+  unsigned long long* mask = (unsigned long long*)(base + 256 * 16);  // [NT][4]
+  const FrameParams& fp = *v.fp;
+  float V[SB][3];
+  uint32_t N[SB];
+#pragma unroll
+  for (int b = 0; b < SB; ++b) {
+    const int k = t + 256 * b;
+    V[b][0] = V[b][1] = V[b][2] = 0.f;
+    N[b] = 0u;
+    if (k < NI) {
+      const int iy = k / RI, ix = k - iy * RI;
+      const T* p = (const T*)io.irr_in + (size_t)i * GI * GI * 3 + ((iy + 1) * GI + ix + 1) * 3;
+      V[b][0] = S::load(p);
+      V[b][1] = S::load(p + 1);
+      V[b][2] = S::load(p + 2);
+      N[b] = io.irr_n_in[(size_t)i * NI + k];
+    } else if (k < NT) {
+      const int kd = k - NI, iy = kd / RD, ix = kd - iy * RD;
+      const T* p = (const T*)io.dep_in + (size_t)i * GD * GD * 2 + ((iy + 1) * GD + ix + 1) * 2;
+      V[b][0] = S::load(p);
+      V[b][1] = S::load(p + 1);
+      N[b] = io.dep_n_in[(size_t)i * ND + kd];
+    }
   }
-  for (int f = lane; f < GD * GD * 2; f += 64) {
-    const int t = f >> 1, c = f & 1, Y = t / GD, X = t - Y * GD;
-    int sx, sy;
-    border_source(X, Y, RD, sx, sy);
-    S::store(dep_out + f, stD[((sy - 1) * RD + (sx - 1)) * 2 + c]);
+  const uint32_t off = v.offsets[i];
+  const uint32_t n = v.offsets[i + 1] - off;
+  const float inv_s = 1.0f / v.s_diag;
+  const float omh = v.one_minus_h, tmax = v.tau_max;
+  float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+  if ((uint32_t)t < n) nxt = v.rec[off + t];
+  for (uint32_t c0 = 0; c0 < n; c0 += 256u) {
+    const uint32_t m = min(256u, n - c0);
+    const float4 cur = nxt;
+    if (c0 + 256u + (uint32_t)t < n) nxt = v.rec[off + c0 + 256u + t];
+    for (int k = t; k < 4 * NT; k += 256) mask[k] = 0ull;
+    __syncthreads();
+    if ((uint32_t)t < m) {
+      const uint32_t j = c0 + (uint32_t)t;
+      rec_s[t] = cur;
+      const float2 uv = oct_encode(sf_direction(j, n, fp.R));
+      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
+      const unsigned long long bit = 1ull << (t & 63);
+      atomicOr(&mask[4 * bI + (t >> 6)], bit);
+      atomicOr(&mask[4 * (NI + bD) + (t >> 6)], bit);
+      if (fp.debug) {
+        v.dbg_ibin[off + j] = (uint16_t)bI;
+        v.dbg_dbin[off + j] = (uint16_t)bD;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < SB; ++b) {
+      const int k = t + 256 * b;
+      if (k >= NT) continue;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        unsigned long long mk = mask[4 * k + w];
+        while (mk) {
+          const int j = 64 * w + __ffsll((long long)mk) - 1;
+          mk &= mk - 1ull;
+          if (k < NI) blend_rgb(V[b], N[b], rec_s[j], omh);
+          else blend_tau(V[b], N[b], rec_s[j].w, inv_s, tmax, omh);
+        }
+      }
+    }
+    __syncthreads();
   }
-  for (int k = lane; k < NI; k += 64) io.irr_n_out[(size_t)i * NI + k] = stN[k];
-  for (int k = lane; k < ND; k += 64) io.dep_n_out[(size_t)i * ND + k] = stN[NI + k];
+  float* stI = (float*)base;
+  float* stD = stI + 3 * NI;
+  uint8_t* stN = (uint8_t*)(stD + 2 * ND);
+#pragma unroll
+  for (int b = 0; b < SB; ++b) {
+    const int k = t + 256 * b;
+    if (k < NI) {
+      stI[3 * k] = V[b][0];
+      stI[3 * k + 1] = V[b][1];
+      stI[3 * k + 2] = V[b][2];
+      stN[k] = (uint8_t)N[b];
+    } else if (k < NT) {
+      stD[2 * (k - NI)] = V[b][0];
+      stD[2 * (k - NI) + 1] = V[b][1];
+      stN[k] = (uint8_t)N[b];
+    }
+  }
+  __syncthreads();
+  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, t, 256);
+  __syncthreads();
+}
+
+// Heavy probes, a whole workgroup each, taken from the front of order[].
+template <int RI, int RD, bool HALF>
+__global__ __launch_bounds__(256) void blend_heavy_kernel(VolumeView v, BlendIO io) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  __shared__ uint32_t item_s;
+  const uint32_t H = v.stats->num_heavy;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(&v.stats->blend_counter, 1u);
+    __syncthreads();
+    const uint32_t w = item_s;
+    __syncthreads();
+    if (w >= H) break;
+    blend_probe_block<RI, RD, HALF>(v, io, v.order[w], smem);
+  }
+}
+
+// Light probes, one wave each; every wave takes the next probe by itself.
+template <int RI, int RD, bool HALF>
+__global__ __launch_bounds__(256) void blend_light_kernel(VolumeView v, BlendIO io) {
+  using W = WaveTile<RI, RD>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const uint32_t H = v.stats->num_heavy;
+  const uint32_t L = (uint32_t)v.P - H;
+  uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
+  for (;;) {
+    uint32_t q = 0;
+    if ((threadIdx.x & 63) == 0) q = atomicAdd(&v.stats->blend_counter2, 1u);
+    q = __shfl(q, 0);
+    if (q >= L) break;
+    blend_probe_wave<RI, RD, HALF>(v, io, v.order[H + q], wbase);
+  }
+}
+
+__global__ void blend_reset_kernel(VolumeView v) {
+  v.stats->blend_counter = 0u;
+  v.stats->blend_counter2 = 0u;
 }
 
 bool blend_wave_supported(const VolumeView& v) {
@@ -416,19 +578,26 @@ size_t blend_lds_bytes(const VolumeView& v, int chunk) {
 }
 
 template <int RI, int RD>
-static void launch_wave(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16) {
-  const size_t lds = 4 * WaveTile<RI, RD>::kWaveBytes;
-  const int grid = (v.P + 3) / 4;
-  if (fp16)
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
-  else
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
+static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int grid) {
+  using W = WaveTile<RI, RD>;
+  hipLaunchKernelGGL(blend_reset_kernel, dim3(1), dim3(1), 0, s, v);
+  const int gh = grid > 1 ? grid / 2 : 1;
+  if (fp16) {
+    hipLaunchKernelGGL((blend_heavy_kernel<RI, RD, true>), dim3(gh), dim3(256), W::kBlockBytes, s, v, io);
+    hipLaunchKernelGGL((blend_light_kernel<RI, RD, true>), dim3(grid), dim3(256), 4 * W::kWaveBytes, s, v,
+                       io);
+  } else {
+    hipLaunchKernelGGL((blend_heavy_kernel<RI, RD, false>), dim3(gh), dim3(256), W::kBlockBytes, s, v, io);
+    hipLaunchKernelGGL((blend_light_kernel<RI, RD, false>), dim3(grid), dim3(256), 4 * W::kWaveBytes, s,
+                       v, io);
+  }
 }
 
-hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk) {
-  if (chunk == 0) {  // wave-per-probe kernel
-    if (v.irr_res == 8 && v.dep_res == 16) launch_wave<6, 14>(v, io, s, fp16);
-    else if (v.irr_res == 16 && v.dep_res == 16) launch_wave<14, 14>(v, io, s, fp16);
+hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk,
+                        int grid) {
+  if (chunk == 0) {  // scheduled heavy-first kernel
+    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, fp16, grid);
+    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, fp16, grid);
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }

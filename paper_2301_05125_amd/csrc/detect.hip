@@ -31,6 +31,7 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->node_tests = 0ull;
     st->tri_tests = 0ull;
     st->remainder = 0;
+    st->blend_counter = 0u;
   }
   if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;
 }

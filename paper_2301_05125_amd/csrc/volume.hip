@@ -241,7 +241,9 @@ hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullp
   if ((e = mark(5)) != hipSuccess) return e;
   if (count_work) return hipSuccess;
   BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
-  if ((e = launch_blend(v, io, s, vol->desc.storage == ADGI_FP16, t.blend_chunk)) != hipSuccess) return e;
+  if ((e = launch_blend(v, io, s, vol->desc.storage == ADGI_FP16, t.blend_chunk,
+                        vol->num_cus * t.blend_blocks_per_cu)) != hipSuccess)
+    return e;
   return mark(6);
 }
 
@@ -304,6 +306,8 @@ adgi_tuning default_tuning() {
   t.trace_waves_per_cu = 16;
   t.blend_chunk = 256;
   t.lds_top_nodes = 0;
+  t.blend_blocks_per_cu = 8;
+  t.blend_heavy_rays = 128;
   return t;
 }
 
@@ -312,8 +316,8 @@ bool tuning_valid(const adgi_tuning& t) {
          t.trace_block >= 64 && t.trace_block <= 1024 && t.trace_block % 64 == 0 &&
          t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 &&
          (t.blend_chunk == 0 || (t.blend_chunk >= 64 && t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0)) &&
-         t.lds_top_nodes >= 0 &&
-         t.lds_top_nodes <= 1024;
+         t.lds_top_nodes >= 0 && t.lds_top_nodes <= 1024 && t.blend_blocks_per_cu >= 1 &&
+         t.blend_blocks_per_cu <= 32 && t.blend_heavy_rays >= 1;
 }
 
 }  // namespace
@@ -435,6 +439,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.blk_el, (size_t)((P + 255) / 256) * 4},
       {(void**)&v.blk_rank, (size_t)((P + 255) / 256) * 4},
       {(void**)&v.blk_off, (size_t)((P + 255) / 256) * 4},
+      {(void**)&v.order, (size_t)P * 4},
       {(void**)&v.rec, R * 16},
   };
   if (dbg) {
@@ -475,6 +480,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.tau_max = d->tau_max;
   v.max_rays = (uint32_t)R;
   if (blend_wave_supported(v)) vol->tun.blend_chunk = 0;
+  v.heavy_rays = vol->tun.blend_heavy_rays;
   *out = vol;
   return ADGI_OK;
 }
@@ -801,6 +807,7 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
   HIP_TRY(vol, hipStreamSynchronize(vol->stream));
   drop_graphs(vol);
   vol->tun = *t;
+  vol->v.heavy_rays = t->blend_heavy_rays;
   vol->tuned = true;
   return ADGI_OK;
 }
@@ -1002,7 +1009,9 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     float bm = INFINITY;
     for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
       if ((err = hipEventRecord(vol->ev_t0, s)) != hipSuccess) break;
-      if ((err = launch_blend(vol->v, io, s, vol->desc.storage == ADGI_FP16, ch)) != hipSuccess) break;
+      if ((err = launch_blend(vol->v, io, s, vol->desc.storage == ADGI_FP16, ch,
+                              vol->num_cus * best_t.blend_blocks_per_cu)) != hipSuccess)
+        break;
       if ((err = hipEventRecord(vol->ev_t1, s)) != hipSuccess) break;
       if ((err = hipEventSynchronize(vol->ev_t1)) != hipSuccess) break;
       float ms = 0.f;
