@@ -547,21 +547,18 @@ __global__ __launch_bounds__(256) void blend_heavy_kernel(VolumeView v, BlendIO 
   }
 }
 
-// Light probes, one wave each; every wave takes the next probe by itself.
+// Light probes, one wave each, assigned round-robin over all waves of the grid
+// (each has at most heavy_rays rays, so a static split is balanced).
 template <int RI, int RD, bool HALF>
 __global__ __launch_bounds__(256) void blend_light_kernel(VolumeView v, BlendIO io) {
   using W = WaveTile<RI, RD>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const uint32_t H = v.stats->num_heavy;
   const uint32_t L = (uint32_t)v.P - H;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
-  for (;;) {
-    uint32_t q = 0;
-    if ((threadIdx.x & 63) == 0) q = atomicAdd(&v.stats->blend_counter2, 1u);
-    q = __shfl(q, 0);
-    if (q >= L) break;
+  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < L; q += waves)
     blend_probe_wave<RI, RD, HALF>(v, io, v.order[H + q], wbase);
-  }
 }
 
 __global__ void blend_reset_kernel(VolumeView v) {
