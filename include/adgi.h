@@ -198,13 +198,12 @@ typedef struct {
                                  0: one thread per ray, grid sized to the rays    */
   int32_t trace_block;        /* threads per traversal workgroup: 64..1024, x64   */
   int32_t trace_waves_per_cu; /* persistent grid = CUs * this / (block/64), 1..32 */
-  int32_t blend_chunk;        /* 0: wave-per-probe blend (tiles 8/16 or 16/16);
+  int32_t blend_chunk;        /* 0: wave-per-probe blend (tiles 8/16 or 16/16),
+                                 probes taken in most-rays-first order;
                                  64..2048, x64: rays staged in LDS per step of the
                                  workgroup-per-probe blend                        */
   int32_t lds_top_nodes;      /* BVH nodes staged in LDS per workgroup: 0..1024   */
-  int32_t blend_blocks_per_cu;/* scheduled blend: workgroups per CU, 1..32         */
-  int32_t blend_heavy_rays;   /* scheduled blend: probes with more rays are blended
-                                 by a whole workgroup, the rest one per wave      */
+  int32_t blend_blocks_per_cu;/* wave-per-probe blend: workgroups per CU, 1..32    */
 } adgi_tuning;
 
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);

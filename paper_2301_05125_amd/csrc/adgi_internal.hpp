@@ -35,8 +35,9 @@ struct BlendIO {
   uint8_t* irr_n_out;
   uint8_t* dep_n_out;
 };
-// chunk = 0 selects the persistent heavy-first kernel (tile sizes 8/16 and
-// 16/16) with `grid` workgroups; otherwise one workgroup per probe.
+// chunk = 0 selects the wave-per-probe kernel (tile sizes 8/16 and 16/16) with
+// `grid` workgroups walking the allocation's probe order; otherwise one
+// workgroup per probe with `chunk` rays staged per step.
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk,
                         int grid = 0);
 bool blend_wave_supported(const VolumeView& v);

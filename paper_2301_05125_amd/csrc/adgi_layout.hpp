@@ -12,6 +12,7 @@ constexpr int kMaxLights = 8;
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
 constexpr int kStackLds = 16;                   // traversal stack entries kept in LDS
+constexpr int kOrderBuckets = 32;               // blend order: 64-ray chunks per probe, capped
 constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
 constexpr float kShadowOffset = 1e-4f;          // shadow origin offset, units of s
 constexpr float kShadowShorten = 1e-6f;         // relative shortening of shadow rays
@@ -64,10 +65,8 @@ struct FrameStats {
   uint64_t node_tests;      // work-counting traversal only
   uint64_t tri_tests;
   int64_t remainder;        // R = B' - sum e_i(lambda*)
-  uint32_t blend_counter;   // heavy-probe blend queue cursor
-  uint32_t num_heavy;       // probes blended by a whole workgroup (set by allocation)
-  uint32_t num_light;
-  uint32_t blend_counter2;  // light-probe blend queue cursor
+  uint32_t bucket_count[kOrderBuckets];   // probes per ray-chunk bucket
+  uint32_t bucket_cursor[kOrderBuckets];  // scatter cursors
   uint64_t sums[4][kAllocCandidates];
 };
 
@@ -103,8 +102,7 @@ struct VolumeView {
   uint32_t* blk_el;           // per-block count of probes eligible for the top-up
   uint32_t* blk_rank;         // per-block exclusive rank base among eligible probes
   uint32_t* blk_off;          // per-block exclusive ray offset
-  int32_t* order;             // [P] blend order: heavy probes first, then light
-  int32_t heavy_rays;         // probes with more rays are blended by a workgroup
+  int32_t* order;             // [P] blend order: most 64-ray chunks first
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
   int32_t* dbg_tri;           // [max_rays] or null

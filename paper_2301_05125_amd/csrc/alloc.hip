@@ -122,23 +122,49 @@ __device__ int64_t block_exclusive_scan(int64_t x, int64_t* sm, int64_t& total) 
   return v - x + sm[wave];
 }
 
-// Blend work order: heavy probes (more than heavy_rays rays) from the front of
-// order[], light ones from the back, one atomic per wave and list. The order
-// within each list depends on timing, which does not matter: every probe's
-// blend is independent of the others.
-__device__ void append_blend_order(const VolumeView& v, bool valid, int i, int n) {
-  const bool heavy = valid && n > v.heavy_rays, light = valid && !heavy;
-  const uint64_t mh = __ballot(heavy), ml = __ballot(light);
-  const uint32_t lane = __lane_id();
-  uint32_t bh = 0, bl = 0;
-  if (lane == 0) {
-    if (mh) bh = atomicAdd(&v.stats->num_heavy, (uint32_t)__popcll(mh));
-    if (ml) bl = atomicAdd(&v.stats->num_light, (uint32_t)__popcll(ml));
+// Blend work order: probes sorted by their number of 64-ray chunks, most
+// first, so that the longest per-probe blends start first. Bucket b holds the
+// probes with min(ceil(n/64), 32) = 32 - b chunks. Counting happens with the
+// allocation; order_scatter_kernel then places every probe. The order inside a
+// bucket depends on timing, which does not matter: every probe's blend is
+// independent of the others.
+__device__ __forceinline__ int order_bucket(int n) {
+  const int c = min((n + 63) >> 6, kOrderBuckets);
+  return kOrderBuckets - c;
+}
+
+__device__ void count_buckets(const VolumeView& v, bool valid, int n, uint32_t* hist) {
+  if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+  __syncthreads();
+  if (valid) atomicAdd(&hist[order_bucket(n)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && hist[threadIdx.x])
+    atomicAdd(&v.stats->bucket_count[threadIdx.x], hist[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(VolumeView v) {
+  __shared__ uint32_t start[kOrderBuckets], hist[kOrderBuckets], base[kOrderBuckets];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+      start[b] = acc;
+      acc += v.stats->bucket_count[b];
+    }
   }
-  bh = __shfl(bh, 0);
-  bl = __shfl(bl, 0);
-  if (heavy) v.order[bh + lanes_below(mh)] = i;
-  if (light) v.order[v.P - 1 - (bl + lanes_below(ml))] = i;
+  if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+  __syncthreads();
+  int b = 0;
+  uint32_t local = 0;
+  if (i < v.P) {
+    b = order_bucket(v.n[i]);
+    local = atomicAdd(&hist[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && hist[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&v.stats->bucket_cursor[threadIdx.x], hist[threadIdx.x]);
+  __syncthreads();
+  if (i < v.P) v.order[start[b] + base[b] + local] = i;
 }
 
 // Finalize in three parallel steps over blocks of 256 probes:
@@ -221,8 +247,6 @@ __global__ __launch_bounds__(1024) void alloc_scan_blocks_kernel(VolumeView v) {
     }
   }
   if (threadIdx.x == 0) {
-    v.stats->num_heavy = 0u;
-    v.stats->num_light = 0u;
     v.stats->remainder = R;
     v.offsets[v.P] = (uint32_t)carry_off;
     v.stats->budget_used = (uint64_t)carry_off;
@@ -235,6 +259,7 @@ __global__ __launch_bounds__(256) void alloc_write_kernel(VolumeView v) {
   const FrameParams& fp = *v.fp;
   if (!fp.adaptive) return;
   __shared__ int64_t sm[17];
+  __shared__ uint32_t hist[kOrderBuckets];
   const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
   const uint32_t lam = v.stats->lambda;
   const int64_t R = v.stats->remainder;
@@ -255,7 +280,7 @@ __global__ __launch_bounds__(256) void alloc_write_kernel(VolumeView v) {
     v.offsets[i] = (uint32_t)off;
     nmin = nmax = n;
   }
-  append_blend_order(v, i < v.P, i, n);
+  count_buckets(v, i < v.P, n, hist);
   for (int o = 32; o > 0; o >>= 1) {
     nmin = min(nmin, __shfl_xor(nmin, o));
     nmax = max(nmax, __shfl_xor(nmax, o));
@@ -271,15 +296,10 @@ __global__ void uniform_offsets_kernel(VolumeView v) {
   if (fp.adaptive) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = (uint32_t)fp.n_uniform;
-  if (i < v.P) {
-    v.n[i] = (int)n;
-    v.order[i] = i;
-  }
+  if (i < v.P) v.n[i] = (int)n;
   if (i <= v.P) v.offsets[i] = (uint32_t)i * n;
   if (i == 0) {
-    const bool heavy = (int)n > v.heavy_rays;
-    v.stats->num_heavy = heavy ? (uint32_t)v.P : 0u;
-    v.stats->num_light = heavy ? 0u : (uint32_t)v.P;
+    v.stats->bucket_count[order_bucket((int)n)] = (uint32_t)v.P;
     v.stats->n_min_seen = (int)n;
     v.stats->n_max_seen = (int)n;
     v.stats->budget_used = (uint64_t)v.P * n;
@@ -294,11 +314,13 @@ hipError_t launch_alloc(const VolumeView& v, hipStream_t s) {
   hipLaunchKernelGGL(alloc_blocks_kernel, dim3(g), dim3(256), 0, s, v);
   hipLaunchKernelGGL(alloc_scan_blocks_kernel, dim3(1), dim3(1024), 0, s, v);
   hipLaunchKernelGGL(alloc_write_kernel, dim3(g), dim3(256), 0, s, v);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, v);
   return hipGetLastError();
 }
 
 hipError_t launch_uniform_offsets(const VolumeView& v, hipStream_t s) {
   hipLaunchKernelGGL(uniform_offsets_kernel, dim3((v.P + 1 + 255) / 256), dim3(256), 0, s, v);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, v);
   return hipGetLastError();
 }
 

@@ -242,16 +242,15 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
 }
 
 // ---------------------------------------------------------------------------
-// Scheduled variant for the common tile sizes: the allocation writes a probe
-// order with the probes that have many rays first. A persistent kernel blends
-// those heavy probes, one whole 256-thread workgroup each, 256 rays per step,
-// one interior texel per thread; a second persistent kernel then blends the
-// light probes, one 64-lane wave each, 64 rays per step, every wave taking the
-// next probe from a queue. In
-// both cases each ray ORs its bit into a per-texel LDS mask (one 64-bit word
-// per wave of rays), and the texel's owner walks the set bits from the lowest
-// word and bit: that is ascending ray order, so no sort is needed. The next
-// step's records are loaded while the current step is applied.
+// Wave-per-probe variant for the common tile sizes. One 64-lane wave owns one
+// probe: interior texel k lives in the registers of lane k % 64 (slot k / 64)
+// for the whole frame. Rays are taken 64 at a time, one per lane; each lane
+// ORs its lane bit into a 64-bit LDS mask of the irradiance texel and of the
+// depth texel its direction falls in, and every owner then walks the set bits
+// of its texels' masks from the lowest: that is ascending ray order, so no sort
+// is needed and all synchronisation stays within the wave. The next 64 records
+// are loaded while the current ones are applied. Waves take probes in the
+// allocation's order (most rays first) so the longest blends start first.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -267,10 +266,6 @@ struct WaveTile {
   static constexpr size_t kStageBytes = 4 * (3 * (size_t)NI + 2 * (size_t)ND) + NT;
   static constexpr size_t kWaveBytes =
       ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
-  // heavy path over the whole workgroup: 256 records + 4 mask words per texel
-  static constexpr size_t kBlockChunk = 256 * 16 + 32 * (size_t)NT;
-  static constexpr size_t kBlockBytes =
-      ((kBlockChunk > 4 * kWaveBytes ? kBlockChunk : 4 * kWaveBytes) + 15) & ~(size_t)15;
 };
 
 // One texel update with the moving average of Alg. MovingAvgUpdate.
@@ -290,35 +285,47 @@ __device__ __forceinline__ void blend_tau(float* V, uint32_t& N, float t, float 
   N = min(N + 1u, 255u);
 }
 
+// Tile element -> interior source element (border fold), built once per
+// workgroup in LDS: irradiance [GI*GI*3], then depth [GD*GD*2].
+template <int RI, int RD>
+__device__ void build_fold_tables(uint16_t* tab) {
+  using W = WaveTile<RI, RD>;
+  constexpr int GI = W::GI, GD = W::GD;
+  for (int f = threadIdx.x; f < GI * GI * 3; f += blockDim.x) {
+    const int t = f / 3, c = f - 3 * t, Y = t / GI, X = t - Y * GI;
+    int sx, sy;
+    border_source(X, Y, RI, sx, sy);
+    tab[f] = (uint16_t)(((sy - 1) * RI + (sx - 1)) * 3 + c);
+  }
+  for (int f = threadIdx.x; f < GD * GD * 2; f += blockDim.x) {
+    const int t = f >> 1, c = f & 1, Y = t / GD, X = t - Y * GD;
+    int sx, sy;
+    border_source(X, Y, RD, sx, sy);
+    tab[GI * GI * 3 + f] = (uint16_t)(((sy - 1) * RD + (sx - 1)) * 2 + c);
+  }
+}
+
 // Write the staged interior (stI, stD, stN in LDS) as full tiles with the border fold.
 template <int RI, int RD, bool HALF>
 __device__ void write_tiles(const VolumeView& v, const BlendIO& io, int i, const float* stI,
-                            const float* stD, const uint8_t* stN, int t0, int nthreads) {
+                            const float* stD, const uint8_t* stN, const uint16_t* tab, int t0,
+                            int nthreads) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
   constexpr int NI = W::NI, ND = W::ND, GI = W::GI, GD = W::GD;
   T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
   T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
-  for (int f = t0; f < GI * GI * 3; f += nthreads) {
-    const int t = f / 3, c = f - 3 * t, Y = t / GI, X = t - Y * GI;
-    int sx, sy;
-    border_source(X, Y, RI, sx, sy);
-    S::store(irr_out + f, stI[((sy - 1) * RI + (sx - 1)) * 3 + c]);
-  }
-  for (int f = t0; f < GD * GD * 2; f += nthreads) {
-    const int t = f >> 1, c = f & 1, Y = t / GD, X = t - Y * GD;
-    int sx, sy;
-    border_source(X, Y, RD, sx, sy);
-    S::store(dep_out + f, stD[((sy - 1) * RD + (sx - 1)) * 2 + c]);
-  }
+  for (int f = t0; f < GI * GI * 3; f += nthreads) S::store(irr_out + f, stI[tab[f]]);
+  for (int f = t0; f < GD * GD * 2; f += nthreads) S::store(dep_out + f, stD[tab[GI * GI * 3 + f]]);
   for (int k = t0; k < NI; k += nthreads) io.irr_n_out[(size_t)i * NI + k] = stN[k];
   for (int k = t0; k < ND; k += nthreads) io.dep_n_out[(size_t)i * ND + k] = stN[NI + k];
 }
 
 // Light probe: one wave.
 template <int RI, int RD, bool HALF>
-__device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase) {
+__device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
+                                 const uint16_t* tab) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
@@ -428,142 +435,23 @@ __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, 
     }
   }
   wave_sync();
-  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, lane, 64);
+  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, tab, lane, 64);
   wave_sync();
 }
 
-// Heavy probe: the whole workgroup; thread t owns texels t and t + 256.
+// One wave per probe, probes taken round-robin over all waves of the grid in
+// the allocation's order (most chunks first).
 template <int RI, int RD, bool HALF>
-__device__ void blend_probe_block(const VolumeView& v, const BlendIO& io, int i, uint8_t* base) {
-  using S = Store<HALF>;
-  using T = typename S::T;
-  using W = WaveTile<RI, RD>;
-  constexpr int NI = W::NI, ND = W::ND, NT = W::NT, GI = W::GI, GD = W::GD;
-  constexpr int SB = (NT + 255) / 256;
-  const int t = threadIdx.x;
-  float4* rec_s = (float4*)base;
-  unsigned long long* mask = (unsigned long long*)(base + 256 * 16);  // [NT][4]
-  const FrameParams& fp = *v.fp;
-  float V[SB][3];
-  uint32_t N[SB];
-#pragma unroll
-  for (int b = 0; b < SB; ++b) {
-    const int k = t + 256 * b;
-    V[b][0] = V[b][1] = V[b][2] = 0.f;
-    N[b] = 0u;
-    if (k < NI) {
-      const int iy = k / RI, ix = k - iy * RI;
-      const T* p = (const T*)io.irr_in + (size_t)i * GI * GI * 3 + ((iy + 1) * GI + ix + 1) * 3;
-      V[b][0] = S::load(p);
-      V[b][1] = S::load(p + 1);
-      V[b][2] = S::load(p + 2);
-      N[b] = io.irr_n_in[(size_t)i * NI + k];
-    } else if (k < NT) {
-      const int kd = k - NI, iy = kd / RD, ix = kd - iy * RD;
-      const T* p = (const T*)io.dep_in + (size_t)i * GD * GD * 2 + ((iy + 1) * GD + ix + 1) * 2;
-      V[b][0] = S::load(p);
-      V[b][1] = S::load(p + 1);
-      N[b] = io.dep_n_in[(size_t)i * ND + kd];
-    }
-  }
-  const uint32_t off = v.offsets[i];
-  const uint32_t n = v.offsets[i + 1] - off;
-  const float inv_s = 1.0f / v.s_diag;
-  const float omh = v.one_minus_h, tmax = v.tau_max;
-  float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-  if ((uint32_t)t < n) nxt = v.rec[off + t];
-  for (uint32_t c0 = 0; c0 < n; c0 += 256u) {
-    const uint32_t m = min(256u, n - c0);
-    const float4 cur = nxt;
-    if (c0 + 256u + (uint32_t)t < n) nxt = v.rec[off + c0 + 256u + t];
-    for (int k = t; k < 4 * NT; k += 256) mask[k] = 0ull;
-    __syncthreads();
-    if ((uint32_t)t < m) {
-      const uint32_t j = c0 + (uint32_t)t;
-      rec_s[t] = cur;
-      const float2 uv = oct_encode(sf_direction(j, n, fp.R));
-      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
-      const unsigned long long bit = 1ull << (t & 63);
-      atomicOr(&mask[4 * bI + (t >> 6)], bit);
-      atomicOr(&mask[4 * (NI + bD) + (t >> 6)], bit);
-      if (fp.debug) {
-        v.dbg_ibin[off + j] = (uint16_t)bI;
-        v.dbg_dbin[off + j] = (uint16_t)bD;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < SB; ++b) {
-      const int k = t + 256 * b;
-      if (k >= NT) continue;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        unsigned long long mk = mask[4 * k + w];
-        while (mk) {
-          const int j = 64 * w + __ffsll((long long)mk) - 1;
-          mk &= mk - 1ull;
-          if (k < NI) blend_rgb(V[b], N[b], rec_s[j], omh);
-          else blend_tau(V[b], N[b], rec_s[j].w, inv_s, tmax, omh);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  float* stI = (float*)base;
-  float* stD = stI + 3 * NI;
-  uint8_t* stN = (uint8_t*)(stD + 2 * ND);
-#pragma unroll
-  for (int b = 0; b < SB; ++b) {
-    const int k = t + 256 * b;
-    if (k < NI) {
-      stI[3 * k] = V[b][0];
-      stI[3 * k + 1] = V[b][1];
-      stI[3 * k + 2] = V[b][2];
-      stN[k] = (uint8_t)N[b];
-    } else if (k < NT) {
-      stD[2 * (k - NI)] = V[b][0];
-      stD[2 * (k - NI) + 1] = V[b][1];
-      stN[k] = (uint8_t)N[b];
-    }
-  }
-  __syncthreads();
-  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, t, 256);
-  __syncthreads();
-}
-
-// Heavy probes, a whole workgroup each, taken from the front of order[].
-template <int RI, int RD, bool HALF>
-__global__ __launch_bounds__(256) void blend_heavy_kernel(VolumeView v, BlendIO io) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  __shared__ uint32_t item_s;
-  const uint32_t H = v.stats->num_heavy;
-  for (;;) {
-    if (threadIdx.x == 0) item_s = atomicAdd(&v.stats->blend_counter, 1u);
-    __syncthreads();
-    const uint32_t w = item_s;
-    __syncthreads();
-    if (w >= H) break;
-    blend_probe_block<RI, RD, HALF>(v, io, v.order[w], smem);
-  }
-}
-
-// Light probes, one wave each, assigned round-robin over all waves of the grid
-// (each has at most heavy_rays rays, so a static split is balanced).
-template <int RI, int RD, bool HALF>
-__global__ __launch_bounds__(256) void blend_light_kernel(VolumeView v, BlendIO io) {
+__global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io) {
   using W = WaveTile<RI, RD>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  const uint32_t H = v.stats->num_heavy;
-  const uint32_t L = (uint32_t)v.P - H;
+  uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
+  build_fold_tables<RI, RD>(tab);
+  __syncthreads();
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
-  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < L; q += waves)
-    blend_probe_wave<RI, RD, HALF>(v, io, v.order[H + q], wbase);
-}
-
-__global__ void blend_reset_kernel(VolumeView v) {
-  v.stats->blend_counter = 0u;
-  v.stats->blend_counter2 = 0u;
+  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
+    blend_probe_wave<RI, RD, HALF>(v, io, v.order[q], wbase, tab);
 }
 
 bool blend_wave_supported(const VolumeView& v) {
@@ -577,22 +465,16 @@ size_t blend_lds_bytes(const VolumeView& v, int chunk) {
 template <int RI, int RD>
 static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int grid) {
   using W = WaveTile<RI, RD>;
-  hipLaunchKernelGGL(blend_reset_kernel, dim3(1), dim3(1), 0, s, v);
-  const int gh = grid > 1 ? grid / 2 : 1;
-  if (fp16) {
-    hipLaunchKernelGGL((blend_heavy_kernel<RI, RD, true>), dim3(gh), dim3(256), W::kBlockBytes, s, v, io);
-    hipLaunchKernelGGL((blend_light_kernel<RI, RD, true>), dim3(grid), dim3(256), 4 * W::kWaveBytes, s, v,
-                       io);
-  } else {
-    hipLaunchKernelGGL((blend_heavy_kernel<RI, RD, false>), dim3(gh), dim3(256), W::kBlockBytes, s, v, io);
-    hipLaunchKernelGGL((blend_light_kernel<RI, RD, false>), dim3(grid), dim3(256), 4 * W::kWaveBytes, s,
-                       v, io);
-  }
+  const size_t lds = 4 * W::kWaveBytes + 2 * (W::GI * W::GI * 3 + W::GD * W::GD * 2);
+  if (fp16)
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
+  else
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
 }
 
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk,
                         int grid) {
-  if (chunk == 0) {  // scheduled heavy-first kernel
+  if (chunk == 0) {  // wave-per-probe kernel in most-rays-first order
     if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, fp16, grid);
     else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, fp16, grid);
     else return hipErrorInvalidValue;

@@ -19,6 +19,10 @@ __global__ void frame_begin_kernel(VolumeView v) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   FrameStats* st = v.stats;
   if (tid < 4 * kAllocCandidates) (&st->sums[0][0])[tid] = 0ull;
+  if (tid < kOrderBuckets) {
+    st->bucket_count[tid] = 0u;
+    st->bucket_cursor[tid] = 0u;
+  }
   if (tid == 0) {
     st->ray_counter = 0u;
     st->pilot_counter = 0u;
@@ -31,7 +35,6 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->node_tests = 0ull;
     st->tri_tests = 0ull;
     st->remainder = 0;
-    st->blend_counter = 0u;
   }
   if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;
 }

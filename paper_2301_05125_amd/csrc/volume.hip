@@ -307,7 +307,6 @@ adgi_tuning default_tuning() {
   t.blend_chunk = 256;
   t.lds_top_nodes = 0;
   t.blend_blocks_per_cu = 8;
-  t.blend_heavy_rays = 128;
   return t;
 }
 
@@ -317,7 +316,7 @@ bool tuning_valid(const adgi_tuning& t) {
          t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 &&
          (t.blend_chunk == 0 || (t.blend_chunk >= 64 && t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0)) &&
          t.lds_top_nodes >= 0 && t.lds_top_nodes <= 1024 && t.blend_blocks_per_cu >= 1 &&
-         t.blend_blocks_per_cu <= 32 && t.blend_heavy_rays >= 1;
+         t.blend_blocks_per_cu <= 32;
 }
 
 }  // namespace
@@ -480,7 +479,6 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.tau_max = d->tau_max;
   v.max_rays = (uint32_t)R;
   if (blend_wave_supported(v)) vol->tun.blend_chunk = 0;
-  v.heavy_rays = vol->tun.blend_heavy_rays;
   *out = vol;
   return ADGI_OK;
 }
@@ -807,7 +805,6 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
   HIP_TRY(vol, hipStreamSynchronize(vol->stream));
   drop_graphs(vol);
   vol->tun = *t;
-  vol->v.heavy_rays = t->blend_heavy_rays;
   vol->tuned = true;
   return ADGI_OK;
 }
