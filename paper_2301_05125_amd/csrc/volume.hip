@@ -306,7 +306,7 @@ adgi_tuning default_tuning() {
   t.trace_waves_per_cu = 16;
   t.blend_chunk = 256;
   t.lds_top_nodes = 0;
-  t.blend_blocks_per_cu = 8;
+  t.blend_blocks_per_cu = 16;
   return t;
 }
 
@@ -997,17 +997,20 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     }
   }
   float best_blend = INFINITY;
-  const int chunks[] = {0, 128, 256, 512};
-  for (int ch : chunks) {
+  struct BlendCand {
+    int chunk, bpc;
+  };
+  const BlendCand bcands[] = {{0, 4}, {0, 8}, {0, 16}, {128, 8}, {256, 8}, {512, 8}};
+  for (const BlendCand& bc : bcands) {
     if (err != hipSuccess) break;
-    if (ch == 0 && !blend_wave_supported(vol->v)) continue;
-    if (ch != 0 && blend_lds_bytes(vol->v, ch) > 65536) continue;
+    if (bc.chunk == 0 && !blend_wave_supported(vol->v)) continue;
+    if (bc.chunk != 0 && blend_lds_bytes(vol->v, bc.chunk) > 65536) continue;
     BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, so_irr, so_dep, (uint8_t*)so_in, (uint8_t*)so_dn};
     float bm = INFINITY;
     for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
       if ((err = hipEventRecord(vol->ev_t0, s)) != hipSuccess) break;
-      if ((err = launch_blend(vol->v, io, s, vol->desc.storage == ADGI_FP16, ch,
-                              vol->num_cus * best_t.blend_blocks_per_cu)) != hipSuccess)
+      if ((err = launch_blend(vol->v, io, s, vol->desc.storage == ADGI_FP16, bc.chunk,
+                              vol->num_cus * bc.bpc)) != hipSuccess)
         break;
       if ((err = hipEventRecord(vol->ev_t1, s)) != hipSuccess) break;
       if ((err = hipEventSynchronize(vol->ev_t1)) != hipSuccess) break;
@@ -1017,7 +1020,8 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     }
     if (bm < best_blend) {
       best_blend = bm;
-      best_t.blend_chunk = ch;
+      best_t.blend_chunk = bc.chunk;
+      best_t.blend_blocks_per_cu = bc.bpc;
     }
   }
   if (err != hipSuccess) {
