@@ -1,7 +1,9 @@
 """Build the gfx950 probe-update library (libadgi.so) in-tree with hipcc.
 
 Every HIP source is compiled for gfx950 only, with packed FP32 instructions
-disabled, then linked into one shared library next to this file.
+disabled and floating-point contraction off (the kernels write fmaf where a
+fused multiply-add is meant, so every kernel rounds the same expression the
+same way), then linked into one shared library next to this file.
 """
 from __future__ import annotations
 
@@ -22,7 +24,8 @@ SOURCES = ["volume.hip", "trace.hip", "detect.hip", "alloc.hip", "blend.hip", "r
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
+         "-Wall", "-Wno-unused-function",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          f"-I{os.path.join(ROOT, 'include')}"]
 
