@@ -42,7 +42,9 @@ constexpr float kTwoPi = 6.28318530717958647692f;
 // rotated by the row-major frame rotation R. The azimuth fraction is the top
 // 32 bits of the 64-bit fixed-point product j * 2^64/golden.
 __device__ __forceinline__ float3 sf_direction(uint32_t j, uint32_t n, const float* R) {
-  float a = (float)(2u * j + 1u) / (float)n;     // 1 - z
+  // 1 - z with the hardware reciprocal (<= 1 ulp); every kernel that needs
+  // a probe-ray direction calls this same function, so they agree bitwise
+  float a = (float)(2u * j + 1u) * __builtin_amdgcn_rcpf((float)n);
   float z = 1.0f - a;
   float r = sqrtf(fmaxf(0.0f, a * (2.0f - a)));  // sqrt(1 - z^2) without cancellation
   uint64_t f = (uint64_t)j * 0x9E3779B97F4A7C15ull;
@@ -72,7 +74,7 @@ __device__ __forceinline__ float3 pilot_direction(uint64_t seed, uint32_t probe,
 // ------------------------------------------------------------- octahedral
 // Octahedral map (Cigolle et al. 2014) and its half-open texel bins.
 __device__ __forceinline__ float2 oct_encode(float3 d) {
-  float inv = 1.0f / (fabsf(d.x) + fabsf(d.y) + fabsf(d.z));
+  float inv = __builtin_amdgcn_rcpf(fabsf(d.x) + fabsf(d.y) + fabsf(d.z));
   float x = d.x * inv, y = d.y * inv;
   if (d.z < 0.0f) {
     float nx = (1.0f - fabsf(y)) * (x >= 0.0f ? 1.0f : -1.0f);

@@ -260,18 +260,33 @@ __device__ __forceinline__ void wave_sync() {
 template <int RI, int RD>
 struct WaveTile {
   static constexpr int NI = RI * RI, ND = RD * RD, NT = NI + ND;
+  static constexpr int SI = (NI + 63) / 64, SD = (ND + 63) / 64;
   static constexpr int GI = RI + 2, GD = RD + 2;
-  // per-wave LDS: records, texel masks, irradiance state (float4 per texel),
-  // depth state (float2 per texel), counts (u8)
-  static constexpr size_t kRec = 0;
-  static constexpr size_t kMask = kRec + 64 * 16;
-  static constexpr size_t kStI = kMask + 8 * (size_t)NT;
-  static constexpr size_t kStD = kStI + 16 * (size_t)NI;
-  static constexpr size_t kCnt = kStD + 8 * (size_t)ND;
-  static constexpr size_t kWaveBytes = (kCnt + NT + 15) & ~(size_t)15;
-  static constexpr size_t kTabBytes = 2 * (GI * GI * 3 + GD * GD * 2);
-  static constexpr size_t kBlockBytes = 4 * kWaveBytes + ((kTabBytes + 15) & ~(size_t)15) + 256 * 4;
+  static constexpr size_t kChunkBytes = 64 * 16 + 8 * (size_t)NT;
+  static constexpr size_t kStageBytes = 4 * (3 * (size_t)NI + 2 * (size_t)ND) + NT;
+  static constexpr size_t kWaveBytes =
+      ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
+  static constexpr size_t kTabBytes = (2 * (GI * GI * 3 + GD * GD * 2) + 15) & ~(size_t)15;
+  static constexpr size_t kBlockBytes = 4 * kWaveBytes + kTabBytes + 256 * 4;
 };
+
+// One texel update with the moving average of Alg. MovingAvgUpdate; the
+// step weight max(1/(N+1), 1-h) comes from a per-workgroup table.
+__device__ __forceinline__ void blend_rgb(float* V, uint32_t& N, float4 r, const float* alpha) {
+  const float al = alpha[N];
+  V[0] = fmaf(al, r.x - V[0], V[0]);
+  V[1] = fmaf(al, r.y - V[1], V[1]);
+  V[2] = fmaf(al, r.z - V[2], V[2]);
+  N = min(N + 1u, 255u);
+}
+__device__ __forceinline__ void blend_tau(float* V, uint32_t& N, float t, float inv_s, float tmax,
+                                          const float* alpha) {
+  const float tau = fminf(t * inv_s, tmax);
+  const float al = alpha[N];
+  V[0] = fmaf(al, tau - V[0], V[0]);
+  V[1] = fmaf(al, tau * tau - V[1], V[1]);
+  N = min(N + 1u, 255u);
+}
 
 // Tile element -> interior source element (border fold), built once per
 // workgroup in LDS: irradiance [GI*GI*3], then depth [GD*GD*2].
@@ -304,106 +319,126 @@ __device__ void write_tiles(const VolumeView& v, const BlendIO& io, int i, const
   constexpr int NI = W::NI, ND = W::ND, GI = W::GI, GD = W::GD;
   T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
   T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
-  for (int f = t0; f < GI * GI * 3; f += nthreads) {
-    const int src = tab[f];  // interior element k*3 + c, stored at k*4 + c
-    S::store(irr_out + f, stI[src + src / 3]);
-  }
+  for (int f = t0; f < GI * GI * 3; f += nthreads) S::store(irr_out + f, stI[tab[f]]);
   for (int f = t0; f < GD * GD * 2; f += nthreads) S::store(dep_out + f, stD[tab[GI * GI * 3 + f]]);
   for (int k = t0; k < NI; k += nthreads) io.irr_n_out[(size_t)i * NI + k] = stN[k];
   for (int k = t0; k < ND; k += nthreads) io.dep_n_out[(size_t)i * ND + k] = stN[NI + k];
 }
 
-// One probe, one wave. Texel state lives in the wave's LDS. For each step of
-// 64 rays, ray j's rank among the rays of the step that fall in the same texel
-// is the number of lower lanes set in that texel's mask; round r then applies
-// every rank-r sample at once, so each texel sees its samples in ascending ray
-// order and all lanes stay busy.
+// Light probe: one wave.
 template <int RI, int RD, bool HALF>
 __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
                                  const uint16_t* tab, const float* alpha) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
-  constexpr int NI = W::NI, ND = W::ND, NT = W::NT, GI = W::GI, GD = W::GD;
+  constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
   const int lane = threadIdx.x & 63;
-  float4* rec_s = (float4*)(wbase + W::kRec);
-  unsigned long long* mask = (unsigned long long*)(wbase + W::kMask);  // [NI | ND]
-  float* stI = (float*)(wbase + W::kStI);                              // [NI][4]
-  float* stD = (float*)(wbase + W::kStD);                              // [ND][2]
-  uint8_t* cnt = wbase + W::kCnt;                                      // [NI | ND]
+  float4* rec_s = (float4*)wbase;
+  unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
   const FrameParams& fp = *v.fp;
   const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
   const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
-  for (int f = lane; f < NI * 3; f += 64) {
-    const int k = f / 3, c = f - 3 * k, iy = k / RI, ix = k - iy * RI;
-    stI[4 * k + c] = S::load(irr_in + ((iy + 1) * GI + ix + 1) * 3 + c);
+  float vi[SI][3], vd[SD][2];
+  uint32_t ni[SI], nd[SD];
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    vi[s][0] = vi[s][1] = vi[s][2] = 0.f;
+    ni[s] = 0u;
+    if (k < NI) {
+      const int iy = k / RI, ix = k - iy * RI;
+      const T* p = irr_in + ((iy + 1) * GI + ix + 1) * 3;
+      vi[s][0] = S::load(p);
+      vi[s][1] = S::load(p + 1);
+      vi[s][2] = S::load(p + 2);
+      ni[s] = io.irr_n_in[(size_t)i * NI + k];
+    }
   }
-  for (int f = lane; f < ND * 2; f += 64) {
-    const int k = f >> 1, c = f & 1, iy = k / RD, ix = k - iy * RD;
-    stD[f] = S::load(dep_in + ((iy + 1) * GD + ix + 1) * 2 + c);
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    vd[s][0] = vd[s][1] = 0.f;
+    nd[s] = 0u;
+    if (k < ND) {
+      const int iy = k / RD, ix = k - iy * RD;
+      const T* p = dep_in + ((iy + 1) * GD + ix + 1) * 2;
+      vd[s][0] = S::load(p);
+      vd[s][1] = S::load(p + 1);
+      nd[s] = io.dep_n_in[(size_t)i * ND + k];
+    }
   }
-  for (int k = lane; k < NT; k += 64)
-    cnt[k] = k < NI ? io.irr_n_in[(size_t)i * NI + k] : io.dep_n_in[(size_t)i * ND + (k - NI)];
   const uint32_t off = v.offsets[i];
   const uint32_t n = v.offsets[i + 1] - off;
   const float inv_s = 1.0f / v.s_diag;
   const float tmax = v.tau_max;
   float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
   if ((uint32_t)lane < n) nxt = v.rec[off + lane];
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
     const uint32_t m = min(64u, n - c0);
     const float4 cur = nxt;
     if (c0 + 64u + (uint32_t)lane < n) nxt = v.rec[off + c0 + 64u + lane];
-    for (int k = lane; k < NT; k += 64) mask[k] = 0ull;
+    for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
     wave_sync();
-    const bool has = (uint32_t)lane < m;
-    uint32_t bI = 0, bD = 0;
-    if (has) {
+    if ((uint32_t)lane < m) {
       const uint32_t j = c0 + (uint32_t)lane;
       rec_s[lane] = cur;
       const float2 uv = oct_encode(sf_direction(j, n, fp.R));
-      bI = oct_bin(uv, RI);
-      bD = NI + oct_bin(uv, RD);
+      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
       atomicOr(&mask[bI], 1ull << lane);
-      atomicOr(&mask[bD], 1ull << lane);
+      atomicOr(&mask[NI + bD], 1ull << lane);
       if (fp.debug) {
         v.dbg_ibin[off + j] = (uint16_t)bI;
-        v.dbg_dbin[off + j] = (uint16_t)(bD - NI);
+        v.dbg_dbin[off + j] = (uint16_t)bD;
       }
     }
     wave_sync();
-    // lanes without a ray take rank -1: never active, never keep the loop going
-    const int rI = has ? __popcll(mask[bI] & below) : -1;
-    const int rD = has ? __popcll(mask[bD] & below) : -1;
-    const float tau = fminf(cur.w * inv_s, tmax);
-    for (int r = 0; __ballot(rI >= r || rD >= r) != 0ull; ++r) {
-      const bool aI = rI == r, aD = rD == r;
-      if (aI) {
-        const uint32_t N = cnt[bI];
-        const float al = alpha[N];
-        float4 V = *(float4*)(stI + 4 * bI);
-        V.x = fmaf(al, cur.x - V.x, V.x);
-        V.y = fmaf(al, cur.y - V.y, V.y);
-        V.z = fmaf(al, cur.z - V.z, V.z);
-        *(float4*)(stI + 4 * bI) = V;
-        cnt[bI] = (uint8_t)min(N + 1u, 255u);
+#pragma unroll
+    for (int s = 0; s < SI; ++s) {
+      const int k = lane + 64 * s;
+      unsigned long long mk = k < NI ? mask[k] : 0ull;
+      while (mk) {
+        const int j = __ffsll((long long)mk) - 1;
+        mk &= mk - 1ull;
+        blend_rgb(vi[s], ni[s], rec_s[j], alpha);
       }
-      if (aD) {
-        const int kd = (int)bD - NI;
-        const uint32_t N = cnt[bD];
-        const float al = alpha[N];
-        float2 V = *(float2*)(stD + 2 * kd);
-        V.x = fmaf(al, tau - V.x, V.x);
-        V.y = fmaf(al, tau * tau - V.y, V.y);
-        *(float2*)(stD + 2 * kd) = V;
-        cnt[bD] = (uint8_t)min(N + 1u, 255u);
+    }
+#pragma unroll
+    for (int s = 0; s < SD; ++s) {
+      const int k = lane + 64 * s;
+      unsigned long long mk = k < ND ? mask[NI + k] : 0ull;
+      while (mk) {
+        const int j = __ffsll((long long)mk) - 1;
+        mk &= mk - 1ull;
+        blend_tau(vd[s], nd[s], rec_s[j].w, inv_s, tmax, alpha);
       }
-      wave_sync();
     }
     wave_sync();
   }
-  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, cnt, tab, lane, 64);
+  float* stI = (float*)wbase;
+  float* stD = stI + 3 * NI;
+  uint8_t* stN = (uint8_t*)(stD + 2 * ND);
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    if (k < NI) {
+      stI[3 * k] = vi[s][0];
+      stI[3 * k + 1] = vi[s][1];
+      stI[3 * k + 2] = vi[s][2];
+      stN[k] = (uint8_t)ni[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    if (k < ND) {
+      stD[2 * k] = vd[s][0];
+      stD[2 * k + 1] = vd[s][1];
+      stN[NI + k] = (uint8_t)nd[s];
+    }
+  }
+  wave_sync();
+  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, tab, lane, 64);
   wave_sync();
 }
 
@@ -414,7 +449,7 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
   using W = WaveTile<RI, RD>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
-  float* alpha = (float*)(smem + 4 * W::kWaveBytes + ((W::kTabBytes + 15) & ~(size_t)15));
+  float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
   build_fold_tables<RI, RD>(tab);
   // step weight of Alg. MovingAvgUpdate by sample count N
   for (int k = threadIdx.x; k < 256; k += blockDim.x)
