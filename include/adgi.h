@@ -202,8 +202,10 @@ typedef struct {
                                  probes taken in most-rays-first order;
                                  64..2048, x64: rays staged in LDS per step of the
                                  workgroup-per-probe blend                        */
-  int32_t lds_top_nodes;      /* BVH nodes staged in LDS per workgroup: 0..1024   */
   int32_t blend_blocks_per_cu;/* wave-per-probe blend: workgroups per CU, 1..32    */
+  int32_t bvh_width;          /* 4: traverse the 4-wide BVH collapsed from the
+                                 binary one (when its stack bound fits), else 2;
+                                 2: the binary BVH                                */
 } adgi_tuning;
 
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);
@@ -217,11 +219,12 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* params, ad
 /* ---- traversal work (for rooflines) --------------------------------------
  * Runs the frame's pilot/detection/allocation steps and a counting variant of
  * the probe-ray traversal (same rays, same kernel shape) on the current
- * scene, then restores the volume's state. node_tests counts box-pair tests
- * (one BVH2 node visit tests both child boxes), tri_tests ray/triangle tests,
- * both over the probe rays and their shadow rays. */
+ * scene, then restores the volume's state. node_tests counts node visits
+ * (a BVH2 visit tests two child boxes, a BVH4 visit four), tri_tests
+ * ray/triangle tests, both over the probe rays and their shadow rays. */
 typedef struct {
   int64_t primary_rays, shadow_rays, node_tests, tri_tests;
+  int64_t box_tests;          /* node_tests x the node width in use (2 or 4) */
 } adgi_trace_work;
 adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* params,
                                     adgi_trace_work* out);

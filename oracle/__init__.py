@@ -16,6 +16,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import os
+import time
 import subprocess
 from typing import Optional
 
@@ -353,12 +354,18 @@ class OracleVolume:
                theta: int = 8, hints: Optional[dict] = None, keep_rays: bool = False) -> dict:
         """One frame. ``hints`` holds the GPU's discrete decisions (lockstep)."""
         hints = hints or {}
+        t0 = time.perf_counter()
         self.set_frame_inputs(frame)
         out = {}
+        secs = {"scene": time.perf_counter() - t0, "pilots": 0.0, "detect_allocate": 0.0,
+                "probes": 0.0}
         if adaptive:
+            t0 = time.perf_counter()
             qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"))
+            t1 = time.perf_counter()
             score = self.detect(frame, qv, qr, theta, mu)
             n, off, lam = allocate(score, budget, n_min, n_max)
+            secs["pilots"], secs["detect_allocate"] = t1 - t0, time.perf_counter() - t1
             out.update(qv=qv, qr=qr, score=score, lam=lam)
         else:
             n = np.full(self.P, n_uniform, np.int32)
@@ -394,12 +401,15 @@ class OracleVolume:
         ib = np.zeros(max(total, 1), np.uint16) if keep_rays else None
         db = np.zeros(max(total, 1), np.uint16) if keep_rays else None
         cnt = Counts()
+        t0 = time.perf_counter()
         lib().orc_probes_frame(
             self.scene.ptr, C.byref(self.grid), nq, _p(self.probes), _p(n_sel), _p(ray_base),
             _p(Rf), C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
             1 if self.fp16 else 0, _p(h_tri), _p(h_sh), _p(h_ib), _p(h_db),
             _p(self.irr), _p(self.irr_n), _p(self.dep), _p(self.dep_n),
             _p(rays), _p(tri), _p(sh), _p(ib), _p(db), C.byref(cnt))
+        secs["probes"] = time.perf_counter() - t0
+        out["seconds"] = secs
         for name, _ in Counts._fields_:
             setattr(self.counts, name, getattr(self.counts, name) + getattr(cnt, name))
         out["counts"] = cnt.as_dict()

@@ -89,7 +89,7 @@ class ProbeReadback(C.Structure):
 
 class TraceWork(C.Structure):
     _fields_ = [("primary_rays", C.c_int64), ("shadow_rays", C.c_int64),
-                ("node_tests", C.c_int64), ("tri_tests", C.c_int64)]
+                ("node_tests", C.c_int64), ("tri_tests", C.c_int64), ("box_tests", C.c_int64)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -98,7 +98,7 @@ class TraceWork(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("persistent", C.c_int32), ("trace_block", C.c_int32),
                 ("trace_waves_per_cu", C.c_int32), ("blend_chunk", C.c_int32),
-                ("lds_top_nodes", C.c_int32), ("blend_blocks_per_cu", C.c_int32)]
+                ("blend_blocks_per_cu", C.c_int32), ("bvh_width", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

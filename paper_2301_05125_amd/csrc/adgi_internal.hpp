@@ -12,9 +12,10 @@
 namespace adgi {
 
 // trace.hip
-size_t trace_lds_bytes(int block, int ntop);
+size_t trace_lds_bytes(int block);
+// w4: traverse the BVH4 (v.nodes4) instead of the BVH2.
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
-                        int grid, int ntop, bool count = false);
+                        int grid, bool count = false, bool w4 = false);
 
 // detect.hip: trigger update and the separable 5x5x5 box sum -> scores
 hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s);
@@ -57,6 +58,9 @@ struct RefitView {
 };
 // level_offsets[d] .. level_offsets[d+1] index level_nodes for depth d
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s);
+// Copy refitted BVH2 child boxes into the BVH4 nodes (one thread per slot).
+hipError_t launch_bvh4_gather(float4* nodes4, const int32_t* src, int num_nodes4, const float4* nodes2,
+                              hipStream_t s);
 
 // bvh_build.cpp: binned SAH on the host
 struct BvhHost {
@@ -66,9 +70,20 @@ struct BvhHost {
   std::vector<int32_t> level_nodes;   // internal nodes grouped by depth (root first)
   std::vector<int32_t> level_offsets; // size depth+1
   int32_t depth = 0;
+  int32_t num_big = 0;             // slots [0, num_big): large triangles outside the tree
 };
 bool build_bvh(const float* positions, int32_t nv, const int32_t* indices, int32_t nt, float pad_abs,
                BvhHost& out, const char** err);
+// BVH4 collapse of a BVH2 (node layout in adgi_layout.hpp), nodes in
+// depth-first order. src[4n+k] = 2*g + side names the BVH2 child slot that
+// child k of node n copies (-1: empty), so a refit of the BVH2 is carried over
+// by a gather. max_stack is the worst-case traversal stack depth.
+struct Bvh4Host {
+  std::vector<float4> nodes;   // 8 per node
+  std::vector<int32_t> src;    // 4 per node
+  int32_t max_stack = 0;
+};
+void collapse_bvh4(const BvhHost& b2, Bvh4Host& out);
 // Conservative box padding (builder and refit): a few ulps of the coordinate
 // plus an absolute term tied to the scene's coordinate scale, so that FP32
 // slab tests from any ray origin in the scene never cull a box a hit lies in.

@@ -11,7 +11,7 @@ constexpr uint64_t kTagPilot = 0x50494Cull;     // "PIL"
 constexpr int kMaxLights = 8;
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
-constexpr int kStackLds = 16;                   // traversal stack entries kept in LDS
+constexpr int kStackLds = 12;                   // traversal stack entries kept in LDS
 constexpr int kOrderBuckets = 32;               // blend order: 64-ray chunks per probe, capped
 constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
 constexpr float kShadowOffset = 1e-4f;          // shadow origin offset, units of s
@@ -28,6 +28,15 @@ constexpr float kShadowShorten = 1e-6f;         // relative shortening of shadow
 constexpr int kLeafShift = 4;
 constexpr int kLeafMaxTris = 16;
 
+// BVH4 node (128 bytes), derived from the BVH2 by pulling grandchildren up
+// into their parent (up to four children per node), child boxes as SoA:
+//   f[0] = lo.x[4], f[1] = lo.y[4], f[2] = lo.z[4],
+//   f[3] = hi.x[4], f[4] = hi.y[4], f[5] = hi.z[4],
+//   f[6] = child[4] as int bits (same codes as BVH2; kEmptyChild = unused),
+//   f[7] = unused.
+// Every child box is a copy of a BVH2 child slot, so padding is unchanged.
+constexpr int kEmptyChild = (int)0x80000000;
+
 // Triangle record in leaf order (48 bytes): (v0, id bits), (e1, 0), (e2, 0).
 
 struct SceneParams {
@@ -37,7 +46,7 @@ struct SceneParams {
   int32_t num_lights;
   int32_t num_tris;
   int32_t num_nodes;
-  int32_t pad;
+  int32_t num_big;    // triangle slots [0, num_big) are tested by every ray before the tree
 };
 
 struct FrameParams {
@@ -83,6 +92,7 @@ struct VolumeView {
   float tau_max;
   // scene
   const float4* nodes;
+  const float4* nodes4;       // BVH4 (null when the collapse does not fit the stack)
   const float4* tris;
   const float4* albedo;       // by original triangle index
   const SceneParams* scene;

@@ -1,12 +1,15 @@
-// bvh_build.cpp - binned-SAH BVH2 builder (host) for the traversal kernels.
+// bvh_build.cpp - binned-SAH BVH2 builder (host) for the traversal kernels,
+// and its collapse into a 4-wide BVH.
 //
 // Top-down build with 16 centroid bins per axis and the surface-area cost
-// C = 1 + (A_L N_L + A_R N_R) / A; leaves hold at most 8 triangles (16 when
-// the depth bound forces it). Below depth 40 nodes are split at the object
-// median so the tree never exceeds the traversal stack bound. The output
-// layout stores the first 1024 internal nodes breadth-first (so a prefix of
-// the array is the top of the tree, which the kernels may stage in LDS) and
-// every remaining subtree depth-first (children near their parents).
+// C = 2 + (A_L N_L + A_R N_R) / A (a traversal step costs about two triangle
+// tests); leaves hold at most 8 triangles (16 when the depth bound forces
+// it). Below depth 40 nodes are split at the object median so the tree never
+// exceeds the traversal stack bound. Up to 8 triangles whose box covers at
+// least 1/16 of the scene box's area are kept out of the tree (every ray
+// tests them first). The output layout stores the first 1024 internal nodes
+// breadth-first (the top of the tree is a prefix of the array) and every
+// remaining subtree depth-first (children near their parents).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,6 +61,11 @@ struct BNode {
 constexpr int kBins = 16;
 constexpr int kLeafTarget = 8;
 constexpr int kMedianDepth = 40;
+constexpr double kBigFraction = 1.0 / 16;  // of the scene box's surface area
+constexpr int32_t kMaxBigTris = 8;
+// SAH cost of one traversal step relative to one triangle test: a node visit
+// (two slab tests, stack work) costs about two triangle tests here.
+constexpr double kTraversalCost = 2.0;
 
 }  // namespace
 
@@ -69,6 +77,7 @@ bool build_bvh(const float* pos, int32_t nv, const int32_t* idx, int32_t nt, flo
   out.level_nodes.clear();
   out.level_offsets.clear();
   out.depth = 0;
+  out.num_big = 0;
   if (nt == 0) {
     // a root whose children are never entered (the kernels skip traversal)
     out.nodes.assign(4, make_float4(0.f, 0.f, 0.f, 0.f));
@@ -100,11 +109,36 @@ bool build_bvh(const float* pos, int32_t nv, const int32_t* idx, int32_t nt, flo
   std::vector<int32_t> ord(nt);
   for (int32_t t = 0; t < nt; ++t) ord[t] = t;
 
+  // Triangles whose box is a large fraction of the scene box (a ground
+  // plane, a wall) would inflate every node on their leaf's path to nearly
+  // the scene's size, so every ray would descend that whole path. They go to
+  // a short list in slots [0, num_big) that rays test before the tree.
+  int32_t nbig = 0;
+  {
+    Box all;
+    all.reset();
+    for (int32_t t = 0; t < nt; ++t) all.grow(tb[t]);
+    const double a_all = all.area();
+    std::vector<int32_t> big;
+    for (int32_t t = 0; t < nt; ++t)
+      if (tb[t].area() >= kBigFraction * a_all) big.push_back(t);
+    std::stable_sort(big.begin(), big.end(),
+                     [&](int32_t x, int32_t y) { return tb[x].area() > tb[y].area(); });
+    nbig = std::min<int32_t>({(int32_t)big.size(), kMaxBigTris, nt - 1});
+    std::vector<char> is_big(nt, 0);
+    for (int32_t k = 0; k < nbig; ++k) is_big[big[k]] = 1;
+    int32_t w = 0;
+    for (int32_t k = 0; k < nbig; ++k) ord[w++] = big[k];
+    for (int32_t t = 0; t < nt; ++t)
+      if (!is_big[t]) ord[w++] = t;
+  }
+  out.num_big = nbig;
+
   std::vector<BNode> bn;
   bn.reserve(2 * (size_t)nt / 2 + 8);
   bn.push_back(BNode());
-  bn[0].start = 0;
-  bn[0].count = nt;
+  bn[0].start = nbig;
+  bn[0].count = nt - nbig;
   std::vector<int> work{0};
   int max_depth = 0;
   while (!work.empty()) {
@@ -165,7 +199,7 @@ bool build_bvh(const float* pos, int32_t nv, const int32_t* idx, int32_t nt, flo
         }
       }
       double parent_area = std::max(nd.box.area(), 1e-30);
-      double split_cost = 1.0 + best / parent_area;
+      double split_cost = kTraversalCost + best / parent_area;
       if (axis >= 0 && !(nd.count <= kLeafTarget && split_cost >= (double)nd.count)) {
         float ext = cb.hi[axis] - cb.lo[axis];
         float k = kBins / ext;
@@ -355,6 +389,72 @@ bool build_bvh(const float* pos, int32_t nv, const int32_t* idx, int32_t nt, flo
     }
   }
   return true;
+}
+
+void collapse_bvh4(const BvhHost& b2, Bvh4Host& out) {
+  out.nodes.clear();
+  out.src.clear();
+  out.max_stack = 0;
+  const float* f2 = (const float*)b2.nodes.data();
+  auto code_of = [&](int ref) {
+    int c;
+    std::memcpy(&c, f2 + 16 * (size_t)(ref >> 1) + 12 + (ref & 1), 4);
+    return c;
+  };
+  auto area_of = [&](int ref) {
+    const float* b = f2 + 16 * (size_t)(ref >> 1) + 6 * (ref & 1);
+    float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+  };
+  // explicit DFS: a node's children are emitted (depth first) before its
+  // next sibling; `patch` is where the parent stores the child's index
+  struct Item {
+    int g2, acc, patch;
+  };
+  std::vector<Item> todo{{0, 0, -1}};
+  while (!todo.empty()) {
+    Item it = todo.back();
+    todo.pop_back();
+    const int me = (int)(out.nodes.size() / 8);
+    if (it.patch >= 0) std::memcpy((float*)out.nodes.data() + it.patch, &me, 4);
+    int refs[4] = {2 * it.g2, 2 * it.g2 + 1, -1, -1};
+    int nch = 2;
+    while (nch < 4) {
+      int best = -1;
+      float best_a = -1.f;
+      for (int k = 0; k < nch; ++k)
+        if (code_of(refs[k]) >= 0 && area_of(refs[k]) > best_a) {
+          best_a = area_of(refs[k]);
+          best = k;
+        }
+      if (best < 0) break;
+      const int c = code_of(refs[best]);
+      refs[best] = 2 * c;
+      refs[nch++] = 2 * c + 1;
+    }
+    const int acc = it.acc + nch - 1;
+    out.max_stack = std::max(out.max_stack, acc);
+    out.nodes.resize(8 * (size_t)(me + 1), make_float4(0.f, 0.f, 0.f, 0.f));
+    out.src.resize(4 * (size_t)(me + 1), -1);
+    float* f = (float*)&out.nodes[8 * (size_t)me];
+    std::vector<Item> kids;
+    for (int k = 0; k < 4; ++k) {
+      int child = kEmptyChild;
+      if (k < nch) {
+        const float* b = f2 + 16 * (size_t)(refs[k] >> 1) + 6 * (refs[k] & 1);
+        for (int a = 0; a < 3; ++a) {
+          f[4 * a + k] = b[a];
+          f[12 + 4 * a + k] = b[3 + a];
+        }
+        out.src[4 * (size_t)me + k] = refs[k];
+        child = code_of(refs[k]);
+        if (child >= 0) kids.push_back({child, acc, 8 * me * 4 + 24 + k});
+      }
+      std::memcpy(f + 24 + k, &child, 4);
+    }
+    // first child on top of the work stack, so it directly follows its parent
+    for (auto k = kids.rbegin(); k != kids.rend(); ++k) todo.push_back(*k);
+  }
 }
 
 }  // namespace adgi

@@ -86,4 +86,30 @@ hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_of
   return hipGetLastError();
 }
 
+// BVH4 child slot k of node n copies BVH2 child slot src = 2g + side.
+__global__ void bvh4_gather_kernel(float4* __restrict__ nodes4, const int32_t* __restrict__ src,
+                                   int num_slots, const float4* __restrict__ nodes2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= num_slots) return;
+  const int ref = src[q];
+  if (ref < 0) return;
+  const float* b = (const float*)(nodes2 + 4 * (size_t)(ref >> 1)) + 6 * (ref & 1);
+  float* f = (float*)(nodes4 + 8 * (size_t)(q >> 2));
+  const int k = q & 3;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    f[4 * a + k] = b[a];
+    f[12 + 4 * a + k] = b[3 + a];
+  }
+}
+
+hipError_t launch_bvh4_gather(float4* nodes4, const int32_t* src, int num_nodes4, const float4* nodes2,
+                              hipStream_t s) {
+  const int slots = 4 * num_nodes4;
+  if (slots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bvh4_gather_kernel, dim3((slots + 255) / 256), dim3(256), 0, s, nodes4, src, slots,
+                     nodes2);
+  return hipGetLastError();
+}
+
 }  // namespace adgi

@@ -8,9 +8,10 @@
 //     output the 10-bit codes of f_v = exp(-2t/s) (eq. ProbeVis) and
 //     f_r = min(lum, beta)/beta (Sec. 4.1.3).
 // Rays are handed out 64 at a time to waves from a global counter (persistent
-// work-stealing launch) or one per thread (plain launch). Traversal is a BVH2
-// while-while loop with a short per-lane stack in LDS (deeper entries in
-// private memory) and optionally the top nodes staged in LDS. Shadow rays of a
+// work-stealing launch) or one per thread (plain launch). Traversal is a
+// while-while loop over the BVH2 or its 4-wide collapse, with a short per-lane
+// stack in LDS (deeper entries in private memory); a few very large triangles
+// sit outside the tree and every ray tests them first. Shadow rays of a
 // wave's front-face hits are compacted with ballot/prefix into a wave-local
 // LDS queue and traced by all 64 lanes together.
 #include "adgi_internal.hpp"
@@ -19,19 +20,34 @@ namespace adgi {
 
 enum { KIND_PRIMARY = 0, KIND_PILOT = 1 };
 
+// Per-lane traversal stack: the first kStackLds entries in the wave's LDS
+// region (entry k of lane l at word 64k + l, so a wave's pushes at one depth
+// hit 64 consecutive words), deeper entries in private memory. The LDS
+// pointer is typed as LDS so the compiler emits ds_ instructions rather than
+// generic (flat) accesses.
+typedef __attribute__((address_space(3))) int lds_int;
+
 struct Stack {
-  int* lds;       // this lane's slot 0; entry k at lds[k * stride]
-  int stride;
+  lds_int* lds;   // this lane's entry 0
   int sp;
   int deep[kStackMax - kStackLds];
   __device__ __forceinline__ void push(int v) {
-    if (sp < kStackLds) lds[sp * stride] = v;
-    else deep[sp - kStackLds] = v;
+    if (sp < kStackLds) {
+      lds[sp << 6] = v;
+    } else {
+      deep[sp - kStackLds] = v;
+    }
     ++sp;
   }
   __device__ __forceinline__ int pop() {
     --sp;
-    return sp < kStackLds ? lds[sp * stride] : deep[sp - kStackLds];
+    int v;
+    if (sp < kStackLds) {
+      v = lds[sp << 6];
+    } else {
+      v = deep[sp - kStackLds];
+    }
+    return v;
   }
 };
 
@@ -40,10 +56,9 @@ struct NodeData {
   int left, right;
 };
 
-__device__ __forceinline__ NodeData fetch_node(const float4* __restrict__ nodes,
-                                               const float4* top, int ntop, int idx) {
+__device__ __forceinline__ NodeData fetch_node(const float4* __restrict__ nodes, int idx) {
   NodeData n;
-  const float4* src = idx < ntop ? top + 4 * idx : nodes + 4 * (size_t)idx;
+  const float4* src = nodes + 4 * (size_t)idx;
   n.a = src[0];
   n.b = src[1];
   n.c = src[2];
@@ -58,20 +73,55 @@ struct Work {
   uint32_t nodes = 0, tris = 0;
 };
 
+// The large triangles kept outside the tree (slots [0, num_big)): closest
+// hit over them, or whether any of them blocks (0, tmax].
+__device__ __forceinline__ void closest_big(const VolumeView& v, const Ray& ray, float& t_best, int& id_best,
+                                            int& slot_best, bool& front_best) {
+  const int nb = v.scene->num_big;
+  for (int k = 0; k < nb; ++k) {
+    const float4* tp = v.tris + 3 * (size_t)k;
+    float4 a = tp[0], b = tp[1], c = tp[2];
+    float t;
+    bool fr;
+    if (tri_hit(ray, a, b, c, 0.0f, t_best, t, fr)) {
+      int id = __float_as_int(a.w);
+      if (t < t_best || id < id_best) {
+        t_best = t;
+        id_best = id;
+        slot_best = k;
+        front_best = fr;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool any_big(const VolumeView& v, const Ray& ray, float tmax) {
+  const int nb = v.scene->num_big;
+  for (int k = 0; k < nb; ++k) {
+    const float4* tp = v.tris + 3 * (size_t)k;
+    float t;
+    bool fr;
+    if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
+  }
+  return false;
+}
+
 // Closest hit: smallest t in (0, inf); equal t resolves to the lowest
 // original triangle index. Returns the triangle slot or -1.
 template <bool COUNT>
-__device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, const Ray& ray,
+__device__ int closest_hit(const VolumeView& v, const Ray& ray,
                            Stack& st, float& t_best, bool& front_best, int& id_best, Work& w) {
   t_best = INFINITY;
   id_best = 0x7fffffff;
   int slot_best = -1;
   front_best = false;
+  closest_big(v, ray, t_best, id_best, slot_best, front_best);
+  if (COUNT) w.tris += v.scene->num_big;
   st.sp = 0;
   int node = 0;
   for (;;) {
     while (node >= 0) {
-      NodeData nd = fetch_node(v.nodes, top, ntop, node);
+      NodeData nd = fetch_node(v.nodes, node);
       if (COUNT) ++w.nodes;
       float tl, tr;
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, t_best, tl);
@@ -114,13 +164,15 @@ __device__ int closest_hit(const VolumeView& v, const float4* top, int ntop, con
 
 // Any hit on (0, tmax].
 template <bool COUNT>
-__device__ bool any_hit(const VolumeView& v, const float4* top, int ntop, const Ray& ray,
+__device__ bool any_hit(const VolumeView& v, const Ray& ray,
                         float tmax, Stack& st, Work& w) {
+  if (COUNT) w.tris += v.scene->num_big;
+  if (any_big(v, ray, tmax)) return true;
   st.sp = 0;
   int node = 0;
   for (;;) {
     while (node >= 0) {
-      NodeData nd = fetch_node(v.nodes, top, ntop, node);
+      NodeData nd = fetch_node(v.nodes, node);
       if (COUNT) ++w.nodes;
       float tl, tr;
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
@@ -132,6 +184,123 @@ __device__ bool any_hit(const VolumeView& v, const float4* top, int ntop, const 
         node = nd.left;
       } else if (hr) {
         node = nd.right;
+      } else {
+        if (st.sp == 0) return false;
+        node = st.pop();
+      }
+    }
+    int code = ~node;
+    int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+    for (int k = 0; k < count; ++k) {
+      const float4* tp = v.tris + 3 * (size_t)(first + k);
+      float t;
+      bool fr;
+      if (COUNT) ++w.tris;
+      if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
+    }
+    if (st.sp == 0) return false;
+    node = st.pop();
+  }
+}
+
+// ---- BVH4 traversal
+// Tests the four child boxes of node `idx` on (0, lim]. Returns the number of
+// boxes hit; the nearest child goes to `next`, the others are pushed farthest
+// first (so they pop nearest first). Empty slots never count as hits.
+__device__ __forceinline__ void order2(float& ka, int& ca, float& kb, int& cb) {
+  const bool sw = kb < ka;
+  const float k = sw ? kb : ka;
+  const int c = sw ? cb : ca;
+  kb = sw ? ka : kb;
+  cb = sw ? ca : cb;
+  ka = k;
+  ca = c;
+}
+
+__device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int idx, const Ray& ray,
+                                          float lim, Stack& st, int& next) {
+  const float4* src = nodes4 + 8 * (size_t)idx;
+  const float4 lx = src[0], ly = src[1], lz = src[2], hx = src[3], hy = src[4], hz = src[5], cf = src[6];
+  int c0 = __float_as_int(cf.x), c1 = __float_as_int(cf.y), c2 = __float_as_int(cf.z),
+      c3 = __float_as_int(cf.w);
+  float t0, t1, t2, t3;
+  const bool h0 = box_hit(ray, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, 0.0f, lim, t0) && c0 != kEmptyChild;
+  const bool h1 = box_hit(ray, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, 0.0f, lim, t1) && c1 != kEmptyChild;
+  const bool h2 = box_hit(ray, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, 0.0f, lim, t2) && c2 != kEmptyChild;
+  const bool h3 = box_hit(ray, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, 0.0f, lim, t3) && c3 != kEmptyChild;
+  // hits sort before misses: finite keys for hits, +inf for misses
+  float k0 = h0 ? fminf(t0, 3.0e38f) : INFINITY, k1 = h1 ? fminf(t1, 3.0e38f) : INFINITY;
+  float k2 = h2 ? fminf(t2, 3.0e38f) : INFINITY, k3 = h3 ? fminf(t3, 3.0e38f) : INFINITY;
+  order2(k0, c0, k1, c1);
+  order2(k2, c2, k3, c3);
+  order2(k0, c0, k2, c2);
+  order2(k1, c1, k3, c3);
+  order2(k1, c1, k2, c2);
+  const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+  if (nh >= 4) st.push(c3);
+  if (nh >= 3) st.push(c2);
+  if (nh >= 2) st.push(c1);
+  next = c0;
+  return nh;
+}
+
+template <bool COUNT>
+__device__ int closest_hit4(const VolumeView& v, const Ray& ray, Stack& st, float& t_best, bool& front_best,
+                            int& id_best, Work& w) {
+  t_best = INFINITY;
+  id_best = 0x7fffffff;
+  int slot_best = -1;
+  front_best = false;
+  closest_big(v, ray, t_best, id_best, slot_best, front_best);
+  if (COUNT) w.tris += v.scene->num_big;
+  st.sp = 0;
+  int node = 0;
+  for (;;) {
+    while (node >= 0) {
+      if (COUNT) ++w.nodes;
+      int next;
+      if (node4_step(v.nodes4, node, ray, t_best, st, next) > 0) {
+        node = next;
+      } else {
+        if (st.sp == 0) return slot_best;
+        node = st.pop();
+      }
+    }
+    int code = ~node;
+    int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+    if (COUNT) w.tris += count;
+    for (int k = 0; k < count; ++k) {
+      const float4* tp = v.tris + 3 * (size_t)(first + k);
+      float4 a = tp[0], b = tp[1], c = tp[2];
+      float t;
+      bool fr;
+      if (tri_hit(ray, a, b, c, 0.0f, t_best, t, fr)) {
+        int id = __float_as_int(a.w);
+        if (t < t_best || id < id_best) {
+          t_best = t;
+          id_best = id;
+          slot_best = first + k;
+          front_best = fr;
+        }
+      }
+    }
+    if (st.sp == 0) return slot_best;
+    node = st.pop();
+  }
+}
+
+template <bool COUNT>
+__device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack& st, Work& w) {
+  if (COUNT) w.tris += v.scene->num_big;
+  if (any_big(v, ray, tmax)) return true;
+  st.sp = 0;
+  int node = 0;
+  for (;;) {
+    while (node >= 0) {
+      if (COUNT) ++w.nodes;
+      int next;
+      if (node4_step(v.nodes4, node, ray, tmax, st, next) > 0) {
+        node = next;
       } else {
         if (st.sp == 0) return false;
         node = st.pop();
@@ -168,8 +337,8 @@ __device__ __forceinline__ float3 probe_position(const VolumeView& v, int i) {
                      fmaf((float)z, v.sz, v.oz));
 }
 
-template <int KIND, bool COUNT>
-__device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Stack& st,
+template <int KIND, bool COUNT, bool W4>
+__device__ void trace_wave(const VolumeView& v, Stack& st,
                            uint16_t* queue, uint32_t* vis, uint32_t base, uint32_t total) {
   const FrameParams& fp = *v.fp;
   const SceneParams& sc = *v.scene;
@@ -199,7 +368,8 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
   Work w;
   if (active && sc.num_tris > 0) {
     Ray ray = make_ray(o, d);
-    slot = closest_hit<COUNT>(v, top, ntop, ray, st, t, front, id, w);
+    slot = W4 ? closest_hit4<COUNT>(v, ray, st, t, front, id, w)
+              : closest_hit<COUNT>(v, ray, st, t, front, id, w);
     if (slot < 0) {
       id = -1;
       t = INFINITY;
@@ -247,7 +417,8 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
       float len = sqrtf(gx * gx + gy * gy + gz * gz);
       float il = 1.0f / len;
       Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
-      bool blocked = any_hit<COUNT>(v, top, ntop, sray, len * (1.0f - kShadowShorten), st, w);
+      const float smax = len * (1.0f - kShadowShorten);
+      bool blocked = W4 ? any_hit4<COUNT>(v, sray, smax, st, w) : any_hit<COUNT>(v, sray, smax, st, w);
       if (!blocked) atomicOr(&vis[src], 1u << l);
     }
   }
@@ -307,20 +478,18 @@ __device__ void trace_wave(const VolumeView& v, const float4* top, int ntop, Sta
   }
 }
 
-template <int KIND, bool COUNT>
-__global__ void trace_kernel(VolumeView v, int persistent, int ntop) {
-  extern __shared__ float4 smem[];
-  float4* top = smem;                                            // ntop * 4
-  int* stack_base = (int*)(smem + 4 * ntop);                     // kStackLds * blockDim
+// Eight waves per SIMD (64 VGPRs): traversal is bound by memory latency, so
+// occupancy pays for the few registers the compiler then keeps in scratch.
+template <int KIND, bool COUNT, bool W4>
+__global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_kernel(VolumeView v, int persistent) {
+  extern __shared__ int smem[];
+  int* stack_base = smem;                                        // kStackLds * blockDim
   uint16_t* queues = (uint16_t*)(stack_base + kStackLds * blockDim.x);  // waves * 64 * kMaxLights
   const int nwaves = blockDim.x >> 6;
   uint32_t* vis_all = (uint32_t*)(queues + nwaves * 64 * kMaxLights);   // waves * 64
-  for (int k = threadIdx.x; k < 4 * ntop; k += blockDim.x) top[k] = v.nodes[k];
-  __syncthreads();
   const int wave = threadIdx.x >> 6;
   Stack st;
-  st.lds = stack_base + threadIdx.x;
-  st.stride = blockDim.x;
+  st.lds = (lds_int*)stack_base + wave * (64 * kStackLds) + lane_id();
   st.sp = 0;
   uint16_t* queue = queues + wave * 64 * kMaxLights;
   uint32_t* vis = vis_all + wave * 64;
@@ -332,31 +501,38 @@ __global__ void trace_kernel(VolumeView v, int persistent, int ntop) {
       if (lane_id() == 0) base = atomicAdd(counter, 64u);
       base = __shfl(base, 0);
       if (base >= total) break;
-      trace_wave<KIND, COUNT>(v, top, ntop, st, queue, vis, base, total);
+      trace_wave<KIND, COUNT, W4>(v, st, queue, vis, base, total);
     }
   } else {
     uint32_t base = (blockIdx.x * blockDim.x) + (uint32_t)wave * 64u;
-    if (base < total) trace_wave<KIND, COUNT>(v, top, ntop, st, queue, vis, base, total);
+    if (base < total) trace_wave<KIND, COUNT, W4>(v, st, queue, vis, base, total);
   }
 }
 
-size_t trace_lds_bytes(int block, int ntop) {
-  return (size_t)ntop * 64 + (size_t)kStackLds * block * 4 + (size_t)(block / 64) * 64 * kMaxLights * 2 +
-         (size_t)(block / 64) * 64 * 4;
+size_t trace_lds_bytes(int block) {
+  return (size_t)kStackLds * block * 4 + (size_t)(block / 64) * 64 * kMaxLights * 2 + (size_t)(block / 64) * 64 * 4;
 }
 
-hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
-                        int grid, int ntop, bool count) {
-  size_t lds = trace_lds_bytes(block, ntop);
-  const int pers = persistent ? 1 : 0;
+template <bool W4>
+static void launch_trace_w(const VolumeView& v, hipStream_t s, bool pilot, int pers, int block, int grid,
+                           bool count) {
+  const size_t lds = trace_lds_bytes(block);
   if (pilot && count)
-    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, true>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
+    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
   else if (pilot)
-    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, false>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
+    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
   else if (count)
-    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, true>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
+    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
   else
-    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, false>), dim3(grid), dim3(block), lds, s, v, pers, ntop);
+    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
+}
+
+hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block, int grid,
+                        bool count, bool w4) {
+  if (w4)
+    launch_trace_w<true>(v, s, pilot, persistent ? 1 : 0, block, grid, count);
+  else
+    launch_trace_w<false>(v, s, pilot, persistent ? 1 : 0, block, grid, count);
   return hipGetLastError();
 }
 

@@ -146,6 +146,10 @@ struct adgi_volume {
   std::vector<int32_t> level_offsets;
   hipGraphExec_t refit_exec = nullptr;
   float4* d_nodes = nullptr;
+  float4* d_nodes4 = nullptr;   // BVH4 collapse (null when its stack bound does not fit)
+  int32_t* d_src4 = nullptr;    // BVH4 slot -> BVH2 slot, for the refit gather
+  int32_t num_nodes4 = 0;
+  int32_t num_big = 0;          // large triangles kept outside the tree
   float4* d_tris = nullptr;
   float4* d_albedo = nullptr;
   std::vector<void*> scene_allocs;
@@ -201,8 +205,8 @@ void drop_graphs(adgi_volume* vol) {
     }
 }
 
-int lds_top_nodes(const adgi_volume* vol) {
-  return std::min(vol->tun.lds_top_nodes, vol->num_nodes);
+bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
+  return t.bvh_width == 4 && vol->d_nodes4 != nullptr;
 }
 
 // Stage boundaries recorded into ev[0..6] when ev is non-null (eager only):
@@ -213,7 +217,7 @@ hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullp
   VolumeView& v = vol->v;
   hipStream_t s = vol->stream;
   hipError_t e;
-  const int ntop = lds_top_nodes(vol);
+  const bool w4 = use_bvh4(vol, t);
   const int pgrid = std::max(1, vol->num_cus * t.trace_waves_per_cu / (t.trace_block / 64));
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
   if ((e = mark(0)) != hipSuccess) return e;
@@ -221,7 +225,8 @@ hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullp
   if ((e = mark(1)) != hipSuccess) return e;
   if (adaptive) {
     int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
-    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, ntop)) != hipSuccess) return e;
+    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
+      return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_detect(v, s)) != hipSuccess) return e;
     if ((e = mark(3)) != hipSuccess) return e;
@@ -236,7 +241,7 @@ hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullp
   if (count_work && (e = launch_frame_begin(v, s)) != hipSuccess) return e;
   int grid = t.persistent ? pgrid
                           : (int)((vol->desc.max_rays_per_frame + t.trace_block - 1) / t.trace_block);
-  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, ntop, count_work)) != hipSuccess)
+  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, count_work, w4)) != hipSuccess)
     return e;
   if ((e = mark(5)) != hipSuccess) return e;
   if (count_work) return hipSuccess;
@@ -272,6 +277,10 @@ void free_scene(adgi_volume* vol) {
   vol->d_idx = vol->d_order = vol->d_levels = nullptr;
   vol->level_offsets.clear();
   vol->d_nodes = vol->d_tris = vol->d_albedo = nullptr;
+  vol->d_nodes4 = nullptr;
+  vol->d_src4 = nullptr;
+  vol->num_nodes4 = 0;
+  vol->v.nodes4 = nullptr;
   if (vol->h_stage) {
     (void)hipHostFree(vol->h_stage);
     vol->h_stage = nullptr;
@@ -302,11 +311,11 @@ adgi_tuning default_tuning() {
   adgi_tuning t;
   t.use_graph = 1;
   t.persistent = 1;
-  t.trace_block = 256;
-  t.trace_waves_per_cu = 16;
+  t.trace_block = 64;
+  t.trace_waves_per_cu = 32;
   t.blend_chunk = 256;
-  t.lds_top_nodes = 0;
   t.blend_blocks_per_cu = 16;
+  t.bvh_width = 2;
   return t;
 }
 
@@ -315,8 +324,8 @@ bool tuning_valid(const adgi_tuning& t) {
          t.trace_block >= 64 && t.trace_block <= 1024 && t.trace_block % 64 == 0 &&
          t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 &&
          (t.blend_chunk == 0 || (t.blend_chunk >= 64 && t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0)) &&
-         t.lds_top_nodes >= 0 && t.lds_top_nodes <= 1024 && t.blend_blocks_per_cu >= 1 &&
-         t.blend_blocks_per_cu <= 32;
+         t.blend_blocks_per_cu >= 1 && t.blend_blocks_per_cu <= 32 &&
+         (t.bvh_width == 2 || t.bvh_width == 4);
 }
 
 }  // namespace
@@ -561,6 +570,9 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
       return fail(ADGI_ERR_INVALID_ARG, "BVH build failed: %s", err);
     vol->last_build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    Bvh4Host bvh4;
+    collapse_bvh4(bvh, bvh4);
+    const bool fits4 = bvh4.max_stack <= kStackMax;
     HIP_TRY(vol, hipStreamSynchronize(vol->stream));
     drop_graphs(vol);
     free_scene(vol);
@@ -574,8 +586,12 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
     vol->d_nodes = (float4*)vol_alloc(vol, bvh.nodes.size() * 16, &g);
     vol->d_tris = (float4*)vol_alloc(vol, std::max<size_t>(bvh.tris.size(), 3) * 16, &g);
     vol->d_albedo = (float4*)vol_alloc(vol, (size_t)std::max(nt, 1) * 16, &g);
+    if (fits4) {
+      vol->d_nodes4 = (float4*)vol_alloc(vol, bvh4.nodes.size() * 16, &g);
+      vol->d_src4 = (int32_t*)vol_alloc(vol, bvh4.src.size() * 4, &g);
+    }
     if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_nodes ||
-        !vol->d_tris || !vol->d_albedo) {
+        !vol->d_tris || !vol->d_albedo || (fits4 && (!vol->d_nodes4 || !vol->d_src4))) {
       free_scene(vol);
       vol->has_scene = false;
       return fail(ADGI_ERR_OUT_OF_MEMORY, "allocator returned NULL for the scene");
@@ -595,19 +611,28 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
     vol->level_offsets = bvh.level_offsets;
     HIP_TRY(vol, hipMemcpy(vol->d_nodes, bvh.nodes.data(), bvh.nodes.size() * 16, hipMemcpyHostToDevice));
     HIP_TRY(vol, hipMemcpy(vol->d_albedo, alb.data(), alb.size() * 16, hipMemcpyHostToDevice));
+    if (fits4) {
+      HIP_TRY(vol, hipMemcpy(vol->d_nodes4, bvh4.nodes.data(), bvh4.nodes.size() * 16, hipMemcpyHostToDevice));
+      HIP_TRY(vol, hipMemcpy(vol->d_src4, bvh4.src.data(), bvh4.src.size() * 4, hipMemcpyHostToDevice));
+      vol->num_nodes4 = (int32_t)(bvh4.nodes.size() / 8);
+    }
     vol->nv = nv;
     vol->nt = nt;
     vol->num_nodes = nn;
     vol->pad_abs = pad_abs;
     vol->bvh_depth = bvh.depth;
     vol->v.nodes = vol->d_nodes;
+    vol->v.nodes4 = vol->d_nodes4;
     vol->v.tris = vol->d_tris;
     vol->v.albedo = vol->d_albedo;
     hp.num_nodes = nn;
+    hp.num_big = bvh.num_big;
+    vol->num_big = bvh.num_big;
     HIP_TRY(vol, hipHostMalloc((void**)&vol->h_stage, std::max<size_t>((size_t)nv * 12, 16), hipHostMallocDefault));
     vol->h_stage_floats = (size_t)nv * 3;
   } else {
     hp.num_nodes = vol->num_nodes;
+    hp.num_big = vol->num_big;
     const size_t cnt = (size_t)(ve - vb) * 3;
     if (cnt) {
       std::memcpy(vol->h_stage + 3 * vb, sc->positions + 3 * vb, cnt * 4);
@@ -620,6 +645,8 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
         hipGraph_t graph = nullptr;
         HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
         hipError_t e = launch_refit(r, vol->level_offsets, vol->stream);
+        if (e == hipSuccess && vol->d_nodes4)
+          e = launch_bvh4_gather(vol->d_nodes4, vol->d_src4, vol->num_nodes4, vol->d_nodes, vol->stream);
         hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
           if (graph) (void)hipGraphDestroy(graph);
@@ -800,7 +827,7 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
     return fail(ADGI_ERR_INVALID_ARG, "blend_chunk 0 (wave kernel) needs tiles 8/16 or 16/16");
   size_t lds = t->blend_chunk ? blend_lds_bytes(vol->v, t->blend_chunk) : 0;
   if (lds > 65536) return fail(ADGI_ERR_INVALID_ARG, "blend_chunk needs %zu bytes of LDS", lds);
-  if (trace_lds_bytes(t->trace_block, t->lds_top_nodes) > 65536)
+  if (trace_lds_bytes(t->trace_block) > 65536)
     return fail(ADGI_ERR_INVALID_ARG, "trace LDS over 64 KiB");
   HIP_TRY(vol, hipStreamSynchronize(vol->stream));
   drop_graphs(vol);
@@ -890,6 +917,7 @@ adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* 
   out->primary_rays = total;
   out->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
   out->node_tests = (int64_t)vol->h_stats->node_tests;
+  out->box_tests = out->node_tests * (use_bvh4(vol, vol->tun) ? 4 : 2);
   out->tri_tests = (int64_t)vol->h_stats->tri_tests;
   return adgi_restore_state(vol, snap.data(), snap.size());
 }
@@ -947,14 +975,15 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   hipStream_t s = vol->stream;
   auto time_trace = [&](const adgi_tuning& c, float& best) -> hipError_t {
     best = INFINITY;
-    const int ntop = std::min(c.lds_top_nodes, vol->num_nodes);
     const int grid = c.persistent ? std::max(1, vol->num_cus * c.trace_waves_per_cu / (c.trace_block / 64))
                                   : (int)((vol->desc.max_rays_per_frame + c.trace_block - 1) / c.trace_block);
     for (int rep = 0; rep < 3; ++rep) {
       hipError_t e;
       if ((e = launch_frame_begin(vol->v, s)) != hipSuccess) return e;
       if ((e = hipEventRecord(vol->ev_t0, s)) != hipSuccess) return e;
-      if ((e = launch_trace(vol->v, s, false, c.persistent != 0, c.trace_block, grid, ntop)) != hipSuccess) return e;
+      if ((e = launch_trace(vol->v, s, false, c.persistent != 0, c.trace_block, grid, false, use_bvh4(vol, c))) !=
+          hipSuccess)
+        return e;
       if ((e = hipEventRecord(vol->ev_t1, s)) != hipSuccess) return e;
       if ((e = hipEventSynchronize(vol->ev_t1)) != hipSuccess) return e;
       float ms = 0.f;
@@ -967,17 +996,17 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   float best_ms = INFINITY;
   hipError_t err = hipSuccess;
   const int blocks[] = {64, 128, 256};
-  const int waves[] = {8, 16, 24};
-  const int tops[] = {0, 256};
-  for (int b : blocks)
-    for (int w : waves)
-      for (int top : tops) {
+  const int waves[] = {16, 24, 32};
+  const int widths[] = {4, 2};
+  for (int width : widths)
+    for (int b : blocks)
+      for (int w : waves) {
         adgi_tuning c = saved;
         c.persistent = 1;
+        c.bvh_width = width;
         c.trace_block = b;
         c.trace_waves_per_cu = w;
-        c.lds_top_nodes = top;
-        if (trace_lds_bytes(b, top) > 65536) continue;
+        if (width == 4 && !vol->d_nodes4) continue;
         float ms;
         if ((err = time_trace(c, ms)) != hipSuccess) break;
         if (ms < best_ms) {

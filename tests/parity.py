@@ -28,6 +28,26 @@ def rel_err(g: np.ndarray, o: np.ndarray, per_probe_axis: int = 0) -> np.ndarray
     return np.abs(g - o) / den
 
 
+def f16_quantum(o) -> np.ndarray:
+    """Spacing of binary16 values at |o|: 2^-24 below 2^-14 (subnormals),
+    else 2^(floor(log2 |o|) - 10)."""
+    a = np.abs(np.asarray(o, np.float64))
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -14)))
+    return np.where(a < 2.0 ** -14, 2.0 ** -24, 2.0 ** (e - 10))
+
+
+def texel_error_report(gi, gd, oi, od) -> dict:
+    """Per-texel relative error distribution (same floor as the parity bar)."""
+    out = {}
+    for name, g, o in (("irradiance", gi, oi), ("depth", gd, od)):
+        e = rel_err(g, o).ravel()
+        out[name] = {"texels": int(e.size), "max": float(e.max(initial=0.0)),
+                     "p99": float(np.percentile(e, 99)) if e.size else 0.0,
+                     "p50": float(np.percentile(e, 50)) if e.size else 0.0,
+                     "mean": float(e.mean()) if e.size else 0.0}
+    return out
+
+
 def gpu_scene_update(vol, scene, frame):
     if scene.anim_vertices and frame > 0:
         vol.update_scene(scene.positions_at(frame), light_pos=scene.light_positions(frame),
@@ -42,7 +62,10 @@ def gpu_scene_update(vol, scene, frame):
 def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget: int = 0,
                  n_min: int = 8, n_max: int = 2048, probes=None, storage=adgi.ADGI_FP32,
                  seed: int = 0x5EED, max_rays=None, tuning=None, check_rays: bool = True,
-                 use_bvh: bool = True) -> dict:
+                 use_bvh: bool = True, fp64_twin: bool = False) -> dict:
+    """``fp64_twin`` also runs an oracle that keeps its texels in FP64 (no
+    binary16 rounding at the frame store), fed the same tie decisions, and
+    returns per-texel error distributions against it."""
     P = scene.num_probes
     if max_rays is None:
         max_rays = max(budget, P * n_uniform, 1)
@@ -52,6 +75,8 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
     fp16 = storage == adgi.ADGI_FP16
     ora = oracle.OracleVolume(scene, seed=seed, fp16=fp16, probes=probes, use_bvh=use_bvh)
     sel = ora.probes
+    twin = (oracle.OracleVolume(scene, seed=seed, fp16=False, probes=probes, use_bvh=use_bvh)
+            if fp64_twin else None)
     res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "max_rel_ray": 0.0,
            "ties": {}, "frames": frames, "rays": 0, "count_mismatch": 0, "score_mismatch": 0,
            "alloc_mismatch": 0, "rotation_mismatch": 0, "max_rel_t": 0.0}
@@ -69,6 +94,9 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
                  "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
         out = ora.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
                          n_uniform=n_uniform, hints=hints, keep_rays=check_rays)
+        if twin is not None:
+            twin.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
+                        n_uniform=n_uniform, hints=hints)
         c = out["counts"]
         mism = c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"]
         if adaptive:
@@ -84,8 +112,20 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
         gd = rb["depth"][sel]
         oi = ora.irradiance_tiles()
         od = ora.depth_tiles()
-        res["max_rel_irr"] = max(res["max_rel_irr"], float(rel_err(gi, oi).max(initial=0.0)))
-        res["max_rel_depth"] = max(res["max_rel_depth"], float(rel_err(gd, od).max(initial=0.0)))
+        ei, ed = rel_err(gi, oi), rel_err(gd, od)
+        if fp16:
+            # Both sides round to binary16 at the frame store, the GPU from FP32 and
+            # the oracle from FP64: a value within rounding distance of a binary16
+            # midpoint may land one quantum apart (a rounding tie). One quantum is
+            # below the relative bar for normal halves, above it only for subnormal
+            # ones, so such texels are counted here and excluded from the maximum.
+            qi = np.abs(gi.astype(np.float64) - oi) <= f16_quantum(oi)
+            qd = np.abs(gd.astype(np.float64) - od) <= f16_quantum(od)
+            res["f16_quantum_ties"] = res.get("f16_quantum_ties", 0) + \
+                int(np.count_nonzero(qi & (ei > 0))) + int(np.count_nonzero(qd & (ed > 0)))
+            ei, ed = np.where(qi, 0.0, ei), np.where(qd, 0.0, ed)
+        res["max_rel_irr"] = max(res["max_rel_irr"], float(ei.max(initial=0.0)))
+        res["max_rel_depth"] = max(res["max_rel_depth"], float(ed.max(initial=0.0)))
         ri, rd = scene_res(vol)
         cnt_i = rb["irr_count"][sel].reshape(len(sel), -1)
         cnt_d = rb["depth_count"][sel].reshape(len(sel), -1)
@@ -119,6 +159,14 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
                 res["max_rel_ray"] = float(e[k])
                 res["worst_ray"] = {"gpu": g[k].tolist(), "oracle": o[k].tolist(),
                                     "tri": int(out["tri"][k]), "frame": f}
+    res["vs_oracle"] = texel_error_report(rb["irradiance"][sel], rb["depth"][sel],
+                                          ora.irradiance_tiles(), ora.depth_tiles())
+    res["mean_count"] = {"irradiance": float(ora.irr_n.mean()), "depth": float(ora.dep_n.mean())}
+    if twin is not None:
+        res["vs_fp64"] = texel_error_report(rb["irradiance"][sel], rb["depth"][sel],
+                                            twin.irradiance_tiles(), twin.depth_tiles())
+        res["oracle_vs_fp64"] = texel_error_report(ora.irradiance_tiles(), ora.depth_tiles(),
+                                                   twin.irradiance_tiles(), twin.depth_tiles())
     res["irr_gpu"] = rb["irradiance"][sel]
     res["irr_oracle"] = ora.irradiance_tiles()
     res["oracle_counts"] = ora.counts.as_dict()

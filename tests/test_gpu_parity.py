@@ -1,4 +1,7 @@
 """GPU vs. oracle parity through the C ABI (needs an MI355X)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -63,15 +66,53 @@ def test_tunnel_adaptive_lockstep():
     _assert_parity(res)
 
 
+def _report(name, res):
+    """Writes the texel error distributions to $ADGI_REPORT_DIR/<name>.json."""
+    d = os.environ.get("ADGI_REPORT_DIR")
+    if not d:
+        return
+    os.makedirs(d, exist_ok=True)
+    keep = {k: v for k, v in res.items() if not isinstance(v, np.ndarray) and k != "stats_last"}
+    with open(os.path.join(d, name + ".json"), "w") as f:
+        json.dump(keep, f, indent=1, default=str)
+
+
 def test_box_field_sampled_probes_with_refit():
     """1M-triangle box field, 65,536 probes, B = 2^23, n in [8, 2048], animated
-    boxes refit on the device every frame; 128 sampled probes, three frames."""
+    boxes refit on the device every frame; 512 sampled probes, four frames
+    (FP32 texels: the companion of the FP16 run below)."""
     sc = scenes.box_field()
-    probes = scenes.sample_probes(sc.num_probes, 128)
-    res = run_lockstep(sc, frames=3, adaptive=True, budget=1 << 23, n_min=8, n_max=2048,
+    probes = scenes.sample_probes(sc.num_probes, 512)
+    res = run_lockstep(sc, frames=4, adaptive=True, budget=1 << 23, n_min=8, n_max=2048,
                        probes=probes)
     print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _report("box_field_fp32", res)
     _assert_parity(res)
+
+
+def test_box_field_fp16_storage_report():
+    """Box field as above with FP16 texel storage (FP32 arithmetic, RNE store
+    at the end of each frame), 512 sampled probes, four frames: <= 2e-3 against
+    the FP16-emulating oracle; the per-texel error against an oracle that keeps
+    FP64 texels is reported, not bounded (binary16 stagnation can exceed 2e-3
+    once the moving average saturates)."""
+    import paper_2301_05125_amd as adgi
+    sc = scenes.box_field()
+    probes = scenes.sample_probes(sc.num_probes, 512)
+    res = run_lockstep(sc, frames=4, adaptive=True, budget=1 << 23, n_min=8, n_max=2048,
+                       probes=probes, storage=adgi.ADGI_FP16, fp64_twin=True)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _report("box_field_fp16", res)
+    # Texels one binary16 quantum apart: the FP32 and FP64 values straddle a
+    # rounding midpoint. They differ by a few FP32 roundings (~3 x 2^-24
+    # relative) and midpoints are 2^-10 apart, so about 2 x 3 x 2^-24 / 2^-10
+    # ~ 4e-4 of the stores are expected to straddle; the bar is 2e-3.
+    texels = res["vs_oracle"]["irradiance"]["texels"] + res["vs_oracle"]["depth"]["texels"]
+    assert res.get("f16_quantum_ties", 0) <= 2e-3 * texels * res["frames"], res
+    assert res["mismatches"] == 0 and res["count_mismatch"] == 0, res
+    assert res["alloc_mismatch"] == 0 and res["score_mismatch"] == 0, res
+    assert res["max_rel_irr"] <= 2e-3 and res["max_rel_depth"] <= 2e-3, res
+    assert res["max_rel_ray"] <= RAY_RGB_TOL and res["max_rel_t"] <= RAY_T_TOL, res
 
 
 def test_fp16_storage_against_fp16_emulating_oracle():

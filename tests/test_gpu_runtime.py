@@ -48,9 +48,12 @@ def test_bitwise_determinism_across_runs():
     {"use_graph": 0},
     {"persistent": 0},
     {"trace_block": 64, "trace_waves_per_cu": 8},
-    {"trace_block": 128, "lds_top_nodes": 256},
+    {"trace_block": 256, "trace_waves_per_cu": 16},
     {"blend_chunk": 64},
     {"blend_chunk": 512},
+    {"bvh_width": 2},
+    {"bvh_width": 2, "persistent": 0},
+    {"bvh_width": 2, "trace_block": 128},
 ])
 def test_launch_shape_does_not_change_results(tuning):
     sc = _small_field()
