@@ -185,6 +185,50 @@ def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
             "seconds": wall}
 
 
+def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=4):
+    """Serving mix: 32 streams (box fields of 10k-500k triangles, 512-32768
+    probes, B = 128 rays per probe), Poisson arrivals at 30-120 Hz each, for
+    duration_s of wall time, under an HBM admission budget of budget_frac of
+    the streams' summed device footprints."""
+    import scenes
+    streams = scenes.serving_streams(duration_s=duration_s)
+    srv = adgi.Server(hbm_budget_bytes=1 << 40, max_inflight=max_inflight)
+    t0 = time.perf_counter()
+    sids = [srv.add_stream(st.scene, budget=st.budget, seed=1000 + k) for k, st in enumerate(streams)]
+    setup_s = time.perf_counter() - t0
+    foot = [srv.stream_info(sid)["footprint_bytes"] for sid in sids]
+    budget = max(int(budget_frac * sum(foot)), max(foot))
+    srv.set_budget(budget)
+    print(f"[bench] serving: {len(sids)} streams added in {setup_s:.1f}s, footprints "
+          f"{sum(foot) / 2**30:.2f} GiB, budget {budget / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    events = sorted((float(t), k) for k, st in enumerate(streams) for t in st.arrivals)
+    nframe = [0] * len(streams)
+    start = srv.now_ns() + 20_000_000
+    for t, k in events:
+        target = start + int(t * 1e9)
+        while srv.now_ns() < target:
+            srv.progress()
+        srv.submit(sids[k], streams[k].scene.light_positions(nframe[k]), arrival_ns=target)
+        nframe[k] += 1
+        srv.progress()
+    srv.drain()
+    st = srv.stats()
+    offered = sum(s.rate_hz * s.budget for s in streams)
+    out = {"streams": len(sids), "duration_s": duration_s, "requests": st["submitted"],
+           "completed": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+           "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+           "rays_per_s": st["primary_rays"] / max(st["span_s"], 1e-9),
+           "offered_rays_per_s": offered, "admissions": st["admissions"],
+           "evictions": st["evictions"], "admit_ms_total": st["admit_ms"],
+           "evict_ms_total": st["evict_ms"], "hbm_budget_bytes": budget,
+           "sum_footprint_bytes": sum(foot), "peak_resident_bytes": st["peak_resident_bytes"],
+           "max_inflight": max_inflight, "setup_s": setup_s,
+           "triangles": [int(s.scene.num_triangles) for s in streams],
+           "probes": [int(s.scene.num_probes) for s in streams]}
+    srv.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +242,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="JSON launch tuning to use instead of the autotuner")
     ap.add_argument("--skip-uniform", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the 32-stream serving mix")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -308,6 +354,9 @@ def main():
         "scene_build_s": build_s,
     }
     vol.destroy_volume()
+    if not args.no_serve:
+        out["serving"] = run_serving(adgi, duration_s=args.serve_seconds)
+        print(f"[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, cfg["budget"], cfg["n_min"], cfg["n_max"])

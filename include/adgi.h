@@ -239,6 +239,67 @@ adgi_status adgi_restore_state(adgi_volume* vol, const void* host_src, size_t by
 /* Device bytes the volume holds now (state + scene + frame buffers). */
 size_t adgi_device_bytes(const adgi_volume* vol);
 
+/* ---- serving: many volumes on one GPU -------------------------------------
+ * A server holds streams; each stream is one probe volume with its own scene,
+ * grid, budget and frame parameters (adaptive frames only). A request asks
+ * for the stream's next frame with that frame's light positions. Requests are
+ * dispatched in arrival order, at most one frame of a stream and at most
+ * max_inflight frames in total at a time, each volume on its own HIP stream.
+ * Resident streams are served first. HBM admission: a stream's volume is
+ * resident only while the device bytes of all resident volumes stay within
+ * hbm_budget_bytes; to admit one, idle resident streams with nothing waiting
+ * are evicted, least recently used first (a request waiting over 250 ms may
+ * also evict idle streams resident for over 500 ms). Eviction moves the
+ * temporal state to host memory and frees all the volume's device memory;
+ * re-admission rebuilds the volume from the BVH the server built once per
+ * stream and restores the state, so a stream's results are bitwise those it
+ * would have alone. The server is not thread-safe; its
+ * own errors are described by adgi_server_last_error (volume errors by
+ * adgi_last_error). The scene arrays of adgi_server_add_stream are copied. */
+typedef struct adgi_server adgi_server;
+typedef struct {
+  int64_t hbm_budget_bytes;   /* > 0: device bytes of resident volumes, at most */
+  int32_t max_inflight;       /* 1..64: frames in flight across all streams      */
+  int32_t reserved;
+} adgi_server_desc;
+typedef struct {
+  adgi_volume_desc volume;
+  adgi_scene_desc scene;      /* REBUILD description; light_pos = initial lights */
+  adgi_update_params params;  /* adaptive = 1; frame and sync are set per request */
+} adgi_stream_desc;
+typedef struct {
+  int64_t submitted, completed, admissions, evictions;
+  int64_t primary_rays;       /* budget of every completed frame                  */
+  int64_t resident_bytes, peak_resident_bytes;
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival -> frame done on the GPU   */
+  double span_s;              /* first arrival -> last completion                 */
+  double admit_ms, evict_ms;  /* host time spent admitting and evicting          */
+} adgi_server_stats;
+
+int64_t adgi_server_now_ns(void);  /* steady clock used for arrival stamps        */
+const char* adgi_server_last_error(void);
+adgi_status adgi_server_create(const adgi_server_desc* desc, const adgi_allocator* alloc, adgi_server** out);
+/* Builds the stream's BVH on the host and measures its device footprint with
+ * one dry frame; the stream starts evicted with zero state at frame 0.
+ * ADGI_ERR_OUT_OF_MEMORY if the footprint alone exceeds the budget. */
+adgi_status adgi_server_add_stream(adgi_server* s, const adgi_stream_desc* d, int32_t* stream_id);
+adgi_status adgi_server_set_budget(adgi_server* s, int64_t hbm_budget_bytes);
+adgi_status adgi_server_stream_info(const adgi_server* s, int32_t stream_id, int64_t* footprint_bytes,
+                                    int32_t* resident, int32_t* frames_done);
+/* light_pos: [num_lights][3] for this frame (copied); arrival_ns on the
+ * adgi_server_now_ns clock (latency is measured from it). */
+adgi_status adgi_server_submit(adgi_server* s, int32_t stream_id, const float* light_pos, int64_t arrival_ns);
+/* Non-blocking: retires finished frames, admits/evicts, dispatches. */
+adgi_status adgi_server_progress(adgi_server* s, int32_t* completed_now);
+/* Blocks until every submitted request is done. */
+adgi_status adgi_server_drain(adgi_server* s);
+adgi_status adgi_server_get_stats(const adgi_server* s, adgi_server_stats* out);
+/* Per-request latencies (ms) in completion order; count = all recorded. */
+adgi_status adgi_server_latencies(const adgi_server* s, double* out_ms, int64_t capacity, int64_t* count);
+/* Readback of an idle stream (admitted first if evicted). */
+adgi_status adgi_server_read_stream(adgi_server* s, int32_t stream_id, adgi_probe_readback* rb);
+void adgi_server_destroy(adgi_server* s);
+
 #ifdef __cplusplus
 }
 #endif

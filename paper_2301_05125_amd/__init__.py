@@ -24,6 +24,8 @@ ADGI_OK = 0
 STATUS = {0: "ADGI_OK", -1: "ADGI_ERR_INVALID_ARG", -2: "ADGI_ERR_OUT_OF_MEMORY",
           -3: "ADGI_ERR_BUDGET", -4: "ADGI_ERR_NO_SCENE", -5: "ADGI_ERR_TOPOLOGY",
           -6: "ADGI_ERR_DEVICE"}
+(ADGI_ERR_INVALID_ARG, ADGI_ERR_OUT_OF_MEMORY, ADGI_ERR_BUDGET, ADGI_ERR_NO_SCENE,
+ ADGI_ERR_TOPOLOGY, ADGI_ERR_DEVICE) = -1, -2, -3, -4, -5, -6
 ADGI_FP32, ADGI_FP16 = 0, 1
 ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
 ADGI_DEBUG_ARRAYS = 1
@@ -95,6 +97,26 @@ class TraceWork(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class StreamDesc(C.Structure):
+    _fields_ = [("volume", VolumeDesc), ("scene", SceneDesc), ("params", UpdateParams)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "admissions", "evictions",
+                                         "primary_rays", "resident_bytes", "peak_resident_bytes")] + \
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "span_s",
+                                          "admit_ms", "evict_ms")]
+
+    def as_dict(self):
+        return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n)))
+                for n, t in self._fields_}
+
+
 class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("persistent", C.c_int32), ("trace_block", C.c_int32),
                 ("trace_waves_per_cu", C.c_int32), ("blend_chunk", C.c_int32),
@@ -145,6 +167,25 @@ def lib():
         L.adgi_restore_state.argtypes = [P, P, C.c_size_t]
         L.adgi_device_bytes.argtypes = [P]
         L.adgi_device_bytes.restype = C.c_size_t
+        L.adgi_server_now_ns.restype = C.c_int64
+        L.adgi_server_last_error.restype = C.c_char_p
+        L.adgi_server_create.argtypes = [P, P, P]
+        L.adgi_server_add_stream.argtypes = [P, P, P]
+        L.adgi_server_set_budget.argtypes = [P, C.c_int64]
+        L.adgi_server_stream_info.argtypes = [P, C.c_int32, P, P, P]
+        L.adgi_server_submit.argtypes = [P, C.c_int32, P, C.c_int64]
+        L.adgi_server_progress.argtypes = [P, P]
+        L.adgi_server_drain.argtypes = [P]
+        L.adgi_server_get_stats.argtypes = [P, P]
+        L.adgi_server_latencies.argtypes = [P, P, C.c_int64, P]
+        L.adgi_server_read_stream.argtypes = [P, C.c_int32, P]
+        L.adgi_server_destroy.argtypes = [P]
+        L.adgi_server_destroy.restype = None
+        for name in ("adgi_server_create", "adgi_server_add_stream", "adgi_server_set_budget",
+                     "adgi_server_stream_info", "adgi_server_submit", "adgi_server_progress",
+                     "adgi_server_drain", "adgi_server_get_stats", "adgi_server_latencies",
+                     "adgi_server_read_stream"):
+            getattr(L, name).restype = C.c_int
         for name in ("adgi_create_volume", "adgi_update_scene", "adgi_update_probes",
                      "adgi_read_probes", "adgi_get_tuning", "adgi_set_tuning", "adgi_autotune",
                      "adgi_measure_trace_work",
@@ -157,6 +198,11 @@ def lib():
 def _check(status: int):
     if status != ADGI_OK:
         raise AdgiError(status, lib().adgi_last_error().decode())
+
+
+def _check_server(status: int):
+    if status != ADGI_OK:
+        raise AdgiError(status, lib().adgi_server_last_error().decode())
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -362,3 +408,118 @@ def volume_for_scene(scene, storage=ADGI_FP32, max_rays=None, seed=1, debug=Fals
     vol.update_scene(scene.positions, scene.indices, scene.albedo, scene.light_positions(0),
                      scene.light_intensity, scene.sky)
     return vol
+
+
+def _texel_buffers(d, P) -> dict:
+    gi, gd = d.irr_res, d.depth_res
+    return {"irradiance": np.zeros((P, gi, gi, 3), np.float32),
+            "depth": np.zeros((P, gd, gd, 2), np.float32),
+            "irr_count": np.zeros((P, gi - 2, gi - 2), np.uint8),
+            "depth_count": np.zeros((P, gd - 2, gd - 2), np.uint8),
+            "rays_per_probe": np.zeros(P, np.int32),
+            "score": np.zeros(P, np.int64)}
+
+
+class Server:
+    """Many probe volumes on one GPU: per-stream frame requests, HBM
+    admission by device footprint, eviction to host snapshots (adgi_server_*).
+
+    allocator=None lets the server pool device blocks itself (re-admission
+    then allocates nothing); "torch" routes them through torch's allocator."""
+
+    def __init__(self, hbm_budget_bytes, max_inflight=4, allocator=None):
+        d = ServerDesc(int(hbm_budget_bytes), int(max_inflight), 0)
+        self._alloc = _torch_allocator() if allocator == "torch" else allocator
+        h = C.c_void_p()
+        _check_server(lib().adgi_server_create(C.byref(d), C.byref(self._alloc) if self._alloc else None,
+                                               C.byref(h)))
+        self.h = h
+        self._streams = []
+
+    @staticmethod
+    def now_ns() -> int:
+        return int(lib().adgi_server_now_ns())
+
+    def add_stream(self, scene, budget, n_min=8, n_max=2048, storage=ADGI_FP32, seed=1,
+                   hysteresis=0.97, beta=5.0, mu=2, theta=8) -> int:
+        d = StreamDesc()
+        v = d.volume
+        v.origin[:] = [float(x) for x in scene.grid_origin]
+        v.spacing[:] = [float(x) for x in scene.grid_spacing]
+        v.dims[:] = [int(x) for x in scene.grid_dims]
+        v.irr_res, v.depth_res, v.storage = 8, 16, int(storage)
+        v.hysteresis, v.tau_max = float(hysteresis), TAU_MAX
+        v.max_rays_per_frame = int(budget)
+        v.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        v.flags = 0
+        pos = np.ascontiguousarray(scene.positions, np.float32).reshape(-1, 3)
+        idx = np.ascontiguousarray(scene.indices, np.int32).reshape(-1, 3)
+        alb = np.ascontiguousarray(scene.albedo, np.float32).reshape(-1, 3)
+        lp = np.ascontiguousarray(scene.light_positions(0), np.float32).reshape(-1, 3)
+        li = np.ascontiguousarray(scene.light_intensity, np.float32).reshape(-1, 3)
+        sd = d.scene
+        sd.positions, sd.num_vertices = _ptr(pos), pos.shape[0]
+        sd.indices, sd.num_triangles = _ptr(idx), idx.shape[0]
+        sd.albedo = _ptr(alb)
+        sd.light_pos, sd.light_intensity, sd.num_lights = _ptr(lp), _ptr(li), lp.shape[0]
+        sd.sky[:] = [float(x) for x in scene.sky]
+        sd.mode = ADGI_SCENE_REBUILD
+        d.params = UpdateParams(0, 1, int(budget), int(n_min), int(n_max), 0, float(beta), int(mu),
+                                int(theta), 0)
+        sid = C.c_int32()
+        _check_server(lib().adgi_server_add_stream(self.h, C.byref(d), C.byref(sid)))
+        self._streams.append((scene, v))
+        return int(sid.value)
+
+    def set_budget(self, hbm_budget_bytes):
+        _check_server(lib().adgi_server_set_budget(self.h, int(hbm_budget_bytes)))
+
+    def stream_info(self, sid) -> dict:
+        fb, res, fd = C.c_int64(), C.c_int32(), C.c_int32()
+        _check_server(lib().adgi_server_stream_info(self.h, int(sid), C.byref(fb), C.byref(res),
+                                                    C.byref(fd)))
+        return {"footprint_bytes": int(fb.value), "resident": bool(res.value),
+                "frames_done": int(fd.value)}
+
+    def submit(self, sid, light_pos, arrival_ns=None):
+        lp = np.ascontiguousarray(light_pos, np.float32).reshape(-1, 3)
+        t = self.now_ns() if arrival_ns is None else int(arrival_ns)
+        _check_server(lib().adgi_server_submit(self.h, int(sid), _ptr(lp), t))
+
+    def progress(self) -> int:
+        n = C.c_int32()
+        _check_server(lib().adgi_server_progress(self.h, C.byref(n)))
+        return int(n.value)
+
+    def drain(self):
+        _check_server(lib().adgi_server_drain(self.h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check_server(lib().adgi_server_get_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def latencies(self) -> np.ndarray:
+        n = C.c_int64()
+        _check_server(lib().adgi_server_latencies(self.h, None, 0, C.byref(n)))
+        out = np.zeros(max(int(n.value), 1), np.float64)
+        _check_server(lib().adgi_server_latencies(self.h, _ptr(out), out.size, C.byref(n)))
+        return out[:int(n.value)]
+
+    def read_stream(self, sid) -> dict:
+        scene, v = self._streams[sid]
+        P = int(np.prod([int(x) for x in v.dims]))
+        out = _texel_buffers(v, P)
+        rb = ProbeReadback()
+        for k, a in out.items():
+            setattr(rb, k, _ptr(a))
+        _check_server(lib().adgi_server_read_stream(self.h, int(sid), C.byref(rb)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().adgi_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        self.destroy()

@@ -6,6 +6,7 @@
 
 #include <vector>
 
+#include "../../include/adgi.h"
 #include "adgi_device.hpp"
 #include "adgi_layout.hpp"
 
@@ -84,6 +85,20 @@ struct Bvh4Host {
   int32_t max_stack = 0;
 };
 void collapse_bvh4(const BvhHost& b2, Bvh4Host& out);
+
+// volume.hip: a REBUILD split into its host build and the device install, so
+// a caller that keeps scenes on the host (the server) builds each BVH once.
+struct BuiltScene {
+  BvhHost bvh;
+  Bvh4Host bvh4;
+  bool fits4 = false;
+  float pad_abs = 0.f;
+  double build_ms = 0.0;
+};
+bool build_scene(const adgi_volume_desc& d, const adgi_scene_desc* sc, BuiltScene& out, const char** err);
+// adgi_update_scene with an optional prebuilt BVH for a REBUILD (same checks).
+adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const BuiltScene* prebuilt);
+hipStream_t volume_stream(adgi_volume* vol);
 // Conservative box padding (builder and refit): a few ulps of the coordinate
 // plus an absolute term tied to the scene's coordinate scale, so that FP32
 // slab tests from any ray origin in the scene never cull a box a hit lies in.

@@ -498,7 +498,32 @@ void adgi_destroy_volume(adgi_volume* vol) {
   delete vol;
 }
 
-adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
+}  // extern "C"
+
+namespace adgi {
+
+// Host half of a REBUILD: the conservative padding term and both BVHs.
+bool build_scene(const adgi_volume_desc& d, const adgi_scene_desc* sc, BuiltScene& out, const char** err) {
+  // coordinate scale of the scene and the grid for conservative box padding
+  double scale = 0.0;
+  for (int64_t k = 0; k < 3 * (int64_t)sc->num_vertices; ++k) scale = std::max(scale, (double)std::fabs(sc->positions[k]));
+  for (int a = 0; a < 3; ++a) {
+    double far = std::fabs((double)d.origin[a]) + std::fabs((double)d.spacing[a]) * (d.dims[a] - 1);
+    scale = std::max(scale, far);
+  }
+  for (int l = 0; l < sc->num_lights; ++l)
+    for (int a = 0; a < 3; ++a) scale = std::max(scale, (double)std::fabs(sc->light_pos[3 * l + a]));
+  out.pad_abs = (float)(scale * 1e-6) + 1e-30f;
+  auto t0 = std::chrono::steady_clock::now();
+  if (!build_bvh(sc->positions, sc->num_vertices, sc->indices, sc->num_triangles, out.pad_abs, out.bvh, err))
+    return false;
+  collapse_bvh4(out.bvh, out.bvh4);
+  out.fits4 = out.bvh4.max_stack <= kStackMax;
+  out.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return true;
+}
+
+adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const BuiltScene* prebuilt) {
   if (!vol || !sc) return fail(ADGI_ERR_INVALID_ARG, "volume and scene must not be NULL");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (sc->num_lights < 0 || sc->num_lights > ADGI_MAX_LIGHTS)
@@ -552,27 +577,18 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
   hp.num_tris = sc->num_triangles;
 
   if (!refit) {
-    // coordinate scale of the scene and the grid for conservative box padding
-    double scale = 0.0;
-    for (int64_t k = 0; k < 3 * (int64_t)sc->num_vertices; ++k) scale = std::max(scale, (double)std::fabs(sc->positions[k]));
-    for (int a = 0; a < 3; ++a) {
-      double far = std::fabs((double)vol->desc.origin[a]) +
-                   std::fabs((double)vol->desc.spacing[a]) * (vol->desc.dims[a] - 1);
-      scale = std::max(scale, far);
+    BuiltScene local;
+    const BuiltScene* built = prebuilt;
+    if (!built) {
+      const char* err = "";
+      if (!build_scene(vol->desc, sc, local, &err)) return fail(ADGI_ERR_INVALID_ARG, "BVH build failed: %s", err);
+      built = &local;
     }
-    for (int l = 0; l < sc->num_lights; ++l)
-      for (int a = 0; a < 3; ++a) scale = std::max(scale, (double)std::fabs(sc->light_pos[3 * l + a]));
-    const float pad_abs = (float)(scale * 1e-6) + 1e-30f;
-    BvhHost bvh;
-    const char* err = "";
-    auto t0 = std::chrono::steady_clock::now();
-    if (!build_bvh(sc->positions, sc->num_vertices, sc->indices, sc->num_triangles, pad_abs, bvh, &err))
-      return fail(ADGI_ERR_INVALID_ARG, "BVH build failed: %s", err);
-    vol->last_build_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    Bvh4Host bvh4;
-    collapse_bvh4(bvh, bvh4);
-    const bool fits4 = bvh4.max_stack <= kStackMax;
+    const BvhHost& bvh = built->bvh;
+    const Bvh4Host& bvh4 = built->bvh4;
+    const bool fits4 = built->fits4;
+    const float pad_abs = built->pad_abs;
+    vol->last_build_ms = built->build_ms;
     HIP_TRY(vol, hipStreamSynchronize(vol->stream));
     drop_graphs(vol);
     free_scene(vol);
@@ -669,6 +685,16 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
   HIP_TRY(vol, hipEventRecord(vol->ev_stage, vol->stream));
   vol->has_scene = true;
   return order_user_after(vol);
+}
+
+hipStream_t volume_stream(adgi_volume* vol) { return vol->stream; }
+
+}  // namespace adgi
+
+extern "C" {
+
+adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
+  return adgi::update_scene_impl(vol, sc, nullptr);
 }
 
 adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, adgi_update_stats* stats) {
