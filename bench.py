@@ -28,9 +28,10 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # FP32 operations of the two traversal tests as written (adgi_device.hpp):
 # slab test of one child box = 6 fma + 6 min/max + 6 min/max + 1 compare = 19,
-# a node visit tests two child boxes; Moller-Trumbore = 2 crosses (12),
-# 4 dots (12), 3 subtractions, 2 sign products, 4 compares = 33.
-OPS_PER_NODE = 38
+# a BVH2 node visit tests two child boxes, a BVH4 visit four; Moller-Trumbore
+# = 2 crosses (12), 4 dots (12), 3 subtractions, 2 sign products, 4 compares
+# = 33.
+OPS_PER_BOX = 19
 OPS_PER_TRI = 33
 
 WORKLOADS = {
@@ -185,7 +186,7 @@ def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
             "seconds": wall}
 
 
-def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=4):
+def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=8):
     """Serving mix: 32 streams (box fields of 10k-500k triangles, 512-32768
     probes, B = 128 rays per probe), Poisson arrivals at 30-120 Hz each, for
     duration_s of wall time, under an HBM admission budget of budget_frac of
@@ -314,17 +315,18 @@ def main():
     value = R * args.steps / res_a["seconds"]
     ms_step = res_a["seconds"] / args.steps * 1e3
     trace_ms, blend_ms = stages_a[4], stages_a[5]
-    ops = tw["node_tests"] * OPS_PER_NODE + tw["tri_tests"] * OPS_PER_TRI
+    ops = tw["box_tests"] * OPS_PER_BOX + tw["tri_tests"] * OPS_PER_TRI
     trace_tops = ops / (trace_ms * 1e-3) / 1e12
     bbytes = blend_bytes(P, R, fp16)
     blend_gbs = bbytes / (blend_ms * 1e-3) / 1e9
-    h_trace = source_hash("trace.hip", "adgi_device.hpp")
+    h_trace = source_hash("trace.hip", "adgi_device.hpp", "adgi_layout.hpp", "bvh_build.cpp")
     h_blend = source_hash("blend.hip", "adgi_device.hpp")
     roof_trace = {"bound": "alu", "kernel": "trace_kernel<primary>", "achieved": trace_tops,
                   "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": trace_tops / VALU_PEAK_TOPS,
                   "traffic": read_traffic("trace_boxfield", h_trace),
                   "ms": trace_ms, "node_tests_per_ray": tw["node_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
                   "tri_tests_per_ray": tw["tri_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
+                  "bvh_width": tuning.get("bvh_width"),
                   "rays_incl_shadow": tw["primary_rays"] + tw["shadow_rays"]}
     roof_blend = {"bound": "hbm", "kernel": "blend_kernel", "achieved": blend_gbs, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": blend_gbs / HBM_PEAK_GBS,
