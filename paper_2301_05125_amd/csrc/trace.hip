@@ -178,8 +178,9 @@ __device__ bool any_hit(const VolumeView& v, const Ray& ray,
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
       if (hl && hr) {
-        st.push(nd.right);
-        node = nd.left;
+        bool lf = tl <= tr;
+        st.push(lf ? nd.right : nd.left);
+        node = lf ? nd.left : nd.right;
       } else if (hl) {
         node = nd.left;
       } else if (hr) {
