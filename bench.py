@@ -66,23 +66,45 @@ def source_hash(*names):
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_key, src_hash):
-    """HBM bytes per dispatch from a committed rocprofv3 counter summary,
-    valid only while the kernel source is unchanged."""
+def read_profile(kernel_key, src_hash):
+    """Counter figures from a committed rocprofv3 summary (HBM bytes per
+    dispatch, VALU busy/utilisation), valid only while the kernel source is
+    unchanged; {} otherwise."""
     path = os.path.join(ROOT, "profiles", f"{kernel_key}_pmc.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != src_hash:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_dispatch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for key, name in (("hbm_bytes_per_dispatch", "traffic"), ("VALUBusy", "valu_busy_pct"),
+                      ("VALUUtilization", "valu_utilization_pct"), ("kernel_trace_avg_us", "rocprof_avg_us")):
+        try:
+            out[name] = float(vals[key])
+        except (KeyError, ValueError):
+            pass
+    return out
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read + write), best of reps, GB/s."""
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del x, y
+    return 2 * nbytes / (best * 1e-3) / 1e9
 
 
 def light_frame(frame, period=60):
@@ -119,19 +141,26 @@ def run_mode(vol, sc, adgi, torch, frame0, steps, warmup, latency_frames, **p):
         f += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # latency: one synchronous frame at a time
-    host_ms, gpu_ms, rays, shadow = [], [], [], []
+    # latency: one synchronous frame at a time; the scene update before it is
+    # timed on its own (host work + upload + refit, to device completion)
+    host_ms, gpu_ms, rays, shadow, scene_ms, shadow_only = [], [], [], [], [], []
     for _ in range(latency_frames):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
         step_scene(vol, sc, f, adgi)
+        torch.cuda.synchronize()
+        scene_ms.append((time.perf_counter() - a) * 1e3)
         a = time.perf_counter()
         st = vol.update_probes(f, sync=True, **p)
         host_ms.append((time.perf_counter() - a) * 1e3)
         gpu_ms.append(st["ms_total"])
         rays.append(st["primary_rays"])
         shadow.append(st["shadow_rays"] + st["pilot_rays"])
+        shadow_only.append(st["shadow_rays"])
         f += 1
-    return dict(seconds=t1 - t0, frames_end=f, host_ms=host_ms, gpu_ms=gpu_ms,
-                rays_per_frame=sum(rays) / len(rays), extra_rays_per_frame=sum(shadow) / len(shadow))
+    return dict(seconds=t1 - t0, frames_end=f, host_ms=host_ms, gpu_ms=gpu_ms, scene_ms=scene_ms,
+                rays_per_frame=sum(rays) / len(rays), extra_rays_per_frame=sum(shadow) / len(shadow),
+                shadow_rays_per_frame=sum(shadow_only) / len(shadow_only))
 
 
 def stage_times(vol, sc, adgi, frame0, frames, **p):
@@ -183,7 +212,58 @@ def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
                       f"(BVH build untimed)",
             "sampled_probe_rays_per_s": sample_rays / max(probes_s, 1e-9),
             "extrapolated_ms_per_frame": frame_s * 1e3,
-            "seconds": wall}
+            "seconds": wall,
+            "host": host_info(),
+            "other_workloads": cpu_small_workloads(oracle)}
+
+
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def cpu_small_workloads(oracle):
+    """The Cornell room (uniform, 64 rays/probe) and the tunnel (adaptive,
+    B = 2^19) as full oracle frames on all threads, and the tunnel's probe
+    rays on one thread (a bounded sample of its probes)."""
+    import scenes as S
+    out = {}
+    sc = S.cornell()
+    vol = oracle.OracleVolume(sc, seed=7)
+    t0 = time.perf_counter()
+    rays = 0
+    for f in range(2):
+        rays += vol.update(f, adaptive=False, n_uniform=64)["counts"]["rays"]
+    dt = time.perf_counter() - t0
+    out["cornell_full_frame"] = {"rays_per_s": rays / dt, "ms_per_frame": dt / 2 * 1e3}
+    sc = S.tunnel()
+    vol = oracle.OracleVolume(sc, seed=7)
+    frame_s = []
+    rays = 0
+    for f in range(2):
+        o = vol.update(f, adaptive=True, budget=1 << 19, n_min=32, n_max=1024)
+        frame_s.append(sum(o["seconds"].values()))
+        rays += o["counts"]["rays"]
+    out["tunnel_full_frame"] = {"rays_per_s": rays / sum(frame_s),
+                                "ms_per_frame": sum(frame_s) / 2 * 1e3}
+    probes = S.sample_probes(sc.num_probes, 128)
+    vol = oracle.OracleVolume(sc, seed=7, probes=probes)
+    nthreads = int(oracle.lib().orc_num_threads())
+    oracle.lib().orc_set_threads(1)
+    try:
+        o = vol.update(0, adaptive=True, budget=1 << 19, n_min=32, n_max=1024)
+    finally:
+        oracle.lib().orc_set_threads(nthreads)
+    out["tunnel_one_thread"] = {"rays_per_s": o["counts"]["rays"] / max(o["seconds"]["probes"], 1e-9),
+                                "sample": f"probe rays of 128 sampled probes, {o['counts']['rays']} rays"}
+    return out
 
 
 def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=8):
@@ -310,6 +390,8 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
+        del x, y
+    copy_gbs = copy_bandwidth(torch)
 
     R = res_a["rays_per_frame"]
     value = R * args.steps / res_a["seconds"]
@@ -321,17 +403,23 @@ def main():
     blend_gbs = bbytes / (blend_ms * 1e-3) / 1e9
     h_trace = source_hash("trace.hip", "adgi_device.hpp", "adgi_layout.hpp", "bvh_build.cpp")
     h_blend = source_hash("blend.hip", "adgi_device.hpp")
+    prof_trace, prof_blend = read_profile("trace_boxfield", h_trace), read_profile("blend_boxfield", h_blend)
+    nrays = max(tw["primary_rays"] + tw["shadow_rays"], 1)
     roof_trace = {"bound": "alu", "kernel": "trace_kernel<primary>", "achieved": trace_tops,
                   "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": trace_tops / VALU_PEAK_TOPS,
-                  "traffic": read_traffic("trace_boxfield", h_trace),
+                  "traffic": prof_trace.get("traffic"),
+                  "valu_busy_pct": prof_trace.get("valu_busy_pct"),
+                  "valu_utilization_pct": prof_trace.get("valu_utilization_pct"),
+                  "mrays_per_s_primary": tw["primary_rays"] / (trace_ms * 1e-3) / 1e6,
+                  "mrays_per_s_primary_plus_shadow": nrays / (trace_ms * 1e-3) / 1e6,
                   "ms": trace_ms, "node_tests_per_ray": tw["node_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
                   "tri_tests_per_ray": tw["tri_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
                   "bvh_width": tuning.get("bvh_width"),
                   "rays_incl_shadow": tw["primary_rays"] + tw["shadow_rays"]}
     roof_blend = {"bound": "hbm", "kernel": "blend_kernel", "achieved": blend_gbs, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": blend_gbs / HBM_PEAK_GBS,
-                  "traffic": read_traffic("blend_boxfield", h_blend), "ms": blend_ms,
-                  "algorithmic_bytes": bbytes}
+                  "traffic": prof_blend.get("traffic"), "ms": blend_ms,
+                  "algorithmic_bytes": bbytes, "copy_gbs": copy_gbs, "frac_of_copy": blend_gbs / copy_gbs}
     dominant = roof_trace if trace_ms >= blend_ms else roof_blend
     out = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -345,6 +433,9 @@ def main():
                    "parallelism": "1 GPU", "tuning": tuning},
         "adaptive": {"rays_per_s": value, "probe_updates_per_s": P * args.steps / res_a["seconds"],
                      "pilot_plus_shadow_rays_per_s": res_a["extra_rays_per_frame"] * args.steps / res_a["seconds"],
+                     "shadow_rays_per_s": res_a["shadow_rays_per_frame"] * args.steps / res_a["seconds"],
+                     "scene_update_p50_ms": pct(res_a["scene_ms"], 50),
+                     "scene_update_p99_ms": pct(res_a["scene_ms"], 99),
                      "p50_ms": pct(res_a["host_ms"], 50), "p99_ms": pct(res_a["host_ms"], 99),
                      "gpu_p50_ms": pct(res_a["gpu_ms"], 50), "gpu_p99_ms": pct(res_a["gpu_ms"], 99),
                      "stage_ms": dict(zip(["setup", "pilot_trace", "detect", "allocate", "probe_trace",

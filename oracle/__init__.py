@@ -122,6 +122,8 @@ def lib():
         L.orc_round_half.restype = C.c_double
         L.orc_round_half.argtypes = [C.c_double]
         L.orc_num_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 

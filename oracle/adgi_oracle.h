@@ -170,6 +170,8 @@ double orc_blend_alpha(int32_t n, double hysteresis);
 double orc_round_half(double x);
 
 int32_t orc_num_threads(void);
+/* Threads for the following OpenMP regions (timing only). */
+void orc_set_threads(int32_t n);
 
 #ifdef __cplusplus
 }
