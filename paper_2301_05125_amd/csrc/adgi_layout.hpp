@@ -11,7 +11,7 @@ constexpr uint64_t kTagPilot = 0x50494Cull;     // "PIL"
 constexpr int kMaxLights = 8;
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
-constexpr int kStackLds = 12;                   // traversal stack entries kept in LDS
+constexpr int kStackLds = 7;                    // traversal stack entries kept in LDS
 constexpr int kOrderBuckets = 32;               // blend order: 64-ray chunks per probe, capped
 constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
 constexpr float kShadowOffset = 1e-4f;          // shadow origin offset, units of s

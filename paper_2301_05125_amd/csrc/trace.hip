@@ -20,34 +20,50 @@ namespace adgi {
 
 enum { KIND_PRIMARY = 0, KIND_PILOT = 1 };
 
-// Per-lane traversal stack: the first kStackLds entries in the wave's LDS
-// region (entry k of lane l at word 64k + l, so a wave's pushes at one depth
-// hit 64 consecutive words), deeper entries in private memory. The LDS
-// pointer is typed as LDS so the compiler emits ds_ instructions rather than
-// generic (flat) accesses.
-typedef __attribute__((address_space(3))) int lds_int;
+// Per-lane traversal stack of (node, entry distance of its box): the first
+// kStackLds entries in the wave's LDS region (entry k of lane l at 8-byte
+// word 64k + l, so a wave's pushes at one depth hit consecutive words), deeper
+// entries in private memory. The LDS pointer is typed as LDS so the compiler
+// emits ds_ instructions rather than generic (flat) accesses. A closest-hit
+// traversal drops popped entries whose box starts beyond the current best
+// hit: the box test would reject them (and their children, whose boxes lie
+// inside theirs) with the same comparison.
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
 
 struct Stack {
-  lds_int* lds;   // this lane's entry 0
+  lds_u64* lds;   // this lane's entry 0; an entry is (t bits << 32) | node
   int sp;
-  int deep[kStackMax - kStackLds];
-  __device__ __forceinline__ void push(int v) {
+  uint64_t deep[kStackMax - kStackLds];
+  __device__ __forceinline__ void push(int node, float t) {
+    const uint64_t e = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)node;
     if (sp < kStackLds) {
-      lds[sp << 6] = v;
+      lds[sp << 6] = e;
     } else {
-      deep[sp - kStackLds] = v;
+      deep[sp - kStackLds] = e;
     }
     ++sp;
   }
-  __device__ __forceinline__ int pop() {
+  __device__ __forceinline__ uint64_t pop() {
     --sp;
-    int v;
+    uint64_t e;
     if (sp < kStackLds) {
-      v = lds[sp << 6];
+      e = lds[sp << 6];
     } else {
-      v = deep[sp - kStackLds];
+      e = deep[sp - kStackLds];
     }
-    return v;
+    return e;
+  }
+  __device__ __forceinline__ int pop_node() { return (int)(uint32_t)pop(); }
+  // Next entry whose box may hold a hit at t <= tmax; false when none is left.
+  __device__ __forceinline__ bool pop_live(float tmax, int& node) {
+    while (sp > 0) {
+      const uint64_t e = pop();
+      if (__uint_as_float((uint32_t)(e >> 32)) <= tmax) {
+        node = (int)(uint32_t)e;
+        return true;
+      }
+    }
+    return false;
   }
 };
 
@@ -128,15 +144,14 @@ __device__ int closest_hit(const VolumeView& v, const Ray& ray,
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, t_best, tr);
       if (hl && hr) {
         bool lf = tl <= tr;
-        st.push(lf ? nd.right : nd.left);
+        st.push(lf ? nd.right : nd.left, lf ? tr : tl);
         node = lf ? nd.left : nd.right;
       } else if (hl) {
         node = nd.left;
       } else if (hr) {
         node = nd.right;
       } else {
-        if (st.sp == 0) return slot_best;
-        node = st.pop();
+        if (!st.pop_live(t_best, node)) return slot_best;
       }
     }
     int code = ~node;
@@ -157,8 +172,7 @@ __device__ int closest_hit(const VolumeView& v, const Ray& ray,
         }
       }
     }
-    if (st.sp == 0) return slot_best;
-    node = st.pop();
+    if (!st.pop_live(t_best, node)) return slot_best;
   }
 }
 
@@ -179,7 +193,7 @@ __device__ bool any_hit(const VolumeView& v, const Ray& ray,
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
       if (hl && hr) {
         bool lf = tl <= tr;
-        st.push(lf ? nd.right : nd.left);
+        st.push(lf ? nd.right : nd.left, lf ? tr : tl);
         node = lf ? nd.left : nd.right;
       } else if (hl) {
         node = nd.left;
@@ -187,7 +201,7 @@ __device__ bool any_hit(const VolumeView& v, const Ray& ray,
         node = nd.right;
       } else {
         if (st.sp == 0) return false;
-        node = st.pop();
+        node = st.pop_node();
       }
     }
     int code = ~node;
@@ -200,7 +214,7 @@ __device__ bool any_hit(const VolumeView& v, const Ray& ray,
       if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
     }
     if (st.sp == 0) return false;
-    node = st.pop();
+    node = st.pop_node();
   }
 }
 
@@ -238,9 +252,9 @@ __device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int
   order2(k1, c1, k3, c3);
   order2(k1, c1, k2, c2);
   const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
-  if (nh >= 4) st.push(c3);
-  if (nh >= 3) st.push(c2);
-  if (nh >= 2) st.push(c1);
+  if (nh >= 4) st.push(c3, k3);
+  if (nh >= 3) st.push(c2, k2);
+  if (nh >= 2) st.push(c1, k1);
   next = c0;
   return nh;
 }
@@ -263,8 +277,7 @@ __device__ int closest_hit4(const VolumeView& v, const Ray& ray, Stack& st, floa
       if (node4_step(v.nodes4, node, ray, t_best, st, next) > 0) {
         node = next;
       } else {
-        if (st.sp == 0) return slot_best;
-        node = st.pop();
+        if (!st.pop_live(t_best, node)) return slot_best;
       }
     }
     int code = ~node;
@@ -285,8 +298,7 @@ __device__ int closest_hit4(const VolumeView& v, const Ray& ray, Stack& st, floa
         }
       }
     }
-    if (st.sp == 0) return slot_best;
-    node = st.pop();
+    if (!st.pop_live(t_best, node)) return slot_best;
   }
 }
 
@@ -304,7 +316,7 @@ __device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack&
         node = next;
       } else {
         if (st.sp == 0) return false;
-        node = st.pop();
+        node = st.pop_node();
       }
     }
     int code = ~node;
@@ -317,7 +329,7 @@ __device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack&
       if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
     }
     if (st.sp == 0) return false;
-    node = st.pop();
+    node = st.pop_node();
   }
 }
 
@@ -483,14 +495,14 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
 // occupancy pays for the few registers the compiler then keeps in scratch.
 template <int KIND, bool COUNT, bool W4>
 __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_kernel(VolumeView v, int persistent) {
-  extern __shared__ int smem[];
-  int* stack_base = smem;                                        // kStackLds * blockDim
+  extern __shared__ uint64_t smem[];
+  uint64_t* stack_base = (uint64_t*)smem;                         // kStackLds * blockDim
   uint16_t* queues = (uint16_t*)(stack_base + kStackLds * blockDim.x);  // waves * 64 * kMaxLights
   const int nwaves = blockDim.x >> 6;
   uint32_t* vis_all = (uint32_t*)(queues + nwaves * 64 * kMaxLights);   // waves * 64
   const int wave = threadIdx.x >> 6;
   Stack st;
-  st.lds = (lds_int*)stack_base + wave * (64 * kStackLds) + lane_id();
+  st.lds = (lds_u64*)stack_base + wave * (64 * kStackLds) + lane_id();
   st.sp = 0;
   uint16_t* queue = queues + wave * 64 * kMaxLights;
   uint32_t* vis = vis_all + wave * 64;
@@ -511,7 +523,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_kernel(VolumeVi
 }
 
 size_t trace_lds_bytes(int block) {
-  return (size_t)kStackLds * block * 4 + (size_t)(block / 64) * 64 * kMaxLights * 2 + (size_t)(block / 64) * 64 * 4;
+  return (size_t)kStackLds * block * 8 + (size_t)(block / 64) * 64 * kMaxLights * 2 + (size_t)(block / 64) * 64 * 4;
 }
 
 template <bool W4>
