@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
                                "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -123,6 +123,15 @@ def lib():
         L.orc_round_half.argtypes = [C.c_double]
         L.orc_num_threads.restype = C.c_int32
         L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_ln32.restype = C.c_float
+        L.orc_ln32.argtypes = [C.c_float]
+        L.orc_exp32.restype = C.c_float
+        L.orc_exp32.argtypes = [C.c_float]
+        L.orc_pack_encode.restype = C.c_uint32
+        L.orc_pack_encode.argtypes = [C.c_float, C.c_float, C.c_float, C.c_int32]
+        L.orc_pack_decode.restype = C.c_float
+        L.orc_pack_decode.argtypes = [C.c_uint32, C.c_float, C.c_float, C.c_int32]
+        L.orc_packed_blend.restype = None
         L.orc_set_threads.restype = None
         _lib = L
     return _lib
@@ -209,6 +218,54 @@ def blend_alpha(n: int, h: float) -> float:
 
 def round_half(x: float) -> float:
     return lib().orc_round_half(x)
+
+
+def pack_encode(v: float, beta: float, gamma: float, bits: int) -> int:
+    return int(lib().orc_pack_encode(float(v), float(beta), float(gamma), int(bits)))
+
+
+def pack_decode(q: int, beta: float, gamma: float, bits: int) -> float:
+    return float(lib().orc_pack_decode(int(q), float(beta), float(gamma), int(bits)))
+
+
+# (beta, gamma, bits) per channel of the packed words
+PACK_IRR = ((5.0, 15.0, 9), (5.0, 15.0, 9), (5.0, 15.0, 8))
+PACK_DEP = ((5.0, 15.0, 13), (8.0, 20.0, 13))
+
+
+def unpack_words(words: np.ndarray, channels) -> tuple:
+    """Packed words -> (decoded FP32 values [..., C], counts [...])."""
+    w = np.asarray(words, np.uint32)
+    vals = np.zeros(w.shape + (len(channels),), np.float32)
+    shift = 0
+    dec = np.vectorize(lambda q, b, g, n: pack_decode(int(q), b, g, n), otypes=[np.float32])
+    for c, (b, g, n) in enumerate(channels):
+        q = (w >> shift) & ((1 << n) - 1)
+        vals[..., c] = dec(q, b, g, n) if w.size else 0
+        shift += n
+    return vals, (w >> 26).astype(np.uint8)
+
+
+def packed_alpha_table(hysteresis: float) -> np.ndarray:
+    """Step weights max(1/(N+1), 1-h) for N = 0..63, in FP32 as the kernel's table."""
+    omh = np.float32(1.0 - float(np.float32(hysteresis)))
+    k = np.arange(64, dtype=np.float32)
+    return np.maximum(np.float32(1.0) / (k + np.float32(1.0)), omh).astype(np.float32)
+
+
+def packed_blend(n, ray_base, rec, ibin, dbin, ri, rd, inv_s, tau_max, alpha, irr_words, dep_words):
+    """Apply one frame of samples to packed interior words in place (FP32)."""
+    n = np.ascontiguousarray(n, np.int32)
+    ray_base = np.ascontiguousarray(ray_base, np.int64)
+    rec = np.ascontiguousarray(rec, np.float32)
+    ibin = np.ascontiguousarray(ibin, np.uint16)
+    dbin = np.ascontiguousarray(dbin, np.uint16)
+    alpha = np.ascontiguousarray(alpha, np.float32)
+    assert irr_words.dtype == np.uint32 and dep_words.dtype == np.uint32
+    assert irr_words.flags["C_CONTIGUOUS"] and dep_words.flags["C_CONTIGUOUS"]
+    lib().orc_packed_blend(C.c_int32(len(n)), _p(n), _p(ray_base), _p(rec), _p(ibin), _p(dbin),
+                           C.c_int32(ri), C.c_int32(rd), C.c_float(inv_s), C.c_float(tau_max),
+                           _p(alpha), _p(irr_words), _p(dep_words))
 
 
 def allocate(score: np.ndarray, budget: int, n_min: int, n_max: int):

@@ -1121,6 +1121,111 @@ void orc_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, cons
   }
 }
 
+/* ------------------------------------------------------- packed texels */
+
+/* ln on binary32 for y >= 1: y = m 2^e with m in [sqrt(1/2), sqrt(2)), then
+ * ln m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, by its series to s^11
+ * (truncation < 1e-10), and e ln 2 split in two parts (Cody and Waite) so the
+ * product stays exact. */
+static const float kLn2Hi = 0.693145751953125f;       /* 0x3F317200: 16 bits */
+static const float kLn2Lo = 1.42860682030941723212e-6f; /* ln 2 - kLn2Hi */
+
+float orc_ln32(float y) {
+  uint32_t b;
+  memcpy(&b, &y, 4);
+  int32_t e = (int32_t)((b >> 23) & 0xFFu) - 127;
+  uint32_t mb = (b & 0x7FFFFFu) | 0x3F800000u;
+  float m;
+  memcpy(&m, &mb, 4);
+  if (m > 1.41421356f) {
+    m = m * 0.5f;
+    e = e + 1;
+  }
+  float s = (m - 1.0f) / (m + 1.0f);
+  float s2 = s * s;
+  float p = fmaf(s2, 1.0f / 11.0f, 1.0f / 9.0f);
+  p = fmaf(s2, p, 1.0f / 7.0f);
+  p = fmaf(s2, p, 1.0f / 5.0f);
+  p = fmaf(s2, p, 1.0f / 3.0f);
+  p = fmaf(s2, p, 1.0f);
+  float lnm = 2.0f * s * p;
+  float fe = (float)e;
+  return fmaf(fe, kLn2Hi, fmaf(fe, kLn2Lo, lnm));
+}
+
+/* e^x on binary32 for 0 <= x <= 16: x = k ln 2 + r, |r| <= ln 2 / 2 (Cody
+ * and Waite reduction), e^r by its Taylor series to r^7 (truncation < 6e-9),
+ * scaled by 2^k through the exponent bits. */
+float orc_exp32(float x) {
+  float k = rintf(x * 1.44269504f);
+  float r = fmaf(-k, kLn2Hi, x);
+  r = fmaf(-k, kLn2Lo, r);
+  float p = fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
+  p = fmaf(r, p, 1.0f / 120.0f);
+  p = fmaf(r, p, 1.0f / 24.0f);
+  p = fmaf(r, p, 1.0f / 6.0f);
+  p = fmaf(r, p, 0.5f);
+  p = fmaf(r, p, 1.0f);
+  p = fmaf(r, p, 1.0f);
+  uint32_t sb = (uint32_t)((int32_t)k + 127) << 23;
+  float scale;
+  memcpy(&scale, &sb, 4);
+  return p * scale;
+}
+
+uint32_t orc_pack_encode(float v, float beta, float gamma, int32_t bits) {
+  const float qmax = (float)((1u << bits) - 1u);
+  float x = v > 0.0f ? v : 0.0f;
+  float u = fminf(orc_ln32(fmaf(gamma, x, 1.0f)), beta) / beta;
+  float q = floorf(u * qmax);
+  return q >= qmax ? (uint32_t)qmax : (uint32_t)q;
+}
+
+float orc_pack_decode(uint32_t q, float beta, float gamma, int32_t bits) {
+  const float qmax = (float)((1u << bits) - 1u);
+  float u = (float)q / qmax;
+  return (orc_exp32(beta * u) - 1.0f) / gamma;
+}
+
+void orc_packed_blend(int32_t count, const int32_t* n, const int64_t* ray_base, const float* rec,
+                      const uint16_t* ibin, const uint16_t* dbin, int32_t ri, int32_t rd, float inv_s,
+                      float tau_max, const float* alpha, uint32_t* irr, uint32_t* dep) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t q = 0; q < count; ++q) {
+    uint32_t* wi = irr + (size_t)q * ri * ri;
+    uint32_t* wd = dep + (size_t)q * rd * rd;
+    for (int32_t j = 0; j < n[q]; ++j) {
+      const int64_t r = ray_base[q] + j;
+      const float* x = rec + 4 * r;
+      /* irradiance texel: (R, G, B) */
+      uint32_t w = wi[ibin[r]];
+      uint32_t N = w >> 26;
+      float al = alpha[N];
+      uint32_t c0 = w & 0x1FFu, c1 = (w >> 9) & 0x1FFu, c2 = (w >> 18) & 0xFFu;
+      float o0 = orc_pack_decode(c0, 5.0f, 15.0f, 9);
+      float o1 = orc_pack_decode(c1, 5.0f, 15.0f, 9);
+      float o2 = orc_pack_decode(c2, 5.0f, 15.0f, 8);
+      c0 = orc_pack_encode(fmaf(al, x[0] - o0, o0), 5.0f, 15.0f, 9);
+      c1 = orc_pack_encode(fmaf(al, x[1] - o1, o1), 5.0f, 15.0f, 9);
+      c2 = orc_pack_encode(fmaf(al, x[2] - o2, o2), 5.0f, 15.0f, 8);
+      N = N < 63u ? N + 1u : 63u;
+      wi[ibin[r]] = c0 | (c1 << 9) | (c2 << 18) | (N << 26);
+      /* depth texel: (tau, tau^2) */
+      w = wd[dbin[r]];
+      N = w >> 26;
+      al = alpha[N];
+      uint32_t d0 = w & 0x1FFFu, d1 = (w >> 13) & 0x1FFFu;
+      float tau = fminf(x[3] * inv_s, tau_max);
+      float p0 = orc_pack_decode(d0, 5.0f, 15.0f, 13);
+      float p1 = orc_pack_decode(d1, 8.0f, 20.0f, 13);
+      d0 = orc_pack_encode(fmaf(al, tau - p0, p0), 5.0f, 15.0f, 13);
+      d1 = orc_pack_encode(fmaf(al, tau * tau - p1, p1), 8.0f, 20.0f, 13);
+      N = N < 63u ? N + 1u : 63u;
+      wd[dbin[r]] = d0 | (d1 << 13) | (N << 26);
+    }
+  }
+}
+
 int32_t orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

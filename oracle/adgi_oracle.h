@@ -169,6 +169,27 @@ double orc_blend_alpha(int32_t n, double hysteresis);
 /* binary16 round-to-nearest-even of a double */
 double orc_round_half(double x);
 
+/* ---- packed 32-bit texels (eq. rgbEnc; Sec. 4.6; App. B) ----------------
+ * The quantised codes are decisions of the paper's FP32 shader arithmetic, so
+ * this part computes in IEEE binary32 (every operation written out, fused
+ * multiply-adds explicit, no contraction) with its own ln and exp. */
+float orc_ln32(float y);            /* natural log, y >= 1                    */
+float orc_exp32(float x);           /* e^x, 0 <= x <= 16                      */
+/* floor(min(ln(gamma v + 1), beta) / beta * (2^bits - 1)) for v >= 0 */
+uint32_t orc_pack_encode(float v, float beta, float gamma, int32_t bits);
+/* (exp(beta q / (2^bits - 1)) - 1) / gamma */
+float orc_pack_decode(uint32_t q, float beta, float gamma, int32_t bits);
+/* Moving average of Alg. MovingAvgUpdate on packed words, samples of each
+ * probe applied in ray order: irradiance word = R9 | G9 << 9 | B8 << 18 |
+ * N6 << 26 (beta 5, gamma 15), depth word = tau13 | tau^2_13 << 13 | N6 << 26
+ * (beta 5 / gamma 15 and beta 8 / gamma 20). rec[r] = (R, G, B, t) as the
+ * trace wrote it (FP32); tau = min(t * inv_s, tau_max); alpha[N] the step
+ * weight for count N (N saturates at 63). irr: [count][ri*ri], dep:
+ * [count][rd*rd] interior words, updated in place. */
+void orc_packed_blend(int32_t count, const int32_t* n, const int64_t* ray_base, const float* rec,
+                      const uint16_t* ibin, const uint16_t* dbin, int32_t ri, int32_t rd, float inv_s,
+                      float tau_max, const float* alpha, uint32_t* irr, uint32_t* dep);
+
 int32_t orc_num_threads(void);
 /* Threads for the following OpenMP regions (timing only). */
 void orc_set_threads(int32_t n);

@@ -645,3 +645,90 @@ def test_pin8_allocation_properties():
     assert np.all(n3[:5] == 257) and np.all(n3[5:] == 256)
     with pytest.raises(ValueError):
         oracle.allocate(score, 32 * P - 1, 32, 1024)
+
+
+# ---------------------------------------------------------------- packed texels
+# The packed words of eq. rgbEnc / App. B (R9 G9 B8 + N6; two 13-bit depth
+# channels + N6) are computed in FP32 with the oracle's own ln/exp. Pins: the
+# library log/exp, the closed form of the encoding, the round-down property
+# the paper states for its quantisation (dark samples drive a texel to zero),
+# the fixed point of the quantised moving average, and the count field.
+
+def test_packed_exp_ln_against_libm():
+    L = oracle.lib()
+    xs = np.linspace(0.0, 16.0, 4001).astype(np.float32)
+    e = np.array([L.orc_exp32(float(x)) for x in xs], np.float64)
+    ref = np.exp(xs.astype(np.float64))
+    assert np.max(np.abs(e - ref) / np.spacing(ref.astype(np.float32)).astype(np.float64)) <= 1.0
+    ys = np.exp(np.linspace(0.0, 20.0, 4001)).astype(np.float32)
+    ln = np.array([L.orc_ln32(float(y)) for y in ys], np.float64)
+    ref = np.log(ys.astype(np.float64))
+    ulp = np.spacing(np.maximum(np.abs(ref), 1e-3).astype(np.float32)).astype(np.float64)
+    assert np.max(np.abs(ln - ref) / ulp) <= 3.0
+
+
+@pytest.mark.parametrize("beta,gamma,bits", [(5.0, 15.0, 9), (5.0, 15.0, 8), (5.0, 15.0, 13),
+                                             (8.0, 20.0, 13)])
+def test_packed_encode_closed_form(beta, gamma, bits):
+    qmax = (1 << bits) - 1
+    rng = np.random.default_rng(bits)
+    vs = np.concatenate([np.exp(rng.uniform(-12, 4, 3000)), [0.0, 1e-30]]).astype(np.float32)
+    vmax = (math.exp(beta) - 1.0) / gamma
+    for v in vs:
+        q = oracle.pack_encode(float(v), beta, gamma, bits)
+        exact = min(math.log(gamma * float(v) + 1.0), beta) / beta * qmax
+        if abs(exact - round(exact)) > 1e-4 * max(1.0, exact):  # not on a code boundary
+            assert q == min(math.floor(exact), qmax), (v, q, exact)
+        d = oracle.pack_decode(q, beta, gamma, bits)
+        # round down: the stored value never exceeds the sample ...
+        assert d <= float(v) * (1 + 1e-6) + 1e-12
+        # ... and lies within one code of it (unless saturated)
+        if q < qmax:
+            assert float(v) <= oracle.pack_decode(q + 1, beta, gamma, bits) * (1 + 1e-6)
+        else:
+            assert float(v) >= vmax * (1 - 1e-5)
+    assert oracle.pack_decode(0, beta, gamma, bits) == 0.0
+    assert abs(oracle.pack_decode(qmax, beta, gamma, bits) - vmax) <= 1e-6 * vmax
+    dec = [oracle.pack_decode(q, beta, gamma, bits) for q in range(0, qmax + 1, max(1, qmax // 511))]
+    assert all(b > a for a, b in zip(dec, dec[1:]))
+
+
+def _blend_one_texel(samples, h=0.97, start_word=0):
+    """Feed a sample sequence to one irradiance texel and one depth texel."""
+    m = len(samples)
+    rec = np.zeros((max(m, 1), 4), np.float32)
+    rec[:m, 0] = rec[:m, 1] = rec[:m, 2] = samples
+    rec[:m, 3] = samples
+    irr = np.full(36, start_word, np.uint32)
+    dep = np.full(196, start_word, np.uint32)
+    zeros = np.zeros(max(m, 1), np.uint16)
+    oracle.packed_blend([m], [0], rec, zeros, zeros, 6, 14, 1.0, oracle.TAU_MAX,
+                        oracle.packed_alpha_table(h), irr, dep)
+    return irr, dep
+
+
+def test_packed_dark_samples_reach_zero():
+    # the paper's reason for round-down: low samples pull a texel to zero
+    full = (511 | (511 << 9) | (255 << 18) | (63 << 26))
+    irr, _ = _blend_one_texel(np.zeros(4000, np.float32), start_word=full)
+    assert irr[0] & 0x3FFFFFF == 0 and irr[0] >> 26 == 63
+
+
+def test_packed_constant_input_fixed_point_and_count():
+    h = 0.97
+    for x in (0.02, 0.3, 1.0, 4.0):
+        for m in (1, 5, 40, 600):
+            irr, dep = _blend_one_texel(np.full(m, x, np.float32), h)
+            assert irr[0] >> 26 == min(m, 63) and dep[0] >> 26 == min(m, 63)
+            assert np.all(irr[1:] == 0) and np.all(dep[1:] == 0)
+            vals, _ = oracle.unpack_words(irr[:1], oracle.PACK_IRR)
+            q = int(irr[0] & 0x1FF)
+            d, d_next = vals[0, 0], oracle.pack_decode(q + 1, 5.0, 15.0, 9)
+            assert d <= x * (1 + 1e-6)
+            if m == 1:
+                assert q == oracle.pack_encode(x, 5.0, 15.0, 9)  # first sample: weight 1
+            else:
+                # a fixed point of the quantised average lies below x by less
+                # than one code step divided by the step weight
+                a = max(1.0 / min(m, 63), 1.0 - h)
+                assert x - d <= (d_next - d) / a * (1 + 1e-5)
