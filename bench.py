@@ -40,11 +40,12 @@ WORKLOADS = {
 }
 
 
-def blend_bytes(P, R, fp16):
+def blend_bytes(P, R, storage):
     """Algorithmic HBM bytes of one blend launch: per probe read the interior
     texels (36 x 12 + 196 x 8 B FP32), write full tiles (64 x 12 + 256 x 8 B),
-    read+write counts (2 x 232 B); FP16 halves the texel bytes; 16 B per ray."""
-    per_probe = 2872 if fp16 else 5280
+    read+write counts (2 x 232 B); FP16 halves the texel bytes; packed words
+    (counts inside) read 232 x 4 B and write 320 x 4 B; 16 B per ray."""
+    per_probe = {"fp32": 5280, "fp16": 2872, "packed": 2208}[storage]
     return P * per_probe + 16 * R
 
 
@@ -319,7 +320,7 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "packed"])
     ap.add_argument("--tuning", default=None,
                     help="JSON launch tuning to use instead of the autotuner")
     ap.add_argument("--skip-uniform", action="store_true")
@@ -343,8 +344,7 @@ def main():
     cfg = WORKLOADS[args.workload]
     sc = scenes.box_field() if args.workload == "box_field" else scenes.tunnel()
     sc.frames = 61  # light_frame() walks frames 0..60 back and forth
-    fp16 = args.storage == "fp16"
-    storage = adgi.ADGI_FP16 if fp16 else adgi.ADGI_FP32
+    storage = {"fp32": adgi.ADGI_FP32, "fp16": adgi.ADGI_FP16, "packed": adgi.ADGI_PACKED}[args.storage]
     P = sc.num_probes
     max_rays = max(cfg["budget"], P * cfg["uniform_equal_rays"])
     print(f"[bench] workload={args.workload} P={P} tris={sc.num_triangles} B={cfg['budget']}",
@@ -399,7 +399,7 @@ def main():
     trace_ms, blend_ms = stages_a[4], stages_a[5]
     ops = tw["box_tests"] * OPS_PER_BOX + tw["tri_tests"] * OPS_PER_TRI
     trace_tops = ops / (trace_ms * 1e-3) / 1e12
-    bbytes = blend_bytes(P, R, fp16)
+    bbytes = blend_bytes(P, R, args.storage)
     blend_gbs = bbytes / (blend_ms * 1e-3) / 1e9
     h_trace = source_hash("trace.hip", "adgi_device.hpp", "adgi_layout.hpp", "bvh_build.cpp")
     h_blend = source_hash("blend.hip", "adgi_device.hpp")

@@ -64,7 +64,13 @@ typedef enum {
   ADGI_ERR_DEVICE = -6         /* a HIP call failed; sticky until destroy         */
 } adgi_status;
 
-enum { ADGI_FP32 = 0, ADGI_FP16 = 1 };                       /* texel storage */
+/* Texel storage. ADGI_PACKED is the paper's 32-bit texel (Sec. 4.5-4.6, eq.
+ * rgbEnc, App. B): irradiance R9 G9 B8 + count N6, each colour channel
+ * u = min(ln(15 v + 1), 5) / 5 stored as floor(u (2^bits - 1)); depth tau13 +
+ * tau^2_13 + N6 with (beta, gamma) = (5, 15) and (8, 20); counts saturate at
+ * 63; every sample decodes, updates and re-encodes its texel (binary32
+ * arithmetic). Needs tiles 8/16 or 16/16. */
+enum { ADGI_FP32 = 0, ADGI_FP16 = 1, ADGI_PACKED = 2 };
 enum { ADGI_SCENE_REBUILD = 0, ADGI_SCENE_REFIT = 1 };      /* scene update mode */
 enum { ADGI_DEBUG_ARRAYS = 1u << 0 };                        /* volume flags */
 enum { ADGI_MAX_LIGHTS = 8 };
@@ -84,7 +90,7 @@ typedef struct {
   int32_t dims[3];            /* >= 1 each; P = product, P <= 2^24               */
   int32_t irr_res;            /* irradiance tile side incl. border, 3..34 (8)    */
   int32_t depth_res;          /* depth tile side incl. border, 3..34 (16)        */
-  int32_t storage;            /* ADGI_FP32 or ADGI_FP16                           */
+  int32_t storage;            /* ADGI_FP32, ADGI_FP16 or ADGI_PACKED              */
   float hysteresis;           /* h in [0, 1): step = max(1/(N+1), 1-h) (0.97)    */
   float tau_max;              /* depth clamp in units of s ((e^5-1)/15)          */
   int64_t max_rays_per_frame; /* capacity of the per-frame ray buffers, < 2^31   */
@@ -137,8 +143,10 @@ typedef struct {
 } adgi_update_stats;
 
 /* Readback destinations (host). NULL fields are skipped. Texel arrays are
- * FP32 whatever the storage (FP16 is widened exactly). Debug arrays need
- * ADGI_DEBUG_ARRAYS and hold the last frame. */
+ * FP32 whatever the storage (FP16 is widened exactly, packed words decoded
+ * on the host); with ADGI_PACKED the counts come from the words and the raw
+ * words are available too. Debug arrays need ADGI_DEBUG_ARRAYS and hold the
+ * last frame. */
 typedef struct {
   float* irradiance;          /* [P][irr_res][irr_res][3]                          */
   float* depth;               /* [P][depth_res][depth_res][2] (tau, tau^2)         */
@@ -157,6 +165,8 @@ typedef struct {
   uint16_t* q10_rad;          /* [P][8] pilot radiance code of the last frame      */
   float* frame_rotation;      /* [9] row-major rotation of the last frame          */
   int64_t num_rays;           /* out: R of the last frame                           */
+  uint32_t* irr_words;        /* ADGI_PACKED: [P][irr_res][irr_res] raw words      */
+  uint32_t* depth_words;      /* ADGI_PACKED: [P][depth_res][depth_res] raw words  */
 } adgi_probe_readback;
 
 /* Create a volume. desc/alloc are host, copied. hip_stream (hipStream_t or

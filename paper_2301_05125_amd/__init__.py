@@ -26,7 +26,7 @@ STATUS = {0: "ADGI_OK", -1: "ADGI_ERR_INVALID_ARG", -2: "ADGI_ERR_OUT_OF_MEMORY"
           -6: "ADGI_ERR_DEVICE"}
 (ADGI_ERR_INVALID_ARG, ADGI_ERR_OUT_OF_MEMORY, ADGI_ERR_BUDGET, ADGI_ERR_NO_SCENE,
  ADGI_ERR_TOPOLOGY, ADGI_ERR_DEVICE) = -1, -2, -3, -4, -5, -6
-ADGI_FP32, ADGI_FP16 = 0, 1
+ADGI_FP32, ADGI_FP16, ADGI_PACKED = 0, 1, 2
 ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
 ADGI_DEBUG_ARRAYS = 1
 MAX_LIGHTS = 8
@@ -86,7 +86,8 @@ class ProbeReadback(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "irradiance", "depth", "irr_count", "depth_count", "rays_per_probe", "score",
         "ray_offsets", "hit_tri", "shadow_bits", "irr_bin", "depth_bin", "ray_record",
-        "q10_vis", "q10_rad", "frame_rotation")] + [("num_rays", C.c_int64)]
+        "q10_vis", "q10_rad", "frame_rotation")] + [("num_rays", C.c_int64)] + \
+        [("irr_words", C.c_void_p), ("depth_words", C.c_void_p)]
 
 
 class TraceWork(C.Structure):
@@ -334,6 +335,9 @@ class Volume:
         out["q10_vis"] = np.zeros(P * 8, np.uint16)
         out["q10_rad"] = np.zeros(P * 8, np.uint16)
         out["frame_rotation"] = np.zeros(9, np.float32)
+        if d.storage == ADGI_PACKED:
+            out["irr_words"] = np.zeros((P, gi, gi), np.uint32)
+            out["depth_words"] = np.zeros((P, gd, gd), np.uint32)
         for k, a in out.items():
             setattr(rb, k, _ptr(a))
         _check(lib().adgi_read_probes(self.h, C.byref(rb)))

@@ -40,7 +40,8 @@ struct BlendIO {
 // chunk = 0 selects the wave-per-probe kernel (tile sizes 8/16 and 16/16) with
 // `grid` workgroups walking the allocation's probe order; otherwise one
 // workgroup per probe with `chunk` rays staged per step.
-hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk,
+// storage: ADGI_FP32, ADGI_FP16 or ADGI_PACKED (wave kernel only)
+hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
                         int grid = 0);
 bool blend_wave_supported(const VolumeView& v);
 size_t blend_lds_bytes(const VolumeView& v, int chunk);

@@ -461,6 +461,152 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
     blend_probe_wave<RI, RD, HALF>(v, io, v.order[q], wbase, tab, alpha);
 }
 
+// ---------------------------------------------------------------------------
+// Packed 32-bit texels: the same wave-per-probe walk, with each interior
+// texel's word in its owner lane's registers. A sample decodes the word,
+// applies the moving average in binary32 and re-encodes it (the paper's
+// per-sample update of Alg. AtomicMovingAvg; a probe belongs to one wave, so
+// no compare-and-swap is needed). Counts saturate at 63 (6 bits).
+__device__ __forceinline__ uint32_t packed_rgb(uint32_t w, float4 r, const float* alpha) {
+  uint32_t N = w >> 26;
+  const float al = alpha[N];
+  const float o0 = pk_decode(w & 0x1FFu, 5.0f, 15.0f, 9);
+  const float o1 = pk_decode((w >> 9) & 0x1FFu, 5.0f, 15.0f, 9);
+  const float o2 = pk_decode((w >> 18) & 0xFFu, 5.0f, 15.0f, 8);
+  const uint32_t c0 = pk_encode(fmaf(al, r.x - o0, o0), 5.0f, 15.0f, 9);
+  const uint32_t c1 = pk_encode(fmaf(al, r.y - o1, o1), 5.0f, 15.0f, 9);
+  const uint32_t c2 = pk_encode(fmaf(al, r.z - o2, o2), 5.0f, 15.0f, 8);
+  N = N < 63u ? N + 1u : 63u;
+  return c0 | (c1 << 9) | (c2 << 18) | (N << 26);
+}
+
+__device__ __forceinline__ uint32_t packed_tau(uint32_t w, float t, float inv_s, float tmax, const float* alpha) {
+  uint32_t N = w >> 26;
+  const float al = alpha[N];
+  const float tau = fminf(t * inv_s, tmax);
+  const float p0 = pk_decode(w & 0x1FFFu, 5.0f, 15.0f, 13);
+  const float p1 = pk_decode((w >> 13) & 0x1FFFu, 8.0f, 20.0f, 13);
+  const uint32_t d0 = pk_encode(fmaf(al, tau - p0, p0), 5.0f, 15.0f, 13);
+  const uint32_t d1 = pk_encode(fmaf(al, tau * tau - p1, p1), 8.0f, 20.0f, 13);
+  N = N < 63u ? N + 1u : 63u;
+  return d0 | (d1 << 13) | (N << 26);
+}
+
+template <int RI, int RD>
+__device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
+                                   const uint16_t* tab, const float* alpha) {
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
+  const int lane = threadIdx.x & 63;
+  float4* rec_s = (float4*)wbase;
+  unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
+  const FrameParams& fp = *v.fp;
+  const uint32_t* irr_in = (const uint32_t*)io.irr_in + (size_t)i * GI * GI;
+  const uint32_t* dep_in = (const uint32_t*)io.dep_in + (size_t)i * GD * GD;
+  uint32_t wi[SI], wd[SD];
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    wi[s] = 0u;
+    if (k < NI) {
+      const int iy = k / RI, ix = k - iy * RI;
+      wi[s] = irr_in[(iy + 1) * GI + ix + 1];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    wd[s] = 0u;
+    if (k < ND) {
+      const int iy = k / RD, ix = k - iy * RD;
+      wd[s] = dep_in[(iy + 1) * GD + ix + 1];
+    }
+  }
+  const uint32_t off = v.offsets[i];
+  const uint32_t n = v.offsets[i + 1] - off;
+  const float inv_s = 1.0f / v.s_diag;
+  const float tmax = v.tau_max;
+  float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+  if ((uint32_t)lane < n) nxt = v.rec[off + lane];
+  for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
+    const uint32_t m = min(64u, n - c0);
+    const float4 cur = nxt;
+    if (c0 + 64u + (uint32_t)lane < n) nxt = v.rec[off + c0 + 64u + lane];
+    for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
+    wave_sync();
+    if ((uint32_t)lane < m) {
+      const uint32_t j = c0 + (uint32_t)lane;
+      rec_s[lane] = cur;
+      const float2 uv = oct_encode(sf_direction(j, n, fp.R));
+      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
+      atomicOr(&mask[bI], 1ull << lane);
+      atomicOr(&mask[NI + bD], 1ull << lane);
+      if (fp.debug) {
+        v.dbg_ibin[off + j] = (uint16_t)bI;
+        v.dbg_dbin[off + j] = (uint16_t)bD;
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < SI; ++s) {
+      const int k = lane + 64 * s;
+      unsigned long long mk = k < NI ? mask[k] : 0ull;
+      while (mk) {
+        const int j = __ffsll((long long)mk) - 1;
+        mk &= mk - 1ull;
+        wi[s] = packed_rgb(wi[s], rec_s[j], alpha);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SD; ++s) {
+      const int k = lane + 64 * s;
+      unsigned long long mk = k < ND ? mask[NI + k] : 0ull;
+      while (mk) {
+        const int j = __ffsll((long long)mk) - 1;
+        mk &= mk - 1ull;
+        wd[s] = packed_tau(wd[s], rec_s[j].w, inv_s, tmax, alpha);
+      }
+    }
+    wave_sync();
+  }
+  // stage the interior words, then write both tiles with the border fold
+  uint32_t* stW = (uint32_t*)wbase;
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    if (k < NI) stW[k] = wi[s];
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    if (k < ND) stW[NI + k] = wd[s];
+  }
+  wave_sync();
+  uint32_t* irr_out = (uint32_t*)io.irr_out + (size_t)i * GI * GI;
+  uint32_t* dep_out = (uint32_t*)io.dep_out + (size_t)i * GD * GD;
+  // the fold table maps tile channel elements to interior channel elements;
+  // channel 0 of a texel gives its interior texel
+  for (int f = lane; f < GI * GI; f += 64) irr_out[f] = stW[tab[3 * f] / 3];
+  for (int f = lane; f < GD * GD; f += 64) dep_out[f] = stW[NI + tab[GI * GI * 3 + 2 * f] / 2];
+  wave_sync();
+}
+
+template <int RI, int RD>
+__global__ __launch_bounds__(256) void blend_packed_kernel(VolumeView v, BlendIO io) {
+  using W = WaveTile<RI, RD>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
+  float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
+  build_fold_tables<RI, RD>(tab);
+  for (int k = threadIdx.x; k < 256; k += blockDim.x)
+    alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
+  __syncthreads();
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
+  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
+    blend_probe_packed<RI, RD>(v, io, v.order[q], wbase, tab, alpha);
+}
+
 bool blend_wave_supported(const VolumeView& v) {
   return (v.irr_res == 8 && v.dep_res == 16) || (v.irr_res == 16 && v.dep_res == 16);
 }
@@ -470,23 +616,26 @@ size_t blend_lds_bytes(const VolumeView& v, int chunk) {
 }
 
 template <int RI, int RD>
-static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int grid) {
+static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int grid) {
   using W = WaveTile<RI, RD>;
   const size_t lds = W::kBlockBytes;
-  if (fp16)
+  if (storage == ADGI_PACKED)
+    hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(256), lds, s, v, io);
+  else if (storage == ADGI_FP16)
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
   else
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
 }
 
-hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, bool fp16, int chunk,
+hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
                         int grid) {
-  if (chunk == 0) {  // wave-per-probe kernel in most-rays-first order
-    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, fp16, grid);
-    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, fp16, grid);
+  if (chunk == 0 || storage == ADGI_PACKED) {  // wave-per-probe kernel in most-rays-first order
+    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, storage, grid);
+    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, storage, grid);
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }
+  const bool fp16 = storage == ADGI_FP16;
   size_t lds = blend_lds_bytes(v, chunk);
   if (fp16)
     hipLaunchKernelGGL(blend_kernel<true>, dim3(v.P), dim3(256), lds, s, v, io, chunk);

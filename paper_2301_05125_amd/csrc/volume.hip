@@ -246,7 +246,7 @@ hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullp
   if ((e = mark(5)) != hipSuccess) return e;
   if (count_work) return hipSuccess;
   BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
-  if ((e = launch_blend(v, io, s, vol->desc.storage == ADGI_FP16, t.blend_chunk,
+  if ((e = launch_blend(v, io, s, vol->desc.storage, t.blend_chunk,
                         vol->num_cus * t.blend_blocks_per_cu)) != hipSuccess)
     return e;
   return mark(6);
@@ -305,6 +305,23 @@ void release(adgi_volume* vol) {
   if (vol->stream) (void)hipStreamDestroy(vol->stream);
 }
 
+// Bytes of one probe's irradiance / depth tile (with border) in HBM.
+size_t irr_tile_bytes(const adgi_volume_desc& d) {
+  const size_t g = (size_t)d.irr_res * d.irr_res;
+  return d.storage == ADGI_PACKED ? g * 4 : g * 3 * (d.storage == ADGI_FP16 ? 2 : 4);
+}
+size_t dep_tile_bytes(const adgi_volume_desc& d) {
+  const size_t g = (size_t)d.depth_res * d.depth_res;
+  return d.storage == ADGI_PACKED ? g * 4 : g * 2 * (d.storage == ADGI_FP16 ? 2 : 4);
+}
+
+// Host decode of a packed channel, (exp(beta q / qmax) - 1) / gamma, for the
+// FP32 readback view (the words themselves are the state).
+float packed_decode_host(uint32_t q, float beta, float gamma, int bits) {
+  const double qmax = (double)((1u << bits) - 1u);
+  return (float)((std::exp((double)beta * (double)q / qmax) - 1.0) / (double)gamma);
+}
+
 bool finite3(const float* x) { return std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]); }
 
 adgi_tuning default_tuning() {
@@ -338,8 +355,7 @@ struct Part {
 };
 std::vector<Part> state_parts(adgi_volume* vol) {
   const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res, ri = gi - 2, rd = gd - 2;
-  const size_t el = vol->desc.storage == ADGI_FP16 ? 2 : 4;
-  return {{vol->irr, P * gi * gi * 3 * el}, {vol->dep, P * gd * gd * 2 * el}, {vol->irr_n, P * ri * ri},
+  return {{vol->irr, irr_tile_bytes(vol->desc) * P}, {vol->dep, dep_tile_bytes(vol->desc) * P}, {vol->irr_n, P * ri * ri},
           {vol->dep_n, P * rd * rd},         {vol->v.qv[0], P * 16},           {vol->v.qv[1], P * 16},
           {vol->v.qr[0], P * 16},            {vol->v.qr[1], P * 16},           {vol->v.trig, P * 64},
           {vol->v.score, P * 8},             {vol->v.n, P * 4},                {vol->v.offsets, (P + 1) * 4}};
@@ -372,8 +388,10 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   if (P > (1 << 24)) return fail(ADGI_ERR_INVALID_ARG, "P = %lld exceeds 2^24", (long long)P);
   if (d->irr_res < 3 || d->irr_res > 34 || d->depth_res < 3 || d->depth_res > 34)
     return fail(ADGI_ERR_INVALID_ARG, "irr_res/depth_res must be in [3, 34]");
-  if (d->storage != ADGI_FP32 && d->storage != ADGI_FP16)
-    return fail(ADGI_ERR_INVALID_ARG, "storage must be ADGI_FP32 or ADGI_FP16");
+  if (d->storage != ADGI_FP32 && d->storage != ADGI_FP16 && d->storage != ADGI_PACKED)
+    return fail(ADGI_ERR_INVALID_ARG, "storage must be ADGI_FP32, ADGI_FP16 or ADGI_PACKED");
+  if (d->storage == ADGI_PACKED && !((d->irr_res == 8 && d->depth_res == 16) || (d->irr_res == 16 && d->depth_res == 16)))
+    return fail(ADGI_ERR_INVALID_ARG, "ADGI_PACKED needs tiles 8/16 or 16/16");
   if (!(d->hysteresis >= 0.f && d->hysteresis < 1.f))
     return fail(ADGI_ERR_INVALID_ARG, "hysteresis must be in [0, 1)");
   if (!(d->tau_max > 0.f) || !std::isfinite(d->tau_max))
@@ -417,7 +435,6 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   std::memset(vol->h_scene, 0, sizeof(SceneParams));
 
   const size_t gi = d->irr_res, gd = d->depth_res, ri = gi - 2, rd = gd - 2;
-  const size_t el = d->storage == ADGI_FP16 ? 2 : 4;
   const size_t R = (size_t)d->max_rays_per_frame;
   const bool dbg = d->flags & ADGI_DEBUG_ARRAYS;
   VolumeView& v = vol->v;
@@ -426,8 +443,8 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
     size_t bytes;
   };
   std::vector<Req> reqs = {
-      {&vol->irr, (size_t)P * gi * gi * 3 * el},
-      {&vol->dep, (size_t)P * gd * gd * 2 * el},
+      {&vol->irr, (size_t)P * irr_tile_bytes(*d)},
+      {&vol->dep, (size_t)P * dep_tile_bytes(*d)},
       {(void**)&vol->irr_n, (size_t)P * ri * ri},
       {(void**)&vol->dep_n, (size_t)P * rd * rd},
       {(void**)&v.fp, sizeof(FrameParams)},
@@ -805,18 +822,50 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
   HIP_TRY(vol, hipStreamSynchronize(vol->stream));
   const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res, ri = gi - 2, rd = gd - 2;
   const bool h = vol->desc.storage == ADGI_FP16;
-  auto copy_texels = [&](float* dst, const void* src, size_t count) -> hipError_t {
-    if (!h) return hipMemcpy(dst, src, count * 4, hipMemcpyDeviceToHost);
-    std::vector<uint16_t> tmp(count);
-    hipError_t e = hipMemcpy(tmp.data(), src, count * 2, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return e;
-    for (size_t k = 0; k < count; ++k) dst[k] = half_bits_to_float(tmp[k]);
-    return hipSuccess;
-  };
-  if (out->irradiance) HIP_TRY(vol, copy_texels(out->irradiance, vol->irr, P * gi * gi * 3));
-  if (out->depth) HIP_TRY(vol, copy_texels(out->depth, vol->dep, P * gd * gd * 2));
-  if (out->irr_count) HIP_TRY(vol, hipMemcpy(out->irr_count, vol->irr_n, P * ri * ri, hipMemcpyDeviceToHost));
-  if (out->depth_count) HIP_TRY(vol, hipMemcpy(out->depth_count, vol->dep_n, P * rd * rd, hipMemcpyDeviceToHost));
+  if (vol->desc.storage == ADGI_PACKED) {
+    if (out->irr_words || out->irradiance || out->irr_count) {
+      std::vector<uint32_t> w(P * gi * gi);
+      HIP_TRY(vol, hipMemcpy(w.data(), vol->irr, w.size() * 4, hipMemcpyDeviceToHost));
+      if (out->irr_words) std::memcpy(out->irr_words, w.data(), w.size() * 4);
+      for (size_t k = 0; out->irradiance && k < w.size(); ++k) {
+        out->irradiance[3 * k] = packed_decode_host(w[k] & 0x1FFu, 5.f, 15.f, 9);
+        out->irradiance[3 * k + 1] = packed_decode_host((w[k] >> 9) & 0x1FFu, 5.f, 15.f, 9);
+        out->irradiance[3 * k + 2] = packed_decode_host((w[k] >> 18) & 0xFFu, 5.f, 15.f, 8);
+      }
+      for (size_t i = 0; out->irr_count && i < P; ++i)
+        for (size_t y = 0; y < ri; ++y)
+          for (size_t x = 0; x < ri; ++x)
+            out->irr_count[(i * ri + y) * ri + x] = (uint8_t)(w[(i * gi + y + 1) * gi + x + 1] >> 26);
+    }
+    if (out->depth_words || out->depth || out->depth_count) {
+      std::vector<uint32_t> w(P * gd * gd);
+      HIP_TRY(vol, hipMemcpy(w.data(), vol->dep, w.size() * 4, hipMemcpyDeviceToHost));
+      if (out->depth_words) std::memcpy(out->depth_words, w.data(), w.size() * 4);
+      for (size_t k = 0; out->depth && k < w.size(); ++k) {
+        out->depth[2 * k] = packed_decode_host(w[k] & 0x1FFFu, 5.f, 15.f, 13);
+        out->depth[2 * k + 1] = packed_decode_host((w[k] >> 13) & 0x1FFFu, 8.f, 20.f, 13);
+      }
+      for (size_t i = 0; out->depth_count && i < P; ++i)
+        for (size_t y = 0; y < rd; ++y)
+          for (size_t x = 0; x < rd; ++x)
+            out->depth_count[(i * rd + y) * rd + x] = (uint8_t)(w[(i * gd + y + 1) * gd + x + 1] >> 26);
+    }
+  } else {
+    if (out->irr_words || out->depth_words) return fail(ADGI_ERR_INVALID_ARG, "raw words need ADGI_PACKED");
+    auto copy_texels = [&](float* dst, const void* src, size_t count) -> hipError_t {
+      if (!h) return hipMemcpy(dst, src, count * 4, hipMemcpyDeviceToHost);
+      std::vector<uint16_t> tmp(count);
+      hipError_t e = hipMemcpy(tmp.data(), src, count * 2, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return e;
+      for (size_t k = 0; k < count; ++k) dst[k] = half_bits_to_float(tmp[k]);
+      return hipSuccess;
+    };
+    if (out->irradiance) HIP_TRY(vol, copy_texels(out->irradiance, vol->irr, P * gi * gi * 3));
+    if (out->depth) HIP_TRY(vol, copy_texels(out->depth, vol->dep, P * gd * gd * 2));
+    if (out->irr_count) HIP_TRY(vol, hipMemcpy(out->irr_count, vol->irr_n, P * ri * ri, hipMemcpyDeviceToHost));
+    if (out->depth_count)
+      HIP_TRY(vol, hipMemcpy(out->depth_count, vol->dep_n, P * rd * rd, hipMemcpyDeviceToHost));
+  }
   if (out->rays_per_probe) HIP_TRY(vol, hipMemcpy(out->rays_per_probe, vol->v.n, P * 4, hipMemcpyDeviceToHost));
   if (out->score) HIP_TRY(vol, hipMemcpy(out->score, vol->v.score, P * 8, hipMemcpyDeviceToHost));
   std::vector<uint32_t> off(P + 1);
@@ -851,6 +900,8 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (t->blend_chunk == 0 && !blend_wave_supported(vol->v))
     return fail(ADGI_ERR_INVALID_ARG, "blend_chunk 0 (wave kernel) needs tiles 8/16 or 16/16");
+  if (t->blend_chunk != 0 && vol->desc.storage == ADGI_PACKED)
+    return fail(ADGI_ERR_INVALID_ARG, "ADGI_PACKED blends with the wave kernel (blend_chunk 0)");
   size_t lds = t->blend_chunk ? blend_lds_bytes(vol->v, t->blend_chunk) : 0;
   if (lds > 65536) return fail(ADGI_ERR_INVALID_ARG, "blend_chunk needs %zu bytes of LDS", lds);
   if (trace_lds_bytes(t->trace_block) > 65536)
@@ -983,10 +1034,9 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   }
   // scratch outputs so the blend candidates leave the state alone
   const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res;
-  const size_t el = vol->desc.storage == ADGI_FP16 ? 2 : 4;
   std::vector<void*> scratch;
-  void* so_irr = vol_alloc(vol, P * gi * gi * 3 * el, &scratch);
-  void* so_dep = vol_alloc(vol, P * gd * gd * 2 * el, &scratch);
+  void* so_irr = vol_alloc(vol, P * irr_tile_bytes(vol->desc), &scratch);
+  void* so_dep = vol_alloc(vol, P * dep_tile_bytes(vol->desc), &scratch);
   void* so_in = vol_alloc(vol, P * (gi - 2) * (gi - 2), &scratch);
   void* so_dn = vol_alloc(vol, P * (gd - 2) * (gd - 2), &scratch);
   auto cleanup = [&]() {
@@ -1060,11 +1110,12 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     if (err != hipSuccess) break;
     if (bc.chunk == 0 && !blend_wave_supported(vol->v)) continue;
     if (bc.chunk != 0 && blend_lds_bytes(vol->v, bc.chunk) > 65536) continue;
+    if (bc.chunk != 0 && vol->desc.storage == ADGI_PACKED) continue;
     BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, so_irr, so_dep, (uint8_t*)so_in, (uint8_t*)so_dn};
     float bm = INFINITY;
     for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
       if ((err = hipEventRecord(vol->ev_t0, s)) != hipSuccess) break;
-      if ((err = launch_blend(vol->v, io, s, vol->desc.storage == ADGI_FP16, bc.chunk,
+      if ((err = launch_blend(vol->v, io, s, vol->desc.storage, bc.chunk,
                               vol->num_cus * bc.bpc)) != hipSuccess)
         break;
       if ((err = hipEventRecord(vol->ev_t1, s)) != hipSuccess) break;

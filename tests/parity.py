@@ -73,8 +73,20 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
     if tuning:
         vol.set_tuning(**tuning)
     fp16 = storage == adgi.ADGI_FP16
+    packed = storage == adgi.ADGI_PACKED
     ora = oracle.OracleVolume(scene, seed=seed, fp16=fp16, probes=probes, use_bvh=use_bvh)
     sel = ora.probes
+    ri, rd = vol.desc.irr_res - 2, vol.desc.depth_res - 2
+    if packed:
+        # the packed words follow from the GPU's samples through the oracle's
+        # FP32 word update (the codes are FP32 decisions by the paper's precision)
+        pk_irr = np.zeros((len(sel), ri * ri), np.uint32)
+        pk_dep = np.zeros((len(sel), rd * rd), np.uint32)
+        spacing = np.asarray(vol.desc.spacing[:], np.float64)
+        s_diag = np.float32(np.sqrt(np.sum(spacing * spacing)))
+        pk_inv_s = float(np.float32(1.0) / s_diag)
+        pk_alpha = oracle.packed_alpha_table(vol.desc.hysteresis)
+        res_pk = {"packed_word_mismatch": 0, "packed_border_mismatch": 0}
     twin = (oracle.OracleVolume(scene, seed=seed, fp16=False, probes=probes, use_bvh=use_bvh)
             if fp64_twin else None)
     res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "max_rel_ray": 0.0,
@@ -112,6 +124,19 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
         gd = rb["depth"][sel]
         oi = ora.irradiance_tiles()
         od = ora.depth_tiles()
+        if packed:
+            oracle.packed_blend(rb["rays_per_probe"][sel], rb["ray_offsets"][sel], rb["ray_record"],
+                                rb["irr_bin"], rb["depth_bin"], ri, rd, pk_inv_s,
+                                float(np.float32(vol.desc.tau_max)), pk_alpha, pk_irr, pk_dep)
+            wi, wd = rb["irr_words"][sel], rb["depth_words"][sel]
+            res_pk["packed_word_mismatch"] += int(np.count_nonzero(
+                wi[:, 1:-1, 1:-1].reshape(len(sel), -1) != pk_irr)) + int(np.count_nonzero(
+                    wd[:, 1:-1, 1:-1].reshape(len(sel), -1) != pk_dep))
+            for q in range(len(sel)):
+                fi = oracle.fold_tile(pk_irr[q].astype(np.float64), ri, 1).reshape(ri + 2, ri + 2)
+                fd = oracle.fold_tile(pk_dep[q].astype(np.float64), rd, 1).reshape(rd + 2, rd + 2)
+                res_pk["packed_border_mismatch"] += int(np.count_nonzero(fi != wi[q])) + \
+                    int(np.count_nonzero(fd != wd[q]))
         ei, ed = rel_err(gi, oi), rel_err(gd, od)
         if fp16:
             # Both sides round to binary16 at the frame store, the GPU from FP32 and
@@ -126,11 +151,11 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             ei, ed = np.where(qi, 0.0, ei), np.where(qd, 0.0, ed)
         res["max_rel_irr"] = max(res["max_rel_irr"], float(ei.max(initial=0.0)))
         res["max_rel_depth"] = max(res["max_rel_depth"], float(ed.max(initial=0.0)))
-        ri, rd = scene_res(vol)
         cnt_i = rb["irr_count"][sel].reshape(len(sel), -1)
         cnt_d = rb["depth_count"][sel].reshape(len(sel), -1)
-        res["count_mismatch"] += int(np.count_nonzero(cnt_i != ora.irr_n)) + \
-            int(np.count_nonzero(cnt_d != ora.dep_n))
+        cap = 63 if packed else 255
+        res["count_mismatch"] += int(np.count_nonzero(cnt_i != np.minimum(ora.irr_n, cap))) + \
+            int(np.count_nonzero(cnt_d != np.minimum(ora.dep_n, cap)))
         if check_rays:
             base = rb["ray_offsets"][sel]
             n_sel = out["n"][sel]
@@ -159,6 +184,8 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
                 res["max_rel_ray"] = float(e[k])
                 res["worst_ray"] = {"gpu": g[k].tolist(), "oracle": o[k].tolist(),
                                     "tri": int(out["tri"][k]), "frame": f}
+    if packed:
+        res.update(res_pk)
     res["vs_oracle"] = texel_error_report(rb["irradiance"][sel], rb["depth"][sel],
                                           ora.irradiance_tiles(), ora.depth_tiles())
     res["mean_count"] = {"irradiance": float(ora.irr_n.mean()), "depth": float(ora.dep_n.mean())}

@@ -123,3 +123,34 @@ def test_fp16_storage_against_fp16_emulating_oracle():
                        storage=adgi.ADGI_FP16)
     assert res["mismatches"] == 0 and res["count_mismatch"] == 0, res
     assert res["max_rel_irr"] <= 2e-3 and res["max_rel_depth"] <= 2e-3, res
+
+
+def _assert_packed(res):
+    assert res["rotation_mismatch"] == 0 and res["mismatches"] == 0, res
+    assert res["alloc_mismatch"] == 0 and res["score_mismatch"] == 0, res
+    assert res["count_mismatch"] == 0, res
+    assert res["packed_word_mismatch"] == 0 and res["packed_border_mismatch"] == 0, res
+    assert res["max_rel_ray"] <= RAY_RGB_TOL and res["max_rel_t"] <= RAY_T_TOL, res
+
+
+def test_packed_words_cornell_uniform():
+    """Packed 32-bit texels: every word equals the oracle's FP32 word update
+    of the same samples, over 8 frames (counts saturate at 63)."""
+    import paper_2301_05125_amd as adgi
+    res = run_lockstep(scenes.cornell(), frames=8, adaptive=False, n_uniform=64,
+                       storage=adgi.ADGI_PACKED)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_packed(res)
+
+
+def test_packed_words_box_field_adaptive():
+    """Packed texels on the box field (adaptive, refit), 256 sampled probes,
+    four frames; the decoded texels' error against FP64 texels is reported."""
+    import paper_2301_05125_amd as adgi
+    sc = scenes.box_field()
+    probes = scenes.sample_probes(sc.num_probes, 256)
+    res = run_lockstep(sc, frames=4, adaptive=True, budget=1 << 23, n_min=8, n_max=2048,
+                       probes=probes, storage=adgi.ADGI_PACKED)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _report("box_field_packed", res)
+    _assert_packed(res)
