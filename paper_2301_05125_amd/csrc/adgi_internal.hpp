@@ -44,6 +44,8 @@ struct BlendIO {
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
                         int grid = 0);
 bool blend_wave_supported(const VolumeView& v);
+// Fills the table of decoded values of every packed code (v.pk_dec).
+hipError_t launch_packed_decode_table(float* dec, hipStream_t s);
 size_t blend_lds_bytes(const VolumeView& v, int chunk);
 
 // refit.hip

@@ -14,6 +14,8 @@ constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary s
 constexpr int kStackLds = 7;                    // traversal stack entries kept in LDS
 constexpr int kOrderBuckets = 32;               // blend order: 64-ray chunks per probe, capped
 constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
+constexpr int kPkDecIrr9 = 0, kPkDecIrr8 = 512, kPkDecTau = 768, kPkDecTau2 = 768 + 8192;
+constexpr int kPkDecSize = 768 + 2 * 8192;      // decoded values of all packed codes
 constexpr float kShadowOffset = 1e-4f;          // shadow origin offset, units of s
 constexpr float kShadowShorten = 1e-6f;         // relative shortening of shadow rays
 
@@ -113,6 +115,8 @@ struct VolumeView {
   uint32_t* blk_rank;         // per-block exclusive rank base among eligible probes
   uint32_t* blk_off;          // per-block exclusive ray offset
   int32_t* order;             // [P] blend order: most 64-ray chunks first
+  const float* pk_dec;        // packed storage: decoded value of every code
+                              // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
   int32_t* dbg_tri;           // [max_rays] or null

@@ -467,12 +467,30 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
 // applies the moving average in binary32 and re-encodes it (the paper's
 // per-sample update of Alg. AtomicMovingAvg; a probe belongs to one wave, so
 // no compare-and-swap is needed). Counts saturate at 63 (6 bits).
-__device__ __forceinline__ uint32_t packed_rgb(uint32_t w, float4 r, const float* alpha) {
+// Decoding goes through tables of pk_decode over every code (built once per
+// volume, bitwise the same values); the irradiance tables sit in LDS.
+__global__ void packed_decode_table_kernel(float* dec) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kPkDecSize) return;
+  float v;
+  if (k < kPkDecIrr8) v = pk_decode((uint32_t)k, 5.0f, 15.0f, 9);
+  else if (k < kPkDecTau) v = pk_decode((uint32_t)(k - kPkDecIrr8), 5.0f, 15.0f, 8);
+  else if (k < kPkDecTau2) v = pk_decode((uint32_t)(k - kPkDecTau), 5.0f, 15.0f, 13);
+  else v = pk_decode((uint32_t)(k - kPkDecTau2), 8.0f, 20.0f, 13);
+  dec[k] = v;
+}
+
+hipError_t launch_packed_decode_table(float* dec, hipStream_t s) {
+  hipLaunchKernelGGL(packed_decode_table_kernel, dim3((kPkDecSize + 255) / 256), dim3(256), 0, s, dec);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ uint32_t packed_rgb(uint32_t w, float4 r, const float* alpha, const float* dec_irr) {
   uint32_t N = w >> 26;
   const float al = alpha[N];
-  const float o0 = pk_decode(w & 0x1FFu, 5.0f, 15.0f, 9);
-  const float o1 = pk_decode((w >> 9) & 0x1FFu, 5.0f, 15.0f, 9);
-  const float o2 = pk_decode((w >> 18) & 0xFFu, 5.0f, 15.0f, 8);
+  const float o0 = dec_irr[kPkDecIrr9 + (w & 0x1FFu)];
+  const float o1 = dec_irr[kPkDecIrr9 + ((w >> 9) & 0x1FFu)];
+  const float o2 = dec_irr[kPkDecIrr8 + ((w >> 18) & 0xFFu)];
   const uint32_t c0 = pk_encode(fmaf(al, r.x - o0, o0), 5.0f, 15.0f, 9);
   const uint32_t c1 = pk_encode(fmaf(al, r.y - o1, o1), 5.0f, 15.0f, 9);
   const uint32_t c2 = pk_encode(fmaf(al, r.z - o2, o2), 5.0f, 15.0f, 8);
@@ -480,12 +498,13 @@ __device__ __forceinline__ uint32_t packed_rgb(uint32_t w, float4 r, const float
   return c0 | (c1 << 9) | (c2 << 18) | (N << 26);
 }
 
-__device__ __forceinline__ uint32_t packed_tau(uint32_t w, float t, float inv_s, float tmax, const float* alpha) {
+__device__ __forceinline__ uint32_t packed_tau(uint32_t w, float t, float inv_s, float tmax, const float* alpha,
+                                               const float* __restrict__ dec) {
   uint32_t N = w >> 26;
   const float al = alpha[N];
   const float tau = fminf(t * inv_s, tmax);
-  const float p0 = pk_decode(w & 0x1FFFu, 5.0f, 15.0f, 13);
-  const float p1 = pk_decode((w >> 13) & 0x1FFFu, 8.0f, 20.0f, 13);
+  const float p0 = dec[kPkDecTau + (w & 0x1FFFu)];
+  const float p1 = dec[kPkDecTau2 + ((w >> 13) & 0x1FFFu)];
   const uint32_t d0 = pk_encode(fmaf(al, tau - p0, p0), 5.0f, 15.0f, 13);
   const uint32_t d1 = pk_encode(fmaf(al, tau * tau - p1, p1), 8.0f, 20.0f, 13);
   N = N < 63u ? N + 1u : 63u;
@@ -494,7 +513,7 @@ __device__ __forceinline__ uint32_t packed_tau(uint32_t w, float t, float inv_s,
 
 template <int RI, int RD>
 __device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
-                                   const uint16_t* tab, const float* alpha) {
+                                   const uint16_t* tab, const float* alpha, const float* dec_irr) {
   using W = WaveTile<RI, RD>;
   constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
   const int lane = threadIdx.x & 63;
@@ -554,7 +573,7 @@ __device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i
       while (mk) {
         const int j = __ffsll((long long)mk) - 1;
         mk &= mk - 1ull;
-        wi[s] = packed_rgb(wi[s], rec_s[j], alpha);
+        wi[s] = packed_rgb(wi[s], rec_s[j], alpha, dec_irr);
       }
     }
 #pragma unroll
@@ -564,7 +583,7 @@ __device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i
       while (mk) {
         const int j = __ffsll((long long)mk) - 1;
         mk &= mk - 1ull;
-        wd[s] = packed_tau(wd[s], rec_s[j].w, inv_s, tmax, alpha);
+        wd[s] = packed_tau(wd[s], rec_s[j].w, inv_s, tmax, alpha, v.pk_dec);
       }
     }
     wave_sync();
@@ -598,13 +617,15 @@ __global__ __launch_bounds__(256) void blend_packed_kernel(VolumeView v, BlendIO
   uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
   float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
   build_fold_tables<RI, RD>(tab);
+  float* dec_irr = alpha + 256;  // kPkDecTau floats
   for (int k = threadIdx.x; k < 256; k += blockDim.x)
     alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
+  for (int k = threadIdx.x; k < kPkDecTau; k += blockDim.x) dec_irr[k] = v.pk_dec[k];
   __syncthreads();
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
   for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
-    blend_probe_packed<RI, RD>(v, io, v.order[q], wbase, tab, alpha);
+    blend_probe_packed<RI, RD>(v, io, v.order[q], wbase, tab, alpha, dec_irr);
 }
 
 bool blend_wave_supported(const VolumeView& v) {
@@ -620,7 +641,7 @@ static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, 
   using W = WaveTile<RI, RD>;
   const size_t lds = W::kBlockBytes;
   if (storage == ADGI_PACKED)
-    hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(256), lds + 4 * kPkDecTau, s, v, io);
   else if (storage == ADGI_FP16)
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
   else

@@ -467,6 +467,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.order, (size_t)P * 4},
       {(void**)&v.rec, R * 16},
   };
+  if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)kPkDecSize * 4});
   if (dbg) {
     reqs.push_back({(void**)&v.dbg_tri, R * 4});
     reqs.push_back({(void**)&v.dbg_shadow, R});
@@ -482,6 +483,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   }
   // zero the temporal state
   for (auto& r : reqs) CREATE_TRY(hipMemsetAsync(*r.p, 0, r.bytes, vol->stream));
+  if (d->storage == ADGI_PACKED) CREATE_TRY(launch_packed_decode_table((float*)v.pk_dec, vol->stream));
   CREATE_TRY(hipStreamSynchronize(vol->stream));
 #undef CREATE_TRY
   v.ox = d->origin[0];
