@@ -57,7 +57,7 @@ class Counts(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "hit_ties", "shadow_ties", "bin_ties", "q10_ties",
         "hit_mismatch", "shadow_mismatch", "bin_mismatch", "q10_mismatch",
-        "rays", "shadow_rays")]
+        "rays", "shadow_rays", "chain_ties", "chain_mismatch")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -132,6 +132,10 @@ def lib():
         L.orc_pack_decode.restype = C.c_float
         L.orc_pack_decode.argtypes = [C.c_uint32, C.c_float, C.c_float, C.c_int32]
         L.orc_packed_blend.restype = None
+        L.orc_chain_h.restype = C.c_double
+        L.orc_chain_frame.restype = None
+        L.orc_chain_probes_frame.restype = None
+        L.orc_chain_dir.restype = None
         L.orc_set_threads.restype = None
         _lib = L
     return _lib
@@ -266,6 +270,52 @@ def packed_blend(n, ray_base, rec, ibin, dbin, ri, rd, inv_s, tau_max, alpha, ir
     lib().orc_packed_blend(C.c_int32(len(n)), _p(n), _p(ray_base), _p(rec), _p(ibin), _p(dbin),
                            C.c_int32(ri), C.c_int32(rd), C.c_float(inv_s), C.c_float(tau_max),
                            _p(alpha), _p(irr_words), _p(dep_words))
+
+
+class ChainParams(C.Structure):
+    _fields_ = [("chains", C.c_int32), ("steps", C.c_int32), ("burn_in", C.c_int32),
+                ("sigma_pos", C.c_double), ("sigma_dir", C.c_double)]
+
+
+SIGMA_DIR = math.sqrt(math.pi / 256.0)  # the paper's angular step (Sec. 4.7)
+
+
+def chain_h(grid, qv, irr_prev, r: int, x) -> tuple:
+    """(h, nearest probe, tie) of the static chain's target at x = (p, uv)."""
+    x = np.ascontiguousarray(x, np.float64)
+    qv = np.ascontiguousarray(qv, np.uint16)
+    irr_prev = np.ascontiguousarray(irr_prev, np.float64)
+    pr, tie = C.c_int32(), C.c_int32()
+    h = lib().orc_chain_h(C.byref(grid), _p(qv), _p(irr_prev), C.c_int32(r), _p(x), C.byref(pr), C.byref(tie))
+    return float(h), int(pr.value), int(tie.value)
+
+
+def chain_frame(grid, params: ChainParams, seed: int, frame: int, qv, irr_prev, r: int, state,
+                init: bool, hint_accept=None, counts=None) -> dict:
+    """One frame of every chain (state [C][5] updated in place)."""
+    C_, M, K = params.chains, params.steps, params.burn_in
+    S = max(M - K - 1, 0)
+    qv = np.ascontiguousarray(qv, np.uint16)
+    irr_prev = np.ascontiguousarray(irr_prev, np.float64)
+    assert state.dtype == np.float64 and state.flags["C_CONTIGUOUS"] and state.shape == (C_, 5)
+    acc = np.zeros(max(C_ * M, 1), np.uint8)
+    sp = np.zeros(max(C_ * S, 1), np.int32)
+    suv = np.zeros((max(C_ * S, 1), 2), np.float64)
+    ha = None if hint_accept is None else np.ascontiguousarray(hint_accept, np.uint8)
+    cnt = counts if counts is not None else Counts()
+    lib().orc_chain_frame(C.byref(grid), C.byref(params), C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                          C.c_int32(frame), _p(qv), _p(irr_prev), C.c_int32(r), _p(state),
+                          C.c_int32(1 if init else 0), _p(ha), _p(acc), _p(sp), _p(suv), C.byref(cnt))
+    return {"accept": acc[:C_ * M], "sample_probe": sp[:C_ * S], "sample_uv": suv[:C_ * S]}
+
+
+def chain_order(sample_probe: np.ndarray, P: int):
+    """Samples grouped by probe, ascending sample index within a probe:
+    (permutation, samples per probe, first sample of each probe)."""
+    perm = np.argsort(np.asarray(sample_probe), kind="stable")
+    n = np.bincount(np.asarray(sample_probe, np.int64), minlength=P).astype(np.int32)
+    base = np.concatenate([[0], np.cumsum(n, dtype=np.int64)])[:-1]
+    return perm, n, base
 
 
 def allocate(score: np.ndarray, budget: int, n_min: int, n_max: int):
@@ -475,6 +525,43 @@ class OracleVolume:
         if keep_rays:
             out.update(rays=rays[:total], tri=tri[:total], shadow=sh[:total], irr_bin=ib[:total],
                        depth_bin=db[:total], ray_base=ray_base)
+        return out
+
+    def chain_update(self, frame: int, params: "ChainParams", state: np.ndarray, init: bool,
+                     beta: float = 5.0, hints: Optional[dict] = None) -> dict:
+        """One frame of the static Metropolis chain sampler: pilots (for
+        f_v), one frame of every chain against the previous frame's
+        irradiance, then each sample's two rays blended into its nearest
+        probe in sample order. Tracks every probe (the target reads any
+        probe's irradiance). ``state`` [C][5] is updated in place; ``hints``
+        may hold the GPU's qv/qr codes, accept decisions and per-ray
+        decisions (in the GPU's sorted sample order)."""
+        assert self.probes.shape[0] == self.P, "chain frames need every probe tracked"
+        hints = hints or {}
+        self.set_frame_inputs(frame)
+        qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"))
+        ri, rd = self.irr_res - 2, self.depth_res - 2
+        irr_prev = self.irr.copy()
+        cnt = Counts()
+        out = chain_frame(self.grid, params, self.seed, frame, qv, irr_prev, ri, state, init,
+                          hints.get("accept"), cnt)
+        perm, n, base = chain_order(out["sample_probe"], self.P)
+        suv = np.ascontiguousarray(out["sample_uv"][perm])
+
+        def h(name, dtype):
+            a = hints.get(name)
+            return None if a is None else np.ascontiguousarray(np.asarray(a)[:2 * len(perm)], dtype)
+
+        lib().orc_chain_probes_frame(
+            self.scene.ptr, C.byref(self.grid), self.P, _p(self.probes), _p(n), _p(base), _p(suv),
+            C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
+            _p(h("hit_tri", np.int32)), _p(h("shadow_bits", np.uint8)), _p(h("irr_bin", np.uint16)),
+            _p(h("depth_bin", np.uint16)), _p(self.irr), _p(self.irr_n), _p(self.dep), _p(self.dep_n),
+            C.byref(cnt))
+        for name, _ in Counts._fields_:
+            setattr(self.counts, name, getattr(self.counts, name) + getattr(cnt, name))
+        out.update(qv=qv, qr=qr, n=n, offsets=np.concatenate([base, [len(perm)]]), perm=perm,
+                   counts=cnt.as_dict())
         return out
 
     # views in the library's readback layout

@@ -1226,6 +1226,253 @@ void orc_packed_blend(int32_t count, const int32_t* n, const int64_t* ray_base, 
   }
 }
 
+/* ------------------------------------------------ Metropolis chains */
+
+static int near_frac(double f, double band) {
+  double r = f - floor(f);
+  return r < band || r > 1.0 - band;
+}
+
+void orc_chain_dir(const double uv[2], double d[3]) { orc_oct_decode(uv, d); }
+
+/* p within the box of probe centres, uv within [-1, 1]^2 (closed). */
+static int chain_in_domain(const orc_grid* g, const double x[5], int* tie) {
+  int in = 1, t = 0;
+  for (int a = 0; a < 3; ++a) {
+    double lo = g->origin[a], hi = g->origin[a] + (g->dims[a] - 1) * g->spacing[a];
+    double band = 1e-6 * g->spacing[a] + 1e-7 * fabs(x[a]);
+    if (x[a] < lo || x[a] > hi) in = 0;
+    if (fabs(x[a] - lo) <= band || fabs(x[a] - hi) <= band) t = 1;
+  }
+  for (int a = 3; a < 5; ++a) {
+    if (x[a] < -1.0 || x[a] > 1.0) in = 0;
+    if (fabs(fabs(x[a]) - 1.0) <= 1e-6) t = 1;
+  }
+  if (tie) *tie = t;
+  return in;
+}
+
+double orc_chain_h(const orc_grid* g, const uint16_t* qv, const double* irr_prev, int32_t r,
+                   const double x[5], int32_t* probe, int32_t* tie) {
+  int t = 0;
+  int32_t idx[3];
+  for (int a = 0; a < 3; ++a) {
+    double f = g->dims[a] > 1 ? (x[a] - g->origin[a]) / g->spacing[a] : 0.0;
+    int32_t i = (int32_t)floor(f + 0.5);
+    if (i < 0) i = 0;
+    if (i > g->dims[a] - 1) i = g->dims[a] - 1;
+    idx[a] = i;
+    if (g->dims[a] > 1 && near_frac(f + 0.5, 1e-5)) t = 1;
+  }
+  int32_t pr = idx[0] + g->dims[0] * (idx[1] + g->dims[1] * idx[2]);
+  if (probe) *probe = pr;
+  double d[3];
+  orc_oct_decode(x + 3, d);
+  int32_t k = (d[0] < 0.0 ? 1 : 0) | (d[1] < 0.0 ? 2 : 0) | (d[2] < 0.0 ? 4 : 0);
+  for (int a = 0; a < 3; ++a)
+    if (fabs(d[a]) < 1e-6) t = 1;
+  double f = (double)qv[8 * pr + k] / 1024.0;
+  if (f <= 0.0) {
+    if (tie) *tie = t;
+    return 0.0;
+  }
+  /* the texel one level coarser (2x2 interior texels) that holds uv */
+  int32_t m = r / 2, cell[2];
+  for (int a = 0; a < 2; ++a) {
+    double c = (x[3 + a] + 1.0) * 0.5 * m;
+    int32_t ci = (int32_t)floor(c);
+    if (ci > m - 1) ci = m - 1;
+    if (ci < 0) ci = 0;
+    cell[a] = ci;
+    if (near_frac(c, 1e-5) && c > 1e-5 && c < m - 1e-5) t = 1;
+  }
+  double rgb[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) {
+      const double* T = irr_prev + 3 * ((size_t)pr * r * r + (size_t)(2 * cell[1] + b) * r + 2 * cell[0] + a);
+      for (int ch = 0; ch < 3; ++ch) rgb[ch] += T[ch];
+    }
+  double lum = 0.2126 * (rgb[0] / 4.0) + 0.7152 * (rgb[1] / 4.0) + 0.0722 * (rgb[2] / 4.0);
+  if (tie) *tie = t;
+  return exp(fmin(lum / f, 1.0)) * f;
+}
+
+void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, int32_t frame,
+                     const uint16_t* qv, const double* irr_prev, int32_t r, double* state, int32_t init,
+                     const uint8_t* hint_accept, uint8_t* accept, int32_t* sample_probe,
+                     double* sample_uv, orc_counts* counts) {
+  const int32_t C = cp->chains, M = cp->steps, K = cp->burn_in;
+  const int32_t S = M - K - 1 > 0 ? M - K - 1 : 0;
+  int64_t ties = 0, mism = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : ties, mism)
+  for (int32_t c = 0; c < C; ++c) {
+    double* x = state + 5 * (size_t)c;
+    if (init) {
+      uint64_t key = orc_key(seed, ORC_TAG_CHAININIT, (uint64_t)(uint32_t)c, 0, 0);
+      for (int a = 0; a < 3; ++a)
+        x[a] = g->origin[a] + orc_uniform(key, (uint64_t)(a + 1)) * (g->dims[a] - 1) * g->spacing[a];
+      x[3] = 2.0 * orc_uniform(key, 4) - 1.0;
+      x[4] = 2.0 * orc_uniform(key, 5) - 1.0;
+    }
+    int32_t pr = 0;
+    int tie_y = 0, dtie = 0;
+    double y = 0.0;
+    if (chain_in_domain(g, x, &dtie)) y = orc_chain_h(g, qv, irr_prev, r, x, &pr, &tie_y);
+    tie_y |= dtie;
+    for (int32_t i = 0; i < M; ++i) {
+      uint64_t key = orc_key(seed, ORC_TAG_CHAIN, (uint64_t)(uint32_t)c, (uint64_t)(uint32_t)frame,
+                             (uint64_t)(uint32_t)i);
+      double u[8];
+      for (int q = 1; q <= 7; ++q) u[q] = orc_uniform(key, (uint64_t)q);
+      double gs[6];
+      for (int q = 0; q < 3; ++q) {
+        double rr = sqrt(-2.0 * log(1.0 - u[2 * q + 1]));
+        double th = 2.0 * PI * u[2 * q + 2];
+        gs[2 * q] = rr * cos(th);
+        gs[2 * q + 1] = rr * sin(th);
+      }
+      double xp[5];
+      for (int a = 0; a < 3; ++a) xp[a] = x[a] + cp->sigma_pos * g->spacing[a] * gs[a];
+      xp[3] = x[3] + cp->sigma_dir * gs[3];
+      xp[4] = x[4] + cp->sigma_dir * gs[4];
+      int ptie = 0, ttie = 0;
+      int in = chain_in_domain(g, xp, &ttie);
+      double yp = 0.0;
+      int32_t prp = pr;
+      if (in) yp = orc_chain_h(g, qv, irr_prev, r, xp, &prp, &ptie);
+      ptie |= ttie;
+      int acc = in && (y <= 0.0 || u[7] * y <= yp);
+      int tie = ptie || tie_y || (in && y > 0.0 && fabs(u[7] * y - yp) <= 1e-4 * fmax(yp, u[7] * y)) ||
+                (in && y > 0.0 && y <= 1e-12);
+      if (hint_accept) {
+        int gd = hint_accept[(size_t)c * M + i] != 0;
+        if (gd != acc) {
+          if (tie) {
+            ++ties;
+            acc = gd;
+            if (acc && !in) acc = 0;  /* never leave the domain */
+          } else {
+            ++mism;
+          }
+        }
+      }
+      if (acc) {
+        for (int a = 0; a < 5; ++a) x[a] = xp[a];
+        y = yp;
+        pr = prp;
+        tie_y = ptie;
+      }
+      if (accept) accept[(size_t)c * M + i] = (uint8_t)acc;
+      if (i > K) {
+        size_t s = (size_t)c * S + (size_t)(i - K - 1);
+        if (sample_probe) sample_probe[s] = pr;
+        if (sample_uv) {
+          sample_uv[2 * s] = x[3];
+          sample_uv[2 * s + 1] = x[4];
+        }
+      }
+    }
+  }
+  if (counts) {
+    counts->chain_ties += ties;
+    counts->chain_mismatch += mism;
+  }
+}
+
+void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
+                            const int32_t* nsamp, const int64_t* sample_base, const double* sample_uv,
+                            const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
+                            double tau_max, const int32_t* hint_tri, const uint8_t* hint_shadow,
+                            const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
+                            uint8_t* irr_n, double* dep, uint8_t* dep_n, orc_counts* counts) {
+  const int32_t ri = irr_r - 2, rd = dep_r - 2;
+  orc_counts total;
+  memset(&total, 0, sizeof(total));
+#pragma omp parallel
+  {
+    orc_counts loc;
+    memset(&loc, 0, sizeof(loc));
+#pragma omp for schedule(dynamic, 4)
+    for (int32_t q = 0; q < count; ++q) {
+      double o[3];
+      orc_probe_pos(g, probes[q], o);
+      double* I = irr + (size_t)q * ri * ri * 3;
+      double* D = dep + (size_t)q * rd * rd * 2;
+      uint8_t* IN = irr_n + (size_t)q * ri * ri;
+      uint8_t* DN = dep_n + (size_t)q * rd * rd;
+      int64_t ties[2] = {0, 0}, mism[2] = {0, 0};
+      for (int32_t j = 0; j < nsamp[q]; ++j) {
+        const int64_t k = sample_base[q] + j;
+        double d[3], nd[3];
+        orc_chain_dir(sample_uv + 2 * k, d);
+        for (int a = 0; a < 3; ++a) nd[a] = -d[a];
+        /* irradiance: the ray along d, shaded as a probe ray */
+        orc_ray ra, rb;
+        orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[2 * k] : -2,
+                      hint_shadow ? (int32_t)hint_shadow[2 * k] : -1, &ra, ties, mism);
+        loc.rays += 1;
+        if (ra.tri >= 0 && ra.front) loc.shadow_rays += s->nl;
+        int32_t ti = 0;
+        int32_t ki = orc_oct_bin(d, ri, tol ? tol->bin_eps : 0.0, &ti);
+        if (hint_ibin && hint_ibin[2 * k] != ki) {
+          if (ti && hint_ibin[2 * k] < ri * ri) {
+            loc.bin_ties++;
+            ki = hint_ibin[2 * k];
+          } else {
+            loc.bin_mismatch++;
+          }
+        }
+        double ai = orc_blend_alpha(IN[ki], hysteresis);
+        for (int c = 0; c < 3; ++c) I[3 * ki + c] += ai * (ra.rgb[c] - I[3 * ki + c]);
+        if (IN[ki] < 255) IN[ki]++;
+        /* visibility: the ray along -d, its distance into the depth texel of -d */
+        orc_shade_ray(s, o, nd, g->s, tol, hint_tri ? hint_tri[2 * k + 1] : -2, -1, &rb, ties, mism);
+        loc.rays += 1;
+        int32_t td = 0;
+        int32_t kd = orc_oct_bin(nd, rd, tol ? tol->bin_eps : 0.0, &td);
+        if (hint_dbin && hint_dbin[2 * k + 1] != kd) {
+          if (td && hint_dbin[2 * k + 1] < rd * rd) {
+            loc.bin_ties++;
+            kd = hint_dbin[2 * k + 1];
+          } else {
+            loc.bin_mismatch++;
+          }
+        }
+        double tau = isfinite(rb.t) ? fmin(rb.t / g->s, tau_max) : tau_max;
+        double ad = orc_blend_alpha(DN[kd], hysteresis);
+        D[2 * kd + 0] += ad * (tau - D[2 * kd + 0]);
+        D[2 * kd + 1] += ad * (tau * tau - D[2 * kd + 1]);
+        if (DN[kd] < 255) DN[kd]++;
+      }
+      loc.hit_ties += ties[0];
+      loc.shadow_ties += ties[1];
+      loc.hit_mismatch += mism[0];
+      loc.shadow_mismatch += mism[1];
+    }
+#pragma omp critical
+    {
+      total.hit_ties += loc.hit_ties;
+      total.shadow_ties += loc.shadow_ties;
+      total.bin_ties += loc.bin_ties;
+      total.hit_mismatch += loc.hit_mismatch;
+      total.shadow_mismatch += loc.shadow_mismatch;
+      total.bin_mismatch += loc.bin_mismatch;
+      total.rays += loc.rays;
+      total.shadow_rays += loc.shadow_rays;
+    }
+  }
+  if (counts) {
+    counts->hit_ties += total.hit_ties;
+    counts->shadow_ties += total.shadow_ties;
+    counts->bin_ties += total.bin_ties;
+    counts->hit_mismatch += total.hit_mismatch;
+    counts->shadow_mismatch += total.shadow_mismatch;
+    counts->bin_mismatch += total.bin_mismatch;
+    counts->rays += total.rays;
+    counts->shadow_rays += total.shadow_rays;
+  }
+}
+
 int32_t orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -41,6 +41,8 @@ uint64_t orc_key(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t c
 double   orc_uniform(uint64_t key, uint64_t q);   /* top 24 bits of mix(key^q) * 2^-24 */
 #define ORC_TAG_ROTATION 0x524F54ull  /* "ROT" */
 #define ORC_TAG_PILOT    0x50494Cull  /* "PIL" */
+#define ORC_TAG_CHAIN    0x4D4353ull  /* "MCS": a Metropolis step */
+#define ORC_TAG_CHAININIT 0x4D4349ull /* "MCI": a chain's first state */
 
 /* Per-frame rotation (Shoemake, Graphics Gems III 1992), FP64 -> FP32. */
 void orc_frame_rotation(uint64_t seed, int32_t frame, float R[9]);
@@ -116,6 +118,7 @@ typedef struct {
   int64_t hit_ties, shadow_ties, bin_ties, q10_ties;
   int64_t hit_mismatch, shadow_mismatch, bin_mismatch, q10_mismatch;
   int64_t rays, shadow_rays;
+  int64_t chain_ties, chain_mismatch;  /* Metropolis accept decisions */
 } orc_counts;
 
 /* ---- grid */
@@ -189,6 +192,54 @@ float orc_pack_decode(uint32_t q, float beta, float gamma, int32_t bits);
 void orc_packed_blend(int32_t count, const int32_t* n, const int64_t* ray_base, const float* rec,
                       const uint16_t* ibin, const uint16_t* dbin, int32_t ri, int32_t rd, float inv_s,
                       float tau_max, const float* alpha, uint32_t* irr, uint32_t* dep);
+
+/* ---- Metropolis chains over (position, direction) (Sec. 3.2, Alg.
+ * MarkovChainMT, Alg. MetropolisStep, Sec. 4.7: the static chain).
+ * State x = (p, uv): p in the box spanned by the probe centres, uv the
+ * octahedral coordinates of the direction in [-1, 1]^2. Target
+ * h = exp(min(g/f, 1)) f, f = Qv/1024 of the nearest probe's octant of the
+ * direction (the 10-bit f_v code of the current frame's pilots), g the
+ * luminance of that probe's irradiance averaged over the 2x2 texels (one
+ * level coarser) whose cell holds uv, from the previous frame; h = 0 where
+ * f = 0. Step i of frame t for chain c draws u1..u7 from key (seed, MCS, c,
+ * t, i): Box-Muller normals (u1,u2) -> g1,g2, (u3,u4) -> g3,g4, (u5,u6) -> g5,
+ * proposal p' = p + sigma_pos*spacing*(g1,g2,g3), uv' = uv + sigma_dir*(g4,g5);
+ * a proposal outside the domain is rejected; otherwise it is accepted when
+ * the current density is 0 or u7*h(x) <= h(x'). Steps i > burn_in emit the
+ * state after the step: S = steps - burn_in - 1 samples per chain and frame,
+ * sample c*S + i - burn_in - 1, as (nearest probe, uv). */
+typedef struct {
+  int32_t chains, steps, burn_in;
+  double sigma_pos, sigma_dir;
+} orc_chain_params;
+/* probe: nearest probe; tie: the evaluation sits within tolerance of a
+ * discrete boundary (domain, nearest probe, octant, coarse cell). */
+double orc_chain_h(const orc_grid* g, const uint16_t* qv, const double* irr_prev, int32_t r,
+                   const double x[5], int32_t* probe, int32_t* tie);
+/* One frame of every chain. state [C][5] (p, uv) in/out; init != 0 draws the
+ * first states from key (seed, MCI, c, 0, 0) (p uniform in the box, uv
+ * uniform in the square). irr_prev: interior irradiance [P][r*r][3].
+ * hint_accept [C][steps] (optional): the GPU's decisions, adopted where the
+ * oracle's decision is a tie (counted) and counted as mismatches elsewhere.
+ * Outputs (optional): accept [C][steps], sample_probe [C*S], sample_uv [C*S][2]. */
+void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, int32_t frame,
+                     const uint16_t* qv, const double* irr_prev, int32_t r, double* state, int32_t init,
+                     const uint8_t* hint_accept, uint8_t* accept, int32_t* sample_probe,
+                     double* sample_uv, orc_counts* counts);
+/* Octahedral decode of uv to a unit direction (O1). */
+void orc_chain_dir(const double uv[2], double d[3]);
+/* Chain samples of the listed probes, each probe's samples in ascending
+ * sample order: ray along d(uv) from the probe centre (shaded, as probe rays)
+ * updates the irradiance texel of d; ray along -d updates the depth texel of
+ * -d with its distance (the visibility ray of Sec. 4.7). Samples of list
+ * entry q: [sample_base[q], sample_base[q] + nsamp[q]) of sample_uv; hints
+ * and ray outputs indexed 2k (ray along d) and 2k+1 (along -d). */
+void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
+                            const int32_t* nsamp, const int64_t* sample_base, const double* sample_uv,
+                            const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
+                            double tau_max, const int32_t* hint_tri, const uint8_t* hint_shadow,
+                            const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
+                            uint8_t* irr_n, double* dep, uint8_t* dep_n, orc_counts* counts);
 
 int32_t orc_num_threads(void);
 /* Threads for the following OpenMP regions (timing only). */

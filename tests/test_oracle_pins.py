@@ -732,3 +732,103 @@ def test_packed_constant_input_fixed_point_and_count():
                 # than one code step divided by the step weight
                 a = max(1.0 / min(m, 63), 1.0 - h)
                 assert x - d <= (d_next - d) / a * (1 + 1e-5)
+
+
+# ------------------------------------------------------- Metropolis chains
+# The static chain (Alg. MarkovChainMT with Alg. MetropolisStep, target
+# h = exp(min(g/f, 1)) f of Sec. 4.7). Pins: the properties of h the paper
+# states (g is trusted only where f is low: h in [f, e f], h = f without
+# feedback, h = e f once g >= f, zero where f is zero), and the theorem that
+# makes the sampler correct: a symmetric random walk with Metropolis
+# acceptance and rejection outside the domain has h (restricted to the domain)
+# as its stationary density. Probe cells and octants are given different f;
+# the chains' occupancy must match their h-weighted volumes.
+
+def _chain_grid(dims=(2, 2, 2)):
+    return oracle.make_grid(np.zeros(3, np.float32), np.ones(3, np.float32),
+                            np.asarray(dims, np.int32))
+
+
+def test_chain_target_properties():
+    g = _chain_grid()
+    P, r = 8, 6
+    rng = np.random.default_rng(3)
+    qv = rng.integers(1, 1024, P * 8).astype(np.uint16)
+    qv[8 * 3 + 5] = 0
+    for gval in (0.0, 0.05, 0.3, 2.0):
+        irr = np.full((P, r * r * 3), gval)
+        for _ in range(200):
+            x = np.concatenate([rng.uniform(0, 1, 3), rng.uniform(-1, 1, 2)])
+            h, pr, tie = oracle.chain_h(g, qv, irr, r, x)
+            d = np.zeros(3)
+            oracle.lib().orc_chain_dir(oracle._p(np.ascontiguousarray(x[3:])), oracle._p(d))
+            k = int(d[0] < 0) | int(d[1] < 0) << 1 | int(d[2] < 0) << 2
+            assert pr == int(np.round(x[0])) + 2 * (int(np.round(x[1])) + 2 * int(np.round(x[2])))
+            f = qv[8 * pr + k] / 1024.0
+            if f == 0:
+                assert h == 0.0
+                continue
+            assert f * (1 - 1e-12) <= h <= math.e * f * (1 + 1e-12)
+            if gval == 0.0:
+                assert abs(h - f) <= 1e-12
+            if gval >= f:
+                assert abs(h - math.e * f) <= 1e-12 * h
+
+
+def _octant_of_uv(uv):
+    # signs of the decoded direction: x follows u, y follows v, z < 0 outside
+    # the diamond |u| + |v| <= 1
+    u, v = uv[:, 0], uv[:, 1]
+    return (u < 0).astype(int) | (v < 0).astype(int) << 1 | (np.abs(u) + np.abs(v) > 1).astype(int) << 2
+
+
+def test_chain_stationary_distribution():
+    g = _chain_grid()
+    P, r = 8, 6
+    rng = np.random.default_rng(11)
+    qv = rng.integers(64, 1024, P * 8).astype(np.uint16)
+    irr = np.zeros((P, r * r * 3))
+    irr[2] = 0.4  # one probe with feedback: h = exp(min(0.4/f, 1)) f there
+    cp = oracle.ChainParams(1024, 64, 0, 0.3, 0.35)
+    state = np.zeros((1024, 5))
+    occ = np.zeros(P * 8)
+    for frame in range(96):
+        out = oracle.chain_frame(g, cp, 99, frame, qv, irr, r, state, init=(frame == 0))
+        if frame < 2:
+            continue  # burn-in across frames
+        cell = 8 * out["sample_probe"] + _octant_of_uv(out["sample_uv"])
+        occ += np.bincount(cell, minlength=P * 8)
+    # h is constant on each (probe cell, octant); the cells have equal volume
+    # in this 2x2x2 grid and the octants equal areas in the octahedral square
+    f = qv / 1024.0
+    gl = np.zeros(P * 8)
+    gl[16:24] = 0.4
+    h = np.exp(np.minimum(gl / f, 1.0)) * f
+    want = h / h.sum()
+    got = occ / occ.sum()
+    assert np.max(np.abs(got - want) / want) < 0.06, np.max(np.abs(got - want) / want)
+    # a sampler that ignored h would be uniform: far from the target
+    assert np.max(np.abs(1.0 / (P * 8) - want) / want) > 0.5
+
+
+def test_chain_samples_layout_and_domain():
+    g = _chain_grid((3, 2, 4))
+    P, r = 24, 6
+    qv = np.full(P * 8, 500, np.uint16)
+    irr = np.zeros((P, r * r * 3))
+    cp = oracle.ChainParams(16, 10, 3, 1.0, 0.2)
+    state = np.zeros((16, 5))
+    a = oracle.chain_frame(g, cp, 5, 0, qv, irr, r, state, init=True)
+    assert len(a["sample_probe"]) == 16 * 6 and len(a["accept"]) == 16 * 10
+    assert np.all(state[:, 0] >= 0) and np.all(state[:, 0] <= 2) and np.all(state[:, 2] <= 3)
+    assert np.all(np.abs(state[:, 3:]) <= 1)
+    # the last sample of a chain is its final state
+    uv_last = a["sample_uv"].reshape(16, 6, 2)[:, -1]
+    assert np.array_equal(uv_last, state[:, 3:])
+    # deterministic in the seed, different across seeds
+    s2 = np.zeros((16, 5))
+    b = oracle.chain_frame(g, cp, 5, 0, qv, irr, r, s2, init=True)
+    assert np.array_equal(a["sample_uv"], b["sample_uv"]) and np.array_equal(state, s2)
+    s3 = np.zeros((16, 5))
+    c = oracle.chain_frame(g, cp, 6, 0, qv, irr, r, s3, init=True)
+    assert not np.array_equal(a["sample_uv"], c["sample_uv"])
