@@ -20,7 +20,10 @@
  *      depth-moment (visibility) texel it falls in with the moving average of
  *      Alg. MovingAvgUpdate (Alg. ApproxAlgo, Sec. 4.5-4.7).
  * With adaptive = 0 every probe traces n_uniform rays and steps 1-2 are
- * skipped (the uniform DDGI-style update).
+ * skipped (the uniform DDGI-style update). With adaptive = ADGI_MODE_CHAIN
+ * the rays are placed by static Metropolis chains instead of steps 2-3
+ * (Sec. 3.2, Alg. MarkovChainMT and MetropolisStep, Sec. 4.7): see
+ * adgi_update_params.
  *
  * Conventions
  *   - Probe i sits at origin + (x, y, z) * spacing with
@@ -74,6 +77,8 @@ enum { ADGI_FP32 = 0, ADGI_FP16 = 1, ADGI_PACKED = 2 };
 enum { ADGI_SCENE_REBUILD = 0, ADGI_SCENE_REFIT = 1 };      /* scene update mode */
 enum { ADGI_DEBUG_ARRAYS = 1u << 0 };                        /* volume flags */
 enum { ADGI_MAX_LIGHTS = 8 };
+enum { ADGI_MODE_UNIFORM = 0, ADGI_MODE_ADAPTIVE = 1, ADGI_MODE_CHAIN = 2 };  /* params.adaptive */
+enum { ADGI_CHAIN_MAX_STEPS = 256 };
 
 /* Device memory provider. alloc returns device memory of at least `bytes`
  * (256-byte aligned) or NULL; free releases it. Both are called only from
@@ -96,6 +101,10 @@ typedef struct {
   int64_t max_rays_per_frame; /* capacity of the per-frame ray buffers, < 2^31   */
   uint64_t seed;              /* seeds the frame rotation and the pilot rays     */
   uint32_t flags;             /* ADGI_DEBUG_ARRAYS keeps per-ray decisions       */
+  int32_t max_chains;         /* 0, or the most Metropolis chains a frame may run
+                                 (ADGI_FP32 / ADGI_FP16, tiles 8/16 or 16/16);
+                                 allocates the chain state and sample buffers for
+                                 max_rays/2 samples                               */
 } adgi_volume_desc;
 
 typedef struct {
@@ -126,6 +135,33 @@ typedef struct {
   int32_t mu;                 /* weight of radiance change vs visibility change (2) */
   int32_t theta;              /* trigger decays to 0 in theta detection steps (8)  */
   int32_t sync;               /* 1: wait for completion and fill stats             */
+  /* ADGI_MODE_CHAIN (Sec. 3.2, Sec. 4.7). Chain c's state is a point x = (p, uv):
+   * p in the box spanned by the probe centres, uv the octahedral coordinates
+   * of a direction. Its target density is h(x) = exp(min(g/f, 1)) f, with
+   * f = Qv/1024 the pilot visibility code of this frame in the octant of uv at
+   * the probe nearest to p, and g the luminance of that probe's irradiance
+   * averaged over the 2x2 interior texels whose cell holds uv, as the
+   * previous frame left it. Every frame each chain takes chain_steps
+   * Metropolis steps from where it stopped (normal proposals, sigma_pos *
+   * spacing per axis and sigma_dir in uv; a proposal outside the domain is
+   * rejected; it is accepted when h(x) = 0 or u h(x) <= h(x'), all uniforms
+   * from the counter-based stream; a grid axis with one probe has no extent
+   * and chains do not move along it). Each step after the first
+   * chain_burn_in + 1 emits a sample (nearest probe, uv), so a frame makes
+   * S = chain_count (chain_steps - chain_burn_in - 1) samples. A sample
+   * traces two rays from its probe's centre: d(uv), shaded with direct light
+   * and blended into the irradiance texel of d, and -d, whose distance only
+   * is blended into the depth texel of -d. Per-probe lists are the samples
+   * in chain-major order. Pilots run as in ADAPTIVE; detection and
+   * allocation are skipped. Chain frames run eagerly (no graph). */
+  int32_t chain_count;        /* C, 1..max_chains                                  */
+  int32_t chain_steps;        /* M, 2..ADGI_CHAIN_MAX_STEPS                        */
+  int32_t chain_burn_in;      /* K, 0 <= K <= M - 2                                */
+  float chain_sigma_pos;      /* > 0, in units of the grid spacing (0.5)           */
+  float chain_sigma_dir;      /* > 0, in octahedral uv units (sqrt(pi/256))        */
+  int32_t chain_reset;        /* 1: start every chain from its seeded initial point;
+                                 chains also start there on their first frame and
+                                 whenever chain_count changes                      */
 } adgi_update_params;
 
 typedef struct {
@@ -167,6 +203,16 @@ typedef struct {
   int64_t num_rays;           /* out: R of the last frame                           */
   uint32_t* irr_words;        /* ADGI_PACKED: [P][irr_res][irr_res] raw words      */
   uint32_t* depth_words;      /* ADGI_PACKED: [P][depth_res][depth_res] raw words  */
+  /* chain frames (max_chains > 0): after the last chain frame. With a chain
+   * frame last, rays_per_probe / ray_offsets count samples per probe, the
+   * per-ray debug arrays hold 2 * num_samples rays (sample k: rays 2k, 2k+1) */
+  float* chain_state;         /* [chain_count][5] (p.xyz, u, v)                    */
+  uint32_t* sample_probe;     /* [num_samples] probe of each sample, grouped       */
+  float* sample_uv;           /* [num_samples][2] uv of each sample, grouped       */
+  uint8_t* chain_accept;      /* debug: [chain_count][chain_steps] 1 = accepted    */
+  int64_t num_samples;        /* out                                               */
+  int32_t num_chains;         /* out: chain_count of the last chain frame (0: none) */
+  int32_t chain_steps;        /* out: chain_steps of the last chain frame          */
 } adgi_probe_readback;
 
 /* Create a volume. desc/alloc are host, copied. hip_stream (hipStream_t or

@@ -74,7 +74,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        srcs = [os.path.join(_HERE, n) for n in ("adgi_oracle.c", "adgi_oracle.h")]
+        if not os.path.exists(_LIB_PATH) or \
+                os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(x) for x in srcs):
             build(force=True)
         L = C.CDLL(_LIB_PATH)
         P = C.c_void_p
@@ -135,6 +137,8 @@ def lib():
         L.orc_chain_h.restype = C.c_double
         L.orc_chain_frame.restype = None
         L.orc_chain_probes_frame.restype = None
+        L.orc_chain_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32,
+                                             C.c_double, C.c_double, C.c_int32] + [P] * 9
         L.orc_chain_dir.restype = None
         L.orc_set_threads.restype = None
         _lib = L
@@ -555,7 +559,7 @@ class OracleVolume:
         lib().orc_chain_probes_frame(
             self.scene.ptr, C.byref(self.grid), self.P, _p(self.probes), _p(n), _p(base), _p(suv),
             C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
-            _p(h("hit_tri", np.int32)), _p(h("shadow_bits", np.uint8)), _p(h("irr_bin", np.uint16)),
+            1 if self.fp16 else 0, _p(h("hit_tri", np.int32)), _p(h("shadow_bits", np.uint8)), _p(h("irr_bin", np.uint16)),
             _p(h("depth_bin", np.uint16)), _p(self.irr), _p(self.irr_n), _p(self.dep), _p(self.dep_n),
             C.byref(cnt))
         for name, _ in Counts._fields_:

@@ -1235,14 +1235,16 @@ static int near_frac(double f, double band) {
 
 void orc_chain_dir(const double uv[2], double d[3]) { orc_oct_decode(uv, d); }
 
-/* p within the box of probe centres, uv within [-1, 1]^2 (closed). */
+/* p within the box of probe centres, uv within [-1, 1]^2 (closed). An axis
+ * with a single probe has no extent: the chain sits at its one coordinate and
+ * never moves along it, so no boundary decision is taken there. */
 static int chain_in_domain(const orc_grid* g, const double x[5], int* tie) {
   int in = 1, t = 0;
   for (int a = 0; a < 3; ++a) {
     double lo = g->origin[a], hi = g->origin[a] + (g->dims[a] - 1) * g->spacing[a];
     double band = 1e-6 * g->spacing[a] + 1e-7 * fabs(x[a]);
     if (x[a] < lo || x[a] > hi) in = 0;
-    if (fabs(x[a] - lo) <= band || fabs(x[a] - hi) <= band) t = 1;
+    if (g->dims[a] > 1 && (fabs(x[a] - lo) <= band || fabs(x[a] - hi) <= band)) t = 1;
   }
   for (int a = 3; a < 5; ++a) {
     if (x[a] < -1.0 || x[a] > 1.0) in = 0;
@@ -1332,7 +1334,8 @@ void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t see
         gs[2 * q + 1] = rr * sin(th);
       }
       double xp[5];
-      for (int a = 0; a < 3; ++a) xp[a] = x[a] + cp->sigma_pos * g->spacing[a] * gs[a];
+      for (int a = 0; a < 3; ++a)
+        xp[a] = g->dims[a] > 1 ? x[a] + cp->sigma_pos * g->spacing[a] * gs[a] : x[a];
       xp[3] = x[3] + cp->sigma_dir * gs[3];
       xp[4] = x[4] + cp->sigma_dir * gs[4];
       int ptie = 0, ttie = 0;
@@ -1382,7 +1385,7 @@ void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t see
 void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
                             const int32_t* nsamp, const int64_t* sample_base, const double* sample_uv,
                             const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
-                            double tau_max, const int32_t* hint_tri, const uint8_t* hint_shadow,
+                            double tau_max, int32_t fp16, const int32_t* hint_tri, const uint8_t* hint_shadow,
                             const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
                             uint8_t* irr_n, double* dep, uint8_t* dep_n, orc_counts* counts) {
   const int32_t ri = irr_r - 2, rd = dep_r - 2;
@@ -1443,6 +1446,10 @@ void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count
         D[2 * kd + 0] += ad * (tau - D[2 * kd + 0]);
         D[2 * kd + 1] += ad * (tau * tau - D[2 * kd + 1]);
         if (DN[kd] < 255) DN[kd]++;
+      }
+      if (fp16) { /* binary16 texel store at the end of the frame, as for probe rays */
+        for (int32_t k = 0; k < ri * ri * 3; ++k) I[k] = orc_round_half(I[k]);
+        for (int32_t k = 0; k < rd * rd * 2; ++k) D[k] = orc_round_half(D[k]);
       }
       loc.hit_ties += ties[0];
       loc.shadow_ties += ties[1];

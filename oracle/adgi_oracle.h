@@ -237,7 +237,7 @@ void orc_chain_dir(const double uv[2], double d[3]);
 void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
                             const int32_t* nsamp, const int64_t* sample_base, const double* sample_uv,
                             const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
-                            double tau_max, const int32_t* hint_tri, const uint8_t* hint_shadow,
+                            double tau_max, int32_t fp16, const int32_t* hint_tri, const uint8_t* hint_shadow,
                             const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
                             uint8_t* irr_n, double* dep, uint8_t* dep_n, orc_counts* counts);
 

@@ -29,6 +29,9 @@ STATUS = {0: "ADGI_OK", -1: "ADGI_ERR_INVALID_ARG", -2: "ADGI_ERR_OUT_OF_MEMORY"
 ADGI_FP32, ADGI_FP16, ADGI_PACKED = 0, 1, 2
 ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
 ADGI_DEBUG_ARRAYS = 1
+ADGI_MODE_UNIFORM, ADGI_MODE_ADAPTIVE, ADGI_MODE_CHAIN = 0, 1, 2
+CHAIN_MAX_STEPS = 256
+CHAIN_SIGMA_DIR = math.sqrt(math.pi / 256.0)  # default octahedral step of the chains (Sec. 4.7)
 MAX_LIGHTS = 8
 TAU_MAX = (math.exp(5.0) - 1.0) / 15.0
 
@@ -51,7 +54,8 @@ class VolumeDesc(C.Structure):
     _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("dims", C.c_int32 * 3),
                 ("irr_res", C.c_int32), ("depth_res", C.c_int32), ("storage", C.c_int32),
                 ("hysteresis", C.c_float), ("tau_max", C.c_float),
-                ("max_rays_per_frame", C.c_int64), ("seed", C.c_uint64), ("flags", C.c_uint32)]
+                ("max_rays_per_frame", C.c_int64), ("seed", C.c_uint64), ("flags", C.c_uint32),
+                ("max_chains", C.c_int32)]
 
 
 class SceneDesc(C.Structure):
@@ -65,7 +69,10 @@ class SceneDesc(C.Structure):
 class UpdateParams(C.Structure):
     _fields_ = [("frame", C.c_int32), ("adaptive", C.c_int32), ("budget", C.c_int64),
                 ("n_min", C.c_int32), ("n_max", C.c_int32), ("n_uniform", C.c_int32),
-                ("beta", C.c_float), ("mu", C.c_int32), ("theta", C.c_int32), ("sync", C.c_int32)]
+                ("beta", C.c_float), ("mu", C.c_int32), ("theta", C.c_int32), ("sync", C.c_int32),
+                ("chain_count", C.c_int32), ("chain_steps", C.c_int32), ("chain_burn_in", C.c_int32),
+                ("chain_sigma_pos", C.c_float), ("chain_sigma_dir", C.c_float),
+                ("chain_reset", C.c_int32)]
 
 
 class UpdateStats(C.Structure):
@@ -87,7 +94,9 @@ class ProbeReadback(C.Structure):
         "irradiance", "depth", "irr_count", "depth_count", "rays_per_probe", "score",
         "ray_offsets", "hit_tri", "shadow_bits", "irr_bin", "depth_bin", "ray_record",
         "q10_vis", "q10_rad", "frame_rotation")] + [("num_rays", C.c_int64)] + \
-        [("irr_words", C.c_void_p), ("depth_words", C.c_void_p)]
+        [("irr_words", C.c_void_p), ("depth_words", C.c_void_p)] + \
+        [(n, C.c_void_p) for n in ("chain_state", "sample_probe", "sample_uv", "chain_accept")] + \
+        [("num_samples", C.c_int64), ("num_chains", C.c_int32), ("chain_steps", C.c_int32)]
 
 
 class TraceWork(C.Structure):
@@ -235,9 +244,9 @@ def _torch_allocator():
 
 def create_volume(origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
                   hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
-                  debug=False, stream=None, allocator="torch") -> "Volume":
+                  debug=False, stream=None, allocator="torch", max_chains=0) -> "Volume":
     return Volume(origin, spacing, dims, irr_res, depth_res, storage, hysteresis, tau_max,
-                  max_rays_per_frame, seed, debug, stream, allocator)
+                  max_rays_per_frame, seed, debug, stream, allocator, max_chains)
 
 
 class Volume:
@@ -245,7 +254,7 @@ class Volume:
 
     def __init__(self, origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
                  hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
-                 debug=False, stream=None, allocator="torch"):
+                 debug=False, stream=None, allocator="torch", max_chains=0):
         d = VolumeDesc()
         d.origin[:] = [float(x) for x in origin]
         d.spacing[:] = [float(x) for x in spacing]
@@ -255,6 +264,7 @@ class Volume:
         d.max_rays_per_frame = int(max_rays_per_frame)
         d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         d.flags = ADGI_DEBUG_ARRAYS if debug else 0
+        d.max_chains = int(max_chains)
         self.desc = d
         self.P = int(np.prod([int(x) for x in dims]))
         self._alloc = None
@@ -318,6 +328,18 @@ class Volume:
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
 
+    def update_chains(self, frame, chains, steps, burn_in, sigma_pos=0.5, sigma_dir=CHAIN_SIGMA_DIR,
+                      reset=False, beta=5.0, sync=True) -> dict:
+        """One chain frame (ADGI_MODE_CHAIN): pilots, `chains` static
+        Metropolis chains of `steps` steps each (the first burn_in + 1 emit
+        nothing), two rays per sample, blend."""
+        p = UpdateParams(int(frame), ADGI_MODE_CHAIN, 0, 1, 1, 1, float(beta), 2, 8,
+                         1 if sync else 0, int(chains), int(steps), int(burn_in),
+                         float(sigma_pos), float(sigma_dir), 1 if reset else 0)
+        st = UpdateStats()
+        _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
+        return st.as_dict() if sync else {}
+
     def read_probes(self, texels=True, debug=False, probes=None) -> dict:
         d = self.desc
         P = self.P
@@ -341,8 +363,22 @@ class Volume:
         for k, a in out.items():
             setattr(rb, k, _ptr(a))
         _check(lib().adgi_read_probes(self.h, C.byref(rb)))
+        if d.max_chains > 0 and rb.num_chains > 0:
+            Cn, M, S = int(rb.num_chains), int(rb.chain_steps), int(rb.num_samples)
+            ch = {"chain_state": np.zeros((Cn, 5), np.float32),
+                  "sample_probe": np.zeros(max(S, 1), np.uint32),
+                  "sample_uv": np.zeros((max(S, 1), 2), np.float32)}
+            if debug:
+                ch["chain_accept"] = np.zeros((Cn, M), np.uint8)
+            rb3 = ProbeReadback()
+            for k, a in ch.items():
+                setattr(rb3, k, _ptr(a))
+            _check(lib().adgi_read_probes(self.h, C.byref(rb3)))
+            ch["sample_probe"], ch["sample_uv"] = ch["sample_probe"][:S], ch["sample_uv"][:S]
+            out.update(ch)
+            out["num_samples"] = S
         if debug:
-            R = int(out["ray_offsets"][-1])
+            R = int(rb.num_rays)
             dbg = {"hit_tri": np.zeros(max(R, 1), np.int32),
                    "shadow_bits": np.zeros(max(R, 1), np.uint8),
                    "irr_bin": np.zeros(max(R, 1), np.uint16),
@@ -354,7 +390,7 @@ class Volume:
             _check(lib().adgi_read_probes(self.h, C.byref(rb2)))
             for k, a in dbg.items():
                 out[k] = a[:R]
-        out["num_rays"] = int(out["ray_offsets"][-1])
+        out["num_rays"] = int(rb.num_rays)
         return out
 
     def get_tuning(self) -> dict:

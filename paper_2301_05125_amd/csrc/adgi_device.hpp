@@ -85,6 +85,20 @@ __device__ __forceinline__ float2 oct_encode(float3 d) {
   return make_float2(x, y);
 }
 
+// Unit direction of octahedral coordinates uv (the map's inverse).
+__device__ __forceinline__ float3 oct_decode_dir(float2 uv) {
+  float x = uv.x, y = uv.y;
+  const float z = 1.0f - fabsf(x) - fabsf(y);
+  if (z < 0.0f) {
+    const float nx = (1.0f - fabsf(y)) * (x >= 0.0f ? 1.0f : -1.0f);
+    const float ny = (1.0f - fabsf(x)) * (y >= 0.0f ? 1.0f : -1.0f);
+    x = nx;
+    y = ny;
+  }
+  const float inv = 1.0f / sqrtf(x * x + y * y + z * z);
+  return make_float3(x * inv, y * inv, z * inv);
+}
+
 __device__ __forceinline__ uint32_t oct_bin(float2 uv, int r) {
   int ix = (int)floorf((uv.x + 1.0f) * 0.5f * (float)r);
   int iy = (int)floorf((uv.y + 1.0f) * 0.5f * (float)r);

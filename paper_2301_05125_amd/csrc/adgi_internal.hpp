@@ -14,9 +14,20 @@ namespace adgi {
 
 // trace.hip
 size_t trace_lds_bytes(int block);
-// w4: traverse the BVH4 (v.nodes4) instead of the BVH2.
+// w4: traverse the BVH4 (v.nodes4) instead of the BVH2. chain: the two rays of
+// each chain sample (probe rays otherwise).
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
-                        int grid, bool count = false, bool w4 = false);
+                        int grid, bool count = false, bool w4 = false, bool chain = false);
+
+// chain.hip: one frame of `chains` Metropolis chains, then their samples
+// sorted by probe (v.smp_probe / v.smp_uv, v.offsets / v.n as per-probe
+// sample ranges). samples = chains * (steps - burn_in - 1).
+size_t chain_sort_temp_bytes(uint32_t max_samples, int P);
+size_t chain_sort_needed_bytes(uint32_t samples, int P);
+// alloc.hip: blend order (most 64-entry chunks first) from counts already in v.n
+hipError_t launch_blend_order(const VolumeView& v, hipStream_t s);
+hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int chains, uint32_t samples,
+                         void* sort_temp, size_t sort_temp_bytes, hipStream_t s);
 
 // detect.hip: trigger update and the separable 5x5x5 box sum -> scores
 hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s);
@@ -41,8 +52,9 @@ struct BlendIO {
 // `grid` workgroups walking the allocation's probe order; otherwise one
 // workgroup per probe with `chunk` rays staged per step.
 // storage: ADGI_FP32, ADGI_FP16 or ADGI_PACKED (wave kernel only)
+// chain: the lists are chain samples (wave kernel; not with ADGI_PACKED)
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
-                        int grid = 0);
+                        int grid = 0, bool chain = false);
 bool blend_wave_supported(const VolumeView& v);
 // Fills the table of decoded values of every packed code (v.pk_dec).
 hipError_t launch_packed_decode_table(float* dec, hipStream_t s);

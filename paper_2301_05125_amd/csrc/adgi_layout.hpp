@@ -8,6 +8,9 @@ namespace adgi {
 
 constexpr uint64_t kTagRotation = 0x524F54ull;  // "ROT"
 constexpr uint64_t kTagPilot = 0x50494Cull;     // "PIL"
+constexpr uint64_t kTagChain = 0x4D4353ull;     // "MCS": one Metropolis step
+constexpr uint64_t kTagChainInit = 0x4D4349ull; // "MCI": a chain's first state
+constexpr int kChainMaxSteps = 256;
 constexpr int kMaxLights = 8;
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
@@ -61,7 +64,11 @@ struct FrameParams {
   int32_t mu, theta;
   float beta;
   int32_t debug;
-  int32_t pad[3];
+  // chain frames (adaptive == 2)
+  int32_t chains, chain_steps, chain_burn_in, chain_init;
+  float chain_sp[3];          // position step per axis (sigma_pos * spacing)
+  float chain_sd;             // octahedral uv step
+  int32_t pad[2];
 };
 
 struct FrameStats {
@@ -115,6 +122,16 @@ struct VolumeView {
   uint32_t* blk_rank;         // per-block exclusive rank base among eligible probes
   uint32_t* blk_off;          // per-block exclusive ray offset
   int32_t* order;             // [P] blend order: most 64-ray chunks first
+  // chain frames: state [C][8] = (p.xyz, u, v, -, -, -); samples in chain
+  // order (probe, uv) and grouped by probe (sorted)
+  float* chain_state;
+  uint32_t* smp_probe_raw;
+  float2* smp_uv_raw;
+  uint32_t* smp_probe;        // sorted
+  uint32_t* smp_index;        // 0, 1, 2, ... (sort input)
+  uint32_t* smp_order;        // sorted: raw sample index
+  float2* smp_uv;             // sorted
+  uint8_t* dbg_accept;        // [C][steps] (debug)
   const float* pk_dec;        // packed storage: decoded value of every code
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]
   // trace / blend

@@ -124,12 +124,13 @@ __device__ int64_t block_exclusive_scan(int64_t x, int64_t* sm, int64_t& total) 
 
 // Blend work order: probes sorted by their number of 64-ray chunks, most
 // first, so that the longest per-probe blends start first. Bucket b holds the
-// probes with min(ceil(n/64), 32) = 32 - b chunks. Counting happens with the
+// probes with min(max(ceil(n/64), 1), 32) = 32 - b chunks (a probe without
+// rays, possible in chain frames, joins the one-chunk bucket). Counting happens with the
 // allocation; order_scatter_kernel then places every probe. The order inside a
 // bucket depends on timing, which does not matter: every probe's blend is
 // independent of the others.
 __device__ __forceinline__ int order_bucket(int n) {
-  const int c = min((n + 63) >> 6, kOrderBuckets);
+  const int c = min(max((n + 63) >> 6, 1), kOrderBuckets);
   return kOrderBuckets - c;
 }
 
@@ -315,6 +316,19 @@ hipError_t launch_alloc(const VolumeView& v, hipStream_t s) {
   hipLaunchKernelGGL(alloc_scan_blocks_kernel, dim3(1), dim3(1024), 0, s, v);
   hipLaunchKernelGGL(alloc_write_kernel, dim3(g), dim3(256), 0, s, v);
   hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+// Blend order for lists whose counts v.n are already set (chain samples).
+__global__ __launch_bounds__(256) void order_count_kernel(VolumeView v) {
+  __shared__ uint32_t hist[kOrderBuckets];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  count_buckets(v, i < v.P, i < v.P ? v.n[i] : 0, hist);
+}
+
+hipError_t launch_blend_order(const VolumeView& v, hipStream_t s) {
+  hipLaunchKernelGGL(order_count_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, v);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, v);
   return hipGetLastError();
 }
 

@@ -326,7 +326,15 @@ __device__ void write_tiles(const VolumeView& v, const BlendIO& io, int i, const
 }
 
 // Light probe: one wave.
-template <int RI, int RD, bool HALF>
+// CHAIN: the probe's list holds chain samples k (grouped by probe): the
+// irradiance texel of d(uv_k) takes the radiance of ray 2k, the depth texel
+// of -d takes the distance of ray 2k+1.
+__device__ __forceinline__ float4 chain_record(const VolumeView& v, uint32_t k) {
+  const float4 a = v.rec[2 * (size_t)k];
+  return make_float4(a.x, a.y, a.z, v.rec[2 * (size_t)k + 1].w);
+}
+
+template <int RI, int RD, bool HALF, bool CHAIN>
 __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
                                  const uint16_t* tab, const float* alpha) {
   using S = Store<HALF>;
@@ -373,24 +381,37 @@ __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, 
   const float inv_s = 1.0f / v.s_diag;
   const float tmax = v.tau_max;
   float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-  if ((uint32_t)lane < n) nxt = v.rec[off + lane];
+  if ((uint32_t)lane < n) nxt = CHAIN ? chain_record(v, off + lane) : v.rec[off + lane];
   for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
     const uint32_t m = min(64u, n - c0);
     const float4 cur = nxt;
-    if (c0 + 64u + (uint32_t)lane < n) nxt = v.rec[off + c0 + 64u + lane];
+    if (c0 + 64u + (uint32_t)lane < n)
+      nxt = CHAIN ? chain_record(v, off + c0 + 64u + lane) : v.rec[off + c0 + 64u + lane];
     for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
     wave_sync();
     if ((uint32_t)lane < m) {
       const uint32_t j = c0 + (uint32_t)lane;
       rec_s[lane] = cur;
-      const float2 uv = oct_encode(sf_direction(j, n, fp.R));
-      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
+      uint32_t bI, bD;
+      if (CHAIN) {
+        const float3 d = oct_decode_dir(v.smp_uv[off + j]);
+        bI = oct_bin(oct_encode(d), RI);
+        bD = oct_bin(oct_encode(make_float3(-d.x, -d.y, -d.z)), RD);
+        if (fp.debug) {
+          v.dbg_ibin[2 * (size_t)(off + j)] = (uint16_t)bI;
+          v.dbg_dbin[2 * (size_t)(off + j) + 1] = (uint16_t)bD;
+        }
+      } else {
+        const float2 uv = oct_encode(sf_direction(j, n, fp.R));
+        bI = oct_bin(uv, RI);
+        bD = oct_bin(uv, RD);
+        if (fp.debug) {
+          v.dbg_ibin[off + j] = (uint16_t)bI;
+          v.dbg_dbin[off + j] = (uint16_t)bD;
+        }
+      }
       atomicOr(&mask[bI], 1ull << lane);
       atomicOr(&mask[NI + bD], 1ull << lane);
-      if (fp.debug) {
-        v.dbg_ibin[off + j] = (uint16_t)bI;
-        v.dbg_dbin[off + j] = (uint16_t)bD;
-      }
     }
     wave_sync();
 #pragma unroll
@@ -444,7 +465,7 @@ __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, 
 
 // One wave per probe, probes taken round-robin over all waves of the grid in
 // the allocation's order (most chunks first).
-template <int RI, int RD, bool HALF>
+template <int RI, int RD, bool HALF, bool CHAIN>
 __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io) {
   using W = WaveTile<RI, RD>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -458,7 +479,7 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
   for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
-    blend_probe_wave<RI, RD, HALF>(v, io, v.order[q], wbase, tab, alpha);
+    blend_probe_wave<RI, RD, HALF, CHAIN>(v, io, v.order[q], wbase, tab, alpha);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,22 +658,27 @@ size_t blend_lds_bytes(const VolumeView& v, int chunk) {
 }
 
 template <int RI, int RD>
-static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int grid) {
+static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int grid,
+                         bool chain) {
   using W = WaveTile<RI, RD>;
   const size_t lds = W::kBlockBytes;
-  if (storage == ADGI_PACKED)
+  if (chain && storage == ADGI_FP16)
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, true>), dim3(grid), dim3(256), lds, s, v, io);
+  else if (chain)
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, true>), dim3(grid), dim3(256), lds, s, v, io);
+  else if (storage == ADGI_PACKED)
     hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(256), lds + 4 * kPkDecTau, s, v, io);
   else if (storage == ADGI_FP16)
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, false>), dim3(grid), dim3(256), lds, s, v, io);
   else
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, false>), dim3(grid), dim3(256), lds, s, v, io);
 }
 
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
-                        int grid) {
-  if (chunk == 0 || storage == ADGI_PACKED) {  // wave-per-probe kernel in most-rays-first order
-    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, storage, grid);
-    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, storage, grid);
+                        int grid, bool chain) {
+  if (chunk == 0 || storage == ADGI_PACKED || chain) {  // wave-per-probe kernel, most-rays-first order
+    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, storage, grid, chain);
+    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, storage, grid, chain);
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }

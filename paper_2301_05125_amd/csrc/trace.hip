@@ -4,6 +4,9 @@
 //   KIND_PRIMARY: ray r of probe i is the j-th point of a rotated spherical
 //     Fibonacci set of n_i directions (r = offsets[i] + j); output one 16-byte
 //     record (radiance RGB, hit distance) per ray.
+//   KIND_CHAIN:   rays 2k and 2k+1 belong to chain sample k (probes' samples
+//     grouped by probe): along d(uv_k) from the sample's probe, shaded, and
+//     along -d, distance only (the visibility ray of Sec. 4.7);
 //   KIND_PILOT:   ray r = 8i + k is the pilot of octant k (Sec. 4.1, 4.4);
 //     output the 10-bit codes of f_v = exp(-2t/s) (eq. ProbeVis) and
 //     f_r = min(lum, beta)/beta (Sec. 4.1.3).
@@ -18,7 +21,7 @@
 
 namespace adgi {
 
-enum { KIND_PRIMARY = 0, KIND_PILOT = 1 };
+enum { KIND_PRIMARY = 0, KIND_PILOT = 1, KIND_CHAIN = 2 };
 
 // Per-lane traversal stack of (node, entry distance of its box): the first
 // kStackLds entries in the wave's LDS region (entry k of lane l at 8-byte
@@ -367,6 +370,11 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
       uint32_t b = v.offsets[i], n = v.offsets[i + 1] - b;
       o = probe_position(v, i);
       d = sf_direction(r - b, n, fp.R);
+    } else if (KIND == KIND_CHAIN) {
+      const uint32_t k = r >> 1;
+      o = probe_position(v, (int)v.smp_probe[k]);
+      d = oct_decode_dir(v.smp_uv[k]);
+      if (r & 1u) d = make_float3(-d.x, -d.y, -d.z);
     } else {
       uint32_t i = r >> 3, k = r & 7;
       o = probe_position(v, (int)i);
@@ -390,7 +398,7 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
   }
 
   // ---- direct light at front-face hits, shadow rays compacted per wave
-  const bool lit_hit = active && slot >= 0 && front;
+  const bool lit_hit = active && slot >= 0 && front && !(KIND == KIND_CHAIN && (r & 1u));
   float3 x = make_float3(0.f, 0.f, 0.f), nrm = make_float3(0.f, 0.f, 0.f);
   if (lit_hit) {
     const float4* tp = v.tris + 3 * (size_t)slot;
@@ -474,7 +482,7 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
 
   // ---- outputs
   if (!active) return;
-  if (KIND == KIND_PRIMARY) {
+  if (KIND != KIND_PILOT) {
     v.rec[r] = make_float4(L.x, L.y, L.z, t);
     if (fp.debug) {
       v.dbg_tri[r] = id;
@@ -506,9 +514,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_kernel(VolumeVi
   st.sp = 0;
   uint16_t* queue = queues + wave * 64 * kMaxLights;
   uint32_t* vis = vis_all + wave * 64;
-  const uint32_t total = KIND == KIND_PRIMARY ? v.offsets[v.P] : 8u * (uint32_t)v.P;
+  const uint32_t total = KIND == KIND_PRIMARY ? v.offsets[v.P]
+                         : KIND == KIND_CHAIN ? 2u * v.offsets[v.P] : 8u * (uint32_t)v.P;
   if (persistent) {
-    uint32_t* counter = KIND == KIND_PRIMARY ? &v.stats->ray_counter : &v.stats->pilot_counter;
+    uint32_t* counter = KIND == KIND_PILOT ? &v.stats->pilot_counter : &v.stats->ray_counter;
     for (;;) {
       uint32_t base = 0;
       if (lane_id() == 0) base = atomicAdd(counter, 64u);
@@ -528,9 +537,13 @@ size_t trace_lds_bytes(int block) {
 
 template <bool W4>
 static void launch_trace_w(const VolumeView& v, hipStream_t s, bool pilot, int pers, int block, int grid,
-                           bool count) {
+                           bool count, bool chain) {
   const size_t lds = trace_lds_bytes(block);
-  if (pilot && count)
+  if (chain && count)
+    hipLaunchKernelGGL((trace_kernel<KIND_CHAIN, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
+  else if (chain)
+    hipLaunchKernelGGL((trace_kernel<KIND_CHAIN, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
+  else if (pilot && count)
     hipLaunchKernelGGL((trace_kernel<KIND_PILOT, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
   else if (pilot)
     hipLaunchKernelGGL((trace_kernel<KIND_PILOT, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
@@ -541,11 +554,11 @@ static void launch_trace_w(const VolumeView& v, hipStream_t s, bool pilot, int p
 }
 
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block, int grid,
-                        bool count, bool w4) {
+                        bool count, bool w4, bool chain) {
   if (w4)
-    launch_trace_w<true>(v, s, pilot, persistent ? 1 : 0, block, grid, count);
+    launch_trace_w<true>(v, s, pilot, persistent ? 1 : 0, block, grid, count, chain);
   else
-    launch_trace_w<false>(v, s, pilot, persistent ? 1 : 0, block, grid, count);
+    launch_trace_w<false>(v, s, pilot, persistent ? 1 : 0, block, grid, count, chain);
   return hipGetLastError();
 }
 

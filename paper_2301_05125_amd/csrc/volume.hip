@@ -6,7 +6,9 @@
 // offsets] -> primary trace -> blend, captured once per mode as a hipGraph and
 // relaunched every frame; only the 128-byte parameter block is copied per
 // frame (outside the graph, from a ring of pinned host slots). All counts stay
-// on the device, so nothing is read back inside a frame.
+// on the device, so nothing is read back inside a frame. Chain frames
+// (pilot trace -> Metropolis chains -> sort by probe -> trace -> blend) are
+// launched eagerly.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -162,6 +164,11 @@ struct adgi_volume {
   bool tuned = false;
   int32_t last_frame = -1, last_adaptive = 0;
   float last_R[9] = {};
+  // chain frames
+  void* d_sort_temp = nullptr;
+  size_t sort_temp_bytes = 0;
+  int32_t chain_count = 0, chain_steps = 0;  // of the last chain frame (0: chains not started)
+  int64_t num_samples = 0;
 };
 
 namespace {
@@ -210,20 +217,36 @@ bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
 }
 
 // Stage boundaries recorded into ev[0..6] when ev is non-null (eager only):
-// 0 start, 1 frame_begin, 2 pilot trace, 3 detect, 4 allocate, 5 probe trace, 6 blend.
-hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullptr,
+// 0 start, 1 frame_begin, 2 pilot trace, 3 detect | chains, 4 allocate |
+// blend order, 5 probe trace, 6 blend. mode: ADGI_MODE_*. A counting run of a
+// chain frame traces the samples the last chain frame left.
+hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
                          bool count_work = false) {
   const adgi_tuning& t = vol->tun;
   VolumeView& v = vol->v;
   hipStream_t s = vol->stream;
   hipError_t e;
   const bool w4 = use_bvh4(vol, t);
+  const bool adaptive = mode == ADGI_MODE_ADAPTIVE, chain = mode == ADGI_MODE_CHAIN;
   const int pgrid = std::max(1, vol->num_cus * t.trace_waves_per_cu / (t.trace_block / 64));
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
   if ((e = mark(0)) != hipSuccess) return e;
   if ((e = launch_frame_begin(v, s)) != hipSuccess) return e;
   if ((e = mark(1)) != hipSuccess) return e;
-  if (adaptive) {
+  if (chain && !count_work) {
+    int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
+    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
+      return e;
+    if ((e = mark(2)) != hipSuccess) return e;
+    if ((e = launch_chains(v, vol->desc.storage == ADGI_FP16, vol->irr, vol->chain_count,
+                           (uint32_t)vol->num_samples, vol->d_sort_temp, vol->sort_temp_bytes, s)) != hipSuccess)
+      return e;
+    if ((e = mark(3)) != hipSuccess) return e;
+    if ((e = launch_blend_order(v, s)) != hipSuccess) return e;
+  } else if (chain) {
+    if ((e = mark(2)) != hipSuccess) return e;
+    if ((e = mark(3)) != hipSuccess) return e;
+  } else if (adaptive) {
     int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
     if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
       return e;
@@ -241,13 +264,14 @@ hipError_t enqueue_frame(adgi_volume* vol, bool adaptive, hipEvent_t* ev = nullp
   if (count_work && (e = launch_frame_begin(v, s)) != hipSuccess) return e;
   int grid = t.persistent ? pgrid
                           : (int)((vol->desc.max_rays_per_frame + t.trace_block - 1) / t.trace_block);
-  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, count_work, w4)) != hipSuccess)
+  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, count_work, w4, chain)) !=
+      hipSuccess)
     return e;
   if ((e = mark(5)) != hipSuccess) return e;
   if (count_work) return hipSuccess;
   BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
-  if ((e = launch_blend(v, io, s, vol->desc.storage, t.blend_chunk,
-                        vol->num_cus * t.blend_blocks_per_cu)) != hipSuccess)
+  if ((e = launch_blend(v, io, s, vol->desc.storage, chain ? 0 : t.blend_chunk,
+                        vol->num_cus * t.blend_blocks_per_cu, chain)) != hipSuccess)
     return e;
   return mark(6);
 }
@@ -355,10 +379,12 @@ struct Part {
 };
 std::vector<Part> state_parts(adgi_volume* vol) {
   const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res, ri = gi - 2, rd = gd - 2;
-  return {{vol->irr, irr_tile_bytes(vol->desc) * P}, {vol->dep, dep_tile_bytes(vol->desc) * P}, {vol->irr_n, P * ri * ri},
+  std::vector<Part> parts = {{vol->irr, irr_tile_bytes(vol->desc) * P}, {vol->dep, dep_tile_bytes(vol->desc) * P}, {vol->irr_n, P * ri * ri},
           {vol->dep_n, P * rd * rd},         {vol->v.qv[0], P * 16},           {vol->v.qv[1], P * 16},
           {vol->v.qr[0], P * 16},            {vol->v.qr[1], P * 16},           {vol->v.trig, P * 64},
           {vol->v.score, P * 8},             {vol->v.n, P * 4},                {vol->v.offsets, (P + 1) * 4}};
+  if (vol->desc.max_chains > 0) parts.push_back({vol->v.chain_state, (size_t)vol->desc.max_chains * 32});
+  return parts;
 }
 constexpr uint64_t kSnapMagic = 0x5041534E49474441ull;  // "ADGINSAP"
 struct SnapHeader {
@@ -366,7 +392,7 @@ struct SnapHeader {
   int32_t P, irr_res, depth_res, storage;
   int32_t last_frame, last_adaptive;
   float last_R[9];
-  int32_t pad;
+  int32_t max_chains, chain_count, chain_steps;
 };
 
 }  // namespace
@@ -399,6 +425,14 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   if (d->max_rays_per_frame < 1 || d->max_rays_per_frame >= (int64_t)1 << 31)
     return fail(ADGI_ERR_INVALID_ARG, "max_rays_per_frame must be in [1, 2^31)");
   if (d->flags & ~(uint32_t)ADGI_DEBUG_ARRAYS) return fail(ADGI_ERR_INVALID_ARG, "unknown flags");
+  if (d->max_chains < 0 || d->max_chains > (1 << 24))
+    return fail(ADGI_ERR_INVALID_ARG, "max_chains must be in [0, 2^24]");
+  if (d->max_chains > 0 && d->storage == ADGI_PACKED)
+    return fail(ADGI_ERR_INVALID_ARG, "chains need ADGI_FP32 or ADGI_FP16 storage");
+  if (d->max_chains > 0 && !((d->irr_res == 8 && d->depth_res == 16) || (d->irr_res == 16 && d->depth_res == 16)))
+    return fail(ADGI_ERR_INVALID_ARG, "chains need tiles 8/16 or 16/16");
+  if (d->max_chains > 0 && d->max_rays_per_frame < 2)
+    return fail(ADGI_ERR_INVALID_ARG, "chains need max_rays_per_frame >= 2");
   if (alloc && (!alloc->alloc || !alloc->free))
     return fail(ADGI_ERR_INVALID_ARG, "allocator needs both alloc and free");
 
@@ -468,6 +502,19 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.rec, R * 16},
   };
   if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)kPkDecSize * 4});
+  if (d->max_chains > 0) {
+    const size_t C = (size_t)d->max_chains, Smax = R / 2;
+    vol->sort_temp_bytes = chain_sort_temp_bytes((uint32_t)Smax, (int)P);
+    reqs.push_back({(void**)&v.chain_state, C * 32});
+    reqs.push_back({(void**)&v.smp_probe_raw, Smax * 4});
+    reqs.push_back({(void**)&v.smp_uv_raw, Smax * 8});
+    reqs.push_back({(void**)&v.smp_probe, Smax * 4});
+    reqs.push_back({(void**)&v.smp_index, Smax * 4});
+    reqs.push_back({(void**)&v.smp_order, Smax * 4});
+    reqs.push_back({(void**)&v.smp_uv, Smax * 8});
+    reqs.push_back({&vol->d_sort_temp, std::max<size_t>(vol->sort_temp_bytes, 4)});
+    if (dbg) reqs.push_back({(void**)&v.dbg_accept, C * kChainMaxSteps});
+  }
   if (dbg) {
     reqs.push_back({(void**)&v.dbg_tri, R * 4});
     reqs.push_back({(void**)&v.dbg_shadow, R});
@@ -721,9 +768,30 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "update_probes before update_scene");
   if (p->frame < 0) return fail(ADGI_ERR_INVALID_ARG, "frame must be >= 0");
-  if (p->adaptive != 0 && p->adaptive != 1) return fail(ADGI_ERR_INVALID_ARG, "adaptive must be 0 or 1");
+  if (p->adaptive < ADGI_MODE_UNIFORM || p->adaptive > ADGI_MODE_CHAIN)
+    return fail(ADGI_ERR_INVALID_ARG, "adaptive must be 0, 1 or 2 (ADGI_MODE_*)");
   const int64_t P = vol->P, cap = vol->desc.max_rays_per_frame;
-  if (p->adaptive) {
+  const int mode = p->adaptive;
+  int64_t samples = 0;
+  if (mode == ADGI_MODE_CHAIN) {
+    if (vol->desc.max_chains < 1) return fail(ADGI_ERR_INVALID_ARG, "the volume was created with max_chains = 0");
+    if (p->chain_count < 1 || p->chain_count > vol->desc.max_chains)
+      return fail(ADGI_ERR_INVALID_ARG, "chain_count must be in [1, %d]", vol->desc.max_chains);
+    if (p->chain_steps < 2 || p->chain_steps > ADGI_CHAIN_MAX_STEPS)
+      return fail(ADGI_ERR_INVALID_ARG, "chain_steps must be in [2, %d]", ADGI_CHAIN_MAX_STEPS);
+    if (p->chain_burn_in < 0 || p->chain_burn_in > p->chain_steps - 2)
+      return fail(ADGI_ERR_INVALID_ARG, "chain_burn_in must be in [0, chain_steps - 2]");
+    if (!(p->chain_sigma_pos > 0.f) || !std::isfinite(p->chain_sigma_pos) || !(p->chain_sigma_dir > 0.f) ||
+        !std::isfinite(p->chain_sigma_dir))
+      return fail(ADGI_ERR_INVALID_ARG, "chain sigmas must be finite and > 0");
+    if (p->chain_reset != 0 && p->chain_reset != 1) return fail(ADGI_ERR_INVALID_ARG, "chain_reset must be 0 or 1");
+    if (!(p->beta > 0.f) || !std::isfinite(p->beta)) return fail(ADGI_ERR_INVALID_ARG, "beta must be > 0");
+    samples = (int64_t)p->chain_count * (p->chain_steps - p->chain_burn_in - 1);
+    if (2 * samples > cap)
+      return fail(ADGI_ERR_BUDGET, "2 * chain samples (%lld) exceed max_rays_per_frame", (long long)(2 * samples));
+    if (chain_sort_needed_bytes((uint32_t)samples, vol->P) > vol->sort_temp_bytes)
+      return fail(ADGI_ERR_INVALID_ARG, "sort workspace too small for %lld samples", (long long)samples);
+  } else if (mode == ADGI_MODE_ADAPTIVE) {
     if (p->n_min < 1 || p->n_max < p->n_min) return fail(ADGI_ERR_BUDGET, "need 1 <= n_min <= n_max");
     if (p->budget < P * p->n_min)
       return fail(ADGI_ERR_BUDGET, "budget %lld < P*n_min = %lld", (long long)p->budget, (long long)(P * p->n_min));
@@ -735,7 +803,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
     if (p->n_uniform < 1) return fail(ADGI_ERR_BUDGET, "n_uniform must be >= 1");
     if (P * p->n_uniform > cap) return fail(ADGI_ERR_BUDGET, "P*n_uniform exceeds max_rays_per_frame");
   }
-  if (p->n_max > 65535 && p->adaptive) return fail(ADGI_ERR_BUDGET, "n_max must be <= 65535");
+  if (p->n_max > 65535 && mode == ADGI_MODE_ADAPTIVE) return fail(ADGI_ERR_BUDGET, "n_max must be <= 65535");
 
   adgi_status st = order_after_user(vol);
   if (st != ADGI_OK) return st;
@@ -757,15 +825,27 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   fp.theta = p->theta;
   fp.beta = p->beta;
   fp.debug = (vol->desc.flags & ADGI_DEBUG_ARRAYS) ? 1 : 0;
+  if (mode == ADGI_MODE_CHAIN) {
+    fp.chains = p->chain_count;
+    fp.chain_steps = p->chain_steps;
+    fp.chain_burn_in = p->chain_burn_in;
+    fp.chain_init = (p->chain_reset || vol->chain_count != p->chain_count) ? 1 : 0;
+    // an axis with one probe has no extent: chains do not move along it
+    for (int a = 0; a < 3; ++a)
+      fp.chain_sp[a] = vol->desc.dims[a] > 1 ? p->chain_sigma_pos * vol->desc.spacing[a] : 0.0f;
+    fp.chain_sd = p->chain_sigma_dir;
+    vol->chain_count = p->chain_count;
+    vol->chain_steps = p->chain_steps;
+    vol->num_samples = samples;
+  }
   HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.fp, &fp, sizeof(FrameParams), hipMemcpyHostToDevice, vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
-  const int mode = p->adaptive ? 1 : 0;
-  if (vol->tun.use_graph) {
+  if (vol->tun.use_graph && mode != ADGI_MODE_CHAIN) {
     if (!vol->exec[mode]) {
       hipGraph_t graph = nullptr;
       HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
-      hipError_t e = enqueue_frame(vol, p->adaptive != 0);
+      hipError_t e = enqueue_frame(vol, mode);
       hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -782,7 +862,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
     }
     HIP_TRY(vol, hipGraphLaunch(vol->exec[mode], vol->stream));
   } else {
-    HIP_TRY(vol, enqueue_frame(vol, p->adaptive != 0, p->sync ? vol->ev_k : nullptr));
+    HIP_TRY(vol, enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr));
   }
   HIP_TRY(vol, hipEventRecord(vol->ev_t1, vol->stream));
   vol->last_frame = p->frame;
@@ -797,8 +877,8 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       uint32_t total = 0;
       HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
       std::memset(stats, 0, sizeof(*stats));
-      stats->primary_rays = total;
-      stats->pilot_rays = p->adaptive ? 8 * P : 0;
+      stats->primary_rays = mode == ADGI_MODE_CHAIN ? 2 * (int64_t)total : (int64_t)total;
+      stats->pilot_rays = mode != ADGI_MODE_UNIFORM ? 8 * P : 0;
       stats->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
       stats->budget_used = (int64_t)vol->h_stats->budget_used;
       stats->lambda = vol->h_stats->lambda;
@@ -807,7 +887,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       float ms = 0.f;
       HIP_TRY(vol, hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1));
       stats->ms_total = ms;
-      if (!vol->tun.use_graph)
+      if (!vol->tun.use_graph || mode == ADGI_MODE_CHAIN)
         for (int k = 0; k < 6; ++k)
           HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[k], vol->ev_k[k], vol->ev_k[k + 1]));
     }
@@ -874,7 +954,7 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
   HIP_TRY(vol, hipMemcpy(off.data(), vol->v.offsets, (P + 1) * 4, hipMemcpyDeviceToHost));
   if (out->ray_offsets)
     for (size_t i = 0; i <= P; ++i) out->ray_offsets[i] = off[i];
-  const size_t R = vol->last_frame >= 0 ? off[P] : 0;
+  const size_t R = vol->last_frame < 0 ? 0 : vol->last_adaptive == ADGI_MODE_CHAIN ? 2 * (size_t)off[P] : off[P];
   out->num_rays = (int64_t)R;
   if (R) {
     if (out->hit_tri) HIP_TRY(vol, hipMemcpy(out->hit_tri, vol->v.dbg_tri, R * 4, hipMemcpyDeviceToHost));
@@ -887,6 +967,25 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
   if (out->q10_vis) HIP_TRY(vol, hipMemcpy(out->q10_vis, vol->v.qv[qs], P * 16, hipMemcpyDeviceToHost));
   if (out->q10_rad) HIP_TRY(vol, hipMemcpy(out->q10_rad, vol->v.qr[qs], P * 16, hipMemcpyDeviceToHost));
   if (out->frame_rotation) std::memcpy(out->frame_rotation, vol->last_R, sizeof(vol->last_R));
+  out->num_chains = vol->chain_count;
+  out->chain_steps = vol->chain_steps;
+  out->num_samples = vol->chain_count ? vol->num_samples : 0;
+  if (out->chain_state || out->sample_probe || out->sample_uv || out->chain_accept) {
+    if (vol->desc.max_chains < 1) return fail(ADGI_ERR_INVALID_ARG, "chain arrays need max_chains > 0");
+    if (out->chain_accept && !dbg) return fail(ADGI_ERR_INVALID_ARG, "chain_accept needs ADGI_DEBUG_ARRAYS");
+    const size_t C = (size_t)vol->chain_count, S = (size_t)out->num_samples;
+    if (out->chain_state && C) {
+      std::vector<float> st(C * 8);
+      HIP_TRY(vol, hipMemcpy(st.data(), vol->v.chain_state, C * 32, hipMemcpyDeviceToHost));
+      for (size_t c = 0; c < C; ++c)
+        for (int a = 0; a < 5; ++a) out->chain_state[5 * c + a] = st[8 * c + a];
+    }
+    if (out->sample_probe && S)
+      HIP_TRY(vol, hipMemcpy(out->sample_probe, vol->v.smp_probe, S * 4, hipMemcpyDeviceToHost));
+    if (out->sample_uv && S) HIP_TRY(vol, hipMemcpy(out->sample_uv, vol->v.smp_uv, S * 8, hipMemcpyDeviceToHost));
+    if (out->chain_accept && C)
+      HIP_TRY(vol, hipMemcpy(out->chain_accept, vol->v.dbg_accept, C * vol->chain_steps, hipMemcpyDeviceToHost));
+  }
   return ADGI_OK;
 }
 
@@ -938,6 +1037,9 @@ adgi_status adgi_save_state(adgi_volume* vol, void* dst, size_t bytes) {
   h.last_frame = vol->last_frame;
   h.last_adaptive = vol->last_adaptive;
   std::memcpy(h.last_R, vol->last_R, sizeof(h.last_R));
+  h.max_chains = vol->desc.max_chains;
+  h.chain_count = vol->chain_count;
+  h.chain_steps = vol->chain_steps;
   uint8_t* o = (uint8_t*)dst;
   std::memcpy(o, &h, sizeof(h));
   o += sizeof(h);
@@ -955,7 +1057,7 @@ adgi_status adgi_restore_state(adgi_volume* vol, const void* src, size_t bytes) 
   SnapHeader h;
   std::memcpy(&h, src, sizeof(h));
   if (h.magic != kSnapMagic || h.P != vol->P || h.irr_res != vol->desc.irr_res ||
-      h.depth_res != vol->desc.depth_res || h.storage != vol->desc.storage)
+      h.depth_res != vol->desc.depth_res || h.storage != vol->desc.storage || h.max_chains != vol->desc.max_chains)
     return fail(ADGI_ERR_INVALID_ARG, "snapshot does not match this volume");
   HIP_TRY(vol, hipStreamSynchronize(vol->stream));
   const uint8_t* o = (const uint8_t*)src + sizeof(h);
@@ -966,6 +1068,8 @@ adgi_status adgi_restore_state(adgi_volume* vol, const void* src, size_t bytes) 
   vol->last_frame = h.last_frame;
   vol->last_adaptive = h.last_adaptive;
   std::memcpy(vol->last_R, h.last_R, sizeof(h.last_R));
+  vol->chain_count = h.chain_count;
+  vol->chain_steps = h.chain_steps;
   return ADGI_OK;
 }
 
@@ -988,12 +1092,12 @@ adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* 
     (void)adgi_restore_state(vol, snap.data(), snap.size());
     return st;
   }
-  HIP_TRY(vol, enqueue_frame(vol, p->adaptive != 0, nullptr, true));
+  HIP_TRY(vol, enqueue_frame(vol, p->adaptive, nullptr, true));
   HIP_TRY(vol, hipStreamSynchronize(vol->stream));
   HIP_TRY(vol, hipMemcpy(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost));
   uint32_t total = 0;
   HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
-  out->primary_rays = total;
+  out->primary_rays = p->adaptive == ADGI_MODE_CHAIN ? 2 * (int64_t)total : (int64_t)total;
   out->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
   out->node_tests = (int64_t)vol->h_stats->node_tests;
   out->box_tests = out->node_tests * (use_bvh4(vol, vol->tun) ? 4 : 2);
@@ -1007,6 +1111,8 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   if (!vol || !p) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "autotune before update_scene");
+  if (p->adaptive == ADGI_MODE_CHAIN)
+    return fail(ADGI_ERR_INVALID_ARG, "autotune takes a uniform or budgeted frame (chain frames reuse its shapes)");
   const TuneKey key{vol->device, 32 - __builtin_clz((unsigned)vol->P), vol->desc.irr_res * 64 + vol->desc.depth_res,
                     vol->desc.storage * 2 + p->adaptive};
   {

@@ -203,3 +203,95 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
 
 def scene_res(vol):
     return vol.desc.irr_res - 2, vol.desc.depth_res - 2
+
+
+def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int,
+                       sigma_pos: float = 0.5, warm_uniform: int = 2, n_uniform: int = 64,
+                       storage=adgi.ADGI_FP32, seed: int = 0x5EED, tuning=None) -> dict:
+    """Chain frames (ADGI_MODE_CHAIN) in lockstep with the oracle's static
+    Metropolis sampler, after ``warm_uniform`` uniform frames that give the
+    guide a previous irradiance. Every probe is tracked (the guide reads any
+    probe's texels). Each frame the oracle starts from the chain state the GPU
+    left (FP32 values, so FP32/FP64 step rounding does not accumulate across
+    frames), adopts the GPU's accept decisions only where it flags a tie, and
+    must then produce the same samples: probes exactly, uv within 1e-4."""
+    P = scene.num_probes
+    samples = chains * (steps - burn_in - 1)
+    max_rays = max(2 * samples, P * n_uniform)
+    vol = adgi.volume_for_scene(scene, storage=storage, max_rays=max_rays, seed=seed, debug=True,
+                                max_chains=chains)
+    if tuning:
+        vol.set_tuning(**tuning)
+    fp16 = storage == adgi.ADGI_FP16
+    ora = oracle.OracleVolume(scene, seed=seed, fp16=fp16)
+    cp = oracle.ChainParams(chains, steps, burn_in, float(np.float32(sigma_pos)),
+                            float(np.float32(adgi.CHAIN_SIGMA_DIR)))
+    state = np.zeros((chains, 5), np.float64)
+    res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "count_mismatch": 0,
+           "alloc_mismatch": 0, "code_mismatch": 0, "accept_mismatch": 0, "probe_mismatch": 0,
+           "sample_count_mismatch": 0, "max_uv_err": 0.0, "max_state_err": 0.0, "ties": {},
+           "frames": frames, "samples": 0, "accept_rate": 0.0, "max_rel_ray": 0.0}
+    for f in range(warm_uniform + frames):
+        if f > 0:
+            gpu_scene_update(vol, scene, f)
+        chain = f >= warm_uniform
+        if chain:
+            st = vol.update_chains(f, chains, steps, burn_in, sigma_pos=sigma_pos, sync=True)
+        else:
+            st = vol.update_probes(f, adaptive=False, n_uniform=n_uniform, sync=True)
+        rb = vol.read_probes(texels=True, debug=True)
+        hints = {"hit_tri": rb["hit_tri"], "shadow_bits": rb["shadow_bits"],
+                 "irr_bin": rb["irr_bin"], "depth_bin": rb["depth_bin"],
+                 "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
+        if chain:
+            hints["accept"] = rb["chain_accept"].reshape(-1)
+            out = ora.chain_update(f, cp, state, init=(f == warm_uniform), hints=hints)
+            res["code_mismatch"] += int(np.count_nonzero(out["qv"] != rb["q10_vis"])) + \
+                int(np.count_nonzero(out["qr"] != rb["q10_rad"]))
+            res["accept_mismatch"] += int(np.count_nonzero(out["accept"] != hints["accept"]))
+            res["accept_rate"] = float(np.mean(out["accept"]))
+            sp_o = out["sample_probe"][out["perm"]]
+            suv_o = out["sample_uv"][out["perm"]]
+            if rb["num_samples"] != len(sp_o) or st["primary_rays"] != 2 * len(sp_o):
+                res["sample_count_mismatch"] += 1
+            else:
+                res["probe_mismatch"] += int(np.count_nonzero(rb["sample_probe"] != sp_o))
+                res["max_uv_err"] = max(res["max_uv_err"], float(np.abs(
+                    rb["sample_uv"].astype(np.float64) - suv_o).max(initial=0.0)))
+            res["max_state_err"] = max(res["max_state_err"], float(np.abs(
+                rb["chain_state"].astype(np.float64) - state).max(initial=0.0)))
+            res["samples"] += len(sp_o)
+            # the next frame starts where the GPU's chains stopped
+            state[:] = rb["chain_state"].astype(np.float64)
+            c = out["counts"]
+            res["mismatches"] += c["chain_mismatch"] + c["q10_mismatch"]
+            for k in ("chain_ties", "q10_ties"):
+                res["ties"][k] = res["ties"].get(k, 0) + c[k]
+        else:
+            out = ora.update(f, adaptive=False, n_uniform=n_uniform, hints=hints)
+            c = out["counts"]
+        res["mismatches"] += c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"]
+        for k in ("hit_ties", "shadow_ties", "bin_ties"):
+            res["ties"][k] = res["ties"].get(k, 0) + c[k]
+        res["alloc_mismatch"] += int(np.count_nonzero(out["n"] != rb["rays_per_probe"]))
+        ei = rel_err(rb["irradiance"], ora.irradiance_tiles())
+        ed = rel_err(rb["depth"], ora.depth_tiles())
+        if fp16:
+            qi = np.abs(rb["irradiance"].astype(np.float64) - ora.irradiance_tiles()) <= \
+                f16_quantum(ora.irradiance_tiles())
+            qd = np.abs(rb["depth"].astype(np.float64) - ora.depth_tiles()) <= \
+                f16_quantum(ora.depth_tiles())
+            res["f16_quantum_ties"] = res.get("f16_quantum_ties", 0) + \
+                int(np.count_nonzero(qi & (ei > 0))) + int(np.count_nonzero(qd & (ed > 0)))
+            ei, ed = np.where(qi, 0.0, ei), np.where(qd, 0.0, ed)
+        res["max_rel_irr"] = max(res["max_rel_irr"], float(ei.max(initial=0.0)))
+        res["max_rel_depth"] = max(res["max_rel_depth"], float(ed.max(initial=0.0)))
+        res["count_mismatch"] += int(np.count_nonzero(
+            rb["irr_count"].reshape(P, -1) != np.minimum(ora.irr_n, 255))) + int(np.count_nonzero(
+                rb["depth_count"].reshape(P, -1) != np.minimum(ora.dep_n, 255)))
+        res["stats_last"] = st
+    res["vs_oracle"] = texel_error_report(rb["irradiance"], rb["depth"], ora.irradiance_tiles(),
+                                          ora.depth_tiles())
+    res["oracle_counts"] = ora.counts.as_dict()
+    vol.destroy_volume()
+    return res

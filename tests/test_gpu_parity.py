@@ -154,3 +154,54 @@ def test_packed_words_box_field_adaptive():
     print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
     _report("box_field_packed", res)
     _assert_packed(res)
+
+
+# ---- static Metropolis chains (ADGI_MODE_CHAIN)
+
+def _assert_chain_parity(res, tol=1e-4):
+    assert res["mismatches"] == 0, res
+    assert res["code_mismatch"] == 0 and res["accept_mismatch"] == 0, res
+    assert res["sample_count_mismatch"] == 0 and res["probe_mismatch"] == 0, res
+    assert res["alloc_mismatch"] == 0 and res["count_mismatch"] == 0, res
+    # chain states: one frame of FP32 steps from the same start
+    assert res["max_uv_err"] <= 1e-4 and res["max_state_err"] <= 1e-4, res
+    assert res["max_rel_irr"] <= tol and res["max_rel_depth"] <= tol, res
+
+
+def test_chains_cornell_lockstep():
+    """256 chains x 64 steps (burn-in 15) in the Cornell room after two
+    uniform frames, three chain frames: samples, accept decisions, per-probe
+    sample counts and texels against the oracle."""
+    from tests.parity import run_chain_lockstep
+    res = run_chain_lockstep(scenes.cornell(), frames=3, chains=256, steps=64, burn_in=15)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    assert res["samples"] == 3 * 256 * 48
+    assert 0.05 < res["accept_rate"] < 0.95, res
+    _report("chains_cornell", res)
+    _assert_chain_parity(res)
+
+
+def test_chains_flat_box_field_lockstep():
+    """A one-layer probe grid (8 x 1 x 8) over a box field: 2048 chains x 40
+    steps (burn-in 7), two chain frames; the chains move in x, z and uv only."""
+    from tests.parity import run_chain_lockstep
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 300, lattice=24, dims=(8, 1, 8), n_lights=2,
+                          frames=8)
+    res = run_chain_lockstep(sc, frames=2, chains=2048, steps=40, burn_in=7, n_uniform=32)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_chain_parity(res)
+
+
+def test_chains_box_field_ragged_lockstep():
+    """Box field, 8 x 2 x 8 probes, 1000 chains (not a multiple of the wave)
+    x 23 steps (burn-in 4), FP16 texels against the binary16-emulating oracle."""
+    import paper_2301_05125_amd as adgi
+    from tests.parity import run_chain_lockstep
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 301, lattice=24, dims=(8, 2, 8), n_lights=1,
+                          frames=8)
+    res = run_chain_lockstep(sc, frames=3, chains=1000, steps=23, burn_in=4, n_uniform=48,
+                             storage=adgi.ADGI_FP16)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    texels = res["vs_oracle"]["irradiance"]["texels"] + res["vs_oracle"]["depth"]["texels"]
+    assert res.get("f16_quantum_ties", 0) <= 2e-3 * texels * (res["frames"] + 2), res
+    _assert_chain_parity(res, tol=2e-3)

@@ -150,3 +150,109 @@ def test_allocator_failure_reports_out_of_memory():
     with pytest.raises(adgi.AdgiError) as e:
         adgi.Volume(sc.grid_origin, sc.grid_spacing, sc.grid_dims, allocator=a)
     assert e.value.status == -2
+
+
+# ---- chain frames
+
+def _chain_run(sc, frames, tuning=None, vol=None, start=0, chains=768, steps=24, burn_in=5):
+    own = vol is None
+    if own:
+        vol = adgi.volume_for_scene(sc, max_rays=max(2 * chains * steps, sc.num_probes * 32), seed=5,
+                                    max_chains=chains)
+    if tuning:
+        vol.set_tuning(**tuning)
+    for f in range(start, start + frames):
+        vol.update_scene(sc.positions_at(f), light_pos=sc.light_positions(f),
+                         light_intensity=sc.light_intensity, sky=sc.sky,
+                         mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, sc.anim_vertices))
+        if f < 1:
+            vol.update_probes(f, adaptive=False, n_uniform=32, sync=True)
+        else:
+            st = vol.update_chains(f, chains, steps, burn_in, sync=True)
+            assert st["primary_rays"] == 2 * chains * (steps - burn_in - 1)
+            assert st["pilot_rays"] == 8 * sc.num_probes
+    rb = vol.read_probes()
+    if own:
+        vol.destroy_volume()
+    return rb
+
+
+def _same_chain(a, b):
+    _same(a, b)
+    for k in ("chain_state", "sample_probe", "sample_uv"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("tuning", [
+    {"persistent": 0},
+    {"trace_block": 256, "trace_waves_per_cu": 16},
+    {"bvh_width": 4},
+    {"blend_blocks_per_cu": 4},
+])
+def test_chain_launch_shape_does_not_change_results(tuning):
+    sc = _small_field()
+    _same_chain(_chain_run(sc, 4), _chain_run(sc, 4, tuning=tuning))
+
+
+def test_chain_snapshot_resumes_bit_identically():
+    sc = _small_field()
+    ref = _chain_run(sc, 5)
+    vol = adgi.volume_for_scene(sc, max_rays=2 * 768 * 24, seed=5, max_chains=768)
+    _chain_run(sc, 3, vol=vol)
+    snap = vol.save_state()
+    vol.destroy_volume()
+    vol2 = adgi.volume_for_scene(sc, max_rays=2 * 768 * 24, seed=5, max_chains=768)
+    vol2.restore_state(snap)
+    got = _chain_run(sc, 2, vol=vol2, start=3)
+    vol2.destroy_volume()
+    _same_chain(ref, got)
+
+
+def test_chain_and_budgeted_frames_interleave():
+    """A budgeted frame between chain frames leaves the chains where they
+    stopped; the sequence is deterministic."""
+    sc = _small_field()
+
+    def run():
+        vol = adgi.volume_for_scene(sc, max_rays=1 << 16, seed=9, max_chains=512)
+        vol.update_probes(0, adaptive=False, n_uniform=16, sync=True)
+        vol.update_chains(1, 512, 20, 3, sync=True)
+        s1 = vol.read_probes(texels=False)["chain_state"].copy()
+        vol.update_probes(2, adaptive=True, budget=sc.num_probes * 16, n_min=4, n_max=64, sync=True)
+        s2 = vol.read_probes(texels=False)["chain_state"].copy()
+        vol.update_chains(3, 512, 20, 3, sync=True)
+        rb = vol.read_probes()
+        vol.destroy_volume()
+        return s1, s2, rb
+
+    a1, a2, ra = run()
+    b1, b2, rb = run()
+    assert np.array_equal(a1, a2)
+    assert np.array_equal(a1, b1)
+    _same_chain(ra, rb)
+
+
+def test_chain_error_paths():
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 210, lattice=16, dims=(8, 2, 8), n_lights=1,
+                          frames=2)
+    plain = adgi.volume_for_scene(sc, max_rays=4096)
+    with pytest.raises(adgi.AdgiError) as e:
+        plain.update_chains(0, 16, 8, 1)
+    assert e.value.status == adgi.ADGI_ERR_INVALID_ARG
+    plain.destroy_volume()
+    with pytest.raises(adgi.AdgiError) as e:
+        adgi.volume_for_scene(sc, storage=adgi.ADGI_PACKED, max_rays=4096, max_chains=16)
+    assert e.value.status == adgi.ADGI_ERR_INVALID_ARG
+    vol = adgi.volume_for_scene(sc, max_rays=4096, max_chains=64)
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_chains(0, 64, 40, 0)  # 2 * 64 * 39 rays > 4096
+    assert e.value.status == adgi.ADGI_ERR_BUDGET
+    for bad in ((65, 8, 1), (16, 1, 0), (16, 8, 7), (16, 300, 1)):
+        with pytest.raises(adgi.AdgiError) as e:
+            vol.update_chains(0, *bad)
+        assert e.value.status == adgi.ADGI_ERR_INVALID_ARG, bad
+    with pytest.raises(adgi.AdgiError):
+        vol.update_chains(0, 16, 8, 1, sigma_pos=0.0)
+    st = vol.update_chains(0, 64, 16, 0, sync=True)
+    assert st["primary_rays"] == 2 * 64 * 15
+    vol.destroy_volume()

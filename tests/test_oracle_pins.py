@@ -832,3 +832,61 @@ def test_chain_samples_layout_and_domain():
     s3 = np.zeros((16, 5))
     c = oracle.chain_frame(g, cp, 6, 0, qv, irr, r, s3, init=True)
     assert not np.array_equal(a["sample_uv"], c["sample_uv"])
+
+
+def _np_oct_uv(d):
+    """Octahedral coordinates of unit directions (Cigolle et al. 2014), numpy."""
+    d = np.asarray(d, np.float64)
+    p = d[:, :2] / np.abs(d).sum(axis=1, keepdims=True)
+    low = d[:, 2] < 0
+    s = np.where(p >= 0, 1.0, -1.0)
+    fold = (1.0 - np.abs(p[:, ::-1])) * s
+    return np.where(low[:, None], fold, p)
+
+
+def _np_oct_dir(uv):
+    uv = np.asarray(uv, np.float64)
+    z = 1.0 - np.abs(uv).sum(axis=1)
+    s = np.where(uv >= 0, 1.0, -1.0)
+    xy = np.where((z < 0)[:, None], (1.0 - np.abs(uv[:, ::-1])) * s, uv)
+    d = np.concatenate([xy, z[:, None]], axis=1)
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def test_chain_update_two_rays_per_sample():
+    """A chain frame on a fresh volume with hysteresis 0: each sample adds one
+    irradiance count in the texel of d(uv) and one depth count in the texel of
+    -d at its nearest probe, and each depth texel then holds tau of the last
+    such sample's -d ray, found here by brute force over the triangles."""
+    sc = scenes.cornell()
+    ora = oracle.OracleVolume(sc, seed=21, hysteresis=0.0)
+    cp = oracle.ChainParams(24, 12, 3, 0.5, oracle.SIGMA_DIR)
+    state = np.zeros((24, 5))
+    out = ora.chain_update(0, cp, state, init=True)
+    ri, rd = ora.irr_res - 2, ora.depth_res - 2
+    perm, sp, suv = out["perm"], out["sample_probe"], out["sample_uv"]
+    assert len(sp) == 24 * 8 and out["n"].sum() == len(sp)
+    assert np.array_equal(np.sort(sp, kind="stable"), sp[perm])
+    d = _np_oct_dir(suv[perm])
+    probes = sp[perm]
+    bi = np.clip(np.floor((_np_oct_uv(d) + 1.0) * 0.5 * ri).astype(int), 0, ri - 1)
+    bd = np.clip(np.floor((_np_oct_uv(-d) + 1.0) * 0.5 * rd).astype(int), 0, rd - 1)
+    ki = bi[:, 1] * ri + bi[:, 0]
+    kd = bd[:, 1] * rd + bd[:, 0]
+    want_i = np.zeros((ora.P, ri * ri), np.int64)
+    want_d = np.zeros((ora.P, rd * rd), np.int64)
+    np.add.at(want_i, (probes, ki), 1)
+    np.add.at(want_d, (probes, kd), 1)
+    assert np.array_equal(ora.irr_n, want_i) and np.array_equal(ora.dep_n, want_d)
+    s = float(np.sqrt(np.sum(np.asarray(sc.grid_spacing, np.float64) ** 2)))
+    last = {}
+    for k in range(len(probes)):
+        last[(probes[k], kd[k])] = k
+    for (p, b), k in last.items():
+        dx, dy, _ = (int(x) for x in sc.grid_dims)
+        o = np.asarray(sc.grid_origin, np.float64) + np.asarray(sc.grid_spacing, np.float64) * \
+            np.array([p % dx, (p // dx) % dy, p // (dx * dy)])
+        h = ora.scene.closest_hit(o, -d[k], brute=True)
+        tau = min(h.t / s, ora.tau_max) if h.tri >= 0 else ora.tau_max
+        assert abs(ora.dep[p, 2 * b] - tau) <= 1e-9 * max(tau, 1.0), (p, b)
+        assert abs(ora.dep[p, 2 * b + 1] - tau * tau) <= 1e-9 * max(tau * tau, 1.0), (p, b)
