@@ -181,6 +181,76 @@ def stage_times(vol, sc, adgi, frame0, frames, **p):
     return [a / frames for a in acc], f
 
 
+# Chain frames on the same scene: the paper's 4096 static chains (about 64
+# used samples each, Sec. 4.7 and Sec. 5), and as many chains as probes,
+# which traces the adaptive budget B = 2^23 (two rays per sample).
+CHAIN_CONFIGS = {
+    "paper_4096_chains": dict(chains=4096, steps=80, burn_in=15),
+    "equal_budget": dict(chains=65536, steps=80, burn_in=15),
+}
+CHAIN_STAGES = ["setup", "pilot_trace", "chains_and_sort", "blend_order", "sample_trace", "blend"]
+
+
+def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, chains, steps_per_chain,
+               burn_in):
+    """Chain frames: two warm uniform frames give the guide an irradiance,
+    then `warmup` untimed and `steps` timed chain frames (scene update
+    included, as in the budgeted steps), then synchronous frames for latency
+    and per-stage times (chain frames launch eagerly, stage events between
+    the kernels)."""
+    P = sc.num_probes
+    S = steps_per_chain - burn_in - 1
+    vol = adgi.volume_for_scene(sc, storage=storage, max_rays=max(2 * chains * S, P * 32), seed=11,
+                                max_chains=chains)
+    vol.set_tuning(**tuning)
+    kw = dict(chains=chains, steps=steps_per_chain, burn_in=burn_in)
+    f = 0
+    for _ in range(2):
+        step_scene(vol, sc, f, adgi)
+        vol.update_probes(f, adaptive=False, n_uniform=32, sync=False)
+        f += 1
+    for _ in range(warmup):
+        step_scene(vol, sc, f, adgi)
+        vol.update_chains(f, sync=False, **kw)
+        f += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_scene(vol, sc, f, adgi)
+        vol.update_chains(f, sync=False, **kw)
+        f += 1
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    host_ms, gpu_ms, stage = [], [], [0.0] * 6
+    for _ in range(latency_frames):
+        step_scene(vol, sc, f, adgi)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = vol.update_chains(f, sync=True, **kw)
+        host_ms.append((time.perf_counter() - a) * 1e3)
+        gpu_ms.append(st["ms_total"])
+        for k in range(6):
+            stage[k] += st["ms_stage"][k] / latency_frames
+        f += 1
+    tw = vol.measure_chain_trace_work(f, **kw)
+    rb = vol.read_probes(texels=False)
+    n = rb["rays_per_probe"]
+    vol.destroy_volume()
+    rays = 2 * chains * S
+    trace_ms = stage[4]
+    nr = max(tw["primary_rays"] + tw["shadow_rays"], 1)
+    return {"chains": chains, "steps": steps_per_chain, "burn_in": burn_in, "samples_per_frame": chains * S,
+            "rays_per_frame": rays, "rays_per_s": rays * steps / seconds,
+            "ms_per_step": seconds / steps * 1e3,
+            "p50_ms": pct(host_ms, 50), "p99_ms": pct(host_ms, 99),
+            "gpu_p50_ms": pct(gpu_ms, 50), "gpu_p99_ms": pct(gpu_ms, 99),
+            "stage_ms": dict(zip(CHAIN_STAGES, stage)),
+            "sample_trace_mrays_per_s_incl_shadow": nr / (trace_ms * 1e-3) / 1e6 if trace_ms else None,
+            "sample_trace_tops": (tw["box_tests"] * OPS_PER_BOX + tw["tri_tests"] * OPS_PER_TRI)
+            / (trace_ms * 1e-3) / 1e12 if trace_ms else None,
+            "probes_with_samples": int((n > 0).sum()), "max_samples_per_probe": int(n.max())}
+
+
 def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
     """The oracle as it stands, on the host cores, on a bounded sample of the
     adaptive frame: the scene update, all pilot rays, detection and allocation
@@ -326,6 +396,8 @@ def main():
     ap.add_argument("--skip-uniform", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the 32-stream serving mix")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--chains", default=",".join(CHAIN_CONFIGS),
+                    help="comma-separated chain-frame configurations to run (none: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -447,6 +519,16 @@ def main():
         "scene_build_s": build_s,
     }
     vol.destroy_volume()
+    chain_names = [c for c in args.chains.split(",") if c and c != "none"]
+    if chain_names:
+        out["chain_frames"] = {}
+        for name in chain_names:
+            c = CHAIN_CONFIGS[name]
+            out["chain_frames"][name] = run_chains(
+                adgi, torch, sc, storage if args.storage != "packed" else adgi.ADGI_FP32, tuning,
+                args.steps, args.warmup, min(args.latency_frames, 20), c["chains"], c["steps"],
+                c["burn_in"])
+            print(f"[bench] chains {name} done", file=sys.stderr, flush=True)
     if not args.no_serve:
         out["serving"] = run_serving(adgi, duration_s=args.serve_seconds)
         print(f"[bench] serving done", file=sys.stderr, flush=True)

@@ -262,6 +262,11 @@ typedef struct {
   int32_t bvh_width;          /* 4: traverse the 4-wide BVH collapsed from the
                                  binary one (when its stack bound fits), else 2;
                                  2: the binary BVH                                */
+  int32_t chain_lanes;        /* chain frames: 1 = one thread per chain, steps in
+                                 sequence; 4 / 8 / 16 / 32 = prefetching groups of
+                                 that many lanes per chain, 2..5 steps per round
+                                 (Brockwell 2006), the same chains bit for bit;
+                                 0 = chosen from the chain count                  */
 } adgi_tuning;
 
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);

@@ -130,7 +130,8 @@ class ServerStats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("persistent", C.c_int32), ("trace_block", C.c_int32),
                 ("trace_waves_per_cu", C.c_int32), ("blend_chunk", C.c_int32),
-                ("blend_blocks_per_cu", C.c_int32), ("bvh_width", C.c_int32)]
+                ("blend_blocks_per_cu", C.c_int32), ("bvh_width", C.c_int32),
+                ("chain_lanes", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -328,14 +329,18 @@ class Volume:
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
 
+    @staticmethod
+    def _chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync):
+        return UpdateParams(int(frame), ADGI_MODE_CHAIN, 0, 1, 1, 1, float(beta), 2, 8,
+                            1 if sync else 0, int(chains), int(steps), int(burn_in),
+                            float(sigma_pos), float(sigma_dir), 1 if reset else 0)
+
     def update_chains(self, frame, chains, steps, burn_in, sigma_pos=0.5, sigma_dir=CHAIN_SIGMA_DIR,
                       reset=False, beta=5.0, sync=True) -> dict:
         """One chain frame (ADGI_MODE_CHAIN): pilots, `chains` static
         Metropolis chains of `steps` steps each (the first burn_in + 1 emit
         nothing), two rays per sample, blend."""
-        p = UpdateParams(int(frame), ADGI_MODE_CHAIN, 0, 1, 1, 1, float(beta), 2, 8,
-                         1 if sync else 0, int(chains), int(steps), int(burn_in),
-                         float(sigma_pos), float(sigma_dir), 1 if reset else 0)
+        p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync)
         st = UpdateStats()
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
@@ -417,6 +422,14 @@ class Volume:
                            n_uniform=64, beta=5.0, mu=2, theta=8) -> dict:
         p = UpdateParams(int(frame), 1 if adaptive else 0, int(budget), int(n_min), int(n_max),
                          int(n_uniform), float(beta), int(mu), int(theta), 1)
+        w = TraceWork()
+        _check(lib().adgi_measure_trace_work(self.h, C.byref(p), C.byref(w)))
+        return w.as_dict()
+
+    def measure_chain_trace_work(self, frame, chains, steps, burn_in, sigma_pos=0.5,
+                                 sigma_dir=CHAIN_SIGMA_DIR, beta=5.0) -> dict:
+        """Traversal work of a chain frame's sample rays (state restored after)."""
+        p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, False, beta, True)
         w = TraceWork()
         _check(lib().adgi_measure_trace_work(self.h, C.byref(p), C.byref(w)))
         return w.as_dict()

@@ -21,12 +21,15 @@ hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool per
 
 // chain.hip: one frame of `chains` Metropolis chains, then their samples
 // sorted by probe (v.smp_probe / v.smp_uv, v.offsets / v.n as per-probe
-// sample ranges). samples = chains * (steps - burn_in - 1).
+// sample ranges). samples = chains * (steps - burn_in - 1). lanes: 1 (one
+// thread per chain) or 4 / 8 / 16 (prefetching groups); chain_lanes_auto
+// picks one from the chain count.
 size_t chain_sort_temp_bytes(uint32_t max_samples, int P);
 size_t chain_sort_needed_bytes(uint32_t samples, int P);
+int chain_lanes_auto(int chains);
 // alloc.hip: blend order (most 64-entry chunks first) from counts already in v.n
 hipError_t launch_blend_order(const VolumeView& v, hipStream_t s);
-hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int chains, uint32_t samples,
+hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int chains, int lanes, uint32_t samples,
                          void* sort_temp, size_t sort_temp_bytes, hipStream_t s);
 
 // detect.hip: trigger update and the separable 5x5x5 box sum -> scores

@@ -128,9 +128,8 @@ struct VolumeView {
   uint32_t* smp_probe_raw;
   float2* smp_uv_raw;
   uint32_t* smp_probe;        // sorted
-  uint32_t* smp_index;        // 0, 1, 2, ... (sort input)
-  uint32_t* smp_order;        // sorted: raw sample index
   float2* smp_uv;             // sorted
+  float* chain_lum;           // [P][(irr_res-2)/2]^2 g of each coarse cell
   uint8_t* dbg_accept;        // [C][steps] (debug)
   const float* pk_dec;        // packed storage: decoded value of every code
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(256) void order_count_kernel(VolumeView v) {
   __shared__ uint32_t hist[kOrderBuckets];
   const int i = blockIdx.x * 256 + threadIdx.x;
   count_buckets(v, i < v.P, i < v.P ? v.n[i] : 0, hist);
+  if (i == 0) v.stats->budget_used = v.offsets[v.P];
 }
 
 hipError_t launch_blend_order(const VolumeView& v, hipStream_t s) {

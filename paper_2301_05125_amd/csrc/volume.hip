@@ -238,7 +238,8 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
     if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
       return e;
     if ((e = mark(2)) != hipSuccess) return e;
-    if ((e = launch_chains(v, vol->desc.storage == ADGI_FP16, vol->irr, vol->chain_count,
+    const int lanes = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->chain_count);
+    if ((e = launch_chains(v, vol->desc.storage == ADGI_FP16, vol->irr, vol->chain_count, lanes,
                            (uint32_t)vol->num_samples, vol->d_sort_temp, vol->sort_temp_bytes, s)) != hipSuccess)
       return e;
     if ((e = mark(3)) != hipSuccess) return e;
@@ -357,6 +358,7 @@ adgi_tuning default_tuning() {
   t.blend_chunk = 256;
   t.blend_blocks_per_cu = 16;
   t.bvh_width = 2;
+  t.chain_lanes = 0;
   return t;
 }
 
@@ -366,7 +368,9 @@ bool tuning_valid(const adgi_tuning& t) {
          t.trace_waves_per_cu >= 1 && t.trace_waves_per_cu <= 32 &&
          (t.blend_chunk == 0 || (t.blend_chunk >= 64 && t.blend_chunk <= 2048 && t.blend_chunk % 64 == 0)) &&
          t.blend_blocks_per_cu >= 1 && t.blend_blocks_per_cu <= 32 &&
-         (t.bvh_width == 2 || t.bvh_width == 4);
+         (t.bvh_width == 2 || t.bvh_width == 4) &&
+         (t.chain_lanes == 0 || t.chain_lanes == 1 || t.chain_lanes == 4 || t.chain_lanes == 8 ||
+          t.chain_lanes == 16 || t.chain_lanes == 32);
 }
 
 }  // namespace
@@ -509,9 +513,9 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
     reqs.push_back({(void**)&v.smp_probe_raw, Smax * 4});
     reqs.push_back({(void**)&v.smp_uv_raw, Smax * 8});
     reqs.push_back({(void**)&v.smp_probe, Smax * 4});
-    reqs.push_back({(void**)&v.smp_index, Smax * 4});
-    reqs.push_back({(void**)&v.smp_order, Smax * 4});
     reqs.push_back({(void**)&v.smp_uv, Smax * 8});
+    const size_t m = (size_t)(d->irr_res - 2) / 2;
+    reqs.push_back({(void**)&v.chain_lum, (size_t)P * m * m * 4});
     reqs.push_back({&vol->d_sort_temp, std::max<size_t>(vol->sort_temp_bytes, 4)});
     if (dbg) reqs.push_back({(void**)&v.dbg_accept, C * kChainMaxSteps});
   }

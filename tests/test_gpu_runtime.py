@@ -188,8 +188,15 @@ def _same_chain(a, b):
     {"trace_block": 256, "trace_waves_per_cu": 16},
     {"bvh_width": 4},
     {"blend_blocks_per_cu": 4},
+    {"chain_lanes": 1},
+    {"chain_lanes": 4},
+    {"chain_lanes": 8},
+    {"chain_lanes": 32},
 ])
 def test_chain_launch_shape_does_not_change_results(tuning):
+    """Every launch shape, and the one-thread-per-chain kernel against the
+    prefetching groups (16 lanes for 768 chains by default), give the same
+    chains and texels bit for bit."""
     sc = _small_field()
     _same_chain(_chain_run(sc, 4), _chain_run(sc, 4, tuning=tuning))
 
