@@ -137,8 +137,21 @@ def lib():
         L.orc_chain_h.restype = C.c_double
         L.orc_chain_frame.restype = None
         L.orc_chain_probes_frame.restype = None
-        L.orc_chain_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32,
+        L.orc_chain_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, P, P, C.c_int32, C.c_int32,
                                              C.c_double, C.c_double, C.c_int32] + [P] * 9
+        L.orc_dynamic_fd.argtypes = [P, C.c_int32, P, P, P, P]
+        L.orc_proxy_dims.argtypes = [P, P]
+        L.orc_proxy_of_probe.restype = C.c_int32
+        L.orc_proxy_of_probe.argtypes = [P, C.c_int32]
+        L.orc_proxy_max.argtypes = [P, P, P]
+        L.orc_dyn_chain_frame.argtypes = [P, P, C.c_uint64, C.c_int32, P, P, C.c_int32, P, P, P, P]
+        L.orc_octant_texels.restype = C.c_int32
+        L.orc_octant_texels.argtypes = [C.c_int32, C.c_int32, P]
+        L.orc_texel_centre_dir.argtypes = [C.c_int32, C.c_int32, P]
+        L.orc_dyn_ray_count.restype = C.c_int32
+        L.orc_dyn_ray_count.argtypes = [C.c_int32, C.c_int32, C.c_uint32]
+        L.orc_dyn_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, C.c_int32, C.c_int32, C.c_double,
+                                           C.c_double, C.c_int32, P, P, P, P, P, P, P]
         L.orc_chain_dir.restype = None
         L.orc_set_threads.restype = None
         _lib = L
@@ -281,7 +294,7 @@ class ChainParams(C.Structure):
                 ("sigma_pos", C.c_double), ("sigma_dir", C.c_double)]
 
 
-SIGMA_DIR = math.sqrt(math.pi / 256.0)  # the paper's angular step (Sec. 4.7)
+SIGMA_DIR = math.sqrt(math.pi / 256.0)  # the paper's angular step (Sec. 4.8)
 
 
 def chain_h(grid, qv, irr_prev, r: int, x) -> tuple:
@@ -311,6 +324,68 @@ def chain_frame(grid, params: ChainParams, seed: int, frame: int, qv, irr_prev, 
                           C.c_int32(frame), _p(qv), _p(irr_prev), C.c_int32(r), _p(state),
                           C.c_int32(1 if init else 0), _p(ha), _p(acc), _p(sp), _p(suv), C.byref(cnt))
     return {"accept": acc[:C_ * M], "sample_probe": sp[:C_ * S], "sample_uv": suv[:C_ * S]}
+
+
+def dynamic_fd(grid, mu: int, qv, tv, tr) -> np.ndarray:
+    """f_d [P*8] (int64) of every (probe, octant), eq. priorDynamic."""
+    P = int(np.prod(np.asarray(grid.dims[:], np.int64)))
+    fd = np.zeros(P * 8, np.int64)
+    lib().orc_dynamic_fd(C.byref(grid), int(mu), _p(np.ascontiguousarray(qv, np.uint16)),
+                         _p(np.ascontiguousarray(tv, np.int32)), _p(np.ascontiguousarray(tr, np.int32)),
+                         _p(fd))
+    return fd
+
+
+def proxy_dims(grid) -> tuple:
+    pd = np.zeros(3, np.int32)
+    lib().orc_proxy_dims(C.byref(grid), _p(pd))
+    return tuple(int(x) for x in pd)
+
+
+def proxy_max(grid, fd) -> np.ndarray:
+    """F [Pp*8] (int64): max of f_d over each 3x3x3 proxy, per octant."""
+    Pp = int(np.prod(proxy_dims(grid)))
+    F = np.zeros(Pp * 8, np.int64)
+    lib().orc_proxy_max(C.byref(grid), _p(np.ascontiguousarray(fd, np.int64)), _p(F))
+    return F
+
+
+def dyn_chain_frame(grid, params: ChainParams, seed: int, frame: int, F, state, init: bool,
+                    hint_accept=None, counts=None) -> dict:
+    """One frame of every dynamic chain (state [C][5] in place) -> marks [Pp*8]."""
+    C_, M = params.chains, params.steps
+    assert state.dtype == np.float64 and state.flags["C_CONTIGUOUS"] and state.shape == (C_, 5)
+    F = np.ascontiguousarray(F, np.int64)
+    mark = np.zeros(F.shape[0], np.uint8)
+    acc = np.zeros(max(C_ * M, 1), np.uint8)
+    ha = None if hint_accept is None else np.ascontiguousarray(hint_accept, np.uint8)
+    cnt = counts if counts is not None else Counts()
+    lib().orc_dyn_chain_frame(C.byref(grid), C.byref(params), seed & 0xFFFFFFFFFFFFFFFF, int(frame), _p(F),
+                              _p(state), 1 if init else 0, _p(ha), _p(acc), _p(mark), C.byref(cnt))
+    return {"accept": acc[:C_ * M], "mark": mark}
+
+
+def octant_texels(r: int, k: int) -> np.ndarray:
+    n = lib().orc_octant_texels(r, k, None)
+    out = np.zeros(max(n, 1), np.int32)
+    lib().orc_octant_texels(r, k, _p(out))
+    return out[:n]
+
+
+def texel_centre_dir(r: int, t: int) -> np.ndarray:
+    d = np.zeros(3)
+    lib().orc_texel_centre_dir(r, t, _p(d))
+    return d
+
+
+def dyn_ray_counts(grid, mark, irr_res: int, depth_res: int) -> np.ndarray:
+    """Dynamic rays of every probe (probe order) given the proxy marks."""
+    P = int(np.prod(np.asarray(grid.dims[:], np.int64)))
+    mark = np.asarray(mark, np.uint8).reshape(-1, 8)
+    bits = (mark.astype(np.uint32) << np.arange(8, dtype=np.uint32)).sum(axis=1)
+    per_mask = np.array([lib().orc_dyn_ray_count(irr_res, depth_res, m) for m in range(256)], np.int64)
+    px = np.array([lib().orc_proxy_of_probe(C.byref(grid), i) for i in range(P)], np.int64)
+    return per_mask[bits[px]]
 
 
 def chain_order(sample_probe: np.ndarray, P: int):
@@ -440,6 +515,7 @@ class OracleVolume:
         self.tv = np.zeros(self.P * 8, np.int32)
         self.tr = np.zeros(self.P * 8, np.int32)
         self.score = np.zeros(self.P, np.int64)
+        self.qv_odd = np.zeros(self.P * 8, np.uint16)  # codes of the last frame that ran detection
         self.counts = Counts()
 
     def set_frame_inputs(self, frame: int):
@@ -532,18 +608,27 @@ class OracleVolume:
         return out
 
     def chain_update(self, frame: int, params: "ChainParams", state: np.ndarray, init: bool,
-                     beta: float = 5.0, hints: Optional[dict] = None) -> dict:
-        """One frame of the static Metropolis chain sampler: pilots (for
-        f_v), one frame of every chain against the previous frame's
-        irradiance, then each sample's two rays blended into its nearest
-        probe in sample order. Tracks every probe (the target reads any
-        probe's irradiance). ``state`` [C][5] is updated in place; ``hints``
-        may hold the GPU's qv/qr codes, accept decisions and per-ray
-        decisions (in the GPU's sorted sample order)."""
+                     beta: float = 5.0, hints: Optional[dict] = None, mu: int = 2, theta: int = 8,
+                     dyn: Optional["ChainParams"] = None, dyn_state: Optional[np.ndarray] = None,
+                     dyn_init: bool = False, h_dyn: float = 0.91) -> dict:
+        """One chain frame: pilots (for f_v), detection (triggers and scores
+        kept current), one frame of every static chain against the previous
+        frame's irradiance, each sample's two rays blended into its nearest
+        probe in sample order; with ``dyn``, the dynamic chains on the 3x3x3
+        proxies of f_d mark (proxy, octant) pairs, static samples at probes
+        with a dynamic component trace through texel centres, and every
+        probe of a marked proxy then updates the octant's texels through
+        their centres with hysteresis ``h_dyn``. Tracks every probe.
+        ``state`` / ``dyn_state`` [C][5] are updated in place; ``hints`` may
+        hold the GPU's qv/qr codes, accept decisions and per-ray decisions
+        (sample rays in the GPU's sorted order, then the dynamic rays)."""
         assert self.probes.shape[0] == self.P, "chain frames need every probe tracked"
         hints = hints or {}
         self.set_frame_inputs(frame)
         qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"))
+        self.detect(frame, qv, qr, theta, mu)
+        if frame & 1:
+            self.qv_odd = qv.copy()
         ri, rd = self.irr_res - 2, self.depth_res - 2
         irr_prev = self.irr.copy()
         cnt = Counts()
@@ -551,21 +636,43 @@ class OracleVolume:
                           hints.get("accept"), cnt)
         perm, n, base = chain_order(out["sample_probe"], self.P)
         suv = np.ascontiguousarray(out["sample_uv"][perm])
+        S2 = 2 * len(perm)
+        quant = None
+        if dyn is not None:
+            self.h_dyn = float(np.float32(h_dyn))
+            fd = dynamic_fd(self.grid, mu, self.qv_odd, self.tv, self.tr)
+            F = proxy_max(self.grid, fd)
+            dout = dyn_chain_frame(self.grid, dyn, self.seed, frame, F, dyn_state, dyn_init,
+                                   hints.get("dyn_accept"), cnt)
+            quant = np.ascontiguousarray(self.score > 0, np.uint8)
+            out.update(F=F, fd=fd, mark=dout["mark"], dyn_accept=dout["accept"])
 
-        def h(name, dtype):
+        def h(name, dtype, lo, hi):
             a = hints.get(name)
-            return None if a is None else np.ascontiguousarray(np.asarray(a)[:2 * len(perm)], dtype)
+            return None if a is None else np.ascontiguousarray(np.asarray(a)[lo:hi], dtype)
 
         lib().orc_chain_probes_frame(
             self.scene.ptr, C.byref(self.grid), self.P, _p(self.probes), _p(n), _p(base), _p(suv),
-            C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
-            1 if self.fp16 else 0, _p(h("hit_tri", np.int32)), _p(h("shadow_bits", np.uint8)), _p(h("irr_bin", np.uint16)),
-            _p(h("depth_bin", np.uint16)), _p(self.irr), _p(self.irr_n), _p(self.dep), _p(self.dep_n),
-            C.byref(cnt))
+            _p(quant), C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
+            1 if (self.fp16 and dyn is None) else 0, _p(h("hit_tri", np.int32, 0, S2)),
+            _p(h("shadow_bits", np.uint8, 0, S2)), _p(h("irr_bin", np.uint16, 0, S2)),
+            _p(h("depth_bin", np.uint16, 0, S2)), _p(self.irr), _p(self.irr_n), _p(self.dep),
+            _p(self.dep_n), C.byref(cnt))
+        if dyn is not None:
+            nd = dyn_ray_counts(self.grid, out["mark"], self.irr_res, self.depth_res)
+            dbase = np.ascontiguousarray(np.concatenate([[0], np.cumsum(nd)])[:-1], np.int64)
+            R = int(nd.sum())
+            lib().orc_dyn_probes_frame(
+                self.scene.ptr, C.byref(self.grid), self.P, _p(self.probes), _p(out["mark"]), _p(dbase),
+                C.byref(self.tol), self.irr_res, self.depth_res, self.h_dyn, self.tau_max,
+                1 if self.fp16 else 0, _p(h("hit_tri", np.int32, S2, S2 + R)),
+                _p(h("shadow_bits", np.uint8, S2, S2 + R)), _p(self.irr), _p(self.irr_n), _p(self.dep),
+                _p(self.dep_n), C.byref(cnt))
+            out.update(dyn_rays=nd, dyn_offsets=np.concatenate([dbase, [R]]))
         for name, _ in Counts._fields_:
             setattr(self.counts, name, getattr(self.counts, name) + getattr(cnt, name))
         out.update(qv=qv, qr=qr, n=n, offsets=np.concatenate([base, [len(perm)]]), perm=perm,
-                   counts=cnt.as_dict())
+                   counts=cnt.as_dict(), score=self.score.copy())
         return out
 
     # views in the library's readback layout

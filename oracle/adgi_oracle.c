@@ -1299,10 +1299,18 @@ double orc_chain_h(const orc_grid* g, const uint16_t* qv, const double* irr_prev
   return exp(fmin(lum / f, 1.0)) * f;
 }
 
-void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, int32_t frame,
-                     const uint16_t* qv, const double* irr_prev, int32_t r, double* state, int32_t init,
-                     const uint8_t* hint_accept, uint8_t* accept, int32_t* sample_probe,
-                     double* sample_uv, orc_counts* counts) {
+/* The chain loop of Alg. MarkovChainMT with the random-walk step of Alg.
+ * MetropolisStep, for any target: h(x) returns the density and the discrete
+ * cell the state falls in (the nearest probe for the static target, proxy
+ * and octant for the dynamic one); emit(s, cell, h, x) receives the state
+ * after every step past the burn-in. */
+typedef double (*chain_target)(const void* ctx, const double x[5], int32_t* cell, int32_t* tie);
+typedef void (*chain_emit)(void* ctx, int64_t s, int32_t cell, double h, const double x[5]);
+
+static void chain_run(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, uint64_t tag_step,
+                      uint64_t tag_init, int32_t frame, chain_target target, const void* tctx, double* state,
+                      int32_t init, const uint8_t* hint_accept, uint8_t* accept, chain_emit emit, void* ectx,
+                      orc_counts* counts) {
   const int32_t C = cp->chains, M = cp->steps, K = cp->burn_in;
   const int32_t S = M - K - 1 > 0 ? M - K - 1 : 0;
   int64_t ties = 0, mism = 0;
@@ -1310,19 +1318,19 @@ void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t see
   for (int32_t c = 0; c < C; ++c) {
     double* x = state + 5 * (size_t)c;
     if (init) {
-      uint64_t key = orc_key(seed, ORC_TAG_CHAININIT, (uint64_t)(uint32_t)c, 0, 0);
+      uint64_t key = orc_key(seed, tag_init, (uint64_t)(uint32_t)c, 0, 0);
       for (int a = 0; a < 3; ++a)
         x[a] = g->origin[a] + orc_uniform(key, (uint64_t)(a + 1)) * (g->dims[a] - 1) * g->spacing[a];
       x[3] = 2.0 * orc_uniform(key, 4) - 1.0;
       x[4] = 2.0 * orc_uniform(key, 5) - 1.0;
     }
-    int32_t pr = 0;
+    int32_t cell = 0;
     int tie_y = 0, dtie = 0;
     double y = 0.0;
-    if (chain_in_domain(g, x, &dtie)) y = orc_chain_h(g, qv, irr_prev, r, x, &pr, &tie_y);
+    if (chain_in_domain(g, x, &dtie)) y = target(tctx, x, &cell, &tie_y);
     tie_y |= dtie;
     for (int32_t i = 0; i < M; ++i) {
-      uint64_t key = orc_key(seed, ORC_TAG_CHAIN, (uint64_t)(uint32_t)c, (uint64_t)(uint32_t)frame,
+      uint64_t key = orc_key(seed, tag_step, (uint64_t)(uint32_t)c, (uint64_t)(uint32_t)frame,
                              (uint64_t)(uint32_t)i);
       double u[8];
       for (int q = 1; q <= 7; ++q) u[q] = orc_uniform(key, (uint64_t)q);
@@ -1341,8 +1349,8 @@ void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t see
       int ptie = 0, ttie = 0;
       int in = chain_in_domain(g, xp, &ttie);
       double yp = 0.0;
-      int32_t prp = pr;
-      if (in) yp = orc_chain_h(g, qv, irr_prev, r, xp, &prp, &ptie);
+      int32_t cellp = cell;
+      if (in) yp = target(tctx, xp, &cellp, &ptie);
       ptie |= ttie;
       int acc = in && (y <= 0.0 || u[7] * y <= yp);
       int tie = ptie || tie_y || (in && y > 0.0 && fabs(u[7] * y - yp) <= 1e-4 * fmax(yp, u[7] * y)) ||
@@ -1362,18 +1370,11 @@ void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t see
       if (acc) {
         for (int a = 0; a < 5; ++a) x[a] = xp[a];
         y = yp;
-        pr = prp;
+        cell = cellp;
         tie_y = ptie;
       }
       if (accept) accept[(size_t)c * M + i] = (uint8_t)acc;
-      if (i > K) {
-        size_t s = (size_t)c * S + (size_t)(i - K - 1);
-        if (sample_probe) sample_probe[s] = pr;
-        if (sample_uv) {
-          sample_uv[2 * s] = x[3];
-          sample_uv[2 * s + 1] = x[4];
-        }
-      }
+      if (i > K) emit(ectx, (int64_t)c * S + (i - K - 1), cell, y, x);
     }
   }
   if (counts) {
@@ -1382,9 +1383,261 @@ void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t see
   }
 }
 
+typedef struct {
+  const orc_grid* g;
+  const uint16_t* qv;
+  const double* irr_prev;
+  int32_t r;
+} static_target_ctx;
+
+static double static_target(const void* ctx, const double x[5], int32_t* cell, int32_t* tie) {
+  const static_target_ctx* t = (const static_target_ctx*)ctx;
+  return orc_chain_h(t->g, t->qv, t->irr_prev, t->r, x, cell, tie);
+}
+
+typedef struct {
+  int32_t* sample_probe;
+  double* sample_uv;
+} static_emit_ctx;
+
+static void static_emit(void* ctx, int64_t s, int32_t cell, double h, const double x[5]) {
+  (void)h;
+  static_emit_ctx* e = (static_emit_ctx*)ctx;
+  if (e->sample_probe) e->sample_probe[s] = cell;
+  if (e->sample_uv) {
+    e->sample_uv[2 * s] = x[3];
+    e->sample_uv[2 * s + 1] = x[4];
+  }
+}
+
+void orc_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, int32_t frame,
+                     const uint16_t* qv, const double* irr_prev, int32_t r, double* state, int32_t init,
+                     const uint8_t* hint_accept, uint8_t* accept, int32_t* sample_probe,
+                     double* sample_uv, orc_counts* counts) {
+  static_target_ctx t = {g, qv, irr_prev, r};
+  static_emit_ctx e = {sample_probe, sample_uv};
+  chain_run(g, cp, seed, ORC_TAG_CHAIN, ORC_TAG_CHAININIT, frame, static_target, &t, state, init, hint_accept,
+            accept, static_emit, &e, counts);
+}
+
+/* ---------------------------------------------------- dynamic chains (Sec. 4.9) */
+
+void orc_dynamic_fd(const orc_grid* g, int32_t mu, const uint16_t* qv, const int32_t* tv, const int32_t* tr,
+                    int64_t* fd) {
+  const int32_t dx = g->dims[0], dy = g->dims[1], dz = g->dims[2];
+  const int64_t P = (int64_t)dx * dy * dz;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < P; ++i) {
+    int32_t x = (int32_t)(i % dx), y = (int32_t)((i / dx) % dy), z = (int32_t)(i / ((int64_t)dx * dy));
+    for (int32_t k = 0; k < 8; ++k) {
+      int64_t cv = 0, cr = 0;
+      for (int32_t zz = z - 2; zz <= z + 2; ++zz)
+        for (int32_t yy = y - 2; yy <= y + 2; ++yy)
+          for (int32_t xx = x - 2; xx <= x + 2; ++xx) {
+            if (xx < 0 || yy < 0 || zz < 0 || xx >= dx || yy >= dy || zz >= dz) continue;
+            int64_t j = xx + (int64_t)dx * (yy + (int64_t)dy * zz);
+            cv += tv[j * 8 + k];
+            cr += tr[j * 8 + k];
+          }
+      fd[i * 8 + k] = (int64_t)qv[i * 8 + k] * (cv + (int64_t)mu * cr);
+    }
+  }
+}
+
+void orc_proxy_dims(const orc_grid* g, int32_t pd[3]) {
+  for (int a = 0; a < 3; ++a) pd[a] = (g->dims[a] + 2) / 3;
+}
+
+int32_t orc_proxy_of_probe(const orc_grid* g, int32_t probe) {
+  int32_t pd[3];
+  orc_proxy_dims(g, pd);
+  const int32_t dx = g->dims[0], dy = g->dims[1];
+  const int32_t x = probe % dx, y = (probe / dx) % dy, z = probe / (dx * dy);
+  return x / 3 + pd[0] * (y / 3 + pd[1] * (z / 3));
+}
+
+void orc_proxy_max(const orc_grid* g, const int64_t* fd, int64_t* F) {
+  int32_t pd[3];
+  orc_proxy_dims(g, pd);
+  const int64_t Pp = (int64_t)pd[0] * pd[1] * pd[2];
+  for (int64_t q = 0; q < Pp * 8; ++q) F[q] = 0;
+  const int64_t P = (int64_t)g->dims[0] * g->dims[1] * g->dims[2];
+  for (int64_t i = 0; i < P; ++i) {
+    const int64_t q = orc_proxy_of_probe(g, (int32_t)i);
+    for (int k = 0; k < 8; ++k)
+      if (fd[i * 8 + k] > F[q * 8 + k]) F[q * 8 + k] = fd[i * 8 + k];
+  }
+}
+
+typedef struct {
+  const orc_grid* g;
+  const int64_t* F;
+} dyn_target_ctx;
+
+/* h = F of the proxy of the nearest probe, in the octant of uv (alpha = 0:
+ * the stored irradiance plays no part). */
+static double dyn_target(const void* ctx, const double x[5], int32_t* cell, int32_t* tie) {
+  const dyn_target_ctx* t = (const dyn_target_ctx*)ctx;
+  const orc_grid* g = t->g;
+  int tt = 0;
+  int32_t idx[3];
+  for (int a = 0; a < 3; ++a) {
+    double f = g->dims[a] > 1 ? (x[a] - g->origin[a]) / g->spacing[a] : 0.0;
+    int32_t i = (int32_t)floor(f + 0.5);
+    if (i < 0) i = 0;
+    if (i > g->dims[a] - 1) i = g->dims[a] - 1;
+    idx[a] = i;
+    if (g->dims[a] > 1 && near_frac(f + 0.5, 1e-5)) tt = 1;
+  }
+  const int32_t pr = idx[0] + g->dims[0] * (idx[1] + g->dims[1] * idx[2]);
+  double d[3];
+  orc_oct_decode(x + 3, d);
+  const int32_t k = (d[0] < 0.0 ? 1 : 0) | (d[1] < 0.0 ? 2 : 0) | (d[2] < 0.0 ? 4 : 0);
+  for (int a = 0; a < 3; ++a)
+    if (fabs(d[a]) < 1e-6) tt = 1;
+  const int32_t q = orc_proxy_of_probe(g, pr);
+  *cell = q * 8 + k;
+  if (tie) *tie = tt;
+  return (double)t->F[q * 8 + k];
+}
+
+static void dyn_emit(void* ctx, int64_t s, int32_t cell, double h, const double x[5]) {
+  (void)s;
+  (void)x;
+  uint8_t* mark = (uint8_t*)ctx;
+  if (h > 0.0) {
+#pragma omp atomic write
+    mark[cell] = 1;
+  }
+}
+
+void orc_dyn_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, int32_t frame,
+                         const int64_t* F, double* state, int32_t init, const uint8_t* hint_accept,
+                         uint8_t* accept, uint8_t* mark, orc_counts* counts) {
+  dyn_target_ctx t = {g, F};
+  chain_run(g, cp, seed, ORC_TAG_DYNCHAIN, ORC_TAG_DYNCHAININIT, frame, dyn_target, &t, state, init,
+            hint_accept, accept, dyn_emit, mark, counts);
+}
+
+int32_t orc_octant_texels(int32_t r, int32_t k, int32_t* list) {
+  int32_t n = 0;
+  for (int32_t y = 0; y < r; ++y)
+    for (int32_t x = 0; x < r; ++x) {
+      /* centre uv = ((2x+1)/r - 1, (2y+1)/r - 1), signs and the diagonal in integers */
+      const int32_t cx = 2 * x + 1 - r, cy = 2 * y + 1 - r;
+      const int32_t o = (cx < 0 ? 1 : 0) | (cy < 0 ? 2 : 0) | (abs(cx) + abs(cy) > r ? 4 : 0);
+      if (o == k) {
+        if (list) list[n] = y * r + x;
+        ++n;
+      }
+    }
+  return n;
+}
+
+void orc_texel_centre_dir(int32_t r, int32_t t, double d[3]) {
+  const int32_t x = t % r, y = t / r;
+  const double uv[2] = {(2.0 * x + 1.0) / r - 1.0, (2.0 * y + 1.0) / r - 1.0};
+  orc_oct_decode(uv, d);
+}
+
+int32_t orc_dyn_ray_count(int32_t irr_r, int32_t dep_r, uint32_t octant_mask) {
+  int32_t n = 0;
+  for (int32_t k = 0; k < 8; ++k)
+    if (octant_mask & (1u << k)) n += orc_octant_texels(irr_r - 2, k, NULL) + orc_octant_texels(dep_r - 2, k, NULL);
+  return n;
+}
+
+void orc_dyn_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
+                          const uint8_t* mark, const int64_t* ray_base, const orc_tol* tol, int32_t irr_r,
+                          int32_t dep_r, double h_dyn, double tau_max, int32_t fp16, const int32_t* hint_tri,
+                          const uint8_t* hint_shadow, double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
+                          orc_counts* counts) {
+  const int32_t ri = irr_r - 2, rd = dep_r - 2;
+  int32_t li[8][34 * 34], ld[8][34 * 34], ni[8], nd[8];
+  for (int32_t k = 0; k < 8; ++k) {
+    ni[k] = orc_octant_texels(ri, k, li[k]);
+    nd[k] = orc_octant_texels(rd, k, ld[k]);
+  }
+  orc_counts total;
+  memset(&total, 0, sizeof(total));
+#pragma omp parallel
+  {
+    orc_counts loc;
+    memset(&loc, 0, sizeof(loc));
+#pragma omp for schedule(dynamic, 4)
+    for (int32_t q = 0; q < count; ++q) {
+      double o[3];
+      orc_probe_pos(g, probes[q], o);
+      double* I = irr + (size_t)q * ri * ri * 3;
+      double* D = dep + (size_t)q * rd * rd * 2;
+      uint8_t* IN = irr_n + (size_t)q * ri * ri;
+      uint8_t* DN = dep_n + (size_t)q * rd * rd;
+      const int32_t px = orc_proxy_of_probe(g, probes[q]);
+      int64_t ties[2] = {0, 0}, mism[2] = {0, 0};
+      int64_t j = ray_base ? ray_base[q] : 0;
+      for (int32_t k = 0; k < 8; ++k) {
+        if (!mark[px * 8 + k]) continue;
+        /* irradiance texels of the octant: one shaded ray through each centre */
+        for (int32_t m = 0; m < ni[k]; ++m, ++j) {
+          const int32_t t = li[k][m];
+          double d[3];
+          orc_texel_centre_dir(ri, t, d);
+          orc_ray ra;
+          orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[j] : -2,
+                        hint_shadow ? (int32_t)hint_shadow[j] : -1, &ra, ties, mism);
+          loc.rays += 1;
+          if (ra.tri >= 0 && ra.front) loc.shadow_rays += s->nl;
+          const double a = orc_blend_alpha(IN[t], h_dyn);
+          for (int c = 0; c < 3; ++c) I[3 * t + c] += a * (ra.rgb[c] - I[3 * t + c]);
+          if (IN[t] < 255) IN[t]++;
+        }
+        /* depth texels of the octant: the distance of a ray through each centre */
+        for (int32_t m = 0; m < nd[k]; ++m, ++j) {
+          const int32_t t = ld[k][m];
+          double d[3];
+          orc_texel_centre_dir(rd, t, d);
+          orc_ray rb;
+          orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[j] : -2, -1, &rb, ties, mism);
+          loc.rays += 1;
+          const double tau = isfinite(rb.t) ? fmin(rb.t / g->s, tau_max) : tau_max;
+          const double a = orc_blend_alpha(DN[t], h_dyn);
+          D[2 * t + 0] += a * (tau - D[2 * t + 0]);
+          D[2 * t + 1] += a * (tau * tau - D[2 * t + 1]);
+          if (DN[t] < 255) DN[t]++;
+        }
+      }
+      if (fp16) { /* the frame's one binary16 store */
+        for (int32_t k = 0; k < ri * ri * 3; ++k) I[k] = orc_round_half(I[k]);
+        for (int32_t k = 0; k < rd * rd * 2; ++k) D[k] = orc_round_half(D[k]);
+      }
+      loc.hit_ties += ties[0];
+      loc.shadow_ties += ties[1];
+      loc.hit_mismatch += mism[0];
+      loc.shadow_mismatch += mism[1];
+    }
+#pragma omp critical
+    {
+      total.hit_ties += loc.hit_ties;
+      total.shadow_ties += loc.shadow_ties;
+      total.hit_mismatch += loc.hit_mismatch;
+      total.shadow_mismatch += loc.shadow_mismatch;
+      total.rays += loc.rays;
+      total.shadow_rays += loc.shadow_rays;
+    }
+  }
+  if (counts) {
+    counts->hit_ties += total.hit_ties;
+    counts->shadow_ties += total.shadow_ties;
+    counts->hit_mismatch += total.hit_mismatch;
+    counts->shadow_mismatch += total.shadow_mismatch;
+    counts->rays += total.rays;
+    counts->shadow_rays += total.shadow_rays;
+  }
+}
+
 void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
                             const int32_t* nsamp, const int64_t* sample_base, const double* sample_uv,
-                            const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
+                            const uint8_t* quant, const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
                             double tau_max, int32_t fp16, const int32_t* hint_tri, const uint8_t* hint_shadow,
                             const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
                             uint8_t* irr_n, double* dep, uint8_t* dep_n, orc_counts* counts) {
@@ -1409,12 +1662,6 @@ void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count
         double d[3], nd[3];
         orc_chain_dir(sample_uv + 2 * k, d);
         for (int a = 0; a < 3; ++a) nd[a] = -d[a];
-        /* irradiance: the ray along d, shaded as a probe ray */
-        orc_ray ra, rb;
-        orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[2 * k] : -2,
-                      hint_shadow ? (int32_t)hint_shadow[2 * k] : -1, &ra, ties, mism);
-        loc.rays += 1;
-        if (ra.tri >= 0 && ra.front) loc.shadow_rays += s->nl;
         int32_t ti = 0;
         int32_t ki = orc_oct_bin(d, ri, tol ? tol->bin_eps : 0.0, &ti);
         if (hint_ibin && hint_ibin[2 * k] != ki) {
@@ -1425,12 +1672,6 @@ void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count
             loc.bin_mismatch++;
           }
         }
-        double ai = orc_blend_alpha(IN[ki], hysteresis);
-        for (int c = 0; c < 3; ++c) I[3 * ki + c] += ai * (ra.rgb[c] - I[3 * ki + c]);
-        if (IN[ki] < 255) IN[ki]++;
-        /* visibility: the ray along -d, its distance into the depth texel of -d */
-        orc_shade_ray(s, o, nd, g->s, tol, hint_tri ? hint_tri[2 * k + 1] : -2, -1, &rb, ties, mism);
-        loc.rays += 1;
         int32_t td = 0;
         int32_t kd = orc_oct_bin(nd, rd, tol ? tol->bin_eps : 0.0, &td);
         if (hint_dbin && hint_dbin[2 * k + 1] != kd) {
@@ -1441,6 +1682,24 @@ void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count
             loc.bin_mismatch++;
           }
         }
+        /* a probe with a dynamic component traces through the texel centres
+         * (Sec. 4.9): the rays then add no sampling noise to the texels */
+        if (quant && quant[q]) {
+          orc_texel_centre_dir(ri, ki, d);
+          orc_texel_centre_dir(rd, kd, nd);
+        }
+        /* irradiance: the ray along d, shaded as a probe ray */
+        orc_ray ra, rb;
+        orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[2 * k] : -2,
+                      hint_shadow ? (int32_t)hint_shadow[2 * k] : -1, &ra, ties, mism);
+        loc.rays += 1;
+        if (ra.tri >= 0 && ra.front) loc.shadow_rays += s->nl;
+        double ai = orc_blend_alpha(IN[ki], hysteresis);
+        for (int c = 0; c < 3; ++c) I[3 * ki + c] += ai * (ra.rgb[c] - I[3 * ki + c]);
+        if (IN[ki] < 255) IN[ki]++;
+        /* visibility: the ray along -d, its distance into the depth texel of -d */
+        orc_shade_ray(s, o, nd, g->s, tol, hint_tri ? hint_tri[2 * k + 1] : -2, -1, &rb, ties, mism);
+        loc.rays += 1;
         double tau = isfinite(rb.t) ? fmin(rb.t / g->s, tau_max) : tau_max;
         double ad = orc_blend_alpha(DN[kd], hysteresis);
         D[2 * kd + 0] += ad * (tau - D[2 * kd + 0]);

@@ -43,6 +43,8 @@ double   orc_uniform(uint64_t key, uint64_t q);   /* top 24 bits of mix(key^q) *
 #define ORC_TAG_PILOT    0x50494Cull  /* "PIL" */
 #define ORC_TAG_CHAIN    0x4D4353ull  /* "MCS": a Metropolis step */
 #define ORC_TAG_CHAININIT 0x4D4349ull /* "MCI": a chain's first state */
+#define ORC_TAG_DYNCHAIN 0x4D4453ull  /* "MDS": a dynamic-chain step */
+#define ORC_TAG_DYNCHAININIT 0x4D4449ull /* "MDI": a dynamic chain's first state */
 
 /* Per-frame rotation (Shoemake, Graphics Gems III 1992), FP64 -> FP32. */
 void orc_frame_rotation(uint64_t seed, int32_t frame, float R[9]);
@@ -193,8 +195,8 @@ void orc_packed_blend(int32_t count, const int32_t* n, const int64_t* ray_base, 
                       const uint16_t* ibin, const uint16_t* dbin, int32_t ri, int32_t rd, float inv_s,
                       float tau_max, const float* alpha, uint32_t* irr, uint32_t* dep);
 
-/* ---- Metropolis chains over (position, direction) (Sec. 3.2, Alg.
- * MarkovChainMT, Alg. MetropolisStep, Sec. 4.7: the static chain).
+/* ---- Metropolis chains over (position, direction) (Sec. 3.2-3.3, Alg.
+ * MarkovChainMT, Alg. MetropolisStep, Sec. 4.8: the static chain).
  * State x = (p, uv): p in the box spanned by the probe centres, uv the
  * octahedral coordinates of the direction in [-1, 1]^2. Target
  * h = exp(min(g/f, 1)) f, f = Qv/1024 of the nearest probe's octant of the
@@ -231,15 +233,58 @@ void orc_chain_dir(const double uv[2], double d[3]);
 /* Chain samples of the listed probes, each probe's samples in ascending
  * sample order: ray along d(uv) from the probe centre (shaded, as probe rays)
  * updates the irradiance texel of d; ray along -d updates the depth texel of
- * -d with its distance (the visibility ray of Sec. 4.7). Samples of list
+ * -d with its distance (the visibility ray of Sec. 4.8). Samples of list
  * entry q: [sample_base[q], sample_base[q] + nsamp[q]) of sample_uv; hints
- * and ray outputs indexed 2k (ray along d) and 2k+1 (along -d). */
+ * and ray outputs indexed 2k (ray along d) and 2k+1 (along -d). quant
+ * (optional, per list entry): nonzero traces the two rays through the centres
+ * of the irradiance texel of d and of the depth texel of -d instead. */
 void orc_chain_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
                             const int32_t* nsamp, const int64_t* sample_base, const double* sample_uv,
-                            const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
+                            const uint8_t* quant, const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis,
                             double tau_max, int32_t fp16, const int32_t* hint_tri, const uint8_t* hint_shadow,
                             const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
                             uint8_t* irr_n, double* dep, uint8_t* dep_n, orc_counts* counts);
+
+/* ---- dynamic chains on virtual proxies (Sec. 4.9) -----------------------
+ * f_d of every (probe, octant), eq. priorDynamic with f_c = 1: Qv (Cv + mu Cr),
+ * C the 5x5x5 sums (zero outside the grid) of the triggers Tv, Tr, Qv the
+ * pilot visibility codes of the frame that last ran detection. */
+void orc_dynamic_fd(const orc_grid* g, int32_t mu, const uint16_t* qv, const int32_t* tv, const int32_t* tr,
+                    int64_t* fd);
+/* Virtual proxies: groups of 3x3x3 probes (proxy (X,Y,Z) holds probes with
+ * x/3 = X, y/3 = Y, z/3 = Z; the last group along an axis may be smaller),
+ * proxy grid ceil(dims/3). F[proxy][octant] = max of f_d over its probes. */
+void orc_proxy_dims(const orc_grid* g, int32_t pd[3]);
+int32_t orc_proxy_of_probe(const orc_grid* g, int32_t probe);
+void orc_proxy_max(const orc_grid* g, const int64_t* fd, int64_t* F);
+/* One frame of the dynamic chains: the same random walk as the static chain
+ * (keys MDS / MDI instead of MCS / MCI) on the target h = F[proxy of the
+ * nearest probe][octant of uv] (alpha = 0). Every state past the burn-in with
+ * h > 0 sets mark[proxy][octant] = 1 (each marked octant is updated once). */
+void orc_dyn_chain_frame(const orc_grid* g, const orc_chain_params* cp, uint64_t seed, int32_t frame,
+                         const int64_t* F, double* state, int32_t init, const uint8_t* hint_accept,
+                         uint8_t* accept, uint8_t* mark, orc_counts* counts);
+/* Interior texels (row-major y*r + x) whose centres lie in octant k, in
+ * ascending order: centre uv = ((2x+1)/r - 1, (2y+1)/r - 1), octant bits
+ * u < 0, v < 0, |u| + |v| > 1 (centres on the diagonal belong to the upper
+ * half); returns the count; list may be NULL. */
+int32_t orc_octant_texels(int32_t r, int32_t k, int32_t* list);
+/* Unit direction through the centre of interior texel t of an r x r map. */
+void orc_texel_centre_dir(int32_t r, int32_t t, double d[3]);
+/* Dynamic rays of a probe whose proxy has the octants in octant_mask marked. */
+int32_t orc_dyn_ray_count(int32_t irr_r, int32_t dep_r, uint32_t octant_mask);
+/* Dynamic updates of the listed probes, after the frame's static samples: for
+ * each marked octant of the probe's proxy, ascending, one shaded ray through
+ * the centre of each irradiance texel of the octant (into that texel) and
+ * then one ray through the centre of each depth texel of the octant (its
+ * distance into that texel), both with a = max(1/(N+1), 1 - h_dyn). Ray j of
+ * list entry q is hint index ray_base[q] + j. fp16: round the tiles to
+ * binary16 at the end (the frame's only store). */
+void orc_dyn_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
+                          const uint8_t* mark, const int64_t* ray_base, const orc_tol* tol, int32_t irr_r,
+                          int32_t dep_r, double h_dyn, double tau_max, int32_t fp16, const int32_t* hint_tri,
+                          const uint8_t* hint_shadow, double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
+                          orc_counts* counts);
 
 int32_t orc_num_threads(void);
 /* Threads for the following OpenMP regions (timing only). */

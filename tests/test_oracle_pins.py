@@ -736,7 +736,7 @@ def test_packed_constant_input_fixed_point_and_count():
 
 # ------------------------------------------------------- Metropolis chains
 # The static chain (Alg. MarkovChainMT with Alg. MetropolisStep, target
-# h = exp(min(g/f, 1)) f of Sec. 4.7). Pins: the properties of h the paper
+# h = exp(min(g/f, 1)) f of Sec. 4.8). Pins: the properties of h the paper
 # states (g is trusted only where f is low: h in [f, e f], h = f without
 # feedback, h = e f once g >= f, zero where f is zero), and the theorem that
 # makes the sampler correct: a symmetric random walk with Metropolis
@@ -890,3 +890,200 @@ def test_chain_update_two_rays_per_sample():
         tau = min(h.t / s, ora.tau_max) if h.tri >= 0 else ora.tau_max
         assert abs(ora.dep[p, 2 * b] - tau) <= 1e-9 * max(tau, 1.0), (p, b)
         assert abs(ora.dep[p, 2 * b + 1] - tau * tau) <= 1e-9 * max(tau * tau, 1.0), (p, b)
+
+
+# ---- dynamic chains on 3x3x3 virtual proxies (Sec. 4.9)
+
+@pytest.mark.parametrize("r", [5, 6, 7, 14])
+def test_octant_texels_partition_the_map(r):
+    """The octants' texel-centre lists partition the r x r map, and each
+    centre's direction lies in its octant (sign of x, y, z; centres on the
+    diagonal |u| + |v| = 1 give z = 0 and belong to the upper half)."""
+    seen = np.zeros(r * r, np.int64)
+    for k in range(8):
+        lst = oracle.octant_texels(r, k)
+        seen[lst] += 1
+        for t in lst:
+            d = oracle.texel_centre_dir(r, int(t))
+            assert abs(np.linalg.norm(d) - 1.0) < 1e-12
+            if abs(d[0]) > 1e-12:
+                assert (d[0] < 0) == bool(k & 1)
+            if abs(d[1]) > 1e-12:
+                assert (d[1] < 0) == bool(k & 2)
+            if abs(d[2]) > 1e-12:
+                assert (d[2] < 0) == bool(k & 4)
+            # the ray through a centre falls in that texel
+            assert oracle.oct_bin(d, r)[0] == t
+    assert np.all(seen == 1)
+    if r == 6:
+        assert [len(oracle.octant_texels(6, k)) for k in range(8)] == [6, 6, 6, 6, 3, 3, 3, 3]
+    if r == 14:
+        assert [len(oracle.octant_texels(14, k)) for k in range(8)] == [28] * 4 + [21] * 4
+
+
+def test_dynamic_fd_closed_form_and_proxy_max():
+    """One visibility trigger T at probe j, octant 3 and one radiance trigger
+    R at probe m, octant 6: f_d(i, k) = Qv(i,k) (T [k=3, i within the 5x5x5
+    box of j] + mu R [k=6, i within the box of m]); F is the max over each
+    3x3x3 block of probes (last blocks partial)."""
+    dims = (7, 4, 5)
+    g = oracle.make_grid(np.zeros(3, np.float32), np.ones(3, np.float32), np.asarray(dims, np.int32))
+    P = 7 * 4 * 5
+    rng = np.random.default_rng(4)
+    qv = rng.integers(0, 1024, P * 8).astype(np.uint16)
+    tv = np.zeros(P * 8, np.int32)
+    tr = np.zeros(P * 8, np.int32)
+    j, m, T, R, mu = 2 + 7 * (1 + 4 * 2), 6 + 7 * (3 + 4 * 0), 700, 300, 2
+    tv[8 * j + 3] = T
+    tr[8 * m + 6] = R
+    fd = oracle.dynamic_fd(g, mu, qv, tv, tr)
+
+    def coords(i):
+        return np.array([i % 7, (i // 7) % 4, i // 28])
+
+    want = np.zeros(P * 8, np.int64)
+    for i in range(P):
+        if np.max(np.abs(coords(i) - coords(j))) <= 2:
+            want[8 * i + 3] += int(qv[8 * i + 3]) * T
+        if np.max(np.abs(coords(i) - coords(m))) <= 2:
+            want[8 * i + 6] += int(qv[8 * i + 6]) * mu * R
+    assert np.array_equal(fd, want)
+    F = oracle.proxy_max(g, fd)
+    pd = oracle.proxy_dims(g)
+    assert pd == (3, 2, 2)
+    grid = fd.reshape(5, 4, 7, 8)  # [z][y][x][octant]
+    for Z in range(pd[2]):
+        for Y in range(pd[1]):
+            for X in range(pd[0]):
+                q = X + pd[0] * (Y + pd[1] * Z)
+                blk = grid[3 * Z:3 * Z + 3, 3 * Y:3 * Y + 3, 3 * X:3 * X + 3].reshape(-1, 8)
+                assert np.array_equal(F[8 * q:8 * q + 8], blk.max(axis=0))
+
+
+def test_dynamic_chain_targets_and_marks():
+    """The dynamic chain's states settle with density proportional to F over
+    (proxy region, octant), and only cells with F > 0 are marked."""
+    dims = (6, 3, 3)
+    g = oracle.make_grid(np.zeros(3, np.float32), np.ones(3, np.float32), np.asarray(dims, np.int32))
+    pd = oracle.proxy_dims(g)
+    assert pd == (2, 1, 1)
+    F = np.zeros(2 * 8, np.int64)
+    F[0 * 8 + 1] = 400
+    F[0 * 8 + 6] = 100
+    F[1 * 8 + 1] = 200
+    F[1 * 8 + 4] = 300
+    cp = oracle.ChainParams(512, 40, 0, 1.5, 6 * oracle.SIGMA_DIR)
+    state = np.zeros((512, 5))
+    occ = np.zeros(16)
+    marks_seen = np.zeros(16, np.uint8)
+    for frame in range(60):
+        out = oracle.dyn_chain_frame(g, cp, 7, frame, F, state, init=(frame == 0))
+        marks_seen |= out["mark"]
+        if frame < 4:
+            continue
+        px = np.where(state[:, 0] < 2.5, 0, 1)  # nearest probe x < 3 -> proxy 0
+        d = np.array([oracle.oct_decode(uv) for uv in state[:, 3:]])
+        k = (d[:, 0] < 0).astype(int) | (d[:, 1] < 0).astype(int) << 1 | (d[:, 2] < 0).astype(int) << 2
+        np.add.at(occ, 8 * px + k, 1)
+    assert np.all(marks_seen[F == 0] == 0) and np.all(marks_seen[F > 0] == 1)
+    # proxy regions: x in [0, 2.5] and [2.5, 5] have equal volume; octants equal area
+    want = F / F.sum()
+    got = occ / occ.sum()
+    nz = F > 0
+    # chains that started where F = 0 walk freely until they reach F > 0 and
+    # never return: a vanishing share of the late states
+    assert got[~nz].sum() < 2e-3
+    assert np.max(np.abs(got[nz] - want[nz]) / want[nz]) < 0.08, (got, want)
+
+
+def test_dynamic_rays_through_texel_centres():
+    """Cornell room, fresh volume, hysteresis 0 (every update replaces the
+    texel): marking one octant of one proxy updates, in each of its probes,
+    exactly that octant's irradiance and depth texels once, and each depth
+    texel holds tau of the ray through its centre (brute-force distance)."""
+    sc = scenes.cornell()
+    ora = oracle.OracleVolume(sc, seed=3, hysteresis=0.0)
+    g = ora.grid
+    pd = oracle.proxy_dims(g)
+    assert pd == (2, 2, 2)
+    mark = np.zeros(8 * 8, np.uint8)
+    q, k = 5, 6  # proxy (1, 0, 1), octant (x>0, y<0, z<0)
+    mark[8 * q + k] = 1
+    nd = oracle.dyn_ray_counts(g, mark, 8, 16)
+    base = np.ascontiguousarray(np.concatenate([[0], np.cumsum(nd)])[:-1], np.int64)
+    cnt = oracle.Counts()
+    oracle.lib().orc_dyn_probes_frame(
+        ora.scene.ptr, oracle.C.byref(g), ora.P, oracle._p(ora.probes), oracle._p(mark), oracle._p(base),
+        oracle.C.byref(ora.tol), 8, 16, 0.0, ora.tau_max, 0, None, None, oracle._p(ora.irr),
+        oracle._p(ora.irr_n), oracle._p(ora.dep), oracle._p(ora.dep_n), oracle.C.byref(cnt))
+    li, ld = oracle.octant_texels(6, k), oracle.octant_texels(14, k)
+    s = float(np.sqrt(np.sum(np.asarray(sc.grid_spacing, np.float64) ** 2)))
+    members = [i for i in range(64) if oracle.lib().orc_proxy_of_probe(oracle.C.byref(g), i) == q]
+    # 4 probes per axis: blocks of 3 and 1, so proxy (1, 0, 1) holds x = 3, y = 0..2, z = 3
+    assert members == [3 + 4 * (y + 4 * 3) for y in range(3)]
+    assert np.all(nd[members] == len(li) + len(ld))
+    assert nd.sum() == 3 * (len(li) + len(ld)) and cnt.rays == nd.sum()
+    for i in range(64):
+        wi = np.zeros(36, np.uint8)
+        wd = np.zeros(196, np.uint8)
+        if i in members:
+            wi[li] = 1
+            wd[ld] = 1
+        assert np.array_equal(ora.irr_n[i], wi) and np.array_equal(ora.dep_n[i], wd)
+    o = np.asarray(sc.grid_origin, np.float64) + 0.25 * np.array([3, 1, 3])  # probe (3,1,3) of proxy 5
+    i = 3 + 4 * (1 + 4 * 3)
+    for t in ld:
+        h = ora.scene.closest_hit(o, oracle.texel_centre_dir(14, int(t)), brute=True)
+        tau = min(h.t / s, ora.tau_max) if h.tri >= 0 else ora.tau_max
+        assert abs(ora.dep[i, 2 * t] - tau) <= 1e-9 * max(tau, 1.0)
+
+
+def test_quantized_static_samples_trace_texel_centres():
+    """With quant set, a static sample's rays go through the centres of the
+    irradiance texel of w and of the depth texel of -w: on a fresh volume with
+    hysteresis 0 each touched depth texel holds tau of its centre ray."""
+    sc = scenes.cornell()
+    ora = oracle.OracleVolume(sc, seed=5, hysteresis=0.0)
+    rng = np.random.default_rng(8)
+    n = np.zeros(64, np.int32)
+    n[21] = 40
+    base = np.zeros(64, np.int64)
+    base[22:] = 40
+    uv = np.ascontiguousarray(rng.uniform(-1, 1, size=(40, 2)))
+    quant = np.ones(64, np.uint8)
+    cnt = oracle.Counts()
+    oracle.lib().orc_chain_probes_frame(
+        ora.scene.ptr, oracle.C.byref(ora.grid), 64, oracle._p(ora.probes), oracle._p(n), oracle._p(base),
+        oracle._p(uv), oracle._p(quant), oracle.C.byref(ora.tol), 8, 16, 0.0, ora.tau_max, 0, None, None,
+        None, None, oracle._p(ora.irr), oracle._p(ora.irr_n), oracle._p(ora.dep), oracle._p(ora.dep_n),
+        oracle.C.byref(cnt))
+    s = float(np.sqrt(np.sum(np.asarray(sc.grid_spacing, np.float64) ** 2)))
+    o = np.asarray(sc.grid_origin, np.float64) + 0.25 * np.array([1, 1, 1])  # probe 21 = (1, 1, 1)
+    touched = np.nonzero(ora.dep_n[21])[0]
+    assert len(touched) > 10 and ora.dep_n[21].sum() == 40
+    for t in touched:
+        h = ora.scene.closest_hit(o, oracle.texel_centre_dir(14, int(t)), brute=True)
+        tau = min(h.t / s, ora.tau_max) if h.tri >= 0 else ora.tau_max
+        assert abs(ora.dep[21, 2 * t] - tau) <= 1e-9 * max(tau, 1.0)
+
+
+def test_chain_update_with_dynamic_chains_runs_end_to_end():
+    """A chain frame with dynamic chains after a light change: detection
+    marks proxies, every probe of a marked proxy gets its octants' texel
+    rays, and the ray count adds up."""
+    sc = scenes.cornell()
+    sc.light_a = np.array([[0.5, 0.95, 0.5]], np.float32)
+    sc.light_b = np.array([[0.2, 0.5, 0.3]], np.float32)
+    sc.frames = 6
+    ora = oracle.OracleVolume(sc, seed=9)
+    cp = oracle.ChainParams(64, 12, 3, 0.5, oracle.SIGMA_DIR)
+    dp = oracle.ChainParams(32, 12, 3, 1.5, 6 * oracle.SIGMA_DIR)
+    st, dst = np.zeros((64, 5)), np.zeros((32, 5))
+    for f in range(4):
+        out = ora.chain_update(f, cp, st, init=(f == 0), dyn=dp, dyn_state=dst, dyn_init=(f == 0))
+        R = int(out["dyn_rays"].sum())
+        assert out["counts"]["rays"] == 2 * 64 * 8 + R
+        assert np.all(out["mark"][out["F"] == 0] == 0)
+        if f == 3:
+            assert out["F"].max() > 0 and out["mark"].sum() > 0 and R > 0
+            assert np.array_equal(out["score"] > 0, out["fd"].reshape(-1, 8).sum(axis=1) > 0)
