@@ -22,7 +22,7 @@
  * With adaptive = 0 every probe traces n_uniform rays and steps 1-2 are
  * skipped (the uniform DDGI-style update). With adaptive = ADGI_MODE_CHAIN
  * the rays are placed by static Metropolis chains instead of steps 2-3
- * (Sec. 3.2, Alg. MarkovChainMT and MetropolisStep, Sec. 4.7): see
+ * (Sec. 3.2-3.3, Alg. MarkovChainMT and MetropolisStep, Sec. 4.8): see
  * adgi_update_params.
  *
  * Conventions
@@ -135,7 +135,7 @@ typedef struct {
   int32_t mu;                 /* weight of radiance change vs visibility change (2) */
   int32_t theta;              /* trigger decays to 0 in theta detection steps (8)  */
   int32_t sync;               /* 1: wait for completion and fill stats             */
-  /* ADGI_MODE_CHAIN (Sec. 3.2, Sec. 4.7). Chain c's state is a point x = (p, uv):
+  /* ADGI_MODE_CHAIN (Sec. 3.2-3.3, Sec. 4.8). Chain c's state is a point x = (p, uv):
    * p in the box spanned by the probe centres, uv the octahedral coordinates
    * of a direction. Its target density is h(x) = exp(min(g/f, 1)) f, with
    * f = Qv/1024 the pilot visibility code of this frame in the octant of uv at
@@ -161,7 +161,32 @@ typedef struct {
   float chain_sigma_dir;      /* > 0, in octahedral uv units (sqrt(pi/256))        */
   int32_t chain_reset;        /* 1: start every chain from its seeded initial point;
                                  chains also start there on their first frame and
-                                 whenever chain_count changes                      */
+                                 whenever chain_count changes (dynamic chains too) */
+  /* Dynamic chains (Sec. 4.9), chain frames only. Probes form virtual proxies
+   * of 3x3x3 (the last group along an axis may be smaller). Every (probe,
+   * octant) has a dynamic component f_d = Qv (Cv + mu Cr) (eq. priorDynamic:
+   * Qv the pilot visibility code and C the 5x5x5 trigger sums of the last
+   * detection, which chain frames run as budgeted frames do); F of a proxy
+   * and octant is the max over its probes. dyn_chain_count chains walk
+   * like the static ones (their own random stream, steps dyn_sigma_pos *
+   * spacing and dyn_sigma_dir) on the target h = F[proxy of the nearest
+   * probe][octant of uv]; every state past the burn-in with h > 0 marks its
+   * (proxy, octant). After the frame's static samples, every probe of a
+   * marked proxy updates each irradiance texel of the octant with a shaded
+   * ray through the texel's centre and each depth texel of the octant with
+   * the distance of a ray through its centre (texel centres belong to an
+   * octant by the signs of their octahedral coordinates and |u| + |v| > 1,
+   * centres on the diagonal to the upper half), with the step floor
+   * 1 - dyn_hysteresis. With dynamic chains on, static samples at probes
+   * with score > 0 trace through the centres of their texels. Capacity:
+   * 2 S + min(P (ri^2 + rd^2), 27 m min(8 Pp, C_d S_d)) <= max_rays_per_frame,
+   * ri, rd the interior sides, m the most texels of one octant in both maps. */
+  int32_t dyn_chain_count;    /* 0 (none) or 1..max_chains                         */
+  int32_t dyn_chain_steps;    /* 2..ADGI_CHAIN_MAX_STEPS                           */
+  int32_t dyn_chain_burn_in;  /* 0..dyn_chain_steps - 2                            */
+  float dyn_sigma_pos;        /* > 0 (1.5: three times the static default)         */
+  float dyn_sigma_dir;        /* > 0 (6 sqrt(pi/256))                              */
+  float dyn_hysteresis;       /* [0, 1) (0.91, Tab. cacheDetails)                   */
 } adgi_update_params;
 
 typedef struct {
@@ -213,6 +238,18 @@ typedef struct {
   int64_t num_samples;        /* out                                               */
   int32_t num_chains;         /* out: chain_count of the last chain frame (0: none) */
   int32_t chain_steps;        /* out: chain_steps of the last chain frame          */
+  /* dynamic chains, after the last chain frame (max_chains > 0); with a chain
+   * frame last, the debug arrays then hold 2 num_samples + num_dyn_rays rays */
+  uint8_t* dyn_mark;          /* [Pp][8] marked (proxy, octant) of the last frame */
+  float* dyn_target;          /* [Pp][8] F as the chains saw it (FP32)            */
+  float* dyn_state;           /* [dyn_chain_count][5]                              */
+  int64_t* dyn_ray_offsets;   /* [P+1] dynamic rays per probe, exclusive scan      */
+  uint8_t* dyn_accept;        /* debug: [dyn_chain_count][dyn_chain_steps]         */
+  int64_t num_dyn_rays;       /* out (0 without dynamic chains)                    */
+  int32_t num_dyn_chains;     /* out: dyn_chain_count of the last chain frame      */
+  int32_t dyn_chain_steps;    /* out                                               */
+  int32_t proxy_dims[3];      /* out: ceil(dims / 3)                               */
+  int32_t reserved;
 } adgi_probe_readback;
 
 /* Create a volume. desc/alloc are host, copied. hip_stream (hipStream_t or

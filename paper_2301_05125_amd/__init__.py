@@ -31,7 +31,7 @@ ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
 ADGI_DEBUG_ARRAYS = 1
 ADGI_MODE_UNIFORM, ADGI_MODE_ADAPTIVE, ADGI_MODE_CHAIN = 0, 1, 2
 CHAIN_MAX_STEPS = 256
-CHAIN_SIGMA_DIR = math.sqrt(math.pi / 256.0)  # default octahedral step of the chains (Sec. 4.7)
+CHAIN_SIGMA_DIR = math.sqrt(math.pi / 256.0)  # default octahedral step of the chains (Sec. 4.8)
 MAX_LIGHTS = 8
 TAU_MAX = (math.exp(5.0) - 1.0) / 15.0
 
@@ -72,7 +72,10 @@ class UpdateParams(C.Structure):
                 ("beta", C.c_float), ("mu", C.c_int32), ("theta", C.c_int32), ("sync", C.c_int32),
                 ("chain_count", C.c_int32), ("chain_steps", C.c_int32), ("chain_burn_in", C.c_int32),
                 ("chain_sigma_pos", C.c_float), ("chain_sigma_dir", C.c_float),
-                ("chain_reset", C.c_int32)]
+                ("chain_reset", C.c_int32), ("dyn_chain_count", C.c_int32),
+                ("dyn_chain_steps", C.c_int32), ("dyn_chain_burn_in", C.c_int32),
+                ("dyn_sigma_pos", C.c_float), ("dyn_sigma_dir", C.c_float),
+                ("dyn_hysteresis", C.c_float)]
 
 
 class UpdateStats(C.Structure):
@@ -96,7 +99,10 @@ class ProbeReadback(C.Structure):
         "q10_vis", "q10_rad", "frame_rotation")] + [("num_rays", C.c_int64)] + \
         [("irr_words", C.c_void_p), ("depth_words", C.c_void_p)] + \
         [(n, C.c_void_p) for n in ("chain_state", "sample_probe", "sample_uv", "chain_accept")] + \
-        [("num_samples", C.c_int64), ("num_chains", C.c_int32), ("chain_steps", C.c_int32)]
+        [("num_samples", C.c_int64), ("num_chains", C.c_int32), ("chain_steps", C.c_int32)] + \
+        [(n, C.c_void_p) for n in ("dyn_mark", "dyn_target", "dyn_state", "dyn_ray_offsets", "dyn_accept")] + \
+        [("num_dyn_rays", C.c_int64), ("num_dyn_chains", C.c_int32), ("dyn_chain_steps", C.c_int32),
+         ("proxy_dims", C.c_int32 * 3), ("reserved", C.c_int32)]
 
 
 class TraceWork(C.Structure):
@@ -330,17 +336,27 @@ class Volume:
         return st.as_dict() if sync else {}
 
     @staticmethod
-    def _chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync):
-        return UpdateParams(int(frame), ADGI_MODE_CHAIN, 0, 1, 1, 1, float(beta), 2, 8,
+    def _chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync, mu=2, theta=8,
+                      dyn_chains=0, dyn_steps=0, dyn_burn_in=0, dyn_sigma_pos=1.5,
+                      dyn_sigma_dir=6 * CHAIN_SIGMA_DIR, dyn_hysteresis=0.91):
+        return UpdateParams(int(frame), ADGI_MODE_CHAIN, 0, 1, 1, 1, float(beta), int(mu), int(theta),
                             1 if sync else 0, int(chains), int(steps), int(burn_in),
-                            float(sigma_pos), float(sigma_dir), 1 if reset else 0)
+                            float(sigma_pos), float(sigma_dir), 1 if reset else 0, int(dyn_chains),
+                            int(dyn_steps), int(dyn_burn_in), float(dyn_sigma_pos), float(dyn_sigma_dir),
+                            float(dyn_hysteresis))
 
     def update_chains(self, frame, chains, steps, burn_in, sigma_pos=0.5, sigma_dir=CHAIN_SIGMA_DIR,
-                      reset=False, beta=5.0, sync=True) -> dict:
-        """One chain frame (ADGI_MODE_CHAIN): pilots, `chains` static
-        Metropolis chains of `steps` steps each (the first burn_in + 1 emit
-        nothing), two rays per sample, blend."""
-        p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync)
+                      reset=False, beta=5.0, sync=True, mu=2, theta=8, dyn_chains=0, dyn_steps=0,
+                      dyn_burn_in=0, dyn_sigma_pos=1.5, dyn_sigma_dir=6 * CHAIN_SIGMA_DIR,
+                      dyn_hysteresis=0.91) -> dict:
+        """One chain frame (ADGI_MODE_CHAIN): pilots and detection, `chains`
+        static Metropolis chains of `steps` steps each (the first burn_in + 1
+        emit nothing), two rays per sample; with dyn_chains > 0 also the
+        dynamic chains on the 3x3x3 proxies and their texel-centre rays;
+        blend."""
+        p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync, mu,
+                               theta, dyn_chains, dyn_steps, dyn_burn_in, dyn_sigma_pos, dyn_sigma_dir,
+                               dyn_hysteresis)
         st = UpdateStats()
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
@@ -382,6 +398,23 @@ class Volume:
             ch["sample_probe"], ch["sample_uv"] = ch["sample_probe"][:S], ch["sample_uv"][:S]
             out.update(ch)
             out["num_samples"] = S
+        if d.max_chains > 0:
+            pdims = tuple(int(x) for x in rb.proxy_dims)
+            Pp = pdims[0] * pdims[1] * pdims[2]
+            Cd, Md = int(rb.num_dyn_chains), int(rb.dyn_chain_steps)
+            dy = {"dyn_mark": np.zeros((Pp, 8), np.uint8), "dyn_target": np.zeros((Pp, 8), np.float32),
+                  "dyn_ray_offsets": np.zeros(P + 1, np.int64)}
+            if Cd:
+                dy["dyn_state"] = np.zeros((Cd, 5), np.float32)
+                if debug:
+                    dy["dyn_accept"] = np.zeros((Cd, Md), np.uint8)
+            rb4 = ProbeReadback()
+            for k, a in dy.items():
+                setattr(rb4, k, _ptr(a))
+            _check(lib().adgi_read_probes(self.h, C.byref(rb4)))
+            out.update(dy)
+            out["proxy_dims"] = pdims
+            out["num_dyn_rays"] = int(rb.num_dyn_rays)
         if debug:
             R = int(rb.num_rays)
             dbg = {"hit_tri": np.zeros(max(R, 1), np.int32),

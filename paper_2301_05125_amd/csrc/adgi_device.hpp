@@ -107,6 +107,13 @@ __device__ __forceinline__ uint32_t oct_bin(float2 uv, int r) {
   return (uint32_t)(iy * r + ix);
 }
 
+// Direction through the centre of interior texel t of an r x r map.
+__device__ __forceinline__ float3 texel_centre_dir(uint32_t t, int r) {
+  const int x = (int)(t % (uint32_t)r), y = (int)(t / (uint32_t)r);
+  const float inv = 1.0f / (float)r;
+  return oct_decode_dir(make_float2((float)(2 * x + 1) * inv - 1.0f, (float)(2 * y + 1) * inv - 1.0f));
+}
+
 // Tile coordinate (X,Y) in 0..r+1 -> source interior coordinate (1..r):
 // border texels repeat the texel across the map's edge identification.
 __device__ __forceinline__ void border_source(int X, int Y, int r, int& sx, int& sy) {

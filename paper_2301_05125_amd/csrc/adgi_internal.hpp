@@ -31,6 +31,14 @@ int chain_lanes_auto(int chains);
 hipError_t launch_blend_order(const VolumeView& v, hipStream_t s);
 hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int chains, int lanes, uint32_t samples,
                          void* sort_temp, size_t sort_temp_bytes, hipStream_t s);
+// chain.hip: F per (proxy, octant) from f_d (needs the box sums in box_a),
+// one frame of the dynamic chains (marks), per-probe dynamic ray counts and
+// their scan into v.dyn_off.
+hipError_t launch_dyn_chains(const VolumeView& v, int chains, int lanes, void* scan_temp, size_t scan_temp_bytes,
+                             hipStream_t s);
+// detect.hip: the three 5-tap passes of the box sum into box_a, whatever the
+// frame (the dynamic chains read them on even frames too)
+hipError_t launch_box_sums(const VolumeView& v, hipStream_t s);
 
 // detect.hip: trigger update and the separable 5x5x5 box sum -> scores
 hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s);

@@ -10,7 +10,10 @@ constexpr uint64_t kTagRotation = 0x524F54ull;  // "ROT"
 constexpr uint64_t kTagPilot = 0x50494Cull;     // "PIL"
 constexpr uint64_t kTagChain = 0x4D4353ull;     // "MCS": one Metropolis step
 constexpr uint64_t kTagChainInit = 0x4D4349ull; // "MCI": a chain's first state
+constexpr uint64_t kTagDynChain = 0x4D4453ull;  // "MDS": one dynamic-chain step
+constexpr uint64_t kTagDynChainInit = 0x4D4449ull; // "MDI": a dynamic chain's first state
 constexpr int kChainMaxSteps = 256;
+constexpr int kDynTexels = 196;                  // interior texels of a map, at most (14 x 14)
 constexpr int kMaxLights = 8;
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
@@ -68,7 +71,22 @@ struct FrameParams {
   int32_t chains, chain_steps, chain_burn_in, chain_init;
   float chain_sp[3];          // position step per axis (sigma_pos * spacing)
   float chain_sd;             // octahedral uv step
-  int32_t pad[2];
+  // dynamic chains on the 3x3x3 proxies (dyn_chains = 0: none)
+  int32_t dyn_chains, dyn_steps, dyn_burn_in, dyn_init;
+  float dyn_sp[3];
+  float dyn_sd;
+  float dyn_one_minus_h;      // 1 - h_dyn: the dynamic updates' step floor
+  int32_t pad[3];
+};
+
+// Texel-centre ray tables (dynamic updates): the interior texels of the
+// irradiance (i) and depth (d) maps in octant order, each octant's start, and
+// each texel's octant and rank within its octant.
+struct DynTables {
+  uint16_t ord_i[kDynTexels], ord_d[kDynTexels];
+  uint16_t rank_i[kDynTexels], rank_d[kDynTexels];
+  uint8_t oct_i[kDynTexels], oct_d[kDynTexels];
+  uint16_t start_i[9], start_d[9];
 };
 
 struct FrameStats {
@@ -130,6 +148,16 @@ struct VolumeView {
   uint32_t* smp_probe;        // sorted
   float2* smp_uv;             // sorted
   float* chain_lum;           // [P][(irr_res-2)/2]^2 g of each coarse cell
+  // dynamic chains: state [C][8], F and marks per (proxy, octant), per-probe
+  // dynamic ray counts and offsets (after the 2S sample rays)
+  float* dyn_state;
+  float* dyn_F;               // [Pp*8]
+  uint8_t* dyn_mark;          // [Pp*8]
+  uint32_t* dyn_n;            // [P]
+  uint32_t* dyn_off;          // [P+1]
+  const DynTables* dyn_tab;
+  uint8_t* dbg_dyn_accept;    // [C][steps] (debug)
+  int32_t pdx, pdy, pdz;      // proxy grid
   uint8_t* dbg_accept;        // [C][steps] (debug)
   const float* pk_dec;        // packed storage: decoded value of every code
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]

@@ -267,7 +267,7 @@ struct WaveTile {
   static constexpr size_t kWaveBytes =
       ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
   static constexpr size_t kTabBytes = (2 * (GI * GI * 3 + GD * GD * 2) + 15) & ~(size_t)15;
-  static constexpr size_t kBlockBytes = 4 * kWaveBytes + kTabBytes + 256 * 4;
+  static constexpr size_t kBlockBytes = 4 * kWaveBytes + kTabBytes + 2 * 256 * 4;  // + two step tables
 };
 
 // One texel update with the moving average of Alg. MovingAvgUpdate; the
@@ -336,7 +336,7 @@ __device__ __forceinline__ float4 chain_record(const VolumeView& v, uint32_t k) 
 
 template <int RI, int RD, bool HALF, bool CHAIN>
 __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
-                                 const uint16_t* tab, const float* alpha) {
+                                 const uint16_t* tab, const float* alpha, const float* alpha_dyn) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
@@ -436,6 +436,39 @@ __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, 
     }
     wave_sync();
   }
+  if (CHAIN && fp.dyn_chains > 0) {
+    // dynamic updates after the static samples (Sec. 4.9): every texel of a
+    // marked octant of the probe's proxy takes its texel-centre ray once,
+    // with the dynamic step floor
+    const int x = i % v.dx, y = (i / v.dx) % v.dy, z = i / (v.dx * v.dy);
+    const uint8_t* mk = v.dyn_mark + 8 * (x / 3 + v.pdx * (y / 3 + v.pdy * (z / 3)));
+    const DynTables& tb = *v.dyn_tab;
+    uint32_t pre[8], acc = 2u * v.offsets[v.P] + v.dyn_off[i];
+#pragma unroll
+    for (int oc = 0; oc < 8; ++oc) {
+      pre[oc] = acc;
+      if (mk[oc]) acc += (uint32_t)(tb.start_i[oc + 1] - tb.start_i[oc]) + (uint32_t)(tb.start_d[oc + 1] - tb.start_d[oc]);
+    }
+#pragma unroll
+    for (int s = 0; s < SI; ++s) {
+      const int k = lane + 64 * s;
+      if (k < NI) {
+        const int oc = tb.oct_i[k];
+        if (mk[oc]) blend_rgb(vi[s], ni[s], v.rec[pre[oc] + tb.rank_i[k]], alpha_dyn);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SD; ++s) {
+      const int k = lane + 64 * s;
+      if (k < ND) {
+        const int oc = tb.oct_d[k];
+        if (mk[oc]) {
+          const uint32_t ni_oc = (uint32_t)(tb.start_i[oc + 1] - tb.start_i[oc]);
+          blend_tau(vd[s], nd[s], v.rec[pre[oc] + ni_oc + tb.rank_d[k]].w, inv_s, tmax, alpha_dyn);
+        }
+      }
+    }
+  }
   float* stI = (float*)wbase;
   float* stD = stI + 3 * NI;
   uint8_t* stN = (uint8_t*)(stD + 2 * ND);
@@ -471,15 +504,18 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
   float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
+  float* alpha_dyn = alpha + 256;
   build_fold_tables<RI, RD>(tab);
-  // step weight of Alg. MovingAvgUpdate by sample count N
-  for (int k = threadIdx.x; k < 256; k += blockDim.x)
+  // step weight of Alg. MovingAvgUpdate by sample count N (static and dynamic)
+  for (int k = threadIdx.x; k < 256; k += blockDim.x) {
     alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
+    if (CHAIN) alpha_dyn[k] = fmaxf(1.0f / (float)(k + 1), v.fp->dyn_one_minus_h);
+  }
   __syncthreads();
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
   for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
-    blend_probe_wave<RI, RD, HALF, CHAIN>(v, io, v.order[q], wbase, tab, alpha);
+    blend_probe_wave<RI, RD, HALF, CHAIN>(v, io, v.order[q], wbase, tab, alpha, alpha_dyn);
 }
 
 // ---------------------------------------------------------------------------

@@ -58,9 +58,9 @@ __global__ void trigger_kernel(VolumeView v) {
 // the kernel is straight-line code: the coordinate along the axis is
 // (i / div) % D and neighbours are 8 * div elements apart.
 __global__ void box_pass_kernel(VolumeView v, const int2* __restrict__ src, int2* __restrict__ dst,
-                                int div, int D) {
+                                int div, int D, int force) {
   const FrameParams& fp = *v.fp;
-  if (!fp.adaptive || (fp.frame & 1) == 0) return;
+  if (!force && (!fp.adaptive || (fp.frame & 1) == 0)) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 8 * v.P) return;
   const int i = e >> 3;
@@ -99,15 +99,25 @@ hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_box_sums(const VolumeView& v, hipStream_t s) {
+  const int n = 8 * v.P, g = (n + 255) / 256;
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.trig, v.box_a, 1, v.dx, 1);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_a, v.box_b, v.dx,
+                     v.dy, 1);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_b, v.box_a,
+                     v.dx * v.dy, v.dz, 1);
+  return hipGetLastError();
+}
+
 hipError_t launch_detect(const VolumeView& v, hipStream_t s) {
   const int n = 8 * v.P, g = (n + 255) / 256;
   hipLaunchKernelGGL(trigger_kernel, dim3(g), dim3(256), 0, s, v);
   // box sum: trig -> a (x) -> b (y) -> a (z); the score reads a
-  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.trig, v.box_a, 1, v.dx);
+  hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.trig, v.box_a, 1, v.dx, 0);
   hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_a, v.box_b, v.dx,
-                     v.dy);
+                     v.dy, 0);
   hipLaunchKernelGGL(box_pass_kernel, dim3(g), dim3(256), 0, s, v, (const int2*)v.box_b, v.box_a,
-                     v.dx * v.dy, v.dz);
+                     v.dx * v.dy, v.dz, 0);
   VolumeView w = v;
   w.box_b = v.box_a;  // score reads the z-pass output
   hipLaunchKernelGGL(score_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, w);

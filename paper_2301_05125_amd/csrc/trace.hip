@@ -6,7 +6,13 @@
 //     record (radiance RGB, hit distance) per ray.
 //   KIND_CHAIN:   rays 2k and 2k+1 belong to chain sample k (probes' samples
 //     grouped by probe): along d(uv_k) from the sample's probe, shaded, and
-//     along -d, distance only (the visibility ray of Sec. 4.7);
+//     along -d, distance only (the visibility ray of Sec. 4.8); with dynamic
+//     chains, a probe with a dynamic component (score > 0) traces them
+//     through the centres of the irradiance texel of d and the depth texel
+//     of -d, and rays 2S + dyn_off[i] + j are probe i's dynamic rays: for
+//     each marked octant of its proxy, ascending, a shaded ray through the
+//     centre of each irradiance texel of the octant, then a distance-only
+//     ray through the centre of each depth texel of the octant (Sec. 4.9);
 //   KIND_PILOT:   ray r = 8i + k is the pilot of octant k (Sec. 4.1, 4.4);
 //     output the 10-bit codes of f_v = exp(-2t/s) (eq. ProbeVis) and
 //     f_r = min(lum, beta)/beta (Sec. 4.1.3).
@@ -364,6 +370,7 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
 
   // ---- ray generation
   float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
+  bool shade = true;  // chain frames: false for distance-only rays
   if (active) {
     if (KIND == KIND_PRIMARY) {
       int i = probe_of_ray(v.offsets, v.P, r);
@@ -371,10 +378,43 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
       o = probe_position(v, i);
       d = sf_direction(r - b, n, fp.R);
     } else if (KIND == KIND_CHAIN) {
-      const uint32_t k = r >> 1;
-      o = probe_position(v, (int)v.smp_probe[k]);
-      d = oct_decode_dir(v.smp_uv[k]);
-      if (r & 1u) d = make_float3(-d.x, -d.y, -d.z);
+      const uint32_t S2 = 2u * v.offsets[v.P];
+      if (r < S2) {
+        const uint32_t k = r >> 1;
+        const int i = (int)v.smp_probe[k];
+        o = probe_position(v, i);
+        d = oct_decode_dir(v.smp_uv[k]);
+        if (r & 1u) d = make_float3(-d.x, -d.y, -d.z);
+        if (fp.dyn_chains > 0 && v.score[i] > 0) {  // through the texel centre
+          const int R = (r & 1u) ? v.dep_res - 2 : v.irr_res - 2;
+          d = texel_centre_dir(oct_bin(oct_encode(d), R), R);
+        }
+        shade = !(r & 1u);
+      } else {
+        const uint32_t rr = r - S2;
+        const int i = probe_of_ray(v.dyn_off, v.P, rr);
+        uint32_t j = rr - v.dyn_off[i];
+        o = probe_position(v, i);
+        const int x = i % v.dx, y = (i / v.dx) % v.dy, z = i / (v.dx * v.dy);
+        const uint8_t* mk = v.dyn_mark + 8 * (x / 3 + v.pdx * (y / 3 + v.pdy * (z / 3)));
+        const DynTables& tb = *v.dyn_tab;
+        for (int oc = 0; oc < 8; ++oc) {
+          if (!mk[oc]) continue;
+          const uint32_t ni = tb.start_i[oc + 1] - tb.start_i[oc], nd = tb.start_d[oc + 1] - tb.start_d[oc];
+          if (j < ni) {
+            d = texel_centre_dir(tb.ord_i[tb.start_i[oc] + j], v.irr_res - 2);
+            shade = true;
+            break;
+          }
+          j -= ni;
+          if (j < nd) {
+            d = texel_centre_dir(tb.ord_d[tb.start_d[oc] + j], v.dep_res - 2);
+            shade = false;
+            break;
+          }
+          j -= nd;
+        }
+      }
     } else {
       uint32_t i = r >> 3, k = r & 7;
       o = probe_position(v, (int)i);
@@ -398,7 +438,7 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
   }
 
   // ---- direct light at front-face hits, shadow rays compacted per wave
-  const bool lit_hit = active && slot >= 0 && front && !(KIND == KIND_CHAIN && (r & 1u));
+  const bool lit_hit = active && slot >= 0 && front && (KIND != KIND_CHAIN || shade);
   float3 x = make_float3(0.f, 0.f, 0.f), nrm = make_float3(0.f, 0.f, 0.f);
   if (lit_hit) {
     const float4* tp = v.tris + 3 * (size_t)slot;
@@ -515,7 +555,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_kernel(VolumeVi
   uint16_t* queue = queues + wave * 64 * kMaxLights;
   uint32_t* vis = vis_all + wave * 64;
   const uint32_t total = KIND == KIND_PRIMARY ? v.offsets[v.P]
-                         : KIND == KIND_CHAIN ? 2u * v.offsets[v.P] : 8u * (uint32_t)v.P;
+                         : KIND == KIND_CHAIN ? 2u * v.offsets[v.P] + (v.fp->dyn_chains > 0 ? v.dyn_off[v.P] : 0u)
+                                              : 8u * (uint32_t)v.P;
   if (persistent) {
     uint32_t* counter = KIND == KIND_PILOT ? &v.stats->pilot_counter : &v.stats->ray_counter;
     for (;;) {

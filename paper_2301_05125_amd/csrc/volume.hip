@@ -169,6 +169,10 @@ struct adgi_volume {
   size_t sort_temp_bytes = 0;
   int32_t chain_count = 0, chain_steps = 0;  // of the last chain frame (0: chains not started)
   int64_t num_samples = 0;
+  int32_t dyn_count = 0, dyn_steps = 0;      // dynamic chains of the last chain frame
+  bool dyn_last = false;                     // the last (or current) chain frame runs dynamic chains
+  int32_t frame_now = 0;                     // frame being enqueued
+  int32_t Pp = 0;                            // proxies
 };
 
 namespace {
@@ -237,11 +241,23 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
     int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
     if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
       return e;
+    // detection keeps triggers and scores current (odd frames); the dynamic
+    // chains read the box sums on every frame
+    if (vol->frame_now & 1) {
+      if ((e = launch_detect(v, s)) != hipSuccess) return e;
+    } else if (vol->dyn_last) {
+      if ((e = launch_box_sums(v, s)) != hipSuccess) return e;
+    }
     if ((e = mark(2)) != hipSuccess) return e;
     const int lanes = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->chain_count);
     if ((e = launch_chains(v, vol->desc.storage == ADGI_FP16, vol->irr, vol->chain_count, lanes,
                            (uint32_t)vol->num_samples, vol->d_sort_temp, vol->sort_temp_bytes, s)) != hipSuccess)
       return e;
+    if (vol->dyn_last) {
+      const int dl = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->dyn_count);
+      if ((e = launch_dyn_chains(v, vol->dyn_count, dl, vol->d_sort_temp, vol->sort_temp_bytes, s)) != hipSuccess)
+        return e;
+    }
     if ((e = mark(3)) != hipSuccess) return e;
     if ((e = launch_blend_order(v, s)) != hipSuccess) return e;
   } else if (chain) {
@@ -362,6 +378,45 @@ adgi_tuning default_tuning() {
   return t;
 }
 
+// Texel-centre ray tables of r_i x r_i irradiance and r_d x r_d depth
+// interiors: a texel (x, y) belongs to the octant of its centre uv =
+// ((2x+1)/r - 1, (2y+1)/r - 1), decided in integers: u < 0, v < 0 and
+// |u| + |v| > 1 (centres on the diagonal give z = 0: upper half).
+DynTables dyn_tables(int ri, int rd) {
+  DynTables tb;
+  std::memset(&tb, 0, sizeof(tb));
+  auto build = [](int r, uint16_t* ord, uint16_t* rank, uint8_t* oct, uint16_t* start) {
+    int n = 0;
+    for (int oc = 0; oc < 8; ++oc) {
+      start[oc] = (uint16_t)n;
+      int k = 0;
+      for (int t = 0; t < r * r; ++t) {
+        const int cx = 2 * (t % r) + 1 - r, cy = 2 * (t / r) + 1 - r;
+        const int o = (cx < 0 ? 1 : 0) | (cy < 0 ? 2 : 0) | (std::abs(cx) + std::abs(cy) > r ? 4 : 0);
+        if (o != oc) continue;
+        ord[n++] = (uint16_t)t;
+        rank[t] = (uint16_t)k++;
+        oct[t] = (uint8_t)oc;
+      }
+    }
+    start[8] = (uint16_t)n;
+  };
+  build(ri, tb.ord_i, tb.rank_i, tb.oct_i, tb.start_i);
+  build(rd, tb.ord_d, tb.rank_d, tb.oct_d, tb.start_d);
+  return tb;
+}
+
+// Most dynamic rays one chain frame can trace (the capacity bound of
+// adgi_update_params).
+int64_t dyn_ray_bound(const adgi_volume_desc& d, int64_t P, int64_t Pp, int64_t chains, int64_t samples) {
+  const DynTables tb = dyn_tables(d.irr_res - 2, d.depth_res - 2);
+  int64_t m = 0;
+  for (int oc = 0; oc < 8; ++oc)
+    m = std::max<int64_t>(m, (tb.start_i[oc + 1] - tb.start_i[oc]) + (tb.start_d[oc + 1] - tb.start_d[oc]));
+  const int64_t ri = d.irr_res - 2, rd = d.depth_res - 2;
+  return std::min(P * (ri * ri + rd * rd), 27 * m * std::min(8 * Pp, chains * samples));
+}
+
 bool tuning_valid(const adgi_tuning& t) {
   return (t.use_graph == 0 || t.use_graph == 1) && (t.persistent == 0 || t.persistent == 1) &&
          t.trace_block >= 64 && t.trace_block <= 1024 && t.trace_block % 64 == 0 &&
@@ -387,7 +442,10 @@ std::vector<Part> state_parts(adgi_volume* vol) {
           {vol->dep_n, P * rd * rd},         {vol->v.qv[0], P * 16},           {vol->v.qv[1], P * 16},
           {vol->v.qr[0], P * 16},            {vol->v.qr[1], P * 16},           {vol->v.trig, P * 64},
           {vol->v.score, P * 8},             {vol->v.n, P * 4},                {vol->v.offsets, (P + 1) * 4}};
-  if (vol->desc.max_chains > 0) parts.push_back({vol->v.chain_state, (size_t)vol->desc.max_chains * 32});
+  if (vol->desc.max_chains > 0) {
+    parts.push_back({vol->v.chain_state, (size_t)vol->desc.max_chains * 32});
+    parts.push_back({vol->v.dyn_state, (size_t)vol->desc.max_chains * 32});
+  }
   return parts;
 }
 constexpr uint64_t kSnapMagic = 0x5041534E49474441ull;  // "ADGINSAP"
@@ -397,6 +455,7 @@ struct SnapHeader {
   int32_t last_frame, last_adaptive;
   float last_R[9];
   int32_t max_chains, chain_count, chain_steps;
+  int32_t dyn_count, dyn_steps, pad2;
 };
 
 }  // namespace
@@ -516,6 +575,14 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
     reqs.push_back({(void**)&v.smp_uv, Smax * 8});
     const size_t m = (size_t)(d->irr_res - 2) / 2;
     reqs.push_back({(void**)&v.chain_lum, (size_t)P * m * m * 4});
+    const size_t Pp = (size_t)((d->dims[0] + 2) / 3) * ((d->dims[1] + 2) / 3) * ((d->dims[2] + 2) / 3);
+    reqs.push_back({(void**)&v.dyn_state, C * 32});
+    reqs.push_back({(void**)&v.dyn_F, Pp * 32});
+    reqs.push_back({(void**)&v.dyn_mark, Pp * 8});
+    reqs.push_back({(void**)&v.dyn_n, (size_t)P * 4});
+    reqs.push_back({(void**)&v.dyn_off, (size_t)(P + 1) * 4});
+    reqs.push_back({(void**)&v.dyn_tab, sizeof(DynTables)});
+    if (dbg) reqs.push_back({(void**)&v.dbg_dyn_accept, C * kChainMaxSteps});
     reqs.push_back({&vol->d_sort_temp, std::max<size_t>(vol->sort_temp_bytes, 4)});
     if (dbg) reqs.push_back({(void**)&v.dbg_accept, C * kChainMaxSteps});
   }
@@ -535,6 +602,11 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   // zero the temporal state
   for (auto& r : reqs) CREATE_TRY(hipMemsetAsync(*r.p, 0, r.bytes, vol->stream));
   if (d->storage == ADGI_PACKED) CREATE_TRY(launch_packed_decode_table((float*)v.pk_dec, vol->stream));
+  // the tables go after the zero fill on the volume's (non-blocking) stream;
+  // tb lives until the synchronisation below
+  const DynTables tb = dyn_tables(d->irr_res - 2, d->depth_res - 2);
+  if (d->max_chains > 0)
+    CREATE_TRY(hipMemcpyAsync((void*)v.dyn_tab, &tb, sizeof(tb), hipMemcpyHostToDevice, vol->stream));
   CREATE_TRY(hipStreamSynchronize(vol->stream));
 #undef CREATE_TRY
   v.ox = d->origin[0];
@@ -546,6 +618,10 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.dx = d->dims[0];
   v.dy = d->dims[1];
   v.dz = d->dims[2];
+  v.pdx = (d->dims[0] + 2) / 3;
+  v.pdy = (d->dims[1] + 2) / 3;
+  v.pdz = (d->dims[2] + 2) / 3;
+  vol->Pp = v.pdx * v.pdy * v.pdz;
   v.P = (int32_t)P;
   {
     double s2 = 0.0;
@@ -791,8 +867,27 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
     if (p->chain_reset != 0 && p->chain_reset != 1) return fail(ADGI_ERR_INVALID_ARG, "chain_reset must be 0 or 1");
     if (!(p->beta > 0.f) || !std::isfinite(p->beta)) return fail(ADGI_ERR_INVALID_ARG, "beta must be > 0");
     samples = (int64_t)p->chain_count * (p->chain_steps - p->chain_burn_in - 1);
-    if (2 * samples > cap)
-      return fail(ADGI_ERR_BUDGET, "2 * chain samples (%lld) exceed max_rays_per_frame", (long long)(2 * samples));
+    if (p->mu < 0 || p->mu > 1024) return fail(ADGI_ERR_INVALID_ARG, "mu must be in [0, 1024]");
+    if (p->theta < 1) return fail(ADGI_ERR_INVALID_ARG, "theta must be >= 1");
+    int64_t dyn_rays = 0;
+    if (p->dyn_chain_count != 0) {
+      if (p->dyn_chain_count < 0 || p->dyn_chain_count > vol->desc.max_chains)
+        return fail(ADGI_ERR_INVALID_ARG, "dyn_chain_count must be in [0, %d]", vol->desc.max_chains);
+      if (p->dyn_chain_steps < 2 || p->dyn_chain_steps > ADGI_CHAIN_MAX_STEPS)
+        return fail(ADGI_ERR_INVALID_ARG, "dyn_chain_steps must be in [2, %d]", ADGI_CHAIN_MAX_STEPS);
+      if (p->dyn_chain_burn_in < 0 || p->dyn_chain_burn_in > p->dyn_chain_steps - 2)
+        return fail(ADGI_ERR_INVALID_ARG, "dyn_chain_burn_in must be in [0, dyn_chain_steps - 2]");
+      if (!(p->dyn_sigma_pos > 0.f) || !std::isfinite(p->dyn_sigma_pos) || !(p->dyn_sigma_dir > 0.f) ||
+          !std::isfinite(p->dyn_sigma_dir))
+        return fail(ADGI_ERR_INVALID_ARG, "dynamic chain sigmas must be finite and > 0");
+      if (!(p->dyn_hysteresis >= 0.f && p->dyn_hysteresis < 1.f))
+        return fail(ADGI_ERR_INVALID_ARG, "dyn_hysteresis must be in [0, 1)");
+      dyn_rays = dyn_ray_bound(vol->desc, P, vol->Pp, p->dyn_chain_count,
+                               p->dyn_chain_steps - p->dyn_chain_burn_in - 1);
+    }
+    if (2 * samples + dyn_rays > cap)
+      return fail(ADGI_ERR_BUDGET, "2 * chain samples (%lld) + dynamic rays (up to %lld) exceed max_rays_per_frame",
+                  (long long)(2 * samples), (long long)dyn_rays);
     if (chain_sort_needed_bytes((uint32_t)samples, vol->P) > vol->sort_temp_bytes)
       return fail(ADGI_ERR_INVALID_ARG, "sort workspace too small for %lld samples", (long long)samples);
   } else if (mode == ADGI_MODE_ADAPTIVE) {
@@ -841,7 +936,21 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
     vol->chain_count = p->chain_count;
     vol->chain_steps = p->chain_steps;
     vol->num_samples = samples;
+    fp.dyn_chains = p->dyn_chain_count;
+    if (p->dyn_chain_count > 0) {
+      fp.dyn_steps = p->dyn_chain_steps;
+      fp.dyn_burn_in = p->dyn_chain_burn_in;
+      fp.dyn_init = (p->chain_reset || vol->dyn_count != p->dyn_chain_count) ? 1 : 0;
+      for (int a = 0; a < 3; ++a)
+        fp.dyn_sp[a] = vol->desc.dims[a] > 1 ? p->dyn_sigma_pos * vol->desc.spacing[a] : 0.0f;
+      fp.dyn_sd = p->dyn_sigma_dir;
+      fp.dyn_one_minus_h = (float)(1.0 - (double)p->dyn_hysteresis);
+      vol->dyn_count = p->dyn_chain_count;
+      vol->dyn_steps = p->dyn_chain_steps;
+    }
+    vol->dyn_last = p->dyn_chain_count > 0;
   }
+  vol->frame_now = p->frame;
   HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.fp, &fp, sizeof(FrameParams), hipMemcpyHostToDevice, vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
@@ -881,7 +990,10 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       uint32_t total = 0;
       HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
       std::memset(stats, 0, sizeof(*stats));
-      stats->primary_rays = mode == ADGI_MODE_CHAIN ? 2 * (int64_t)total : (int64_t)total;
+      uint32_t dyn = 0;
+      if (mode == ADGI_MODE_CHAIN && vol->dyn_last)
+        HIP_TRY(vol, hipMemcpy(&dyn, vol->v.dyn_off + vol->P, 4, hipMemcpyDeviceToHost));
+      stats->primary_rays = mode == ADGI_MODE_CHAIN ? 2 * (int64_t)total + dyn : (int64_t)total;
       stats->pilot_rays = mode != ADGI_MODE_UNIFORM ? 8 * P : 0;
       stats->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
       stats->budget_used = (int64_t)vol->h_stats->budget_used;
@@ -958,7 +1070,12 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
   HIP_TRY(vol, hipMemcpy(off.data(), vol->v.offsets, (P + 1) * 4, hipMemcpyDeviceToHost));
   if (out->ray_offsets)
     for (size_t i = 0; i <= P; ++i) out->ray_offsets[i] = off[i];
-  const size_t R = vol->last_frame < 0 ? 0 : vol->last_adaptive == ADGI_MODE_CHAIN ? 2 * (size_t)off[P] : off[P];
+  uint32_t dyn_total = 0;
+  if (vol->last_frame >= 0 && vol->last_adaptive == ADGI_MODE_CHAIN && vol->dyn_last)
+    HIP_TRY(vol, hipMemcpy(&dyn_total, vol->v.dyn_off + P, 4, hipMemcpyDeviceToHost));
+  const size_t R = vol->last_frame < 0                            ? 0
+                   : vol->last_adaptive == ADGI_MODE_CHAIN ? 2 * (size_t)off[P] + dyn_total
+                                                           : off[P];
   out->num_rays = (int64_t)R;
   if (R) {
     if (out->hit_tri) HIP_TRY(vol, hipMemcpy(out->hit_tri, vol->v.dbg_tri, R * 4, hipMemcpyDeviceToHost));
@@ -989,6 +1106,32 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
     if (out->sample_uv && S) HIP_TRY(vol, hipMemcpy(out->sample_uv, vol->v.smp_uv, S * 8, hipMemcpyDeviceToHost));
     if (out->chain_accept && C)
       HIP_TRY(vol, hipMemcpy(out->chain_accept, vol->v.dbg_accept, C * vol->chain_steps, hipMemcpyDeviceToHost));
+  }
+  out->num_dyn_chains = vol->dyn_last ? vol->dyn_count : 0;
+  out->dyn_chain_steps = vol->dyn_last ? vol->dyn_steps : 0;
+  out->num_dyn_rays = dyn_total;
+  out->proxy_dims[0] = vol->v.pdx;
+  out->proxy_dims[1] = vol->v.pdy;
+  out->proxy_dims[2] = vol->v.pdz;
+  if (out->dyn_mark || out->dyn_target || out->dyn_state || out->dyn_ray_offsets || out->dyn_accept) {
+    if (vol->desc.max_chains < 1) return fail(ADGI_ERR_INVALID_ARG, "dynamic-chain arrays need max_chains > 0");
+    if (out->dyn_accept && !dbg) return fail(ADGI_ERR_INVALID_ARG, "dyn_accept needs ADGI_DEBUG_ARRAYS");
+    const size_t Pp = (size_t)vol->Pp, Cd = (size_t)out->num_dyn_chains;
+    if (out->dyn_mark) HIP_TRY(vol, hipMemcpy(out->dyn_mark, vol->v.dyn_mark, Pp * 8, hipMemcpyDeviceToHost));
+    if (out->dyn_target) HIP_TRY(vol, hipMemcpy(out->dyn_target, vol->v.dyn_F, Pp * 32, hipMemcpyDeviceToHost));
+    if (out->dyn_state && Cd) {
+      std::vector<float> st(Cd * 8);
+      HIP_TRY(vol, hipMemcpy(st.data(), vol->v.dyn_state, Cd * 32, hipMemcpyDeviceToHost));
+      for (size_t c = 0; c < Cd; ++c)
+        for (int a = 0; a < 5; ++a) out->dyn_state[5 * c + a] = st[8 * c + a];
+    }
+    if (out->dyn_ray_offsets) {
+      std::vector<uint32_t> o(P + 1);
+      HIP_TRY(vol, hipMemcpy(o.data(), vol->v.dyn_off, (P + 1) * 4, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i <= P; ++i) out->dyn_ray_offsets[i] = vol->dyn_last ? o[i] : 0;
+    }
+    if (out->dyn_accept && Cd)
+      HIP_TRY(vol, hipMemcpy(out->dyn_accept, vol->v.dbg_dyn_accept, Cd * vol->dyn_steps, hipMemcpyDeviceToHost));
   }
   return ADGI_OK;
 }
@@ -1044,6 +1187,8 @@ adgi_status adgi_save_state(adgi_volume* vol, void* dst, size_t bytes) {
   h.max_chains = vol->desc.max_chains;
   h.chain_count = vol->chain_count;
   h.chain_steps = vol->chain_steps;
+  h.dyn_count = vol->dyn_count;
+  h.dyn_steps = vol->dyn_steps;
   uint8_t* o = (uint8_t*)dst;
   std::memcpy(o, &h, sizeof(h));
   o += sizeof(h);
@@ -1074,6 +1219,8 @@ adgi_status adgi_restore_state(adgi_volume* vol, const void* src, size_t bytes) 
   std::memcpy(vol->last_R, h.last_R, sizeof(h.last_R));
   vol->chain_count = h.chain_count;
   vol->chain_steps = h.chain_steps;
+  vol->dyn_count = h.dyn_count;
+  vol->dyn_steps = h.dyn_steps;
   return ADGI_OK;
 }
 
@@ -1101,7 +1248,10 @@ adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* 
   HIP_TRY(vol, hipMemcpy(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost));
   uint32_t total = 0;
   HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
-  out->primary_rays = p->adaptive == ADGI_MODE_CHAIN ? 2 * (int64_t)total : (int64_t)total;
+  uint32_t dyn = 0;
+  if (p->adaptive == ADGI_MODE_CHAIN && vol->dyn_last)
+    HIP_TRY(vol, hipMemcpy(&dyn, vol->v.dyn_off + vol->P, 4, hipMemcpyDeviceToHost));
+  out->primary_rays = p->adaptive == ADGI_MODE_CHAIN ? 2 * (int64_t)total + dyn : (int64_t)total;
   out->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
   out->node_tests = (int64_t)vol->h_stats->node_tests;
   out->box_tests = out->node_tests * (use_bvh4(vol, vol->tun) ? 4 : 2);

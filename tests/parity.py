@@ -207,19 +207,25 @@ def scene_res(vol):
 
 def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int,
                        sigma_pos: float = 0.5, warm_uniform: int = 2, n_uniform: int = 64,
-                       storage=adgi.ADGI_FP32, seed: int = 0x5EED, tuning=None) -> dict:
+                       storage=adgi.ADGI_FP32, seed: int = 0x5EED, tuning=None, dyn_chains: int = 0,
+                       dyn_steps: int = 16, dyn_burn_in: int = 3, dyn_hysteresis: float = 0.91,
+                       max_rays=None) -> dict:
     """Chain frames (ADGI_MODE_CHAIN) in lockstep with the oracle's static
     Metropolis sampler, after ``warm_uniform`` uniform frames that give the
     guide a previous irradiance. Every probe is tracked (the guide reads any
     probe's texels). Each frame the oracle starts from the chain state the GPU
     left (FP32 values, so FP32/FP64 step rounding does not accumulate across
     frames), adopts the GPU's accept decisions only where it flags a tie, and
-    must then produce the same samples: probes exactly, uv within 1e-4."""
+    must then produce the same samples: probes exactly, uv within 1e-4.
+    With dyn_chains, the dynamic chains run too: the same for their state,
+    accept decisions and marks, F exactly (FP32 of the same integers), and
+    the per-probe dynamic ray counts exactly."""
     P = scene.num_probes
     samples = chains * (steps - burn_in - 1)
-    max_rays = max(2 * samples, P * n_uniform)
+    if max_rays is None:
+        max_rays = max(2 * samples + (P * 232 if dyn_chains else 0), P * n_uniform)
     vol = adgi.volume_for_scene(scene, storage=storage, max_rays=max_rays, seed=seed, debug=True,
-                                max_chains=chains)
+                                max_chains=max(chains, dyn_chains))
     if tuning:
         vol.set_tuning(**tuning)
     fp16 = storage == adgi.ADGI_FP16
@@ -227,7 +233,13 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
     cp = oracle.ChainParams(chains, steps, burn_in, float(np.float32(sigma_pos)),
                             float(np.float32(adgi.CHAIN_SIGMA_DIR)))
     state = np.zeros((chains, 5), np.float64)
-    res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "count_mismatch": 0,
+    dp = None
+    if dyn_chains:
+        dp = oracle.ChainParams(dyn_chains, dyn_steps, dyn_burn_in, float(np.float32(1.5)),
+                                float(np.float32(6 * adgi.CHAIN_SIGMA_DIR)))
+    dstate = np.zeros((max(dyn_chains, 1), 5), np.float64)
+    res = {"mark_mismatch": 0, "F_mismatch": 0, "dyn_ray_mismatch": 0, "dyn_accept_mismatch": 0,
+           "marks": 0, "dyn_rays": 0, "max_dyn_state_err": 0.0,"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "count_mismatch": 0,
            "alloc_mismatch": 0, "code_mismatch": 0, "accept_mismatch": 0, "probe_mismatch": 0,
            "sample_count_mismatch": 0, "max_uv_err": 0.0, "max_state_err": 0.0, "ties": {},
            "frames": frames, "samples": 0, "accept_rate": 0.0, "max_rel_ray": 0.0}
@@ -236,7 +248,9 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
             gpu_scene_update(vol, scene, f)
         chain = f >= warm_uniform
         if chain:
-            st = vol.update_chains(f, chains, steps, burn_in, sigma_pos=sigma_pos, sync=True)
+            st = vol.update_chains(f, chains, steps, burn_in, sigma_pos=sigma_pos, sync=True,
+                                   dyn_chains=dyn_chains, dyn_steps=dyn_steps, dyn_burn_in=dyn_burn_in,
+                                   dyn_hysteresis=dyn_hysteresis)
         else:
             st = vol.update_probes(f, adaptive=False, n_uniform=n_uniform, sync=True)
         rb = vol.read_probes(texels=True, debug=True)
@@ -245,14 +259,30 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
                  "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
         if chain:
             hints["accept"] = rb["chain_accept"].reshape(-1)
-            out = ora.chain_update(f, cp, state, init=(f == warm_uniform), hints=hints)
+            if dyn_chains:
+                hints["dyn_accept"] = rb["dyn_accept"].reshape(-1)
+            out = ora.chain_update(f, cp, state, init=(f == warm_uniform), hints=hints, dyn=dp,
+                                   dyn_state=dstate[:dyn_chains] if dyn_chains else None,
+                                   dyn_init=(f == warm_uniform), h_dyn=dyn_hysteresis)
+            if dyn_chains:
+                res["F_mismatch"] += int(np.count_nonzero(
+                    out["F"].astype(np.float32) != rb["dyn_target"].reshape(-1)))
+                res["mark_mismatch"] += int(np.count_nonzero(out["mark"] != rb["dyn_mark"].reshape(-1)))
+                res["marks"] += int(out["mark"].sum())
+                res["dyn_accept_mismatch"] += int(np.count_nonzero(out["dyn_accept"] != hints["dyn_accept"]))
+                res["dyn_ray_mismatch"] += int(np.count_nonzero(out["dyn_offsets"] != rb["dyn_ray_offsets"]))
+                res["dyn_rays"] += int(out["dyn_offsets"][-1])
+                res["max_dyn_state_err"] = max(res["max_dyn_state_err"], float(np.abs(
+                    rb["dyn_state"].astype(np.float64) - dstate[:dyn_chains]).max(initial=0.0)))
+                dstate[:dyn_chains] = rb["dyn_state"].astype(np.float64)
             res["code_mismatch"] += int(np.count_nonzero(out["qv"] != rb["q10_vis"])) + \
                 int(np.count_nonzero(out["qr"] != rb["q10_rad"]))
             res["accept_mismatch"] += int(np.count_nonzero(out["accept"] != hints["accept"]))
             res["accept_rate"] = float(np.mean(out["accept"]))
             sp_o = out["sample_probe"][out["perm"]]
             suv_o = out["sample_uv"][out["perm"]]
-            if rb["num_samples"] != len(sp_o) or st["primary_rays"] != 2 * len(sp_o):
+            if rb["num_samples"] != len(sp_o) or \
+                    st["primary_rays"] != 2 * len(sp_o) + (int(out["dyn_offsets"][-1]) if dyn_chains else 0):
                 res["sample_count_mismatch"] += 1
             else:
                 res["probe_mismatch"] += int(np.count_nonzero(rb["sample_probe"] != sp_o))

@@ -205,3 +205,41 @@ def test_chains_box_field_ragged_lockstep():
     texels = res["vs_oracle"]["irradiance"]["texels"] + res["vs_oracle"]["depth"]["texels"]
     assert res.get("f16_quantum_ties", 0) <= 2e-3 * texels * (res["frames"] + 2), res
     _assert_chain_parity(res, tol=2e-3)
+
+
+def _assert_dyn_parity(res, tol=1e-4):
+    _assert_chain_parity(res, tol)
+    assert res["F_mismatch"] == 0 and res["mark_mismatch"] == 0, res
+    assert res["dyn_accept_mismatch"] == 0 and res["dyn_ray_mismatch"] == 0, res
+    assert res["max_dyn_state_err"] <= 1e-4, res
+
+
+def test_dynamic_chains_cornell_lockstep():
+    """Static chains plus 64 dynamic chains (16 steps, burn-in 3) in the
+    Cornell room under a moving light, four chain frames after two uniform
+    ones: f_d proxies, marks, the texel-centre rays and the dynamic blend
+    (hysteresis 0.91) against the oracle."""
+    from tests.parity import run_chain_lockstep
+    sc = scenes.cornell()
+    sc.light_a = np.array([[0.5, 0.95, 0.5]], np.float32)
+    sc.light_b = np.array([[0.25, 0.6, 0.35]], np.float32)
+    sc.frames = 8
+    res = run_chain_lockstep(sc, frames=4, chains=256, steps=64, burn_in=15, dyn_chains=64)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    assert res["marks"] > 0 and res["dyn_rays"] > 0, res
+    _report("dynamic_chains_cornell", res)
+    _assert_dyn_parity(res)
+
+
+def test_dynamic_chains_box_field_refit_lockstep():
+    """Box field with bobbing boxes (refit every frame), 9 x 3 x 9 probes
+    (3 x 1 x 3 full proxies), 1500 static and 300 dynamic chains, three
+    chain frames."""
+    from tests.parity import run_chain_lockstep
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 302, lattice=27, dims=(9, 3, 9), n_lights=2, frames=8,
+                          anim_fraction=0.3)
+    res = run_chain_lockstep(sc, frames=3, chains=1500, steps=24, burn_in=5, n_uniform=32,
+                             dyn_chains=300, dyn_steps=12, dyn_burn_in=2)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    assert res["marks"] > 0, res
+    _assert_dyn_parity(res)

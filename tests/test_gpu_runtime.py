@@ -37,7 +37,10 @@ def _same(a, b):
     for k in ("irradiance", "depth", "irr_count", "depth_count", "rays_per_probe", "score",
               "irr_words", "depth_words"):
         if k in a or k in b:
-            assert np.array_equal(a[k], b[k]), k
+            if not np.array_equal(a[k], b[k], equal_nan=a[k].dtype.kind == "f"):
+                bad = np.argwhere(a[k] != b[k])
+                raise AssertionError(f"{k}: {len(bad)} elements differ, first {bad[:4].tolist()}, "
+                                     f"max |diff| {np.max(np.abs(a[k].astype(np.float64) - b[k])):.3g}")
 
 
 def test_bitwise_determinism_across_runs():
@@ -180,7 +183,7 @@ def _chain_run(sc, frames, tuning=None, vol=None, start=0, chains=768, steps=24,
 def _same_chain(a, b):
     _same(a, b)
     for k in ("chain_state", "sample_probe", "sample_uv"):
-        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], b[k]), (k, int(np.count_nonzero(a[k] != b[k])))
 
 
 @pytest.mark.parametrize("tuning", [
@@ -262,4 +265,64 @@ def test_chain_error_paths():
         vol.update_chains(0, 16, 8, 1, sigma_pos=0.0)
     st = vol.update_chains(0, 64, 16, 0, sync=True)
     assert st["primary_rays"] == 2 * 64 * 15
+    vol.destroy_volume()
+
+
+def _dyn_run(sc, frames, tuning=None, vol=None, start=0):
+    own = vol is None
+    if own:
+        vol = adgi.volume_for_scene(sc, max_rays=2 * 512 * 20 + sc.num_probes * 232, seed=6, max_chains=512)
+    if tuning:
+        vol.set_tuning(**tuning)
+    for f in range(start, start + frames):
+        vol.update_scene(sc.positions_at(f), light_pos=sc.light_positions(f),
+                         light_intensity=sc.light_intensity, sky=sc.sky,
+                         mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, sc.anim_vertices))
+        if f < 1:
+            vol.update_probes(f, adaptive=False, n_uniform=32, sync=True)
+        else:
+            vol.update_chains(f, 512, 24, 3, sync=True, dyn_chains=128, dyn_steps=12, dyn_burn_in=2)
+    rb = vol.read_probes()
+    if own:
+        vol.destroy_volume()
+    return rb
+
+
+def _same_dyn(a, b):
+    _same_chain(a, b)
+    for k in ("dyn_mark", "dyn_target", "dyn_state", "dyn_ray_offsets"):
+        assert np.array_equal(a[k], b[k]), (k, int(np.count_nonzero(a[k] != b[k])))
+
+
+@pytest.mark.parametrize("tuning", [{"chain_lanes": 1}, {"persistent": 0}, {"bvh_width": 4}])
+def test_dynamic_chain_launch_shape_does_not_change_results(tuning):
+    sc = _small_field()
+    a = _dyn_run(sc, 5)
+    assert a["dyn_mark"].sum() > 0 and a["num_dyn_rays"] > 0
+    _same_dyn(a, _dyn_run(sc, 5, tuning=tuning))
+
+
+def test_dynamic_chain_snapshot_resumes_bit_identically():
+    sc = _small_field()
+    ref = _dyn_run(sc, 6)
+    vol = adgi.volume_for_scene(sc, max_rays=2 * 512 * 20 + sc.num_probes * 232, seed=6, max_chains=512)
+    _dyn_run(sc, 3, vol=vol)
+    snap = vol.save_state()
+    vol.destroy_volume()
+    vol2 = adgi.volume_for_scene(sc, max_rays=2 * 512 * 20 + sc.num_probes * 232, seed=6, max_chains=512)
+    vol2.restore_state(snap)
+    got = _dyn_run(sc, 3, vol=vol2, start=3)
+    vol2.destroy_volume()
+    _same_dyn(ref, got)
+
+
+def test_dynamic_chain_capacity_check():
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 211, lattice=16, dims=(8, 2, 8), n_lights=1, frames=2)
+    vol = adgi.volume_for_scene(sc, max_rays=4096, max_chains=64)
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_chains(0, 16, 8, 1, dyn_chains=64, dyn_steps=16, dyn_burn_in=1)
+    assert e.value.status == adgi.ADGI_ERR_BUDGET
+    with pytest.raises(adgi.AdgiError) as e:
+        vol.update_chains(0, 16, 8, 1, dyn_chains=65, dyn_steps=16, dyn_burn_in=1)
+    assert e.value.status == adgi.ADGI_ERR_INVALID_ARG
     vol.destroy_volume()
