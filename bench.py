@@ -182,17 +182,20 @@ def stage_times(vol, sc, adgi, frame0, frames, **p):
 
 
 # Chain frames on the same scene: the paper's 4096 static chains (about 64
-# used samples each, Sec. 4.7 and Sec. 5), and as many chains as probes,
+# used samples each, Sec. 5), and as many chains as probes,
 # which traces the adaptive budget B = 2^23 (two rays per sample).
 CHAIN_CONFIGS = {
     "paper_4096_chains": dict(chains=4096, steps=80, burn_in=15),
     "equal_budget": dict(chains=65536, steps=80, burn_in=15),
+    # the paper's 4096 static + 1024 dynamic chains (Sec. 5)
+    "paper_static_dynamic": dict(chains=4096, steps=80, burn_in=15, dyn_chains=1024, dyn_steps=8,
+                                 dyn_burn_in=3),
 }
 CHAIN_STAGES = ["setup", "pilot_trace", "chains_and_sort", "blend_order", "sample_trace", "blend"]
 
 
 def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, chains, steps_per_chain,
-               burn_in):
+               burn_in, dyn_chains=0, dyn_steps=0, dyn_burn_in=0):
     """Chain frames: two warm uniform frames give the guide an irradiance,
     then `warmup` untimed and `steps` timed chain frames (scene update
     included, as in the budgeted steps), then synchronous frames for latency
@@ -200,10 +203,14 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
     the kernels)."""
     P = sc.num_probes
     S = steps_per_chain - burn_in - 1
-    vol = adgi.volume_for_scene(sc, storage=storage, max_rays=max(2 * chains * S, P * 32), seed=11,
-                                max_chains=chains)
+    Sd = dyn_steps - dyn_burn_in - 1 if dyn_chains else 0
+    pd = [(int(x) + 2) // 3 for x in sc.grid_dims]
+    dyn_cap = min(P * 232, 27 * 34 * min(8 * pd[0] * pd[1] * pd[2], dyn_chains * Sd)) if dyn_chains else 0
+    vol = adgi.volume_for_scene(sc, storage=storage, max_rays=max(2 * chains * S + dyn_cap, P * 32), seed=11,
+                                max_chains=max(chains, dyn_chains))
     vol.set_tuning(**tuning)
-    kw = dict(chains=chains, steps=steps_per_chain, burn_in=burn_in)
+    kw = dict(chains=chains, steps=steps_per_chain, burn_in=burn_in, dyn_chains=dyn_chains, dyn_steps=dyn_steps,
+              dyn_burn_in=dyn_burn_in)
     f = 0
     for _ in range(2):
         step_scene(vol, sc, f, adgi)
@@ -221,7 +228,7 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
         f += 1
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
-    host_ms, gpu_ms, stage = [], [], [0.0] * 6
+    host_ms, gpu_ms, stage, rays_seen, marks = [], [], [0.0] * 6, [], []
     for _ in range(latency_frames):
         step_scene(vol, sc, f, adgi)
         torch.cuda.synchronize()
@@ -229,6 +236,9 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
         st = vol.update_chains(f, sync=True, **kw)
         host_ms.append((time.perf_counter() - a) * 1e3)
         gpu_ms.append(st["ms_total"])
+        rays_seen.append(st["primary_rays"])
+        if dyn_chains:
+            marks.append(int(vol.read_probes(texels=False)["dyn_mark"].sum()))
         for k in range(6):
             stage[k] += st["ms_stage"][k] / latency_frames
         f += 1
@@ -236,7 +246,9 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
     rb = vol.read_probes(texels=False)
     n = rb["rays_per_probe"]
     vol.destroy_volume()
-    rays = 2 * chains * S
+    # rays per frame: 2 per static sample plus the dynamic texel-centre rays
+    # (measured on the synchronous frames; the timed frames trace as many)
+    rays = sum(rays_seen) / len(rays_seen)
     trace_ms = stage[4]
     nr = max(tw["primary_rays"] + tw["shadow_rays"], 1)
     return {"chains": chains, "steps": steps_per_chain, "burn_in": burn_in, "samples_per_frame": chains * S,
@@ -248,7 +260,10 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
             "sample_trace_mrays_per_s_incl_shadow": nr / (trace_ms * 1e-3) / 1e6 if trace_ms else None,
             "sample_trace_tops": (tw["box_tests"] * OPS_PER_BOX + tw["tri_tests"] * OPS_PER_TRI)
             / (trace_ms * 1e-3) / 1e12 if trace_ms else None,
-            "probes_with_samples": int((n > 0).sum()), "max_samples_per_probe": int(n.max())}
+            "probes_with_samples": int((n > 0).sum()), "max_samples_per_probe": int(n.max()),
+            **({"dyn_chains": dyn_chains, "dyn_steps": dyn_steps, "dyn_burn_in": dyn_burn_in,
+                "marked_proxy_octants_per_frame": sum(marks) / len(marks),
+                "dynamic_rays_per_frame": rays - 2 * chains * S} if dyn_chains else {})}
 
 
 def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
@@ -527,7 +542,7 @@ def main():
             out["chain_frames"][name] = run_chains(
                 adgi, torch, sc, storage if args.storage != "packed" else adgi.ADGI_FP32, tuning,
                 args.steps, args.warmup, min(args.latency_frames, 20), c["chains"], c["steps"],
-                c["burn_in"])
+                c["burn_in"], c.get("dyn_chains", 0), c.get("dyn_steps", 0), c.get("dyn_burn_in", 0))
             print(f"[bench] chains {name} done", file=sys.stderr, flush=True)
     if not args.no_serve:
         out["serving"] = run_serving(adgi, duration_s=args.serve_seconds)

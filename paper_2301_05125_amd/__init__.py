@@ -460,9 +460,11 @@ class Volume:
         return w.as_dict()
 
     def measure_chain_trace_work(self, frame, chains, steps, burn_in, sigma_pos=0.5,
-                                 sigma_dir=CHAIN_SIGMA_DIR, beta=5.0) -> dict:
-        """Traversal work of a chain frame's sample rays (state restored after)."""
-        p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, False, beta, True)
+                                 sigma_dir=CHAIN_SIGMA_DIR, beta=5.0, dyn_chains=0, dyn_steps=0,
+                                 dyn_burn_in=0) -> dict:
+        """Traversal work of a chain frame's rays (state restored after)."""
+        p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, False, beta, True,
+                               dyn_chains=dyn_chains, dyn_steps=dyn_steps, dyn_burn_in=dyn_burn_in)
         w = TraceWork()
         _check(lib().adgi_measure_trace_work(self.h, C.byref(p), C.byref(w)))
         return w.as_dict()
