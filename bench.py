@@ -81,7 +81,7 @@ def read_profile(kernel_key, src_hash):
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != src_hash:
         return {}
-    out = {}
+    out = {"kernel_name": vals.get("kernel", "")}
     for key, name in (("hbm_bytes_per_dispatch", "traffic"), ("VALUBusy", "valu_busy_pct"),
                       ("VALUUtilization", "valu_utilization_pct"), ("kernel_trace_avg_us", "rocprof_avg_us")):
         try:
@@ -491,8 +491,14 @@ def main():
     h_trace = source_hash("trace.hip", "adgi_device.hpp", "adgi_layout.hpp", "bvh_build.cpp")
     h_blend = source_hash("blend.hip", "adgi_device.hpp")
     prof_trace, prof_blend = read_profile("trace_boxfield", h_trace), read_profile("blend_boxfield", h_blend)
+    # the counters belong to one traversal variant (BVH2: trace_kernel<0, false, false>)
+    w4 = tuning.get("bvh_width") == 4 and prof_trace.get("kernel_name", "").endswith("true>(adgi::VolumeView, int)")
+    w2 = tuning.get("bvh_width") != 4 and prof_trace.get("kernel_name", "").endswith("false>(adgi::VolumeView, int)")
+    if not (w4 or w2):
+        prof_trace = {}
     nrays = max(tw["primary_rays"] + tw["shadow_rays"], 1)
-    roof_trace = {"bound": "alu", "kernel": "trace_kernel<primary>", "achieved": trace_tops,
+    roof_trace = {"bound": "alu", "kernel": "trace_kernel<primary, BVH%d>" % (4 if tuning.get("bvh_width") == 4 else 2),
+                  "achieved": trace_tops,
                   "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": trace_tops / VALU_PEAK_TOPS,
                   "traffic": prof_trace.get("traffic"),
                   "valu_busy_pct": prof_trace.get("valu_busy_pct"),

@@ -1335,8 +1335,14 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   hipError_t err = hipSuccess;
   const int blocks[] = {64, 128, 256};
   const int waves[] = {16, 24, 32};
-  const int widths[] = {4, 2};
-  for (int width : widths)
+  // the 4-wide tree is taken only when it beats the binary one by 3%: the
+  // two are often within timing noise, and a stable choice keeps results
+  // and profiles comparable from run to run
+  adgi_tuning best_w[2] = {saved, saved};
+  float best_wms[2] = {INFINITY, INFINITY};
+  for (int wi = 0; wi < 2 && err == hipSuccess; ++wi) {
+    const int width = wi == 0 ? 2 : 4;
+    if (width == 4 && !vol->d_nodes4) continue;
     for (int b : blocks)
       for (int w : waves) {
         adgi_tuning c = saved;
@@ -1344,14 +1350,19 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
         c.bvh_width = width;
         c.trace_block = b;
         c.trace_waves_per_cu = w;
-        if (width == 4 && !vol->d_nodes4) continue;
         float ms;
         if ((err = time_trace(c, ms)) != hipSuccess) break;
-        if (ms < best_ms) {
-          best_ms = ms;
-          best_t = c;
+        if (ms < best_wms[wi]) {
+          best_wms[wi] = ms;
+          best_w[wi] = c;
         }
       }
+  }
+  if (err == hipSuccess) {
+    const int wi = best_wms[1] < 0.97f * best_wms[0] ? 1 : 0;
+    best_t = best_w[wi];
+    best_ms = best_wms[wi];
+  }
   if (err == hipSuccess) {
     adgi_tuning c = best_t;
     c.persistent = 0;
