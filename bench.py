@@ -266,6 +266,95 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
                 "dynamic_rays_per_frame": rays - 2 * chains * S} if dyn_chains else {})}
 
 
+def run_quality(adgi, torch, sc, cfg, tuning, frames=40, every=8, ref_rays=2304):
+    """Texel error of the samplers at equal rays per frame against a converged
+    reference (the paper's protocol for its reference renderer, Sec. 5: the
+    texels are cleared every frame and take a true average, here of
+    ref_rays = 64 x 36 spherical-Fibonacci rays per probe, hysteresis close to
+    1 so that a = 1/(N+1)). Every `every` frames of the animated scene the
+    reference is rebuilt at that frame and each sampler's irradiance
+    luminance is compared texel by texel: RMSE and mean absolute error
+    relative to the mean reference luminance, over all probes and over the
+    probes whose reference changed most since the previous checkpoint (the
+    top 10%). A second reference with other rays gives the reference's own
+    noise on the same scale."""
+    import numpy as np
+    P = sc.num_probes
+    B = cfg["budget"]
+    contenders = {
+        "adaptive": dict(kind="adaptive"),
+        "uniform": dict(kind="uniform", n=B // P),
+        "chains": dict(kind="chains", chains=B // 128, steps=80, burn_in=15),
+    }
+    vols = {}
+    for name, c in contenders.items():
+        if c["kind"] == "chains":
+            v = adgi.volume_for_scene(sc, max_rays=B + P * 64, seed=11, max_chains=c["chains"])
+        else:
+            v = adgi.volume_for_scene(sc, max_rays=max(B, P * c.get("n", 0)), seed=11)
+        v.set_tuning(**tuning)
+        vols[name] = v
+    ref = adgi.volume_for_scene(sc, max_rays=P * ref_rays, seed=12, hysteresis=0.99999)
+    ref2 = adgi.volume_for_scene(sc, max_rays=P * ref_rays, seed=13, hysteresis=0.99999)
+    blank = ref.save_state()
+
+    def lum(rb):
+        irr = rb["irradiance"][:, 1:-1, 1:-1, :].astype(np.float64)
+        return 0.2126 * irr[..., 0] + 0.7152 * irr[..., 1] + 0.0722 * irr[..., 2]
+
+    out = {name: [] for name in list(contenders) + ["reference_noise"]}
+    prev_ref = None
+    rays = {name: 0 for name in contenders}
+    for f in range(frames):
+        for name, v in vols.items():
+            step_scene(v, sc, f, adgi)
+            c = contenders[name]
+            if c["kind"] == "adaptive":
+                st = v.update_probes(f, adaptive=True, budget=B, n_min=cfg["n_min"], n_max=cfg["n_max"], sync=True)
+            elif c["kind"] == "uniform" or f < 2:
+                st = v.update_probes(f, adaptive=False, n_uniform=c.get("n", 32), sync=True)
+            else:
+                st = v.update_chains(f, c["chains"], c["steps"], c["burn_in"], sync=True)
+            rays[name] += st["primary_rays"]
+        if f % every != every - 1:
+            continue
+        refs = []
+        for rv in (ref, ref2):
+            rv.restore_state(blank)
+            step_scene(rv, sc, f, adgi)
+            rv.update_probes(f, adaptive=False, n_uniform=ref_rays, sync=True)
+            refs.append(lum(rv.read_probes()))
+        lr = refs[0]
+        mean = float(lr.mean())
+        changed = None
+        if prev_ref is not None:
+            d = np.abs(lr - prev_ref).reshape(P, -1).mean(axis=1)
+            changed = d >= np.quantile(d, 0.9)
+        prev_ref = lr
+        for name in out:
+            got = refs[1] if name == "reference_noise" else lum(vols[name].read_probes())
+            e = (got - lr).reshape(P, -1)
+            row = {"frame": f, "rmse_rel": float(np.sqrt(np.mean(e * e)) / mean),
+                   "mae_rel": float(np.mean(np.abs(e)) / mean)}
+            if changed is not None:
+                row["rmse_rel_changed"] = float(np.sqrt(np.mean(e[changed] ** 2)) / mean)
+                row["mae_rel_changed"] = float(np.mean(np.abs(e[changed])) / mean)
+            out[name].append(row)
+        print(f"[bench] quality frame {f}: mae " + ", ".join(
+            f"{n} {out[n][-1]['mae_rel']:.4f}" for n in out), file=sys.stderr, flush=True)
+    for v in list(vols.values()) + [ref, ref2]:
+        v.destroy_volume()
+    summary = {}
+    for name in out:
+        rows = out[name][1:]  # after the first checkpoint the caches have history
+        summary[name] = {"rays_per_frame": rays[name] / frames if name in rays else ref_rays * P,
+                         **{f"{m}_mean": float(np.mean([r[m] for r in rows]))
+                            for m in ("rmse_rel", "mae_rel", "rmse_rel_changed", "mae_rel_changed")},
+                         "checkpoints": out[name]}
+    return {"reference": f"cleared every checkpoint, true average of {ref_rays} rays per probe",
+            "frames": frames, "every": every, "samplers": summary}
+
+
 def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
     """The oracle as it stands, on the host cores, on a bounded sample of the
     adaptive frame: the scene update, all pilot rays, detection and allocation
@@ -411,6 +500,8 @@ def main():
     ap.add_argument("--skip-uniform", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the 32-stream serving mix")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--quality", action="store_true",
+                    help="texel error against a converged reference: adaptive vs uniform vs chains")
     ap.add_argument("--chains", default=",".join(CHAIN_CONFIGS),
                     help="comma-separated chain-frame configurations to run (none: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -540,6 +631,9 @@ def main():
         "scene_build_s": build_s,
     }
     vol.destroy_volume()
+    if args.quality:
+        out["quality"] = run_quality(adgi, torch, sc, cfg, tuning)
+        print("[bench] quality done", file=sys.stderr, flush=True)
     chain_names = [c for c in args.chains.split(",") if c and c != "none"]
     if chain_names:
         out["chain_frames"] = {}
