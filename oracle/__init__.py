@@ -118,7 +118,7 @@ def lib():
         L.orc_probe_frame.argtypes = [P, P, C.c_int32, C.c_int32, P, P, C.c_int32, C.c_int32,
                                       C.c_double, C.c_double, C.c_int32] + [P] * 14
         L.orc_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32,
-                                       C.c_double, C.c_double, C.c_int32] + [P] * 14
+                                       C.c_double, C.c_double, C.c_int32, C.c_int32] + [P] * 14
         L.orc_blend_alpha.restype = C.c_double
         L.orc_blend_alpha.argtypes = [C.c_int32, C.c_double]
         L.orc_round_half.restype = C.c_double
@@ -490,7 +490,7 @@ class OracleVolume:
     def __init__(self, scene, irr_res: int = 8, depth_res: int = 16,
                  hysteresis: float = 0.97, tau_max: float = TAU_MAX, seed: int = 1,
                  fp16: bool = False, probes: Optional[np.ndarray] = None,
-                 use_bvh: bool = True, tol: Optional[Tol] = None):
+                 use_bvh: bool = True, tol: Optional[Tol] = None, gather: bool = False):
         self.sc = scene
         self.scene = OracleScene(scene.positions, scene.indices, scene.albedo, use_bvh=use_bvh)
         self.grid = make_grid(scene.grid_origin, scene.grid_spacing, scene.grid_dims)
@@ -501,6 +501,7 @@ class OracleVolume:
         self.tau_max = float(np.float32(tau_max))
         self.seed = seed
         self.fp16 = bool(fp16)
+        self.gather = bool(gather)  # DDGI's cosine-weighted gather instead of per-sample updates
         self.tol = tol if tol is not None else default_tol()
         self.probes = (np.arange(self.P, dtype=np.int32) if probes is None
                        else np.ascontiguousarray(probes, np.int32))
@@ -594,7 +595,7 @@ class OracleVolume:
         lib().orc_probes_frame(
             self.scene.ptr, C.byref(self.grid), nq, _p(self.probes), _p(n_sel), _p(ray_base),
             _p(Rf), C.byref(self.tol), self.irr_res, self.depth_res, self.h, self.tau_max,
-            1 if self.fp16 else 0, _p(h_tri), _p(h_sh), _p(h_ib), _p(h_db),
+            1 if self.fp16 else 0, 1 if self.gather else 0, _p(h_tri), _p(h_sh), _p(h_ib), _p(h_db),
             _p(self.irr), _p(self.irr_n), _p(self.dep), _p(self.dep_n),
             _p(rays), _p(tri), _p(sh), _p(ib), _p(db), C.byref(cnt))
         secs["probes"] = time.perf_counter() - t0

@@ -987,9 +987,12 @@ double orc_round_half(double x) {
   return copysign(r, x);
 }
 
+/* DDGI's depth weight sharpness (the cosine raised to this power) */
+#define ORC_GATHER_DEPTH_POWER 50
+
 static void probe_frame_one(const orc_scene* s, const orc_grid* g, int32_t probe, int32_t n,
                             const float R[9], const orc_tol* tol, int32_t irr_r, int32_t dep_r,
-                            double hyst, double tau_max, int32_t fp16, const int32_t* hint_tri,
+                            double hyst, double tau_max, int32_t fp16, int32_t gather, const int32_t* hint_tri,
                             const uint8_t* hint_shadow, const uint16_t* hint_ibin,
                             const uint16_t* hint_dbin, double* irr, uint8_t* irr_n, double* dep,
                             uint8_t* dep_n, double* rays, int32_t* tri, uint8_t* shadow,
@@ -998,6 +1001,14 @@ static void probe_frame_one(const orc_scene* s, const orc_grid* g, int32_t probe
   orc_probe_pos(g, probe, o);
   int32_t ri = irr_r - 2, rd = dep_r - 2;
   int64_t ties[2] = {0, 0}, mism[2] = {0, 0};
+  /* gather: per texel the sums of w, w rgb (irradiance) and w, w tau, w tau^2
+   * (depth) over the frame's rays */
+  double* gi = NULL;
+  double* gd = NULL;
+  if (gather) {
+    gi = (double*)calloc((size_t)ri * ri * 4, sizeof(double));
+    gd = (double*)calloc((size_t)rd * rd * 3, sizeof(double));
+  }
   for (int32_t j = 0; j < n; ++j) {
     double d[3];
     orc_sf_dir(j, n, R, d);
@@ -1025,16 +1036,36 @@ static void probe_frame_one(const orc_scene* s, const orc_grid* g, int32_t probe
         cnt->bin_mismatch++;
       }
     }
-    /* irradiance texel: radiance sample */
-    double ai = orc_blend_alpha(irr_n[ki], hyst);
-    for (int c = 0; c < 3; ++c) irr[3 * ki + c] += ai * (ray.rgb[c] - irr[3 * ki + c]);
-    if (irr_n[ki] < 255) irr_n[ki]++;
-    /* depth texel: first two moments of the normalised distance (Sec. 4.6) */
     double tau = isfinite(ray.t) ? fmin(ray.t / g->s, tau_max) : tau_max;
-    double ad = orc_blend_alpha(dep_n[kd], hyst);
-    dep[2 * kd + 0] += ad * (tau - dep[2 * kd + 0]);
-    dep[2 * kd + 1] += ad * (tau * tau - dep[2 * kd + 1]);
-    if (dep_n[kd] < 255) dep_n[kd]++;
+    if (gather) {
+      /* every texel takes the ray, weighted by the cosine to its centre
+       * direction (irradiance) or that cosine to the 50th power (depth) */
+      for (int32_t k = 0; k < ri * ri; ++k) {
+        double c[3];
+        orc_texel_centre_dir(ri, k, c);
+        const double w = fmax(0.0, c[0] * d[0] + c[1] * d[1] + c[2] * d[2]);
+        gi[4 * k] += w;
+        for (int a = 0; a < 3; ++a) gi[4 * k + 1 + a] += w * ray.rgb[a];
+      }
+      for (int32_t k = 0; k < rd * rd; ++k) {
+        double c[3];
+        orc_texel_centre_dir(rd, k, c);
+        const double w = pow(fmax(0.0, c[0] * d[0] + c[1] * d[1] + c[2] * d[2]), ORC_GATHER_DEPTH_POWER);
+        gd[3 * k] += w;
+        gd[3 * k + 1] += w * tau;
+        gd[3 * k + 2] += w * tau * tau;
+      }
+    } else {
+      /* irradiance texel: radiance sample */
+      double ai = orc_blend_alpha(irr_n[ki], hyst);
+      for (int c = 0; c < 3; ++c) irr[3 * ki + c] += ai * (ray.rgb[c] - irr[3 * ki + c]);
+      if (irr_n[ki] < 255) irr_n[ki]++;
+      /* depth texel: first two moments of the normalised distance (Sec. 4.6) */
+      double ad = orc_blend_alpha(dep_n[kd], hyst);
+      dep[2 * kd + 0] += ad * (tau - dep[2 * kd + 0]);
+      dep[2 * kd + 1] += ad * (tau * tau - dep[2 * kd + 1]);
+      if (dep_n[kd] < 255) dep_n[kd]++;
+    }
     if (rays) {
       rays[4 * j + 0] = ray.rgb[0];
       rays[4 * j + 1] = ray.rgb[1];
@@ -1045,6 +1076,25 @@ static void probe_frame_one(const orc_scene* s, const orc_grid* g, int32_t probe
     if (shadow) shadow[j] = ray.shadow;
     if (ibin) ibin[j] = (uint16_t)ki;
     if (dbin) dbin[j] = (uint16_t)kd;
+  }
+  if (gather) {
+    /* the frame's weighted mean, blended with the step rule of the per-sample
+     * update counted in frames: a = max(1/(N+1), 1-h) */
+    for (int32_t k = 0; k < ri * ri; ++k) {
+      if (!(gi[4 * k] > 0.0)) continue;
+      const double a = orc_blend_alpha(irr_n[k], hyst);
+      for (int c = 0; c < 3; ++c) irr[3 * k + c] += a * (gi[4 * k + 1 + c] / gi[4 * k] - irr[3 * k + c]);
+      if (irr_n[k] < 255) irr_n[k]++;
+    }
+    for (int32_t k = 0; k < rd * rd; ++k) {
+      if (!(gd[3 * k] > 0.0)) continue;
+      const double a = orc_blend_alpha(dep_n[k], hyst);
+      dep[2 * k + 0] += a * (gd[3 * k + 1] / gd[3 * k] - dep[2 * k + 0]);
+      dep[2 * k + 1] += a * (gd[3 * k + 2] / gd[3 * k] - dep[2 * k + 1]);
+      if (dep_n[k] < 255) dep_n[k]++;
+    }
+    free(gi);
+    free(gd);
   }
   if (fp16) {
     for (int32_t k = 0; k < ri * ri * 3; ++k) irr[k] = orc_round_half(irr[k]);
@@ -1063,7 +1113,7 @@ void orc_probe_frame(const orc_scene* s, const orc_grid* g, int32_t probe, int32
                      const uint16_t* hint_dbin, double* irr, uint8_t* irr_n, double* dep,
                      uint8_t* dep_n, double* rays, int32_t* tri, uint8_t* shadow, uint16_t* ibin,
                      uint16_t* dbin, orc_counts* counts) {
-  probe_frame_one(s, g, probe, n, R, tol, irr_r, dep_r, hysteresis, tau_max, fp16, hint_tri,
+  probe_frame_one(s, g, probe, n, R, tol, irr_r, dep_r, hysteresis, tau_max, fp16, 0, hint_tri,
                   hint_shadow, hint_ibin, hint_dbin, irr, irr_n, dep, dep_n, rays, tri, shadow,
                   ibin, dbin, counts);
 }
@@ -1071,7 +1121,7 @@ void orc_probe_frame(const orc_scene* s, const orc_grid* g, int32_t probe, int32
 void orc_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
                       const int32_t* n, const int64_t* ray_base, const float R[9], const orc_tol* tol,
                       int32_t irr_r, int32_t dep_r, double hysteresis, double tau_max, int32_t fp16,
-                      const int32_t* hint_tri, const uint8_t* hint_shadow,
+                      int32_t gather, const int32_t* hint_tri, const uint8_t* hint_shadow,
                       const uint16_t* hint_ibin, const uint16_t* hint_dbin, double* irr,
                       uint8_t* irr_n, double* dep, uint8_t* dep_n, double* rays, int32_t* tri,
                       uint8_t* shadow, uint16_t* ibin, uint16_t* dbin, orc_counts* counts) {
@@ -1085,7 +1135,7 @@ void orc_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, cons
 #pragma omp for schedule(dynamic, 1)
     for (int32_t q = 0; q < count; ++q) {
       int64_t b = ray_base[q];
-      probe_frame_one(s, g, probes[q], n[q], R, tol, irr_r, dep_r, hysteresis, tau_max, fp16,
+      probe_frame_one(s, g, probes[q], n[q], R, tol, irr_r, dep_r, hysteresis, tau_max, fp16, gather,
                       hint_tri ? hint_tri + b : NULL, hint_shadow ? hint_shadow + b : NULL,
                       hint_ibin ? hint_ibin + b : NULL, hint_dbin ? hint_dbin + b : NULL,
                       irr + (int64_t)q * ri * ri * 3, irr_n + (int64_t)q * ri * ri,

@@ -159,11 +159,16 @@ void orc_probe_frame(const orc_scene* s, const orc_grid* g, int32_t probe, int32
                      double* rays, int32_t* tri, uint8_t* shadow, uint16_t* ibin, uint16_t* dbin,
                      orc_counts* counts);
 /* many probes in parallel (OpenMP); state arrays indexed by position in list;
- * hints/outputs indexed by ray offset ray_base[q] + j */
+ * hints/outputs indexed by ray offset ray_base[q] + j. gather != 0 replaces the
+ * per-sample update by DDGI's gather (Majercik et al. 2019, the blend Sec. 3.1
+ * describes): every texel takes the frame's rays weighted by max(0, c.d) (c
+ * its centre direction; depth: that cosine to the 50th power), and the
+ * weighted mean enters the texel with a = max(1/(N+1), 1-h), N counting the
+ * frames in which the texel had weight. */
 void orc_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, const int32_t* probes,
                       const int32_t* n, const int64_t* ray_base, const float R[9], const orc_tol* tol,
                       int32_t irr_r, int32_t dep_r, double hysteresis, double tau_max, int32_t fp16,
-                      const int32_t* hint_tri, const uint8_t* hint_shadow,
+                      int32_t gather, const int32_t* hint_tri, const uint8_t* hint_shadow,
                       const uint16_t* hint_ibin, const uint16_t* hint_dbin,
                       double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
                       double* rays, int32_t* tri, uint8_t* shadow, uint16_t* ibin, uint16_t* dbin,
