@@ -78,6 +78,16 @@ enum { ADGI_SCENE_REBUILD = 0, ADGI_SCENE_REFIT = 1 };      /* scene update mode
 enum { ADGI_DEBUG_ARRAYS = 1u << 0 };                        /* volume flags */
 enum { ADGI_MAX_LIGHTS = 8 };
 enum { ADGI_MODE_UNIFORM = 0, ADGI_MODE_ADAPTIVE = 1, ADGI_MODE_CHAIN = 2 };  /* params.adaptive */
+/* Texel update (volume desc): ADGI_BLEND_SAMPLE, the paper's per-sample
+ * moving average into the texel holding each direction (Alg. ApproxAlgo,
+ * Alg. MovingAvgUpdate); ADGI_BLEND_GATHER, DDGI's cosine-weighted gather
+ * (Majercik et al. 2019; the update Sec. 3.1 describes): every texel takes all
+ * of the probe's rays of the frame weighted by max(0, c.d), c its centre
+ * direction (depth: that cosine to the 50th power), and their weighted mean
+ * enters the texel with a = max(1/(N+1), 1 - h), N counting the frames in
+ * which the texel had weight. Gather: ADGI_FP32 / ADGI_FP16, tiles 8/16 or
+ * 16/16, budgeted or uniform frames. */
+enum { ADGI_BLEND_SAMPLE = 0, ADGI_BLEND_GATHER = 1 };
 enum { ADGI_CHAIN_MAX_STEPS = 256 };
 
 /* Device memory provider. alloc returns device memory of at least `bytes`
@@ -105,6 +115,7 @@ typedef struct {
                                  (ADGI_FP32 / ADGI_FP16, tiles 8/16 or 16/16);
                                  allocates the chain state and sample buffers for
                                  max_rays/2 samples                               */
+  int32_t blend_mode;         /* ADGI_BLEND_SAMPLE (0) or ADGI_BLEND_GATHER         */
 } adgi_volume_desc;
 
 typedef struct {

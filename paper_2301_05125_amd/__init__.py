@@ -30,6 +30,7 @@ ADGI_FP32, ADGI_FP16, ADGI_PACKED = 0, 1, 2
 ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
 ADGI_DEBUG_ARRAYS = 1
 ADGI_MODE_UNIFORM, ADGI_MODE_ADAPTIVE, ADGI_MODE_CHAIN = 0, 1, 2
+ADGI_BLEND_SAMPLE, ADGI_BLEND_GATHER = 0, 1
 CHAIN_MAX_STEPS = 256
 CHAIN_SIGMA_DIR = math.sqrt(math.pi / 256.0)  # default octahedral step of the chains (Sec. 4.8)
 MAX_LIGHTS = 8
@@ -55,7 +56,7 @@ class VolumeDesc(C.Structure):
                 ("irr_res", C.c_int32), ("depth_res", C.c_int32), ("storage", C.c_int32),
                 ("hysteresis", C.c_float), ("tau_max", C.c_float),
                 ("max_rays_per_frame", C.c_int64), ("seed", C.c_uint64), ("flags", C.c_uint32),
-                ("max_chains", C.c_int32)]
+                ("max_chains", C.c_int32), ("blend_mode", C.c_int32)]
 
 
 class SceneDesc(C.Structure):
@@ -251,9 +252,10 @@ def _torch_allocator():
 
 def create_volume(origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
                   hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
-                  debug=False, stream=None, allocator="torch", max_chains=0) -> "Volume":
+                  debug=False, stream=None, allocator="torch", max_chains=0,
+                  blend_mode=ADGI_BLEND_SAMPLE) -> "Volume":
     return Volume(origin, spacing, dims, irr_res, depth_res, storage, hysteresis, tau_max,
-                  max_rays_per_frame, seed, debug, stream, allocator, max_chains)
+                  max_rays_per_frame, seed, debug, stream, allocator, max_chains, blend_mode)
 
 
 class Volume:
@@ -261,7 +263,8 @@ class Volume:
 
     def __init__(self, origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
                  hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
-                 debug=False, stream=None, allocator="torch", max_chains=0):
+                 debug=False, stream=None, allocator="torch", max_chains=0,
+                 blend_mode=ADGI_BLEND_SAMPLE):
         d = VolumeDesc()
         d.origin[:] = [float(x) for x in origin]
         d.spacing[:] = [float(x) for x in spacing]
@@ -272,6 +275,7 @@ class Volume:
         d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         d.flags = ADGI_DEBUG_ARRAYS if debug else 0
         d.max_chains = int(max_chains)
+        d.blend_mode = int(blend_mode)
         self.desc = d
         self.P = int(np.prod([int(x) for x in dims]))
         self._alloc = None

@@ -64,8 +64,10 @@ struct BlendIO {
 // workgroup per probe with `chunk` rays staged per step.
 // storage: ADGI_FP32, ADGI_FP16 or ADGI_PACKED (wave kernel only)
 // chain: the lists are chain samples (wave kernel; not with ADGI_PACKED)
+// gather: DDGI's cosine-weighted gather instead of the per-sample update
+// (wave kernel; not with ADGI_PACKED or chain frames)
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
-                        int grid = 0, bool chain = false);
+                        int grid = 0, bool chain = false, bool gather = false);
 bool blend_wave_supported(const VolumeView& v);
 // Fills the table of decoded values of every packed code (v.pk_dec).
 hipError_t launch_packed_decode_table(float* dec, hipStream_t s);

@@ -519,6 +519,142 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
 }
 
 // ---------------------------------------------------------------------------
+// DDGI's cosine-weighted gather (Majercik et al. 2019; the update Sec. 3.1
+// describes), a measured alternative to the per-sample update: every texel
+// takes all of the probe's rays of the frame, weighted by max(0, c.d) with c
+// its centre direction (depth: that cosine to the 50th power, the DDGI
+// sharpness), and the weighted mean enters the texel with
+// a = max(1/(N+1), 1-h), N counting the frames in which the texel had weight.
+// One wave per probe, its texels in registers; per step of 64 rays the
+// directions (recomputed from the ray index), radiance and tau are staged in
+// LDS and every lane runs over them for each texel it owns.
+__device__ __forceinline__ float pow50(float c) {
+  const float c2 = c * c, c4 = c2 * c2, c8 = c4 * c4, c16 = c8 * c8, c32 = c16 * c16;
+  return c32 * c16 * c2;
+}
+
+template <int RI, int RD, bool HALF>
+__device__ void gather_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
+                                  const uint16_t* tab, const float* alpha) {
+  using S = Store<HALF>;
+  using T = typename S::T;
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
+  static_assert(64 * 32 <= W::kWaveBytes, "ray staging does not fit the wave's LDS");
+  const int lane = threadIdx.x & 63;
+  float4* st_dir = (float4*)wbase;        // (d.x, d.y, d.z, tau)
+  float4* st_rgb = st_dir + 64;           // (r, g, b, -)
+  const FrameParams& fp = *v.fp;
+  const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
+  const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
+  float3 ci[SI], cd[SD];
+  float ai[SI][4], ad[SD][3];
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    ci[s] = k < NI ? texel_centre_dir((uint32_t)k, RI) : make_float3(0.f, 0.f, 0.f);
+    ai[s][0] = ai[s][1] = ai[s][2] = ai[s][3] = 0.f;
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    cd[s] = k < ND ? texel_centre_dir((uint32_t)k, RD) : make_float3(0.f, 0.f, 0.f);
+    ad[s][0] = ad[s][1] = ad[s][2] = 0.f;
+  }
+  const uint32_t off = v.offsets[i];
+  const uint32_t n = v.offsets[i + 1] - off;
+  const float inv_s = 1.0f / v.s_diag;
+  for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
+    const uint32_t m = min(64u, n - c0);
+    if ((uint32_t)lane < m) {
+      const float3 d = sf_direction(c0 + (uint32_t)lane, n, fp.R);
+      const float4 r = v.rec[off + c0 + (uint32_t)lane];
+      st_dir[lane] = make_float4(d.x, d.y, d.z, fminf(r.w * inv_s, v.tau_max));
+      st_rgb[lane] = r;
+    }
+    wave_sync();
+    for (uint32_t j = 0; j < m; ++j) {
+      const float4 dt = st_dir[j];
+      const float4 rgb = st_rgb[j];
+#pragma unroll
+      for (int s = 0; s < SI; ++s) {
+        const float w = fmaxf(0.0f, ci[s].x * dt.x + ci[s].y * dt.y + ci[s].z * dt.z);
+        ai[s][0] += w;
+        ai[s][1] = fmaf(w, rgb.x, ai[s][1]);
+        ai[s][2] = fmaf(w, rgb.y, ai[s][2]);
+        ai[s][3] = fmaf(w, rgb.z, ai[s][3]);
+      }
+#pragma unroll
+      for (int s = 0; s < SD; ++s) {
+        const float w = pow50(fmaxf(0.0f, cd[s].x * dt.x + cd[s].y * dt.y + cd[s].z * dt.z));
+        ad[s][0] += w;
+        ad[s][1] = fmaf(w, dt.w, ad[s][1]);
+        ad[s][2] = fmaf(w, dt.w * dt.w, ad[s][2]);
+      }
+    }
+    wave_sync();
+  }
+  float* stI = (float*)wbase;
+  float* stD = stI + 3 * NI;
+  uint8_t* stN = (uint8_t*)(stD + 2 * ND);
+#pragma unroll
+  for (int s = 0; s < SI; ++s) {
+    const int k = lane + 64 * s;
+    if (k < NI) {
+      const int iy = k / RI, ix = k - iy * RI;
+      const T* p = irr_in + ((iy + 1) * GI + ix + 1) * 3;
+      float V[3] = {S::load(p), S::load(p + 1), S::load(p + 2)};
+      uint32_t N = io.irr_n_in[(size_t)i * NI + k];
+      if (ai[s][0] > 0.0f) {
+        const float inv = 1.0f / ai[s][0];
+        blend_rgb(V, N, make_float4(ai[s][1] * inv, ai[s][2] * inv, ai[s][3] * inv, 0.f), alpha);
+      }
+      stI[3 * k] = V[0];
+      stI[3 * k + 1] = V[1];
+      stI[3 * k + 2] = V[2];
+      stN[k] = (uint8_t)N;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SD; ++s) {
+    const int k = lane + 64 * s;
+    if (k < ND) {
+      const int iy = k / RD, ix = k - iy * RD;
+      const T* p = dep_in + ((iy + 1) * GD + ix + 1) * 2;
+      float V[2] = {S::load(p), S::load(p + 1)};
+      uint32_t N = io.dep_n_in[(size_t)i * ND + k];
+      if (ad[s][0] > 0.0f) {
+        const float inv = 1.0f / ad[s][0], al = alpha[N];
+        V[0] = fmaf(al, ad[s][1] * inv - V[0], V[0]);
+        V[1] = fmaf(al, ad[s][2] * inv - V[1], V[1]);
+        N = min(N + 1u, 255u);
+      }
+      stD[2 * k] = V[0];
+      stD[2 * k + 1] = V[1];
+      stN[NI + k] = (uint8_t)N;
+    }
+  }
+  wave_sync();
+  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, tab, lane, 64);
+  wave_sync();
+}
+
+template <int RI, int RD, bool HALF>
+__global__ __launch_bounds__(256) void blend_gather_kernel(VolumeView v, BlendIO io) {
+  using W = WaveTile<RI, RD>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
+  float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
+  build_fold_tables<RI, RD>(tab);
+  for (int k = threadIdx.x; k < 256; k += blockDim.x) alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
+  __syncthreads();
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
+  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
+    gather_probe_wave<RI, RD, HALF>(v, io, v.order[q], wbase, tab, alpha);
+}
+
+// ---------------------------------------------------------------------------
 // Packed 32-bit texels: the same wave-per-probe walk, with each interior
 // texel's word in its owner lane's registers. A sample decodes the word,
 // applies the moving average in binary32 and re-encodes it (the paper's
@@ -695,10 +831,14 @@ size_t blend_lds_bytes(const VolumeView& v, int chunk) {
 
 template <int RI, int RD>
 static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int grid,
-                         bool chain) {
+                         bool chain, bool gather) {
   using W = WaveTile<RI, RD>;
   const size_t lds = W::kBlockBytes;
-  if (chain && storage == ADGI_FP16)
+  if (gather && storage == ADGI_FP16)
+    hipLaunchKernelGGL((blend_gather_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
+  else if (gather)
+    hipLaunchKernelGGL((blend_gather_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
+  else if (chain && storage == ADGI_FP16)
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, true>), dim3(grid), dim3(256), lds, s, v, io);
   else if (chain)
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, true>), dim3(grid), dim3(256), lds, s, v, io);
@@ -711,10 +851,10 @@ static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, 
 }
 
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
-                        int grid, bool chain) {
-  if (chunk == 0 || storage == ADGI_PACKED || chain) {  // wave-per-probe kernel, most-rays-first order
-    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, storage, grid, chain);
-    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, storage, grid, chain);
+                        int grid, bool chain, bool gather) {
+  if (chunk == 0 || storage == ADGI_PACKED || chain || gather) {  // wave-per-probe kernels, most-rays-first order
+    if (v.irr_res == 8 && v.dep_res == 16) launch_sched<6, 14>(v, io, s, storage, grid, chain, gather);
+    else if (v.irr_res == 16 && v.dep_res == 16) launch_sched<14, 14>(v, io, s, storage, grid, chain, gather);
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }

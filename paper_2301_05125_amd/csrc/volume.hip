@@ -287,8 +287,9 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
   if ((e = mark(5)) != hipSuccess) return e;
   if (count_work) return hipSuccess;
   BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
-  if ((e = launch_blend(v, io, s, vol->desc.storage, chain ? 0 : t.blend_chunk,
-                        vol->num_cus * t.blend_blocks_per_cu, chain)) != hipSuccess)
+  const bool gather = vol->desc.blend_mode == ADGI_BLEND_GATHER;
+  if ((e = launch_blend(v, io, s, vol->desc.storage, chain || gather ? 0 : t.blend_chunk,
+                        vol->num_cus * t.blend_blocks_per_cu, chain, gather)) != hipSuccess)
     return e;
   return mark(6);
 }
@@ -494,6 +495,11 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
     return fail(ADGI_ERR_INVALID_ARG, "chains need ADGI_FP32 or ADGI_FP16 storage");
   if (d->max_chains > 0 && !((d->irr_res == 8 && d->depth_res == 16) || (d->irr_res == 16 && d->depth_res == 16)))
     return fail(ADGI_ERR_INVALID_ARG, "chains need tiles 8/16 or 16/16");
+  if (d->blend_mode != ADGI_BLEND_SAMPLE && d->blend_mode != ADGI_BLEND_GATHER)
+    return fail(ADGI_ERR_INVALID_ARG, "blend_mode must be ADGI_BLEND_SAMPLE or ADGI_BLEND_GATHER");
+  if (d->blend_mode == ADGI_BLEND_GATHER &&
+      (d->storage == ADGI_PACKED || !((d->irr_res == 8 && d->depth_res == 16) || (d->irr_res == 16 && d->depth_res == 16))))
+    return fail(ADGI_ERR_INVALID_ARG, "ADGI_BLEND_GATHER needs FP32 or FP16 storage and tiles 8/16 or 16/16");
   if (d->max_chains > 0 && d->max_rays_per_frame < 2)
     return fail(ADGI_ERR_INVALID_ARG, "chains need max_rays_per_frame >= 2");
   if (alloc && (!alloc->alloc || !alloc->free))
@@ -634,6 +640,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.tau_max = d->tau_max;
   v.max_rays = (uint32_t)R;
   if (blend_wave_supported(v)) vol->tun.blend_chunk = 0;
+  if (d->blend_mode == ADGI_BLEND_GATHER) vol->tun.blend_chunk = 0;
   *out = vol;
   return ADGI_OK;
 }
@@ -855,6 +862,8 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   int64_t samples = 0;
   if (mode == ADGI_MODE_CHAIN) {
     if (vol->desc.max_chains < 1) return fail(ADGI_ERR_INVALID_ARG, "the volume was created with max_chains = 0");
+    if (vol->desc.blend_mode != ADGI_BLEND_SAMPLE)
+      return fail(ADGI_ERR_INVALID_ARG, "chain frames need ADGI_BLEND_SAMPLE");
     if (p->chain_count < 1 || p->chain_count > vol->desc.max_chains)
       return fail(ADGI_ERR_INVALID_ARG, "chain_count must be in [1, %d]", vol->desc.max_chains);
     if (p->chain_steps < 2 || p->chain_steps > ADGI_CHAIN_MAX_STEPS)
@@ -1150,6 +1159,8 @@ adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t) {
     return fail(ADGI_ERR_INVALID_ARG, "blend_chunk 0 (wave kernel) needs tiles 8/16 or 16/16");
   if (t->blend_chunk != 0 && vol->desc.storage == ADGI_PACKED)
     return fail(ADGI_ERR_INVALID_ARG, "ADGI_PACKED blends with the wave kernel (blend_chunk 0)");
+  if (t->blend_chunk != 0 && vol->desc.blend_mode == ADGI_BLEND_GATHER)
+    return fail(ADGI_ERR_INVALID_ARG, "ADGI_BLEND_GATHER blends with the wave kernel (blend_chunk 0)");
   size_t lds = t->blend_chunk ? blend_lds_bytes(vol->v, t->blend_chunk) : 0;
   if (lds > 65536) return fail(ADGI_ERR_INVALID_ARG, "blend_chunk needs %zu bytes of LDS", lds);
   if (trace_lds_bytes(t->trace_block) > 65536)
@@ -1383,13 +1394,13 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     if (err != hipSuccess) break;
     if (bc.chunk == 0 && !blend_wave_supported(vol->v)) continue;
     if (bc.chunk != 0 && blend_lds_bytes(vol->v, bc.chunk) > 65536) continue;
-    if (bc.chunk != 0 && vol->desc.storage == ADGI_PACKED) continue;
+    if (bc.chunk != 0 && (vol->desc.storage == ADGI_PACKED || vol->desc.blend_mode == ADGI_BLEND_GATHER)) continue;
     BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, so_irr, so_dep, (uint8_t*)so_in, (uint8_t*)so_dn};
     float bm = INFINITY;
     for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
       if ((err = hipEventRecord(vol->ev_t0, s)) != hipSuccess) break;
-      if ((err = launch_blend(vol->v, io, s, vol->desc.storage, bc.chunk,
-                              vol->num_cus * bc.bpc)) != hipSuccess)
+      if ((err = launch_blend(vol->v, io, s, vol->desc.storage, bc.chunk, vol->num_cus * bc.bpc, false,
+                              vol->desc.blend_mode == ADGI_BLEND_GATHER)) != hipSuccess)
         break;
       if ((err = hipEventRecord(vol->ev_t1, s)) != hipSuccess) break;
       if ((err = hipEventSynchronize(vol->ev_t1)) != hipSuccess) break;

@@ -62,19 +62,20 @@ def gpu_scene_update(vol, scene, frame):
 def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget: int = 0,
                  n_min: int = 8, n_max: int = 2048, probes=None, storage=adgi.ADGI_FP32,
                  seed: int = 0x5EED, max_rays=None, tuning=None, check_rays: bool = True,
-                 use_bvh: bool = True, fp64_twin: bool = False) -> dict:
+                 use_bvh: bool = True, fp64_twin: bool = False, gather: bool = False) -> dict:
     """``fp64_twin`` also runs an oracle that keeps its texels in FP64 (no
     binary16 rounding at the frame store), fed the same tie decisions, and
     returns per-texel error distributions against it."""
     P = scene.num_probes
     if max_rays is None:
         max_rays = max(budget, P * n_uniform, 1)
-    vol = adgi.volume_for_scene(scene, storage=storage, max_rays=max_rays, seed=seed, debug=True)
+    vol = adgi.volume_for_scene(scene, storage=storage, max_rays=max_rays, seed=seed, debug=True,
+                                blend_mode=adgi.ADGI_BLEND_GATHER if gather else adgi.ADGI_BLEND_SAMPLE)
     if tuning:
         vol.set_tuning(**tuning)
     fp16 = storage == adgi.ADGI_FP16
     packed = storage == adgi.ADGI_PACKED
-    ora = oracle.OracleVolume(scene, seed=seed, fp16=fp16, probes=probes, use_bvh=use_bvh)
+    ora = oracle.OracleVolume(scene, seed=seed, fp16=fp16, probes=probes, use_bvh=use_bvh, gather=gather)
     sel = ora.probes
     ri, rd = vol.desc.irr_res - 2, vol.desc.depth_res - 2
     if packed:
@@ -104,6 +105,8 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
         hints = {"hit_tri": rb["hit_tri"], "shadow_bits": rb["shadow_bits"],
                  "irr_bin": rb["irr_bin"], "depth_bin": rb["depth_bin"],
                  "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
+        if gather:  # the gather blend takes every texel; no bin decisions
+            del hints["irr_bin"], hints["depth_bin"]
         out = ora.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
                          n_uniform=n_uniform, hints=hints, keep_rays=check_rays)
         if twin is not None:

@@ -326,3 +326,27 @@ def test_dynamic_chain_capacity_check():
         vol.update_chains(0, 16, 8, 1, dyn_chains=65, dyn_steps=16, dyn_burn_in=1)
     assert e.value.status == adgi.ADGI_ERR_INVALID_ARG
     vol.destroy_volume()
+
+
+@pytest.mark.parametrize("tuning", [{"use_graph": 0}, {"blend_blocks_per_cu": 4}, {"bvh_width": 4}])
+def test_gather_launch_shape_does_not_change_results(tuning):
+    sc = _small_field()
+
+    def run(t):
+        vol = adgi.volume_for_scene(sc, max_rays=sc.num_probes * 40, seed=3, blend_mode=adgi.ADGI_BLEND_GATHER)
+        return _run(sc, 4, True, tuning=t, budget=sc.num_probes * 40, vol=vol)
+
+    _same(run(None), run(tuning))
+
+
+def test_gather_rejected_where_unsupported():
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 212, lattice=16, dims=(8, 2, 8), n_lights=1, frames=2)
+    with pytest.raises(adgi.AdgiError):
+        adgi.volume_for_scene(sc, max_rays=4096, storage=adgi.ADGI_PACKED, blend_mode=adgi.ADGI_BLEND_GATHER)
+    vol = adgi.volume_for_scene(sc, max_rays=4096, blend_mode=adgi.ADGI_BLEND_GATHER, max_chains=16)
+    with pytest.raises(adgi.AdgiError):
+        vol.update_chains(0, 16, 8, 1)
+    with pytest.raises(adgi.AdgiError):
+        vol.set_tuning(blend_chunk=128)
+    vol.update_probes(0, adaptive=False, n_uniform=16, sync=True)
+    vol.destroy_volume()
