@@ -283,6 +283,7 @@ def run_quality(adgi, torch, sc, cfg, tuning, frames=40, every=8, ref_rays=2304)
     B = cfg["budget"]
     contenders = {
         "adaptive": dict(kind="adaptive"),
+        "adaptive_gather": dict(kind="adaptive", gather=True),
         "uniform": dict(kind="uniform", n=B // P),
         "chains": dict(kind="chains", chains=B // 128, steps=80, burn_in=15),
     }
@@ -291,8 +292,12 @@ def run_quality(adgi, torch, sc, cfg, tuning, frames=40, every=8, ref_rays=2304)
         if c["kind"] == "chains":
             v = adgi.volume_for_scene(sc, max_rays=B + P * 64, seed=11, max_chains=c["chains"])
         else:
-            v = adgi.volume_for_scene(sc, max_rays=max(B, P * c.get("n", 0)), seed=11)
-        v.set_tuning(**tuning)
+            v = adgi.volume_for_scene(sc, max_rays=max(B, P * c.get("n", 0)), seed=11,
+                                      blend_mode=adgi.ADGI_BLEND_GATHER if c.get("gather") else adgi.ADGI_BLEND_SAMPLE)
+        t = dict(tuning)
+        if c.get("gather"):
+            t["blend_chunk"] = 0
+        v.set_tuning(**t)
         vols[name] = v
     ref = adgi.volume_for_scene(sc, max_rays=P * ref_rays, seed=12, hysteresis=0.99999)
     ref2 = adgi.volume_for_scene(sc, max_rays=P * ref_rays, seed=13, hysteresis=0.99999)
@@ -631,6 +636,27 @@ def main():
         "scene_build_s": build_s,
     }
     vol.destroy_volume()
+    # DDGI's cosine-weighted gather in place of the per-sample update, same frames
+    if not args.skip_uniform:
+        vg = adgi.volume_for_scene(sc, storage=storage if args.storage != "packed" else adgi.ADGI_FP32,
+                                   max_rays=max_rays, seed=11, blend_mode=adgi.ADGI_BLEND_GATHER)
+        tg = dict(tuning)
+        tg["blend_chunk"] = 0
+        vg.set_tuning(**tg)
+        rg = run_mode(vg, sc, adgi, torch, 0, args.steps, args.warmup, min(args.latency_frames, 20), **ad)
+        stages_g, _ = stage_times(vg, sc, adgi, rg["frames_end"], 5, **ad)
+        vg.destroy_volume()
+        # per ray: 36 irradiance texels x (3-term dot, max, 4 fma) and 196 depth
+        # texels x (dot, max, 7 multiplies for the 50th power, 3 fma) as written
+        gops = R * (36 * 9 + 196 * 17)
+        out["gather_blend"] = {
+            "rays_per_s": rg["rays_per_frame"] * args.steps / rg["seconds"],
+            "ms_per_step": rg["seconds"] / args.steps * 1e3,
+            "p50_ms": pct(rg["host_ms"], 50), "p99_ms": pct(rg["host_ms"], 99),
+            "blend_ms": stages_g[5], "per_sample_blend_ms": blend_ms,
+            "roofline": {"bound": "alu", "achieved": gops / (stages_g[5] * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
+                         "unit": "TFLOP/s", "frac": gops / (stages_g[5] * 1e-3) / 1e12 / VALU_PEAK_TOPS}}
+        print("[bench] gather blend done", file=sys.stderr, flush=True)
     if args.quality:
         out["quality"] = run_quality(adgi, torch, sc, cfg, tuning)
         print("[bench] quality done", file=sys.stderr, flush=True)
