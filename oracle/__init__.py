@@ -150,6 +150,7 @@ def lib():
         L.orc_texel_centre_dir.argtypes = [C.c_int32, C.c_int32, P]
         L.orc_dyn_ray_count.restype = C.c_int32
         L.orc_dyn_ray_count.argtypes = [C.c_int32, C.c_int32, C.c_uint32]
+        L.orc_query_irradiance.argtypes = [P, P, C.c_int32, P, C.c_int32, P, P, P]
         L.orc_dyn_probes_frame.argtypes = [P, P, C.c_int32, P, P, P, P, C.c_int32, C.c_int32, C.c_double,
                                            C.c_double, C.c_int32, P, P, P, P, P, P, P]
         L.orc_chain_dir.restype = None
@@ -386,6 +387,21 @@ def dyn_ray_counts(grid, mark, irr_res: int, depth_res: int) -> np.ndarray:
     per_mask = np.array([lib().orc_dyn_ray_count(irr_res, depth_res, m) for m in range(256)], np.int64)
     px = np.array([lib().orc_proxy_of_probe(C.byref(grid), i) for i in range(P)], np.int64)
     return per_mask[bits[px]]
+
+
+def query_irradiance(grid, irr_tiles, dep_tiles, points, normals) -> np.ndarray:
+    """Irradiance [K][3] at points [K][3] with normals [K][3] from full tiles."""
+    irr = np.ascontiguousarray(irr_tiles, np.float64)
+    dep = np.ascontiguousarray(dep_tiles, np.float64)
+    pts = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(normals, np.float64).reshape(-1, 3)
+    out = np.zeros((pts.shape[0], 3))
+    row = np.zeros(3)
+    for k in range(pts.shape[0]):
+        lib().orc_query_irradiance(C.byref(grid), _p(irr), irr.shape[1], _p(dep), dep.shape[1],
+                                   _p(pts[k]), _p(nrm[k]), _p(row))
+        out[k] = row
+    return out
 
 
 def chain_order(sample_probe: np.ndarray, P: int):

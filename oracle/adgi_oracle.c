@@ -1804,3 +1804,92 @@ void orc_set_threads(int32_t n) {
   (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------ query */
+
+/* Bilinear sample of a full tile (interior r x r with a one-texel border,
+ * c channels) at the direction d: interior texel i spans [i, i+1) of
+ * f = (uv + 1) / 2 * r and holds its value at i + 1/2; the border supplies
+ * the neighbours across the map's edges. */
+static void tile_bilinear(const double* tile, int32_t r, int32_t c, const double d[3], double* out) {
+  double uv[2];
+  orc_oct_encode(d, uv);
+  const double fx = (uv[0] + 1.0) * 0.5 * r - 0.5, fy = (uv[1] + 1.0) * 0.5 * r - 0.5;
+  double x0 = floor(fx), y0 = floor(fy);
+  if (x0 < -1.0) x0 = -1.0;
+  if (x0 > r - 1) x0 = r - 1;
+  if (y0 < -1.0) y0 = -1.0;
+  if (y0 > r - 1) y0 = r - 1;
+  const double ax = fx - x0, ay = fy - y0;
+  const int32_t X = (int32_t)x0 + 1, Y = (int32_t)y0 + 1, g = r + 2;
+  for (int32_t k = 0; k < c; ++k) {
+    const double v00 = tile[(Y * g + X) * c + k], v01 = tile[(Y * g + X + 1) * c + k];
+    const double v10 = tile[((Y + 1) * g + X) * c + k], v11 = tile[((Y + 1) * g + X + 1) * c + k];
+    out[k] = (1.0 - ay) * ((1.0 - ax) * v00 + ax * v01) + ay * ((1.0 - ax) * v10 + ax * v11);
+  }
+}
+
+void orc_query_irradiance(const orc_grid* g, const double* irr_tiles, int32_t irr_res, const double* dep_tiles,
+                          int32_t dep_res, const double x[3], const double n[3], double rgb[3]) {
+  const int32_t ri = irr_res - 2, rd = dep_res - 2;
+  int32_t base[3];
+  double al[3];
+  for (int a = 0; a < 3; ++a) {
+    if (g->dims[a] == 1) {
+      base[a] = 0;
+      al[a] = 0.0;
+      continue;
+    }
+    const double f = (x[a] - g->origin[a]) / g->spacing[a];
+    double b = floor(f);
+    if (b < 0.0) b = 0.0;
+    if (b > g->dims[a] - 2) b = g->dims[a] - 2;
+    base[a] = (int32_t)b;
+    double t = f - b;
+    al[a] = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  }
+  double sum[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
+  for (int32_t corner = 0; corner < 8; ++corner) {
+    int32_t idx[3];
+    double tri = 1.0;
+    int skip = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int32_t o = (corner >> a) & 1;
+      if (o && g->dims[a] == 1) skip = 1;
+      idx[a] = base[a] + o;
+      tri *= o ? al[a] : 1.0 - al[a];
+    }
+    if (skip) continue;
+    const int32_t pr = idx[0] + g->dims[0] * (idx[1] + g->dims[1] * idx[2]);
+    double p[3];
+    orc_probe_pos(g, pr, p);
+    double dir[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
+    const double len = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double w = 1.0;
+    if (len > 0.0) {
+      for (int a = 0; a < 3; ++a) dir[a] /= len;
+      /* smooth backface term: probes behind the surface count less */
+      const double c = (dir[0] * n[0] + dir[1] * n[1] + dir[2] * n[2] + 1.0) * 0.5;
+      w *= c * c + 0.2;
+      /* visibility: the probe's depth moments towards the point, one-sided
+       * Chebyshev bound on the probability that the point is unoccluded */
+      const double back[3] = {-dir[0], -dir[1], -dir[2]};
+      double m[2];
+      tile_bilinear(dep_tiles + (size_t)pr * dep_res * dep_res * 2, rd, 2, back, m);
+      const double rr = len / g->s;
+      if (rr > m[0]) {
+        const double var = fabs(m[1] - m[0] * m[0]);
+        const double dd = rr - m[0];
+        const double cheb = var / (var + dd * dd);
+        w *= cheb * cheb * cheb;
+      }
+    }
+    if (w < 1e-6) w = 1e-6;
+    w *= tri;
+    double e[3];
+    tile_bilinear(irr_tiles + (size_t)pr * irr_res * irr_res * 3, ri, 3, n, e);
+    for (int k = 0; k < 3; ++k) sum[k] += w * e[k];
+    wsum += w;
+  }
+  for (int k = 0; k < 3; ++k) rgb[k] = wsum > 0.0 ? sum[k] / wsum : 0.0;
+}

@@ -291,6 +291,19 @@ void orc_dyn_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, 
                           const uint8_t* hint_shadow, double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
                           orc_counts* counts);
 
+/* ---- irradiance query (the deferred-shading lookup of Sec. 3.1, DDGI) -----
+ * Irradiance at a point x with unit normal n from the 8 probes of the grid
+ * cell around x (clamped to the grid; an axis with one probe uses one layer):
+ * weight of a probe = trilinear weight x (((dir.n + 1)/2)^2 + 0.2) (dir from x
+ * to the probe) x Chebyshev visibility (if r = |x - p|/s exceeds the mean tau
+ * of the probe's depth moments towards x: (var / (var + (r - mean)^2))^3,
+ * var = |mean2 - mean^2|), floored at 1e-6 before the trilinear factor; the
+ * result is the weighted mean of the probes' irradiance in direction n.
+ * Texels are read bilinearly from full tiles (with borders): irr_tiles
+ * [P][irr_res][irr_res][3], dep_tiles [P][dep_res][dep_res][2]. */
+void orc_query_irradiance(const orc_grid* g, const double* irr_tiles, int32_t irr_res, const double* dep_tiles,
+                          int32_t dep_res, const double x[3], const double n[3], double rgb[3]);
+
 int32_t orc_num_threads(void);
 /* Threads for the following OpenMP regions (timing only). */
 void orc_set_threads(int32_t n);

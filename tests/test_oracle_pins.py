@@ -1139,3 +1139,75 @@ def test_gather_step_rule_counts_frames():
     fresh.update(1, adaptive=False, n_uniform=512)
     assert np.allclose(ora.irr, first + 0.5 * (fresh.irr - first), rtol=0, atol=1e-12)
     assert np.all(ora.irr_n == 2)
+
+
+# ---- irradiance query (the 8-probe lookup of Sec. 3.1, DDGI's weights)
+
+def _query_grid(dims, spacing=1.0):
+    return oracle.make_grid(np.zeros(3, np.float32), np.full(3, spacing, np.float32), np.asarray(dims, np.int32))
+
+
+def _tiles(P, value_irr, value_dep):
+    irr = np.broadcast_to(np.asarray(value_irr, np.float64), (P, 8, 8, 3)).copy()
+    dep = np.broadcast_to(np.asarray(value_dep, np.float64), (P, 16, 16, 2)).copy()
+    return irr, dep
+
+
+def test_query_constant_field():
+    """Every probe holding the same irradiance c gives c anywhere, for any
+    normal and any visibility (the weights are normalised)."""
+    g = _query_grid((3, 2, 4))
+    rng = np.random.default_rng(1)
+    irr, dep = _tiles(24, [0.3, 0.5, 0.7], [0.2, 0.05])
+    pts = rng.uniform([-0.5, -0.5, -0.5], [2.5, 1.5, 3.5], size=(50, 3))
+    nrm = rng.normal(size=(50, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    out = oracle.query_irradiance(g, irr, dep, pts, nrm)
+    assert np.allclose(out, [0.3, 0.5, 0.7], rtol=0, atol=1e-12)
+
+
+def test_query_linear_between_two_visible_probes():
+    """Two probes along x, normal along y (both probes at the same backface
+    angle), no occluder: the query is the linear interpolation of the two
+    probes' irradiance in direction n."""
+    g = _query_grid((2, 1, 1))
+    irr, dep = _tiles(2, [0.0, 0.0, 0.0], [50.0, 2500.0])
+    irr[0] = [0.2, 0.4, 0.6]
+    irr[1] = [1.0, 0.1, 0.3]
+    for a in (0.0, 0.25, 0.6, 1.0):
+        out = oracle.query_irradiance(g, irr, dep, [[a, 0.0, 0.0]], [[0.0, 1.0, 0.0]])[0]
+        assert np.allclose(out, (1 - a) * irr[0, 0, 0] + a * irr[1, 0, 0], rtol=0, atol=1e-12), a
+
+
+def test_query_chebyshev_hides_an_occluded_probe():
+    """Probe 0 saw a wall at distance 0.1 s in every direction (variance 0):
+    a point halfway to probe 1 is occluded from probe 0, so the query returns
+    probe 1's irradiance up to the 1e-6 weight floor."""
+    g = _query_grid((2, 1, 1))
+    irr, dep = _tiles(2, [0.0, 0.0, 0.0], [50.0, 2500.0])
+    irr[0] = [5.0, 5.0, 5.0]
+    irr[1] = [0.3, 0.2, 0.1]
+    dep[0] = [0.1, 0.01]
+    out = oracle.query_irradiance(g, irr, dep, [[0.5, 0.0, 0.0]], [[0.0, 0.0, 1.0]])[0]
+    assert np.allclose(out, [0.3, 0.2, 0.1], rtol=0, atol=5e-5 * 5.0)
+    # and without the wall the first probe counts in full again
+    dep[0] = [50.0, 2500.0]
+    out = oracle.query_irradiance(g, irr, dep, [[0.5, 0.0, 0.0]], [[0.0, 0.0, 1.0]])[0]
+    assert np.allclose(out, 0.5 * (irr[0, 0, 0] + irr[1, 0, 0]), rtol=0, atol=1e-12)
+
+
+def test_query_at_a_probe_reads_its_texel():
+    """Just off a probe along n, with n through the centre of interior texel
+    k, the query returns that probe's texel k (bilinear at a texel centre)."""
+    g = _query_grid((3, 3, 3))
+    rng = np.random.default_rng(6)
+    ri = 6
+    interior = rng.uniform(0.1, 1.0, size=(27, ri * ri * 3))
+    irr = np.stack([oracle.fold_tile(t, ri, 3).reshape(8, 8, 3) for t in interior])
+    dep = np.broadcast_to(np.asarray([50.0, 2500.0]), (27, 16, 16, 2)).copy()
+    p = 1 + 3 * (1 + 3 * 1)  # probe (1, 1, 1) at (1, 1, 1)
+    for k in (0, 7, 14, 21, 35):
+        n = oracle.texel_centre_dir(ri, k)
+        x = np.array([1.0, 1.0, 1.0]) + 1e-9 * n
+        out = oracle.query_irradiance(g, irr, dep, [x], [n])[0]
+        assert np.allclose(out, interior[p, 3 * k:3 * k + 3], rtol=0, atol=1e-7), k
