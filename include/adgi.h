@@ -287,6 +287,22 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* param
 /* Wait for the volume's work and copy state into caller buffers. */
 adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out);
 
+/* Irradiance at shading points (the deferred-shading lookup of Sec. 3.1, with
+ * DDGI's weights): the 8 probes of the grid cell around x (clamped to the
+ * grid; an axis with one probe uses its one layer), each weighted by its
+ * trilinear weight x (((dir.n + 1)/2)^2 + 0.2) (dir: unit vector from x to the
+ * probe, n the unit normal) x (var / (var + (r - m)^2))^3 when
+ * r = |x - p|/s exceeds the mean m of the probe's depth moments (m, m2) read
+ * towards x (var = |m2 - m^2|), the product floored at 1e-6 before the
+ * trilinear factor; out = the weighted mean of the probes' irradiance read
+ * in direction n. Texels are read bilinearly across the tiles' borders.
+ * points, normals, out_rgb: device memory, [count][3] FP32, owned by the
+ * caller and not retained. Enqueued after the volume's frames (and the
+ * caller's stream work); asynchronous like a frame. ADGI_FP32 and ADGI_FP16
+ * storage (ADGI_ERR_INVALID_ARG for ADGI_PACKED). */
+adgi_status adgi_query_irradiance(adgi_volume* vol, const float* points, const float* normals, int64_t count,
+                                  float* out_rgb);
+
 /* Complete pending work and release every device allocation. NULL is a no-op. */
 void adgi_destroy_volume(adgi_volume* vol);
 

@@ -435,6 +435,18 @@ class Volume:
         out["num_rays"] = int(rb.num_rays)
         return out
 
+    def query_irradiance(self, points, normals):
+        """Irradiance [K][3] at points [K][3] with unit normals [K][3]
+        (torch CUDA float32 tensors, or anything torch.as_tensor takes)."""
+        import torch
+        pts = torch.as_tensor(points, dtype=torch.float32, device="cuda").reshape(-1, 3).contiguous()
+        nrm = torch.as_tensor(normals, dtype=torch.float32, device="cuda").reshape(-1, 3).contiguous()
+        out = torch.empty_like(pts)
+        _check(lib().adgi_query_irradiance(self.h, C.c_void_p(pts.data_ptr()), C.c_void_p(nrm.data_ptr()),
+                                           C.c_int64(pts.shape[0]), C.c_void_p(out.data_ptr())))
+        torch.cuda.current_stream().synchronize()
+        return out
+
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(lib().adgi_get_tuning(self.h, C.byref(t)))

@@ -40,6 +40,11 @@ hipError_t launch_dyn_chains(const VolumeView& v, int chains, int lanes, void* s
 // frame (the dynamic chains read them on even frames too)
 hipError_t launch_box_sums(const VolumeView& v, hipStream_t s);
 
+// query.hip: irradiance at count points (device [count][3] points, normals,
+// out) from the bordered tiles
+hipError_t launch_query(const VolumeView& v, bool fp16, const void* irr, const void* dep, const float* pts,
+                        const float* nrm, float* out, int64_t count, hipStream_t s);
+
 // detect.hip: trigger update and the separable 5x5x5 box sum -> scores
 hipError_t launch_frame_begin(const VolumeView& v, hipStream_t s);
 hipError_t launch_detect(const VolumeView& v, hipStream_t s);

@@ -1145,6 +1145,21 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
   return ADGI_OK;
 }
 
+adgi_status adgi_query_irradiance(adgi_volume* vol, const float* points, const float* normals, int64_t count,
+                                  float* out_rgb) {
+  if (!vol) return fail(ADGI_ERR_INVALID_ARG, "volume must not be NULL");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (count < 0) return fail(ADGI_ERR_INVALID_ARG, "count must be >= 0");
+  if (count > 0 && (!points || !normals || !out_rgb)) return fail(ADGI_ERR_INVALID_ARG, "NULL array");
+  if (vol->desc.storage == ADGI_PACKED) return fail(ADGI_ERR_INVALID_ARG, "the query reads FP32 or FP16 texels");
+  if (count == 0) return ADGI_OK;
+  adgi_status st = order_after_user(vol);
+  if (st != ADGI_OK) return st;
+  HIP_TRY(vol, launch_query(vol->v, vol->desc.storage == ADGI_FP16, vol->irr, vol->dep, points, normals, out_rgb,
+                            count, vol->stream));
+  return order_user_after(vol);
+}
+
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out) {
   if (!vol || !out) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
   *out = vol->tun;

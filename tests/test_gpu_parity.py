@@ -281,3 +281,44 @@ def test_gather_fp16_storage():
                        gather=True)
     assert res["mismatches"] == 0 and res["count_mismatch"] == 0, res
     assert res["max_rel_irr"] <= 2e-3 and res["max_rel_depth"] <= 2e-3, res
+
+
+# ---- irradiance query
+
+def _query_case(sc, storage, seed, frames=4, count=4096):
+    import paper_2301_05125_amd as adgi
+    import oracle
+    vol = adgi.volume_for_scene(sc, storage=storage, max_rays=sc.num_probes * 64, seed=seed)
+    for f in range(frames):
+        vol.update_probes(f, adaptive=False, n_uniform=64, sync=True)
+    rb = vol.read_probes()
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(sc.grid_origin, np.float64) - 0.3 * np.asarray(sc.grid_spacing, np.float64)
+    hi = lo + (np.asarray(sc.grid_dims, np.float64) - 1 + 0.6) * np.asarray(sc.grid_spacing, np.float64)
+    pts = rng.uniform(lo, hi, size=(count, 3)).astype(np.float32)
+    nrm = rng.normal(size=(count, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    got = vol.query_irradiance(pts, nrm).cpu().numpy().astype(np.float64)
+    vol.destroy_volume()
+    grid = oracle.make_grid(sc.grid_origin, sc.grid_spacing, sc.grid_dims)
+    want = oracle.query_irradiance(grid, rb["irradiance"].astype(np.float64), rb["depth"].astype(np.float64),
+                                   pts.astype(np.float64), nrm.astype(np.float64))
+    floor = 1e-3 * np.abs(want).max()
+    return float((np.abs(got - want) / np.maximum(np.abs(want), floor)).max()), float(np.abs(want).max())
+
+
+def test_query_irradiance_cornell_fp32():
+    """The GPU query against the oracle's query of the same texels: 4096
+    random points (also just outside the grid) with random normals."""
+    import paper_2301_05125_amd as adgi
+    err, peak = _query_case(scenes.cornell(), adgi.ADGI_FP32, 21)
+    print(err, peak)
+    assert peak > 0 and err <= 1e-4
+
+
+def test_query_irradiance_box_field_fp16():
+    import paper_2301_05125_amd as adgi
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 303, lattice=24, dims=(8, 3, 8), n_lights=2, frames=4)
+    err, peak = _query_case(sc, adgi.ADGI_FP16, 22)
+    print(err, peak)
+    assert peak > 0 and err <= 1e-4
