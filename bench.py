@@ -24,8 +24,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "probe rays/sec + p50/p99 probe-update ms/frame, adaptive vs uniform, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate of one MI355X without packed FP32: 256 CUs x 64 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# FP32 vector peak of one MI355X in lane operations (an FMA is one operation):
+# 157.3 TFLOP/s counts an FMA as two flops, i.e. 256 CUs x 128 lanes x 2.4 GHz.
+# Non-packed VOP2 code reaches most of it (v_add_f32 with independent chains
+# sustains 68 T ops/s), so the 64-lane-per-clock figure is not the ceiling.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # FP32 operations of the two traversal tests as written (adgi_device.hpp):
 # slab test of one child box = 6 fma + 6 min/max + 6 min/max + 1 compare = 19,
 # a BVH2 node visit tests two child boxes, a BVH4 visit four; Moller-Trumbore
@@ -646,9 +649,10 @@ def main():
         rg = run_mode(vg, sc, adgi, torch, 0, args.steps, args.warmup, min(args.latency_frames, 20), **ad)
         stages_g, _ = stage_times(vg, sc, adgi, rg["frames_end"], 5, **ad)
         vg.destroy_volume()
-        # per ray: 36 irradiance texels x (3-term dot, max, 4 fma) and 196 depth
-        # texels x (dot, max, 7 multiplies for the 50th power, 3 fma) as written
-        gops = R * (36 * 9 + 196 * 17)
+        # per ray: 36 irradiance texels x 8 ops (dot 3, max 1, weight sum 1,
+        # 3 fma) and 196 depth texels x 14 ops (dot 3, max 1, 7 multiplies for
+        # the 50th power, weight sum 1, 2 fma), plus tau^2 once per ray
+        gops = R * (36 * 8 + 196 * 14 + 1)
         out["gather_blend"] = {
             "rays_per_s": rg["rays_per_frame"] * args.steps / rg["seconds"],
             "ms_per_step": rg["seconds"] / args.steps * 1e3,
