@@ -172,12 +172,12 @@ def stage_times(vol, sc, adgi, frame0, frames, **p):
     kernels on the volume's own stream (the stream the kernels run on)."""
     tun = vol.get_tuning()
     vol.set_tuning(use_graph=0)
-    acc = [0.0] * 6
+    acc = [0.0] * 8
     f = frame0
     for _ in range(frames):
         step_scene(vol, sc, f, adgi)
         st = vol.update_probes(f, sync=True, **p)
-        for k in range(6):
+        for k in range(8):
             acc[k] += st["ms_stage"][k]
         f += 1
     vol.set_tuning(use_graph=tun["use_graph"])
@@ -583,36 +583,39 @@ def main():
     value = R * args.steps / res_a["seconds"]
     ms_step = res_a["seconds"] / args.steps * 1e3
     trace_ms, blend_ms = stages_a[4], stages_a[5]
-    ops = tw["box_tests"] * OPS_PER_BOX + tw["tri_tests"] * OPS_PER_TRI
-    trace_tops = ops / (trace_ms * 1e-3) / 1e12
     bbytes = blend_bytes(P, R, args.storage)
     blend_gbs = bbytes / (blend_ms * 1e-3) / 1e9
     h_trace = source_hash("trace.hip", "adgi_device.hpp", "adgi_layout.hpp", "bvh_build.cpp")
     h_blend = source_hash("blend.hip", "adgi_device.hpp")
-    prof_trace, prof_blend = read_profile("trace_boxfield", h_trace), read_profile("blend_boxfield", h_blend)
-    # the counters belong to one traversal variant (BVH2: trace_kernel<0, false, false>)
-    w4 = tuning.get("bvh_width") == 4 and prof_trace.get("kernel_name", "").endswith("true>(adgi::VolumeView, int)")
-    w2 = tuning.get("bvh_width") != 4 and prof_trace.get("kernel_name", "").endswith("false>(adgi::VolumeView, int)")
-    if not (w4 or w2):
-        prof_trace = {}
-    nrays = max(tw["primary_rays"] + tw["shadow_rays"], 1)
-    roof_trace = {"bound": "alu", "kernel": "trace_kernel<primary, BVH%d>" % (4 if tuning.get("bvh_width") == 4 else 2),
-                  "achieved": trace_tops,
-                  "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": trace_tops / VALU_PEAK_TOPS,
-                  "traffic": prof_trace.get("traffic"),
-                  "valu_busy_pct": prof_trace.get("valu_busy_pct"),
-                  "valu_utilization_pct": prof_trace.get("valu_utilization_pct"),
-                  "mrays_per_s_primary": tw["primary_rays"] / (trace_ms * 1e-3) / 1e6,
-                  "mrays_per_s_primary_plus_shadow": nrays / (trace_ms * 1e-3) / 1e6,
-                  "ms": trace_ms, "node_tests_per_ray": tw["node_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
-                  "tri_tests_per_ray": tw["tri_tests"] / max(tw["primary_rays"] + tw["shadow_rays"], 1),
-                  "bvh_width": tuning.get("bvh_width"),
-                  "rays_incl_shadow": tw["primary_rays"] + tw["shadow_rays"]}
+    prof_blend = read_profile("blend_boxfield", h_blend)
+    width = 4 if tuning.get("bvh_width") == 4 else 2
+
+    def trace_roof(kernel, ms, nodes, tris, rays, prof_key):
+        """ALU roofline of one traversal kernel: its slab and triangle tests
+        (counted by the work-counting run) over its eager duration."""
+        ops = nodes * width * OPS_PER_BOX + tris * OPS_PER_TRI
+        tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
+        prof = read_profile(prof_key, h_trace)
+        # the counters belong to one traversal variant (<kind, count, width 4>)
+        if not prof.get("kernel_name", "").endswith("%s>(adgi::VolumeView, int)" % ("true" if width == 4 else "false")):
+            prof = {}
+        return {"bound": "alu", "kernel": "%s<primary, BVH%d>" % (kernel, width), "achieved": tops,
+                "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": tops / VALU_PEAK_TOPS,
+                "traffic": prof.get("traffic"), "valu_busy_pct": prof.get("valu_busy_pct"),
+                "valu_utilization_pct": prof.get("valu_utilization_pct"), "ms": ms, "rays": rays,
+                "mrays_per_s": rays / (ms * 1e-3) / 1e6 if ms else None,
+                "node_tests_per_ray": nodes / max(rays, 1), "tri_tests_per_ray": tris / max(rays, 1),
+                "bvh_width": width}
+
+    roof_hit = trace_roof("trace_hit_kernel", stages_a[6], tw["node_tests"] - tw["shade_node_tests"],
+                          tw["tri_tests"] - tw["shade_tri_tests"], tw["primary_rays"], "trace_hit_boxfield")
+    roof_shade = trace_roof("trace_shade_kernel", stages_a[7], tw["shade_node_tests"], tw["shade_tri_tests"],
+                            tw["shadow_rays"], "trace_shade_boxfield")
     roof_blend = {"bound": "hbm", "kernel": "blend_kernel", "achieved": blend_gbs, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": blend_gbs / HBM_PEAK_GBS,
                   "traffic": prof_blend.get("traffic"), "ms": blend_ms,
                   "algorithmic_bytes": bbytes, "copy_gbs": copy_gbs, "frac_of_copy": blend_gbs / copy_gbs}
-    dominant = roof_trace if trace_ms >= blend_ms else roof_blend
+    dominant = max((roof_hit, roof_shade, roof_blend), key=lambda x: x["ms"])
     out = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -631,10 +634,13 @@ def main():
                      "p50_ms": pct(res_a["host_ms"], 50), "p99_ms": pct(res_a["host_ms"], 99),
                      "gpu_p50_ms": pct(res_a["gpu_ms"], 50), "gpu_p99_ms": pct(res_a["gpu_ms"], 99),
                      "stage_ms": dict(zip(["setup", "pilot_trace", "detect", "allocate", "probe_trace",
-                                           "blend"], stages_a))},
+                                           "blend", "probe_trace_hit", "probe_trace_shade"], stages_a))},
         **uni,
         "roofline": dominant,
-        "roofline_trace": roof_trace,
+        "roofline_trace_hit": roof_hit,
+        "roofline_trace_shade": roof_shade,
+        "trace": {"ms": trace_ms, "rays_incl_shadow": tw["primary_rays"] + tw["shadow_rays"],
+                  "mrays_per_s_incl_shadow": (tw["primary_rays"] + tw["shadow_rays"]) / (trace_ms * 1e-3) / 1e6},
         "roofline_blend": roof_blend,
         "scene_build_s": build_s,
     }

@@ -209,8 +209,10 @@ typedef struct {
   int32_t n_min_seen, n_max_seen;
   float ms_total;             /* device time of the frame (sync = 1)               */
   float ms_stage[8];          /* eager launches with sync = 1: frame setup, pilot
-                                 trace, detection, allocation, probe trace, blend
-                                 (ms each); zero when the frame ran as a graph    */
+                                 trace, detection, allocation, probe trace, blend,
+                                 then the probe trace's two parts: closest-hit
+                                 kernel and shading (shadow-ray) kernel (ms
+                                 each); zero when the frame ran as a graph        */
   int64_t ties[4];            /* reserved                                          */
 } adgi_update_stats;
 
@@ -346,10 +348,13 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* params, ad
  * the probe-ray traversal (same rays, same kernel shape) on the current
  * scene, then restores the volume's state. node_tests counts node visits
  * (a BVH2 visit tests two child boxes, a BVH4 visit four), tri_tests
- * ray/triangle tests, both over the probe rays and their shadow rays. */
+ * ray/triangle tests, both over the probe rays and their shadow rays;
+ * shade_node_tests and shade_tri_tests are the shadow rays' share (the
+ * shading kernel's work). */
 typedef struct {
   int64_t primary_rays, shadow_rays, node_tests, tri_tests;
   int64_t box_tests;          /* node_tests x the node width in use (2 or 4) */
+  int64_t shade_node_tests, shade_tri_tests;
 } adgi_trace_work;
 adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* params,
                                     adgi_trace_work* out);

@@ -90,7 +90,7 @@ class UpdateStats(C.Structure):
                 "shadow_rays": self.shadow_rays, "budget_used": self.budget_used,
                 "lambda": self.lambda_, "n_min_seen": self.n_min_seen,
                 "n_max_seen": self.n_max_seen, "ms_total": self.ms_total,
-                "ms_stage": [float(x) for x in self.ms_stage[:6]]}
+                "ms_stage": [float(x) for x in self.ms_stage[:8]]}
 
 
 class ProbeReadback(C.Structure):
@@ -108,7 +108,8 @@ class ProbeReadback(C.Structure):
 
 class TraceWork(C.Structure):
     _fields_ = [("primary_rays", C.c_int64), ("shadow_rays", C.c_int64),
-                ("node_tests", C.c_int64), ("tri_tests", C.c_int64), ("box_tests", C.c_int64)]
+                ("node_tests", C.c_int64), ("tri_tests", C.c_int64), ("box_tests", C.c_int64),
+                ("shade_node_tests", C.c_int64), ("shade_tri_tests", C.c_int64)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

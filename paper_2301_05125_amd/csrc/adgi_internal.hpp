@@ -17,7 +17,8 @@ size_t trace_lds_bytes(int block);
 // w4: traverse the BVH4 (v.nodes4) instead of the BVH2. chain: the two rays of
 // each chain sample (probe rays otherwise).
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block,
-                        int grid, bool count = false, bool w4 = false, bool chain = false);
+                        int grid, int shade_grid, bool count = false, bool w4 = false, bool chain = false,
+                        hipEvent_t between = nullptr);
 
 // chain.hip: one frame of `chains` Metropolis chains, then their samples
 // sorted by probe (v.smp_probe / v.smp_uv, v.offsets / v.n as per-probe

@@ -15,6 +15,8 @@ constexpr uint64_t kTagDynChainInit = 0x4D4449ull; // "MDI": a dynamic chain's f
 constexpr int kChainMaxSteps = 256;
 constexpr int kDynTexels = 196;                  // interior texels of a map, at most (14 x 14)
 constexpr int kMaxLights = 8;
+constexpr int kPairsPerBatch = 64 * kMaxLights;  // shadow pairs of one 64-ray batch, at most
+constexpr int kPairScanPer = 1024;               // batches per block of the pair-count scan
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
 constexpr int kStackLds = 7;                    // traversal stack entries kept in LDS
@@ -90,8 +92,8 @@ struct DynTables {
 };
 
 struct FrameStats {
-  uint32_t ray_counter;     // persistent work-stealing cursor (primary)
-  uint32_t pilot_counter;   // persistent cursor (pilots)
+  uint32_t pair_batches;    // 64-ray batches of the last trace pass
+  uint32_t pair_total;      // shadow pairs of the last trace pass
   uint64_t shadow_rays;
   uint64_t max_score;
   uint32_t lambda;
@@ -100,6 +102,8 @@ struct FrameStats {
   uint64_t budget_used;
   uint64_t node_tests;      // work-counting traversal only
   uint64_t tri_tests;
+  uint64_t shade_node_tests; // the shading kernel's part of the two above
+  uint64_t shade_tri_tests;
   int64_t remainder;        // R = B' - sum e_i(lambda*)
   uint32_t bucket_count[kOrderBuckets];   // probes per ray-chunk bucket
   uint32_t bucket_cursor[kOrderBuckets];  // scatter cursors
@@ -163,6 +167,19 @@ struct VolumeView {
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
+  // lit hits waiting for their shadow rays (the pilot and probe passes of a
+  // frame use them one after the other), by ray index: hit point and t, unit
+  // normal and original triangle index, and a word (pending shadow rays << 8
+  // | visible lights); per batch of 64 rays, its (lane | light << 6) pairs,
+  // light-major, their number, and its offset in the frame's pair list
+  float4* hit_pos;            // [hit_cap]
+  float4* hit_nrm;            // [hit_cap]
+  uint32_t* hit_vis;          // [hit_cap]
+  uint16_t* pairs;            // [ceil(hit_cap/64)][kPairsPerBatch]
+  uint32_t* pair_cnt;         // [ceil(hit_cap/64)]
+  uint32_t* pair_off;         // [ceil(hit_cap/64) + 1] exclusive scan of pair_cnt
+  uint32_t* pair_blk;         // [ceil(hit_cap/64)/kPairScanPer + 1] scan block totals
+  uint32_t hit_cap;           // max(max_rays, 8 P)
   int32_t* dbg_tri;           // [max_rays] or null
   uint8_t* dbg_shadow;
   uint16_t* dbg_ibin;

@@ -24,8 +24,6 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->bucket_cursor[tid] = 0u;
   }
   if (tid == 0) {
-    st->ray_counter = 0u;
-    st->pilot_counter = 0u;
     st->shadow_rays = 0ull;
     st->max_score = 0ull;
     st->lambda = 0u;
@@ -34,6 +32,8 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->budget_used = 0ull;
     st->node_tests = 0ull;
     st->tri_tests = 0ull;
+    st->shade_node_tests = 0ull;
+    st->shade_tri_tests = 0ull;
     st->remainder = 0;
   }
   if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;

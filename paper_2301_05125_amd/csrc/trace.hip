@@ -1,6 +1,6 @@
 // trace.hip - probe-ray and pilot-ray traversal, direct light and shadow rays.
 //
-// One kernel template serves both ray sources:
+// One pair of kernels serves every ray source:
 //   KIND_PRIMARY: ray r of probe i is the j-th point of a rotated spherical
 //     Fibonacci set of n_i directions (r = offsets[i] + j); output one 16-byte
 //     record (radiance RGB, hit distance) per ray.
@@ -16,13 +16,16 @@
 //   KIND_PILOT:   ray r = 8i + k is the pilot of octant k (Sec. 4.1, 4.4);
 //     output the 10-bit codes of f_v = exp(-2t/s) (eq. ProbeVis) and
 //     f_r = min(lum, beta)/beta (Sec. 4.1.3).
-// Rays are handed out 64 at a time to waves from a global counter (persistent
-// work-stealing launch) or one per thread (plain launch). Traversal is a
-// while-while loop over the BVH2 or its 4-wide collapse, with a short per-lane
-// stack in LDS (deeper entries in private memory); a few very large triangles
-// sit outside the tree and every ray tests them first. Shadow rays of a
-// wave's front-face hits are compacted with ballot/prefix into a wave-local
-// LDS queue and traced by all 64 lanes together.
+// The closest-hit kernel finds every ray's hit and writes the final output
+// of misses and unlit hits; a lit front-face hit keeps its hit data at its
+// ray index and lists one (ray, light) pair per light on its front side. The
+// shading kernel traces those pairs' shadow rays in full 64-lane batches and
+// writes the lit rays' output. Work goes to waves by fixed batch index (grid
+// stride when persistent): no wave waits on a counter shared by the whole
+// grid, which costs more here than the traversal it would balance.
+// Traversal is a while-while loop over the BVH2 or its 4-wide collapse, with
+// a short per-lane stack in LDS (deeper entries in private memory); a few
+// very large triangles sit outside the tree and every ray tests them first.
 #include "adgi_internal.hpp"
 
 namespace adgi {
@@ -227,6 +230,7 @@ __device__ bool any_hit(const VolumeView& v, const Ray& ray,
   }
 }
 
+
 // ---- BVH4 traversal
 // Tests the four child boxes of node `idx` on (0, lim]. Returns the number of
 // boxes hit; the nearest child goes to `next`, the others are pushed farthest
@@ -267,6 +271,7 @@ __device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int
   next = c0;
   return nh;
 }
+
 
 template <bool COUNT>
 __device__ int closest_hit4(const VolumeView& v, const Ray& ray, Stack& st, float& t_best, bool& front_best,
@@ -342,6 +347,7 @@ __device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack&
   }
 }
 
+
 // First probe i with offsets[i+1] > r (offsets ascending, offsets[0] = 0).
 __device__ __forceinline__ int probe_of_ray(const uint32_t* __restrict__ off, int P, uint32_t r) {
   int lo = 0, hi = P - 1;
@@ -359,169 +365,77 @@ __device__ __forceinline__ float3 probe_position(const VolumeView& v, int i) {
                      fmaf((float)z, v.sz, v.oz));
 }
 
-template <int KIND, bool COUNT, bool W4>
-__device__ void trace_wave(const VolumeView& v, Stack& st,
-                           uint16_t* queue, uint32_t* vis, uint32_t base, uint32_t total) {
+// ---- ray sources
+template <int KIND>
+__device__ __forceinline__ uint32_t ray_total(const VolumeView& v) {
+  return KIND == KIND_PRIMARY ? v.offsets[v.P]
+         : KIND == KIND_CHAIN ? 2u * v.offsets[v.P] + (v.fp->dyn_chains > 0 ? v.dyn_off[v.P] : 0u)
+                              : 8u * (uint32_t)v.P;
+}
+
+// Origin and direction of ray r; `shade` is false for the distance-only rays
+// of chain frames.
+template <int KIND>
+__device__ __forceinline__ void gen_ray(const VolumeView& v, uint32_t r, float3& o, float3& d, bool& shade) {
   const FrameParams& fp = *v.fp;
-  const SceneParams& sc = *v.scene;
-  const uint32_t lane = lane_id();
-  const uint32_t r = base + lane;
-  const bool active = r < total;
-
-  // ---- ray generation
-  float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
-  bool shade = true;  // chain frames: false for distance-only rays
-  if (active) {
-    if (KIND == KIND_PRIMARY) {
-      int i = probe_of_ray(v.offsets, v.P, r);
-      uint32_t b = v.offsets[i], n = v.offsets[i + 1] - b;
+  shade = true;
+  if (KIND == KIND_PRIMARY) {
+    int i = probe_of_ray(v.offsets, v.P, r);
+    uint32_t b = v.offsets[i], n = v.offsets[i + 1] - b;
+    o = probe_position(v, i);
+    d = sf_direction(r - b, n, fp.R);
+  } else if (KIND == KIND_CHAIN) {
+    const uint32_t S2 = 2u * v.offsets[v.P];
+    d = make_float3(0.f, 0.f, 1.f);
+    if (r < S2) {
+      const uint32_t k = r >> 1;
+      const int i = (int)v.smp_probe[k];
       o = probe_position(v, i);
-      d = sf_direction(r - b, n, fp.R);
-    } else if (KIND == KIND_CHAIN) {
-      const uint32_t S2 = 2u * v.offsets[v.P];
-      if (r < S2) {
-        const uint32_t k = r >> 1;
-        const int i = (int)v.smp_probe[k];
-        o = probe_position(v, i);
-        d = oct_decode_dir(v.smp_uv[k]);
-        if (r & 1u) d = make_float3(-d.x, -d.y, -d.z);
-        if (fp.dyn_chains > 0 && v.score[i] > 0) {  // through the texel centre
-          const int R = (r & 1u) ? v.dep_res - 2 : v.irr_res - 2;
-          d = texel_centre_dir(oct_bin(oct_encode(d), R), R);
-        }
-        shade = !(r & 1u);
-      } else {
-        const uint32_t rr = r - S2;
-        const int i = probe_of_ray(v.dyn_off, v.P, rr);
-        uint32_t j = rr - v.dyn_off[i];
-        o = probe_position(v, i);
-        const int x = i % v.dx, y = (i / v.dx) % v.dy, z = i / (v.dx * v.dy);
-        const uint8_t* mk = v.dyn_mark + 8 * (x / 3 + v.pdx * (y / 3 + v.pdy * (z / 3)));
-        const DynTables& tb = *v.dyn_tab;
-        for (int oc = 0; oc < 8; ++oc) {
-          if (!mk[oc]) continue;
-          const uint32_t ni = tb.start_i[oc + 1] - tb.start_i[oc], nd = tb.start_d[oc + 1] - tb.start_d[oc];
-          if (j < ni) {
-            d = texel_centre_dir(tb.ord_i[tb.start_i[oc] + j], v.irr_res - 2);
-            shade = true;
-            break;
-          }
-          j -= ni;
-          if (j < nd) {
-            d = texel_centre_dir(tb.ord_d[tb.start_d[oc] + j], v.dep_res - 2);
-            shade = false;
-            break;
-          }
-          j -= nd;
-        }
+      d = oct_decode_dir(v.smp_uv[k]);
+      if (r & 1u) d = make_float3(-d.x, -d.y, -d.z);
+      if (fp.dyn_chains > 0 && v.score[i] > 0) {  // through the texel centre
+        const int R = (r & 1u) ? v.dep_res - 2 : v.irr_res - 2;
+        d = texel_centre_dir(oct_bin(oct_encode(d), R), R);
       }
+      shade = !(r & 1u);
     } else {
-      uint32_t i = r >> 3, k = r & 7;
-      o = probe_position(v, (int)i);
-      d = pilot_direction(fp.seed, i, k, (uint32_t)fp.frame >> 1);
+      const uint32_t rr = r - S2;
+      const int i = probe_of_ray(v.dyn_off, v.P, rr);
+      uint32_t j = rr - v.dyn_off[i];
+      o = probe_position(v, i);
+      const int x = i % v.dx, y = (i / v.dx) % v.dy, z = i / (v.dx * v.dy);
+      const uint8_t* mk = v.dyn_mark + 8 * (x / 3 + v.pdx * (y / 3 + v.pdy * (z / 3)));
+      const DynTables& tb = *v.dyn_tab;
+      for (int oc = 0; oc < 8; ++oc) {
+        if (!mk[oc]) continue;
+        const uint32_t ni = tb.start_i[oc + 1] - tb.start_i[oc], nd = tb.start_d[oc + 1] - tb.start_d[oc];
+        if (j < ni) {
+          d = texel_centre_dir(tb.ord_i[tb.start_i[oc] + j], v.irr_res - 2);
+          break;
+        }
+        j -= ni;
+        if (j < nd) {
+          d = texel_centre_dir(tb.ord_d[tb.start_d[oc] + j], v.dep_res - 2);
+          shade = false;
+          break;
+        }
+        j -= nd;
+      }
     }
+  } else {
+    uint32_t i = r >> 3, k = r & 7;
+    o = probe_position(v, (int)i);
+    d = pilot_direction(fp.seed, i, k, (uint32_t)fp.frame >> 1);
   }
+}
 
-  // ---- closest hit
-  float t = INFINITY;
-  bool front = false;
-  int id = -1, slot = -1;
-  Work w;
-  if (active && sc.num_tris > 0) {
-    Ray ray = make_ray(o, d);
-    slot = W4 ? closest_hit4<COUNT>(v, ray, st, t, front, id, w)
-              : closest_hit<COUNT>(v, ray, st, t, front, id, w);
-    if (slot < 0) {
-      id = -1;
-      t = INFINITY;
-    }
-  }
-
-  // ---- direct light at front-face hits, shadow rays compacted per wave
-  const bool lit_hit = active && slot >= 0 && front && (KIND != KIND_CHAIN || shade);
-  float3 x = make_float3(0.f, 0.f, 0.f), nrm = make_float3(0.f, 0.f, 0.f);
-  if (lit_hit) {
-    const float4* tp = v.tris + 3 * (size_t)slot;
-    float4 b = tp[1], c = tp[2];
-    float nx = b.y * c.z - b.z * c.y, ny = b.z * c.x - b.x * c.z, nz = b.x * c.y - b.y * c.x;
-    float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
-    nrm = make_float3(nx * inv, ny * inv, nz * inv);
-    x = make_float3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
-  }
-  const int nl = sc.num_lights;
-  uint32_t qtotal = 0;
-  for (int l = 0; l < nl; ++l) {
-    bool need = false;
-    if (lit_hit) {
-      float lx = sc.lpos[l][0] - x.x, ly = sc.lpos[l][1] - x.y, lz = sc.lpos[l][2] - x.z;
-      need = nrm.x * lx + nrm.y * ly + nrm.z * lz > 0.0f;
-    }
-    uint64_t mask = ballot(need);
-    if (need) queue[qtotal + lanes_below(mask)] = (uint16_t)(lane | (l << 6));
-    qtotal += (uint32_t)__popcll(mask);
-  }
-  vis[lane] = 0u;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const float off_len = kShadowOffset * v.s_diag;
-  for (uint32_t qb = 0; qb < qtotal; qb += 64) {
-    uint32_t q = qb + lane;
-    bool has = q < qtotal;
-    uint32_t e = has ? queue[q] : 0u;
-    int src = (int)(e & 63u), l = (int)(e >> 6);
-    float sx = __shfl(x.x, src), sy = __shfl(x.y, src), sz = __shfl(x.z, src);
-    float mx = __shfl(nrm.x, src), my = __shfl(nrm.y, src), mz = __shfl(nrm.z, src);
-    if (has) {
-      float3 so = make_float3(fmaf(off_len, mx, sx), fmaf(off_len, my, sy), fmaf(off_len, mz, sz));
-      float gx = sc.lpos[l][0] - so.x, gy = sc.lpos[l][1] - so.y, gz = sc.lpos[l][2] - so.z;
-      float len = sqrtf(gx * gx + gy * gy + gz * gz);
-      float il = 1.0f / len;
-      Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
-      const float smax = len * (1.0f - kShadowShorten);
-      bool blocked = W4 ? any_hit4<COUNT>(v, sray, smax, st, w) : any_hit<COUNT>(v, sray, smax, st, w);
-      if (!blocked) atomicOr(&vis[src], 1u << l);
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  uint32_t bits = vis[lane];
-  if (COUNT) {
-    uint32_t n = w.nodes, tt = w.tris;
-    for (int o2 = 32; o2 > 0; o2 >>= 1) {
-      n += __shfl_xor(n, o2);
-      tt += __shfl_xor(tt, o2);
-    }
-    if (lane == 0) {
-      atomicAdd((unsigned long long*)&v.stats->node_tests, (unsigned long long)n);
-      atomicAdd((unsigned long long*)&v.stats->tri_tests, (unsigned long long)tt);
-    }
-  }
-  if (lane == 0 && qtotal > 0) atomicAdd((unsigned long long*)&v.stats->shadow_rays, (unsigned long long)qtotal);
-
-  float3 L = make_float3(0.f, 0.f, 0.f);
-  if (active && slot < 0) {
-    L = make_float3(sc.sky[0], sc.sky[1], sc.sky[2]);
-  } else if (lit_hit) {
-    float er = 0.f, eg = 0.f, eb = 0.f;
-    for (int l = 0; l < nl; ++l) {
-      if (!((bits >> l) & 1u)) continue;
-      float lx = sc.lpos[l][0] - x.x, ly = sc.lpos[l][1] - x.y, lz = sc.lpos[l][2] - x.z;
-      float d2 = lx * lx + ly * ly + lz * lz;
-      float cs = (nrm.x * lx + nrm.y * ly + nrm.z * lz) / sqrtf(d2);
-      float w = fmaxf(cs, 0.0f) / d2;
-      er = fmaf(sc.lint[l][0], w, er);
-      eg = fmaf(sc.lint[l][1], w, eg);
-      eb = fmaf(sc.lint[l][2], w, eb);
-    }
-    float4 rho = v.albedo[id];
-    const float inv_pi = 0.318309886183790671538f;
-    L = make_float3(rho.x * inv_pi * er, rho.y * inv_pi * eg, rho.z * inv_pi * eb);
-  }
-
-  // ---- outputs
-  if (!active) return;
+// Final output of ray r: the record (radiance, t) of probe and chain rays, the
+// 10-bit codes of f_v = exp(-2t/s) (eq. ProbeVis) and f_r = min(lum, beta)/beta
+// (Sec. 4.1.3) of pilots.
+template <int KIND>
+__device__ __forceinline__ void emit_ray(const VolumeView& v, uint32_t r, float3 L, float t, int id,
+                                         uint32_t bits) {
+  const FrameParams& fp = *v.fp;
   if (KIND != KIND_PILOT) {
     v.rec[r] = make_float4(L.x, L.y, L.z, t);
     if (fp.debug) {
@@ -539,68 +453,310 @@ __device__ void trace_wave(const VolumeView& v, Stack& st,
   }
 }
 
-// Eight waves per SIMD (64 VGPRs): traversal is bound by memory latency, so
-// occupancy pays for the few registers the compiler then keeps in scratch.
-template <int KIND, bool COUNT, bool W4>
-__global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_kernel(VolumeView v, int persistent) {
-  extern __shared__ uint64_t smem[];
-  uint64_t* stack_base = (uint64_t*)smem;                         // kStackLds * blockDim
-  uint16_t* queues = (uint16_t*)(stack_base + kStackLds * blockDim.x);  // waves * 64 * kMaxLights
-  const int nwaves = blockDim.x >> 6;
-  uint32_t* vis_all = (uint32_t*)(queues + nwaves * 64 * kMaxLights);   // waves * 64
-  const int wave = threadIdx.x >> 6;
-  Stack st;
-  st.lds = (lds_u64*)stack_base + wave * (64 * kStackLds) + lane_id();
-  st.sp = 0;
-  uint16_t* queue = queues + wave * 64 * kMaxLights;
-  uint32_t* vis = vis_all + wave * 64;
-  const uint32_t total = KIND == KIND_PRIMARY ? v.offsets[v.P]
-                         : KIND == KIND_CHAIN ? 2u * v.offsets[v.P] + (v.fp->dyn_chains > 0 ? v.dyn_off[v.P] : 0u)
-                                              : 8u * (uint32_t)v.P;
-  if (persistent) {
-    uint32_t* counter = KIND == KIND_PILOT ? &v.stats->pilot_counter : &v.stats->ray_counter;
-    for (;;) {
-      uint32_t base = 0;
-      if (lane_id() == 0) base = atomicAdd(counter, 64u);
-      base = __shfl(base, 0);
-      if (base >= total) break;
-      trace_wave<KIND, COUNT, W4>(v, st, queue, vis, base, total);
+// Lights on the front side of a hit at x with normal n, one bit each.
+__device__ __forceinline__ uint32_t lights_facing(const SceneParams& sc, float3 x, float3 n) {
+  uint32_t m = 0u;
+  for (int l = 0; l < sc.num_lights; ++l) {
+    const float lx = sc.lpos[l][0] - x.x, ly = sc.lpos[l][1] - x.y, lz = sc.lpos[l][2] - x.z;
+    if (n.x * lx + n.y * ly + n.z * lz > 0.0f) m |= 1u << l;
+  }
+  return m;
+}
+
+// Adds the work counters of the wave's lanes to the frame statistics (the
+// shading kernel's also to its own pair); `shadow`, the wave's shadow pairs,
+// is the same in every lane.
+template <bool COUNT, bool SHADE>
+__device__ __forceinline__ void flush_stats(const VolumeView& v, const Work& w, uint32_t shadow) {
+  uint32_t n = COUNT ? w.nodes : 0u, tt = COUNT ? w.tris : 0u;
+  const uint32_t s = shadow;
+  if (COUNT) {
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      n += __shfl_xor(n, o2);
+      tt += __shfl_xor(tt, o2);
     }
-  } else {
-    uint32_t base = (blockIdx.x * blockDim.x) + (uint32_t)wave * 64u;
-    if (base < total) trace_wave<KIND, COUNT, W4>(v, st, queue, vis, base, total);
+  }
+  if (lane_id() == 0) {
+    if (COUNT) {
+      atomicAdd((unsigned long long*)&v.stats->node_tests, (unsigned long long)n);
+      atomicAdd((unsigned long long*)&v.stats->tri_tests, (unsigned long long)tt);
+      if (SHADE) {
+        atomicAdd((unsigned long long*)&v.stats->shade_node_tests, (unsigned long long)n);
+        atomicAdd((unsigned long long*)&v.stats->shade_tri_tests, (unsigned long long)tt);
+      }
+    }
+    if (s > 0) atomicAdd((unsigned long long*)&v.stats->shadow_rays, (unsigned long long)s);
   }
 }
 
-size_t trace_lds_bytes(int block) {
-  return (size_t)kStackLds * block * 8 + (size_t)(block / 64) * 64 * kMaxLights * 2 + (size_t)(block / 64) * 64 * 4;
+// ---- closest-hit kernel
+// A wave owns 64 consecutive rays (batch b = rays [64b, 64b + 64)); a
+// persistent launch walks the batches with a grid stride, so no wave ever
+// waits on a shared counter. Every ray finds its closest hit. A miss, a back
+// face, a distance-only ray or a lit hit with no light on its front side is
+// final and is written at once; a lit hit with lights on its front side
+// keeps its hit point, t, normal and triangle at its own index, its pending
+// shadow-ray count in its visibility word, and puts one (lane, light) pair
+// per such light into the batch's pair segment, all pairs of light 0 first,
+// then light 1, and so on (neighbouring shadow rays mostly share a light).
+template <int KIND, bool COUNT, bool W4>
+__device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32_t b, uint32_t total, Work& w,
+                                          uint32_t& shadow) {
+  const SceneParams& sc = *v.scene;
+  const uint32_t lane = lane_id();
+  const uint32_t r = b * 64u + lane;
+  const bool active = r < total;
+  float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
+  bool shade = true;
+  if (active) gen_ray<KIND>(v, r, o, d, shade);
+  float t = INFINITY;
+  bool front = false;
+  int id = -1, slot = -1;
+  if (active && sc.num_tris > 0) {
+    Ray ray = make_ray(o, d);
+    slot = W4 ? closest_hit4<COUNT>(v, ray, st, t, front, id, w) : closest_hit<COUNT>(v, ray, st, t, front, id, w);
+    if (slot < 0) {
+      id = -1;
+      t = INFINITY;
+    }
+  }
+  const bool lit = active && slot >= 0 && front && shade;
+  uint32_t need = 0u;
+  if (lit) {
+    const float4* tp = v.tris + 3 * (size_t)slot;
+    const float4 tb = tp[1], tc = tp[2];
+    const float nx = tb.y * tc.z - tb.z * tc.y, ny = tb.z * tc.x - tb.x * tc.z, nz = tb.x * tc.y - tb.y * tc.x;
+    const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+    const float3 nrm = make_float3(nx * inv, ny * inv, nz * inv);
+    const float3 x = make_float3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
+    need = lights_facing(sc, x, nrm);
+    if (need) {
+      v.hit_pos[r] = make_float4(x.x, x.y, x.z, t);
+      v.hit_nrm[r] = make_float4(nrm.x, nrm.y, nrm.z, __int_as_float(id));
+      v.hit_vis[r] = (uint32_t)__popc(need) << 8;
+    }
+  }
+  uint16_t* seg = v.pairs + (size_t)b * kPairsPerBatch;
+  uint32_t n = 0u;
+  for (int l = 0; l < sc.num_lights; ++l) {
+    const bool p = (need >> l) & 1u;
+    const uint64_t m = ballot(p);
+    if (p) seg[n + lanes_below(m)] = (uint16_t)(lane | ((uint32_t)l << 6));
+    n += (uint32_t)__popcll(m);
+  }
+  if (lane == 0) v.pair_cnt[b] = n;
+  shadow += n;
+  if (active && !need) {
+    const bool miss = slot < 0;
+    const float3 L = miss ? make_float3(sc.sky[0], sc.sky[1], sc.sky[2]) : make_float3(0.f, 0.f, 0.f);
+    emit_ray<KIND>(v, r, L, t, id, 0u);
+  } else if (active && v.fp->debug) {
+    v.dbg_tri[r] = id;
+  }
+}
+
+template <int KIND, bool COUNT, bool W4>
+__global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_hit_kernel(VolumeView v, int persistent) {
+  extern __shared__ uint64_t smem[];
+  const int wave = threadIdx.x >> 6;
+  Stack st;
+  st.lds = (lds_u64*)smem + wave * (64 * kStackLds) + lane_id();
+  st.sp = 0;
+  const uint32_t total = ray_total<KIND>(v);
+  const uint32_t nbatch = (total + 63u) / 64u;
+  const uint32_t waves = blockDim.x >> 6;
+  const uint32_t first = blockIdx.x * waves + (uint32_t)wave;
+  const uint32_t stride = persistent ? gridDim.x * waves : nbatch;
+  if (first == 0 && lane_id() == 0) v.stats->pair_batches = nbatch;
+  Work w;
+  uint32_t shadow = 0u;
+  for (uint32_t b = first; b < nbatch; b += stride) hit_batch<KIND, COUNT, W4>(v, st, b, total, w, shadow);
+  flush_stats<COUNT, false>(v, w, shadow);
+}
+
+// ---- exclusive scan of the batches' pair counts -> pair_off[0..nbatch]
+// Three launches over the buffer's batch capacity (counts past the frame's
+// batches read as zero): a block-local scan of kScanPer batches per block
+// with the block totals, a scan of the block totals (one block), and the
+// block offsets added in.
+constexpr int kScanThreads = 256, kScanItems = kPairScanPer / kScanThreads, kScanPer = kPairScanPer;
+
+__device__ __forceinline__ uint32_t block_scan_u32(uint32_t x, uint32_t* sm, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t s = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(s, (unsigned)off);
+    if (lane >= off) s += y;
+  }
+  if (lane == 63) sm[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0u;
+    for (int k = 0; k < nw; ++k) {
+      const uint32_t tk = sm[k];
+      sm[k] = acc;
+      acc += tk;
+    }
+    sm[nw] = acc;
+  }
+  __syncthreads();
+  total = sm[nw];
+  const uint32_t out = s - x + sm[wave];
+  __syncthreads();
+  return out;
+}
+
+__global__ __launch_bounds__(kScanThreads) void pair_scan_local_kernel(VolumeView v) {
+  __shared__ uint32_t sm[kScanThreads / 64 + 1];
+  const uint32_t nb = v.stats->pair_batches;
+  const uint32_t b0 = blockIdx.x * (uint32_t)kScanPer + threadIdx.x * (uint32_t)kScanItems;
+  uint32_t c[kScanItems], sum = 0u;
+  for (int k = 0; k < kScanItems; ++k) {
+    c[k] = b0 + k < nb ? v.pair_cnt[b0 + k] : 0u;
+    sum += c[k];
+  }
+  uint32_t total;
+  uint32_t acc = block_scan_u32(sum, sm, total);
+  for (int k = 0; k < kScanItems; ++k) {
+    if (b0 + k <= nb) v.pair_off[b0 + k] = acc;
+    acc += c[k];
+  }
+  if (threadIdx.x == 0) v.pair_blk[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void pair_scan_blocks_kernel(VolumeView v) {
+  __shared__ uint32_t sm[1024 / 64 + 1];
+  const uint32_t nblk = v.stats->pair_batches / (uint32_t)kScanPer + 1u;
+  uint32_t carry = 0u;
+  for (uint32_t base = 0; base < nblk; base += 1024u) {
+    const uint32_t k = base + threadIdx.x;
+    const uint32_t x = k < nblk ? v.pair_blk[k] : 0u;
+    uint32_t total;
+    const uint32_t e = block_scan_u32(x, sm, total);
+    if (k < nblk) v.pair_blk[k] = carry + e;
+    carry += total;
+  }
+  if (threadIdx.x == 0) v.stats->pair_total = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void pair_scan_add_kernel(VolumeView v) {
+  const uint32_t nb = v.stats->pair_batches;
+  const uint32_t b = blockIdx.x * kScanThreads + threadIdx.x;
+  if (b <= nb) v.pair_off[b] += v.pair_blk[b / (uint32_t)kScanPer];
+}
+
+// ---- shadow and shading kernel
+// Wave-batch q takes pairs [64q, 64q + 64) of the frame's pair list (the
+// batches' segments end to end): lane p finds its batch by binary search in
+// pair_off, traces the shadow ray of its (ray, light) pair from the hit point
+// offset along the normal towards the light (any hit on the shortened
+// segment), and adds its light's bit (if unblocked) and -1 to the ray's
+// pending count in one atomic on the ray's own word. The lane that retires
+// the ray's last shadow ray shades it: rho/pi times the sum over its visible
+// lights of I_l cos / d^2, the lights taken in index order.
+template <int KIND, bool COUNT, bool W4>
+__device__ __forceinline__ void shade_batch(const VolumeView& v, Stack& st, uint32_t q, uint32_t T, uint32_t nb,
+                                            Work& w) {
+  const SceneParams& sc = *v.scene;
+  const uint32_t p = q * 64u + lane_id();
+  if (p >= T) return;
+  uint32_t lo = 0u, hi = nb - 1u;  // last batch with pair_off[b] <= p
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (v.pair_off[mid] <= p) lo = mid;
+    else hi = mid - 1u;
+  }
+  const uint32_t b = lo;
+  const uint32_t e = v.pairs[(size_t)b * kPairsPerBatch + (p - v.pair_off[b])];
+  const uint32_t r = b * 64u + (e & 63u), l = e >> 6;
+  const float4 pos = v.hit_pos[r], nrm = v.hit_nrm[r];
+  const float off_len = kShadowOffset * v.s_diag;
+  const float3 so = make_float3(fmaf(off_len, nrm.x, pos.x), fmaf(off_len, nrm.y, pos.y),
+                                fmaf(off_len, nrm.z, pos.z));
+  const float gx = sc.lpos[l][0] - so.x, gy = sc.lpos[l][1] - so.y, gz = sc.lpos[l][2] - so.z;
+  const float len = sqrtf(gx * gx + gy * gy + gz * gz);
+  const float il = 1.0f / len;
+  const Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
+  const float smax = len * (1.0f - kShadowShorten);
+  const bool blocked = W4 ? any_hit4<COUNT>(v, sray, smax, st, w) : any_hit<COUNT>(v, sray, smax, st, w);
+  const uint32_t mine = blocked ? 0u : 1u << l;
+  const uint32_t old = atomicAdd(&v.hit_vis[r], mine - 256u);
+  if ((old >> 8) != 1u) return;
+  const uint32_t bits = (old & 0xffu) | mine;
+  float er = 0.f, eg = 0.f, eb = 0.f;
+  for (int k = 0; k < sc.num_lights; ++k) {
+    if (!((bits >> k) & 1u)) continue;
+    const float lx = sc.lpos[k][0] - pos.x, ly = sc.lpos[k][1] - pos.y, lz = sc.lpos[k][2] - pos.z;
+    const float d2 = lx * lx + ly * ly + lz * lz;
+    const float cs = (nrm.x * lx + nrm.y * ly + nrm.z * lz) / sqrtf(d2);
+    const float wl = fmaxf(cs, 0.0f) / d2;
+    er = fmaf(sc.lint[k][0], wl, er);
+    eg = fmaf(sc.lint[k][1], wl, eg);
+    eb = fmaf(sc.lint[k][2], wl, eb);
+  }
+  const int id = __float_as_int(nrm.w);
+  const float4 rho = v.albedo[id];
+  const float inv_pi = 0.318309886183790671538f;
+  const float3 L = make_float3(rho.x * inv_pi * er, rho.y * inv_pi * eg, rho.z * inv_pi * eb);
+  emit_ray<KIND>(v, r, L, pos.w, id, bits);
+}
+
+template <int KIND, bool COUNT, bool W4>
+__global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_shade_kernel(VolumeView v) {
+  extern __shared__ uint64_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const uint32_t waves = blockDim.x >> 6;
+  Stack st;
+  st.lds = (lds_u64*)smem + wave * (64 * kStackLds) + lane_id();
+  st.sp = 0;
+  const uint32_t T = v.stats->pair_total, nb = v.stats->pair_batches;
+  const uint32_t nq = (T + 63u) / 64u;
+  Work w;
+  for (uint32_t q = blockIdx.x * waves + (uint32_t)wave; q < nq; q += gridDim.x * waves)
+    shade_batch<KIND, COUNT, W4>(v, st, q, T, nb, w);
+  flush_stats<COUNT, true>(v, w, 0u);
+}
+
+size_t trace_lds_bytes(int block) { return (size_t)kStackLds * block * 8; }
+
+template <int KIND, bool COUNT, bool W4>
+static hipError_t launch_kind(const VolumeView& v, hipStream_t s, int pers, int block, int grid, int shade_grid,
+                              hipEvent_t between) {
+  const size_t lds = trace_lds_bytes(block);
+  hipLaunchKernelGGL((trace_hit_kernel<KIND, COUNT, W4>), dim3(grid), dim3(block), lds, s, v, pers);
+  if (between) {
+    const hipError_t e = hipEventRecord(between, s);
+    if (e != hipSuccess) return e;
+  }
+  const uint32_t cap_batches = (v.hit_cap + 63u) / 64u;
+  const uint32_t scan_blocks = cap_batches / (uint32_t)kScanPer + 1u;
+  hipLaunchKernelGGL(pair_scan_local_kernel, dim3(scan_blocks), dim3(kScanThreads), 0, s, v);
+  hipLaunchKernelGGL(pair_scan_blocks_kernel, dim3(1), dim3(1024), 0, s, v);
+  hipLaunchKernelGGL(pair_scan_add_kernel, dim3((cap_batches + kScanThreads) / kScanThreads), dim3(kScanThreads), 0,
+                     s, v);
+  hipLaunchKernelGGL((trace_shade_kernel<KIND, COUNT, W4>), dim3(shade_grid), dim3(block), lds, s, v);
+  return hipGetLastError();
 }
 
 template <bool W4>
-static void launch_trace_w(const VolumeView& v, hipStream_t s, bool pilot, int pers, int block, int grid,
-                           bool count, bool chain) {
-  const size_t lds = trace_lds_bytes(block);
-  if (chain && count)
-    hipLaunchKernelGGL((trace_kernel<KIND_CHAIN, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
-  else if (chain)
-    hipLaunchKernelGGL((trace_kernel<KIND_CHAIN, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
-  else if (pilot && count)
-    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
-  else if (pilot)
-    hipLaunchKernelGGL((trace_kernel<KIND_PILOT, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
-  else if (count)
-    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, true, W4>), dim3(grid), dim3(block), lds, s, v, pers);
-  else
-    hipLaunchKernelGGL((trace_kernel<KIND_PRIMARY, false, W4>), dim3(grid), dim3(block), lds, s, v, pers);
+static hipError_t launch_trace_w(const VolumeView& v, hipStream_t s, bool pilot, int pers, int block, int grid,
+                                 int shade_grid, bool count, bool chain, hipEvent_t between) {
+  if (chain && count) return launch_kind<KIND_CHAIN, true, W4>(v, s, pers, block, grid, shade_grid, between);
+  if (chain) return launch_kind<KIND_CHAIN, false, W4>(v, s, pers, block, grid, shade_grid, between);
+  if (pilot && count) return launch_kind<KIND_PILOT, true, W4>(v, s, pers, block, grid, shade_grid, between);
+  if (pilot) return launch_kind<KIND_PILOT, false, W4>(v, s, pers, block, grid, shade_grid, between);
+  if (count) return launch_kind<KIND_PRIMARY, true, W4>(v, s, pers, block, grid, shade_grid, between);
+  return launch_kind<KIND_PRIMARY, false, W4>(v, s, pers, block, grid, shade_grid, between);
 }
 
+// grid: blocks of the closest-hit kernel (persistent: the resident grid;
+// otherwise enough for every ray). The shading kernel always runs a resident
+// grid of `waves_per_cu` waves per CU over the frame's pair list. `between`,
+// when given, is recorded after the closest-hit kernel.
 hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool persistent, int block, int grid,
-                        bool count, bool w4, bool chain) {
-  if (w4)
-    launch_trace_w<true>(v, s, pilot, persistent ? 1 : 0, block, grid, count, chain);
-  else
-    launch_trace_w<false>(v, s, pilot, persistent ? 1 : 0, block, grid, count, chain);
-  return hipGetLastError();
+                        int shade_grid, bool count, bool w4, bool chain, hipEvent_t between) {
+  if (w4) return launch_trace_w<true>(v, s, pilot, persistent ? 1 : 0, block, grid, shade_grid, count, chain, between);
+  return launch_trace_w<false>(v, s, pilot, persistent ? 1 : 0, block, grid, shade_grid, count, chain, between);
 }
 
 }  // namespace adgi

@@ -121,7 +121,7 @@ struct adgi_volume {
   hipEvent_t ev_user = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_slot[kParamSlots] = {};
   hipEvent_t ev_stage = nullptr;
-  hipEvent_t ev_k[7] = {};
+  hipEvent_t ev_k[8] = {};
   int device = 0, num_cus = 256;
   int32_t P = 0;
   bool sticky = false;
@@ -220,9 +220,10 @@ bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
   return t.bvh_width == 4 && vol->d_nodes4 != nullptr;
 }
 
-// Stage boundaries recorded into ev[0..6] when ev is non-null (eager only):
+// Stage boundaries recorded into ev[0..7] when ev is non-null (eager only):
 // 0 start, 1 frame_begin, 2 pilot trace, 3 detect | chains, 4 allocate |
-// blend order, 5 probe trace, 6 blend. mode: ADGI_MODE_*. A counting run of a
+// blend order, 5 probe trace, 6 blend; 7 between the probe trace's
+// closest-hit and shading kernels. mode: ADGI_MODE_*. A counting run of a
 // chain frame traces the samples the last chain frame left.
 hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
                          bool count_work = false) {
@@ -239,7 +240,7 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
   if ((e = mark(1)) != hipSuccess) return e;
   if (chain && !count_work) {
     int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
-    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
+    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, pgrid, false, w4)) != hipSuccess)
       return e;
     // detection keeps triggers and scores current (odd frames); the dynamic
     // chains read the box sums on every frame
@@ -265,7 +266,7 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
     if ((e = mark(3)) != hipSuccess) return e;
   } else if (adaptive) {
     int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
-    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, false, w4)) != hipSuccess)
+    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, pgrid, false, w4)) != hipSuccess)
       return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_detect(v, s)) != hipSuccess) return e;
@@ -281,8 +282,8 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
   if (count_work && (e = launch_frame_begin(v, s)) != hipSuccess) return e;
   int grid = t.persistent ? pgrid
                           : (int)((vol->desc.max_rays_per_frame + t.trace_block - 1) / t.trace_block);
-  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, count_work, w4, chain)) !=
-      hipSuccess)
+  if ((e = launch_trace(v, s, false, t.persistent != 0, t.trace_block, grid, pgrid, count_work, w4, chain,
+                        ev ? ev[7] : nullptr)) != hipSuccess)
     return e;
   if ((e = mark(5)) != hipSuccess) return e;
   if (count_work) return hipSuccess;
@@ -569,6 +570,13 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.blk_off, (size_t)((P + 255) / 256) * 4},
       {(void**)&v.order, (size_t)P * 4},
       {(void**)&v.rec, R * 16},
+      {(void**)&v.hit_pos, std::max(R, (size_t)P * 8) * 16},
+      {(void**)&v.hit_nrm, std::max(R, (size_t)P * 8) * 16},
+      {(void**)&v.hit_vis, std::max(R, (size_t)P * 8) * 4},
+      {(void**)&v.pairs, (std::max(R, (size_t)P * 8) + 63) / 64 * kPairsPerBatch * 2},
+      {(void**)&v.pair_cnt, (std::max(R, (size_t)P * 8) + 63) / 64 * 4},
+      {(void**)&v.pair_off, ((std::max(R, (size_t)P * 8) + 63) / 64 + 1) * 4},
+      {(void**)&v.pair_blk, ((std::max(R, (size_t)P * 8) + 63) / 64 / kPairScanPer + 1) * 4},
   };
   if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)kPkDecSize * 4});
   if (d->max_chains > 0) {
@@ -639,6 +647,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.one_minus_h = (float)(1.0 - (double)d->hysteresis);
   v.tau_max = d->tau_max;
   v.max_rays = (uint32_t)R;
+  v.hit_cap = (uint32_t)std::max(R, (size_t)P * 8);
   if (blend_wave_supported(v)) vol->tun.blend_chunk = 0;
   if (d->blend_mode == ADGI_BLEND_GATHER) vol->tun.blend_chunk = 0;
   *out = vol;
@@ -1013,8 +1022,12 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       HIP_TRY(vol, hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1));
       stats->ms_total = ms;
       if (!vol->tun.use_graph || mode == ADGI_MODE_CHAIN)
+      {
         for (int k = 0; k < 6; ++k)
           HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[k], vol->ev_k[k], vol->ev_k[k + 1]));
+        HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[6], vol->ev_k[4], vol->ev_k[7]));
+        HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[7], vol->ev_k[7], vol->ev_k[5]));
+      }
     }
   }
   return ADGI_OK;
@@ -1282,6 +1295,8 @@ adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* 
   out->node_tests = (int64_t)vol->h_stats->node_tests;
   out->box_tests = out->node_tests * (use_bvh4(vol, vol->tun) ? 4 : 2);
   out->tri_tests = (int64_t)vol->h_stats->tri_tests;
+  out->shade_node_tests = (int64_t)vol->h_stats->shade_node_tests;
+  out->shade_tri_tests = (int64_t)vol->h_stats->shade_tri_tests;
   return adgi_restore_state(vol, snap.data(), snap.size());
 }
 
@@ -1345,7 +1360,9 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
       hipError_t e;
       if ((e = launch_frame_begin(vol->v, s)) != hipSuccess) return e;
       if ((e = hipEventRecord(vol->ev_t0, s)) != hipSuccess) return e;
-      if ((e = launch_trace(vol->v, s, false, c.persistent != 0, c.trace_block, grid, false, use_bvh4(vol, c))) !=
+      const int sgrid = std::max(1, vol->num_cus * c.trace_waves_per_cu / (c.trace_block / 64));
+      if ((e = launch_trace(vol->v, s, false, c.persistent != 0, c.trace_block, grid, sgrid, false,
+                            use_bvh4(vol, c))) !=
           hipSuccess)
         return e;
       if ((e = hipEventRecord(vol->ev_t1, s)) != hipSuccess) return e;

@@ -322,3 +322,47 @@ def test_query_irradiance_box_field_fp16():
     err, peak = _query_case(sc, adgi.ADGI_FP16, 22)
     print(err, peak)
     assert peak > 0 and err <= 1e-4
+
+
+@pytest.mark.parametrize("scene_name", ["cornell", "tunnel"])
+def test_shadow_ray_count_is_one_per_facing_light(scene_name):
+    """The frame's shadow-ray count is one ray per (front-face hit, light on
+    the hit surface's front side) pair. Recounted on the host in FP64 from the
+    GPU's hits (triangle, t) and the oracle's ray directions. A light in the
+    plane of the hit surface (cos = 0 exactly, as the Cornell light and the
+    z = 0.5 box face) is decided by rounding, so the count must lie between the
+    pairs with cos > 1e-5 and those with cos > -1e-5."""
+    import oracle
+    import paper_2301_05125_amd as adgi
+    sc = getattr(scenes, scene_name)()
+    P, n, seed = sc.num_probes, 64, 7
+    vol = adgi.volume_for_scene(sc, max_rays=P * n, seed=seed, debug=True)
+    try:
+        st = vol.update_probes(0, adaptive=False, n_uniform=n, sync=True)
+        rb = vol.read_probes(texels=False, debug=True)
+    finally:
+        vol.destroy_volume()
+    dirs = oracle.sf_dirs(n, oracle.frame_rotation(seed, 0))
+    dims = sc.grid_dims.astype(np.int64)
+    i = np.arange(P)
+    cell = np.stack([i % dims[0], (i // dims[0]) % dims[1], i // (dims[0] * dims[1])], axis=1)
+    origin = sc.grid_origin.astype(np.float64) + cell * sc.grid_spacing.astype(np.float64)
+    o = np.repeat(origin, n, axis=0)
+    d = np.tile(dirs, (P, 1))
+    tri, t = rb["hit_tri"][:P * n], rb["ray_record"][:P * n, 3].astype(np.float64)
+    hit = tri >= 0
+    V = sc.positions.astype(np.float64)
+    T = sc.indices[tri[hit]]
+    nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    front = np.einsum("ij,ij->i", nrm, d[hit]) < 0.0
+    x = o[hit] + t[hit, None] * d[hit]
+    to_l = sc.light_positions(0).astype(np.float64)[None, :, :] - x[:, None, :]
+    cos = np.einsum("ij,ilj->il", nrm, to_l) / (
+        np.linalg.norm(nrm, axis=1)[:, None] * np.linalg.norm(to_l, axis=2))
+    lo = int(np.count_nonzero(cos[front] > 1e-5))
+    hi = int(np.count_nonzero(cos[front] > -1e-5))
+    visible = int(np.unpackbits(rb["shadow_bits"][:P * n]).sum())
+    got = int(st["shadow_rays"])
+    print(scene_name, "counted", got, "clear", lo, "with boundary", hi, "visible", visible)
+    assert visible <= got
+    assert lo <= got <= hi, (lo, got, hi)
