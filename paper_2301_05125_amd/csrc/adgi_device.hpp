@@ -233,7 +233,6 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, float4 a, float4 b, float4
   float py = r.d.z * e2.x - r.d.x * e2.z;
   float pz = r.d.x * e2.y - r.d.y * e2.x;
   float det = e1.x * px + e1.y * py + e1.z * pz;
-  if (det == 0.0f) return false;
   float tx = r.o.x - v0.x, ty = r.o.y - v0.y, tz = r.o.z - v0.z;
   float U = tx * px + ty * py + tz * pz;
   float qx = ty * e1.z - tz * e1.y;
@@ -246,8 +245,11 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, float4 a, float4 b, float4
   U *= sg;
   V *= sg;
   float Ts = T * sg;
-  if (U < 0.0f || V < 0.0f || U + V > adet) return false;
-  if (Ts <= tmin * adet || Ts > tmax * adet) return false;
+  // every reject test evaluated (no short circuit), one branch: the same
+  // decisions as testing them in turn, with less control flow per triangle
+  const bool reject = (det == 0.0f) | (U < 0.0f) | (V < 0.0f) | (U + V > adet) | (Ts <= tmin * adet) |
+                      (Ts > tmax * adet);
+  if (reject) return false;
   t_out = T / det;
   if (!(t_out > tmin && t_out <= tmax)) return false;
   front = det > 0.0f;  // (e1 x e2) . d < 0

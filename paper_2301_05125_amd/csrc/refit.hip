@@ -2,10 +2,13 @@
 //
 // 1. Rebuild every triangle record (v0, e1, e2) from the current positions.
 // 2. Refit the boxes level by level from the deepest internal nodes to the
-//    root, one launch per level: a node's child slot gets the (padded) bounds
-//    of its leaf triangles, or the union of the internal child's two slots,
-//    which the previous launch finished. Kernel boundaries order the levels,
-//    so no cross-workgroup atomics or cache maintenance are needed.
+//    root: a node's child slot gets the (padded) bounds of its leaf
+//    triangles, or the union of the internal child's two slots, which the
+//    previous level finished. A level with many nodes gets a launch of its
+//    own; a run of consecutive small levels (the thin bottom of the tree, the
+//    top) runs in one workgroup with a barrier between levels. Kernel
+//    boundaries and barriers order the levels, so no cross-workgroup atomics
+//    or cache maintenance are needed.
 #include "adgi_internal.hpp"
 
 namespace adgi {
@@ -34,10 +37,7 @@ __device__ __forceinline__ void write_slot(float4* node, int side, const float* 
   f[b + 5] = hi[2];
 }
 
-__global__ void refit_level_kernel(RefitView r, const int32_t* __restrict__ nodes_of_level, int count) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= count) return;
-  const int g = nodes_of_level[q];
+__device__ __forceinline__ void refit_node(const RefitView& r, int g) {
   const int* meta = (const int*)(r.nodes + 4 * (size_t)g + 3);
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -74,15 +74,52 @@ __global__ void refit_level_kernel(RefitView r, const int32_t* __restrict__ node
   }
 }
 
+__global__ void refit_level_kernel(RefitView r, const int32_t* __restrict__ nodes_of_level, int count) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < count) refit_node(r, nodes_of_level[q]);
+}
+
+// Consecutive levels of at most kRefitSmall nodes, deepest first: level k
+// holds level_nodes[lo[k], hi[k]).
+constexpr int kRefitSmall = 1024;
+constexpr int kRefitRunMax = 64;
+struct RefitRun {
+  int n;
+  int lo[kRefitRunMax], hi[kRefitRunMax];
+};
+
+__global__ __launch_bounds__(kRefitSmall) void refit_run_kernel(RefitView r, RefitRun run) {
+  for (int k = 0; k < run.n; ++k) {
+    for (int q = run.lo[k] + (int)threadIdx.x; q < run.hi[k]; q += (int)blockDim.x)
+      refit_node(r, r.level_nodes[q]);
+    __syncthreads();
+  }
+}
+
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s) {
   if (r.num_tris == 0) return hipSuccess;
   hipLaunchKernelGGL(refit_tris_kernel, dim3((r.num_tris + 255) / 256), dim3(256), 0, s, r);
+  RefitRun run;
+  run.n = 0;
+  auto flush = [&]() {
+    if (run.n > 0) hipLaunchKernelGGL(refit_run_kernel, dim3(1), dim3(kRefitSmall), 0, s, r, run);
+    run.n = 0;
+  };
   for (int d = (int)level_offsets.size() - 2; d >= 0; --d) {
     const int b = level_offsets[d], cnt = level_offsets[d + 1] - b;
     if (cnt <= 0) continue;
+    if (cnt <= kRefitSmall) {
+      if (run.n == kRefitRunMax) flush();
+      run.lo[run.n] = b;
+      run.hi[run.n] = b + cnt;
+      ++run.n;
+      continue;
+    }
+    flush();
     hipLaunchKernelGGL(refit_level_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, r,
                        r.level_nodes + b, cnt);
   }
+  flush();
   return hipGetLastError();
 }
 

@@ -348,6 +348,17 @@ __device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack&
 }
 
 
+// First probe i in [lo, hi] with offsets[i+1] > r (offsets ascending,
+// offsets[0] = 0; the answer lies in the window).
+__device__ __forceinline__ int probe_in(const uint32_t* __restrict__ off, int lo, int hi, uint32_t r) {
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // First probe i with offsets[i+1] > r (offsets ascending, offsets[0] = 0).
 __device__ __forceinline__ int probe_of_ray(const uint32_t* __restrict__ off, int P, uint32_t r) {
   int lo = 0, hi = P - 1;
@@ -374,13 +385,15 @@ __device__ __forceinline__ uint32_t ray_total(const VolumeView& v) {
 }
 
 // Origin and direction of ray r; `shade` is false for the distance-only rays
-// of chain frames.
+// of chain frames. Probe rays: i0 is the probe of a ray at most 63 before r
+// (every probe has at least one ray, so r's probe is within i0 + 63).
 template <int KIND>
-__device__ __forceinline__ void gen_ray(const VolumeView& v, uint32_t r, float3& o, float3& d, bool& shade) {
+__device__ __forceinline__ void gen_ray(const VolumeView& v, uint32_t r, int i0, float3& o, float3& d,
+                                        bool& shade) {
   const FrameParams& fp = *v.fp;
   shade = true;
   if (KIND == KIND_PRIMARY) {
-    int i = probe_of_ray(v.offsets, v.P, r);
+    int i = probe_in(v.offsets, i0, min(i0 + 63, v.P - 1), r);
     uint32_t b = v.offsets[i], n = v.offsets[i + 1] - b;
     o = probe_position(v, i);
     d = sf_direction(r - b, n, fp.R);
@@ -508,7 +521,9 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
   const bool active = r < total;
   float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
   bool shade = true;
-  if (active) gen_ray<KIND>(v, r, o, d, shade);
+  // probe of the batch's first ray (the same in every lane)
+  const int i0 = KIND == KIND_PRIMARY ? probe_of_ray(v.offsets, v.P, b * 64u) : 0;
+  if (active) gen_ray<KIND>(v, r, i0, o, d, shade);
   float t = INFINITY;
   bool front = false;
   int id = -1, slot = -1;
