@@ -29,23 +29,23 @@ __device__ __forceinline__ uint32_t extra_rays(uint32_t lambda, uint32_t w, uint
   return min(E, __umulhi(lambda, w));
 }
 
-// Interval [lo, hi] containing lambda* after `passes` narrowing passes.
-__device__ void replay_interval(const FrameStats* st, int passes, int64_t Bp, uint32_t& lo,
-                                uint32_t& hi) {
+// Interval [lo, hi] containing lambda* after `passes` narrowing passes,
+// replayed by all kAllocCandidates threads of a block together: candidate m of
+// a pass is kept when it lies in the interval and its sum fits the budget,
+// and since the sums grow with m the kept candidates are m = 1..m_best, so
+// m_best is their count.
+__device__ void replay_interval(const FrameStats* st, int passes, int64_t Bp, uint32_t& lo, uint32_t& hi) {
   lo = 0u;
   hi = 1u << 31;
+  const int m = (int)threadIdx.x;
   for (int p = 0; p < passes; ++p) {
-    uint32_t step = (uint32_t)(((uint64_t)hi - lo + 1 + kAllocCandidates - 1) / kAllocCandidates);
-    int m_best = 0;
-    for (int m = 1; m < kAllocCandidates; ++m) {
-      uint64_t c = (uint64_t)lo + (uint64_t)m * step;
-      if (c > hi) break;
-      if ((int64_t)st->sums[p][m] <= Bp) m_best = m;
-      else break;
-    }
-    uint64_t nlo = (uint64_t)lo + (uint64_t)m_best * step;
-    uint64_t nxt = nlo + step;
-    uint32_t nhi = (m_best + 1 < kAllocCandidates && nxt <= hi) ? (uint32_t)(nxt - 1) : hi;
+    const uint32_t step = (uint32_t)(((uint64_t)hi - lo + 1 + kAllocCandidates - 1) / kAllocCandidates);
+    const uint64_t c = (uint64_t)lo + (uint64_t)m * step;
+    const bool keep = m >= 1 && m < kAllocCandidates && c <= hi && (int64_t)st->sums[p][m] <= Bp;
+    const int m_best = __syncthreads_count(keep);
+    const uint64_t nlo = (uint64_t)lo + (uint64_t)m_best * step;
+    const uint64_t nxt = nlo + step;
+    const uint32_t nhi = (m_best + 1 < kAllocCandidates && nxt <= hi) ? (uint32_t)(nxt - 1) : hi;
     lo = (uint32_t)nlo;
     hi = nhi;
   }
@@ -71,20 +71,14 @@ __global__ __launch_bounds__(256) void lambda_pass_kernel(VolumeView v, int pass
   const FrameParams& fp = *v.fp;
   if (!fp.adaptive) return;
   __shared__ uint32_t w_s[256];
-  __shared__ uint32_t iv[2];
   const int64_t Bp = fp.budget - (int64_t)v.P * fp.n_min;
   const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
-  if (threadIdx.x == 0) {
-    uint32_t lo, hi;
-    replay_interval(v.stats, pass, Bp, lo, hi);
-    iv[0] = lo;
-    iv[1] = hi;
-  }
+  uint32_t lo, hi;
+  replay_interval(v.stats, pass, Bp, lo, hi);
   const uint64_t maxs = v.stats->max_score;
   const int i = blockIdx.x * 256 + threadIdx.x;
   w_s[threadIdx.x] = i < v.P ? weight_of((uint64_t)v.score[i], maxs) : 0u;
   __syncthreads();
-  const uint32_t lo = iv[0], hi = iv[1];
   const uint32_t step = (uint32_t)(((uint64_t)hi - lo + 1 + kAllocCandidates - 1) / kAllocCandidates);
   const int m = threadIdx.x;
   if (m == 0) return;
@@ -175,18 +169,12 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(VolumeView v) {
 __global__ __launch_bounds__(256) void alloc_blocks_kernel(VolumeView v) {
   const FrameParams& fp = *v.fp;
   if (!fp.adaptive) return;
-  __shared__ uint32_t lam_s;
   __shared__ int64_t red_e[4];
   __shared__ uint32_t red_el[4];
   const int64_t Bp = fp.budget - (int64_t)v.P * fp.n_min;
   const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
-  if (threadIdx.x == 0) {
-    uint32_t lo, hi;
-    replay_interval(v.stats, kAllocPasses, Bp, lo, hi);
-    lam_s = lo;
-  }
-  __syncthreads();
-  const uint32_t lam = lam_s;
+  uint32_t lam, hi;
+  replay_interval(v.stats, kAllocPasses, Bp, lam, hi);
   const int i = blockIdx.x * 256 + threadIdx.x;
   int64_t e0 = 0;
   uint32_t el = 0;
@@ -282,11 +270,23 @@ __global__ __launch_bounds__(256) void alloc_write_kernel(VolumeView v) {
     nmin = nmax = n;
   }
   count_buckets(v, i < v.P, n, hist);
+  // block minimum and maximum, then one atomic each per block (a per-wave
+  // atomic on these two words serialises about a thousand times per frame)
+  __shared__ int red_min[4], red_max[4];
   for (int o = 32; o > 0; o >>= 1) {
     nmin = min(nmin, __shfl_xor(nmin, o));
     nmax = max(nmax, __shfl_xor(nmax, o));
   }
   if ((threadIdx.x & 63) == 0) {
+    red_min[threadIdx.x >> 6] = nmin;
+    red_max[threadIdx.x >> 6] = nmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      nmin = min(nmin, red_min[k]);
+      nmax = max(nmax, red_max[k]);
+    }
     atomicMin(&v.stats->n_min_seen, nmin);
     atomicMax(&v.stats->n_max_seen, nmax);
   }
