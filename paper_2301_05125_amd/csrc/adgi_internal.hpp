@@ -86,10 +86,23 @@ struct RefitView {
   const int32_t* tri_order;    // slot -> original triangle
   float4* tris;                // [T][3]
   float4* nodes;               // [N][4]
-  const int32_t* level_nodes;  // node indices grouped by depth
+  const int32_t* level_nodes;  // node indices grouped by depth (RefitPlan order)
   int32_t num_tris;
   int32_t num_nodes;
   float pad_abs;
+  const int32_t* tab;          // RefitPlan::tab on the device
+  int32_t cut, subtrees, deep_levels;
+};
+// Refit plan of a BVH2: the internal nodes at depth >= cut are grouped, in
+// every level, by their ancestor at depth `cut` (one subtree per workgroup,
+// all its levels in one launch); the levels above are refit separately.
+// tab[(d - cut) * (subtrees + 1) + s] is where subtree s starts in level d's
+// part of level_nodes (s = subtrees: the level's end). cut = 0: no deep part.
+struct RefitPlan {
+  int32_t cut = 0, subtrees = 0, deep_levels = 0;
+  std::vector<int32_t> level_nodes;
+  std::vector<int32_t> level_offsets;  // size levels + 1
+  std::vector<int32_t> tab;
 };
 // level_offsets[d] .. level_offsets[d+1] index level_nodes for depth d
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s);
@@ -109,6 +122,7 @@ struct BvhHost {
 };
 bool build_bvh(const float* positions, int32_t nv, const int32_t* indices, int32_t nt, float pad_abs,
                BvhHost& out, const char** err);
+void plan_refit(const BvhHost& bvh, RefitPlan& plan);
 // BVH4 collapse of a BVH2 (node layout in adgi_layout.hpp), nodes in
 // depth-first order. src[4n+k] = 2*g + side names the BVH2 child slot that
 // child k of node n copies (-1: empty), so a refit of the BVH2 is carried over

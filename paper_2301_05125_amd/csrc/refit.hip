@@ -1,15 +1,19 @@
 // refit.hip - device BVH refit after vertex motion (same topology).
 //
 // 1. Rebuild every triangle record (v0, e1, e2) from the current positions.
-// 2. Refit the boxes level by level from the deepest internal nodes to the
-//    root: a node's child slot gets the (padded) bounds of its leaf
-//    triangles, or the union of the internal child's two slots, which the
-//    previous level finished. A level with many nodes gets a launch of its
-//    own; a run of consecutive small levels (the thin bottom of the tree, the
-//    top) runs in one workgroup with a barrier between levels. Kernel
-//    boundaries and barriers order the levels, so no cross-workgroup atomics
-//    or cache maintenance are needed.
+// 2. Refit the boxes from the deepest internal nodes to the root: a node's
+//    child slot gets the (padded) bounds of its leaf triangles, or the union
+//    of the internal child's two slots, which a deeper level finished. The
+//    levels below a cut depth run in one launch, one workgroup per subtree
+//    rooted at the cut, level after level with a barrier between them (a
+//    subtree only reads its own nodes); the levels above the cut follow, runs
+//    of small levels in one workgroup, a large level in a launch of its own.
+//    Kernel boundaries and barriers order the levels, so no cross-workgroup
+//    atomics or cache maintenance are needed.
 #include "adgi_internal.hpp"
+
+#include <algorithm>
+#include <cstring>
 
 namespace adgi {
 
@@ -96,16 +100,69 @@ __global__ __launch_bounds__(kRefitSmall) void refit_run_kernel(RefitView r, Ref
   }
 }
 
+// One workgroup per subtree rooted at depth r.cut: its nodes of every deeper
+// level, deepest first.
+__global__ __launch_bounds__(256) void refit_deep_kernel(RefitView r) {
+  const int sub = blockIdx.x, stride = r.subtrees + 1;
+  for (int k = r.deep_levels - 1; k >= 0; --k) {
+    const int lo = r.tab[k * stride + sub], hi = r.tab[k * stride + sub + 1];
+    for (int q = lo + (int)threadIdx.x; q < hi; q += (int)blockDim.x) refit_node(r, r.level_nodes[q]);
+    __syncthreads();
+  }
+}
+
+// Cut depth: levels 0..kRefitCut-1 (at most 2^d nodes each) stay above it.
+constexpr int kRefitCut = 10;
+
+void plan_refit(const BvhHost& bvh, RefitPlan& p) {
+  p.level_nodes = bvh.level_nodes;
+  p.level_offsets = bvh.level_offsets;
+  p.tab.clear();
+  p.cut = p.subtrees = p.deep_levels = 0;
+  const int levels = (int)bvh.level_offsets.size() - 1;
+  if (levels <= kRefitCut) return;
+  const int cut = kRefitCut;
+  const int S = bvh.level_offsets[cut + 1] - bvh.level_offsets[cut];
+  if (S <= 0) return;
+  const size_t nn = bvh.nodes.size() / 4;
+  std::vector<int32_t> sub(nn, -1);
+  for (int s = 0; s < S; ++s) sub[bvh.level_nodes[bvh.level_offsets[cut] + s]] = s;
+  for (int d = cut + 1; d < levels; ++d)
+    for (int q = bvh.level_offsets[d]; q < bvh.level_offsets[d + 1]; ++q) {
+      const int g = bvh.level_nodes[q];
+      int par;
+      std::memcpy(&par, &bvh.nodes[4 * (size_t)g + 3].z, 4);
+      sub[g] = sub[par];
+    }
+  p.cut = cut;
+  p.subtrees = S;
+  p.deep_levels = levels - cut;
+  p.tab.assign((size_t)p.deep_levels * (S + 1), 0);
+  for (int d = cut; d < levels; ++d) {
+    const int b = bvh.level_offsets[d], e = bvh.level_offsets[d + 1];
+    std::stable_sort(p.level_nodes.begin() + b, p.level_nodes.begin() + e,
+                     [&](int32_t x, int32_t y) { return sub[x] < sub[y]; });
+    int32_t* t = &p.tab[(size_t)(d - cut) * (S + 1)];
+    int q = b;
+    for (int s = 0; s <= S; ++s) {
+      while (q < e && sub[p.level_nodes[q]] < s) ++q;
+      t[s] = q;
+    }
+  }
+}
+
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s) {
   if (r.num_tris == 0) return hipSuccess;
   hipLaunchKernelGGL(refit_tris_kernel, dim3((r.num_tris + 255) / 256), dim3(256), 0, s, r);
+  if (r.subtrees > 0) hipLaunchKernelGGL(refit_deep_kernel, dim3(r.subtrees), dim3(256), 0, s, r);
   RefitRun run;
   run.n = 0;
   auto flush = [&]() {
     if (run.n > 0) hipLaunchKernelGGL(refit_run_kernel, dim3(1), dim3(kRefitSmall), 0, s, r, run);
     run.n = 0;
   };
-  for (int d = (int)level_offsets.size() - 2; d >= 0; --d) {
+  const int top = r.subtrees > 0 ? r.cut : (int)level_offsets.size() - 1;
+  for (int d = top - 1; d >= 0; --d) {
     const int b = level_offsets[d], cnt = level_offsets[d + 1] - b;
     if (cnt <= 0) continue;
     if (cnt <= kRefitSmall) {

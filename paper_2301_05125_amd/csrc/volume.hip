@@ -118,6 +118,11 @@ struct adgi_volume {
   adgi_allocator alloc{};
   hipStream_t user_stream = nullptr;
   hipStream_t stream = nullptr;
+  // Scene uploads and refits run on a stream of their own, after the last
+  // frame's trace (ev_traced) and before the next frame (ev_refit), so the
+  // refit overlaps the last frame's blend, which does not read the scene.
+  hipStream_t scene_stream = nullptr;
+  hipEvent_t ev_traced = nullptr, ev_refit = nullptr;
   hipEvent_t ev_user = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_slot[kParamSlots] = {};
   hipEvent_t ev_stage = nullptr;
@@ -146,6 +151,8 @@ struct adgi_volume {
   int32_t* d_order = nullptr;
   int32_t* d_levels = nullptr;
   std::vector<int32_t> level_offsets;
+  int32_t* d_refit_tab = nullptr;                    // RefitPlan::tab
+  int32_t refit_cut = 0, refit_subtrees = 0, refit_deep = 0;
   hipGraphExec_t refit_exec = nullptr;
   float4* d_nodes = nullptr;
   float4* d_nodes4 = nullptr;   // BVH4 collapse (null when its stack bound does not fit)
@@ -159,7 +166,8 @@ struct adgi_volume {
   int bvh_depth = 0;
   double last_build_ms = 0.0;
   // frame
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};        // frame up to the probe trace
+  hipGraphExec_t exec_blend[2] = {nullptr, nullptr};  // its blend
   adgi_tuning tun{};
   bool tuned = false;
   int32_t last_frame = -1, last_adaptive = 0;
@@ -209,11 +217,23 @@ void vol_free(adgi_volume* vol, void* p) {
 }
 
 void drop_graphs(adgi_volume* vol) {
-  for (auto& e : vol->exec)
-    if (e) {
-      (void)hipGraphExecDestroy(e);
-      e = nullptr;
-    }
+  for (auto* set : {vol->exec, vol->exec_blend})
+    for (int k = 0; k < 2; ++k)
+      if (set[k]) {
+        (void)hipGraphExecDestroy(set[k]);
+        set[k] = nullptr;
+      }
+}
+
+// The texel blend of the frame's rays (reads the records, probe counts,
+// offsets and blend order; not the scene).
+hipError_t enqueue_blend(adgi_volume* vol, int mode, hipStream_t s) {
+  const adgi_tuning& t = vol->tun;
+  const bool chain = mode == ADGI_MODE_CHAIN;
+  BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
+  const bool gather = vol->desc.blend_mode == ADGI_BLEND_GATHER;
+  return launch_blend(vol->v, io, s, vol->desc.storage, chain || gather ? 0 : t.blend_chunk,
+                      vol->num_cus * t.blend_blocks_per_cu, chain, gather);
 }
 
 bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
@@ -224,9 +244,12 @@ bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
 // 0 start, 1 frame_begin, 2 pilot trace, 3 detect | chains, 4 allocate |
 // blend order, 5 probe trace, 6 blend; 7 between the probe trace's
 // closest-hit and shading kernels. mode: ADGI_MODE_*. A counting run of a
-// chain frame traces the samples the last chain frame left.
+// chain frame traces the samples the last chain frame left. part: 0 the
+// whole frame, 1 up to the probe trace, 2 the blend alone (graphs are
+// captured in these two parts). `traced`, when given, is recorded after the
+// probe trace (the scene is free from there on).
 hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
-                         bool count_work = false) {
+                         bool count_work = false, hipEvent_t traced = nullptr, int part = 0) {
   const adgi_tuning& t = vol->tun;
   VolumeView& v = vol->v;
   hipStream_t s = vol->stream;
@@ -235,6 +258,7 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
   const bool adaptive = mode == ADGI_MODE_ADAPTIVE, chain = mode == ADGI_MODE_CHAIN;
   const int pgrid = std::max(1, vol->num_cus * t.trace_waves_per_cu / (t.trace_block / 64));
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  if (part == 2) return enqueue_blend(vol, mode, s);
   if ((e = mark(0)) != hipSuccess) return e;
   if ((e = launch_frame_begin(v, s)) != hipSuccess) return e;
   if ((e = mark(1)) != hipSuccess) return e;
@@ -286,12 +310,9 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
                         ev ? ev[7] : nullptr)) != hipSuccess)
     return e;
   if ((e = mark(5)) != hipSuccess) return e;
-  if (count_work) return hipSuccess;
-  BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
-  const bool gather = vol->desc.blend_mode == ADGI_BLEND_GATHER;
-  if ((e = launch_blend(v, io, s, vol->desc.storage, chain || gather ? 0 : t.blend_chunk,
-                        vol->num_cus * t.blend_blocks_per_cu, chain, gather)) != hipSuccess)
-    return e;
+  if (traced && (e = hipEventRecord(traced, s)) != hipSuccess) return e;
+  if (count_work || part == 1) return hipSuccess;
+  if ((e = enqueue_blend(vol, mode, s)) != hipSuccess) return e;
   return mark(6);
 }
 
@@ -299,11 +320,16 @@ adgi_status order_after_user(adgi_volume* vol) {
   if (vol->user_stream) {
     HIP_TRY(vol, hipEventRecord(vol->ev_user, vol->user_stream));
     HIP_TRY(vol, hipStreamWaitEvent(vol->stream, vol->ev_user, 0));
+    HIP_TRY(vol, hipStreamWaitEvent(vol->scene_stream, vol->ev_user, 0));
   }
   return ADGI_OK;
 }
 
-adgi_status order_user_after(adgi_volume* vol) {
+// `scene_free`: everything queued so far may read the scene, so a later
+// scene update waits for all of it (update_probes marks the point itself,
+// before its blend).
+adgi_status order_user_after(adgi_volume* vol, bool scene_free = true) {
+  if (scene_free) HIP_TRY(vol, hipEventRecord(vol->ev_traced, vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_done, vol->stream));
   if (vol->user_stream) HIP_TRY(vol, hipStreamWaitEvent(vol->user_stream, vol->ev_done, 0));
   return ADGI_OK;
@@ -317,8 +343,9 @@ void free_scene(adgi_volume* vol) {
   for (void* p : vol->scene_allocs) vol_free(vol, p);
   vol->scene_allocs.clear();
   vol->d_pos = nullptr;
-  vol->d_idx = vol->d_order = vol->d_levels = nullptr;
+  vol->d_idx = vol->d_order = vol->d_levels = vol->d_refit_tab = nullptr;
   vol->level_offsets.clear();
+  vol->refit_cut = vol->refit_subtrees = vol->refit_deep = 0;
   vol->d_nodes = vol->d_tris = vol->d_albedo = nullptr;
   vol->d_nodes4 = nullptr;
   vol->d_src4 = nullptr;
@@ -332,6 +359,7 @@ void free_scene(adgi_volume* vol) {
 }
 
 void release(adgi_volume* vol) {
+  if (vol->scene_stream) (void)hipStreamSynchronize(vol->scene_stream);
   if (vol->stream) (void)hipStreamSynchronize(vol->stream);
   drop_graphs(vol);
   free_scene(vol);
@@ -343,9 +371,11 @@ void release(adgi_volume* vol) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : vol->ev_k)
     if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage})
+  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage, vol->ev_traced,
+                      vol->ev_refit})
     if (e) (void)hipEventDestroy(e);
   if (vol->stream) (void)hipStreamDestroy(vol->stream);
+  if (vol->scene_stream) (void)hipStreamDestroy(vol->scene_stream);
 }
 
 // Bytes of one probe's irradiance / depth tile (with border) in HBM.
@@ -528,8 +558,11 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   CREATE_TRY(hipGetDevice(&vol->device));
   CREATE_TRY(hipDeviceGetAttribute(&vol->num_cus, hipDeviceAttributeMultiprocessorCount, vol->device));
   CREATE_TRY(hipStreamCreateWithFlags(&vol->stream, hipStreamNonBlocking));
+  CREATE_TRY(hipStreamCreateWithFlags(&vol->scene_stream, hipStreamNonBlocking));
   for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_t0, &vol->ev_t1, &vol->ev_stage})
     CREATE_TRY(hipEventCreate(e));
+  for (hipEvent_t* e : {&vol->ev_traced, &vol->ev_refit})
+    CREATE_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   for (auto& e : vol->ev_slot) CREATE_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : vol->ev_k) CREATE_TRY(hipEventCreate(&e));
   CREATE_TRY(hipHostMalloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots, hipHostMallocDefault));
@@ -615,6 +648,8 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   }
   // zero the temporal state
   for (auto& r : reqs) CREATE_TRY(hipMemsetAsync(*r.p, 0, r.bytes, vol->stream));
+  CREATE_TRY(hipEventRecord(vol->ev_traced, vol->stream));
+  CREATE_TRY(hipEventRecord(vol->ev_refit, vol->stream));
   if (d->storage == ADGI_PACKED) CREATE_TRY(launch_packed_decode_table((float*)v.pk_dec, vol->stream));
   // the tables go after the zero fill on the volume's (non-blocking) stream;
   // tb lives until the synchronisation below
@@ -725,6 +760,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
 
   adgi_status st = order_after_user(vol);
   if (st != ADGI_OK) return st;
+  hipStream_t ss = vol->scene_stream;
   // scene constants: staged in pinned memory; the previous copy must be done
   HIP_TRY(vol, hipEventSynchronize(vol->ev_stage));
   SceneParams& hp = *vol->h_scene;
@@ -751,6 +787,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     const bool fits4 = built->fits4;
     const float pad_abs = built->pad_abs;
     vol->last_build_ms = built->build_ms;
+    HIP_TRY(vol, hipStreamSynchronize(ss));
     HIP_TRY(vol, hipStreamSynchronize(vol->stream));
     drop_graphs(vol);
     free_scene(vol);
@@ -760,7 +797,10 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     vol->d_pos = (float*)vol_alloc(vol, (size_t)nv * 12, &g);
     vol->d_idx = (int32_t*)vol_alloc(vol, (size_t)nt * 12, &g);
     vol->d_order = (int32_t*)vol_alloc(vol, (size_t)nt * 4, &g);
-    vol->d_levels = (int32_t*)vol_alloc(vol, bvh.level_nodes.size() * 4, &g);
+    RefitPlan plan;
+    plan_refit(bvh, plan);
+    vol->d_levels = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.level_nodes.size(), 1) * 4, &g);
+    vol->d_refit_tab = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.tab.size(), 1) * 4, &g);
     vol->d_nodes = (float4*)vol_alloc(vol, bvh.nodes.size() * 16, &g);
     vol->d_tris = (float4*)vol_alloc(vol, std::max<size_t>(bvh.tris.size(), 3) * 16, &g);
     vol->d_albedo = (float4*)vol_alloc(vol, (size_t)std::max(nt, 1) * 16, &g);
@@ -768,7 +808,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
       vol->d_nodes4 = (float4*)vol_alloc(vol, bvh4.nodes.size() * 16, &g);
       vol->d_src4 = (int32_t*)vol_alloc(vol, bvh4.src.size() * 4, &g);
     }
-    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_nodes ||
+    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_refit_tab || !vol->d_nodes ||
         !vol->d_tris || !vol->d_albedo || (fits4 && (!vol->d_nodes4 || !vol->d_src4))) {
       free_scene(vol);
       vol->has_scene = false;
@@ -783,10 +823,15 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
       HIP_TRY(vol, hipMemcpy(vol->d_order, bvh.tri_order.data(), (size_t)nt * 4, hipMemcpyHostToDevice));
       HIP_TRY(vol, hipMemcpy(vol->d_tris, bvh.tris.data(), bvh.tris.size() * 16, hipMemcpyHostToDevice));
     }
-    if (!bvh.level_nodes.empty())
-      HIP_TRY(vol, hipMemcpy(vol->d_levels, bvh.level_nodes.data(), bvh.level_nodes.size() * 4,
+    if (!plan.level_nodes.empty())
+      HIP_TRY(vol, hipMemcpy(vol->d_levels, plan.level_nodes.data(), plan.level_nodes.size() * 4,
                              hipMemcpyHostToDevice));
-    vol->level_offsets = bvh.level_offsets;
+    if (!plan.tab.empty())
+      HIP_TRY(vol, hipMemcpy(vol->d_refit_tab, plan.tab.data(), plan.tab.size() * 4, hipMemcpyHostToDevice));
+    vol->level_offsets = plan.level_offsets;
+    vol->refit_cut = plan.cut;
+    vol->refit_subtrees = plan.subtrees;
+    vol->refit_deep = plan.deep_levels;
     HIP_TRY(vol, hipMemcpy(vol->d_nodes, bvh.nodes.data(), bvh.nodes.size() * 16, hipMemcpyHostToDevice));
     HIP_TRY(vol, hipMemcpy(vol->d_albedo, alb.data(), alb.size() * 16, hipMemcpyHostToDevice));
     if (fits4) {
@@ -815,17 +860,24 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     if (cnt) {
       std::memcpy(vol->h_stage + 3 * vb, sc->positions + 3 * vb, cnt * 4);
       HIP_TRY(vol, hipMemcpyAsync(vol->d_pos + 3 * vb, vol->h_stage + 3 * vb, cnt * 4,
-                                  hipMemcpyHostToDevice, vol->stream));
-      // the refit (one launch per BVH level) is captured once per build
+                                  hipMemcpyHostToDevice, ss));
+    }
+    // the positions are read by the refit alone; triangles, nodes and lights
+    // change only after the queued work that reads them
+    HIP_TRY(vol, hipStreamWaitEvent(ss, vol->ev_traced, 0));
+    if (cnt) {
+      // the refit is captured once per build
       if (!vol->refit_exec) {
-        RefitView r{vol->d_pos, vol->d_idx, vol->d_order, vol->d_tris, vol->d_nodes, vol->d_levels,
-                    vol->nt, vol->num_nodes, vol->pad_abs};
+        RefitView r{vol->d_pos,   vol->d_idx,     vol->d_order,         vol->d_tris,
+                    vol->d_nodes, vol->d_levels,  vol->nt,              vol->num_nodes,
+                    vol->pad_abs, vol->d_refit_tab, vol->refit_cut, vol->refit_subtrees,
+                    vol->refit_deep};
         hipGraph_t graph = nullptr;
-        HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
-        hipError_t e = launch_refit(r, vol->level_offsets, vol->stream);
+        HIP_TRY(vol, hipStreamBeginCapture(ss, hipStreamCaptureModeRelaxed));
+        hipError_t e = launch_refit(r, vol->level_offsets, ss);
         if (e == hipSuccess && vol->d_nodes4)
-          e = launch_bvh4_gather(vol->d_nodes4, vol->d_src4, vol->num_nodes4, vol->d_nodes, vol->stream);
-        hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
+          e = launch_bvh4_gather(vol->d_nodes4, vol->d_src4, vol->num_nodes4, vol->d_nodes, ss);
+        hipError_t e2 = hipStreamEndCapture(ss, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
           if (graph) (void)hipGraphDestroy(graph);
           vol->sticky = true;
@@ -839,12 +891,14 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
           return fail(ADGI_ERR_DEVICE, "refit graph instantiate failed: %s", hipGetErrorString(e3));
         }
       }
-      HIP_TRY(vol, hipGraphLaunch(vol->refit_exec, vol->stream));
+      HIP_TRY(vol, hipGraphLaunch(vol->refit_exec, ss));
     }
   }
-  HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice,
-                              vol->stream));
-  HIP_TRY(vol, hipEventRecord(vol->ev_stage, vol->stream));
+  HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice, ss));
+  HIP_TRY(vol, hipEventRecord(vol->ev_stage, ss));
+  // every later use of the volume's stream follows the new scene
+  HIP_TRY(vol, hipEventRecord(vol->ev_refit, ss));
+  HIP_TRY(vol, hipStreamWaitEvent(vol->stream, vol->ev_refit, 0));
   vol->has_scene = true;
   return order_user_after(vol);
 }
@@ -973,10 +1027,12 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
   if (vol->tun.use_graph && mode != ADGI_MODE_CHAIN) {
-    if (!vol->exec[mode]) {
+    for (int part = 1; part <= 2; ++part) {
+      hipGraphExec_t& ex = part == 1 ? vol->exec[mode] : vol->exec_blend[mode];
+      if (ex) continue;
       hipGraph_t graph = nullptr;
       HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
-      hipError_t e = enqueue_frame(vol, mode);
+      hipError_t e = enqueue_frame(vol, mode, nullptr, false, nullptr, part);
       hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -984,7 +1040,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
         return fail(ADGI_ERR_DEVICE, "frame capture failed: %s / %s", hipGetErrorString(e),
                     hipGetErrorString(e2));
       }
-      hipError_t e3 = hipGraphInstantiate(&vol->exec[mode], graph, nullptr, nullptr, 0);
+      hipError_t e3 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e3 != hipSuccess) {
         vol->sticky = true;
@@ -992,14 +1048,16 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       }
     }
     HIP_TRY(vol, hipGraphLaunch(vol->exec[mode], vol->stream));
+    HIP_TRY(vol, hipEventRecord(vol->ev_traced, vol->stream));
+    HIP_TRY(vol, hipGraphLaunch(vol->exec_blend[mode], vol->stream));
   } else {
-    HIP_TRY(vol, enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr));
+    HIP_TRY(vol, enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr, false, vol->ev_traced));
   }
   HIP_TRY(vol, hipEventRecord(vol->ev_t1, vol->stream));
   vol->last_frame = p->frame;
   vol->last_adaptive = p->adaptive;
   std::memcpy(vol->last_R, fp.R, sizeof(vol->last_R));
-  st = order_user_after(vol);
+  st = order_user_after(vol, false);
   if (st != ADGI_OK) return st;
   if (p->sync) {
     HIP_TRY(vol, hipStreamSynchronize(vol->stream));
