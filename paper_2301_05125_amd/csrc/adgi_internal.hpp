@@ -92,6 +92,10 @@ struct RefitView {
   float pad_abs;
   const int32_t* tab;          // RefitPlan::tab on the device
   int32_t cut, subtrees, deep_levels;
+  int32_t num_big;             // slots [0, num_big): large triangles outside the tree
+  const int32_t* leaf_slots;   // RefitPlan::leaf_slots on the device
+  int32_t num_leaf_slots;
+  float* tri_box;              // [T][6] scratch: each triangle slot's box
 };
 // Refit plan of a BVH2: the internal nodes at depth >= cut are grouped, in
 // every level, by their ancestor at depth `cut` (one subtree per workgroup,
@@ -103,6 +107,7 @@ struct RefitPlan {
   std::vector<int32_t> level_nodes;
   std::vector<int32_t> level_offsets;  // size levels + 1
   std::vector<int32_t> tab;
+  std::vector<int32_t> leaf_slots;     // 2g + side of every child slot that holds a leaf
 };
 // level_offsets[d] .. level_offsets[d+1] index level_nodes for depth d
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s);

@@ -1,9 +1,11 @@
 // refit.hip - device BVH refit after vertex motion (same topology).
 //
-// 1. Rebuild every triangle record (v0, e1, e2) from the current positions.
-// 2. Refit the boxes from the deepest internal nodes to the root: a node's
-//    child slot gets the (padded) bounds of its leaf triangles, or the union
-//    of the internal child's two slots, which a deeper level finished. The
+// 1. Every triangle record (v0, e1, e2) and triangle box is rebuilt from the
+//    current positions (a thread per triangle), then every leaf child slot
+//    gets the (padded) union of its leaf's triangle boxes (a thread per leaf
+//    slot; a leaf's triangles are contiguous).
+// 2. The internal child slots, from the deepest internal nodes to the root:
+//    the union of the child's two slots, which a deeper level finished. The
 //    levels below a cut depth run in one launch, one workgroup per subtree
 //    rooted at the cut, level after level with a barrier between them (a
 //    subtree only reads its own nodes); the levels above the cut follow, runs
@@ -17,17 +19,27 @@
 
 namespace adgi {
 
+// Record of triangle slot s (original triangle t): (v0, t), e1, e2.
+__device__ __forceinline__ void write_tri(const RefitView& r, int s, int t, const float* v0, const float* v1,
+                                          const float* v2) {
+  r.tris[3 * (size_t)s] = make_float4(v0[0], v0[1], v0[2], __int_as_float(t));
+  r.tris[3 * (size_t)s + 1] = make_float4(v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2], 0.f);
+  r.tris[3 * (size_t)s + 2] = make_float4(v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2], 0.f);
+}
+
+// Record of triangle slot s and its box (min xyz, max xyz of its vertices).
 __global__ void refit_tris_kernel(RefitView r) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= r.num_tris) return;
   const int t = r.tri_order[s];
-  const float* v0 = r.positions + 3 * (size_t)r.indices[3 * t];
-  const float* v1 = r.positions + 3 * (size_t)r.indices[3 * t + 1];
-  const float* v2 = r.positions + 3 * (size_t)r.indices[3 * t + 2];
-  float4 a = make_float4(v0[0], v0[1], v0[2], __int_as_float(t));
-  r.tris[3 * (size_t)s] = a;
-  r.tris[3 * (size_t)s + 1] = make_float4(v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2], 0.f);
-  r.tris[3 * (size_t)s + 2] = make_float4(v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2], 0.f);
+  const float* p[3] = {r.positions + 3 * (size_t)r.indices[3 * t], r.positions + 3 * (size_t)r.indices[3 * t + 1],
+                       r.positions + 3 * (size_t)r.indices[3 * t + 2]};
+  write_tri(r, s, t, p[0], p[1], p[2]);
+  float* b = r.tri_box + 6 * (size_t)s;
+  for (int a = 0; a < 3; ++a) {
+    b[a] = fminf(fminf(p[0][a], p[1][a]), p[2][a]);
+    b[3 + a] = fmaxf(fmaxf(p[0][a], p[1][a]), p[2][a]);
+  }
 }
 
 __device__ __forceinline__ void write_slot(float4* node, int side, const float* lo, const float* hi) {
@@ -41,40 +53,51 @@ __device__ __forceinline__ void write_slot(float4* node, int side, const float* 
   f[b + 5] = hi[2];
 }
 
+// Bounds of a leaf child slot (padded): the union of its triangles' boxes,
+// which refit_tris_kernel left in tri_box (a leaf's slots are contiguous).
+__device__ __forceinline__ void refit_leaf_slot(const RefitView& r, int g, int side) {
+  const int* meta = (const int*)(r.nodes + 4 * (size_t)g + 3);
+  const int code = ~meta[side];
+  const int first = code >> kLeafShift, count_t = (code & (kLeafMaxTris - 1)) + 1;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int k = 0; k < count_t; ++k) {
+    const float* b = r.tri_box + 6 * (size_t)(first + k);
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], b[a]);
+      hi[a] = fmaxf(hi[a], b[3 + a]);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = pad_lo(lo[a], r.pad_abs);
+    hi[a] = pad_hi(hi[a], r.pad_abs);
+  }
+  write_slot(r.nodes + 4 * (size_t)g, side, lo, hi);
+}
+
+// Internal child slots of node g: the union of the child's two (already
+// padded) slots. Leaf slots are done beforehand by refit_leaves_kernel.
 __device__ __forceinline__ void refit_node(const RefitView& r, int g) {
   const int* meta = (const int*)(r.nodes + 4 * (size_t)g + 3);
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const int c = meta[side];
+    if (c < 0) continue;
+    const float* f = (const float*)(r.nodes + 4 * (size_t)c);
     float lo[3], hi[3];
-    if (c < 0) {
-      const int code = ~c;
-      const int first = code >> kLeafShift, count_t = (code & (kLeafMaxTris - 1)) + 1;
-      lo[0] = lo[1] = lo[2] = INFINITY;
-      hi[0] = hi[1] = hi[2] = -INFINITY;
-      for (int k = 0; k < count_t; ++k) {
-        const int t = r.tri_order[first + k];
-        for (int v = 0; v < 3; ++v) {
-          const float* p = r.positions + 3 * (size_t)r.indices[3 * t + v];
-          for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(lo[a], p[a]);
-            hi[a] = fmaxf(hi[a], p[a]);
-          }
-        }
-      }
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = pad_lo(lo[a], r.pad_abs);
-        hi[a] = pad_hi(hi[a], r.pad_abs);
-      }
-    } else {
-      // union of the child's two (already padded) slots
-      const float* f = (const float*)(r.nodes + 4 * (size_t)c);
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = fminf(f[a], f[6 + a]);
-        hi[a] = fmaxf(f[3 + a], f[9 + a]);
-      }
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(f[a], f[6 + a]);
+      hi[a] = fmaxf(f[3 + a], f[9 + a]);
     }
     write_slot(r.nodes + 4 * (size_t)g, side, lo, hi);
+  }
+}
+
+// Every leaf child slot (entry 2g + side of leaf_slots), all independent.
+__global__ void refit_leaves_kernel(RefitView r) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < r.num_leaf_slots) {
+    const int e = r.leaf_slots[q];
+    refit_leaf_slot(r, e >> 1, e & 1);
   }
 }
 
@@ -117,6 +140,13 @@ constexpr int kRefitCut = 10;
 void plan_refit(const BvhHost& bvh, RefitPlan& p) {
   p.level_nodes = bvh.level_nodes;
   p.level_offsets = bvh.level_offsets;
+  p.leaf_slots.clear();
+  for (size_t g = 0; g < bvh.nodes.size() / 4; ++g)
+    for (int side = 0; side < 2; ++side) {
+      int c;
+      std::memcpy(&c, side ? &bvh.nodes[4 * g + 3].y : &bvh.nodes[4 * g + 3].x, 4);
+      if (c < 0) p.leaf_slots.push_back((int32_t)(2 * g + side));
+    }
   p.tab.clear();
   p.cut = p.subtrees = p.deep_levels = 0;
   const int levels = (int)bvh.level_offsets.size() - 1;
@@ -154,6 +184,9 @@ void plan_refit(const BvhHost& bvh, RefitPlan& p) {
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s) {
   if (r.num_tris == 0) return hipSuccess;
   hipLaunchKernelGGL(refit_tris_kernel, dim3((r.num_tris + 255) / 256), dim3(256), 0, s, r);
+  if (level_offsets.size() < 2) return hipGetLastError();  // no internal node
+  if (r.num_leaf_slots > 0)
+    hipLaunchKernelGGL(refit_leaves_kernel, dim3((r.num_leaf_slots + 255) / 256), dim3(256), 0, s, r);
   if (r.subtrees > 0) hipLaunchKernelGGL(refit_deep_kernel, dim3(r.subtrees), dim3(256), 0, s, r);
   RefitRun run;
   run.n = 0;

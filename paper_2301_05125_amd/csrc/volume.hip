@@ -152,7 +152,9 @@ struct adgi_volume {
   int32_t* d_levels = nullptr;
   std::vector<int32_t> level_offsets;
   int32_t* d_refit_tab = nullptr;                    // RefitPlan::tab
-  int32_t refit_cut = 0, refit_subtrees = 0, refit_deep = 0;
+  int32_t* d_leaf_slots = nullptr;                   // RefitPlan::leaf_slots
+  float* d_tri_box = nullptr;                        // refit scratch: triangle boxes
+  int32_t refit_cut = 0, refit_subtrees = 0, refit_deep = 0, num_leaf_slots = 0;
   hipGraphExec_t refit_exec = nullptr;
   float4* d_nodes = nullptr;
   float4* d_nodes4 = nullptr;   // BVH4 collapse (null when its stack bound does not fit)
@@ -343,9 +345,10 @@ void free_scene(adgi_volume* vol) {
   for (void* p : vol->scene_allocs) vol_free(vol, p);
   vol->scene_allocs.clear();
   vol->d_pos = nullptr;
-  vol->d_idx = vol->d_order = vol->d_levels = vol->d_refit_tab = nullptr;
+  vol->d_idx = vol->d_order = vol->d_levels = vol->d_refit_tab = vol->d_leaf_slots = nullptr;
+  vol->d_tri_box = nullptr;
   vol->level_offsets.clear();
-  vol->refit_cut = vol->refit_subtrees = vol->refit_deep = 0;
+  vol->refit_cut = vol->refit_subtrees = vol->refit_deep = vol->num_leaf_slots = 0;
   vol->d_nodes = vol->d_tris = vol->d_albedo = nullptr;
   vol->d_nodes4 = nullptr;
   vol->d_src4 = nullptr;
@@ -801,6 +804,8 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     plan_refit(bvh, plan);
     vol->d_levels = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.level_nodes.size(), 1) * 4, &g);
     vol->d_refit_tab = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.tab.size(), 1) * 4, &g);
+    vol->d_leaf_slots = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.leaf_slots.size(), 1) * 4, &g);
+    vol->d_tri_box = (float*)vol_alloc(vol, (size_t)std::max(nt, 1) * 24, &g);
     vol->d_nodes = (float4*)vol_alloc(vol, bvh.nodes.size() * 16, &g);
     vol->d_tris = (float4*)vol_alloc(vol, std::max<size_t>(bvh.tris.size(), 3) * 16, &g);
     vol->d_albedo = (float4*)vol_alloc(vol, (size_t)std::max(nt, 1) * 16, &g);
@@ -808,7 +813,8 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
       vol->d_nodes4 = (float4*)vol_alloc(vol, bvh4.nodes.size() * 16, &g);
       vol->d_src4 = (int32_t*)vol_alloc(vol, bvh4.src.size() * 4, &g);
     }
-    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_refit_tab || !vol->d_nodes ||
+    if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_refit_tab ||
+        !vol->d_leaf_slots || !vol->d_tri_box || !vol->d_nodes ||
         !vol->d_tris || !vol->d_albedo || (fits4 && (!vol->d_nodes4 || !vol->d_src4))) {
       free_scene(vol);
       vol->has_scene = false;
@@ -828,6 +834,10 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
                              hipMemcpyHostToDevice));
     if (!plan.tab.empty())
       HIP_TRY(vol, hipMemcpy(vol->d_refit_tab, plan.tab.data(), plan.tab.size() * 4, hipMemcpyHostToDevice));
+    if (!plan.leaf_slots.empty())
+      HIP_TRY(vol, hipMemcpy(vol->d_leaf_slots, plan.leaf_slots.data(), plan.leaf_slots.size() * 4,
+                             hipMemcpyHostToDevice));
+    vol->num_leaf_slots = (int32_t)plan.leaf_slots.size();
     vol->level_offsets = plan.level_offsets;
     vol->refit_cut = plan.cut;
     vol->refit_subtrees = plan.subtrees;
@@ -871,7 +881,8 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
         RefitView r{vol->d_pos,   vol->d_idx,     vol->d_order,         vol->d_tris,
                     vol->d_nodes, vol->d_levels,  vol->nt,              vol->num_nodes,
                     vol->pad_abs, vol->d_refit_tab, vol->refit_cut, vol->refit_subtrees,
-                    vol->refit_deep};
+                    vol->refit_deep,  vol->num_big,   vol->d_leaf_slots,    vol->num_leaf_slots,
+                    vol->d_tri_box};
         hipGraph_t graph = nullptr;
         HIP_TRY(vol, hipStreamBeginCapture(ss, hipStreamCaptureModeRelaxed));
         hipError_t e = launch_refit(r, vol->level_offsets, ss);
