@@ -92,7 +92,6 @@ struct RefitView {
   float pad_abs;
   const int32_t* tab;          // RefitPlan::tab on the device
   int32_t cut, subtrees, deep_levels;
-  int32_t num_big;             // slots [0, num_big): large triangles outside the tree
   const int32_t* leaf_slots;   // RefitPlan::leaf_slots on the device
   int32_t num_leaf_slots;
   float* tri_box;              // [T][6] scratch: each triangle slot's box

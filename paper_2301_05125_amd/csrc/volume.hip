@@ -881,8 +881,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
         RefitView r{vol->d_pos,   vol->d_idx,     vol->d_order,         vol->d_tris,
                     vol->d_nodes, vol->d_levels,  vol->nt,              vol->num_nodes,
                     vol->pad_abs, vol->d_refit_tab, vol->refit_cut, vol->refit_subtrees,
-                    vol->refit_deep,  vol->num_big,   vol->d_leaf_slots,    vol->num_leaf_slots,
-                    vol->d_tri_box};
+                    vol->refit_deep,  vol->d_leaf_slots, vol->num_leaf_slots, vol->d_tri_box};
         hipGraph_t graph = nullptr;
         HIP_TRY(vol, hipStreamBeginCapture(ss, hipStreamCaptureModeRelaxed));
         hipError_t e = launch_refit(r, vol->level_offsets, ss);

@@ -49,6 +49,20 @@ def test_bitwise_determinism_across_runs():
     _same(_run(sc, 6, **kw), _run(sc, 6, **kw))
 
 
+def test_large_ray_buffers_take_the_multi_block_pair_scan():
+    """A volume whose ray buffers hold more than 2^14 batches of 64 rays lays
+    out the shadow pairs with the three-launch scan; the frames must match a
+    volume sized to the budget (one-workgroup scan) bit for bit."""
+    sc = _small_field()
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    big = adgi.volume_for_scene(sc, max_rays=(1 << 20) + 64 * 1024, seed=3)
+    try:
+        a = _run(sc, 4, vol=big, **kw)
+    finally:
+        big.destroy_volume()
+    _same(a, _run(sc, 4, **kw))
+
+
 @pytest.mark.parametrize("tuning", [{"use_graph": 0}, {"bvh_width": 4, "trace_block": 128}])
 def test_packed_storage_launch_invariance(tuning):
     sc = _small_field()
