@@ -143,6 +143,7 @@ void collapse_bvh4(const BvhHost& b2, Bvh4Host& out);
 struct BuiltScene {
   BvhHost bvh;
   Bvh4Host bvh4;
+  RefitPlan plan;
   bool fits4 = false;
   float pad_abs = 0.f;
   double build_ms = 0.0;

@@ -168,8 +168,7 @@ struct adgi_volume {
   int bvh_depth = 0;
   double last_build_ms = 0.0;
   // frame
-  hipGraphExec_t exec[2] = {nullptr, nullptr};        // frame up to the probe trace
-  hipGraphExec_t exec_blend[2] = {nullptr, nullptr};  // its blend
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   adgi_tuning tun{};
   bool tuned = false;
   int32_t last_frame = -1, last_adaptive = 0;
@@ -219,12 +218,11 @@ void vol_free(adgi_volume* vol, void* p) {
 }
 
 void drop_graphs(adgi_volume* vol) {
-  for (auto* set : {vol->exec, vol->exec_blend})
-    for (int k = 0; k < 2; ++k)
-      if (set[k]) {
-        (void)hipGraphExecDestroy(set[k]);
-        set[k] = nullptr;
-      }
+  for (auto& e : vol->exec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
 }
 
 // The texel blend of the frame's rays (reads the records, probe counts,
@@ -247,9 +245,9 @@ bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
 // blend order, 5 probe trace, 6 blend; 7 between the probe trace's
 // closest-hit and shading kernels. mode: ADGI_MODE_*. A counting run of a
 // chain frame traces the samples the last chain frame left. part: 0 the
-// whole frame, 1 up to the probe trace, 2 the blend alone (graphs are
-// captured in these two parts). `traced`, when given, is recorded after the
-// probe trace (the scene is free from there on).
+// whole frame, 1 up to the probe trace, 2 the blend alone (a frame graph is
+// composed of the two). `traced`, when given, is recorded after the probe
+// trace (the scene is free from there on).
 hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
                          bool count_work = false, hipEvent_t traced = nullptr, int part = 0) {
   const adgi_tuning& t = vol->tun;
@@ -719,6 +717,7 @@ bool build_scene(const adgi_volume_desc& d, const adgi_scene_desc* sc, BuiltScen
     return false;
   collapse_bvh4(out.bvh, out.bvh4);
   out.fits4 = out.bvh4.max_stack <= kStackMax;
+  plan_refit(out.bvh, out.plan);
   out.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return true;
 }
@@ -800,8 +799,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     vol->d_pos = (float*)vol_alloc(vol, (size_t)nv * 12, &g);
     vol->d_idx = (int32_t*)vol_alloc(vol, (size_t)nt * 12, &g);
     vol->d_order = (int32_t*)vol_alloc(vol, (size_t)nt * 4, &g);
-    RefitPlan plan;
-    plan_refit(bvh, plan);
+    const RefitPlan& plan = built->plan;
     vol->d_levels = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.level_nodes.size(), 1) * 4, &g);
     vol->d_refit_tab = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.tab.size(), 1) * 4, &g);
     vol->d_leaf_slots = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.leaf_slots.size(), 1) * 4, &g);
@@ -1037,29 +1035,30 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
   if (vol->tun.use_graph && mode != ADGI_MODE_CHAIN) {
-    for (int part = 1; part <= 2; ++part) {
-      hipGraphExec_t& ex = part == 1 ? vol->exec[mode] : vol->exec_blend[mode];
-      if (ex) continue;
-      hipGraph_t graph = nullptr;
-      HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
-      hipError_t e = enqueue_frame(vol, mode, nullptr, false, nullptr, part);
-      hipError_t e2 = hipStreamEndCapture(vol->stream, &graph);
-      if (e != hipSuccess || e2 != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        vol->sticky = true;
-        return fail(ADGI_ERR_DEVICE, "frame capture failed: %s / %s", hipGetErrorString(e),
-                    hipGetErrorString(e2));
+    if (!vol->exec[mode]) {
+      // the frame up to the probe trace and its blend, captured apart and
+      // composed with the event node that frees the scene between them
+      hipGraph_t part[2] = {nullptr, nullptr}, graph = nullptr;
+      hipError_t e = hipSuccess, e2 = hipSuccess;
+      for (int k = 0; k < 2 && e == hipSuccess && e2 == hipSuccess; ++k) {
+        HIP_TRY(vol, hipStreamBeginCapture(vol->stream, hipStreamCaptureModeRelaxed));
+        e = enqueue_frame(vol, mode, nullptr, false, nullptr, k + 1);
+        e2 = hipStreamEndCapture(vol->stream, &part[k]);
       }
-      hipError_t e3 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e3 != hipSuccess) {
+      hipGraphNode_t na = nullptr, ne = nullptr, nb = nullptr;
+      if (e == hipSuccess && e2 == hipSuccess) e = hipGraphCreate(&graph, 0);
+      if (e == hipSuccess) e = hipGraphAddChildGraphNode(&na, graph, nullptr, 0, part[0]);
+      if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ne, graph, &na, 1, vol->ev_traced);
+      if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nb, graph, &na, 1, part[1]);
+      if (e == hipSuccess) e = hipGraphInstantiate(&vol->exec[mode], graph, nullptr, nullptr, 0);
+      for (hipGraph_t g : {part[0], part[1], graph})
+        if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess || e2 != hipSuccess) {
         vol->sticky = true;
-        return fail(ADGI_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
+        return fail(ADGI_ERR_DEVICE, "frame graph failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
       }
     }
     HIP_TRY(vol, hipGraphLaunch(vol->exec[mode], vol->stream));
-    HIP_TRY(vol, hipEventRecord(vol->ev_traced, vol->stream));
-    HIP_TRY(vol, hipGraphLaunch(vol->exec_blend[mode], vol->stream));
   } else {
     HIP_TRY(vol, enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr, false, vol->ev_traced));
   }
