@@ -109,7 +109,11 @@ struct Stream {
   adgi_update_params params{};
   int64_t footprint = 0;
   adgi_volume* vol = nullptr;
-  std::vector<uint8_t> state;  // temporal state while evicted (empty: fresh)
+  // temporal state while evicted, in pinned host memory sized when the
+  // stream is added (state_len 0: fresh), so eviction and admission copy at
+  // full PCIe rate
+  uint8_t* state_buf = nullptr;
+  size_t state_cap = 0, state_len = 0;
   int32_t next_frame = 0;
   std::deque<int64_t> pending;  // request ids not yet dispatched, in order
   int64_t inflight = -1;
@@ -158,10 +162,11 @@ namespace {
 
 adgi_status evict(adgi_server* s, Stream& st) {
   auto t0 = now_ns();
-  size_t n = adgi_state_size(st.vol);
-  st.state.resize(n);
-  adgi_status e = adgi_save_state(st.vol, st.state.data(), n);
+  const size_t n = adgi_state_size(st.vol);
+  if (n > st.state_cap) return sfail(ADGI_ERR_DEVICE, "stream state outgrew its host buffer");
+  adgi_status e = adgi_save_state(st.vol, st.state_buf, n);
   if (e != ADGI_OK) return pass(e);
+  st.state_len = n;
   adgi_destroy_volume(st.vol);
   st.vol = nullptr;
   s->resident -= st.footprint;
@@ -178,7 +183,7 @@ adgi_status make_resident(adgi_server* s, Stream& st) {
   std::vector<float> lp(3 * (size_t)std::max(st.num_lights, 1), 0.f);
   adgi_scene_desc sd = st.scene(ADGI_SCENE_REBUILD, lp.data());
   e = adgi::update_scene_impl(vol, &sd, &st.built);
-  if (e == ADGI_OK && !st.state.empty()) e = adgi_restore_state(vol, st.state.data(), st.state.size());
+  if (e == ADGI_OK && st.state_len) e = adgi_restore_state(vol, st.state_buf, st.state_len);
   if (e != ADGI_OK) {
     pass(e);
     adgi_destroy_volume(vol);
@@ -379,9 +384,12 @@ adgi_status adgi_server_add_stream(adgi_server* s, const adgi_stream_desc* d, in
     e = adgi_update_probes(vol, &p, nullptr);
   }
   st->footprint = (int64_t)adgi_device_bytes(vol);
+  st->state_cap = adgi_state_size(vol);
   if (e != ADGI_OK) pass(e);
   adgi_destroy_volume(vol);
   if (e != ADGI_OK) return e;
+  if (hipHostMalloc((void**)&st->state_buf, std::max<size_t>(st->state_cap, 1), hipHostMallocDefault) != hipSuccess)
+    return sfail(ADGI_ERR_OUT_OF_MEMORY, "pinned host buffer for the stream state");
   if (st->footprint > s->budget) return sfail(ADGI_ERR_OUT_OF_MEMORY, "stream footprint exceeds the HBM budget");
   *id = (int32_t)s->streams.size();
   s->streams.push_back(std::move(st));
@@ -482,11 +490,13 @@ adgi_status adgi_server_read_stream(adgi_server* s, int32_t id, adgi_probe_readb
 
 void adgi_server_destroy(adgi_server* s) {
   if (!s) return;
-  for (auto& p : s->streams)
+  for (auto& p : s->streams) {
     if (p->vol) {
       (void)hipStreamSynchronize(adgi::volume_stream(p->vol));
       adgi_destroy_volume(p->vol);
     }
+    if (p->state_buf) (void)hipHostFree(p->state_buf);
+  }
   for (auto& kv : s->pool.size_of) (void)hipFree(kv.first);
   delete s;
 }

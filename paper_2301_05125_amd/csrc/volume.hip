@@ -335,6 +335,49 @@ adgi_status order_user_after(adgi_volume* vol, bool scene_free = true) {
   return ADGI_OK;
 }
 
+// Pinned host blocks (parameter ring, statistics, scene constants, vertex
+// staging) go back to a process-wide cache by exact size instead of to
+// hipHostFree, which can wait on other streams' work: a server that evicts
+// and re-admits volumes reuses them. The cache is never destroyed, so a
+// volume released during process teardown still finds it.
+struct PinnedCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;
+  std::map<void*, size_t> size_of;
+};
+
+PinnedCache& pinned_cache() {
+  static PinnedCache* c = new PinnedCache;
+  return *c;
+}
+
+hipError_t pinned_alloc(void** p, size_t bytes) {
+  PinnedCache& c = pinned_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free_blocks.find(bytes);
+    if (it != c.free_blocks.end()) {
+      *p = it->second;
+      c.free_blocks.erase(it);
+      return hipSuccess;
+    }
+  }
+  const hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.size_of[*p] = bytes;
+  }
+  return e;
+}
+
+void pinned_free(void* p) {
+  if (!p) return;
+  PinnedCache& c = pinned_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.size_of.find(p);
+  if (it != c.size_of.end()) c.free_blocks.insert({it->second, p});
+}
+
 void free_scene(adgi_volume* vol) {
   if (vol->refit_exec) {
     (void)hipGraphExecDestroy(vol->refit_exec);
@@ -353,7 +396,7 @@ void free_scene(adgi_volume* vol) {
   vol->num_nodes4 = 0;
   vol->v.nodes4 = nullptr;
   if (vol->h_stage) {
-    (void)hipHostFree(vol->h_stage);
+    pinned_free(vol->h_stage);
     vol->h_stage = nullptr;
     vol->h_stage_floats = 0;
   }
@@ -365,9 +408,9 @@ void release(adgi_volume* vol) {
   drop_graphs(vol);
   free_scene(vol);
   while (!vol->allocs.empty()) vol_free(vol, vol->allocs.back().first);
-  if (vol->h_fp) (void)hipHostFree(vol->h_fp);
-  if (vol->h_stats) (void)hipHostFree(vol->h_stats);
-  if (vol->h_scene) (void)hipHostFree(vol->h_scene);
+  pinned_free(vol->h_fp);
+  pinned_free(vol->h_stats);
+  pinned_free(vol->h_scene);
   for (auto& e : vol->ev_slot)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : vol->ev_k)
@@ -566,9 +609,9 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
     CREATE_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   for (auto& e : vol->ev_slot) CREATE_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : vol->ev_k) CREATE_TRY(hipEventCreate(&e));
-  CREATE_TRY(hipHostMalloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots, hipHostMallocDefault));
-  CREATE_TRY(hipHostMalloc((void**)&vol->h_stats, sizeof(FrameStats), hipHostMallocDefault));
-  CREATE_TRY(hipHostMalloc((void**)&vol->h_scene, sizeof(SceneParams), hipHostMallocDefault));
+  CREATE_TRY(pinned_alloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots));
+  CREATE_TRY(pinned_alloc((void**)&vol->h_stats, sizeof(FrameStats)));
+  CREATE_TRY(pinned_alloc((void**)&vol->h_scene, sizeof(SceneParams)));
   std::memset(vol->h_fp, 0, sizeof(FrameParams) * kParamSlots);
   std::memset(vol->h_scene, 0, sizeof(SceneParams));
 
@@ -859,7 +902,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     hp.num_nodes = nn;
     hp.num_big = bvh.num_big;
     vol->num_big = bvh.num_big;
-    HIP_TRY(vol, hipHostMalloc((void**)&vol->h_stage, std::max<size_t>((size_t)nv * 12, 16), hipHostMallocDefault));
+    HIP_TRY(vol, pinned_alloc((void**)&vol->h_stage, std::max<size_t>((size_t)nv * 12, 16)));
     vol->h_stage_floats = (size_t)nv * 3;
   } else {
     hp.num_nodes = vol->num_nodes;
