@@ -164,7 +164,11 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(no CPU fallback exists)")
         try:
-            import torch  # noqa: F401  (loads the HIP runtime torch uses)
+            import torch  # (loads the HIP runtime torch uses)
+            # the device is initialised through torch before the library
+            # registers its kernels, as in every process it has run in
+            if torch.cuda.is_available():
+                torch.cuda.init()
         except ImportError:
             pass
         L = C.CDLL(LIB_PATH)

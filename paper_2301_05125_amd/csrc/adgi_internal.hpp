@@ -140,6 +140,10 @@ void collapse_bvh4(const BvhHost& b2, Bvh4Host& out);
 
 // volume.hip: a REBUILD split into its host build and the device install, so
 // a caller that keeps scenes on the host (the server) builds each BVH once.
+// Arrays a REBUILD uploads besides the vertex positions, in the order of
+// their offsets inside a pinned scene image.
+enum PinPart { kPinIdx, kPinOrder, kPinTris, kPinLevels, kPinTab, kPinLeaf, kPinNodes, kPinAlbedo, kPinNodes4,
+               kPinSrc4, kPinParts };
 struct BuiltScene {
   BvhHost bvh;
   Bvh4Host bvh4;
@@ -147,10 +151,27 @@ struct BuiltScene {
   bool fits4 = false;
   float pad_abs = 0.f;
   double build_ms = 0.0;
+  // Optional pinned host copy of the uploaded arrays (pin_scene; released
+  // by unpin_scene, not by the destructor). With it a REBUILD from this
+  // scene enqueues its uploads on the volume's scene stream and returns
+  // before they finish; the image must then outlive every volume it fed.
+  uint8_t* pinned = nullptr;
+  size_t pin_off[kPinParts] = {}, pin_len[kPinParts] = {};
 };
 bool build_scene(const adgi_volume_desc& d, const adgi_scene_desc* sc, BuiltScene& out, const char** err);
+// Pinned image of `b` for the scene `sc` it was built from; false when the
+// pinned allocation fails (the scene then uploads synchronously).
+bool pin_scene(BuiltScene& b, const adgi_scene_desc* sc);
+void unpin_scene(BuiltScene& b);
 // adgi_update_scene with an optional prebuilt BVH for a REBUILD (same checks).
 adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const BuiltScene* prebuilt);
+// adgi_restore_state; with `async` the copies are enqueued on the volume's
+// stream, so `src` must stay unchanged until that stream has passed them.
+adgi_status restore_state_impl(adgi_volume* vol, const void* src, size_t bytes, bool async);
+// adgi_save_state; with `async` the copies are enqueued on the volume's
+// stream behind its queued frames, and `dst` holds the snapshot only once
+// that stream has passed them.
+adgi_status save_state_impl(adgi_volume* vol, void* dst, size_t bytes, bool async);
 hipStream_t volume_stream(adgi_volume* vol);
 // Conservative box padding (builder and refit): a few ulps of the coordinate
 // plus an absolute term tied to the scene's coordinate scale, so that FP32

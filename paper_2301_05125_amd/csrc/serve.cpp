@@ -114,11 +114,24 @@ struct Stream {
   // full PCIe rate
   uint8_t* state_buf = nullptr;
   size_t state_cap = 0, state_len = 0;
+  // an evicted volume whose state copy is still in flight: it keeps its
+  // device memory (and its share of the budget) until retire_ev completes
+  adgi_volume* retiring = nullptr;
+  hipEvent_t retire_ev = nullptr;
   int32_t next_frame = 0;
   std::deque<int64_t> pending;  // request ids not yet dispatched, in order
   int64_t inflight = -1;
   int64_t last_use_ns = 0;
   int64_t admitted_ns = 0;
+
+  Stream() = default;
+  Stream(const Stream&) = delete;
+  Stream& operator=(const Stream&) = delete;
+  ~Stream() {
+    if (retire_ev) (void)hipEventDestroy(retire_ev);
+    if (state_buf) (void)hipHostFree(state_buf);
+    adgi::unpin_scene(built);
+  }
 
   adgi_scene_desc scene(int32_t mode, const float* lights) const {
     adgi_scene_desc d{};
@@ -152,6 +165,7 @@ struct adgi_server {
   std::deque<int64_t> waiting;  // undispatched request ids, arrival order
   int32_t inflight = 0;
   int64_t resident = 0, peak_resident = 0;
+  int64_t retiring_bytes = 0;  // part of `resident` held by retiring volumes
   int64_t admissions = 0, evictions = 0, completed = 0, rays = 0;
   int64_t first_arrival_ns = 0, last_done_ns = 0;
   double admit_ms = 0.0, evict_ms = 0.0;
@@ -160,30 +174,73 @@ struct adgi_server {
 
 namespace {
 
+// Eviction enqueues the state copy behind the stream's last frame and
+// retires the volume; its memory is released once the copy has landed
+// (finish_retire), so the dispatcher never waits on the transfer.
 adgi_status evict(adgi_server* s, Stream& st) {
   auto t0 = now_ns();
   const size_t n = adgi_state_size(st.vol);
   if (n > st.state_cap) return sfail(ADGI_ERR_DEVICE, "stream state outgrew its host buffer");
-  adgi_status e = adgi_save_state(st.vol, st.state_buf, n);
+  adgi_status e = adgi::save_state_impl(st.vol, st.state_buf, n, true);
   if (e != ADGI_OK) return pass(e);
+  if (hipEventRecord(st.retire_ev, adgi::volume_stream(st.vol)) != hipSuccess)
+    return sfail(ADGI_ERR_DEVICE, "hipEventRecord failed");
   st.state_len = n;
-  adgi_destroy_volume(st.vol);
+  st.retiring = st.vol;
   st.vol = nullptr;
-  s->resident -= st.footprint;
+  s->retiring_bytes += st.footprint;
   ++s->evictions;
   s->evict_ms += (now_ns() - t0) * 1e-6;
   return ADGI_OK;
 }
 
+// Releases a retired volume once its state copy is done (or, with `wait`,
+// after waiting for it); true if the volume was released.
+bool finish_retire(adgi_server* s, Stream& st, bool wait) {
+  if (!st.retiring) return false;
+  if (wait) {
+    if (hipEventSynchronize(st.retire_ev) != hipSuccess) return false;
+  } else if (hipEventQuery(st.retire_ev) != hipSuccess) {
+    return false;
+  }
+  auto t0 = now_ns();
+  adgi_destroy_volume(st.retiring);
+  st.retiring = nullptr;
+  s->resident -= st.footprint;
+  s->retiring_bytes -= st.footprint;
+  s->evict_ms += (now_ns() - t0) * 1e-6;
+  return true;
+}
+
+// Releases every retired volume whose copy is done, except `keep`'s.
+void reap(adgi_server* s, const Stream* keep = nullptr) {
+  if (!s->retiring_bytes) return;
+  for (auto& p : s->streams)
+    if (p.get() != keep) finish_retire(s, *p, false);
+}
+
 adgi_status make_resident(adgi_server* s, Stream& st) {
   auto t0 = now_ns();
+  if (st.retiring) {
+    // re-admitted before its eviction finished: the volume still holds the
+    // live state, and the copy in flight ahead of the next frame is harmless
+    st.vol = st.retiring;
+    st.retiring = nullptr;
+    s->retiring_bytes -= st.footprint;
+    st.admitted_ns = now_ns();
+    ++s->admissions;
+    s->admit_ms += (now_ns() - t0) * 1e-6;
+    return ADGI_OK;
+  }
   adgi_volume* vol = nullptr;
   adgi_status e = adgi_create_volume(&st.vdesc, &s->alloc, nullptr, &vol);
   if (e != ADGI_OK) return pass(e);
   std::vector<float> lp(3 * (size_t)std::max(st.num_lights, 1), 0.f);
   adgi_scene_desc sd = st.scene(ADGI_SCENE_REBUILD, lp.data());
   e = adgi::update_scene_impl(vol, &sd, &st.built);
-  if (e == ADGI_OK && st.state_len) e = adgi_restore_state(vol, st.state_buf, st.state_len);
+  // the state copy is enqueued on the volume's stream: state_buf is next
+  // written by this stream's eviction, which first waits for that stream
+  if (e == ADGI_OK && st.state_len) e = adgi::restore_state_impl(vol, st.state_buf, st.state_len, true);
   if (e != ADGI_OK) {
     pass(e);
     adgi_destroy_volume(vol);
@@ -198,10 +255,16 @@ adgi_status make_resident(adgi_server* s, Stream& st) {
   return ADGI_OK;
 }
 
-// Evicts idle streams until `need` more bytes fit; false if they cannot yet.
-// gentle: only streams with no request waiting are evicted.
-bool make_room(adgi_server* s, int64_t need, bool gentle, adgi_status* err) {
-  while (s->resident + need > s->budget) {
+// Makes room to admit `target`: evicts idle streams until it fits once
+// every retiring copy has landed; false if it cannot yet. A target whose
+// own volume is still retiring needs no room (it is revived, and keeps its
+// share of the budget). gentle: only streams with no request waiting are
+// evicted. block: wait for retiring copies instead of returning false while
+// they are in flight.
+bool make_room(adgi_server* s, const Stream& target, bool gentle, bool block, adgi_status* err) {
+  const int64_t need = target.retiring ? 0 : target.footprint;
+  reap(s, &target);
+  while (s->resident - s->retiring_bytes + need > s->budget) {
     Stream* victim = nullptr;
     for (auto& p : s->streams) {
       Stream& c = *p;
@@ -217,7 +280,16 @@ bool make_room(adgi_server* s, int64_t need, bool gentle, adgi_status* err) {
     if (!victim) return false;
     if ((*err = evict(s, *victim)) != ADGI_OK) return false;
   }
-  return true;
+  if (s->resident + need <= s->budget) return true;
+  if (!block) {
+    reap(s, &target);
+    return s->resident + need <= s->budget;
+  }
+  for (auto& p : s->streams) {
+    if (s->resident + need <= s->budget) break;
+    if (p.get() != &target) finish_retire(s, *p, true);
+  }
+  return s->resident + need <= s->budget;
 }
 
 adgi_status dispatch(adgi_server* s, Stream& st, int64_t id) {
@@ -265,7 +337,7 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
     if (!st.vol && st.inflight < 0 && st.pending.front() == id &&
         now_ns() - s->reqs[id].arrival_ns > kMaxWaitNs) {
       adgi_status err = ADGI_OK;
-      if (make_room(s, st.footprint, /*gentle=*/false, &err)) {
+      if (make_room(s, st, /*gentle=*/false, /*block=*/false, &err)) {
         if ((err = make_resident(s, st)) != ADGI_OK) return err;
         if ((err = dispatch(s, st, id)) != ADGI_OK) return err;
         s->waiting.pop_front();
@@ -297,7 +369,7 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
       continue;
     }
     adgi_status err = ADGI_OK;
-    if (!make_room(s, st.footprint, /*gentle=*/true, &err)) {
+    if (!make_room(s, st, /*gentle=*/true, /*block=*/false, &err)) {
       if (err != ADGI_OK) return err;
       break;  // the budget is held by streams in flight or with work waiting
     }
@@ -371,6 +443,10 @@ adgi_status adgi_server_add_stream(adgi_server* s, const adgi_stream_desc* d, in
   adgi_scene_desc bd = st->scene(ADGI_SCENE_REBUILD, sc.light_pos);
   const char* err = "";
   if (!adgi::build_scene(st->vdesc, &bd, st->built, &err)) return sfail(ADGI_ERR_INVALID_ARG, err);
+  // a pinned image of the uploaded arrays lets every admission enqueue them
+  // and return; without one (pinned memory refused) admission copies
+  // synchronously
+  (void)adgi::pin_scene(st->built, &bd);
   // footprint: build the volume once, measure, release
   adgi_volume* vol = nullptr;
   adgi_status e = adgi_create_volume(&st->vdesc, &s->alloc, nullptr, &vol);
@@ -390,6 +466,8 @@ adgi_status adgi_server_add_stream(adgi_server* s, const adgi_stream_desc* d, in
   if (e != ADGI_OK) return e;
   if (hipHostMalloc((void**)&st->state_buf, std::max<size_t>(st->state_cap, 1), hipHostMallocDefault) != hipSuccess)
     return sfail(ADGI_ERR_OUT_OF_MEMORY, "pinned host buffer for the stream state");
+  if (hipEventCreateWithFlags(&st->retire_ev, hipEventDisableTiming) != hipSuccess)
+    return sfail(ADGI_ERR_DEVICE, "hipEventCreate failed");
   if (st->footprint > s->budget) return sfail(ADGI_ERR_OUT_OF_MEMORY, "stream footprint exceeds the HBM budget");
   *id = (int32_t)s->streams.size();
   s->streams.push_back(std::move(st));
@@ -441,6 +519,10 @@ adgi_status adgi_server_drain(adgi_server* s) {
             return sfail(ADGI_ERR_DEVICE, "hipStreamSynchronize failed");
           break;
         }
+    } else if (s->retiring_bytes) {
+      // admissions wait for a state copy to land
+      for (auto& p : s->streams)
+        if (finish_retire(s, *p, true)) break;
     }
   }
 }
@@ -481,7 +563,7 @@ adgi_status adgi_server_read_stream(adgi_server* s, int32_t id, adgi_probe_readb
   if (st.inflight >= 0 || !st.pending.empty()) return sfail(ADGI_ERR_INVALID_ARG, "stream has frames outstanding");
   if (!st.vol) {
     adgi_status err = ADGI_OK;
-    if (!make_room(s, st.footprint, false, &err))
+    if (!make_room(s, st, false, true, &err))
       return err != ADGI_OK ? err : sfail(ADGI_ERR_OUT_OF_MEMORY, "no room to admit the stream");
     if ((err = make_resident(s, st)) != ADGI_OK) return err;
   }
@@ -495,7 +577,7 @@ void adgi_server_destroy(adgi_server* s) {
       (void)hipStreamSynchronize(adgi::volume_stream(p->vol));
       adgi_destroy_volume(p->vol);
     }
-    if (p->state_buf) (void)hipHostFree(p->state_buf);
+    if (p->retiring) adgi_destroy_volume(p->retiring);
   }
   for (auto& kv : s->pool.size_of) (void)hipFree(kv.first);
   delete s;

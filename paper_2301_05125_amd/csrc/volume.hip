@@ -378,6 +378,63 @@ void pinned_free(void* p) {
   if (it != c.size_of.end()) c.free_blocks.insert({it->second, p});
 }
 
+// Streams and events of released volumes, per device, for the next volume:
+// creating and destroying them costs a few tenths of a millisecond each
+// time a server admits or evicts a volume. Every one returned here has no
+// work pending on it (release waits for both streams first).
+struct HandleCache {
+  std::mutex mu;
+  std::multimap<int, hipStream_t> streams;
+  std::multimap<int, hipEvent_t> events[2];  // [timing]
+};
+
+HandleCache& handle_cache() {
+  static HandleCache* c = new HandleCache;
+  return *c;
+}
+
+hipError_t take_stream(int device, hipStream_t* s) {
+  HandleCache& c = handle_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.streams.find(device);
+    if (it != c.streams.end()) {
+      *s = it->second;
+      c.streams.erase(it);
+      return hipSuccess;
+    }
+  }
+  return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+hipError_t take_event(int device, bool timing, hipEvent_t* e) {
+  HandleCache& c = handle_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.events[timing].find(device);
+    if (it != c.events[timing].end()) {
+      *e = it->second;
+      c.events[timing].erase(it);
+      return hipSuccess;
+    }
+  }
+  return timing ? hipEventCreate(e) : hipEventCreateWithFlags(e, hipEventDisableTiming);
+}
+
+void give_stream(int device, hipStream_t s) {
+  if (!s) return;
+  HandleCache& c = handle_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.streams.insert({device, s});
+}
+
+void give_event(int device, bool timing, hipEvent_t e) {
+  if (!e) return;
+  HandleCache& c = handle_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.events[timing].insert({device, e});
+}
+
 void free_scene(adgi_volume* vol) {
   if (vol->refit_exec) {
     (void)hipGraphExecDestroy(vol->refit_exec);
@@ -402,24 +459,29 @@ void free_scene(adgi_volume* vol) {
   }
 }
 
+// Waits for a stream's work. Streams share a few hardware queues, so a
+// synchronisation marker can queue behind other volumes' frames for
+// milliseconds; a stream whose work is known to be done is only queried.
+void finish_stream(hipStream_t s) {
+  if (s && hipStreamQuery(s) != hipSuccess) (void)hipStreamSynchronize(s);
+}
+
 void release(adgi_volume* vol) {
-  if (vol->scene_stream) (void)hipStreamSynchronize(vol->scene_stream);
-  if (vol->stream) (void)hipStreamSynchronize(vol->stream);
+  finish_stream(vol->scene_stream);
+  finish_stream(vol->stream);
   drop_graphs(vol);
   free_scene(vol);
   while (!vol->allocs.empty()) vol_free(vol, vol->allocs.back().first);
   pinned_free(vol->h_fp);
   pinned_free(vol->h_stats);
   pinned_free(vol->h_scene);
-  for (auto& e : vol->ev_slot)
-    if (e) (void)hipEventDestroy(e);
-  for (auto& e : vol->ev_k)
-    if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage, vol->ev_traced,
-                      vol->ev_refit})
-    if (e) (void)hipEventDestroy(e);
-  if (vol->stream) (void)hipStreamDestroy(vol->stream);
-  if (vol->scene_stream) (void)hipStreamDestroy(vol->scene_stream);
+  const int dev = vol->device;
+  for (hipEvent_t e : vol->ev_slot) give_event(dev, false, e);
+  for (hipEvent_t e : vol->ev_k) give_event(dev, true, e);
+  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage}) give_event(dev, true, e);
+  for (hipEvent_t e : {vol->ev_traced, vol->ev_refit}) give_event(dev, false, e);
+  give_stream(dev, vol->stream);
+  give_stream(dev, vol->scene_stream);
 }
 
 // Bytes of one probe's irradiance / depth tile (with border) in HBM.
@@ -601,14 +663,13 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   } while (0)
   CREATE_TRY(hipGetDevice(&vol->device));
   CREATE_TRY(hipDeviceGetAttribute(&vol->num_cus, hipDeviceAttributeMultiprocessorCount, vol->device));
-  CREATE_TRY(hipStreamCreateWithFlags(&vol->stream, hipStreamNonBlocking));
-  CREATE_TRY(hipStreamCreateWithFlags(&vol->scene_stream, hipStreamNonBlocking));
+  CREATE_TRY(take_stream(vol->device, &vol->stream));
+  CREATE_TRY(take_stream(vol->device, &vol->scene_stream));
   for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_t0, &vol->ev_t1, &vol->ev_stage})
-    CREATE_TRY(hipEventCreate(e));
-  for (hipEvent_t* e : {&vol->ev_traced, &vol->ev_refit})
-    CREATE_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
-  for (auto& e : vol->ev_slot) CREATE_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  for (auto& e : vol->ev_k) CREATE_TRY(hipEventCreate(&e));
+    CREATE_TRY(take_event(vol->device, true, e));
+  for (hipEvent_t* e : {&vol->ev_traced, &vol->ev_refit}) CREATE_TRY(take_event(vol->device, false, e));
+  for (auto& e : vol->ev_slot) CREATE_TRY(take_event(vol->device, false, &e));
+  for (auto& e : vol->ev_k) CREATE_TRY(take_event(vol->device, true, &e));
   CREATE_TRY(pinned_alloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots));
   CREATE_TRY(pinned_alloc((void**)&vol->h_stats, sizeof(FrameStats)));
   CREATE_TRY(pinned_alloc((void**)&vol->h_scene, sizeof(SceneParams)));
@@ -695,12 +756,15 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   CREATE_TRY(hipEventRecord(vol->ev_traced, vol->stream));
   CREATE_TRY(hipEventRecord(vol->ev_refit, vol->stream));
   if (d->storage == ADGI_PACKED) CREATE_TRY(launch_packed_decode_table((float*)v.pk_dec, vol->stream));
-  // the tables go after the zero fill on the volume's (non-blocking) stream;
-  // tb lives until the synchronisation below
-  const DynTables tb = dyn_tables(d->irr_res - 2, d->depth_res - 2);
-  if (d->max_chains > 0)
+  // Every reader of the zero-filled buffers runs on the volume's stream or
+  // waits for it, so creation returns without waiting for the fill (which
+  // may queue behind other volumes' work). The chain tables go after the
+  // fill and tb lives until the synchronisation that follows them.
+  if (d->max_chains > 0) {
+    const DynTables tb = dyn_tables(d->irr_res - 2, d->depth_res - 2);
     CREATE_TRY(hipMemcpyAsync((void*)v.dyn_tab, &tb, sizeof(tb), hipMemcpyHostToDevice, vol->stream));
-  CREATE_TRY(hipStreamSynchronize(vol->stream));
+    CREATE_TRY(hipStreamSynchronize(vol->stream));
+  }
 #undef CREATE_TRY
   v.ox = d->origin[0];
   v.oy = d->origin[1];
@@ -832,8 +896,12 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     const bool fits4 = built->fits4;
     const float pad_abs = built->pad_abs;
     vol->last_build_ms = built->build_ms;
-    HIP_TRY(vol, hipStreamSynchronize(ss));
-    HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+    // an old scene's buffers and graphs may still be in use; a volume that
+    // never had one has no frame in flight
+    if (vol->has_scene || !vol->scene_allocs.empty()) {
+      HIP_TRY(vol, hipStreamSynchronize(ss));
+      HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+    }
     drop_graphs(vol);
     free_scene(vol);
     const int32_t nt = sc->num_triangles, nv = sc->num_vertices;
@@ -861,33 +929,45 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
       vol->has_scene = false;
       return fail(ADGI_ERR_OUT_OF_MEMORY, "allocator returned NULL for the scene");
     }
-    std::vector<float4> alb((size_t)std::max(nt, 1), make_float4(0.f, 0.f, 0.f, 0.f));
-    for (int32_t t = 0; t < nt; ++t) alb[t] = make_float4(sc->albedo[3 * t], sc->albedo[3 * t + 1], sc->albedo[3 * t + 2], 0.f);
-    // synchronous uploads (REBUILD is not on the per-frame path)
-    if (nv) HIP_TRY(vol, hipMemcpy(vol->d_pos, sc->positions, (size_t)nv * 12, hipMemcpyHostToDevice));
-    if (nt) {
-      HIP_TRY(vol, hipMemcpy(vol->d_idx, sc->indices, (size_t)nt * 12, hipMemcpyHostToDevice));
-      HIP_TRY(vol, hipMemcpy(vol->d_order, bvh.tri_order.data(), (size_t)nt * 4, hipMemcpyHostToDevice));
-      HIP_TRY(vol, hipMemcpy(vol->d_tris, bvh.tris.data(), bvh.tris.size() * 16, hipMemcpyHostToDevice));
+    HIP_TRY(vol, pinned_alloc((void**)&vol->h_stage, std::max<size_t>((size_t)nv * 12, 16)));
+    vol->h_stage_floats = (size_t)nv * 3;
+    // Uploads: synchronous from the caller's arrays (REBUILD is not on the
+    // per-frame path), or from a pinned scene image enqueued on the scene
+    // stream, whose later event orders every frame after them.
+    const uint8_t* img = built->pinned;
+    auto up = [&](void* dst, const void* host, PinPart part, size_t bytes) -> hipError_t {
+      if (!bytes) return hipSuccess;
+      if (img) return hipMemcpyAsync(dst, img + built->pin_off[part], bytes, hipMemcpyHostToDevice, ss);
+      return hipMemcpy(dst, host, bytes, hipMemcpyHostToDevice);
+    };
+    std::vector<float4> alb;
+    if (!img) {
+      alb.assign((size_t)std::max(nt, 1), make_float4(0.f, 0.f, 0.f, 0.f));
+      for (int32_t t = 0; t < nt; ++t)
+        alb[t] = make_float4(sc->albedo[3 * t], sc->albedo[3 * t + 1], sc->albedo[3 * t + 2], 0.f);
     }
-    if (!plan.level_nodes.empty())
-      HIP_TRY(vol, hipMemcpy(vol->d_levels, plan.level_nodes.data(), plan.level_nodes.size() * 4,
-                             hipMemcpyHostToDevice));
-    if (!plan.tab.empty())
-      HIP_TRY(vol, hipMemcpy(vol->d_refit_tab, plan.tab.data(), plan.tab.size() * 4, hipMemcpyHostToDevice));
-    if (!plan.leaf_slots.empty())
-      HIP_TRY(vol, hipMemcpy(vol->d_leaf_slots, plan.leaf_slots.data(), plan.leaf_slots.size() * 4,
-                             hipMemcpyHostToDevice));
+    if (nv && img) {
+      std::memcpy(vol->h_stage, sc->positions, (size_t)nv * 12);
+      HIP_TRY(vol, hipMemcpyAsync(vol->d_pos, vol->h_stage, (size_t)nv * 12, hipMemcpyHostToDevice, ss));
+    } else if (nv) {
+      HIP_TRY(vol, hipMemcpy(vol->d_pos, sc->positions, (size_t)nv * 12, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(vol, up(vol->d_idx, sc->indices, kPinIdx, (size_t)nt * 12));
+    HIP_TRY(vol, up(vol->d_order, bvh.tri_order.data(), kPinOrder, (size_t)nt * 4));
+    HIP_TRY(vol, up(vol->d_tris, bvh.tris.data(), kPinTris, nt ? bvh.tris.size() * 16 : 0));
+    HIP_TRY(vol, up(vol->d_levels, plan.level_nodes.data(), kPinLevels, plan.level_nodes.size() * 4));
+    HIP_TRY(vol, up(vol->d_refit_tab, plan.tab.data(), kPinTab, plan.tab.size() * 4));
+    HIP_TRY(vol, up(vol->d_leaf_slots, plan.leaf_slots.data(), kPinLeaf, plan.leaf_slots.size() * 4));
     vol->num_leaf_slots = (int32_t)plan.leaf_slots.size();
     vol->level_offsets = plan.level_offsets;
     vol->refit_cut = plan.cut;
     vol->refit_subtrees = plan.subtrees;
     vol->refit_deep = plan.deep_levels;
-    HIP_TRY(vol, hipMemcpy(vol->d_nodes, bvh.nodes.data(), bvh.nodes.size() * 16, hipMemcpyHostToDevice));
-    HIP_TRY(vol, hipMemcpy(vol->d_albedo, alb.data(), alb.size() * 16, hipMemcpyHostToDevice));
+    HIP_TRY(vol, up(vol->d_nodes, bvh.nodes.data(), kPinNodes, bvh.nodes.size() * 16));
+    HIP_TRY(vol, up(vol->d_albedo, alb.data(), kPinAlbedo, (size_t)std::max(nt, 1) * 16));
     if (fits4) {
-      HIP_TRY(vol, hipMemcpy(vol->d_nodes4, bvh4.nodes.data(), bvh4.nodes.size() * 16, hipMemcpyHostToDevice));
-      HIP_TRY(vol, hipMemcpy(vol->d_src4, bvh4.src.data(), bvh4.src.size() * 4, hipMemcpyHostToDevice));
+      HIP_TRY(vol, up(vol->d_nodes4, bvh4.nodes.data(), kPinNodes4, bvh4.nodes.size() * 16));
+      HIP_TRY(vol, up(vol->d_src4, bvh4.src.data(), kPinSrc4, bvh4.src.size() * 4));
       vol->num_nodes4 = (int32_t)(bvh4.nodes.size() / 8);
     }
     vol->nv = nv;
@@ -902,8 +982,6 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     hp.num_nodes = nn;
     hp.num_big = bvh.num_big;
     vol->num_big = bvh.num_big;
-    HIP_TRY(vol, pinned_alloc((void**)&vol->h_stage, std::max<size_t>((size_t)nv * 12, 16)));
-    vol->h_stage_floats = (size_t)nv * 3;
   } else {
     hp.num_nodes = vol->num_nodes;
     hp.num_big = vol->num_big;
@@ -955,6 +1033,116 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
 }
 
 hipStream_t volume_stream(adgi_volume* vol) { return vol->stream; }
+
+bool pin_scene(BuiltScene& b, const adgi_scene_desc* sc) {
+  unpin_scene(b);
+  const size_t nt = (size_t)sc->num_triangles;
+  size_t* len = b.pin_len;
+  len[kPinIdx] = nt * 12;
+  len[kPinOrder] = nt * 4;
+  len[kPinTris] = nt ? b.bvh.tris.size() * 16 : 0;
+  len[kPinLevels] = b.plan.level_nodes.size() * 4;
+  len[kPinTab] = b.plan.tab.size() * 4;
+  len[kPinLeaf] = b.plan.leaf_slots.size() * 4;
+  len[kPinNodes] = b.bvh.nodes.size() * 16;
+  len[kPinAlbedo] = std::max<size_t>(nt, 1) * 16;
+  len[kPinNodes4] = b.fits4 ? b.bvh4.nodes.size() * 16 : 0;
+  len[kPinSrc4] = b.fits4 ? b.bvh4.src.size() * 4 : 0;
+  size_t total = 0;
+  for (int k = 0; k < kPinParts; ++k) {
+    b.pin_off[k] = total;
+    total += (len[k] + 255) & ~(size_t)255;
+  }
+  uint8_t* img = nullptr;
+  // the image lives as long as its owner (a serving stream), so it takes
+  // its own allocation rather than a block of the reuse cache
+  if (hipHostMalloc((void**)&img, std::max<size_t>(total, 256), hipHostMallocDefault) != hipSuccess) return false;
+  auto put = [&](PinPart k, const void* src) {
+    if (len[k]) std::memcpy(img + b.pin_off[k], src, len[k]);
+  };
+  put(kPinIdx, sc->indices);
+  put(kPinOrder, b.bvh.tri_order.data());
+  put(kPinTris, b.bvh.tris.data());
+  put(kPinLevels, b.plan.level_nodes.data());
+  put(kPinTab, b.plan.tab.data());
+  put(kPinLeaf, b.plan.leaf_slots.data());
+  put(kPinNodes, b.bvh.nodes.data());
+  float4* alb = reinterpret_cast<float4*>(img + b.pin_off[kPinAlbedo]);
+  alb[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (size_t t = 0; t < nt; ++t)
+    alb[t] = make_float4(sc->albedo[3 * t], sc->albedo[3 * t + 1], sc->albedo[3 * t + 2], 0.f);
+  put(kPinNodes4, b.bvh4.nodes.data());
+  put(kPinSrc4, b.bvh4.src.data());
+  b.pinned = img;
+  return true;
+}
+
+void unpin_scene(BuiltScene& b) {
+  if (b.pinned) (void)hipHostFree(b.pinned);
+  b.pinned = nullptr;
+}
+
+adgi_status save_state_impl(adgi_volume* vol, void* dst, size_t bytes, bool async) {
+  if (!vol || !dst) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (bytes < adgi_state_size(vol)) return fail(ADGI_ERR_INVALID_ARG, "buffer too small");
+  if (!async) HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  SnapHeader h{};
+  h.magic = kSnapMagic;
+  h.P = vol->P;
+  h.irr_res = vol->desc.irr_res;
+  h.depth_res = vol->desc.depth_res;
+  h.storage = vol->desc.storage;
+  h.last_frame = vol->last_frame;
+  h.last_adaptive = vol->last_adaptive;
+  std::memcpy(h.last_R, vol->last_R, sizeof(h.last_R));
+  h.max_chains = vol->desc.max_chains;
+  h.chain_count = vol->chain_count;
+  h.chain_steps = vol->chain_steps;
+  h.dyn_count = vol->dyn_count;
+  h.dyn_steps = vol->dyn_steps;
+  uint8_t* o = (uint8_t*)dst;
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  for (const Part& p : state_parts(vol)) {
+    if (async)
+      HIP_TRY(vol, hipMemcpyAsync(o, p.dev, p.bytes, hipMemcpyDeviceToHost, vol->stream));
+    else
+      HIP_TRY(vol, hipMemcpy(o, p.dev, p.bytes, hipMemcpyDeviceToHost));
+    o += p.bytes;
+  }
+  return ADGI_OK;
+}
+
+adgi_status restore_state_impl(adgi_volume* vol, const void* src, size_t bytes, bool async) {
+  if (!vol || !src) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
+  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
+  if (bytes < adgi_state_size(vol)) return fail(ADGI_ERR_INVALID_ARG, "snapshot too small");
+  SnapHeader h;
+  std::memcpy(&h, src, sizeof(h));
+  if (h.magic != kSnapMagic || h.P != vol->P || h.irr_res != vol->desc.irr_res ||
+      h.depth_res != vol->desc.depth_res || h.storage != vol->desc.storage || h.max_chains != vol->desc.max_chains)
+    return fail(ADGI_ERR_INVALID_ARG, "snapshot does not match this volume");
+  // the synchronous copies run on the null stream, which does not wait
+  // for the volume's non-blocking stream
+  if (!async) HIP_TRY(vol, hipStreamSynchronize(vol->stream));
+  const uint8_t* o = (const uint8_t*)src + sizeof(h);
+  for (const Part& p : state_parts(vol)) {
+    if (async)
+      HIP_TRY(vol, hipMemcpyAsync(p.dev, o, p.bytes, hipMemcpyHostToDevice, vol->stream));
+    else
+      HIP_TRY(vol, hipMemcpy(p.dev, o, p.bytes, hipMemcpyHostToDevice));
+    o += p.bytes;
+  }
+  vol->last_frame = h.last_frame;
+  vol->last_adaptive = h.last_adaptive;
+  std::memcpy(vol->last_R, h.last_R, sizeof(h.last_R));
+  vol->chain_count = h.chain_count;
+  vol->chain_steps = h.chain_steps;
+  vol->dyn_count = h.dyn_count;
+  vol->dyn_steps = h.dyn_steps;
+  return ADGI_OK;
+}
 
 }  // namespace adgi
 
@@ -1320,59 +1508,12 @@ size_t adgi_state_size(const adgi_volume* vol) {
 }
 
 adgi_status adgi_save_state(adgi_volume* vol, void* dst, size_t bytes) {
-  if (!vol || !dst) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
-  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
-  if (bytes < adgi_state_size(vol)) return fail(ADGI_ERR_INVALID_ARG, "buffer too small");
-  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
-  SnapHeader h{};
-  h.magic = kSnapMagic;
-  h.P = vol->P;
-  h.irr_res = vol->desc.irr_res;
-  h.depth_res = vol->desc.depth_res;
-  h.storage = vol->desc.storage;
-  h.last_frame = vol->last_frame;
-  h.last_adaptive = vol->last_adaptive;
-  std::memcpy(h.last_R, vol->last_R, sizeof(h.last_R));
-  h.max_chains = vol->desc.max_chains;
-  h.chain_count = vol->chain_count;
-  h.chain_steps = vol->chain_steps;
-  h.dyn_count = vol->dyn_count;
-  h.dyn_steps = vol->dyn_steps;
-  uint8_t* o = (uint8_t*)dst;
-  std::memcpy(o, &h, sizeof(h));
-  o += sizeof(h);
-  for (const Part& p : state_parts(vol)) {
-    HIP_TRY(vol, hipMemcpy(o, p.dev, p.bytes, hipMemcpyDeviceToHost));
-    o += p.bytes;
-  }
-  return ADGI_OK;
+  return adgi::save_state_impl(vol, dst, bytes, false);
 }
 
 adgi_status adgi_restore_state(adgi_volume* vol, const void* src, size_t bytes) {
-  if (!vol || !src) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
-  if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
-  if (bytes < adgi_state_size(vol)) return fail(ADGI_ERR_INVALID_ARG, "snapshot too small");
-  SnapHeader h;
-  std::memcpy(&h, src, sizeof(h));
-  if (h.magic != kSnapMagic || h.P != vol->P || h.irr_res != vol->desc.irr_res ||
-      h.depth_res != vol->desc.depth_res || h.storage != vol->desc.storage || h.max_chains != vol->desc.max_chains)
-    return fail(ADGI_ERR_INVALID_ARG, "snapshot does not match this volume");
-  HIP_TRY(vol, hipStreamSynchronize(vol->stream));
-  const uint8_t* o = (const uint8_t*)src + sizeof(h);
-  for (const Part& p : state_parts(vol)) {
-    HIP_TRY(vol, hipMemcpy(p.dev, o, p.bytes, hipMemcpyHostToDevice));
-    o += p.bytes;
-  }
-  vol->last_frame = h.last_frame;
-  vol->last_adaptive = h.last_adaptive;
-  std::memcpy(vol->last_R, h.last_R, sizeof(h.last_R));
-  vol->chain_count = h.chain_count;
-  vol->chain_steps = h.chain_steps;
-  vol->dyn_count = h.dyn_count;
-  vol->dyn_steps = h.dyn_steps;
-  return ADGI_OK;
+  return adgi::restore_state_impl(vol, src, bytes, false);
 }
-
 
 adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* p, adgi_trace_work* out) {
   if (!vol || !p || !out) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
