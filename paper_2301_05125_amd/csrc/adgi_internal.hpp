@@ -173,6 +173,15 @@ adgi_status restore_state_impl(adgi_volume* vol, const void* src, size_t bytes, 
 // that stream has passed them.
 adgi_status save_state_impl(adgi_volume* vol, void* dst, size_t bytes, bool async);
 hipStream_t volume_stream(adgi_volume* vol);
+// Runs the volume's later work on `lane` (its scene work too), or on its own
+// streams again when lane is NULL. Work queued on the volume's own streams
+// is ordered before the lane's; the caller guarantees that the volume's work
+// on a lane it leaves is complete, and returns the volume to its own streams
+// before destroying it or the lane.
+adgi_status bind_streams(adgi_volume* vol, hipStream_t lane);
+// True once nothing is queued on the volume's own streams (creation fills,
+// scene uploads, state copies), so binding it to a lane adds no wait there.
+bool volume_settled(adgi_volume* vol);
 // Conservative box padding (builder and refit): a few ulps of the coordinate
 // plus an absolute term tied to the scene's coordinate scale, so that FP32
 // slab tests from any ray origin in the scene never cull a box a hit lies in.

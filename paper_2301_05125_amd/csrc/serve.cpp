@@ -15,8 +15,11 @@
 // temporal state to host memory and frees every device byte; admission
 // re-creates the volume, installs the scene from the BVH built once when the
 // stream was added, and restores the state, so a stream's results do not
-// depend on the mix it runs in. Completion times are taken by a host function
-// enqueued behind each frame, on the volume's stream.
+// depend on the mix it runs in. Frames run on server-owned lanes (one stream
+// per in-flight slot); a frame's completion is an event recorded behind it,
+// polled by the dispatcher, which stamps the time it sees the event done.
+// Eviction and admission enqueue their copies and return: an evicted volume
+// keeps its memory until its state copy has landed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -118,6 +121,8 @@ struct Stream {
   // device memory (and its share of the budget) until retire_ev completes
   adgi_volume* retiring = nullptr;
   hipEvent_t retire_ev = nullptr;
+  hipEvent_t done_ev = nullptr;  // recorded behind the frame in flight
+  int32_t lane = -1;             // server lane of the frame in flight
   int32_t next_frame = 0;
   std::deque<int64_t> pending;  // request ids not yet dispatched, in order
   int64_t inflight = -1;
@@ -129,6 +134,7 @@ struct Stream {
   Stream& operator=(const Stream&) = delete;
   ~Stream() {
     if (retire_ev) (void)hipEventDestroy(retire_ev);
+    if (done_ev) (void)hipEventDestroy(done_ev);
     if (state_buf) (void)hipHostFree(state_buf);
     adgi::unpin_scene(built);
   }
@@ -151,7 +157,6 @@ struct Stream {
   }
 };
 
-void mark_done(void* p) { static_cast<Request*>(p)->done_ns.store(now_ns()); }
 
 }  // namespace
 
@@ -160,6 +165,12 @@ struct adgi_server {
   Pool pool;
   int64_t budget = 0;
   int32_t max_inflight = 4;
+  // Frames run on a few server-owned streams ("lanes"), created in a row so
+  // the runtime spreads them over its hardware queues: a hardware queue
+  // runs its work in order, and streams created one volume at a time can
+  // all land on the same queue, serialising every stream's frames.
+  std::vector<hipStream_t> lanes;
+  std::vector<int32_t> lane_load;
   std::vector<std::unique_ptr<Stream>> streams;
   std::deque<Request> reqs;     // stable addresses for the completion callbacks
   std::deque<int64_t> waiting;  // undispatched request ids, arrival order
@@ -181,7 +192,10 @@ adgi_status evict(adgi_server* s, Stream& st) {
   auto t0 = now_ns();
   const size_t n = adgi_state_size(st.vol);
   if (n > st.state_cap) return sfail(ADGI_ERR_DEVICE, "stream state outgrew its host buffer");
-  adgi_status e = adgi::save_state_impl(st.vol, st.state_buf, n, true);
+  // idle: the copy goes on the volume's own stream, not behind a lane
+  adgi_status e = adgi::bind_streams(st.vol, nullptr);
+  if (e != ADGI_OK) return pass(e);
+  e = adgi::save_state_impl(st.vol, st.state_buf, n, true);
   if (e != ADGI_OK) return pass(e);
   if (hipEventRecord(st.retire_ev, adgi::volume_stream(st.vol)) != hipSuccess)
     return sfail(ADGI_ERR_DEVICE, "hipEventRecord failed");
@@ -294,17 +308,25 @@ bool make_room(adgi_server* s, const Stream& target, bool gentle, bool block, ad
 
 adgi_status dispatch(adgi_server* s, Stream& st, int64_t id) {
   Request& r = s->reqs[id];
+  // the stream is idle: its last frame is done, so it may change lanes
+  size_t k = 0;
+  for (size_t j = 1; j < s->lanes.size(); ++j)
+    if (s->lane_load[j] < s->lane_load[k]) k = j;
+  adgi_status e = adgi::bind_streams(st.vol, s->lanes[k]);
+  if (e != ADGI_OK) return pass(e);
   adgi_scene_desc sd = st.scene(ADGI_SCENE_REFIT, &r.lights[0][0]);
-  adgi_status e = adgi_update_scene(st.vol, &sd);
+  e = adgi_update_scene(st.vol, &sd);
   if (e != ADGI_OK) return pass(e);
   adgi_update_params p = st.params;
   p.frame = st.next_frame;
   p.sync = 0;
   if ((e = adgi_update_probes(st.vol, &p, nullptr)) != ADGI_OK) return pass(e);
-  if (hipLaunchHostFunc(adgi::volume_stream(st.vol), mark_done, &r) != hipSuccess)
-    return sfail(ADGI_ERR_DEVICE, "hipLaunchHostFunc failed");
+  if (hipEventRecord(st.done_ev, adgi::volume_stream(st.vol)) != hipSuccess)
+    return sfail(ADGI_ERR_DEVICE, "hipEventRecord failed");
   r.frame = st.next_frame++;
   r.dispatch_ns = now_ns();
+  st.lane = (int32_t)k;
+  ++s->lane_load[k];
   st.inflight = id;
   st.pending.pop_front();
   ++s->inflight;
@@ -317,14 +339,17 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
     Stream& st = *p;
     if (st.inflight < 0) continue;
     Request& r = s->reqs[st.inflight];
-    const int64_t t = r.done_ns.load();
-    if (t == 0) continue;
+    if (hipEventQuery(st.done_ev) != hipSuccess) continue;
+    const int64_t t = now_ns();
+    r.done_ns.store(t);
     r.completed = true;
     s->latency_ms.push_back((t - r.arrival_ns) * 1e-6);
     s->rays += st.params.budget;
     s->last_done_ns = std::max(s->last_done_ns, t);
     st.last_use_ns = t;
     st.inflight = -1;
+    --s->lane_load[st.lane];
+    st.lane = -1;
     --s->inflight;
     ++s->completed;
     ++done;
@@ -339,8 +364,7 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
       adgi_status err = ADGI_OK;
       if (make_room(s, st, /*gentle=*/false, /*block=*/false, &err)) {
         if ((err = make_resident(s, st)) != ADGI_OK) return err;
-        if ((err = dispatch(s, st, id)) != ADGI_OK) return err;
-        s->waiting.pop_front();
+        // dispatched by (2) once its setup copies have landed
       } else if (err != ADGI_OK) {
         return err;
       }
@@ -350,7 +374,9 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
   for (size_t k = 0; k < s->waiting.size() && s->inflight < s->max_inflight;) {
     const int64_t id = s->waiting[k];
     Stream& st = *s->streams[s->reqs[id].stream];
-    if (!st.vol || st.inflight >= 0 || st.pending.front() != id) {
+    // a volume just admitted waits until its uploads and state copy have
+    // landed: a lane made to wait for them would hold up every frame behind
+    if (!st.vol || st.inflight >= 0 || st.pending.front() != id || !adgi::volume_settled(st.vol)) {
       ++k;
       continue;
     }
@@ -374,8 +400,12 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
       break;  // the budget is held by streams in flight or with work waiting
     }
     if ((err = make_resident(s, st)) != ADGI_OK) return err;
-    if ((err = dispatch(s, st, id)) != ADGI_OK) return err;
-    s->waiting.erase(s->waiting.begin() + (std::ptrdiff_t)k);
+    if (adgi::volume_settled(st.vol)) {
+      if ((err = dispatch(s, st, id)) != ADGI_OK) return err;
+      s->waiting.erase(s->waiting.begin() + (std::ptrdiff_t)k);
+    } else {
+      ++k;  // dispatched by (2) on a later pass
+    }
   }
   if (done_now) *done_now = done;
   return ADGI_OK;
@@ -410,6 +440,17 @@ adgi_status adgi_server_create(const adgi_server_desc* desc, const adgi_allocato
     return sfail(ADGI_ERR_INVALID_ARG, "allocator callbacks must not be NULL");
   }
   s->alloc = alloc ? *alloc : adgi_allocator{pool_alloc, pool_free, &s->pool};
+  const int nl = std::min(desc->max_inflight, 16);
+  for (int k = 0; k < nl; ++k) {
+    hipStream_t l = nullptr;
+    if (hipStreamCreateWithFlags(&l, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : s->lanes) (void)hipStreamDestroy(x);
+      delete s;
+      return sfail(ADGI_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    s->lanes.push_back(l);
+  }
+  s->lane_load.assign(s->lanes.size(), 0);
   *out = s;
   return ADGI_OK;
 }
@@ -466,7 +507,8 @@ adgi_status adgi_server_add_stream(adgi_server* s, const adgi_stream_desc* d, in
   if (e != ADGI_OK) return e;
   if (hipHostMalloc((void**)&st->state_buf, std::max<size_t>(st->state_cap, 1), hipHostMallocDefault) != hipSuccess)
     return sfail(ADGI_ERR_OUT_OF_MEMORY, "pinned host buffer for the stream state");
-  if (hipEventCreateWithFlags(&st->retire_ev, hipEventDisableTiming) != hipSuccess)
+  if (hipEventCreateWithFlags(&st->retire_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&st->done_ev, hipEventDisableTiming) != hipSuccess)
     return sfail(ADGI_ERR_DEVICE, "hipEventCreate failed");
   if (st->footprint > s->budget) return sfail(ADGI_ERR_OUT_OF_MEMORY, "stream footprint exceeds the HBM budget");
   *id = (int32_t)s->streams.size();
@@ -567,6 +609,9 @@ adgi_status adgi_server_read_stream(adgi_server* s, int32_t id, adgi_probe_readb
       return err != ADGI_OK ? err : sfail(ADGI_ERR_OUT_OF_MEMORY, "no room to admit the stream");
     if ((err = make_resident(s, st)) != ADGI_OK) return err;
   }
+  // idle: read on the volume's own stream rather than behind a lane
+  adgi_status e = adgi::bind_streams(st.vol, nullptr);
+  if (e != ADGI_OK) return pass(e);
   return pass(adgi_read_probes(st.vol, rb));
 }
 
@@ -575,11 +620,13 @@ void adgi_server_destroy(adgi_server* s) {
   for (auto& p : s->streams) {
     if (p->vol) {
       (void)hipStreamSynchronize(adgi::volume_stream(p->vol));
+      (void)adgi::bind_streams(p->vol, nullptr);
       adgi_destroy_volume(p->vol);
     }
     if (p->retiring) adgi_destroy_volume(p->retiring);
   }
   for (auto& kv : s->pool.size_of) (void)hipFree(kv.first);
+  for (hipStream_t l : s->lanes) (void)hipStreamDestroy(l);
   delete s;
 }
 

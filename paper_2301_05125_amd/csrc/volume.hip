@@ -122,6 +122,10 @@ struct adgi_volume {
   // frame's trace (ev_traced) and before the next frame (ev_refit), so the
   // refit overlaps the last frame's blend, which does not read the scene.
   hipStream_t scene_stream = nullptr;
+  // The volume's own pair; stream/scene_stream may instead name a stream
+  // lent by a caller for a while (bind_streams).
+  hipStream_t own_stream = nullptr, own_scene = nullptr;
+  hipEvent_t ev_bind[2] = {};
   hipEvent_t ev_traced = nullptr, ev_refit = nullptr;
   hipEvent_t ev_user = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_slot[kParamSlots] = {};
@@ -378,14 +382,13 @@ void pinned_free(void* p) {
   if (it != c.size_of.end()) c.free_blocks.insert({it->second, p});
 }
 
-// Streams and events of released volumes, per device, for the next volume:
-// creating and destroying them costs a few tenths of a millisecond each
-// time a server admits or evicts a volume. Every one returned here has no
-// work pending on it (release waits for both streams first).
+// Streams of released volumes, per device, for the next volume: creating
+// and destroying a pair costs about 0.3 ms each time a server admits or
+// evicts a volume. Every one returned here has no work pending on it
+// (release waits for both streams first).
 struct HandleCache {
   std::mutex mu;
   std::multimap<int, hipStream_t> streams;
-  std::multimap<int, hipEvent_t> events[2];  // [timing]
 };
 
 HandleCache& handle_cache() {
@@ -407,17 +410,10 @@ hipError_t take_stream(int device, hipStream_t* s) {
   return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
 }
 
-hipError_t take_event(int device, bool timing, hipEvent_t* e) {
-  HandleCache& c = handle_cache();
-  {
-    std::lock_guard<std::mutex> lk(c.mu);
-    auto it = c.events[timing].find(device);
-    if (it != c.events[timing].end()) {
-      *e = it->second;
-      c.events[timing].erase(it);
-      return hipSuccess;
-    }
-  }
+// Events are not recycled: one keeps the runtime's record of where it was
+// last recorded (a graph node, a capturing stream), which decides what a
+// later owner may do with it, and creating one costs microseconds.
+hipError_t take_event(bool timing, hipEvent_t* e) {
   return timing ? hipEventCreate(e) : hipEventCreateWithFlags(e, hipEventDisableTiming);
 }
 
@@ -428,11 +424,8 @@ void give_stream(int device, hipStream_t s) {
   c.streams.insert({device, s});
 }
 
-void give_event(int device, bool timing, hipEvent_t e) {
-  if (!e) return;
-  HandleCache& c = handle_cache();
-  std::lock_guard<std::mutex> lk(c.mu);
-  c.events[timing].insert({device, e});
+void give_event(hipEvent_t e) {
+  if (e) (void)hipEventDestroy(e);
 }
 
 void free_scene(adgi_volume* vol) {
@@ -469,6 +462,8 @@ void finish_stream(hipStream_t s) {
 void release(adgi_volume* vol) {
   finish_stream(vol->scene_stream);
   finish_stream(vol->stream);
+  if (vol->scene_stream != vol->own_scene) finish_stream(vol->own_scene);
+  if (vol->stream != vol->own_stream) finish_stream(vol->own_stream);
   drop_graphs(vol);
   free_scene(vol);
   while (!vol->allocs.empty()) vol_free(vol, vol->allocs.back().first);
@@ -476,12 +471,13 @@ void release(adgi_volume* vol) {
   pinned_free(vol->h_stats);
   pinned_free(vol->h_scene);
   const int dev = vol->device;
-  for (hipEvent_t e : vol->ev_slot) give_event(dev, false, e);
-  for (hipEvent_t e : vol->ev_k) give_event(dev, true, e);
-  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage}) give_event(dev, true, e);
-  for (hipEvent_t e : {vol->ev_traced, vol->ev_refit}) give_event(dev, false, e);
-  give_stream(dev, vol->stream);
-  give_stream(dev, vol->scene_stream);
+  for (hipEvent_t e : vol->ev_slot) give_event(e);
+  for (hipEvent_t e : vol->ev_k) give_event(e);
+  for (hipEvent_t e : {vol->ev_user, vol->ev_done, vol->ev_t0, vol->ev_t1, vol->ev_stage, vol->ev_traced,
+                      vol->ev_refit, vol->ev_bind[0], vol->ev_bind[1]})
+    give_event(e);
+  give_stream(dev, vol->own_stream);
+  give_stream(dev, vol->own_scene);
 }
 
 // Bytes of one probe's irradiance / depth tile (with border) in HBM.
@@ -663,13 +659,16 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   } while (0)
   CREATE_TRY(hipGetDevice(&vol->device));
   CREATE_TRY(hipDeviceGetAttribute(&vol->num_cus, hipDeviceAttributeMultiprocessorCount, vol->device));
-  CREATE_TRY(take_stream(vol->device, &vol->stream));
-  CREATE_TRY(take_stream(vol->device, &vol->scene_stream));
+  CREATE_TRY(take_stream(vol->device, &vol->own_stream));
+  CREATE_TRY(take_stream(vol->device, &vol->own_scene));
+  vol->stream = vol->own_stream;
+  vol->scene_stream = vol->own_scene;
+  for (auto& e : vol->ev_bind) CREATE_TRY(take_event(false, &e));
   for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_t0, &vol->ev_t1, &vol->ev_stage})
-    CREATE_TRY(take_event(vol->device, true, e));
-  for (hipEvent_t* e : {&vol->ev_traced, &vol->ev_refit}) CREATE_TRY(take_event(vol->device, false, e));
-  for (auto& e : vol->ev_slot) CREATE_TRY(take_event(vol->device, false, &e));
-  for (auto& e : vol->ev_k) CREATE_TRY(take_event(vol->device, true, &e));
+    CREATE_TRY(take_event(true, e));
+  for (hipEvent_t* e : {&vol->ev_traced, &vol->ev_refit}) CREATE_TRY(take_event(false, e));
+  for (auto& e : vol->ev_slot) CREATE_TRY(take_event(false, &e));
+  for (auto& e : vol->ev_k) CREATE_TRY(take_event(true, &e));
   CREATE_TRY(pinned_alloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots));
   CREATE_TRY(pinned_alloc((void**)&vol->h_stats, sizeof(FrameStats)));
   CREATE_TRY(pinned_alloc((void**)&vol->h_scene, sizeof(SceneParams)));
@@ -1033,6 +1032,32 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
 }
 
 hipStream_t volume_stream(adgi_volume* vol) { return vol->stream; }
+
+bool volume_settled(adgi_volume* vol) {
+  return hipStreamQuery(vol->own_stream) == hipSuccess && hipStreamQuery(vol->own_scene) == hipSuccess;
+}
+
+adgi_status bind_streams(adgi_volume* vol, hipStream_t lane) {
+  hipStream_t m = lane ? lane : vol->own_stream, sc = lane ? lane : vol->own_scene;
+  if (m == vol->stream && sc == vol->scene_stream) return ADGI_OK;
+  // work still queued on the volume's own streams (zero fill, uploads, state
+  // copies) goes before anything on the new ones; work on a lent stream is
+  // complete by the caller's contract, and waiting on that stream would also
+  // wait for other volumes' work behind it
+  if (vol->stream == vol->own_stream && hipStreamQuery(vol->own_stream) != hipSuccess) {
+    HIP_TRY(vol, hipEventRecord(vol->ev_bind[0], vol->own_stream));
+    HIP_TRY(vol, hipStreamWaitEvent(m, vol->ev_bind[0], 0));
+    if (sc != m) HIP_TRY(vol, hipStreamWaitEvent(sc, vol->ev_bind[0], 0));
+  }
+  if (vol->scene_stream == vol->own_scene && hipStreamQuery(vol->own_scene) != hipSuccess) {
+    HIP_TRY(vol, hipEventRecord(vol->ev_bind[1], vol->own_scene));
+    HIP_TRY(vol, hipStreamWaitEvent(m, vol->ev_bind[1], 0));
+    if (sc != m) HIP_TRY(vol, hipStreamWaitEvent(sc, vol->ev_bind[1], 0));
+  }
+  vol->stream = m;
+  vol->scene_stream = sc;
+  return ADGI_OK;
+}
 
 bool pin_scene(BuiltScene& b, const adgi_scene_desc* sc) {
   unpin_scene(b);

@@ -49,6 +49,17 @@ def test_bitwise_determinism_across_runs():
     _same(_run(sc, 6, **kw), _run(sc, 6, **kw))
 
 
+def test_later_volumes_reuse_released_streams():
+    """The streams of a destroyed volume go to the next one created (its
+    events are new): volumes made one after another, each running more
+    graph frames than its parameter ring has slots, agree bit for bit."""
+    sc = scenes.box_field(lattice=48, dims=(16, 4, 16), frames=12)
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    first = _run(sc, 10, **kw)
+    for _ in range(3):
+        _same(first, _run(sc, 10, **kw))
+
+
 def test_large_ray_buffers_take_the_multi_block_pair_scan():
     """A volume whose ray buffers hold more than 2^14 batches of 64 rays lays
     out the shadow pairs with the three-launch scan; the frames must match a

@@ -56,6 +56,15 @@ def test_serving_mix_equals_streams_alone():
         sent[s] += 1
         srv.progress()
     srv.drain()
+    assert srv.stats()["evictions"] > 0
+    # one more frame for every stream: the evicted ones come back through
+    # admission and restore their state
+    for s in sids:
+        srv.submit(int(s), scs[s].light_positions(sent[s]))
+        sent[s] += 1
+        frames[s] += 1
+        srv.progress()
+    srv.drain()
     st = srv.stats()
     print(st)
     assert st["completed"] == st["submitted"] == sum(frames)
