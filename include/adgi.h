@@ -374,16 +374,19 @@ size_t adgi_device_bytes(const adgi_volume* vol);
  * grid, budget and frame parameters (adaptive frames only). A request asks
  * for the stream's next frame with that frame's light positions. Requests are
  * dispatched in arrival order, at most one frame of a stream and at most
- * max_inflight frames in total at a time, each volume on its own HIP stream.
- * Resident streams are served first. HBM admission: a stream's volume is
+ * max_inflight frames in total at a time, on min(max_inflight, 16) streams
+ * the server creates ("lanes"; an idle volume takes the least-loaded lane for
+ * its next frame). Resident streams are served first. HBM admission: a stream's volume is
  * resident only while the device bytes of all resident volumes stay within
  * hbm_budget_bytes; to admit one, idle resident streams with nothing waiting
  * are evicted, least recently used first (a request waiting over 250 ms may
- * also evict idle streams resident for over 500 ms). Eviction moves the
- * temporal state to host memory and frees all the volume's device memory;
- * re-admission rebuilds the volume from the BVH the server built once per
- * stream and restores the state, so a stream's results are bitwise those it
- * would have alone. The server is not thread-safe; its
+ * also evict idle streams resident for over 500 ms). Eviction enqueues the
+ * copy of the temporal state to pinned host memory and frees all the
+ * volume's device memory once it has landed (until then the bytes stay
+ * counted against the budget); re-admission rebuilds the volume from the BVH
+ * the server built once per stream (uploaded from a pinned copy) and
+ * restores the state, and its first frame is dispatched once those copies
+ * have landed, so a stream's results are bitwise those it would have alone. The server is not thread-safe; its
  * own errors are described by adgi_server_last_error (volume errors by
  * adgi_last_error). The scene arrays of adgi_server_add_stream are copied. */
 typedef struct adgi_server adgi_server;
@@ -401,7 +404,7 @@ typedef struct {
   int64_t submitted, completed, admissions, evictions;
   int64_t primary_rays;       /* budget of every completed frame                  */
   int64_t resident_bytes, peak_resident_bytes;
-  double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival -> frame done on the GPU   */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival -> frame seen done (event) */
   double span_s;              /* first arrival -> last completion                 */
   double admit_ms, evict_ms;  /* host time spent admitting and evicting          */
 } adgi_server_stats;

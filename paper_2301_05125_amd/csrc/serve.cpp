@@ -98,7 +98,7 @@ struct Request {
   int32_t frame = 0;
   float lights[ADGI_MAX_LIGHTS][3] = {};
   int64_t arrival_ns = 0, dispatch_ns = 0;
-  std::atomic<int64_t> done_ns{0};
+  int64_t done_ns = 0;  // when the dispatcher saw the frame done
   bool completed = false;
 };
 
@@ -341,7 +341,7 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
     Request& r = s->reqs[st.inflight];
     if (hipEventQuery(st.done_ev) != hipSuccess) continue;
     const int64_t t = now_ns();
-    r.done_ns.store(t);
+    r.done_ns = t;
     r.completed = true;
     s->latency_ms.push_back((t - r.arrival_ns) * 1e-6);
     s->rays += st.params.budget;
