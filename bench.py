@@ -16,6 +16,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -597,7 +598,8 @@ def main():
         tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
         prof = read_profile(prof_key, h_trace)
         # the counters belong to one traversal variant (<kind, count, width 4>)
-        if not prof.get("kernel_name", "").endswith("%s>(adgi::VolumeView, int)" % ("true" if width == 4 else "false")):
+        m = re.search(r"<\s*\d+\s*,\s*(true|false)\s*,\s*(true|false)\s*>", prof.get("kernel_name", ""))
+        if not m or m.group(2) != ("true" if width == 4 else "false"):
             prof = {}
         return {"bound": "alu", "kernel": "%s<primary, BVH%d>" % (kernel, width), "achieved": tops,
                 "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": tops / VALU_PEAK_TOPS,
