@@ -374,9 +374,9 @@ size_t adgi_device_bytes(const adgi_volume* vol);
  * grid, budget and frame parameters (adaptive frames only). A request asks
  * for the stream's next frame with that frame's light positions. Requests are
  * dispatched in arrival order, at most one frame of a stream and at most
- * max_inflight frames in total at a time, on min(max_inflight, 16) streams
- * the server creates ("lanes"; an idle volume takes the least-loaded lane for
- * its next frame). Resident streams are served first. HBM admission: a stream's volume is
+ * max_inflight frames in total at a time, on min(2 max_inflight, 16)
+ * streams the server creates ("lanes"; an idle volume takes the next
+ * least-loaded lane in rotation for its next frame). Resident streams are served first. HBM admission: a stream's volume is
  * resident only while the device bytes of all resident volumes stay within
  * hbm_budget_bytes; to admit one, idle resident streams with nothing waiting
  * are evicted, least recently used first (a request waiting over 250 ms may

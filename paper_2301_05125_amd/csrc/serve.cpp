@@ -169,8 +169,13 @@ struct adgi_server {
   // the runtime spreads them over its hardware queues: a hardware queue
   // runs its work in order, and streams created one volume at a time can
   // all land on the same queue, serialising every stream's frames.
+  // The runtime gives a new stream the queue with the fewest streams, so
+  // lanes created after other streams crowd onto the emptiest queues first;
+  // there are twice as many lanes as in-flight slots and frames take them in
+  // rotation (least loaded first), which spreads them over every queue.
   std::vector<hipStream_t> lanes;
   std::vector<int32_t> lane_load;
+  size_t next_lane = 0;
   std::vector<std::unique_ptr<Stream>> streams;
   std::deque<Request> reqs;     // stable addresses for the completion callbacks
   std::deque<int64_t> waiting;  // undispatched request ids, arrival order
@@ -309,9 +314,12 @@ bool make_room(adgi_server* s, const Stream& target, bool gentle, bool block, ad
 adgi_status dispatch(adgi_server* s, Stream& st, int64_t id) {
   Request& r = s->reqs[id];
   // the stream is idle: its last frame is done, so it may change lanes
-  size_t k = 0;
-  for (size_t j = 1; j < s->lanes.size(); ++j)
+  const size_t nl = s->lanes.size();
+  size_t k = s->next_lane % nl;
+  for (size_t a = 1; a < nl; ++a) {
+    const size_t j = (s->next_lane + a) % nl;
     if (s->lane_load[j] < s->lane_load[k]) k = j;
+  }
   adgi_status e = adgi::bind_streams(st.vol, s->lanes[k]);
   if (e != ADGI_OK) return pass(e);
   adgi_scene_desc sd = st.scene(ADGI_SCENE_REFIT, &r.lights[0][0]);
@@ -327,6 +335,7 @@ adgi_status dispatch(adgi_server* s, Stream& st, int64_t id) {
   r.dispatch_ns = now_ns();
   st.lane = (int32_t)k;
   ++s->lane_load[k];
+  s->next_lane = k + 1;
   st.inflight = id;
   st.pending.pop_front();
   ++s->inflight;
@@ -440,7 +449,7 @@ adgi_status adgi_server_create(const adgi_server_desc* desc, const adgi_allocato
     return sfail(ADGI_ERR_INVALID_ARG, "allocator callbacks must not be NULL");
   }
   s->alloc = alloc ? *alloc : adgi_allocator{pool_alloc, pool_free, &s->pool};
-  const int nl = std::min(desc->max_inflight, 16);
+  const int nl = std::min(2 * desc->max_inflight, 16);
   for (int k = 0; k < nl; ++k) {
     hipStream_t l = nullptr;
     if (hipStreamCreateWithFlags(&l, hipStreamNonBlocking) != hipSuccess) {
