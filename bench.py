@@ -95,6 +95,13 @@ def read_profile(kernel_key, src_hash):
     return out
 
 
+def profile_matches_width(kernel_name, width):
+    """True if a profiled traversal kernel (template <kind, count, width 4>)
+    is the variant of the given BVH width."""
+    m = re.search(r"<\s*\d+\s*,\s*(true|false)\s*,\s*(true|false)\s*>", kernel_name)
+    return bool(m) and m.group(2) == ("true" if width == 4 else "false")
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy of nbytes (read + write), best of reps, GB/s."""
     x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -598,8 +605,7 @@ def main():
         tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
         prof = read_profile(prof_key, h_trace)
         # the counters belong to one traversal variant (<kind, count, width 4>)
-        m = re.search(r"<\s*\d+\s*,\s*(true|false)\s*,\s*(true|false)\s*>", prof.get("kernel_name", ""))
-        if not m or m.group(2) != ("true" if width == 4 else "false"):
+        if not profile_matches_width(prof.get("kernel_name", ""), width):
             prof = {}
         return {"bound": "alu", "kernel": "%s<primary, BVH%d>" % (kernel, width), "achieved": tops,
                 "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": tops / VALU_PEAK_TOPS,
