@@ -457,6 +457,24 @@ def cpu_small_workloads(oracle):
     return out
 
 
+def run_serving_child(duration_s):
+    """The serving mix in a process of its own: a failure there is reported
+    in its place ({"error": ...}) and does not take the main measurement
+    with it."""
+    import subprocess
+    try:
+        r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
+                            "--serve-seconds", str(duration_s)], capture_output=True, text=True,
+                           timeout=120 + 10 * duration_s)
+    except subprocess.TimeoutExpired:
+        return {"error": "serving process timed out"}
+    sys.stderr.write(r.stderr[-2000:])
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"serving process exited with status {r.returncode}"}
+    return json.loads(lines[-1])
+
+
 def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=8):
     """Serving mix: 32 streams (box fields of 10k-500k triangles, 512-32768
     probes, B = 128 rays per probe), Poisson arrivals at 30-120 Hz each, for
@@ -516,6 +534,8 @@ def main():
     ap.add_argument("--skip-uniform", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the 32-stream serving mix")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving mix and print its JSON (the bench runs it so, as a child)")
     ap.add_argument("--quality", action="store_true",
                     help="texel error against a converged reference: adaptive vs uniform vs chains")
     ap.add_argument("--chains", default=",".join(CHAIN_CONFIGS),
@@ -523,6 +543,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    if args.serve_only:
+        import torch
+        import paper_2301_05125_amd as adgi
+        torch.cuda.set_device(0)
+        print(json.dumps(run_serving(adgi, duration_s=args.serve_seconds)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see the sharding design); use --gpus 1", file=sys.stderr)
@@ -689,7 +715,7 @@ def main():
                 c["burn_in"], c.get("dyn_chains", 0), c.get("dyn_steps", 0), c.get("dyn_burn_in", 0))
             print(f"[bench] chains {name} done", file=sys.stderr, flush=True)
     if not args.no_serve:
-        out["serving"] = run_serving(adgi, duration_s=args.serve_seconds)
+        out["serving"] = run_serving_child(args.serve_seconds)
         print(f"[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
