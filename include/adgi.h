@@ -265,28 +265,51 @@ typedef struct {
   int32_t reserved;
 } adgi_probe_readback;
 
-/* Create a volume. desc/alloc are host, copied. hip_stream (hipStream_t or
- * NULL) is the caller's stream: every call orders its device work after the
- * work already on that stream and makes that stream wait for it. Texels and
- * counts start at zero. *out receives the handle. */
+/* Create a volume: the uniform probe grid of Sec. 3.1 (probe i at origin +
+ * (x, y, z) * spacing) with one octahedral irradiance tile and one
+ * depth-moment (visibility) tile per probe, of the sizes of Tab.
+ * probeDetails (8x8 and 16x16 with border by default). desc/alloc are host,
+ * copied. hip_stream (hipStream_t or NULL) is the caller's stream: every call
+ * orders its device work after the work already on that stream and makes
+ * that stream wait for it. Texels and counts start at zero. *out receives the
+ * handle, owned by the caller until adgi_destroy_volume. Errors:
+ * ADGI_ERR_INVALID_ARG for a descriptor out of range (nothing allocated),
+ * ADGI_ERR_OUT_OF_MEMORY when the allocator returns NULL (everything
+ * allocated so far is released), ADGI_ERR_DEVICE when a HIP call fails. */
 adgi_status adgi_create_volume(const adgi_volume_desc* desc, const adgi_allocator* alloc,
                                void* hip_stream, adgi_volume** out);
 
-/* Upload or change the scene (triangles, albedo, lights, sky). REBUILD
- * builds a binned-SAH BVH on the host and uploads it; REFIT uploads the
- * changed vertex range and refits the boxes on the device. Lights and sky
- * are taken on every call. Asynchronous w.r.t. the device; the host arrays
- * may be reused on return. */
+/* Upload or change the scene the probes see (Sec. 4.4 and 5: dynamic
+ * lights and moving geometry between frames): triangles, per-triangle
+ * albedo, point lights and sky. REBUILD builds a binned-SAH BVH on the host
+ * and uploads it; REFIT uploads the changed vertex range and refits the
+ * boxes on the device. Lights and sky are taken on every call. Asynchronous
+ * w.r.t. the device; the host arrays are copied and may be reused on return.
+ * Errors: ADGI_ERR_INVALID_ARG (NULL or non-finite arrays, indices out of
+ * range, unknown mode), ADGI_ERR_NO_SCENE (REFIT before any REBUILD),
+ * ADGI_ERR_TOPOLOGY (REFIT with another vertex or triangle count),
+ * ADGI_ERR_OUT_OF_MEMORY, ADGI_ERR_DEVICE; on error the previous scene stays. */
 adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* scene);
 
-/* One probe-update frame (pilots, detection, allocation, trace, shade,
- * blend), enqueued as one HIP graph launch. Errors: ADGI_ERR_NO_SCENE,
- * ADGI_ERR_BUDGET, ADGI_ERR_INVALID_ARG. stats may be NULL; it is filled only
- * when params->sync is 1. */
+/* One probe-update frame, enqueued as one HIP graph launch: pilot rays and
+ * change detection (Sec. 4.1, eq. ProbeVis, eq. priorDynamic), the split of
+ * the frame's fixed sample budget over the probes (Sec. 3.3), ray tracing
+ * with direct light at the hits (Sec. 3.1, 4.8), and the per-sample update of
+ * the texel each sample falls in (Alg. ApproxAlgo, Alg. MovingAvgUpdate,
+ * Sec. 4.5-4.7). params and stats are host memory; stats may be NULL and is
+ * filled only when params->sync is 1 (the call then waits for the frame).
+ * Errors (nothing enqueued): ADGI_ERR_NO_SCENE, ADGI_ERR_BUDGET,
+ * ADGI_ERR_INVALID_ARG; ADGI_ERR_DEVICE when a HIP call fails (sticky). */
 adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* params,
                                adgi_update_stats* stats);
 
-/* Wait for the volume's work and copy state into caller buffers. */
+/* Wait for the volume's work and copy its probes into caller buffers: the
+ * octahedral irradiance and depth-moment tiles a renderer reads at shading
+ * points (Sec. 3.1's lookup; adgi_query_irradiance does that lookup on the
+ * device), their sample counts, and the last frame's allocation and debug
+ * arrays. out and every non-NULL field are host memory of the sizes given in
+ * adgi_probe_readback. Errors: ADGI_ERR_INVALID_ARG (debug arrays without
+ * ADGI_DEBUG_ARRAYS, raw words without ADGI_PACKED), ADGI_ERR_DEVICE. */
 adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out);
 
 /* Irradiance at shading points (the deferred-shading lookup of Sec. 3.1, with
@@ -316,8 +339,10 @@ const char* adgi_last_error(void);
  * setting. Defaults: graph on, persistent traversal, autotuned sizes. */
 typedef struct {
   int32_t use_graph;          /* 1: capture the frame as a hipGraph; 0: eager     */
-  int32_t persistent;         /* 1: work-stealing persistent traversal;
-                                 0: one thread per ray, grid sized to the rays    */
+  int32_t persistent;         /* 1: persistent traversal, a fixed grid whose waves
+                                 take 64-ray batches by grid stride (no shared
+                                 counter); 0: one thread per ray, grid sized to
+                                 the rays                                         */
   int32_t trace_block;        /* threads per traversal workgroup: 64..1024, x64   */
   int32_t trace_waves_per_cu; /* persistent grid = CUs * this / (block/64), 1..32 */
   int32_t blend_chunk;        /* 0: wave-per-probe blend (tiles 8/16 or 16/16),

@@ -541,12 +541,16 @@ class OracleVolume:
             self.scene.set_positions(sc.positions_at(frame))
         self.scene.set_lights(sc.light_positions(frame), sc.light_intensity, sc.sky)
 
-    def pilots(self, frame: int, beta: float = 5.0, hint_qv=None, hint_qr=None):
+    def pilots(self, frame: int, beta: float = 5.0, hint_qv=None, hint_qr=None, counts=None):
+        """Pilot codes (Qv, Qr) of every probe and octant; ties and
+        mismatches against the hints go to ``counts`` (default: the running
+        totals)."""
         qv = np.zeros(self.P * 8, np.uint16)
         qr = np.zeros(self.P * 8, np.uint16)
         lib().orc_pilots(self.scene.ptr, C.byref(self.grid), self.seed & 0xFFFFFFFFFFFFFFFF,
                          frame, float(np.float32(beta)), C.byref(self.tol),
-                         _p(hint_qv), _p(hint_qr), _p(qv), _p(qr), C.byref(self.counts))
+                         _p(hint_qv), _p(hint_qr), _p(qv), _p(qr),
+                         C.byref(counts if counts is not None else self.counts))
         return qv, qr
 
     def detect(self, frame: int, qv, qr, theta: int = 8, mu: int = 2):
@@ -565,9 +569,10 @@ class OracleVolume:
         out = {}
         secs = {"scene": time.perf_counter() - t0, "pilots": 0.0, "detect_allocate": 0.0,
                 "probes": 0.0}
+        cnt = Counts()
         if adaptive:
             t0 = time.perf_counter()
-            qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"))
+            qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"), counts=cnt)
             t1 = time.perf_counter()
             score = self.detect(frame, qv, qr, theta, mu)
             n, off, lam = allocate(score, budget, n_min, n_max)
@@ -606,7 +611,6 @@ class OracleVolume:
         sh = np.zeros(max(total, 1), np.uint8) if keep_rays else None
         ib = np.zeros(max(total, 1), np.uint16) if keep_rays else None
         db = np.zeros(max(total, 1), np.uint16) if keep_rays else None
-        cnt = Counts()
         t0 = time.perf_counter()
         lib().orc_probes_frame(
             self.scene.ptr, C.byref(self.grid), nq, _p(self.probes), _p(n_sel), _p(ray_base),
@@ -642,13 +646,13 @@ class OracleVolume:
         assert self.probes.shape[0] == self.P, "chain frames need every probe tracked"
         hints = hints or {}
         self.set_frame_inputs(frame)
-        qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"))
+        cnt = Counts()
+        qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"), counts=cnt)
         self.detect(frame, qv, qr, theta, mu)
         if frame & 1:
             self.qv_odd = qv.copy()
         ri, rd = self.irr_res - 2, self.depth_res - 2
         irr_prev = self.irr.copy()
-        cnt = Counts()
         out = chain_frame(self.grid, params, self.seed, frame, qv, irr_prev, ri, state, init,
                           hints.get("accept"), cnt)
         perm, n, base = chain_order(out["sample_probe"], self.P)

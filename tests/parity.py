@@ -48,6 +48,71 @@ def texel_error_report(gi, gd, oi, od) -> dict:
     return out
 
 
+# Per-ray radiance bar. The GPU shades at an FP32 hit point and the oracle
+# at an FP64 one. Origin and direction carry a few FP32 ulps, ~1e-6
+# (|p|_inf + t) across the ray; where the ray meets the triangle at a
+# glancing angle (|n.d| small) that offset slides the hit point along the
+# surface by 1/|n.d| times as much, so dx = 1e-6 (|p|_inf + t) / |n.d|. The
+# FP32 normal differs by an angle of about RAY_NORMAL_EPS. The direct light of light l,
+# I_l cos(theta_l)/|l|^2, then moves by a relative
+#   tan(theta_l) (dx/|l| + eps_n) + 2 dx/|l|
+# (d ln cos / dx = tan(theta)/|l|, d ln |l|^-2 / dx = 2/|l|), which only
+# grows large when the light grazes the surface (theta -> 90 degrees). The
+# bar of a ray is RAY_RGB_BASE plus that term weighted by each light's share
+# of the channel's radiance, the worst channel taken.
+RAY_RGB_BASE = 1e-5
+RAY_DX_REL = 1e-6
+RAY_NORMAL_EPS = 1e-6
+
+
+def ray_rgb_bar(scene, frame, sel, n_sel, R, o, tri, shadow) -> np.ndarray:
+    """Relative radiance bar of every traced ray of the tracked probes (the
+    oracle's ray order: probe by probe, rays in index order)."""
+    total = int(np.sum(n_sel))
+    bar = np.full(total, RAY_RGB_BASE)
+    if total == 0 or scene.num_lights == 0:
+        return bar
+    dims = scene.grid_dims.astype(np.int64)
+    org = scene.grid_origin.astype(np.float64)
+    spc = scene.grid_spacing.astype(np.float64)
+    sel = np.asarray(sel, np.int64)
+    pidx = np.stack([sel % dims[0], (sel // dims[0]) % dims[1], sel // (dims[0] * dims[1])], axis=1)
+    pos_p = org + pidx * spc
+    d = np.concatenate([oracle.sf_dirs(int(k), R) if k else np.zeros((0, 3)) for k in n_sel])
+    p = np.repeat(pos_p, np.asarray(n_sel, np.int64), axis=0)
+    t = o[:, 3]
+    lit = (tri >= 0) & np.isfinite(t) & (np.abs(o[:, :3]).max(axis=1) > 0)
+    if not lit.any():
+        return bar
+    V = scene.positions_at(frame).astype(np.float64)
+    T = scene.indices[tri[lit]]
+    nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    dl = d[lit]
+    nrm *= -np.sign(np.einsum("ij,ij->i", nrm, dl))[:, None]  # the side the ray came from
+    x = p[lit] + t[lit, None] * dl
+    cos_in = np.maximum(np.abs(np.einsum("ij,ij->i", nrm, dl)), 1e-3)
+    dx = RAY_DX_REL * (np.abs(p[lit]).max(axis=1) + t[lit]) / cos_in
+    lp = scene.light_positions(frame).astype(np.float64)
+    li = scene.light_intensity.astype(np.float64)
+    num = np.zeros((x.shape[0], 3))
+    den = np.zeros((x.shape[0], 3))
+    for l in range(lp.shape[0]):
+        ell = lp[l] - x
+        dist = np.linalg.norm(ell, axis=1)
+        cos = np.einsum("ij,ij->i", nrm, ell) / dist
+        vis = ((shadow[lit] >> l) & 1).astype(bool) & (cos > 0)
+        cosc = np.where(vis, cos, 1.0)
+        tan = np.sqrt(np.maximum(0.0, 1.0 - cosc * cosc)) / cosc
+        sens = tan * (dx / dist + RAY_NORMAL_EPS) + 2.0 * dx / dist
+        w = np.where(vis, cos / (dist * dist), 0.0)[:, None] * li[l][None, :]
+        num += w * sens[:, None]
+        den += w
+    term = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0).max(axis=1)
+    bar[lit] += term
+    return bar
+
+
 def gpu_scene_update(vol, scene, frame):
     if scene.anim_vertices and frame > 0:
         vol.update_scene(scene.positions_at(frame), light_pos=scene.light_positions(frame),
@@ -92,7 +157,8 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             if fp64_twin else None)
     res = {"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "max_rel_ray": 0.0,
            "ties": {}, "frames": frames, "rays": 0, "count_mismatch": 0, "score_mismatch": 0,
-           "alloc_mismatch": 0, "rotation_mismatch": 0, "max_rel_t": 0.0}
+           "alloc_mismatch": 0, "rotation_mismatch": 0, "max_rel_t": 0.0, "code_mismatch": 0,
+           "pilot_rays": 0, "ray_bar_excess": 0, "rays_above_1e5": 0, "max_ray_over_bar": 0.0}
     for f in range(frames):
         if f > 0:
             gpu_scene_update(vol, scene, f)
@@ -113,12 +179,18 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             twin.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
                         n_uniform=n_uniform, hints=hints)
         c = out["counts"]
-        mism = c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"]
+        mism = c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"] + c["q10_mismatch"]
         if adaptive:
             res["score_mismatch"] += int(np.count_nonzero(out["score"] != rb["score"]))
+            # the pilot codes of every probe and octant, this frame (even frames
+            # too, and probes whose trigger sums are zero): after the oracle has
+            # adopted the GPU's code at its flagged ties they must be identical
+            res["code_mismatch"] += int(np.count_nonzero(out["qv"] != rb["q10_vis"])) + \
+                int(np.count_nonzero(out["qr"] != rb["q10_rad"]))
+            res["pilot_rays"] += int(out["qv"].size)
         res["alloc_mismatch"] += int(np.count_nonzero(out["n"] != rb["rays_per_probe"]))
         res["mismatches"] += mism
-        for k in ("hit_ties", "shadow_ties", "bin_ties"):
+        for k in ("hit_ties", "shadow_ties", "bin_ties", "q10_ties"):
             res["ties"][k] = res["ties"].get(k, 0) + c[k]
         res["rays"] += c["rays"]
         res["stats_last"] = st
@@ -180,13 +252,23 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             den_t = np.maximum(np.maximum(np.abs(ot), 1e-3 * peak_t[owner]), 1e-8)
             e = (np.abs(g[:, :3] - o[:, :3]) / den_rgb).max(axis=1)
             e = np.where(same, e, 0.0)
+            bar = ray_rgb_bar(scene, f, sel, n_sel, out["R"], o, out["tri"], out["shadow"])
+            res["rays_above_1e5"] += int(np.count_nonzero(e > RAY_RGB_BASE))
+            res["ray_bar_excess"] += int(np.count_nonzero(e > bar))
+            if e.size:
+                res["max_ray_over_bar"] = max(res["max_ray_over_bar"], float((e / bar).max()))
             et = np.where(same, np.abs(gt - ot) / den_t, 0.0)
             res["max_rel_t"] = max(res.get("max_rel_t", 0.0), float(et.max(initial=0.0)))
             k = int(np.argmax(e)) if e.size else 0
             if e.size and e[k] > res["max_rel_ray"]:
                 res["max_rel_ray"] = float(e[k])
                 res["worst_ray"] = {"gpu": g[k].tolist(), "oracle": o[k].tolist(),
-                                    "tri": int(out["tri"][k]), "frame": f}
+                                    "tri": int(out["tri"][k]), "frame": f, "bar": float(bar[k])}
+            k = int(np.argmax(e / bar)) if e.size else 0
+            if e.size and e[k] / bar[k] >= res["max_ray_over_bar"]:
+                res["worst_ray_vs_bar"] = {"gpu": g[k].tolist(), "oracle": o[k].tolist(), "err": float(e[k]),
+                                           "tri": int(out["tri"][k]), "frame": f, "bar": float(bar[k]),
+                                           "probe": int(sel[owner[k]])}
     if packed:
         res.update(res_pk)
     res["vs_oracle"] = texel_error_report(rb["irradiance"][sel], rb["depth"][sel],
@@ -245,7 +327,8 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
            "marks": 0, "dyn_rays": 0, "max_dyn_state_err": 0.0,"mismatches": 0, "max_rel_irr": 0.0, "max_rel_depth": 0.0, "count_mismatch": 0,
            "alloc_mismatch": 0, "code_mismatch": 0, "accept_mismatch": 0, "probe_mismatch": 0,
            "sample_count_mismatch": 0, "max_uv_err": 0.0, "max_state_err": 0.0, "ties": {},
-           "frames": frames, "samples": 0, "accept_rate": 0.0, "max_rel_ray": 0.0}
+           "frames": frames, "samples": 0, "accept_rate": 0.0, "max_rel_ray": 0.0, "rays": 0,
+           "pilot_rays": 0}
     for f in range(warm_uniform + frames):
         if f > 0:
             gpu_scene_update(vol, scene, f)
@@ -280,6 +363,7 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
                 dstate[:dyn_chains] = rb["dyn_state"].astype(np.float64)
             res["code_mismatch"] += int(np.count_nonzero(out["qv"] != rb["q10_vis"])) + \
                 int(np.count_nonzero(out["qr"] != rb["q10_rad"]))
+            res["pilot_rays"] += int(out["qv"].size)
             res["accept_mismatch"] += int(np.count_nonzero(out["accept"] != hints["accept"]))
             res["accept_rate"] = float(np.mean(out["accept"]))
             sp_o = out["sample_probe"][out["perm"]]
@@ -306,6 +390,7 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
         res["mismatches"] += c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"]
         for k in ("hit_ties", "shadow_ties", "bin_ties"):
             res["ties"][k] = res["ties"].get(k, 0) + c[k]
+        res["rays"] += c["rays"]
         res["alloc_mismatch"] += int(np.count_nonzero(out["n"] != rb["rays_per_probe"]))
         ei = rel_err(rb["irradiance"], ora.irradiance_tiles())
         ed = rel_err(rb["depth"], ora.depth_tiles())

@@ -11,24 +11,44 @@ from tests.parity import run_lockstep
 pytestmark = pytest.mark.gpu
 
 
-# Per-ray radiance: GPU (FP32 direction) and oracle (FP64 direction) shade
-# points about 1e-7 t apart; under grazing light (cos ~ 1e-3) the radiance
-# moves by ~1e-4 relative over that distance, so the per-ray bar is 1e-3
-# (per-probe floor). Texels, which the spec bar is about, stay at 1e-4.
-RAY_RGB_TOL = 1e-3
+# Per-ray radiance: 1e-5 relative plus a grazing term derived from the
+# FP32/FP64 hit-point and normal difference (tests/parity.py, ray_rgb_bar);
+# every ray must sit under its own bar. Hit distances: 1e-4 relative.
 RAY_T_TOL = 1e-4
+
+# Caps on the share of decisions the oracle flags as ties (and adopts from
+# the GPU): a systematic GPU error at triangle edges, shadow boundaries,
+# texel edges or code edges would show up as a tie rate far above these.
+HIT_TIE_CAP = 5e-3      # of all traced rays (probe + pilot)
+SHADOW_TIE_CAP = 5e-3
+BIN_TIE_CAP = 1e-3
+Q10_TIE_CAP = 1e-2      # of pilot codes (two per pilot)
+
+
+def _assert_ties(res, hit=HIT_TIE_CAP, shadow=SHADOW_TIE_CAP, bins=BIN_TIE_CAP, q10=Q10_TIE_CAP):
+    t, n = res["ties"], max(res["rays"], 1)
+    assert t.get("hit_ties", 0) <= hit * n, res
+    assert t.get("shadow_ties", 0) <= shadow * n, res
+    assert t.get("bin_ties", 0) <= bins * n, res
+    assert t.get("q10_ties", 0) <= q10 * max(2 * res.get("pilot_rays", 0), 1), res
+
+
+def _assert_rays(res):
+    assert res["ray_bar_excess"] == 0, res
+    assert res["max_rel_t"] <= RAY_T_TOL, res
 
 
 def _assert_parity(res, tol=1e-4):
     assert res["rotation_mismatch"] == 0, res
     assert res["mismatches"] == 0, res
+    assert res["code_mismatch"] == 0, res
     assert res["alloc_mismatch"] == 0, res
     assert res["score_mismatch"] == 0, res
     assert res["count_mismatch"] == 0, res
     assert res["max_rel_irr"] <= tol, res
     assert res["max_rel_depth"] <= tol, res
-    assert res["max_rel_ray"] <= RAY_RGB_TOL, res
-    assert res["max_rel_t"] <= RAY_T_TOL, res
+    _assert_rays(res)
+    _assert_ties(res)
 
 
 def test_cornell_uniform_8_frames():
@@ -112,7 +132,9 @@ def test_box_field_fp16_storage_report():
     assert res["mismatches"] == 0 and res["count_mismatch"] == 0, res
     assert res["alloc_mismatch"] == 0 and res["score_mismatch"] == 0, res
     assert res["max_rel_irr"] <= 2e-3 and res["max_rel_depth"] <= 2e-3, res
-    assert res["max_rel_ray"] <= RAY_RGB_TOL and res["max_rel_t"] <= RAY_T_TOL, res
+    assert res["code_mismatch"] == 0, res
+    _assert_rays(res)
+    _assert_ties(res)
 
 
 def test_fp16_storage_against_fp16_emulating_oracle():
@@ -130,7 +152,9 @@ def _assert_packed(res):
     assert res["alloc_mismatch"] == 0 and res["score_mismatch"] == 0, res
     assert res["count_mismatch"] == 0, res
     assert res["packed_word_mismatch"] == 0 and res["packed_border_mismatch"] == 0, res
-    assert res["max_rel_ray"] <= RAY_RGB_TOL and res["max_rel_t"] <= RAY_T_TOL, res
+    assert res["code_mismatch"] == 0, res
+    _assert_rays(res)
+    _assert_ties(res)
 
 
 def test_packed_words_cornell_uniform():
@@ -158,7 +182,8 @@ def test_packed_words_box_field_adaptive():
 
 # ---- static Metropolis chains (ADGI_MODE_CHAIN)
 
-def _assert_chain_parity(res, tol=1e-4):
+def _assert_chain_parity(res, tol=1e-4, hit_ties=HIT_TIE_CAP, shadow_ties=SHADOW_TIE_CAP):
+    _assert_ties(res, hit=hit_ties, shadow=shadow_ties)
     assert res["mismatches"] == 0, res
     assert res["code_mismatch"] == 0 and res["accept_mismatch"] == 0, res
     assert res["sample_count_mismatch"] == 0 and res["probe_mismatch"] == 0, res
@@ -207,8 +232,8 @@ def test_chains_box_field_ragged_lockstep():
     _assert_chain_parity(res, tol=2e-3)
 
 
-def _assert_dyn_parity(res, tol=1e-4):
-    _assert_chain_parity(res, tol)
+def _assert_dyn_parity(res, tol=1e-4, **caps):
+    _assert_chain_parity(res, tol, **caps)
     assert res["F_mismatch"] == 0 and res["mark_mismatch"] == 0, res
     assert res["dyn_accept_mismatch"] == 0 and res["dyn_ray_mismatch"] == 0, res
     assert res["max_dyn_state_err"] <= 1e-4, res
@@ -228,7 +253,12 @@ def test_dynamic_chains_cornell_lockstep():
     print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
     assert res["marks"] > 0 and res["dyn_rays"] > 0, res
     _report("dynamic_chains_cornell", res)
-    _assert_dyn_parity(res)
+    # Texel-centre rays from probes on a lattice aligned with the room meet
+    # its walls on the diagonals that split each wall quad into two
+    # triangles (and shadow rays meet the boxes' edges): both triangles of
+    # such a tie lie in one plane with one albedo, so either decision gives
+    # the same radiance. Measured 7.7% hit and 1.7% shadow ties.
+    _assert_dyn_parity(res, hit_ties=0.1, shadow_ties=0.03)
 
 
 def test_dynamic_chains_box_field_refit_lockstep():
@@ -255,7 +285,7 @@ def test_gather_cornell_uniform():
 
 
 # A gather texel mixes every ray of its probe, so the per-ray FP32 / FP64
-# shading differences (RAY_RGB_TOL, relative to the probe's brightest ray)
+# shading differences (the per-ray bar of ray_rgb_bar, up to 1e-4 under grazing light)
 # reach dark texels through the cosine weights instead of staying in the
 # texel of their own direction; measured 1.2e-4 on the tunnel. The bar for
 # the gather variant is 2e-4.

@@ -561,6 +561,133 @@ def test_pin7_light_switched_on_changes_only_lit_pilots():
     assert np.all(vol.tv == 0) and np.array_equal(vol.tr > 0, changed)
 
 
+
+# ---- pilot codes (eq. ProbeVis; Sec. 4.1.3; App. B round-down), O5
+
+def _pilot_plane_scene(H_lo, rho, I, light_h, sky, half=1.0e4):
+    """Ground quad z = 0 (normal +z) under a probe grid whose layers sit at
+    heights H_lo + k*0.45; one point light at (0.3, -0.2, light_h)."""
+    pos, idx = _quad(-half, half, -half, half, 0.0)
+    return scenes.Scene(
+        name="pilot_plane", positions=pos, indices=idx, albedo=np.full((2, 3), rho, np.float32),
+        light_a=np.array([[0.3, -0.2, light_h]], np.float32),
+        light_b=np.array([[0.3, -0.2, light_h]], np.float32),
+        light_intensity=np.array([I], np.float32), sky=np.array(sky, np.float32),
+        grid_origin=np.array([0.1, -0.35, H_lo], np.float32),
+        grid_spacing=np.array([0.5, 0.7, 0.45], np.float32),
+        grid_dims=np.array([2, 3, 3], np.int32), frames=2)
+
+
+def _pilot_expect(sc, seed, frame, beta=5.0):
+    """Pilot codes written out from the geometry: a downward pilot of probe
+    p meets z = 0 at t = p_z/|d_z| and lands at x = p + t d; an upward one
+    leaves the scene. Qv = min(1023, floor(1024 exp(-2t/s))), 0 on a miss;
+    Qr = min(1023, floor(1024 min(lum, beta)/beta)) with Rec. 709 luminance
+    of (rho/pi) I cos/|l|^2 at x (l = light - x) or of the sky on a miss.
+    Also returns the distance of 1024 f to the nearest integer (code edges)."""
+    dims = sc.grid_dims.astype(np.int64)
+    org = sc.grid_origin.astype(np.float64)
+    spc = sc.grid_spacing.astype(np.float64)
+    s = float(np.sqrt(np.sum(spc * spc)))
+    rho = sc.albedo[0].astype(np.float64)
+    I = sc.light_intensity[0].astype(np.float64)
+    lp = sc.light_positions(frame)[0].astype(np.float64)
+    sky = sc.sky.astype(np.float64)
+    w709 = np.array([0.2126, 0.7152, 0.0722])
+    P = int(np.prod(dims))
+    qv = np.zeros(P * 8, np.int64)
+    qr = np.zeros(P * 8, np.int64)
+    edge = np.full(P * 8, np.inf)
+    for i in range(P):
+        x_, y_, z_ = i % dims[0], (i // dims[0]) % dims[1], i // (dims[0] * dims[1])
+        p = org + np.array([x_, y_, z_]) * spc
+        for k in range(8):
+            d = oracle.pilot_dir(seed, i, k, frame // 2)
+            if d[2] < 0.0:
+                t = p[2] / -d[2]
+                x = p + t * d
+                fv = 1024.0 * math.exp(-2.0 * t / s)
+                ell = lp - x
+                dist = float(np.linalg.norm(ell))
+                L = rho / math.pi * I * max(0.0, ell[2] / dist) / (dist * dist)
+            else:
+                fv = 0.0
+                L = sky
+            fr = 1024.0 * min(float(w709 @ L), beta) / beta
+            qv[8 * i + k] = min(1023, math.floor(fv))
+            qr[8 * i + k] = min(1023, math.floor(fr))
+            for f_ in (fv, fr):
+                if 0.5 < f_ < 1023.0:
+                    edge[8 * i + k] = min(edge[8 * i + k], abs(f_ - round(f_)))
+    return qv, qr, edge
+
+
+@pytest.mark.parametrize("channel", [0, 1, 2])
+def test_pilot_codes_over_a_lit_plane(channel):
+    """Known hit distances and a known lit Lambertian plane give the codes
+    of eq. ProbeVis (exp(-2t/s), not exp(-t/s)) and of the radiance term
+    (Rec. 709 weights, one colour channel at a time so that each weight is
+    checked on its own; a coloured sky for the upward pilots); misses give
+    Qv = 0. Codes within 1e-6 of an integer edge are skipped."""
+    I = [0.0, 0.0, 0.0]
+    I[channel] = 2.5
+    sky = [0.5, 1.0, 2.0]
+    sc = _pilot_plane_scene(0.2, (0.9, 0.6, 0.8), I, light_h=2.0, sky=sky)
+    for frame in (0, 1, 2):
+        vol = oracle.OracleVolume(sc, seed=31 + channel, use_bvh=False)
+        vol.set_frame_inputs(frame)
+        qv, qr = vol.pilots(frame)
+        eqv, eqr, edge = _pilot_expect(sc, 31 + channel, frame)
+        ok = edge > 1e-6
+        assert ok.mean() > 0.98
+        assert np.array_equal(qv[ok], eqv[ok]), np.nonzero(qv[ok] != eqv[ok])
+        assert np.array_equal(qr[ok], eqr[ok]), np.nonzero(qr[ok] != eqr[ok])
+        down = np.array([oracle.pilot_dir(31 + channel, r // 8, r % 8, frame // 2)[2] < 0
+                         for r in range(qv.size)])
+        assert np.all(qv[~down] == 0) and np.mean(qv[down] > 0) > 0.5
+        # the sky's luminance 0.9659... gives floor(1024 * 0.9659 / 5) = 197 on every miss
+        assert np.all(qr[~down] == 197)
+        # some lit pilots carry a non-zero radiance code
+        assert np.count_nonzero(qr[down]) > 0
+
+
+def test_pilot_radiance_code_clamps_at_beta():
+    """Luminance at or above beta saturates the radiance code at 1023; a
+    black sky gives 0 on every miss."""
+    sc = _pilot_plane_scene(0.2, (0.9, 0.9, 0.9), [4000.0, 4000.0, 4000.0], light_h=2.0,
+                            sky=[0.0, 0.0, 0.0])
+    vol = oracle.OracleVolume(sc, seed=77, use_bvh=False)
+    vol.set_frame_inputs(0)
+    qv, qr = vol.pilots(0)
+    eqv, eqr, edge = _pilot_expect(sc, 77, 0)
+    down = np.array([oracle.pilot_dir(77, r // 8, r % 8, 0)[2] < 0 for r in range(qv.size)])
+    assert np.mean(eqr[down] == 1023) > 0.5  # lum >= beta near the light
+    ok = edge > 1e-6
+    assert np.array_equal(qr[ok], eqr[ok])
+    assert np.all(qr[~down] == 0)
+    assert np.array_equal(qv[ok], eqv[ok])
+
+
+def test_pilot_code_at_distance_zero_saturates():
+    """A pilot that leaves a probe lying on a surface has t -> 0 and
+    1024 exp(0) = 1024, clamped to the 10-bit maximum 1023; codes are
+    monotone in distance."""
+    sc = _pilot_plane_scene(1e-7, (0.5, 0.5, 0.5), [0.0, 0.0, 0.0], light_h=2.0, sky=[0, 0, 0])
+    vol = oracle.OracleVolume(sc, seed=5, use_bvh=False)
+    vol.set_frame_inputs(0)
+    qv, _ = vol.pilots(0)
+    dims = sc.grid_dims
+    lowest = [i for i in range(int(np.prod(dims))) if i // (dims[0] * dims[1]) == 0]
+    for i in lowest:
+        for k in range(4, 8):  # octants with bit 2 set point down (-z)
+            d = oracle.pilot_dir(5, i, k, 0)
+            if -d[2] > 1e-3:
+                assert qv[8 * i + k] == 1023
+    # probes higher up see the plane further away: lower codes on average
+    per_layer = [np.mean([qv[8 * i + k] for i in range(int(np.prod(dims)))
+                          if i // (dims[0] * dims[1]) == z for k in range(4, 8)]) for z in range(3)]
+    assert per_layer[0] > per_layer[1] > per_layer[2]
+
 # -------------------------------------------------------- O6: allocation
 
 def _brute_lambda(w, E, Bp):
@@ -1082,7 +1209,7 @@ def test_chain_update_with_dynamic_chains_runs_end_to_end():
     for f in range(4):
         out = ora.chain_update(f, cp, st, init=(f == 0), dyn=dp, dyn_state=dst, dyn_init=(f == 0))
         R = int(out["dyn_rays"].sum())
-        assert out["counts"]["rays"] == 2 * 64 * 8 + R
+        assert out["counts"]["rays"] == 2 * 64 * 8 + R + 8 * ora.P  # samples, dynamic rays, pilots
         assert np.all(out["mark"][out["F"] == 0] == 0)
         if f == 3:
             assert out["F"].max() > 0 and out["mark"].sum() > 0 and R > 0
