@@ -12,6 +12,7 @@ blend. ``value`` is probe (primary) rays per second over the timed steps.
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import hashlib
 import json
 import math
@@ -190,6 +191,50 @@ def stage_times(vol, sc, adgi, frame0, frames, **p):
         f += 1
     vol.set_tuning(use_graph=tun["use_graph"])
     return [a / frames for a in acc], f
+
+
+def run_config(adgi, torch, sc, cfg, storage_name, tuning, steps, warmup, latency_frames, uniform=()):
+    """Adaptive frames of one workload (and uniform baselines of the given
+    rays per probe on fresh volumes): throughput, latency, stage times and
+    the blend's HBM roofline. tuning None: autotuned for this scene."""
+    storage = {"fp32": adgi.ADGI_FP32, "fp16": adgi.ADGI_FP16, "packed": adgi.ADGI_PACKED}[storage_name]
+    P = sc.num_probes
+    max_rays = max([cfg["budget"]] + [P * n for n in uniform])
+    ad = dict(adaptive=True, budget=cfg["budget"], n_min=cfg["n_min"], n_max=cfg["n_max"])
+    vol = adgi.volume_for_scene(sc, storage=storage, max_rays=max_rays, seed=11)
+    if tuning is None:
+        tuning = vol.autotune(0, **ad)
+    else:
+        vol.set_tuning(**tuning)
+    r = run_mode(vol, sc, adgi, torch, 0, steps, warmup, latency_frames, **ad)
+    stages, _ = stage_times(vol, sc, adgi, r["frames_end"], 5, **ad)
+    vol.destroy_volume()
+    R = r["rays_per_frame"]
+    bbytes = blend_bytes(P, R, storage_name)
+    gbs = bbytes / (stages[5] * 1e-3) / 1e9
+    out = {"workload": f"{sc.name}: {sc.num_triangles} triangles, {P} probes "
+                       f"{tuple(int(x) for x in sc.grid_dims)}, adaptive B={cfg['budget']} "
+                       f"n in [{cfg['n_min']},{cfg['n_max']}], texels {storage_name}",
+           "tuning": tuning,
+           "adaptive": {"rays_per_s": R * steps / r["seconds"], "ms_per_step": r["seconds"] / steps * 1e3,
+                        "probe_updates_per_s": P * steps / r["seconds"],
+                        "p50_ms": pct(r["host_ms"], 50), "p99_ms": pct(r["host_ms"], 99),
+                        "gpu_p50_ms": pct(r["gpu_ms"], 50), "gpu_p99_ms": pct(r["gpu_ms"], 99),
+                        "stage_ms": dict(zip(["setup", "pilot_trace", "detect", "allocate", "probe_trace",
+                                              "blend", "probe_trace_hit", "probe_trace_shade"], stages))},
+           "roofline_blend": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": gbs / HBM_PEAK_GBS, "ms": stages[5], "algorithmic_bytes": bbytes,
+                              "target_ms_at_half_peak": bbytes / (0.5 * HBM_PEAK_GBS * 1e9) * 1e3}}
+    for n in uniform:
+        v2 = adgi.volume_for_scene(sc, storage=storage, max_rays=max_rays, seed=11)
+        v2.set_tuning(**tuning)
+        ru = run_mode(v2, sc, adgi, torch, 0, steps, warmup, latency_frames, adaptive=False, n_uniform=n)
+        v2.destroy_volume()
+        out[f"uniform_{n}"] = {"rays_per_probe": n, "rays_per_s": P * n * steps / ru["seconds"],
+                               "ms_per_step": ru["seconds"] / steps * 1e3,
+                               "p50_ms": pct(ru["host_ms"], 50), "p99_ms": pct(ru["host_ms"], 99),
+                               "gpu_p50_ms": pct(ru["gpu_ms"], 50), "gpu_p99_ms": pct(ru["gpu_ms"], 99)}
+    return out
 
 
 # Chain frames on the same scene: the paper's 4096 static chains (about 64
@@ -459,27 +504,71 @@ def cpu_small_workloads(oracle):
 
 def run_serving_child(duration_s):
     """The serving mix in a process of its own: a failure there is reported
-    in its place ({"error": ...}) and does not take the main measurement
-    with it."""
+    in its place ({"error": ...}, with the end of the child's stderr) and does
+    not take the main measurement with it; main() also lists it under the
+    line's top-level "errors"."""
     import subprocess
     try:
         r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
                             "--serve-seconds", str(duration_s)], capture_output=True, text=True,
-                           timeout=120 + 10 * duration_s)
+                           timeout=240 + 40 * duration_s)
     except subprocess.TimeoutExpired:
         return {"error": "serving process timed out"}
-    sys.stderr.write(r.stderr[-2000:])
+    sys.stderr.write(r.stderr[-3000:])
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
     if r.returncode != 0 or not lines:
-        return {"error": f"serving process exited with status {r.returncode}"}
+        return {"error": f"serving process exited with status {r.returncode}",
+                "stderr_tail": r.stderr[-1500:]}
     return json.loads(lines[-1])
 
 
-def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=8):
+def serve_phase(srv, sids, streams, scale, duration_s, nframe):
+    """One serving phase: every stream's Poisson arrivals with its rate times
+    ``scale`` (the seeded arrival times divided by scale) for duration_s, then
+    a drain. Latencies, rays and device busy time are this phase's share of
+    the server's running totals."""
+    import numpy as np
+    lat0 = len(srv.latencies())
+    st0 = srv.stats()
+    events = sorted((float(t) / scale, k) for k, st in enumerate(streams) for t in st.arrivals
+                    if float(t) / scale < duration_s)
+    start = srv.now_ns() + 20_000_000
+    for t, k in events:
+        target = start + int(t * 1e9)
+        while srv.now_ns() < target:
+            srv.progress()
+        srv.submit(sids[k], streams[k].scene.light_positions(nframe[k] % streams[k].scene.frames),
+                   arrival_ns=target)
+        nframe[k] += 1
+        srv.progress()
+    srv.drain()
+    span = (srv.now_ns() - start) * 1e-9
+    st1 = srv.stats()
+    lat = srv.latencies()[lat0:]
+    rays = st1["primary_rays"] - st0["primary_rays"]
+    offered = sum(s.rate_hz * scale * s.budget for s in streams)
+    return {"rate_scale": scale, "offered_rays_per_s": offered, "requests": len(events),
+            "completed": int(st1["completed"] - st0["completed"]),
+            "rays_per_s": rays / max(span, 1e-9),
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_ms": float(np.mean(lat)) if len(lat) else None,
+            "max_ms": float(np.max(lat)) if len(lat) else None,
+            "span_s": span,
+            "device_overlap": (st1["device_busy_ms"] - st0["device_busy_ms"]) * 1e-3 / max(span, 1e-9),
+            "admissions": int(st1["admissions"] - st0["admissions"]),
+            "evictions": int(st1["evictions"] - st0["evictions"])}
+
+
+def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=8, sweep=(0.7, 0.5)):
     """Serving mix: 32 streams (box fields of 10k-500k triangles, 512-32768
     probes, B = 128 rays per probe), Poisson arrivals at 30-120 Hz each, for
     duration_s of wall time, under an HBM admission budget of budget_frac of
-    the streams' summed device footprints."""
+    the streams' summed device footprints. First the mix as drawn (it offers
+    more rays than the GPU completes: an overload, whose latencies measure
+    queue growth), then the same arrival processes slowed so that they offer
+    the given fractions of the throughput the overload phase completed.
+    device_overlap is the mean number of frames on the device at once."""
     import scenes
     streams = scenes.serving_streams(duration_s=duration_s)
     srv = adgi.Server(hbm_budget_bytes=1 << 40, max_inflight=max_inflight)
@@ -491,29 +580,22 @@ def run_serving(adgi, duration_s=10.0, budget_frac=0.6, max_inflight=8):
     srv.set_budget(budget)
     print(f"[bench] serving: {len(sids)} streams added in {setup_s:.1f}s, footprints "
           f"{sum(foot) / 2**30:.2f} GiB, budget {budget / 2**30:.2f} GiB", file=sys.stderr, flush=True)
-    events = sorted((float(t), k) for k, st in enumerate(streams) for t in st.arrivals)
     nframe = [0] * len(streams)
-    start = srv.now_ns() + 20_000_000
-    for t, k in events:
-        target = start + int(t * 1e9)
-        while srv.now_ns() < target:
-            srv.progress()
-        srv.submit(sids[k], streams[k].scene.light_positions(nframe[k]), arrival_ns=target)
-        nframe[k] += 1
-        srv.progress()
-    srv.drain()
-    st = srv.stats()
-    offered = sum(s.rate_hz * s.budget for s in streams)
-    out = {"streams": len(sids), "duration_s": duration_s, "requests": st["submitted"],
-           "completed": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-           "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
-           "rays_per_s": st["primary_rays"] / max(st["span_s"], 1e-9),
-           "offered_rays_per_s": offered, "admissions": st["admissions"],
-           "evictions": st["evictions"], "admit_ms_total": st["admit_ms"],
-           "evict_ms_total": st["evict_ms"], "hbm_budget_bytes": budget,
-           "sum_footprint_bytes": sum(foot), "peak_resident_bytes": st["peak_resident_bytes"],
-           "max_inflight": max_inflight, "setup_s": setup_s,
-           "triangles": [int(s.scene.num_triangles) for s in streams],
+    over = serve_phase(srv, sids, streams, 1.0, duration_s, nframe)
+    print(f"[bench] serving overload phase: {over['rays_per_s'] / 1e9:.2f} G rays/s of "
+          f"{over['offered_rays_per_s'] / 1e9:.2f} offered", file=sys.stderr, flush=True)
+    phases = []
+    for frac in sweep:
+        scale = min(1.0, frac * over["rays_per_s"] / over["offered_rays_per_s"])
+        ph = serve_phase(srv, sids, streams, scale, duration_s, nframe)
+        ph["fraction_of_capacity"] = frac
+        phases.append(ph)
+        print(f"[bench] serving at {frac:.2f} of capacity: p50 {ph['p50_ms']:.1f} ms, "
+              f"p99 {ph['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    out = {"streams": len(sids), "duration_s": duration_s, "overload": over, "below_capacity": phases,
+           "hbm_budget_bytes": budget, "sum_footprint_bytes": sum(foot),
+           "peak_resident_bytes": srv.stats()["peak_resident_bytes"], "max_inflight": max_inflight,
+           "setup_s": setup_s, "triangles": [int(s.scene.num_triangles) for s in streams],
            "probes": [int(s.scene.num_probes) for s in streams]}
     srv.destroy()
     return out
@@ -532,6 +614,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="JSON launch tuning to use instead of the autotuner")
     ap.add_argument("--skip-uniform", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the FP16-storage box field and the tunnel (adaptive vs uniform)")
     ap.add_argument("--no-serve", action="store_true", help="skip the 32-stream serving mix")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-only", action="store_true",
@@ -543,6 +627,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    faulthandler.enable()  # a crash prints the Python stack of every thread
+    errors = []
     if args.serve_only:
         import torch
         import paper_2301_05125_amd as adgi
@@ -679,6 +765,22 @@ def main():
         "scene_build_s": build_s,
     }
     vol.destroy_volume()
+    if not args.no_configs:
+        # the FP16-storage variant of the same scene (texels stored as binary16,
+        # FP32 arithmetic); its per-texel error against the FP64 oracle is the
+        # parity suite's (box-field FP16 storage report)
+        out["fp16_storage"] = run_config(adgi, torch, sc, cfg, "fp16", tuning, args.steps, args.warmup,
+                                         min(args.latency_frames, 30))
+        print("[bench] fp16 storage done", file=sys.stderr, flush=True)
+        # the tunnel: adaptive B = 2^19 against uniform 256 (equal budget) and
+        # 264 (equal traced rays, the budget plus the pilots) rays per probe
+        tn = scenes.tunnel()
+        tn.frames = 61
+        tcfg = WORKLOADS["tunnel"]
+        out["tunnel"] = run_config(adgi, torch, tn, tcfg, "fp32", None, args.steps, args.warmup,
+                                   min(args.latency_frames, 30),
+                                   uniform=(tcfg["uniform_equal_b"], tcfg["uniform_equal_rays"]))
+        print("[bench] tunnel done", file=sys.stderr, flush=True)
     # DDGI's cosine-weighted gather in place of the per-sample update, same frames
     if not args.skip_uniform:
         vg = adgi.volume_for_scene(sc, storage=storage if args.storage != "packed" else adgi.ADGI_FP32,
@@ -716,10 +818,15 @@ def main():
             print(f"[bench] chains {name} done", file=sys.stderr, flush=True)
     if not args.no_serve:
         out["serving"] = run_serving_child(args.serve_seconds)
+        if "error" in out["serving"]:
+            errors.append("serving: " + out["serving"]["error"])
         print(f"[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, cfg["budget"], cfg["n_min"], cfg["n_max"])
+    out["errors"] = errors
+    if errors:
+        print("[bench] ERRORS: " + "; ".join(errors), file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

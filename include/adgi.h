@@ -358,6 +358,10 @@ typedef struct {
                                  that many lanes per chain, 2..5 steps per round
                                  (Brockwell 2006), the same chains bit for bit;
                                  0 = chosen from the chain count                  */
+  int32_t ray_order;          /* probe rays: 1 = each wave traces a compact patch
+                                 of directions (a probe's spherical Fibonacci
+                                 indices cut into bands, each band taken in
+                                 azimuth order); 0 = index order                  */
 } adgi_tuning;
 
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);
@@ -432,6 +436,11 @@ typedef struct {
   double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival -> frame seen done (event) */
   double span_s;              /* first arrival -> last completion                 */
   double admit_ms, evict_ms;  /* host time spent admitting and evicting          */
+  double device_busy_ms;      /* sum over completed frames of their device span
+                                 (an event on the lane before the frame's scene
+                                 update to one after its blend): divided by the
+                                 wall time it is the mean number of frames on
+                                 the device at once                              */
 } adgi_server_stats;
 
 int64_t adgi_server_now_ns(void);  /* steady clock used for arrival stamps        */

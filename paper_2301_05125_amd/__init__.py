@@ -128,7 +128,7 @@ class ServerStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "admissions", "evictions",
                                          "primary_rays", "resident_bytes", "peak_resident_bytes")] + \
                [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "span_s",
-                                          "admit_ms", "evict_ms")]
+                                          "admit_ms", "evict_ms", "device_busy_ms")]
 
     def as_dict(self):
         return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n)))
@@ -139,7 +139,7 @@ class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("persistent", C.c_int32), ("trace_block", C.c_int32),
                 ("trace_waves_per_cu", C.c_int32), ("blend_chunk", C.c_int32),
                 ("blend_blocks_per_cu", C.c_int32), ("bvh_width", C.c_int32),
-                ("chain_lanes", C.c_int32)]
+                ("chain_lanes", C.c_int32), ("ray_order", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

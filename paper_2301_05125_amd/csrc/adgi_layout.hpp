@@ -167,6 +167,8 @@ struct VolumeView {
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
+  uint32_t* ray_bins;         // [max_rays] probe rays: interior irradiance texel
+                              // | interior depth texel << 16 of the direction
   // lit hits waiting for their shadow rays (the pilot and probe passes of a
   // frame use them one after the other), by ray index: hit point and t, unit
   // normal and original triangle index, and a word (pending shadow rays << 8
@@ -175,6 +177,11 @@ struct VolumeView {
   float4* hit_pos;            // [hit_cap]
   float4* hit_nrm;            // [hit_cap]
   uint32_t* hit_vis;          // [hit_cap]
+  uint32_t* hit_dst;          // [hit_cap] probe rays: index of the ray a slot traces
+  // coherent order of a probe's rays (null: natural order): slot k of a probe
+  // with n <= ray_perm_max rays traces ray ray_perm[n (n - 1) / 2 + k]
+  const uint16_t* ray_perm;
+  int32_t ray_perm_max;
   uint16_t* pairs;            // [ceil(hit_cap/64)][kPairsPerBatch]
   uint32_t* pair_cnt;         // [ceil(hit_cap/64)]
   uint32_t* pair_off;         // [ceil(hit_cap/64) + 1] exclusive scan of pair_cnt

@@ -150,10 +150,6 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
       L.bins[chunk + j] = (uint16_t)(nI + bD);
       atomicAdd(&L.hist[bI], 1u);
       atomicAdd(&L.hist[nI + bD], 1u);
-      if (fp.debug) {
-        v.dbg_ibin[off + c0 + j] = (uint16_t)bI;
-        v.dbg_dbin[off + c0 + j] = (uint16_t)bD;
-      }
     }
     __syncthreads();
     // exclusive scan of the histogram over the combined texel space
@@ -243,14 +239,18 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
 
 // ---------------------------------------------------------------------------
 // Wave-per-probe variant for the common tile sizes. One 64-lane wave owns one
-// probe: interior texel k lives in the registers of lane k % 64 (slot k / 64)
-// for the whole frame. Rays are taken 64 at a time, one per lane; each lane
-// ORs its lane bit into a 64-bit LDS mask of the irradiance texel and of the
-// depth texel its direction falls in, and every owner then walks the set bits
-// of its texels' masks from the lowest: that is ascending ray order, so no sort
-// is needed and all synchronisation stays within the wave. The next 64 records
-// are loaded while the current ones are applied. Waves take probes in the
-// allocation's order (most rays first) so the longest blends start first.
+// probe and keeps its interior texels, depth moments and counts in LDS for
+// the whole frame (loaded row by row, coalesced). Rays are taken 64 at a
+// time, one per lane, with the texel indices the trace stored for each ray.
+// Each lane ORs its lane bit into a 64-bit LDS mask of its irradiance texel
+// and of its depth texel; the set bits below a lane give its rank among the
+// chunk's samples of the same texel. Round r then applies, in every lane of
+// rank r at once, that lane's sample to its texel: a texel takes its samples
+// in ascending ray order and no two lanes touch one texel in a round, so the
+// moving average is the same sequence of FP32 operations as one sample at a
+// time. The next 64 records are loaded while the current ones are applied.
+// Waves take probes in the allocation's order (most rays first) so the
+// longest blends start first.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -262,12 +262,24 @@ struct WaveTile {
   static constexpr int NI = RI * RI, ND = RD * RD, NT = NI + ND;
   static constexpr int SI = (NI + 63) / 64, SD = (ND + 63) / 64;
   static constexpr int GI = RI + 2, GD = RD + 2;
+  // the per-sample wave's LDS: the interior texels as planes, irradiance
+  // r[NI] g[NI] b[NI] N[NI] and depth tau[ND] tau^2[ND] N[ND] (N the sample
+  // count, one word each), so lanes that update different texels of one map
+  // touch consecutive words (distinct banks) instead of strided records
+  static constexpr size_t kStI = 0, kStD = 16 * (size_t)NI;
+  static constexpr size_t kRankBytes = kStD + 12 * (size_t)ND;
+  // bits of an interior texel index
+  static constexpr int BI = NI <= 64 ? 6 : NI <= 128 ? 7 : NI <= 256 ? 8 : 9;
+  static constexpr int BD = ND <= 64 ? 6 : ND <= 128 ? 7 : ND <= 256 ? 8 : 9;
+  // the other wave kernels' LDS (packed, gather): a chunk of records and the masks,
+  // or the staged interior
   static constexpr size_t kChunkBytes = 64 * 16 + 8 * (size_t)NT;
   static constexpr size_t kStageBytes = 4 * (3 * (size_t)NI + 2 * (size_t)ND) + NT;
-  static constexpr size_t kWaveBytes =
-      ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
+  static constexpr size_t kOldBytes = ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
+  static constexpr size_t kWaveBytes = kOldBytes > kRankBytes ? kOldBytes : kRankBytes;
   static constexpr size_t kTabBytes = (2 * (GI * GI * 3 + GD * GD * 2) + 15) & ~(size_t)15;
   static constexpr size_t kBlockBytes = 4 * kWaveBytes + kTabBytes + 2 * 256 * 4;  // + two step tables
+  static_assert(NI % 4 == 0 && ND % 4 == 0, "counts are moved as 32-bit words");
 };
 
 // One texel update with the moving average of Alg. MovingAvgUpdate; the
@@ -289,8 +301,10 @@ __device__ __forceinline__ void blend_tau(float* V, uint32_t& N, float t, float 
 }
 
 // Tile element -> interior source element (border fold), built once per
-// workgroup in LDS: irradiance [GI*GI*3], then depth [GD*GD*2].
-template <int RI, int RD>
+// workgroup in LDS: irradiance [GI*GI*3], then depth [GD*GD*2]. Interior
+// texel k's channel c sits at 3k + c / 2k + c, or with PLANAR at c NI + k /
+// c ND + k.
+template <int RI, int RD, bool PLANAR = false>
 __device__ void build_fold_tables(uint16_t* tab) {
   using W = WaveTile<RI, RD>;
   constexpr int GI = W::GI, GD = W::GD;
@@ -298,13 +312,15 @@ __device__ void build_fold_tables(uint16_t* tab) {
     const int t = f / 3, c = f - 3 * t, Y = t / GI, X = t - Y * GI;
     int sx, sy;
     border_source(X, Y, RI, sx, sy);
-    tab[f] = (uint16_t)(((sy - 1) * RI + (sx - 1)) * 3 + c);
+    const int k = (sy - 1) * RI + (sx - 1);
+    tab[f] = (uint16_t)(PLANAR ? c * W::NI + k : 3 * k + c);
   }
   for (int f = threadIdx.x; f < GD * GD * 2; f += blockDim.x) {
     const int t = f >> 1, c = f & 1, Y = t / GD, X = t - Y * GD;
     int sx, sy;
     border_source(X, Y, RD, sx, sy);
-    tab[GI * GI * 3 + f] = (uint16_t)(((sy - 1) * RD + (sx - 1)) * 2 + c);
+    const int k = (sy - 1) * RD + (sx - 1);
+    tab[GI * GI * 3 + f] = (uint16_t)(PLANAR ? c * W::ND + k : 2 * k + c);
   }
 }
 
@@ -334,107 +350,231 @@ __device__ __forceinline__ float4 chain_record(const VolumeView& v, uint32_t k) 
   return make_float4(a.x, a.y, a.z, v.rec[2 * (size_t)k + 1].w);
 }
 
+// One sample into texel k of the LDS planes: the moving average of Alg.
+// MovingAvgUpdate with the step weight max(1/(N+1), 1-h) from the
+// workgroup's table (the same FP32 operations as blend_rgb / blend_tau).
+template <int NI>
+__device__ __forceinline__ void plane_rgb(float* sI, uint32_t k, float4 r, const float* alpha) {
+  uint32_t* nk = (uint32_t*)(sI + 3 * NI) + k;
+  const uint32_t n = *nk;
+  const float al = alpha[n];
+  sI[k] = fmaf(al, r.x - sI[k], sI[k]);
+  sI[NI + k] = fmaf(al, r.y - sI[NI + k], sI[NI + k]);
+  sI[2 * NI + k] = fmaf(al, r.z - sI[2 * NI + k], sI[2 * NI + k]);
+  *nk = min(n + 1u, 255u);
+}
+template <int ND>
+__device__ __forceinline__ void plane_tau(float* sD, uint32_t k, float tau, float tau2, const float* alpha) {
+  uint32_t* nk = (uint32_t*)(sD + 2 * ND) + k;
+  const uint32_t n = *nk;
+  const float al = alpha[n];
+  sD[k] = fmaf(al, tau - sD[k], sD[k]);
+  sD[ND + k] = fmaf(al, tau2 - sD[ND + k], sD[ND + k]);
+  *nk = min(n + 1u, 255u);
+}
+
+// Lanes (among `live`) whose key equals this lane's, from one ballot per key
+// bit: the wave-wide match without memory traffic.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_key(uint32_t key, uint64_t live) {
+  uint64_t m = live;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const bool bit = (key >> b) & 1u;
+    const uint64_t on = ballot(bit);
+    m &= bit ? on : ~on;
+  }
+  return m;
+}
+
+// What a wave loads for a probe before it works on it: its interior texels
+// (row by row, so consecutive lanes read consecutive words), its counts as
+// 32-bit words, and the record and texel indices of its first 64 samples.
 template <int RI, int RD, bool HALF, bool CHAIN>
-__device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
-                                 const uint16_t* tab, const float* alpha, const float* alpha_dyn) {
+struct ProbeRegs {
+  using W = WaveTile<RI, RD>;
+  static constexpr int LI = (3 * W::NI + 63) / 64, LD = (2 * W::ND + 63) / 64;
+  static constexpr int CI = (W::NI / 4 + 63) / 64, CD = (W::ND / 4 + 63) / 64;
+  float ti[LI], td[LD];
+  uint32_t ci[CI], cd[CD];
+  float4 rec;
+  uint32_t bins;  // budgeted frames: irradiance texel | depth texel << 16
+  float2 uv;      // chain frames: the sample's octahedral coordinates
+};
+
+// Record and texel indices (or chain uv) of sample j of the list at off.
+template <bool CHAIN>
+__device__ __forceinline__ void load_sample(const VolumeView& v, uint32_t off, uint32_t j, float4& rec,
+                                            uint32_t& bins, float2& uv) {
+  if (CHAIN) {
+    rec = chain_record(v, off + j);
+    uv = v.smp_uv[off + j];
+  } else {
+    rec = v.rec[off + j];
+    bins = v.ray_bins[off + j];
+  }
+}
+
+template <int RI, int RD, bool HALF, bool CHAIN>
+__device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& io, int i, uint32_t off,
+                                           uint32_t n, ProbeRegs<RI, RD, HALF, CHAIN>& g) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
-  constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
+  using G = ProbeRegs<RI, RD, HALF, CHAIN>;
+  constexpr int NI = W::NI, ND = W::ND, GI = W::GI, GD = W::GD;
   const int lane = threadIdx.x & 63;
-  float4* rec_s = (float4*)wbase;
-  unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
-  const FrameParams& fp = *v.fp;
   const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
   const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
-  float vi[SI][3], vd[SD][2];
-  uint32_t ni[SI], nd[SD];
 #pragma unroll
-  for (int s = 0; s < SI; ++s) {
-    const int k = lane + 64 * s;
-    vi[s][0] = vi[s][1] = vi[s][2] = 0.f;
-    ni[s] = 0u;
-    if (k < NI) {
-      const int iy = k / RI, ix = k - iy * RI;
-      const T* p = irr_in + ((iy + 1) * GI + ix + 1) * 3;
-      vi[s][0] = S::load(p);
-      vi[s][1] = S::load(p + 1);
-      vi[s][2] = S::load(p + 2);
-      ni[s] = io.irr_n_in[(size_t)i * NI + k];
+  for (int s = 0; s < G::LI; ++s) {
+    const int f = lane + 64 * s;
+    if (f < 3 * NI) {
+      const int row = f / (3 * RI), col = f - row * (3 * RI);
+      g.ti[s] = S::load(irr_in + ((row + 1) * GI + 1) * 3 + col);
     }
   }
 #pragma unroll
-  for (int s = 0; s < SD; ++s) {
-    const int k = lane + 64 * s;
-    vd[s][0] = vd[s][1] = 0.f;
-    nd[s] = 0u;
-    if (k < ND) {
-      const int iy = k / RD, ix = k - iy * RD;
-      const T* p = dep_in + ((iy + 1) * GD + ix + 1) * 2;
-      vd[s][0] = S::load(p);
-      vd[s][1] = S::load(p + 1);
-      nd[s] = io.dep_n_in[(size_t)i * ND + k];
+  for (int s = 0; s < G::LD; ++s) {
+    const int f = lane + 64 * s;
+    if (f < 2 * ND) {
+      const int row = f / (2 * RD), col = f - row * (2 * RD);
+      g.td[s] = S::load(dep_in + ((row + 1) * GD + 1) * 2 + col);
     }
   }
-  const uint32_t off = v.offsets[i];
-  const uint32_t n = v.offsets[i + 1] - off;
+  const uint32_t* ni_in = (const uint32_t*)(io.irr_n_in + (size_t)i * NI);
+  const uint32_t* nd_in = (const uint32_t*)(io.dep_n_in + (size_t)i * ND);
+#pragma unroll
+  for (int s = 0; s < G::CI; ++s)
+    if (lane + 64 * s < NI / 4) g.ci[s] = ni_in[lane + 64 * s];
+#pragma unroll
+  for (int s = 0; s < G::CD; ++s)
+    if (lane + 64 * s < ND / 4) g.cd[s] = nd_in[lane + 64 * s];
+  if ((uint32_t)lane < n) load_sample<CHAIN>(v, off, (uint32_t)lane, g.rec, g.bins, g.uv);
+}
+
+template <int RI, int RD, bool HALF, bool CHAIN>
+__device__ __forceinline__ void stage_probe(const ProbeRegs<RI, RD, HALF, CHAIN>& g, uint8_t* wbase) {
+  using W = WaveTile<RI, RD>;
+  using G = ProbeRegs<RI, RD, HALF, CHAIN>;
+  constexpr int NI = W::NI, ND = W::ND;
+  const int lane = threadIdx.x & 63;
+  float* sI = (float*)(wbase + W::kStI);
+  float* sD = (float*)(wbase + W::kStD);
+  uint32_t* nI = (uint32_t*)(sI + 3 * NI);
+  uint32_t* nD = (uint32_t*)(sD + 2 * ND);
+#pragma unroll
+  for (int s = 0; s < G::LI; ++s) {
+    const int f = lane + 64 * s;
+    if (f < 3 * NI) {
+      const int k = f / 3;
+      sI[(f - 3 * k) * NI + k] = g.ti[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::LD; ++s) {
+    const int f = lane + 64 * s;
+    if (f < 2 * ND) sD[(f & 1) * ND + (f >> 1)] = g.td[s];
+  }
+  // counts: word w holds the counts of texels 4w .. 4w+3
+#pragma unroll
+  for (int s = 0; s < G::CI; ++s) {
+    const int w = lane + 64 * s;
+    if (w < NI / 4)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) nI[4 * w + b] = (g.ci[s] >> (8 * b)) & 0xFFu;
+  }
+#pragma unroll
+  for (int s = 0; s < G::CD; ++s) {
+    const int w = lane + 64 * s;
+    if (w < ND / 4)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) nD[4 * w + b] = (g.cd[s] >> (8 * b)) & 0xFFu;
+  }
+}
+
+// The samples of probe i (n of them at off; the first 64 already in
+// rec0/bins0/uv0) into its LDS texels, then the dynamic pass of chain frames.
+// at_last_chunk() runs once, when the probe's last chunk of records has been
+// loaded (before it is applied), so the wave's loads of its next probe go out
+// behind every load of this one and overlap the rest of its work.
+template <int RI, int RD, bool HALF, bool CHAIN, typename F>
+__device__ __forceinline__ void blend_probe_samples(const VolumeView& v, int i, uint32_t off, uint32_t n,
+                                                    float4 rec0, uint32_t bins0, float2 uv0, uint8_t* wbase,
+                                                    const float* alpha, const float* alpha_dyn,
+                                                    F&& at_last_chunk) {
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND;
+  const int lane = threadIdx.x & 63;
+  float* sI = (float*)(wbase + W::kStI);
+  float* sD = (float*)(wbase + W::kStD);
+  const FrameParams& fp = *v.fp;
   const float inv_s = 1.0f / v.s_diag;
   const float tmax = v.tau_max;
-  float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-  if ((uint32_t)lane < n) nxt = CHAIN ? chain_record(v, off + lane) : v.rec[off + lane];
+  float4 nxt = rec0;
+  uint32_t nbin = bins0;
+  float2 nuv = uv0;
+  if (n == 0u) at_last_chunk();
   for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
     const uint32_t m = min(64u, n - c0);
     const float4 cur = nxt;
-    if (c0 + 64u + (uint32_t)lane < n)
-      nxt = CHAIN ? chain_record(v, off + c0 + 64u + lane) : v.rec[off + c0 + 64u + lane];
-    for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
-    wave_sync();
-    if ((uint32_t)lane < m) {
+    uint32_t cbin = nbin;
+    const float2 cuv = nuv;
+    if (c0 + 64u < n) {
+      if (c0 + 64u + (uint32_t)lane < n) load_sample<CHAIN>(v, off, c0 + 64u + lane, nxt, nbin, nuv);
+    } else {
+      at_last_chunk();
+    }
+    const bool act = (uint32_t)lane < m;
+    if (CHAIN && act) {
+      // sample k: irradiance texel of d(uv_k), depth texel of -d
       const uint32_t j = c0 + (uint32_t)lane;
-      rec_s[lane] = cur;
-      uint32_t bI, bD;
-      if (CHAIN) {
-        const float3 d = oct_decode_dir(v.smp_uv[off + j]);
-        bI = oct_bin(oct_encode(d), RI);
-        bD = oct_bin(oct_encode(make_float3(-d.x, -d.y, -d.z)), RD);
-        if (fp.debug) {
-          v.dbg_ibin[2 * (size_t)(off + j)] = (uint16_t)bI;
-          v.dbg_dbin[2 * (size_t)(off + j) + 1] = (uint16_t)bD;
-        }
-      } else {
-        const float2 uv = oct_encode(sf_direction(j, n, fp.R));
-        bI = oct_bin(uv, RI);
-        bD = oct_bin(uv, RD);
-        if (fp.debug) {
-          v.dbg_ibin[off + j] = (uint16_t)bI;
-          v.dbg_dbin[off + j] = (uint16_t)bD;
-        }
-      }
-      atomicOr(&mask[bI], 1ull << lane);
-      atomicOr(&mask[NI + bD], 1ull << lane);
-    }
-    wave_sync();
-#pragma unroll
-    for (int s = 0; s < SI; ++s) {
-      const int k = lane + 64 * s;
-      unsigned long long mk = k < NI ? mask[k] : 0ull;
-      while (mk) {
-        const int j = __ffsll((long long)mk) - 1;
-        mk &= mk - 1ull;
-        blend_rgb(vi[s], ni[s], rec_s[j], alpha);
+      const float3 d = oct_decode_dir(cuv);
+      const uint32_t bI = oct_bin(oct_encode(d), RI);
+      const uint32_t bD = oct_bin(oct_encode(make_float3(-d.x, -d.y, -d.z)), RD);
+      cbin = bI | (bD << 16);
+      if (fp.debug) {
+        v.dbg_ibin[2 * (size_t)(off + j)] = (uint16_t)bI;
+        v.dbg_dbin[2 * (size_t)(off + j) + 1] = (uint16_t)bD;
       }
     }
-#pragma unroll
-    for (int s = 0; s < SD; ++s) {
-      const int k = lane + 64 * s;
-      unsigned long long mk = k < ND ? mask[NI + k] : 0ull;
-      while (mk) {
-        const int j = __ffsll((long long)mk) - 1;
-        mk &= mk - 1ull;
-        blend_tau(vd[s], nd[s], rec_s[j].w, inv_s, tmax, alpha);
-      }
+    const uint32_t bI = cbin & 0xFFFFu, bD = cbin >> 16;
+    // rank of this sample among the chunk's samples of the same texel, and
+    // their number
+    const uint64_t live = ballot(act);
+    const uint64_t mI = match_key<W::BI>(bI, live), mD = match_key<W::BD>(bD, live);
+    const uint32_t rI = lanes_below(mI), rD = lanes_below(mD);
+    // the sample's count N before it is applied is the texel's count before
+    // the chunk plus its rank (saturating at 255), so its step weight is known
+    // before any sample of the chunk is applied; the last sample of each
+    // texel writes the texel's new count
+    uint32_t* nI = (uint32_t*)(sI + 3 * NI);
+    uint32_t* nD = (uint32_t*)(sD + 2 * ND);
+    float aI = 0.f, aD = 0.f;
+    if (act) {
+      const uint32_t n0I = nI[bI], n0D = nD[bD];
+      aI = alpha[min(n0I + rI, 255u)];
+      aD = alpha[min(n0D + rD, 255u)];
+      wave_sync();
+      if (rI + 1u == (uint32_t)__popcll(mI)) nI[bI] = min(n0I + rI + 1u, 255u);
+      if (rD + 1u == (uint32_t)__popcll(mD)) nD[bD] = min(n0D + rD + 1u, 255u);
     }
-    wave_sync();
+    const float tau = fminf(cur.w * inv_s, tmax);
+    const float tau2 = tau * tau;
+    const uint32_t rmax = act ? max(rI, rD) : 0u;
+    for (uint32_t r = 0;; ++r) {
+      if (act && rI == r) {
+        sI[bI] = fmaf(aI, cur.x - sI[bI], sI[bI]);
+        sI[NI + bI] = fmaf(aI, cur.y - sI[NI + bI], sI[NI + bI]);
+        sI[2 * NI + bI] = fmaf(aI, cur.z - sI[2 * NI + bI], sI[2 * NI + bI]);
+      }
+      if (act && rD == r) {
+        sD[bD] = fmaf(aD, tau - sD[bD], sD[bD]);
+        sD[ND + bD] = fmaf(aD, tau2 - sD[ND + bD], sD[ND + bD]);
+      }
+      wave_sync();
+      if (ballot(rmax > r) == 0ull) break;
+    }
   }
   if (CHAIN && fp.dyn_chains > 0) {
     // dynamic updates after the static samples (Sec. 4.9): every texel of a
@@ -449,63 +589,68 @@ __device__ void blend_probe_wave(const VolumeView& v, const BlendIO& io, int i, 
       pre[oc] = acc;
       if (mk[oc]) acc += (uint32_t)(tb.start_i[oc + 1] - tb.start_i[oc]) + (uint32_t)(tb.start_d[oc + 1] - tb.start_d[oc]);
     }
-#pragma unroll
-    for (int s = 0; s < SI; ++s) {
-      const int k = lane + 64 * s;
-      if (k < NI) {
-        const int oc = tb.oct_i[k];
-        if (mk[oc]) blend_rgb(vi[s], ni[s], v.rec[pre[oc] + tb.rank_i[k]], alpha_dyn);
+    for (int k = lane; k < NI; k += 64) {
+      const int oc = tb.oct_i[k];
+      if (mk[oc]) plane_rgb<NI>(sI, k, v.rec[pre[oc] + tb.rank_i[k]], alpha_dyn);
+    }
+    for (int k = lane; k < ND; k += 64) {
+      const int oc = tb.oct_d[k];
+      if (mk[oc]) {
+        const uint32_t ni_oc = (uint32_t)(tb.start_i[oc + 1] - tb.start_i[oc]);
+        const float tau = fminf(v.rec[pre[oc] + ni_oc + tb.rank_d[k]].w * inv_s, tmax);
+        plane_tau<ND>(sD, k, tau, tau * tau, alpha_dyn);
       }
     }
-#pragma unroll
-    for (int s = 0; s < SD; ++s) {
-      const int k = lane + 64 * s;
-      if (k < ND) {
-        const int oc = tb.oct_d[k];
-        if (mk[oc]) {
-          const uint32_t ni_oc = (uint32_t)(tb.start_i[oc + 1] - tb.start_i[oc]);
-          blend_tau(vd[s], nd[s], v.rec[pre[oc] + ni_oc + tb.rank_d[k]].w, inv_s, tmax, alpha_dyn);
-        }
-      }
-    }
+    wave_sync();
   }
-  float* stI = (float*)wbase;
-  float* stD = stI + 3 * NI;
-  uint8_t* stN = (uint8_t*)(stD + 2 * ND);
-#pragma unroll
-  for (int s = 0; s < SI; ++s) {
-    const int k = lane + 64 * s;
-    if (k < NI) {
-      stI[3 * k] = vi[s][0];
-      stI[3 * k + 1] = vi[s][1];
-      stI[3 * k + 2] = vi[s][2];
-      stN[k] = (uint8_t)ni[s];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < SD; ++s) {
-    const int k = lane + 64 * s;
-    if (k < ND) {
-      stD[2 * k] = vd[s][0];
-      stD[2 * k + 1] = vd[s][1];
-      stN[NI + k] = (uint8_t)nd[s];
-    }
-  }
-  wave_sync();
-  write_tiles<RI, RD, HALF>(v, io, i, stI, stD, stN, tab, lane, 64);
-  wave_sync();
+}
+
+// Both tiles of probe i with the border fold, and the counts, from the LDS
+// planes (tab: the fold table of the planar layout).
+template <int RI, int RD, bool HALF>
+__device__ __forceinline__ void store_probe(const BlendIO& io, int i, const uint8_t* wbase, const uint16_t* tab) {
+  using S = Store<HALF>;
+  using T = typename S::T;
+  using W = WaveTile<RI, RD>;
+  constexpr int NI = W::NI, ND = W::ND, GI = W::GI, GD = W::GD;
+  const int lane = threadIdx.x & 63;
+  const float* sI = (const float*)(wbase + W::kStI);
+  const float* sD = (const float*)(wbase + W::kStD);
+  T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
+  T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
+  for (int f = lane; f < GI * GI * 3; f += 64) S::store(irr_out + f, sI[tab[f]]);
+  for (int f = lane; f < GD * GD * 2; f += 64) S::store(dep_out + f, sD[tab[GI * GI * 3 + f]]);
+  uint32_t* ni_out = (uint32_t*)(io.irr_n_out + (size_t)i * NI);
+  uint32_t* nd_out = (uint32_t*)(io.dep_n_out + (size_t)i * ND);
+  const uint32_t* nI = (const uint32_t*)(sI + 3 * NI);
+  const uint32_t* nD = (const uint32_t*)(sD + 2 * ND);
+  for (int w = lane; w < NI / 4; w += 64)
+    ni_out[w] = nI[4 * w] | (nI[4 * w + 1] << 8) | (nI[4 * w + 2] << 16) | (nI[4 * w + 3] << 24);
+  for (int w = lane; w < ND / 4; w += 64)
+    nd_out[w] = nD[4 * w] | (nD[4 * w + 1] << 8) | (nD[4 * w + 2] << 16) | (nD[4 * w + 3] << 24);
 }
 
 // One wave per probe, probes taken round-robin over all waves of the grid in
-// the allocation's order (most chunks first).
+// the allocation's order (most chunks first). Software-pipelined: a wave
+// keeps the probe index and ray range of its next two probes in scalar
+// registers (the probe index two ahead, loaded while it works on a probe, and
+// the ray range of the next one, loaded at the end of the probe before), and
+// issues the loads of its next probe's texels, counts and first 64 records
+// before it works on the current one, so a probe waits for memory once and
+// that wait overlaps another probe's work. order and offsets are passed
+// apart as restrict pointers (no store of the kernel aliases them), which
+// lets their wave-uniform loads go through the scalar cache.
 template <int RI, int RD, bool HALF, bool CHAIN>
-__global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io) {
+__global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io,
+                                                         const int32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ offsets) {
   using W = WaveTile<RI, RD>;
+  using G = ProbeRegs<RI, RD, HALF, CHAIN>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
+  uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);  // planar layout
   float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
   float* alpha_dyn = alpha + 256;
-  build_fold_tables<RI, RD>(tab);
+  build_fold_tables<RI, RD, true>(tab);
   // step weight of Alg. MovingAvgUpdate by sample count N (static and dynamic)
   for (int k = threadIdx.x; k < 256; k += blockDim.x) {
     alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
@@ -514,8 +659,41 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
   __syncthreads();
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
-  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
-    blend_probe_wave<RI, RD, HALF, CHAIN>(v, io, v.order[q], wbase, tab, alpha, alpha_dyn);
+  const uint32_t P = (uint32_t)v.P;
+  uint32_t q = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (q >= P) return;
+  G g;
+  int i = order[q];
+  uint32_t off = offsets[i], n = offsets[i + 1] - off;
+  load_probe<RI, RD, HALF, CHAIN>(v, io, i, off, n, g);
+  uint32_t q1 = q + waves;
+  int i1 = q1 < P ? order[q1] : 0;
+  uint32_t off1 = q1 < P ? offsets[i1] : 0u;
+  uint32_t n1 = q1 < P ? offsets[i1 + 1] - off1 : 0u;
+  while (q < P) {
+    stage_probe<RI, RD, HALF, CHAIN>(g, wbase);
+    const float4 rec0 = g.rec;
+    const uint32_t bins0 = g.bins;
+    const float2 uv0 = g.uv;
+    wave_sync();
+    const uint32_t q2 = q1 + waves;
+    const int i2 = q2 < P ? order[q2] : 0;
+    if (q1 < P) load_probe<RI, RD, HALF, CHAIN>(v, io, i1, off1, n1, g);
+    blend_probe_samples<RI, RD, HALF, CHAIN>(v, i, off, n, rec0, bins0, uv0, wbase, alpha, alpha_dyn,
+                                             []() {});
+    store_probe<RI, RD, HALF>(io, i, wbase, tab);
+    const uint32_t off2 = q2 < P ? offsets[i2] : 0u;
+    const uint32_t n2 = q2 < P ? offsets[i2 + 1] - off2 : 0u;
+    wave_sync();
+    q = q1;
+    i = i1;
+    off = off1;
+    n = n1;
+    q1 = q2;
+    i1 = i2;
+    off1 = off2;
+    n1 = n2;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -712,7 +890,6 @@ __device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i
   const int lane = threadIdx.x & 63;
   float4* rec_s = (float4*)wbase;
   unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
-  const FrameParams& fp = *v.fp;
   const uint32_t* irr_in = (const uint32_t*)io.irr_in + (size_t)i * GI * GI;
   const uint32_t* dep_in = (const uint32_t*)io.dep_in + (size_t)i * GD * GD;
   uint32_t wi[SI], wd[SD];
@@ -749,14 +926,9 @@ __device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i
     if ((uint32_t)lane < m) {
       const uint32_t j = c0 + (uint32_t)lane;
       rec_s[lane] = cur;
-      const float2 uv = oct_encode(sf_direction(j, n, fp.R));
-      const uint32_t bI = oct_bin(uv, RI), bD = oct_bin(uv, RD);
-      atomicOr(&mask[bI], 1ull << lane);
-      atomicOr(&mask[NI + bD], 1ull << lane);
-      if (fp.debug) {
-        v.dbg_ibin[off + j] = (uint16_t)bI;
-        v.dbg_dbin[off + j] = (uint16_t)bD;
-      }
+      const uint32_t bins = v.ray_bins[off + j];
+      atomicOr(&mask[bins & 0xFFFFu], 1ull << lane);
+      atomicOr(&mask[NI + (bins >> 16)], 1ull << lane);
     }
     wave_sync();
 #pragma unroll
@@ -839,15 +1011,15 @@ static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, 
   else if (gather)
     hipLaunchKernelGGL((blend_gather_kernel<RI, RD, false>), dim3(grid), dim3(256), lds, s, v, io);
   else if (chain && storage == ADGI_FP16)
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, true>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, true>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
   else if (chain)
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, true>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, true>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
   else if (storage == ADGI_PACKED)
     hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(256), lds + 4 * kPkDecTau, s, v, io);
   else if (storage == ADGI_FP16)
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, false>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, false>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
   else
-    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, false>), dim3(grid), dim3(256), lds, s, v, io);
+    hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, false>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
 }
 
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,

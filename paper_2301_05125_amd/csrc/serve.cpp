@@ -121,6 +121,7 @@ struct Stream {
   // device memory (and its share of the budget) until retire_ev completes
   adgi_volume* retiring = nullptr;
   hipEvent_t retire_ev = nullptr;
+  hipEvent_t start_ev = nullptr; // recorded on the lane before the frame in flight
   hipEvent_t done_ev = nullptr;  // recorded behind the frame in flight
   int32_t lane = -1;             // server lane of the frame in flight
   int32_t next_frame = 0;
@@ -134,6 +135,7 @@ struct Stream {
   Stream& operator=(const Stream&) = delete;
   ~Stream() {
     if (retire_ev) (void)hipEventDestroy(retire_ev);
+    if (start_ev) (void)hipEventDestroy(start_ev);
     if (done_ev) (void)hipEventDestroy(done_ev);
     if (state_buf) (void)hipHostFree(state_buf);
     adgi::unpin_scene(built);
@@ -185,6 +187,7 @@ struct adgi_server {
   int64_t admissions = 0, evictions = 0, completed = 0, rays = 0;
   int64_t first_arrival_ns = 0, last_done_ns = 0;
   double admit_ms = 0.0, evict_ms = 0.0;
+  double busy_ms = 0.0;  // sum over completed frames of start -> done on the device
   std::vector<double> latency_ms;
 };
 
@@ -196,7 +199,7 @@ namespace {
 adgi_status evict(adgi_server* s, Stream& st) {
   auto t0 = now_ns();
   const size_t n = adgi_state_size(st.vol);
-  if (n > st.state_cap) return sfail(ADGI_ERR_DEVICE, "stream state outgrew its host buffer");
+  if (!st.state_buf || n > st.state_cap) return sfail(ADGI_ERR_DEVICE, "stream state outgrew its host buffer");
   // idle: the copy goes on the volume's own stream, not behind a lane
   adgi_status e = adgi::bind_streams(st.vol, nullptr);
   if (e != ADGI_OK) return pass(e);
@@ -259,6 +262,7 @@ adgi_status make_resident(adgi_server* s, Stream& st) {
   e = adgi::update_scene_impl(vol, &sd, &st.built);
   // the state copy is enqueued on the volume's stream: state_buf is next
   // written by this stream's eviction, which first waits for that stream
+  if (e == ADGI_OK && st.state_len > st.state_cap) e = sfail(ADGI_ERR_DEVICE, "stream state larger than its host buffer");
   if (e == ADGI_OK && st.state_len) e = adgi::restore_state_impl(vol, st.state_buf, st.state_len, true);
   if (e != ADGI_OK) {
     pass(e);
@@ -312,9 +316,12 @@ bool make_room(adgi_server* s, const Stream& target, bool gentle, bool block, ad
 }
 
 adgi_status dispatch(adgi_server* s, Stream& st, int64_t id) {
+  if (id < 0 || id >= (int64_t)s->reqs.size()) return sfail(ADGI_ERR_INVALID_ARG, "request id out of range");
+  if (!st.vol || st.inflight >= 0) return sfail(ADGI_ERR_INVALID_ARG, "stream not idle and resident");
   Request& r = s->reqs[id];
   // the stream is idle: its last frame is done, so it may change lanes
   const size_t nl = s->lanes.size();
+  if (nl == 0 || s->lane_load.size() != nl) return sfail(ADGI_ERR_DEVICE, "server has no lanes");
   size_t k = s->next_lane % nl;
   for (size_t a = 1; a < nl; ++a) {
     const size_t j = (s->next_lane + a) % nl;
@@ -322,6 +329,7 @@ adgi_status dispatch(adgi_server* s, Stream& st, int64_t id) {
   }
   adgi_status e = adgi::bind_streams(st.vol, s->lanes[k]);
   if (e != ADGI_OK) return pass(e);
+  if (hipEventRecord(st.start_ev, s->lanes[k]) != hipSuccess) return sfail(ADGI_ERR_DEVICE, "hipEventRecord failed");
   adgi_scene_desc sd = st.scene(ADGI_SCENE_REFIT, &r.lights[0][0]);
   e = adgi_update_scene(st.vol, &sd);
   if (e != ADGI_OK) return pass(e);
@@ -347,9 +355,13 @@ adgi_status progress_once(adgi_server* s, int32_t* done_now) {
   for (auto& p : s->streams) {
     Stream& st = *p;
     if (st.inflight < 0) continue;
+    if (st.inflight >= (int64_t)s->reqs.size() || st.lane < 0 || st.lane >= (int32_t)s->lanes.size())
+      return sfail(ADGI_ERR_DEVICE, "in-flight bookkeeping out of range");
     Request& r = s->reqs[st.inflight];
     if (hipEventQuery(st.done_ev) != hipSuccess) continue;
     const int64_t t = now_ns();
+    float span_ms = 0.f;
+    if (hipEventElapsedTime(&span_ms, st.start_ev, st.done_ev) == hipSuccess) s->busy_ms += span_ms;
     r.done_ns = t;
     r.completed = true;
     s->latency_ms.push_back((t - r.arrival_ns) * 1e-6);
@@ -517,7 +529,7 @@ adgi_status adgi_server_add_stream(adgi_server* s, const adgi_stream_desc* d, in
   if (hipHostMalloc((void**)&st->state_buf, std::max<size_t>(st->state_cap, 1), hipHostMallocDefault) != hipSuccess)
     return sfail(ADGI_ERR_OUT_OF_MEMORY, "pinned host buffer for the stream state");
   if (hipEventCreateWithFlags(&st->retire_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&st->done_ev, hipEventDisableTiming) != hipSuccess)
+      hipEventCreate(&st->start_ev) != hipSuccess || hipEventCreate(&st->done_ev) != hipSuccess)
     return sfail(ADGI_ERR_DEVICE, "hipEventCreate failed");
   if (st->footprint > s->budget) return sfail(ADGI_ERR_OUT_OF_MEMORY, "stream footprint exceeds the HBM budget");
   *id = (int32_t)s->streams.size();
@@ -597,6 +609,7 @@ adgi_status adgi_server_get_stats(const adgi_server* s, adgi_server_stats* out) 
   out->span_s = s->completed ? (s->last_done_ns - s->first_arrival_ns) * 1e-9 : 0.0;
   out->admit_ms = s->admit_ms;
   out->evict_ms = s->evict_ms;
+  out->device_busy_ms = s->busy_ms;
   return ADGI_OK;
 }
 

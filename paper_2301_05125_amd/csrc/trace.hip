@@ -387,16 +387,22 @@ __device__ __forceinline__ uint32_t ray_total(const VolumeView& v) {
 // Origin and direction of ray r; `shade` is false for the distance-only rays
 // of chain frames. Probe rays: i0 is the probe of a ray at most 63 before r
 // (every probe has at least one ray, so r's probe is within i0 + 63).
+// dst: where the ray's outputs go (probe rays: the index of the ray that the
+// slot traces under the coherent order, else r itself).
 template <int KIND>
 __device__ __forceinline__ void gen_ray(const VolumeView& v, uint32_t r, int i0, float3& o, float3& d,
-                                        bool& shade) {
+                                        bool& shade, uint32_t& dst) {
   const FrameParams& fp = *v.fp;
   shade = true;
+  dst = r;
   if (KIND == KIND_PRIMARY) {
     int i = probe_in(v.offsets, i0, min(i0 + 63, v.P - 1), r);
     uint32_t b = v.offsets[i], n = v.offsets[i + 1] - b;
     o = probe_position(v, i);
-    d = sf_direction(r - b, n, fp.R);
+    uint32_t j = r - b;
+    if (v.ray_perm && n <= (uint32_t)v.ray_perm_max) j = v.ray_perm[(size_t)n * (n - 1u) / 2u + j];
+    dst = b + j;
+    d = sf_direction(j, n, fp.R);
   } else if (KIND == KIND_CHAIN) {
     const uint32_t S2 = 2u * v.offsets[v.P];
     d = make_float3(0.f, 0.f, 1.f);
@@ -521,9 +527,22 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
   const bool active = r < total;
   float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
   bool shade = true;
+  uint32_t dst = r;
   // probe of the batch's first ray (the same in every lane)
   const int i0 = KIND == KIND_PRIMARY ? probe_of_ray(v.offsets, v.P, b * 64u) : 0;
-  if (active) gen_ray<KIND>(v, r, i0, o, d, shade);
+  if (active) gen_ray<KIND>(v, r, i0, o, d, shade, dst);
+  if (KIND == KIND_PRIMARY && active) {
+    // the interior irradiance and depth texels the ray's direction falls in,
+    // for the blend (one 4-byte word per ray instead of regenerating the
+    // direction there)
+    const float2 uv = oct_encode(d);
+    const uint32_t bI = oct_bin(uv, v.irr_res - 2), bD = oct_bin(uv, v.dep_res - 2);
+    v.ray_bins[dst] = bI | (bD << 16);
+    if (v.fp->debug) {
+      v.dbg_ibin[dst] = (uint16_t)bI;
+      v.dbg_dbin[dst] = (uint16_t)bD;
+    }
+  }
   float t = INFINITY;
   bool front = false;
   int id = -1, slot = -1;
@@ -549,6 +568,7 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
       v.hit_pos[r] = make_float4(x.x, x.y, x.z, t);
       v.hit_nrm[r] = make_float4(nrm.x, nrm.y, nrm.z, __int_as_float(id));
       v.hit_vis[r] = (uint32_t)__popc(need) << 8;
+      if (KIND == KIND_PRIMARY) v.hit_dst[r] = dst;
     }
   }
   uint16_t* seg = v.pairs + (size_t)b * kPairsPerBatch;
@@ -564,9 +584,9 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
   if (active && !need) {
     const bool miss = slot < 0;
     const float3 L = miss ? make_float3(sc.sky[0], sc.sky[1], sc.sky[2]) : make_float3(0.f, 0.f, 0.f);
-    emit_ray<KIND>(v, r, L, t, id, 0u);
+    emit_ray<KIND>(v, dst, L, t, id, 0u);
   } else if (active && v.fp->debug) {
-    v.dbg_tri[r] = id;
+    v.dbg_tri[dst] = id;
   }
 }
 
@@ -739,7 +759,7 @@ __device__ __forceinline__ void shade_batch(const VolumeView& v, Stack& st, uint
   const float4 rho = v.albedo[id];
   const float inv_pi = 0.318309886183790671538f;
   const float3 L = make_float3(rho.x * inv_pi * er, rho.y * inv_pi * eg, rho.z * inv_pi * eb);
-  emit_ray<KIND>(v, r, L, pos.w, id, bits);
+  emit_ray<KIND>(v, KIND == KIND_PRIMARY ? v.hit_dst[r] : r, L, pos.w, id, bits);
 }
 
 template <int KIND, bool COUNT, bool W4>

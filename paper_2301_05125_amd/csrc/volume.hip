@@ -179,6 +179,7 @@ struct adgi_volume {
   float last_R[9] = {};
   // chain frames
   void* d_sort_temp = nullptr;
+  uint16_t* d_ray_perm = nullptr;  // coherent ray order tables (ray_order_table)
   size_t sort_temp_bytes = 0;
   int32_t chain_count = 0, chain_steps = 0;  // of the last chain frame (0: chains not started)
   int64_t num_samples = 0;
@@ -256,6 +257,7 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
                          bool count_work = false, hipEvent_t traced = nullptr, int part = 0) {
   const adgi_tuning& t = vol->tun;
   VolumeView& v = vol->v;
+  v.ray_perm = t.ray_order ? vol->d_ray_perm : nullptr;
   hipStream_t s = vol->stream;
   hipError_t e;
   const bool w4 = use_bvh4(vol, t);
@@ -499,6 +501,41 @@ float packed_decode_host(uint32_t q, float beta, float gamma, int bits) {
 
 bool finite3(const float* x) { return std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]); }
 
+// Coherent order of a probe's rays for the traversal. The n rays of a probe
+// are the points of a spherical Fibonacci set, whose index j runs down the
+// sphere in z; 64 consecutive indices form a thin band around the whole
+// sphere, so one wave's rays point every way. Slot k of a probe with n rays
+// traces ray perm_n(k) instead: the indices are cut into bands of B
+// consecutive indices (B a multiple of 64 near sqrt(201 n), which makes the
+// 64-ray patch of a wave about as tall in z as it is wide in azimuth) and
+// each band is listed in ascending azimuth (the 32-bit fraction the
+// direction's angle is computed from). Rays keep their indices, so every
+// output is the same; only which lane traces which ray changes. Tables for
+// n = 1 .. kRayOrderMaxN, n (n-1)/2 entries before n's; built once per process.
+constexpr int kRayOrderMaxN = 2048;
+
+const std::vector<uint16_t>& ray_order_table() {
+  static std::vector<uint16_t> tab;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    tab.resize((size_t)kRayOrderMaxN * (kRayOrderMaxN + 1) / 2);
+    std::vector<std::pair<uint32_t, uint32_t>> key;
+    for (uint32_t n = 1; n <= (uint32_t)kRayOrderMaxN; ++n) {
+      uint16_t* out = tab.data() + (size_t)n * (n - 1) / 2;
+      uint32_t band = 64u * (uint32_t)std::max(1L, std::lround(std::sqrt(201.0 * n) / 64.0));
+      for (uint32_t b0 = 0; b0 < n; b0 += band) {
+        const uint32_t b1 = std::min(n, b0 + band);
+        key.clear();
+        for (uint32_t j = b0; j < b1; ++j)
+          key.push_back({(uint32_t)(((uint64_t)j * 0x9E3779B97F4A7C15ull) >> 32), j});
+        std::sort(key.begin(), key.end());
+        for (uint32_t k = b0; k < b1; ++k) out[k] = (uint16_t)key[k - b0].second;
+      }
+    }
+  });
+  return tab;
+}
+
 adgi_tuning default_tuning() {
   adgi_tuning t;
   t.use_graph = 1;
@@ -509,6 +546,7 @@ adgi_tuning default_tuning() {
   t.blend_blocks_per_cu = 16;
   t.bvh_width = 2;
   t.chain_lanes = 0;
+  t.ray_order = 1;
   return t;
 }
 
@@ -559,7 +597,8 @@ bool tuning_valid(const adgi_tuning& t) {
          t.blend_blocks_per_cu >= 1 && t.blend_blocks_per_cu <= 32 &&
          (t.bvh_width == 2 || t.bvh_width == 4) &&
          (t.chain_lanes == 0 || t.chain_lanes == 1 || t.chain_lanes == 4 || t.chain_lanes == 8 ||
-          t.chain_lanes == 16 || t.chain_lanes == 32);
+          t.chain_lanes == 16 || t.chain_lanes == 32) &&
+         (t.ray_order == 0 || t.ray_order == 1);
 }
 
 }  // namespace
@@ -707,9 +746,12 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.blk_off, (size_t)((P + 255) / 256) * 4},
       {(void**)&v.order, (size_t)P * 4},
       {(void**)&v.rec, R * 16},
+      {(void**)&v.ray_bins, R * 4},
       {(void**)&v.hit_pos, std::max(R, (size_t)P * 8) * 16},
       {(void**)&v.hit_nrm, std::max(R, (size_t)P * 8) * 16},
       {(void**)&v.hit_vis, std::max(R, (size_t)P * 8) * 4},
+      {(void**)&v.hit_dst, std::max(R, (size_t)P * 8) * 4},
+      {(void**)&vol->d_ray_perm, ray_order_table().size() * 2},
       {(void**)&v.pairs, (std::max(R, (size_t)P * 8) + 63) / 64 * kPairsPerBatch * 2},
       {(void**)&v.pair_cnt, (std::max(R, (size_t)P * 8) + 63) / 64 * 4},
       {(void**)&v.pair_off, ((std::max(R, (size_t)P * 8) + 63) / 64 + 1) * 4},
@@ -752,6 +794,11 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   }
   // zero the temporal state
   for (auto& r : reqs) CREATE_TRY(hipMemsetAsync(*r.p, 0, r.bytes, vol->stream));
+  {
+    const std::vector<uint16_t>& tab = ray_order_table();  // lives for the process
+    CREATE_TRY(hipMemcpyAsync(vol->d_ray_perm, tab.data(), tab.size() * 2, hipMemcpyHostToDevice, vol->stream));
+    v.ray_perm_max = kRayOrderMaxN;
+  }
   CREATE_TRY(hipEventRecord(vol->ev_traced, vol->stream));
   CREATE_TRY(hipEventRecord(vol->ev_refit, vol->stream));
   if (d->storage == ADGI_PACKED) CREATE_TRY(launch_packed_decode_table((float*)v.pk_dec, vol->stream));

@@ -257,8 +257,9 @@ def test_dynamic_chains_cornell_lockstep():
     # its walls on the diagonals that split each wall quad into two
     # triangles (and shadow rays meet the boxes' edges): both triangles of
     # such a tie lie in one plane with one albedo, so either decision gives
-    # the same radiance. Measured 7.7% hit and 1.7% shadow ties.
-    _assert_dyn_parity(res, hit_ties=0.1, shadow_ties=0.03)
+    # the same radiance. Measured 1.8% hit and 0.4% shadow ties of all rays
+    # (7.7% and 1.7% of the texel-centre rays).
+    _assert_dyn_parity(res, hit_ties=0.04, shadow_ties=0.01)
 
 
 def test_dynamic_chains_box_field_refit_lockstep():

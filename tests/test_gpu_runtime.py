@@ -92,6 +92,8 @@ def test_packed_storage_launch_invariance(tuning):
     {"bvh_width": 2},
     {"bvh_width": 2, "persistent": 0},
     {"bvh_width": 2, "trace_block": 128},
+    {"ray_order": 0},
+    {"ray_order": 0, "bvh_width": 2, "persistent": 0},
 ])
 def test_launch_shape_does_not_change_results(tuning):
     sc = _small_field()
