@@ -198,6 +198,13 @@ typedef struct {
   float dyn_sigma_pos;        /* > 0 (1.5: three times the static default)         */
   float dyn_sigma_dir;        /* > 0 (6 sqrt(pi/256))                              */
   float dyn_hysteresis;       /* [0, 1) (0.91, Tab. cacheDetails)                   */
+  /* Pilot reuse (Sec. 4.4), adaptive and chain frames: 1 = on the first frame
+   * of each pilot pair (even frames; the second traces the same directions)
+   * every probe's 8 pilot samples also update its caches, before the frame's
+   * own samples, in octant order: each pilot's radiance into the irradiance
+   * texel of its direction and its distance into the depth texel of its
+   * direction. ADGI_FP32 / ADGI_FP16 storage, the per-sample wave blend. */
+  int32_t pilot_reuse;
 } adgi_update_params;
 
 typedef struct {
@@ -263,6 +270,13 @@ typedef struct {
   int32_t dyn_chain_steps;    /* out                                               */
   int32_t proxy_dims[3];      /* out: ceil(dims / 3)                               */
   int32_t reserved;
+  /* debug: the pilot rays of the last adaptive or chain frame, ray 8i + k */
+  float* pilot_record;        /* [P][8][4] radiance RGB, hit distance (inf = miss);
+                                 written on frames that reuse the pilots           */
+  int32_t* pilot_tri;         /* [P][8] closest triangle, -1 for a miss            */
+  uint8_t* pilot_shadow;      /* [P][8] bit l: light l lit the hit point           */
+  uint16_t* pilot_ibin;       /* [P][8] interior irradiance texel (reuse frames)   */
+  uint16_t* pilot_dbin;       /* [P][8] interior depth texel (reuse frames)        */
 } adgi_probe_readback;
 
 /* Create a volume: the uniform probe grid of Sec. 3.1 (probe i at origin +

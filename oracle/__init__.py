@@ -111,7 +111,9 @@ def lib():
         L.orc_shade_ray.argtypes = [P, P, P, C.c_double, P, C.c_int32, C.c_int32, P, P, P]
         L.orc_grid_init.argtypes = [P, P, P, P]
         L.orc_probe_pos.argtypes = [P, C.c_int32, P]
-        L.orc_pilots.argtypes = [P, P, C.c_uint64, C.c_int32, C.c_double, P, P, P, P, P, P]
+        L.orc_pilots.argtypes = [P, P, C.c_uint64, C.c_int32, C.c_double, P, P, P, P, P, P, P, P, P, P]
+        L.orc_pilot_blend.argtypes = [P, C.c_uint64, C.c_int32, C.c_int32, P, P, C.c_int32, C.c_int32,
+                                      C.c_double, C.c_double, P, P, P, P, P, P, P, P, P]
         L.orc_detect.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
         L.orc_allocate.restype = C.c_int32
         L.orc_allocate.argtypes = [C.c_int32, P, C.c_int64, C.c_int32, C.c_int32, P, P, P]
@@ -541,17 +543,37 @@ class OracleVolume:
             self.scene.set_positions(sc.positions_at(frame))
         self.scene.set_lights(sc.light_positions(frame), sc.light_intensity, sc.sky)
 
-    def pilots(self, frame: int, beta: float = 5.0, hint_qv=None, hint_qr=None, counts=None):
+    def pilots(self, frame: int, beta: float = 5.0, hint_qv=None, hint_qr=None, counts=None,
+               hint_tri=None, hint_shadow=None, records: bool = False):
         """Pilot codes (Qv, Qr) of every probe and octant; ties and
         mismatches against the hints go to ``counts`` (default: the running
-        totals)."""
+        totals). With ``records`` also each pilot's radiance [P*8, 3] and
+        hit distance [P*8]."""
         qv = np.zeros(self.P * 8, np.uint16)
         qr = np.zeros(self.P * 8, np.uint16)
+        prgb = np.zeros((self.P * 8, 3)) if records else None
+        pt = np.zeros(self.P * 8) if records else None
+        h_tri = None if hint_tri is None else np.ascontiguousarray(hint_tri, np.int32)
+        h_sh = None if hint_shadow is None else np.ascontiguousarray(hint_shadow, np.uint8)
         lib().orc_pilots(self.scene.ptr, C.byref(self.grid), self.seed & 0xFFFFFFFFFFFFFFFF,
                          frame, float(np.float32(beta)), C.byref(self.tol),
-                         _p(hint_qv), _p(hint_qr), _p(qv), _p(qr),
+                         _p(hint_qv), _p(hint_qr), _p(h_tri), _p(h_sh), _p(qv), _p(qr), _p(prgb), _p(pt),
                          C.byref(counts if counts is not None else self.counts))
+        if records:
+            return qv, qr, prgb, pt
         return qv, qr
+
+    def pilot_blend(self, frame: int, prgb, pt, hint_ibin=None, hint_dbin=None, counts=None):
+        """Pilot reuse (Sec. 4.4): the tracked probes' 8 pilot samples into
+        their texels, in octant order."""
+        h_ib = None if hint_ibin is None else np.ascontiguousarray(hint_ibin, np.uint16)
+        h_db = None if hint_dbin is None else np.ascontiguousarray(hint_dbin, np.uint16)
+        lib().orc_pilot_blend(C.byref(self.grid), self.seed & 0xFFFFFFFFFFFFFFFF, frame,
+                              self.probes.shape[0], _p(self.probes), C.byref(self.tol), self.irr_res,
+                              self.depth_res, self.h, self.tau_max, _p(np.ascontiguousarray(prgb)),
+                              _p(np.ascontiguousarray(pt)), _p(h_ib), _p(h_db), _p(self.irr), _p(self.irr_n),
+                              _p(self.dep), _p(self.dep_n),
+                              C.byref(counts if counts is not None else self.counts))
 
     def detect(self, frame: int, qv, qr, theta: int = 8, mu: int = 2):
         lib().orc_detect(C.byref(self.grid), frame, theta, mu, _p(qv), _p(qr),
@@ -561,8 +583,12 @@ class OracleVolume:
 
     def update(self, frame: int, adaptive: bool, budget: int = 0, n_min: int = 8,
                n_max: int = 2048, n_uniform: int = 64, beta: float = 5.0, mu: int = 2,
-               theta: int = 8, hints: Optional[dict] = None, keep_rays: bool = False) -> dict:
-        """One frame. ``hints`` holds the GPU's discrete decisions (lockstep)."""
+               theta: int = 8, hints: Optional[dict] = None, keep_rays: bool = False,
+               pilot_reuse: bool = False) -> dict:
+        """One frame. ``hints`` holds the GPU's discrete decisions (lockstep).
+        ``pilot_reuse``: on the first frame of each pilot pair the pilots'
+        samples also update the caches, before the frame's probe rays
+        (Sec. 4.4)."""
         hints = hints or {}
         t0 = time.perf_counter()
         self.set_frame_inputs(frame)
@@ -572,7 +598,13 @@ class OracleVolume:
         cnt = Counts()
         if adaptive:
             t0 = time.perf_counter()
-            qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"), counts=cnt)
+            reuse = pilot_reuse and frame % 2 == 0
+            qv, qr, prgb, pt = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"), counts=cnt,
+                                           hint_tri=hints.get("pilot_tri"),
+                                           hint_shadow=hints.get("pilot_shadow"), records=True)
+            if reuse:
+                self.pilot_blend(frame, prgb, pt, hints.get("pilot_ibin"), hints.get("pilot_dbin"), counts=cnt)
+            out.update(pilot_rgb=prgb, pilot_t=pt)
             t1 = time.perf_counter()
             score = self.detect(frame, qv, qr, theta, mu)
             n, off, lam = allocate(score, budget, n_min, n_max)
@@ -631,7 +663,7 @@ class OracleVolume:
     def chain_update(self, frame: int, params: "ChainParams", state: np.ndarray, init: bool,
                      beta: float = 5.0, hints: Optional[dict] = None, mu: int = 2, theta: int = 8,
                      dyn: Optional["ChainParams"] = None, dyn_state: Optional[np.ndarray] = None,
-                     dyn_init: bool = False, h_dyn: float = 0.91) -> dict:
+                     dyn_init: bool = False, h_dyn: float = 0.91, pilot_reuse: bool = False) -> dict:
         """One chain frame: pilots (for f_v), detection (triggers and scores
         kept current), one frame of every static chain against the previous
         frame's irradiance, each sample's two rays blended into its nearest
@@ -647,12 +679,18 @@ class OracleVolume:
         hints = hints or {}
         self.set_frame_inputs(frame)
         cnt = Counts()
-        qv, qr = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"), counts=cnt)
+        qv, qr, prgb, pt = self.pilots(frame, beta, hints.get("qv"), hints.get("qr"), counts=cnt,
+                                       hint_tri=hints.get("pilot_tri"), hint_shadow=hints.get("pilot_shadow"),
+                                       records=True)
         self.detect(frame, qv, qr, theta, mu)
         if frame & 1:
             self.qv_odd = qv.copy()
         ri, rd = self.irr_res - 2, self.depth_res - 2
+        # the guide reads the previous frame's irradiance, before this frame's
+        # pilot samples enter the caches
         irr_prev = self.irr.copy()
+        if pilot_reuse and frame % 2 == 0:
+            self.pilot_blend(frame, prgb, pt, hints.get("pilot_ibin"), hints.get("pilot_dbin"), counts=cnt)
         out = chain_frame(self.grid, params, self.seed, frame, qv, irr_prev, ri, state, init,
                           hints.get("accept"), cnt)
         perm, n, base = chain_order(out["sample_probe"], self.P)

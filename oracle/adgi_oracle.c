@@ -790,18 +790,28 @@ static int near_int(double x, double band) {
  * capped at 1023. Round-down follows the paper's quantisation (App. B). */
 void orc_pilots(const orc_scene* s, const orc_grid* g, uint64_t seed, int32_t frame, double beta,
                 const orc_tol* tol, const uint16_t* hint_qv, const uint16_t* hint_qr,
-                uint16_t* qv, uint16_t* qr, orc_counts* counts) {
+                const int32_t* hint_tri, const uint8_t* hint_shadow,
+                uint16_t* qv, uint16_t* qr, double* prgb, double* pt, orc_counts* counts) {
   int32_t P = g->dims[0] * g->dims[1] * g->dims[2];
   int32_t pair = frame / 2;
-  int64_t ties = 0, mism = 0, sh = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : ties, mism, sh)
+  int64_t ties = 0, mism = 0, sh = 0, hties = 0, sties = 0, hmism = 0, smism = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : ties, mism, sh, hties, sties, hmism, smism)
   for (int64_t r = 0; r < (int64_t)P * 8; ++r) {
     int32_t i = (int32_t)(r / 8), k = (int32_t)(r % 8);
     double o[3], d[3];
     orc_probe_pos(g, i, o);
     orc_pilot_dir(seed, i, k, pair, d);
     orc_ray ray;
-    orc_shade_ray(s, o, d, g->s, tol, -2, -1, &ray, NULL, NULL);
+    int64_t rt[2] = {0, 0}, rm[2] = {0, 0};
+    orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[r] : -2, hint_shadow ? (int32_t)hint_shadow[r] : -1,
+                  &ray, rt, rm);
+    hties += rt[0];
+    sties += rt[1];
+    hmism += rm[0];
+    smism += rm[1];
+    if (prgb)
+      for (int c = 0; c < 3; ++c) prgb[3 * r + c] = ray.rgb[c];
+    if (pt) pt[r] = ray.t;
     for (int32_t l = 0; l < s->nl; ++l) sh += 1;
     double fv = isfinite(ray.t) ? exp(-2.0 * ray.t / g->s) : 0.0;
     double fr = fmin(lum709(ray.rgb), beta) / beta;
@@ -841,9 +851,72 @@ void orc_pilots(const orc_scene* s, const orc_grid* g, uint64_t seed, int32_t fr
   if (counts) {
     counts->q10_ties += ties;
     counts->q10_mismatch += mism;
+    counts->hit_ties += hties;
+    counts->shadow_ties += sties;
+    counts->hit_mismatch += hmism;
+    counts->shadow_mismatch += smism;
     counts->rays += (int64_t)P * 8;
   }
   (void)sh;
+}
+
+/* One sample into an interior irradiance texel ki and depth texel kd: the
+ * moving average of Alg. MovingAvgUpdate (step max(1/(N+1), 1-h), N
+ * saturating at 255), radiance into the irradiance texel and the first two
+ * moments of the normalised distance into the depth texel (Sec. 4.6). */
+static void blend_sample(double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n, int32_t ki, int32_t kd,
+                         const double rgb[3], double tau, double hyst) {
+  double ai = orc_blend_alpha(irr_n[ki], hyst);
+  for (int c = 0; c < 3; ++c) irr[3 * ki + c] += ai * (rgb[c] - irr[3 * ki + c]);
+  if (irr_n[ki] < 255) irr_n[ki]++;
+  double ad = orc_blend_alpha(dep_n[kd], hyst);
+  dep[2 * kd + 0] += ad * (tau - dep[2 * kd + 0]);
+  dep[2 * kd + 1] += ad * (tau * tau - dep[2 * kd + 1]);
+  if (dep_n[kd] < 255) dep_n[kd]++;
+}
+
+/* The octahedral bin of d at resolution r, adopting the hint where the
+ * direction lies on a cell edge (a tie). */
+static int32_t hinted_bin(const double d[3], int32_t r, const orc_tol* tol, const uint16_t* hint,
+                          orc_counts* cnt) {
+  int32_t tie = 0;
+  int32_t k = orc_oct_bin(d, r, tol ? tol->bin_eps : 0.0, &tie);
+  if (hint && *hint != k) {
+    if (tie && *hint < r * r) {
+      cnt->bin_ties++;
+      k = *hint;
+    } else {
+      cnt->bin_mismatch++;
+    }
+  }
+  return k;
+}
+
+void orc_pilot_blend(const orc_grid* g, uint64_t seed, int32_t frame, int32_t count, const int32_t* probes,
+                     const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis, double tau_max,
+                     const double* prgb, const double* pt, const uint16_t* hint_ibin,
+                     const uint16_t* hint_dbin, double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
+                     orc_counts* counts) {
+  const int32_t ri = irr_r - 2, rd = dep_r - 2, pair = frame / 2;
+  orc_counts local;
+  memset(&local, 0, sizeof(local));
+  for (int32_t q = 0; q < count; ++q) {
+    const int32_t i = probes[q];
+    for (int32_t k = 0; k < 8; ++k) {
+      const int64_t r = (int64_t)i * 8 + k;
+      double d[3];
+      orc_pilot_dir(seed, i, k, pair, d);
+      const int32_t ki = hinted_bin(d, ri, tol, hint_ibin ? hint_ibin + r : NULL, &local);
+      const int32_t kd = hinted_bin(d, rd, tol, hint_dbin ? hint_dbin + r : NULL, &local);
+      const double tau = isfinite(pt[r]) ? fmin(pt[r] / g->s, tau_max) : tau_max;
+      blend_sample(irr + (int64_t)q * ri * ri * 3, irr_n + (int64_t)q * ri * ri, dep + (int64_t)q * rd * rd * 2,
+                   dep_n + (int64_t)q * rd * rd, ki, kd, prgb + 3 * r, tau, hysteresis);
+    }
+  }
+  if (counts) {
+    counts->bin_ties += local.bin_ties;
+    counts->bin_mismatch += local.bin_mismatch;
+  }
 }
 
 /* Change detection, second frame of each pair (Sec. 4.1.4, 4.1.5, 4.4):
@@ -1056,15 +1129,7 @@ static void probe_frame_one(const orc_scene* s, const orc_grid* g, int32_t probe
         gd[3 * k + 2] += w * tau * tau;
       }
     } else {
-      /* irradiance texel: radiance sample */
-      double ai = orc_blend_alpha(irr_n[ki], hyst);
-      for (int c = 0; c < 3; ++c) irr[3 * ki + c] += ai * (ray.rgb[c] - irr[3 * ki + c]);
-      if (irr_n[ki] < 255) irr_n[ki]++;
-      /* depth texel: first two moments of the normalised distance (Sec. 4.6) */
-      double ad = orc_blend_alpha(dep_n[kd], hyst);
-      dep[2 * kd + 0] += ad * (tau - dep[2 * kd + 0]);
-      dep[2 * kd + 1] += ad * (tau * tau - dep[2 * kd + 1]);
-      if (dep_n[kd] < 255) dep_n[kd]++;
+      blend_sample(irr, irr_n, dep, dep_n, ki, kd, ray.rgb, tau, hyst);
     }
     if (rays) {
       rays[4 * j + 0] = ray.rgb[0];

@@ -133,10 +133,25 @@ void orc_grid_init(orc_grid* g, const float origin[3], const float spacing[3], c
 void orc_probe_pos(const orc_grid* g, int32_t i, double p[3]);
 
 /* ---- detection (O5): pilots for every probe, Q10 codes with ties.
- * hint_qv/hint_qr may be NULL; otherwise tied codes adopt the hint. */
+ * hint_qv/hint_qr may be NULL; otherwise tied codes adopt the hint.
+ * hint_tri/hint_shadow [P*8] may be NULL; otherwise the pilot rays adopt the
+ * tied hit and shadow decisions (as probe rays do). prgb [P*8*3] and pt
+ * [P*8], if not NULL, receive each pilot's radiance and hit distance. */
 void orc_pilots(const orc_scene* s, const orc_grid* g, uint64_t seed, int32_t frame,
                 double beta, const orc_tol* tol, const uint16_t* hint_qv, const uint16_t* hint_qr,
-                uint16_t* qv, uint16_t* qr, orc_counts* counts);
+                const int32_t* hint_tri, const uint8_t* hint_shadow,
+                uint16_t* qv, uint16_t* qr, double* prgb, double* pt, orc_counts* counts);
+/* ---- pilot reuse (Sec. 4.4): the 8 pilot samples of each listed probe
+ * update its caches like probe rays, in octant order: pilot k's radiance
+ * (prgb, from orc_pilots) into the irradiance texel of its direction, its
+ * distance (pt) into the depth texel of its direction. State arrays are
+ * indexed by position in the list as for orc_probes_frame; hint_ibin /
+ * hint_dbin [P*8] may be NULL. */
+void orc_pilot_blend(const orc_grid* g, uint64_t seed, int32_t frame, int32_t count, const int32_t* probes,
+                     const orc_tol* tol, int32_t irr_r, int32_t dep_r, double hysteresis, double tau_max,
+                     const double* prgb, const double* pt, const uint16_t* hint_ibin,
+                     const uint16_t* hint_dbin, double* irr, uint8_t* irr_n, double* dep, uint8_t* dep_n,
+                     orc_counts* counts);
 /* state arrays are [P*8]; score is [P]. Updates the state for frame t. */
 void orc_detect(const orc_grid* g, int32_t frame, int32_t theta, int32_t mu,
                 const uint16_t* qv, const uint16_t* qr, uint16_t* qv_prev, uint16_t* qr_prev,

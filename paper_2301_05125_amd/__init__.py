@@ -76,7 +76,7 @@ class UpdateParams(C.Structure):
                 ("chain_reset", C.c_int32), ("dyn_chain_count", C.c_int32),
                 ("dyn_chain_steps", C.c_int32), ("dyn_chain_burn_in", C.c_int32),
                 ("dyn_sigma_pos", C.c_float), ("dyn_sigma_dir", C.c_float),
-                ("dyn_hysteresis", C.c_float)]
+                ("dyn_hysteresis", C.c_float), ("pilot_reuse", C.c_int32)]
 
 
 class UpdateStats(C.Structure):
@@ -103,7 +103,8 @@ class ProbeReadback(C.Structure):
         [("num_samples", C.c_int64), ("num_chains", C.c_int32), ("chain_steps", C.c_int32)] + \
         [(n, C.c_void_p) for n in ("dyn_mark", "dyn_target", "dyn_state", "dyn_ray_offsets", "dyn_accept")] + \
         [("num_dyn_rays", C.c_int64), ("num_dyn_chains", C.c_int32), ("dyn_chain_steps", C.c_int32),
-         ("proxy_dims", C.c_int32 * 3), ("reserved", C.c_int32)]
+         ("proxy_dims", C.c_int32 * 3), ("reserved", C.c_int32)] + \
+        [(n, C.c_void_p) for n in ("pilot_record", "pilot_tri", "pilot_shadow", "pilot_ibin", "pilot_dbin")]
 
 
 class TraceWork(C.Structure):
@@ -337,9 +338,10 @@ class Volume:
             self._nt = s.num_triangles
 
     def update_probes(self, frame, adaptive=False, budget=0, n_min=8, n_max=2048, n_uniform=64,
-                      beta=5.0, mu=2, theta=8, sync=True) -> dict:
+                      beta=5.0, mu=2, theta=8, sync=True, pilot_reuse=False) -> dict:
         p = UpdateParams(int(frame), 1 if adaptive else 0, int(budget), int(n_min), int(n_max),
                          int(n_uniform), float(beta), int(mu), int(theta), 1 if sync else 0)
+        p.pilot_reuse = 1 if pilot_reuse else 0
         st = UpdateStats()
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
@@ -357,7 +359,7 @@ class Volume:
     def update_chains(self, frame, chains, steps, burn_in, sigma_pos=0.5, sigma_dir=CHAIN_SIGMA_DIR,
                       reset=False, beta=5.0, sync=True, mu=2, theta=8, dyn_chains=0, dyn_steps=0,
                       dyn_burn_in=0, dyn_sigma_pos=1.5, dyn_sigma_dir=6 * CHAIN_SIGMA_DIR,
-                      dyn_hysteresis=0.91) -> dict:
+                      dyn_hysteresis=0.91, pilot_reuse=False) -> dict:
         """One chain frame (ADGI_MODE_CHAIN): pilots and detection, `chains`
         static Metropolis chains of `steps` steps each (the first burn_in + 1
         emit nothing), two rays per sample; with dyn_chains > 0 also the
@@ -366,6 +368,7 @@ class Volume:
         p = self._chain_params(frame, chains, steps, burn_in, sigma_pos, sigma_dir, reset, beta, sync, mu,
                                theta, dyn_chains, dyn_steps, dyn_burn_in, dyn_sigma_pos, dyn_sigma_dir,
                                dyn_hysteresis)
+        p.pilot_reuse = 1 if pilot_reuse else 0
         st = UpdateStats()
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
@@ -430,13 +433,18 @@ class Volume:
                    "shadow_bits": np.zeros(max(R, 1), np.uint8),
                    "irr_bin": np.zeros(max(R, 1), np.uint16),
                    "depth_bin": np.zeros(max(R, 1), np.uint16),
-                   "ray_record": np.zeros((max(R, 1), 4), np.float32)}
+                   "ray_record": np.zeros((max(R, 1), 4), np.float32),
+                   "pilot_record": np.zeros((P * 8, 4), np.float32),
+                   "pilot_tri": np.zeros(P * 8, np.int32),
+                   "pilot_shadow": np.zeros(P * 8, np.uint8),
+                   "pilot_ibin": np.zeros(P * 8, np.uint16),
+                   "pilot_dbin": np.zeros(P * 8, np.uint16)}
             rb2 = ProbeReadback()
             for k, a in dbg.items():
                 setattr(rb2, k, _ptr(a))
             _check(lib().adgi_read_probes(self.h, C.byref(rb2)))
             for k, a in dbg.items():
-                out[k] = a[:R]
+                out[k] = a if k.startswith("pilot_") else a[:R]
         out["num_rays"] = int(rb.num_rays)
         return out
 

@@ -78,7 +78,8 @@ struct FrameParams {
   float dyn_sp[3];
   float dyn_sd;
   float dyn_one_minus_h;      // 1 - h_dyn: the dynamic updates' step floor
-  int32_t pad[3];
+  int32_t pilot_reuse;        // this frame's pilot samples also update the caches
+  int32_t pad[2];
 };
 
 // Texel-centre ray tables (dynamic updates): the interior texels of the
@@ -167,6 +168,10 @@ struct VolumeView {
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t
+  float4* pilot_rec;          // [8P] pilot radiance RGB, t (pilot reuse frames)
+  uint32_t* pilot_bins;       // [8P] pilot irradiance texel | depth texel << 16
+  int32_t* dbg_ptri;          // [8P] pilot closest triangle (debug)
+  uint8_t* dbg_pshadow;       // [8P] pilot shadow bits (debug)
   uint32_t* ray_bins;         // [max_rays] probe rays: interior irradiance texel
                               // | interior depth texel << 16 of the direction
   // lit hits waiting for their shadow rays (the pilot and probe passes of a

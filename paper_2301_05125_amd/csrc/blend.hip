@@ -400,6 +400,8 @@ struct ProbeRegs {
   float4 rec;
   uint32_t bins;  // budgeted frames: irradiance texel | depth texel << 16
   float2 uv;      // chain frames: the sample's octahedral coordinates
+  float4 prec;    // pilot reuse: pilot (lane < 8) record and texel indices
+  uint32_t pbins;
 };
 
 // Record and texel indices (or chain uv) of sample j of the list at off.
@@ -417,7 +419,7 @@ __device__ __forceinline__ void load_sample(const VolumeView& v, uint32_t off, u
 
 template <int RI, int RD, bool HALF, bool CHAIN>
 __device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& io, int i, uint32_t off,
-                                           uint32_t n, ProbeRegs<RI, RD, HALF, CHAIN>& g) {
+                                           uint32_t n, bool reuse, ProbeRegs<RI, RD, HALF, CHAIN>& g) {
   using S = Store<HALF>;
   using T = typename S::T;
   using W = WaveTile<RI, RD>;
@@ -451,6 +453,10 @@ __device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& i
   for (int s = 0; s < G::CD; ++s)
     if (lane + 64 * s < ND / 4) g.cd[s] = nd_in[lane + 64 * s];
   if ((uint32_t)lane < n) load_sample<CHAIN>(v, off, (uint32_t)lane, g.rec, g.bins, g.uv);
+  if (reuse && lane < 8) {
+    g.prec = v.pilot_rec[8 * (size_t)i + lane];
+    g.pbins = v.pilot_bins[8 * (size_t)i + lane];
+  }
 }
 
 template <int RI, int RD, bool HALF, bool CHAIN>
@@ -500,7 +506,8 @@ __device__ __forceinline__ void stage_probe(const ProbeRegs<RI, RD, HALF, CHAIN>
 // behind every load of this one and overlap the rest of its work.
 template <int RI, int RD, bool HALF, bool CHAIN, typename F>
 __device__ __forceinline__ void blend_probe_samples(const VolumeView& v, int i, uint32_t off, uint32_t n,
-                                                    float4 rec0, uint32_t bins0, float2 uv0, uint8_t* wbase,
+                                                    float4 rec0, uint32_t bins0, float2 uv0, bool reuse,
+                                                    float4 prec, uint32_t pbins, uint8_t* wbase,
                                                     const float* alpha, const float* alpha_dyn,
                                                     F&& at_last_chunk) {
   using W = WaveTile<RI, RD>;
@@ -511,6 +518,50 @@ __device__ __forceinline__ void blend_probe_samples(const VolumeView& v, int i, 
   const FrameParams& fp = *v.fp;
   const float inv_s = 1.0f / v.s_diag;
   const float tmax = v.tau_max;
+  uint32_t* nI = (uint32_t*)(sI + 3 * NI);
+  uint32_t* nD = (uint32_t*)(sD + 2 * ND);
+  // One chunk of up to 64 samples, one per lane (act), each with its record
+  // and its texel indices.
+  auto apply = [&](const float4 cur, const uint32_t cbin, const bool act) {
+    const uint32_t bI = cbin & 0xFFFFu, bD = cbin >> 16;
+    // rank of this sample among the chunk's samples of the same texel, and
+    // their number
+    const uint64_t live = ballot(act);
+    const uint64_t mI = match_key<W::BI>(bI, live), mD = match_key<W::BD>(bD, live);
+    const uint32_t rI = lanes_below(mI), rD = lanes_below(mD);
+    // the sample's count N before it is applied is the texel's count before
+    // the chunk plus its rank (saturating at 255), so its step weight is known
+    // before any sample of the chunk is applied; the last sample of each
+    // texel writes the texel's new count
+    float aI = 0.f, aD = 0.f;
+    if (act) {
+      const uint32_t n0I = nI[bI], n0D = nD[bD];
+      aI = alpha[min(n0I + rI, 255u)];
+      aD = alpha[min(n0D + rD, 255u)];
+      wave_sync();
+      if (rI + 1u == (uint32_t)__popcll(mI)) nI[bI] = min(n0I + rI + 1u, 255u);
+      if (rD + 1u == (uint32_t)__popcll(mD)) nD[bD] = min(n0D + rD + 1u, 255u);
+    }
+    const float tau = fminf(cur.w * inv_s, tmax);
+    const float tau2 = tau * tau;
+    const uint32_t rmax = act ? max(rI, rD) : 0u;
+    for (uint32_t r = 0;; ++r) {
+      if (act && rI == r) {
+        sI[bI] = fmaf(aI, cur.x - sI[bI], sI[bI]);
+        sI[NI + bI] = fmaf(aI, cur.y - sI[NI + bI], sI[NI + bI]);
+        sI[2 * NI + bI] = fmaf(aI, cur.z - sI[2 * NI + bI], sI[2 * NI + bI]);
+      }
+      if (act && rD == r) {
+        sD[bD] = fmaf(aD, tau - sD[bD], sD[bD]);
+        sD[ND + bD] = fmaf(aD, tau2 - sD[ND + bD], sD[ND + bD]);
+      }
+      wave_sync();
+      if (ballot(rmax > r) == 0ull) break;
+    }
+  };
+  // pilot reuse (Sec. 4.4): the probe's 8 pilot samples first, in octant
+  // order, each into the texels of its own direction
+  if (reuse) apply(prec, pbins, lane < 8);
   float4 nxt = rec0;
   uint32_t nbin = bins0;
   float2 nuv = uv0;
@@ -538,43 +589,7 @@ __device__ __forceinline__ void blend_probe_samples(const VolumeView& v, int i, 
         v.dbg_dbin[2 * (size_t)(off + j) + 1] = (uint16_t)bD;
       }
     }
-    const uint32_t bI = cbin & 0xFFFFu, bD = cbin >> 16;
-    // rank of this sample among the chunk's samples of the same texel, and
-    // their number
-    const uint64_t live = ballot(act);
-    const uint64_t mI = match_key<W::BI>(bI, live), mD = match_key<W::BD>(bD, live);
-    const uint32_t rI = lanes_below(mI), rD = lanes_below(mD);
-    // the sample's count N before it is applied is the texel's count before
-    // the chunk plus its rank (saturating at 255), so its step weight is known
-    // before any sample of the chunk is applied; the last sample of each
-    // texel writes the texel's new count
-    uint32_t* nI = (uint32_t*)(sI + 3 * NI);
-    uint32_t* nD = (uint32_t*)(sD + 2 * ND);
-    float aI = 0.f, aD = 0.f;
-    if (act) {
-      const uint32_t n0I = nI[bI], n0D = nD[bD];
-      aI = alpha[min(n0I + rI, 255u)];
-      aD = alpha[min(n0D + rD, 255u)];
-      wave_sync();
-      if (rI + 1u == (uint32_t)__popcll(mI)) nI[bI] = min(n0I + rI + 1u, 255u);
-      if (rD + 1u == (uint32_t)__popcll(mD)) nD[bD] = min(n0D + rD + 1u, 255u);
-    }
-    const float tau = fminf(cur.w * inv_s, tmax);
-    const float tau2 = tau * tau;
-    const uint32_t rmax = act ? max(rI, rD) : 0u;
-    for (uint32_t r = 0;; ++r) {
-      if (act && rI == r) {
-        sI[bI] = fmaf(aI, cur.x - sI[bI], sI[bI]);
-        sI[NI + bI] = fmaf(aI, cur.y - sI[NI + bI], sI[NI + bI]);
-        sI[2 * NI + bI] = fmaf(aI, cur.z - sI[2 * NI + bI], sI[2 * NI + bI]);
-      }
-      if (act && rD == r) {
-        sD[bD] = fmaf(aD, tau - sD[bD], sD[bD]);
-        sD[ND + bD] = fmaf(aD, tau2 - sD[ND + bD], sD[ND + bD]);
-      }
-      wave_sync();
-      if (ballot(rmax > r) == 0ull) break;
-    }
+    apply(cur, cbin, act);
   }
   if (CHAIN && fp.dyn_chains > 0) {
     // dynamic updates after the static samples (Sec. 4.9): every texel of a
@@ -631,15 +646,14 @@ __device__ __forceinline__ void store_probe(const BlendIO& io, int i, const uint
 }
 
 // One wave per probe, probes taken round-robin over all waves of the grid in
-// the allocation's order (most chunks first). Software-pipelined: a wave
-// keeps the probe index and ray range of its next two probes in scalar
-// registers (the probe index two ahead, loaded while it works on a probe, and
-// the ray range of the next one, loaded at the end of the probe before), and
-// issues the loads of its next probe's texels, counts and first 64 records
-// before it works on the current one, so a probe waits for memory once and
-// that wait overlaps another probe's work. order and offsets are passed
-// apart as restrict pointers (no store of the kernel aliases them), which
-// lets their wave-uniform loads go through the scalar cache.
+// the allocation's order (most chunks first). A wave first reads the probe
+// index and ray range of each of its probes (up to 64 at a time, one per
+// lane: two memory round trips for all of them), then takes them from its
+// lanes' registers, so each probe waits on memory once, for its texels,
+// counts and first records. (Also loading the next probe's texels while
+// the current one is applied measured no faster and held 18 more registers.)
+// order and offsets are passed apart as restrict pointers (no store of the
+// kernel aliases them).
 template <int RI, int RD, bool HALF, bool CHAIN>
 __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO io,
                                                          const int32_t* __restrict__ order,
@@ -660,39 +674,37 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
   const uint32_t P = (uint32_t)v.P;
-  uint32_t q = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  if (q >= P) return;
-  G g;
-  int i = order[q];
-  uint32_t off = offsets[i], n = offsets[i + 1] - off;
-  load_probe<RI, RD, HALF, CHAIN>(v, io, i, off, n, g);
-  uint32_t q1 = q + waves;
-  int i1 = q1 < P ? order[q1] : 0;
-  uint32_t off1 = q1 < P ? offsets[i1] : 0u;
-  uint32_t n1 = q1 < P ? offsets[i1 + 1] - off1 : 0u;
-  while (q < P) {
-    stage_probe<RI, RD, HALF, CHAIN>(g, wbase);
-    const float4 rec0 = g.rec;
-    const uint32_t bins0 = g.bins;
-    const float2 uv0 = g.uv;
-    wave_sync();
-    const uint32_t q2 = q1 + waves;
-    const int i2 = q2 < P ? order[q2] : 0;
-    if (q1 < P) load_probe<RI, RD, HALF, CHAIN>(v, io, i1, off1, n1, g);
-    blend_probe_samples<RI, RD, HALF, CHAIN>(v, i, off, n, rec0, bins0, uv0, wbase, alpha, alpha_dyn,
-                                             []() {});
-    store_probe<RI, RD, HALF>(io, i, wbase, tab);
-    const uint32_t off2 = q2 < P ? offsets[i2] : 0u;
-    const uint32_t n2 = q2 < P ? offsets[i2 + 1] - off2 : 0u;
-    wave_sync();
-    q = q1;
-    i = i1;
-    off = off1;
-    n = n1;
-    q1 = q2;
-    i1 = i2;
-    off1 = off2;
-    n1 = n2;
+  const int lane = threadIdx.x & 63;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (first >= P) return;
+  const uint32_t nq = (P - first + waves - 1u) / waves;  // this wave's probes
+  // read once: a load in the loop would wait behind the probe's loads
+  const bool reuse = v.fp->pilot_reuse != 0;
+  for (uint32_t base = 0; base < nq; base += 64u) {
+    const uint32_t k = base + (uint32_t)lane;
+    int ik = 0;
+    uint32_t ok = 0u, ek = 0u;
+    if (k < nq) {
+      ik = order[first + k * waves];
+      ok = offsets[ik];
+      ek = offsets[ik + 1];
+    }
+    const uint32_t cnt = min(64u, nq - base);
+    for (uint32_t kk = 0; kk < cnt; ++kk) {
+      const int i = __builtin_amdgcn_readlane(ik, kk);
+      const uint32_t off = __builtin_amdgcn_readlane(ok, kk);
+      const uint32_t n = __builtin_amdgcn_readlane(ek, kk) - off;
+      {
+        G g;
+        load_probe<RI, RD, HALF, CHAIN>(v, io, i, off, n, reuse, g);
+        stage_probe<RI, RD, HALF, CHAIN>(g, wbase);
+        wave_sync();
+        blend_probe_samples<RI, RD, HALF, CHAIN>(v, i, off, n, g.rec, g.bins, g.uv, reuse, g.prec, g.pbins,
+                                                 wbase, alpha, alpha_dyn, []() {});
+      }
+      store_probe<RI, RD, HALF>(io, i, wbase, tab);
+      wave_sync();
+    }
   }
 }
 

@@ -462,6 +462,11 @@ __device__ __forceinline__ void emit_ray(const VolumeView& v, uint32_t r, float3
       v.dbg_shadow[r] = (uint8_t)bits;
     }
   } else {
+    if (fp.pilot_reuse) v.pilot_rec[r] = make_float4(L.x, L.y, L.z, t);
+    if (fp.debug) {
+      v.dbg_ptri[r] = id;
+      v.dbg_pshadow[r] = (uint8_t)bits;
+    }
     int qv = 0;
     if (t < INFINITY) qv = min(1023, (int)floorf(1024.0f * expf(-2.0f * t / v.s_diag)));
     float lum = 0.2126f * L.x + 0.7152f * L.y + 0.0722f * L.z;
@@ -531,6 +536,10 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
   // probe of the batch's first ray (the same in every lane)
   const int i0 = KIND == KIND_PRIMARY ? probe_of_ray(v.offsets, v.P, b * 64u) : 0;
   if (active) gen_ray<KIND>(v, r, i0, o, d, shade, dst);
+  if (KIND == KIND_PILOT && active && v.fp->pilot_reuse) {
+    const float2 uv = oct_encode(d);
+    v.pilot_bins[r] = oct_bin(uv, v.irr_res - 2) | (oct_bin(uv, v.dep_res - 2) << 16);
+  }
   if (KIND == KIND_PRIMARY && active) {
     // the interior irradiance and depth texels the ray's direction falls in,
     // for the blend (one 4-byte word per ray instead of regenerating the
@@ -586,7 +595,8 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
     const float3 L = miss ? make_float3(sc.sky[0], sc.sky[1], sc.sky[2]) : make_float3(0.f, 0.f, 0.f);
     emit_ray<KIND>(v, dst, L, t, id, 0u);
   } else if (active && v.fp->debug) {
-    v.dbg_tri[dst] = id;
+    if (KIND == KIND_PILOT) v.dbg_ptri[dst] = id;
+    else v.dbg_tri[dst] = id;
   }
 }
 

@@ -747,6 +747,8 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&v.order, (size_t)P * 4},
       {(void**)&v.rec, R * 16},
       {(void**)&v.ray_bins, R * 4},
+      {(void**)&v.pilot_rec, (size_t)P * 8 * 16},
+      {(void**)&v.pilot_bins, (size_t)P * 8 * 4},
       {(void**)&v.hit_pos, std::max(R, (size_t)P * 8) * 16},
       {(void**)&v.hit_nrm, std::max(R, (size_t)P * 8) * 16},
       {(void**)&v.hit_vis, std::max(R, (size_t)P * 8) * 4},
@@ -781,6 +783,8 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   }
   if (dbg) {
     reqs.push_back({(void**)&v.dbg_tri, R * 4});
+    reqs.push_back({(void**)&v.dbg_ptri, (size_t)P * 8 * 4});
+    reqs.push_back({(void**)&v.dbg_pshadow, (size_t)P * 8});
     reqs.push_back({(void**)&v.dbg_shadow, R});
     reqs.push_back({(void**)&v.dbg_ibin, R * 2});
     reqs.push_back({(void**)&v.dbg_dbin, R * 2});
@@ -1234,6 +1238,13 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   const int64_t P = vol->P, cap = vol->desc.max_rays_per_frame;
   const int mode = p->adaptive;
   int64_t samples = 0;
+  if (p->pilot_reuse != 0 && p->pilot_reuse != 1) return fail(ADGI_ERR_INVALID_ARG, "pilot_reuse must be 0 or 1");
+  if (p->pilot_reuse && mode != ADGI_MODE_UNIFORM) {
+    if (vol->desc.storage == ADGI_PACKED || vol->desc.blend_mode != ADGI_BLEND_SAMPLE)
+      return fail(ADGI_ERR_INVALID_ARG, "pilot_reuse needs ADGI_FP32 / ADGI_FP16 storage and the per-sample blend");
+    if (vol->tun.blend_chunk != 0)
+      return fail(ADGI_ERR_INVALID_ARG, "pilot_reuse needs the wave blend (tuning blend_chunk 0)");
+  }
   if (mode == ADGI_MODE_CHAIN) {
     if (vol->desc.max_chains < 1) return fail(ADGI_ERR_INVALID_ARG, "the volume was created with max_chains = 0");
     if (vol->desc.blend_mode != ADGI_BLEND_SAMPLE)
@@ -1307,6 +1318,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   fp.theta = p->theta;
   fp.beta = p->beta;
   fp.debug = (vol->desc.flags & ADGI_DEBUG_ARRAYS) ? 1 : 0;
+  fp.pilot_reuse = (p->pilot_reuse && mode != ADGI_MODE_UNIFORM && (p->frame & 1) == 0) ? 1 : 0;
   if (mode == ADGI_MODE_CHAIN) {
     fp.chains = p->chain_count;
     fp.chain_steps = p->chain_steps;
@@ -1475,6 +1487,19 @@ adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
     if (out->irr_bin) HIP_TRY(vol, hipMemcpy(out->irr_bin, vol->v.dbg_ibin, R * 2, hipMemcpyDeviceToHost));
     if (out->depth_bin) HIP_TRY(vol, hipMemcpy(out->depth_bin, vol->v.dbg_dbin, R * 2, hipMemcpyDeviceToHost));
     if (out->ray_record) HIP_TRY(vol, hipMemcpy(out->ray_record, vol->v.rec, R * 16, hipMemcpyDeviceToHost));
+  }
+  if (!dbg && (out->pilot_tri || out->pilot_shadow || out->pilot_ibin || out->pilot_dbin || out->pilot_record))
+    return fail(ADGI_ERR_INVALID_ARG, "pilot debug arrays need ADGI_DEBUG_ARRAYS");
+  if (out->pilot_tri) HIP_TRY(vol, hipMemcpy(out->pilot_tri, vol->v.dbg_ptri, P * 32, hipMemcpyDeviceToHost));
+  if (out->pilot_shadow) HIP_TRY(vol, hipMemcpy(out->pilot_shadow, vol->v.dbg_pshadow, P * 8, hipMemcpyDeviceToHost));
+  if (out->pilot_record) HIP_TRY(vol, hipMemcpy(out->pilot_record, vol->v.pilot_rec, P * 128, hipMemcpyDeviceToHost));
+  if (out->pilot_ibin || out->pilot_dbin) {
+    std::vector<uint32_t> pb(P * 8);
+    HIP_TRY(vol, hipMemcpy(pb.data(), vol->v.pilot_bins, P * 32, hipMemcpyDeviceToHost));
+    for (size_t r = 0; r < P * 8; ++r) {
+      if (out->pilot_ibin) out->pilot_ibin[r] = (uint16_t)(pb[r] & 0xFFFFu);
+      if (out->pilot_dbin) out->pilot_dbin[r] = (uint16_t)(pb[r] >> 16);
+    }
   }
   const int qs = vol->last_frame >= 0 ? (vol->last_frame & 1) : 0;
   if (out->q10_vis) HIP_TRY(vol, hipMemcpy(out->q10_vis, vol->v.qv[qs], P * 16, hipMemcpyDeviceToHost));

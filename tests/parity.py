@@ -65,6 +65,36 @@ RAY_DX_REL = 1e-6
 RAY_NORMAL_EPS = 1e-6
 
 
+# Hit distance bar: 1e-5 relative plus the same glancing-angle slide of the
+# hit point, dt = 1e-6 (|p|_inf + t) / |n.d|.
+RAY_T_BASE = 1e-5
+
+
+def probe_positions(scene, sel) -> np.ndarray:
+    dims = scene.grid_dims.astype(np.int64)
+    org = scene.grid_origin.astype(np.float64)
+    spc = scene.grid_spacing.astype(np.float64)
+    sel = np.asarray(sel, np.int64)
+    pidx = np.stack([sel % dims[0], (sel // dims[0]) % dims[1], sel // (dims[0] * dims[1])], axis=1)
+    return org + pidx * spc
+
+
+def ray_t_bar(scene, frame, p, d, t, tri) -> np.ndarray:
+    """Relative hit-distance bar of rays from p along unit d that hit
+    triangle tri at distance t (misses: the base bar)."""
+    bar = np.full(t.shape[0], RAY_T_BASE)
+    hit = (tri >= 0) & np.isfinite(t) & (t > 0)
+    if not hit.any():
+        return bar
+    V = scene.positions_at(frame).astype(np.float64)
+    T = scene.indices[tri[hit]]
+    nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    cos_in = np.maximum(np.abs(np.einsum("ij,ij->i", nrm, d[hit])), 1e-3)
+    bar[hit] += RAY_DX_REL * (np.abs(p[hit]).max(axis=1) + t[hit]) / (cos_in * t[hit])
+    return bar
+
+
 def ray_rgb_bar(scene, frame, sel, n_sel, R, o, tri, shadow) -> np.ndarray:
     """Relative radiance bar of every traced ray of the tracked probes (the
     oracle's ray order: probe by probe, rays in index order)."""
@@ -127,7 +157,8 @@ def gpu_scene_update(vol, scene, frame):
 def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget: int = 0,
                  n_min: int = 8, n_max: int = 2048, probes=None, storage=adgi.ADGI_FP32,
                  seed: int = 0x5EED, max_rays=None, tuning=None, check_rays: bool = True,
-                 use_bvh: bool = True, fp64_twin: bool = False, gather: bool = False) -> dict:
+                 use_bvh: bool = True, fp64_twin: bool = False, gather: bool = False,
+                 pilot_reuse: bool = False) -> dict:
     """``fp64_twin`` also runs an oracle that keeps its texels in FP64 (no
     binary16 rounding at the frame store), fed the same tie decisions, and
     returns per-texel error distributions against it."""
@@ -163,21 +194,45 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
         if f > 0:
             gpu_scene_update(vol, scene, f)
         st = vol.update_probes(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
-                               n_uniform=n_uniform, sync=True)
+                               n_uniform=n_uniform, sync=True, pilot_reuse=pilot_reuse)
         rb = vol.read_probes(texels=True, debug=True)
         R = oracle.frame_rotation(seed, f).reshape(9)
         if not np.array_equal(R, rb["frame_rotation"]):
             res["rotation_mismatch"] += 1
         hints = {"hit_tri": rb["hit_tri"], "shadow_bits": rb["shadow_bits"],
                  "irr_bin": rb["irr_bin"], "depth_bin": rb["depth_bin"],
-                 "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
+                 "qv": rb["q10_vis"], "qr": rb["q10_rad"],
+                 "pilot_tri": rb["pilot_tri"], "pilot_shadow": rb["pilot_shadow"]}
+        if pilot_reuse and f % 2 == 0:
+            hints.update(pilot_ibin=rb["pilot_ibin"], pilot_dbin=rb["pilot_dbin"])
         if gather:  # the gather blend takes every texel; no bin decisions
             del hints["irr_bin"], hints["depth_bin"]
         out = ora.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
-                         n_uniform=n_uniform, hints=hints, keep_rays=check_rays)
+                         n_uniform=n_uniform, hints=hints, keep_rays=check_rays, pilot_reuse=pilot_reuse)
         if twin is not None:
             twin.update(f, adaptive=adaptive, budget=budget, n_min=n_min, n_max=n_max,
-                        n_uniform=n_uniform, hints=hints)
+                        n_uniform=n_uniform, hints=hints, pilot_reuse=pilot_reuse)
+        if adaptive and pilot_reuse and f % 2 == 0:
+            # the reused pilot records: hit distance and radiance per pilot
+            # (the oracle adopted the GPU's pilot hit decisions at ties; any
+            # other disagreement is a counted hit mismatch)
+            # (tracked probes' pilots)
+            ridx = (8 * np.asarray(sel, np.int64)[:, None] + np.arange(8)[None, :]).reshape(-1)
+            pr = rb["pilot_record"].astype(np.float64)[ridx]
+            ot, gt = out["pilot_t"][ridx], pr[:, 3]
+            miss = np.isinf(ot) | np.isinf(gt)
+            res["pilot_miss_mismatch"] = res.get("pilot_miss_mismatch", 0) + \
+                int(np.count_nonzero(np.isinf(ot) != np.isinf(gt)))
+            et = np.abs(np.where(miss, 0.0, gt) - np.where(miss, 0.0, ot)) / np.maximum(np.abs(np.where(miss, 1.0, ot)), 1e-8)
+            res["max_rel_pilot_t"] = max(res.get("max_rel_pilot_t", 0.0), float(et.max(initial=0.0)))
+            pp = np.repeat(probe_positions(scene, sel), 8, axis=0)
+            pd = np.array([oracle.pilot_dir(seed, int(r) // 8, int(r) % 8, f // 2) for r in ridx])
+            tbar = ray_t_bar(scene, f, pp, pd, ot, rb["pilot_tri"][ridx])
+            res["pilot_t_bar_excess"] = res.get("pilot_t_bar_excess", 0) + int(np.count_nonzero(et > tbar))
+            eg = np.abs(pr[:, :3] - out["pilot_rgb"][ridx]).max(axis=1) / \
+                np.maximum(np.abs(out["pilot_rgb"][ridx]).max(axis=1), 1e-6)
+            res["max_rel_pilot_rgb"] = max(res.get("max_rel_pilot_rgb", 0.0), float(eg.max(initial=0.0)))
+            res["pilot_samples"] = res.get("pilot_samples", 0) + int(len(sel) * 8)
         c = out["counts"]
         mism = c["hit_mismatch"] + c["shadow_mismatch"] + c["bin_mismatch"] + c["q10_mismatch"]
         if adaptive:
@@ -259,6 +314,10 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
                 res["max_ray_over_bar"] = max(res["max_ray_over_bar"], float((e / bar).max()))
             et = np.where(same, np.abs(gt - ot) / den_t, 0.0)
             res["max_rel_t"] = max(res.get("max_rel_t", 0.0), float(et.max(initial=0.0)))
+            pr = np.repeat(probe_positions(scene, sel), np.asarray(n_sel, np.int64), axis=0)
+            dr = np.concatenate([oracle.sf_dirs(int(k), out["R"]) if k else np.zeros((0, 3)) for k in n_sel])
+            tbar = ray_t_bar(scene, f, pr, dr, np.where(miss_o, np.inf, o[:, 3]), out["tri"])
+            res["t_bar_excess"] = res.get("t_bar_excess", 0) + int(np.count_nonzero(et > tbar))
             k = int(np.argmax(e)) if e.size else 0
             if e.size and e[k] > res["max_rel_ray"]:
                 res["max_rel_ray"] = float(e[k])
@@ -294,7 +353,7 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
                        sigma_pos: float = 0.5, warm_uniform: int = 2, n_uniform: int = 64,
                        storage=adgi.ADGI_FP32, seed: int = 0x5EED, tuning=None, dyn_chains: int = 0,
                        dyn_steps: int = 16, dyn_burn_in: int = 3, dyn_hysteresis: float = 0.91,
-                       max_rays=None) -> dict:
+                       max_rays=None, pilot_reuse: bool = False) -> dict:
     """Chain frames (ADGI_MODE_CHAIN) in lockstep with the oracle's static
     Metropolis sampler, after ``warm_uniform`` uniform frames that give the
     guide a previous irradiance. Every probe is tracked (the guide reads any
@@ -336,7 +395,7 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
         if chain:
             st = vol.update_chains(f, chains, steps, burn_in, sigma_pos=sigma_pos, sync=True,
                                    dyn_chains=dyn_chains, dyn_steps=dyn_steps, dyn_burn_in=dyn_burn_in,
-                                   dyn_hysteresis=dyn_hysteresis)
+                                   dyn_hysteresis=dyn_hysteresis, pilot_reuse=pilot_reuse)
         else:
             st = vol.update_probes(f, adaptive=False, n_uniform=n_uniform, sync=True)
         rb = vol.read_probes(texels=True, debug=True)
@@ -344,12 +403,16 @@ def run_chain_lockstep(scene, frames: int, chains: int, steps: int, burn_in: int
                  "irr_bin": rb["irr_bin"], "depth_bin": rb["depth_bin"],
                  "qv": rb["q10_vis"], "qr": rb["q10_rad"]}
         if chain:
+            hints.update(pilot_tri=rb["pilot_tri"], pilot_shadow=rb["pilot_shadow"])
+            if pilot_reuse and f % 2 == 0:
+                hints.update(pilot_ibin=rb["pilot_ibin"], pilot_dbin=rb["pilot_dbin"])
             hints["accept"] = rb["chain_accept"].reshape(-1)
             if dyn_chains:
                 hints["dyn_accept"] = rb["dyn_accept"].reshape(-1)
             out = ora.chain_update(f, cp, state, init=(f == warm_uniform), hints=hints, dyn=dp,
                                    dyn_state=dstate[:dyn_chains] if dyn_chains else None,
-                                   dyn_init=(f == warm_uniform), h_dyn=dyn_hysteresis)
+                                   dyn_init=(f == warm_uniform), h_dyn=dyn_hysteresis,
+                                   pilot_reuse=pilot_reuse)
             if dyn_chains:
                 res["F_mismatch"] += int(np.count_nonzero(
                     out["F"].astype(np.float32) != rb["dyn_target"].reshape(-1)))

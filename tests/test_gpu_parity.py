@@ -11,10 +11,10 @@ from tests.parity import run_lockstep
 pytestmark = pytest.mark.gpu
 
 
-# Per-ray radiance: 1e-5 relative plus a grazing term derived from the
-# FP32/FP64 hit-point and normal difference (tests/parity.py, ray_rgb_bar);
-# every ray must sit under its own bar. Hit distances: 1e-4 relative.
-RAY_T_TOL = 1e-4
+# Per-ray radiance and hit distance: 1e-5 relative plus a glancing-angle
+# term derived from the FP32/FP64 hit-point and normal difference
+# (tests/parity.py, ray_rgb_bar and ray_t_bar); every ray must sit under its
+# own bars.
 
 # Caps on the share of decisions the oracle flags as ties (and adopts from
 # the GPU): a systematic GPU error at triangle edges, shadow boundaries,
@@ -35,7 +35,7 @@ def _assert_ties(res, hit=HIT_TIE_CAP, shadow=SHADOW_TIE_CAP, bins=BIN_TIE_CAP, 
 
 def _assert_rays(res):
     assert res["ray_bar_excess"] == 0, res
-    assert res["max_rel_t"] <= RAY_T_TOL, res
+    assert res.get("t_bar_excess", 0) == 0, res
 
 
 def _assert_parity(res, tol=1e-4):
@@ -84,6 +84,39 @@ def test_tunnel_adaptive_lockstep():
                        probes=probes)
     print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
     _assert_parity(res)
+
+
+def test_pilot_reuse_cornell_adaptive():
+    """Pilot reuse (Sec. 4.4): on the first frame of each pilot pair the 8
+    pilot samples of every probe also update its caches, before the probe's
+    own rays; Cornell room with a moving light, six adaptive frames."""
+    sc = scenes.cornell()
+    sc.light_a = np.array([[0.5, 0.95, 0.5]], np.float32)
+    sc.light_b = np.array([[0.2, 0.5, 0.3]], np.float32)
+    sc.frames = 6
+    res = run_lockstep(sc, frames=6, adaptive=True, budget=64 * 40, n_min=8, n_max=200, pilot_reuse=True)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_parity(res)
+    assert res["pilot_samples"] == 3 * 64 * 8 and res["pilot_miss_mismatch"] == 0, res
+    assert res["pilot_t_bar_excess"] == 0, res
+
+
+def test_pilot_reuse_box_field_sampled_fp16():
+    """Pilot reuse on the box field (B = 2^23, refit every frame), 256
+    sampled probes, four frames, FP16 texels against the binary16-emulating
+    oracle."""
+    import paper_2301_05125_amd as adgi
+    sc = scenes.box_field()
+    probes = scenes.sample_probes(sc.num_probes, 256)
+    res = run_lockstep(sc, frames=4, adaptive=True, budget=1 << 23, n_min=8, n_max=2048, probes=probes,
+                       storage=adgi.ADGI_FP16, pilot_reuse=True)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    assert res["mismatches"] == 0 and res["count_mismatch"] == 0 and res["code_mismatch"] == 0, res
+    assert res["alloc_mismatch"] == 0 and res["score_mismatch"] == 0, res
+    assert res["max_rel_irr"] <= 2e-3 and res["max_rel_depth"] <= 2e-3, res
+    assert res["pilot_miss_mismatch"] == 0 and res["pilot_t_bar_excess"] == 0, res
+    _assert_rays(res)
+    _assert_ties(res)
 
 
 def _report(name, res):
@@ -203,6 +236,20 @@ def test_chains_cornell_lockstep():
     assert res["samples"] == 3 * 256 * 48
     assert 0.05 < res["accept_rate"] < 0.95, res
     _report("chains_cornell", res)
+    _assert_chain_parity(res)
+
+
+def test_chains_pilot_reuse_cornell():
+    """Chain frames with pilot reuse: on the first frame of each pilot pair
+    the pilots' samples enter the caches before the chain samples; the guide
+    still reads the previous frame's irradiance."""
+    from tests.parity import run_chain_lockstep
+    sc = scenes.cornell()
+    sc.light_a = np.array([[0.5, 0.95, 0.5]], np.float32)
+    sc.light_b = np.array([[0.25, 0.6, 0.35]], np.float32)
+    sc.frames = 8
+    res = run_chain_lockstep(sc, frames=4, chains=256, steps=48, burn_in=15, pilot_reuse=True)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
     _assert_chain_parity(res)
 
 

@@ -688,6 +688,69 @@ def test_pilot_code_at_distance_zero_saturates():
                           if i // (dims[0] * dims[1]) == z for k in range(4, 8)]) for z in range(3)]
     assert per_layer[0] > per_layer[1] > per_layer[2]
 
+
+def test_pilot_reuse_adds_the_pilot_samples_on_the_first_frame_of_a_pair():
+    """Pilot reuse (Sec. 4.4): on the first frame of each pilot pair every
+    probe's 8 pilot samples also enter its caches, each into the texels of its
+    own direction; on the second frame (same directions) they do not. Over a
+    lit plane the pilot records equal the closed form, and after the first
+    frame every sampled texel holds the exact mean of its samples (pilots and
+    probe rays, at most 33 of them, so the moving average is a running mean)."""
+    sc = _pilot_plane_scene(0.2, (0.9, 0.6, 0.8), [2.5, 1.5, 0.5], light_h=2.0, sky=[0.5, 1.0, 2.0])
+    P = sc.num_probes
+    seed = 41
+    kw = dict(adaptive=True, budget=P * 16, n_min=16, n_max=16, keep_rays=True)
+    vol = oracle.OracleVolume(sc, seed=seed, use_bvh=False)
+    plain = oracle.OracleVolume(sc, seed=seed, use_bvh=False)
+    out = vol.update(0, pilot_reuse=True, **kw)
+    plain.update(0, **kw)
+    # pilot records against the plane's closed form
+    org = sc.grid_origin.astype(np.float64)
+    spc = sc.grid_spacing.astype(np.float64)
+    dims = sc.grid_dims
+    rho = sc.albedo[0].astype(np.float64)
+    I = sc.light_intensity[0].astype(np.float64)
+    lp = sc.light_positions(0)[0].astype(np.float64)
+    pdirs = np.zeros((P, 8, 3))
+    for i in range(P):
+        p = org + np.array([i % dims[0], (i // dims[0]) % dims[1], i // (dims[0] * dims[1])]) * spc
+        for k in range(8):
+            d = oracle.pilot_dir(seed, i, k, 0)
+            pdirs[i, k] = d
+            r = 8 * i + k
+            if d[2] < 0:
+                t = p[2] / -d[2]
+                x = p + t * d
+                ell = lp - x
+                dist = np.linalg.norm(ell)
+                L = rho / math.pi * I * max(0.0, ell[2] / dist) / dist ** 2
+                assert abs(out["pilot_t"][r] - t) <= 1e-12 * t
+            else:
+                L = sc.sky.astype(np.float64)
+                assert np.isinf(out["pilot_t"][r])
+            assert np.allclose(out["pilot_rgb"][r], L, rtol=1e-12, atol=0)
+    # counts: the probe rays' bins plus the pilots' bins
+    for q in range(P):
+        b = out["ray_base"][q]
+        ib = out["irr_bin"][b:b + 16]
+        pib = np.array([oracle.oct_bin(pdirs[q, k], 6)[0] for k in range(8)])
+        exp_n = np.bincount(np.concatenate([ib, pib]), minlength=36)
+        assert np.array_equal(vol.irr_n[q], exp_n)
+        assert np.array_equal(plain.irr_n[q], np.bincount(ib, minlength=36))
+        # each sampled texel: the mean of its samples
+        rgb = np.concatenate([out["rays"][b:b + 16, :3], out["pilot_rgb"][8 * q:8 * q + 8]])
+        bins = np.concatenate([ib, pib])
+        irr = vol.irr[q].reshape(36, 3)
+        for k in np.nonzero(exp_n)[0]:
+            assert np.allclose(irr[k], rgb[bins == k].mean(axis=0), rtol=1e-12, atol=1e-15)
+    # second frame of the pair: the same pilot directions, not reused again
+    n0 = vol.irr_n.copy()
+    out1 = vol.update(1, pilot_reuse=True, **kw)
+    for q in range(P):
+        b = out1["ray_base"][q]
+        inc = np.bincount(out1["irr_bin"][b:b + 16], minlength=36)
+        assert np.array_equal(vol.irr_n[q].astype(int) - n0[q], inc)
+
 # -------------------------------------------------------- O6: allocation
 
 def _brute_lambda(w, E, Bp):
