@@ -75,7 +75,12 @@ typedef enum {
  * arithmetic). Needs tiles 8/16 or 16/16. */
 enum { ADGI_FP32 = 0, ADGI_FP16 = 1, ADGI_PACKED = 2 };
 enum { ADGI_SCENE_REBUILD = 0, ADGI_SCENE_REFIT = 1 };      /* scene update mode */
-enum { ADGI_DEBUG_ARRAYS = 1u << 0 };                        /* volume flags */
+/* Volume flags. ADGI_STATIC_SCRATCH: the volume allocates no frame scratch
+ * (pair lists, hit points, detection sums, allocation partials, blend order,
+ * frame counters: about 60 bytes per ray of max(max_rays_per_frame, 8 P)),
+ * and its frames run only through adgi_update_probes_static; needs
+ * max_chains = 0. */
+enum { ADGI_DEBUG_ARRAYS = 1u << 0, ADGI_STATIC_SCRATCH = 1u << 1 };
 enum { ADGI_MAX_LIGHTS = 8 };
 enum { ADGI_MODE_UNIFORM = 0, ADGI_MODE_ADAPTIVE = 1, ADGI_MODE_CHAIN = 2 };  /* params.adaptive */
 /* Texel update (volume desc): ADGI_BLEND_SAMPLE, the paper's per-sample
@@ -110,7 +115,8 @@ typedef struct {
   float tau_max;              /* depth clamp in units of s ((e^5-1)/15)          */
   int64_t max_rays_per_frame; /* capacity of the per-frame ray buffers, < 2^31   */
   uint64_t seed;              /* seeds the frame rotation and the pilot rays     */
-  uint32_t flags;             /* ADGI_DEBUG_ARRAYS keeps per-ray decisions       */
+  uint32_t flags;             /* ADGI_DEBUG_ARRAYS keeps per-ray decisions;
+                                 ADGI_STATIC_SCRATCH (see the flags above)       */
   int32_t max_chains;         /* 0, or the most Metropolis chains a frame may run
                                  (ADGI_FP32 / ADGI_FP16, tiles 8/16 or 16/16);
                                  allocates the chain state and sample buffers for
@@ -316,6 +322,27 @@ adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* scene);
  * ADGI_ERR_INVALID_ARG; ADGI_ERR_DEVICE when a HIP call fails (sticky). */
 adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* params,
                                adgi_update_stats* stats);
+
+/* For callers that cannot allocate device memory while frames run (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same frame as adgi_update_probes, same arguments and
+ * results, bit for bit, but launched eagerly (no graph is instantiated) and
+ * with the frame scratch taken from one fixed device array of
+ * ADGI_STATIC_SCRATCH_BYTES per GPU, held from the first such call on that
+ * GPU until the process ends. The call allocates nothing; the volume's own
+ * state, records and debug arrays stay where adgi_create_volume put them.
+ * Budgeted and uniform frames only. Every call on one GPU shares that GPU's
+ * array and leaves its contents behind; the library orders these calls on
+ * the GPU one after another (each waits for the previous call's frame), so
+ * calls on different volumes and streams of one GPU do not overlap, which
+ * they must not: two frames in the array at once would race.
+ * Errors: those of adgi_update_probes; ADGI_ERR_INVALID_ARG for chain frames;
+ * ADGI_ERR_BUDGET when the frame's scratch (about 60 bytes per hit slot,
+ * max(B, 8 P) budgeted or P n_uniform uniform, plus about 140 bytes per probe)
+ * exceeds ADGI_STATIC_SCRATCH_BYTES. */
+#define ADGI_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+adgi_status adgi_update_probes_static(adgi_volume* vol, const adgi_update_params* params,
+                                      adgi_update_stats* stats);
 
 /* Wait for the volume's work and copy its probes into caller buffers: the
  * octahedral irradiance and depth-moment tiles a renderer reads at shading

@@ -29,6 +29,8 @@ STATUS = {0: "ADGI_OK", -1: "ADGI_ERR_INVALID_ARG", -2: "ADGI_ERR_OUT_OF_MEMORY"
 ADGI_FP32, ADGI_FP16, ADGI_PACKED = 0, 1, 2
 ADGI_SCENE_REBUILD, ADGI_SCENE_REFIT = 0, 1
 ADGI_DEBUG_ARRAYS = 1
+ADGI_STATIC_SCRATCH = 2
+ADGI_STATIC_SCRATCH_BYTES = 64 << 20
 ADGI_MODE_UNIFORM, ADGI_MODE_ADAPTIVE, ADGI_MODE_CHAIN = 0, 1, 2
 ADGI_BLEND_SAMPLE, ADGI_BLEND_GATHER = 0, 1
 CHAIN_MAX_STEPS = 256
@@ -178,6 +180,7 @@ def lib():
         L.adgi_create_volume.argtypes = [P, P, P, P]
         L.adgi_update_scene.argtypes = [P, P]
         L.adgi_update_probes.argtypes = [P, P, P]
+        L.adgi_update_probes_static.argtypes = [P, P, P]
         L.adgi_read_probes.argtypes = [P, P]
         L.adgi_destroy_volume.argtypes = [P]
         L.adgi_destroy_volume.restype = None
@@ -210,7 +213,7 @@ def lib():
                      "adgi_server_drain", "adgi_server_get_stats", "adgi_server_latencies",
                      "adgi_server_read_stream"):
             getattr(L, name).restype = C.c_int
-        for name in ("adgi_create_volume", "adgi_update_scene", "adgi_update_probes",
+        for name in ("adgi_create_volume", "adgi_update_scene", "adgi_update_probes", "adgi_update_probes_static",
                      "adgi_read_probes", "adgi_get_tuning", "adgi_set_tuning", "adgi_autotune",
                      "adgi_measure_trace_work",
                      "adgi_save_state", "adgi_restore_state"):
@@ -259,9 +262,9 @@ def _torch_allocator():
 def create_volume(origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
                   hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
                   debug=False, stream=None, allocator="torch", max_chains=0,
-                  blend_mode=ADGI_BLEND_SAMPLE) -> "Volume":
+                  blend_mode=ADGI_BLEND_SAMPLE, static_scratch=False) -> "Volume":
     return Volume(origin, spacing, dims, irr_res, depth_res, storage, hysteresis, tau_max,
-                  max_rays_per_frame, seed, debug, stream, allocator, max_chains, blend_mode)
+                  max_rays_per_frame, seed, debug, stream, allocator, max_chains, blend_mode, static_scratch)
 
 
 class Volume:
@@ -270,7 +273,7 @@ class Volume:
     def __init__(self, origin, spacing, dims, irr_res=8, depth_res=16, storage=ADGI_FP32,
                  hysteresis=0.97, tau_max=TAU_MAX, max_rays_per_frame=1 << 20, seed=1,
                  debug=False, stream=None, allocator="torch", max_chains=0,
-                 blend_mode=ADGI_BLEND_SAMPLE):
+                 blend_mode=ADGI_BLEND_SAMPLE, static_scratch=False):
         d = VolumeDesc()
         d.origin[:] = [float(x) for x in origin]
         d.spacing[:] = [float(x) for x in spacing]
@@ -279,7 +282,7 @@ class Volume:
         d.hysteresis, d.tau_max = float(hysteresis), float(tau_max)
         d.max_rays_per_frame = int(max_rays_per_frame)
         d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
-        d.flags = ADGI_DEBUG_ARRAYS if debug else 0
+        d.flags = (ADGI_DEBUG_ARRAYS if debug else 0) | (ADGI_STATIC_SCRATCH if static_scratch else 0)
         d.max_chains = int(max_chains)
         d.blend_mode = int(blend_mode)
         self.desc = d
@@ -344,6 +347,17 @@ class Volume:
         p.pilot_reuse = 1 if pilot_reuse else 0
         st = UpdateStats()
         _check(lib().adgi_update_probes(self.h, C.byref(p), C.byref(st)))
+        return st.as_dict() if sync else {}
+
+    def update_probes_static(self, frame, adaptive=False, budget=0, n_min=8, n_max=2048, n_uniform=64,
+                             beta=5.0, mu=2, theta=8, sync=True, pilot_reuse=False) -> dict:
+        """update_probes with the frame scratch in the library's fixed per-GPU
+        array (no allocation, eager launches); budgeted and uniform frames."""
+        p = UpdateParams(int(frame), 1 if adaptive else 0, int(budget), int(n_min), int(n_max),
+                         int(n_uniform), float(beta), int(mu), int(theta), 1 if sync else 0)
+        p.pilot_reuse = 1 if pilot_reuse else 0
+        st = UpdateStats()
+        _check(lib().adgi_update_probes_static(self.h, C.byref(p), C.byref(st)))
         return st.as_dict() if sync else {}
 
     @staticmethod

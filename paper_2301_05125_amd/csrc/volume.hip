@@ -604,6 +604,33 @@ bool tuning_valid(const adgi_tuning& t) {
 }  // namespace
 
 namespace {
+// The frame scratch: buffers that hold data within one frame only (pair
+// lists, hit points, detection sums, allocation partials, blend order, frame
+// counters, per-ray texel indices). f(&pointer, bytes) is called for each, in
+// a fixed order, for P probes, R probe rays and H hit slots (max(R, 8 P) with
+// pilots).
+template <class F>
+void frame_scratch_each(VolumeView& v, size_t P, size_t R, size_t H, F&& f) {
+  const size_t pb = (P + 255) / 256, nb = (H + 63) / 64;
+  f((void**)&v.stats, sizeof(FrameStats));
+  f((void**)&v.box_a, P * 64);
+  f((void**)&v.box_b, P * 64);
+  f((void**)&v.blk_e, pb * 8);
+  f((void**)&v.blk_el, pb * 4);
+  f((void**)&v.blk_rank, pb * 4);
+  f((void**)&v.blk_off, pb * 4);
+  f((void**)&v.order, P * 4);
+  f((void**)&v.ray_bins, R * 4);
+  f((void**)&v.hit_pos, H * 16);
+  f((void**)&v.hit_nrm, H * 16);
+  f((void**)&v.hit_vis, H * 4);
+  f((void**)&v.hit_dst, H * 4);
+  f((void**)&v.pairs, nb * kPairsPerBatch * 2);
+  f((void**)&v.pair_cnt, nb * 4);
+  f((void**)&v.pair_off, (nb + 1) * 4);
+  f((void**)&v.pair_blk, (nb / kPairScanPer + 1) * 4);
+}
+
 // ---- snapshots
 struct Part {
   void* dev;
@@ -660,7 +687,10 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
     return fail(ADGI_ERR_INVALID_ARG, "tau_max must be finite and > 0");
   if (d->max_rays_per_frame < 1 || d->max_rays_per_frame >= (int64_t)1 << 31)
     return fail(ADGI_ERR_INVALID_ARG, "max_rays_per_frame must be in [1, 2^31)");
-  if (d->flags & ~(uint32_t)ADGI_DEBUG_ARRAYS) return fail(ADGI_ERR_INVALID_ARG, "unknown flags");
+  if (d->flags & ~(uint32_t)(ADGI_DEBUG_ARRAYS | ADGI_STATIC_SCRATCH))
+    return fail(ADGI_ERR_INVALID_ARG, "unknown flags");
+  if ((d->flags & ADGI_STATIC_SCRATCH) && d->max_chains > 0)
+    return fail(ADGI_ERR_INVALID_ARG, "ADGI_STATIC_SCRATCH volumes run no chain frames (max_chains must be 0)");
   if (d->max_chains < 0 || d->max_chains > (1 << 24))
     return fail(ADGI_ERR_INVALID_ARG, "max_chains must be in [0, 2^24]");
   if (d->max_chains > 0 && d->storage == ADGI_PACKED)
@@ -729,36 +759,22 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
       {(void**)&vol->dep_n, (size_t)P * rd * rd},
       {(void**)&v.fp, sizeof(FrameParams)},
       {(void**)&v.scene, sizeof(SceneParams)},
-      {(void**)&v.stats, sizeof(FrameStats)},
       {(void**)&v.qv[0], (size_t)P * 16},
       {(void**)&v.qv[1], (size_t)P * 16},
       {(void**)&v.qr[0], (size_t)P * 16},
       {(void**)&v.qr[1], (size_t)P * 16},
       {(void**)&v.trig, (size_t)P * 64},
-      {(void**)&v.box_a, (size_t)P * 64},
-      {(void**)&v.box_b, (size_t)P * 64},
       {(void**)&v.score, (size_t)P * 8},
       {(void**)&v.n, (size_t)P * 4},
       {(void**)&v.offsets, (size_t)(P + 1) * 4},
-      {(void**)&v.blk_e, (size_t)((P + 255) / 256) * 8},
-      {(void**)&v.blk_el, (size_t)((P + 255) / 256) * 4},
-      {(void**)&v.blk_rank, (size_t)((P + 255) / 256) * 4},
-      {(void**)&v.blk_off, (size_t)((P + 255) / 256) * 4},
-      {(void**)&v.order, (size_t)P * 4},
       {(void**)&v.rec, R * 16},
-      {(void**)&v.ray_bins, R * 4},
       {(void**)&v.pilot_rec, (size_t)P * 8 * 16},
       {(void**)&v.pilot_bins, (size_t)P * 8 * 4},
-      {(void**)&v.hit_pos, std::max(R, (size_t)P * 8) * 16},
-      {(void**)&v.hit_nrm, std::max(R, (size_t)P * 8) * 16},
-      {(void**)&v.hit_vis, std::max(R, (size_t)P * 8) * 4},
-      {(void**)&v.hit_dst, std::max(R, (size_t)P * 8) * 4},
       {(void**)&vol->d_ray_perm, ray_order_table().size() * 2},
-      {(void**)&v.pairs, (std::max(R, (size_t)P * 8) + 63) / 64 * kPairsPerBatch * 2},
-      {(void**)&v.pair_cnt, (std::max(R, (size_t)P * 8) + 63) / 64 * 4},
-      {(void**)&v.pair_off, ((std::max(R, (size_t)P * 8) + 63) / 64 + 1) * 4},
-      {(void**)&v.pair_blk, ((std::max(R, (size_t)P * 8) + 63) / 64 / kPairScanPer + 1) * 4},
   };
+  if (!(d->flags & ADGI_STATIC_SCRATCH))
+    frame_scratch_each(v, (size_t)P, R, std::max(R, (size_t)P * 8),
+                       [&](void** p, size_t bytes) { reqs.push_back({p, bytes}); });
   if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)kPkDecSize * 4});
   if (d->max_chains > 0) {
     const size_t C = (size_t)d->max_chains, Smax = R / 2;
@@ -1222,13 +1238,54 @@ adgi_status restore_state_impl(adgi_volume* vol, const void* src, size_t bytes, 
 
 }  // namespace adgi
 
-extern "C" {
+// Frame scratch of adgi_update_probes_static, one copy per device for the
+// life of the process. Host code never passes the array itself (its host-side
+// name is not a device address): the address comes from hipGetSymbolAddress,
+// looked up once per device with that device current.
+static __device__ __align__(256) uint8_t scratch[ADGI_STATIC_SCRATCH_BYTES];
 
-adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
-  return adgi::update_scene_impl(vol, sc, nullptr);
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+struct StaticScratch {
+  uint8_t* ptr = nullptr;     // this device's copy of `scratch`
+  hipEvent_t done = nullptr;  // recorded after the last static frame's blend
+};
+std::mutex g_static_mu;  // guards g_static and orders static frames per device
+StaticScratch g_static[kStaticMaxDevices];
+
+adgi_status static_scratch(int device, StaticScratch** out) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (device < 0 || device >= kStaticMaxDevices)
+    return fail(ADGI_ERR_INVALID_ARG, "static scratch supports devices 0..%d", kStaticMaxDevices - 1);
+  StaticScratch& sc = g_static[device];
+  if (!sc.ptr) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    void* ptr = nullptr;
+    hipEvent_t ev = nullptr;
+    hipError_t e2 = e;
+    if (e2 == hipSuccess) e2 = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (cur >= 0 && cur != device) {
+      const hipError_t e3 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e3;
+    }
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess || !ptr) {
+      if (ev) (void)hipEventDestroy(ev);
+      return fail(ADGI_ERR_DEVICE, "static scratch set-up on device %d failed: %s", device,
+                  e != hipSuccess ? hipGetErrorString(e) : "null symbol address");
+    }
+    sc.ptr = (uint8_t*)ptr;
+    sc.done = ev;
+  }
+  *out = &sc;
+  return ADGI_OK;
 }
 
-adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, adgi_update_stats* stats) {
+adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_update_stats* stats, bool use_static) {
   if (!vol || !p) return fail(ADGI_ERR_INVALID_ARG, "volume and params must not be NULL");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "update_probes before update_scene");
@@ -1238,6 +1295,11 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   const int64_t P = vol->P, cap = vol->desc.max_rays_per_frame;
   const int mode = p->adaptive;
   int64_t samples = 0;
+  if (!use_static && (vol->desc.flags & ADGI_STATIC_SCRATCH))
+    return fail(ADGI_ERR_INVALID_ARG,
+                "the volume was created with ADGI_STATIC_SCRATCH: its frames go through adgi_update_probes_static");
+  if (use_static && mode == ADGI_MODE_CHAIN)
+    return fail(ADGI_ERR_INVALID_ARG, "adgi_update_probes_static runs budgeted and uniform frames only");
   if (p->pilot_reuse != 0 && p->pilot_reuse != 1) return fail(ADGI_ERR_INVALID_ARG, "pilot_reuse must be 0 or 1");
   if (p->pilot_reuse && mode != ADGI_MODE_UNIFORM) {
     if (vol->desc.storage == ADGI_PACKED || vol->desc.blend_mode != ADGI_BLEND_SAMPLE)
@@ -1298,6 +1360,28 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   }
   if (p->n_max > 65535 && mode == ADGI_MODE_ADAPTIVE) return fail(ADGI_ERR_BUDGET, "n_max must be <= 65535");
 
+  // static frames: the frame scratch carved from this device's `scratch`,
+  // sized for this frame's rays (budgeted: B probe rays, 8 P pilot slots)
+  VolumeView sview{};
+  StaticScratch* ssc = nullptr;
+  if (use_static) {
+    const size_t Rc = mode == ADGI_MODE_ADAPTIVE ? (size_t)p->budget : (size_t)(P * p->n_uniform);
+    const size_t Hc = mode == ADGI_MODE_ADAPTIVE ? std::max(Rc, (size_t)P * 8) : Rc;
+    sview = vol->v;
+    size_t need = 0;
+    frame_scratch_each(sview, (size_t)P, Rc, Hc, [&](void** q, size_t bytes) {
+      *q = (void*)need;
+      need += (bytes + 255) & ~(size_t)255;
+    });
+    if (need > ADGI_STATIC_SCRATCH_BYTES)
+      return fail(ADGI_ERR_BUDGET, "the frame needs %zu bytes of scratch, more than the static scratch (%zu bytes)",
+                  need, ADGI_STATIC_SCRATCH_BYTES);
+    adgi_status s2 = static_scratch(vol->device, &ssc);
+    if (s2 != ADGI_OK) return s2;
+    frame_scratch_each(sview, (size_t)P, Rc, Hc, [&](void** q, size_t) { *q = ssc->ptr + (size_t)*q; });
+    sview.hit_cap = (uint32_t)Hc;
+  }
+
   adgi_status st = order_after_user(vol);
   if (st != ADGI_OK) return st;
   // parameter block into the next pinned slot
@@ -1349,7 +1433,25 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.fp, &fp, sizeof(FrameParams), hipMemcpyHostToDevice, vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
-  if (vol->tun.use_graph && mode != ADGI_MODE_CHAIN) {
+  if (use_static) {
+    // one static frame at a time per device: each waits on the GPU for the
+    // previous one's blend, so frames of different volumes never share the
+    // scratch at once; the frame's counters are copied out before the next
+    // frame may start
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    hipError_t e = hipStreamWaitEvent(vol->stream, ssc->done, 0);
+    const VolumeView saved = vol->v;
+    vol->v = sview;
+    if (e == hipSuccess) e = enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr, false, vol->ev_traced);
+    if (e == hipSuccess && p->sync && stats)
+      e = hipMemcpyAsync(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost, vol->stream);
+    if (e == hipSuccess) e = hipEventRecord(ssc->done, vol->stream);
+    vol->v = saved;
+    if (e != hipSuccess) {
+      vol->sticky = true;
+      return fail(ADGI_ERR_DEVICE, "static-scratch frame failed: %s", hipGetErrorString(e));
+    }
+  } else if (vol->tun.use_graph && mode != ADGI_MODE_CHAIN) {
     if (!vol->exec[mode]) {
       // the frame up to the probe trace and its blend, captured apart and
       // composed with the event node that frees the scene between them
@@ -1386,7 +1488,8 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
   if (p->sync) {
     HIP_TRY(vol, hipStreamSynchronize(vol->stream));
     if (stats) {
-      HIP_TRY(vol, hipMemcpy(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost));
+      if (!use_static)
+        HIP_TRY(vol, hipMemcpy(vol->h_stats, vol->v.stats, sizeof(FrameStats), hipMemcpyDeviceToHost));
       uint32_t total = 0;
       HIP_TRY(vol, hipMemcpy(&total, vol->v.offsets + vol->P, 4, hipMemcpyDeviceToHost));
       std::memset(stats, 0, sizeof(*stats));
@@ -1403,8 +1506,7 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
       float ms = 0.f;
       HIP_TRY(vol, hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1));
       stats->ms_total = ms;
-      if (!vol->tun.use_graph || mode == ADGI_MODE_CHAIN)
-      {
+      if (use_static || !vol->tun.use_graph || mode == ADGI_MODE_CHAIN) {
         for (int k = 0; k < 6; ++k)
           HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[k], vol->ev_k[k], vol->ev_k[k + 1]));
         HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[6], vol->ev_k[4], vol->ev_k[7]));
@@ -1413,6 +1515,22 @@ adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, ad
     }
   }
   return ADGI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adgi_status adgi_update_scene(adgi_volume* vol, const adgi_scene_desc* sc) {
+  return adgi::update_scene_impl(vol, sc, nullptr);
+}
+
+adgi_status adgi_update_probes(adgi_volume* vol, const adgi_update_params* p, adgi_update_stats* stats) {
+  return update_impl(vol, p, stats, false);
+}
+
+adgi_status adgi_update_probes_static(adgi_volume* vol, const adgi_update_params* p, adgi_update_stats* stats) {
+  return update_impl(vol, p, stats, true);
 }
 
 adgi_status adgi_read_probes(adgi_volume* vol, adgi_probe_readback* out) {
