@@ -710,10 +710,11 @@ def main():
     prof_blend = read_profile("blend_boxfield", h_blend)
     width = 4 if tuning.get("bvh_width") == 4 else 2
 
-    def trace_roof(kernel, ms, nodes, tris, rays, prof_key):
+    def trace_roof(kernel, ms, nodes, boxes, tris, rays, prof_key):
         """ALU roofline of one traversal kernel: its slab and triangle tests
-        (counted by the work-counting run) over its eager duration."""
-        ops = nodes * width * OPS_PER_BOX + tris * OPS_PER_TRI
+        (counted by the work-counting run; empty BVH4 child slots excluded)
+        over its eager duration."""
+        ops = boxes * OPS_PER_BOX + tris * OPS_PER_TRI
         tops = ops / (ms * 1e-3) / 1e12 if ms else 0.0
         prof = read_profile(prof_key, h_trace)
         # the counters belong to one traversal variant (<kind, count, width 4>)
@@ -724,13 +725,14 @@ def main():
                 "traffic": prof.get("traffic"), "valu_busy_pct": prof.get("valu_busy_pct"),
                 "valu_utilization_pct": prof.get("valu_utilization_pct"), "ms": ms, "rays": rays,
                 "mrays_per_s": rays / (ms * 1e-3) / 1e6 if ms else None,
-                "node_tests_per_ray": nodes / max(rays, 1), "tri_tests_per_ray": tris / max(rays, 1),
-                "bvh_width": width}
+                "node_tests_per_ray": nodes / max(rays, 1), "box_tests_per_ray": boxes / max(rays, 1),
+                "tri_tests_per_ray": tris / max(rays, 1), "bvh_width": width}
 
     roof_hit = trace_roof("trace_hit_kernel", stages_a[6], tw["node_tests"] - tw["shade_node_tests"],
-                          tw["tri_tests"] - tw["shade_tri_tests"], tw["primary_rays"], "trace_hit_boxfield")
-    roof_shade = trace_roof("trace_shade_kernel", stages_a[7], tw["shade_node_tests"], tw["shade_tri_tests"],
-                            tw["shadow_rays"], "trace_shade_boxfield")
+                          tw["box_tests"] - tw["shade_box_tests"], tw["tri_tests"] - tw["shade_tri_tests"],
+                          tw["primary_rays"], "trace_hit_boxfield")
+    roof_shade = trace_roof("trace_shade_kernel", stages_a[7], tw["shade_node_tests"], tw["shade_box_tests"],
+                            tw["shade_tri_tests"], tw["shadow_rays"], "trace_shade_boxfield")
     roof_blend = {"bound": "hbm", "kernel": "blend_kernel", "achieved": blend_gbs, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": blend_gbs / HBM_PEAK_GBS,
                   "traffic": prof_blend.get("traffic"), "ms": blend_ms,

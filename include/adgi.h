@@ -423,8 +423,10 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* params, ad
  * shading kernel's work). */
 typedef struct {
   int64_t primary_rays, shadow_rays, node_tests, tri_tests;
-  int64_t box_tests;          /* node_tests x the node width in use (2 or 4) */
+  int64_t box_tests;          /* child boxes tested: 2 per BVH2 visit, the
+                                 non-empty child slots of a BVH4 visit       */
   int64_t shade_node_tests, shade_tri_tests;
+  int64_t shade_box_tests;    /* the shading kernel's part of box_tests      */
 } adgi_trace_work;
 adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* params,
                                     adgi_trace_work* out);

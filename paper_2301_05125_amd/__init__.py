@@ -112,7 +112,8 @@ class ProbeReadback(C.Structure):
 class TraceWork(C.Structure):
     _fields_ = [("primary_rays", C.c_int64), ("shadow_rays", C.c_int64),
                 ("node_tests", C.c_int64), ("tri_tests", C.c_int64), ("box_tests", C.c_int64),
-                ("shade_node_tests", C.c_int64), ("shade_tri_tests", C.c_int64)]
+                ("shade_node_tests", C.c_int64), ("shade_tri_tests", C.c_int64),
+                ("shade_box_tests", C.c_int64)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

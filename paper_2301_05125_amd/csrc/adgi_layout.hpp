@@ -105,6 +105,8 @@ struct FrameStats {
   uint64_t tri_tests;
   uint64_t shade_node_tests; // the shading kernel's part of the two above
   uint64_t shade_tri_tests;
+  uint64_t box_tests;        // child boxes tested (BVH4: non-empty slots only)
+  uint64_t shade_box_tests;
   int64_t remainder;        // R = B' - sum e_i(lambda*)
   uint32_t bucket_count[kOrderBuckets];   // probes per ray-chunk bucket
   uint32_t bucket_cursor[kOrderBuckets];  // scatter cursors

@@ -34,6 +34,8 @@ __global__ void frame_begin_kernel(VolumeView v) {
     st->tri_tests = 0ull;
     st->shade_node_tests = 0ull;
     st->shade_tri_tests = 0ull;
+    st->box_tests = 0ull;
+    st->shade_box_tests = 0ull;
     st->remainder = 0;
   }
   if (v.fp->frame == 0 && tid < v.P) v.score[tid] = 0;

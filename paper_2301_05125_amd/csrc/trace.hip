@@ -99,6 +99,7 @@ __device__ __forceinline__ NodeData fetch_node(const float4* __restrict__ nodes,
 // Work counters of the counting variant (node visits = box-pair tests).
 struct Work {
   uint32_t nodes = 0, tris = 0;
+  uint32_t boxes = 0;  // child boxes tested: two per BVH2 visit, the non-empty slots of a BVH4 visit
 };
 
 // The large triangles kept outside the tree (slots [0, num_big)): closest
@@ -150,7 +151,10 @@ __device__ int closest_hit(const VolumeView& v, const Ray& ray,
   for (;;) {
     while (node >= 0) {
       NodeData nd = fetch_node(v.nodes, node);
-      if (COUNT) ++w.nodes;
+      if (COUNT) {
+        ++w.nodes;
+        w.boxes += 2u;
+      }
       float tl, tr;
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, t_best, tl);
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, t_best, tr);
@@ -199,7 +203,10 @@ __device__ bool any_hit(const VolumeView& v, const Ray& ray,
   for (;;) {
     while (node >= 0) {
       NodeData nd = fetch_node(v.nodes, node);
-      if (COUNT) ++w.nodes;
+      if (COUNT) {
+        ++w.nodes;
+        w.boxes += 2u;
+      }
       float tl, tr;
       bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
       bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
@@ -245,12 +252,18 @@ __device__ __forceinline__ void order2(float& ka, int& ca, float& kb, int& cb) {
   ca = c;
 }
 
+template <bool COUNT>
 __device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int idx, const Ray& ray,
-                                          float lim, Stack& st, int& next) {
+                                          float lim, Stack& st, int& next, Work& w) {
   const float4* src = nodes4 + 8 * (size_t)idx;
   const float4 lx = src[0], ly = src[1], lz = src[2], hx = src[3], hy = src[4], hz = src[5], cf = src[6];
   int c0 = __float_as_int(cf.x), c1 = __float_as_int(cf.y), c2 = __float_as_int(cf.z),
       c3 = __float_as_int(cf.w);
+  if (COUNT) {
+    ++w.nodes;
+    w.boxes += (uint32_t)(c0 != kEmptyChild) + (uint32_t)(c1 != kEmptyChild) + (uint32_t)(c2 != kEmptyChild) +
+               (uint32_t)(c3 != kEmptyChild);
+  }
   float t0, t1, t2, t3;
   const bool h0 = box_hit(ray, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, 0.0f, lim, t0) && c0 != kEmptyChild;
   const bool h1 = box_hit(ray, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, 0.0f, lim, t1) && c1 != kEmptyChild;
@@ -286,9 +299,8 @@ __device__ int closest_hit4(const VolumeView& v, const Ray& ray, Stack& st, floa
   int node = 0;
   for (;;) {
     while (node >= 0) {
-      if (COUNT) ++w.nodes;
       int next;
-      if (node4_step(v.nodes4, node, ray, t_best, st, next) > 0) {
+      if (node4_step<COUNT>(v.nodes4, node, ray, t_best, st, next, w) > 0) {
         node = next;
       } else {
         if (!st.pop_live(t_best, node)) return slot_best;
@@ -324,9 +336,8 @@ __device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack&
   int node = 0;
   for (;;) {
     while (node >= 0) {
-      if (COUNT) ++w.nodes;
       int next;
-      if (node4_step(v.nodes4, node, ray, tmax, st, next) > 0) {
+      if (node4_step<COUNT>(v.nodes4, node, ray, tmax, st, next, w) > 0) {
         node = next;
       } else {
         if (st.sp == 0) return false;
@@ -492,21 +503,24 @@ __device__ __forceinline__ uint32_t lights_facing(const SceneParams& sc, float3 
 // is the same in every lane.
 template <bool COUNT, bool SHADE>
 __device__ __forceinline__ void flush_stats(const VolumeView& v, const Work& w, uint32_t shadow) {
-  uint32_t n = COUNT ? w.nodes : 0u, tt = COUNT ? w.tris : 0u;
+  uint32_t n = COUNT ? w.nodes : 0u, tt = COUNT ? w.tris : 0u, bx = COUNT ? w.boxes : 0u;
   const uint32_t s = shadow;
   if (COUNT) {
     for (int o2 = 32; o2 > 0; o2 >>= 1) {
       n += __shfl_xor(n, o2);
       tt += __shfl_xor(tt, o2);
+      bx += __shfl_xor(bx, o2);
     }
   }
   if (lane_id() == 0) {
     if (COUNT) {
       atomicAdd((unsigned long long*)&v.stats->node_tests, (unsigned long long)n);
       atomicAdd((unsigned long long*)&v.stats->tri_tests, (unsigned long long)tt);
+      atomicAdd((unsigned long long*)&v.stats->box_tests, (unsigned long long)bx);
       if (SHADE) {
         atomicAdd((unsigned long long*)&v.stats->shade_node_tests, (unsigned long long)n);
         atomicAdd((unsigned long long*)&v.stats->shade_tri_tests, (unsigned long long)tt);
+        atomicAdd((unsigned long long*)&v.stats->shade_box_tests, (unsigned long long)bx);
       }
     }
     if (s > 0) atomicAdd((unsigned long long*)&v.stats->shadow_rays, (unsigned long long)s);

@@ -1759,7 +1759,8 @@ adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* 
   out->primary_rays = p->adaptive == ADGI_MODE_CHAIN ? 2 * (int64_t)total + dyn : (int64_t)total;
   out->shadow_rays = (int64_t)vol->h_stats->shadow_rays;
   out->node_tests = (int64_t)vol->h_stats->node_tests;
-  out->box_tests = out->node_tests * (use_bvh4(vol, vol->tun) ? 4 : 2);
+  out->box_tests = (int64_t)vol->h_stats->box_tests;
+  out->shade_box_tests = (int64_t)vol->h_stats->shade_box_tests;
   out->tri_tests = (int64_t)vol->h_stats->tri_tests;
   out->shade_node_tests = (int64_t)vol->h_stats->shade_node_tests;
   out->shade_tri_tests = (int64_t)vol->h_stats->shade_tri_tests;

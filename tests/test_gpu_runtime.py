@@ -117,6 +117,38 @@ def test_autotune_keeps_state_and_results():
     _same(ref, out)
 
 
+@pytest.mark.parametrize("width", [2, 4])
+def test_trace_work_counts(width):
+    """The work-counting run traces the frame's own probe rays and leaves
+    the state alone: on a uniform frame (no pilots, whose shadow rays the
+    frame's statistics would include) its ray counts equal those of the
+    frame that follows; a BVH2 visit tests two child boxes, a BVH4 visit
+    between one and four (empty slots not counted), and the shading
+    kernel's share is part of the totals."""
+    sc = _small_field()
+    kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
+    vol = adgi.volume_for_scene(sc, max_rays=sc.num_probes * 40, seed=3)
+    vol.set_tuning(bvh_width=width)
+    _run(sc, 2, vol=vol, **kw)
+    vol.update_scene(sc.positions_at(2), light_pos=sc.light_positions(2), light_intensity=sc.light_intensity,
+                     sky=sc.sky, mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, sc.anim_vertices))
+    before = vol.read_probes()
+    assert vol.measure_trace_work(2, **kw)["primary_rays"] == sc.num_probes * 40
+    _same(before, vol.read_probes())
+    ku = dict(adaptive=False, n_uniform=40)
+    tw = vol.measure_trace_work(2, **ku)
+    _same(before, vol.read_probes())
+    st = vol.update_probes(2, sync=True, **ku)
+    vol.destroy_volume()
+    assert tw["primary_rays"] == st["primary_rays"] and tw["shadow_rays"] == st["shadow_rays"]
+    assert tw["node_tests"] > tw["shade_node_tests"] > 0 and tw["tri_tests"] > tw["shade_tri_tests"] > 0
+    assert 0 < tw["shade_box_tests"] < tw["box_tests"]
+    if width == 2:
+        assert tw["box_tests"] == 2 * tw["node_tests"] and tw["shade_box_tests"] == 2 * tw["shade_node_tests"]
+    else:
+        assert tw["node_tests"] <= tw["box_tests"] <= 4 * tw["node_tests"]
+
+
 @pytest.mark.parametrize("storage", [adgi.ADGI_FP32, adgi.ADGI_PACKED])
 def test_snapshot_resumes_bit_identically(storage):
     sc = _small_field()
