@@ -268,15 +268,16 @@ struct WaveTile {
   // touch consecutive words (distinct banks) instead of strided records
   static constexpr size_t kStI = 0, kStD = 16 * (size_t)NI;
   static constexpr size_t kRankBytes = kStD + 12 * (size_t)ND;
-  // bits of an interior texel index
-  static constexpr int BI = NI <= 64 ? 6 : NI <= 128 ? 7 : NI <= 256 ? 8 : 9;
-  static constexpr int BD = ND <= 64 ? 6 : ND <= 128 ? 7 : ND <= 256 ? 8 : 9;
+  // then one 64-bit lane mask per interior texel (irradiance, then depth):
+  // the lanes of the current chunk whose samples fall in that texel
+  static constexpr size_t kMaskI = kRankBytes, kMaskD = kMaskI + 8 * (size_t)NI;
+  static constexpr size_t kMaskEnd = kMaskD + 8 * (size_t)ND;
   // the other wave kernels' LDS (packed, gather): a chunk of records and the masks,
   // or the staged interior
   static constexpr size_t kChunkBytes = 64 * 16 + 8 * (size_t)NT;
   static constexpr size_t kStageBytes = 4 * (3 * (size_t)NI + 2 * (size_t)ND) + NT;
   static constexpr size_t kOldBytes = ((kChunkBytes > kStageBytes ? kChunkBytes : kStageBytes) + 15) & ~(size_t)15;
-  static constexpr size_t kWaveBytes = kOldBytes > kRankBytes ? kOldBytes : kRankBytes;
+  static constexpr size_t kWaveBytes = kOldBytes > kMaskEnd ? kOldBytes : kMaskEnd;
   static constexpr size_t kTabBytes = (2 * (GI * GI * 3 + GD * GD * 2) + 15) & ~(size_t)15;
   static constexpr size_t kBlockBytes = 4 * kWaveBytes + kTabBytes + 2 * 256 * 4;  // + two step tables
   static_assert(NI % 4 == 0 && ND % 4 == 0, "counts are moved as 32-bit words");
@@ -371,20 +372,6 @@ __device__ __forceinline__ void plane_tau(float* sD, uint32_t k, float tau, floa
   sD[k] = fmaf(al, tau - sD[k], sD[k]);
   sD[ND + k] = fmaf(al, tau2 - sD[ND + k], sD[ND + k]);
   *nk = min(n + 1u, 255u);
-}
-
-// Lanes (among `live`) whose key equals this lane's, from one ballot per key
-// bit: the wave-wide match without memory traffic.
-template <int BITS>
-__device__ __forceinline__ uint64_t match_key(uint32_t key, uint64_t live) {
-  uint64_t m = live;
-#pragma unroll
-  for (int b = 0; b < BITS; ++b) {
-    const bool bit = (key >> b) & 1u;
-    const uint64_t on = ballot(bit);
-    m &= bit ? on : ~on;
-  }
-  return m;
 }
 
 // What a wave loads for a probe before it works on it: its interior texels
@@ -522,12 +509,31 @@ __device__ __forceinline__ void blend_probe_samples(const VolumeView& v, int i, 
   uint32_t* nD = (uint32_t*)(sD + 2 * ND);
   // One chunk of up to 64 samples, one per lane (act), each with its record
   // and its texel indices.
+  uint64_t* mkI = (uint64_t*)(wbase + W::kMaskI);
+  uint64_t* mkD = (uint64_t*)(wbase + W::kMaskD);
   auto apply = [&](const float4 cur, const uint32_t cbin, const bool act) {
     const uint32_t bI = cbin & 0xFFFFu, bD = cbin >> 16;
+    // the chunk's lanes in this lane's texels: every lane ORs its bit into
+    // the masks of its two texels (OR commutes, so the order in which the
+    // lanes land does not matter), reads them back, and clears them for the
+    // next chunk (a wave's LDS accesses complete in issue order)
+    uint64_t mI = 0ull, mD = 0ull;
+    if (act) {
+      atomicOr((unsigned long long*)&mkI[bI], 1ull << lane);
+      atomicOr((unsigned long long*)&mkD[bD], 1ull << lane);
+    }
+    wave_sync();
+    if (act) {
+      mI = mkI[bI];
+      mD = mkD[bD];
+    }
+    wave_sync();
+    if (act) {
+      mkI[bI] = 0ull;
+      mkD[bD] = 0ull;
+    }
     // rank of this sample among the chunk's samples of the same texel, and
     // their number
-    const uint64_t live = ballot(act);
-    const uint64_t mI = match_key<W::BI>(bI, live), mD = match_key<W::BD>(bD, live);
     const uint32_t rI = lanes_below(mI), rD = lanes_below(mD);
     // the sample's count N before it is applied is the texel's count before
     // the chunk plus its rank (saturating at 255), so its step weight is known
@@ -675,6 +681,8 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
   uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
   const uint32_t P = (uint32_t)v.P;
   const int lane = threadIdx.x & 63;
+  for (int k = lane; k < W::NI + W::ND; k += 64) ((uint64_t*)(wbase + W::kMaskI))[k] = 0ull;
+  wave_sync();
   const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (first >= P) return;
   const uint32_t nq = (P - first + waves - 1u) / waves;  // this wave's probes
@@ -690,17 +698,27 @@ __global__ __launch_bounds__(256) void blend_wave_kernel(VolumeView v, BlendIO i
       ek = offsets[ik + 1];
     }
     const uint32_t cnt = min(64u, nq - base);
+    G g;
+    {
+      const uint32_t off = __builtin_amdgcn_readlane(ok, 0);
+      load_probe<RI, RD, HALF, CHAIN>(v, io, __builtin_amdgcn_readlane(ik, 0), off,
+                                      __builtin_amdgcn_readlane(ek, 0) - off, reuse, g);
+    }
     for (uint32_t kk = 0; kk < cnt; ++kk) {
       const int i = __builtin_amdgcn_readlane(ik, kk);
       const uint32_t off = __builtin_amdgcn_readlane(ok, kk);
       const uint32_t n = __builtin_amdgcn_readlane(ek, kk) - off;
-      {
-        G g;
-        load_probe<RI, RD, HALF, CHAIN>(v, io, i, off, n, reuse, g);
-        stage_probe<RI, RD, HALF, CHAIN>(g, wbase);
-        wave_sync();
-        blend_probe_samples<RI, RD, HALF, CHAIN>(v, i, off, n, g.rec, g.bins, g.uv, reuse, g.prec, g.pbins,
-                                                 wbase, alpha, alpha_dyn, []() {});
+      stage_probe<RI, RD, HALF, CHAIN>(g, wbase);
+      wave_sync();
+      blend_probe_samples<RI, RD, HALF, CHAIN>(v, i, off, n, g.rec, g.bins, g.uv, reuse, g.prec, g.pbins,
+                                               wbase, alpha, alpha_dyn, []() {});
+      // the next probe's loads go out before this probe's stores: a wave
+      // waits for its loads in issue order, so loads behind the stores would
+      // also wait for the stores to complete
+      if (kk + 1u < cnt) {
+        const uint32_t off1 = __builtin_amdgcn_readlane(ok, kk + 1u);
+        load_probe<RI, RD, HALF, CHAIN>(v, io, __builtin_amdgcn_readlane(ik, kk + 1u), off1,
+                                        __builtin_amdgcn_readlane(ek, kk + 1u) - off1, reuse, g);
       }
       store_probe<RI, RD, HALF>(io, i, wbase, tab);
       wave_sync();
