@@ -127,10 +127,6 @@ def lib():
         L.orc_round_half.argtypes = [C.c_double]
         L.orc_num_threads.restype = C.c_int32
         L.orc_set_threads.argtypes = [C.c_int32]
-        L.orc_ln32.restype = C.c_float
-        L.orc_ln32.argtypes = [C.c_float]
-        L.orc_exp32.restype = C.c_float
-        L.orc_exp32.argtypes = [C.c_float]
         L.orc_pack_encode.restype = C.c_uint32
         L.orc_pack_encode.argtypes = [C.c_float, C.c_float, C.c_float, C.c_int32]
         L.orc_pack_decode.restype = C.c_float

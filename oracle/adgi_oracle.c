@@ -1238,68 +1238,26 @@ void orc_probes_frame(const orc_scene* s, const orc_grid* g, int32_t count, cons
 
 /* ------------------------------------------------------- packed texels */
 
-/* ln on binary32 for y >= 1: y = m 2^e with m in [sqrt(1/2), sqrt(2)), then
- * ln m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, by its series to s^11
- * (truncation < 1e-10), and e ln 2 split in two parts (Cody and Waite) so the
- * product stays exact. */
-static const float kLn2Hi = 0.693145751953125f;       /* 0x3F317200: 16 bits */
-static const float kLn2Lo = 1.42860682030941723212e-6f; /* ln 2 - kLn2Hi */
-
-float orc_ln32(float y) {
-  uint32_t b;
-  memcpy(&b, &y, 4);
-  int32_t e = (int32_t)((b >> 23) & 0xFFu) - 127;
-  uint32_t mb = (b & 0x7FFFFFu) | 0x3F800000u;
-  float m;
-  memcpy(&m, &mb, 4);
-  if (m > 1.41421356f) {
-    m = m * 0.5f;
-    e = e + 1;
-  }
-  float s = (m - 1.0f) / (m + 1.0f);
-  float s2 = s * s;
-  float p = fmaf(s2, 1.0f / 11.0f, 1.0f / 9.0f);
-  p = fmaf(s2, p, 1.0f / 7.0f);
-  p = fmaf(s2, p, 1.0f / 5.0f);
-  p = fmaf(s2, p, 1.0f / 3.0f);
-  p = fmaf(s2, p, 1.0f);
-  float lnm = 2.0f * s * p;
-  float fe = (float)e;
-  return fmaf(fe, kLn2Hi, fmaf(fe, kLn2Lo, lnm));
-}
-
-/* e^x on binary32 for 0 <= x <= 16: x = k ln 2 + r, |r| <= ln 2 / 2 (Cody
- * and Waite reduction), e^r by its Taylor series to r^7 (truncation < 6e-9),
- * scaled by 2^k through the exponent bits. */
-float orc_exp32(float x) {
-  float k = rintf(x * 1.44269504f);
-  float r = fmaf(-k, kLn2Hi, x);
-  r = fmaf(-k, kLn2Lo, r);
-  float p = fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
-  p = fmaf(r, p, 1.0f / 120.0f);
-  p = fmaf(r, p, 1.0f / 24.0f);
-  p = fmaf(r, p, 1.0f / 6.0f);
-  p = fmaf(r, p, 0.5f);
-  p = fmaf(r, p, 1.0f);
-  p = fmaf(r, p, 1.0f);
-  uint32_t sb = (uint32_t)((int32_t)k + 127) << 23;
-  float scale;
-  memcpy(&scale, &sb, 4);
-  return p * scale;
-}
-
+/* eq. rgbEnc, one channel: the code of a binary32 value v >= 0 is
+ * floor(qmax min(ln(gamma v + 1), beta) / beta), qmax = 2^bits - 1 (rounded
+ * down, App. B). Evaluated in FP64: gamma v is exact there, log1p and the
+ * scaling round at about 1e-16 relative, and no binary32 input lies closer
+ * than that to a code boundary (checked at every boundary of the four
+ * channel types against 50-digit arithmetic), so the floor is the exact
+ * one. */
 uint32_t orc_pack_encode(float v, float beta, float gamma, int32_t bits) {
-  const float qmax = (float)((1u << bits) - 1u);
-  float x = v > 0.0f ? v : 0.0f;
-  float u = fminf(orc_ln32(fmaf(gamma, x, 1.0f)), beta) / beta;
-  float q = floorf(u * qmax);
+  const double qmax = (double)((1u << bits) - 1u);
+  const double x = v > 0.0f ? (double)v : 0.0;
+  const double u = fmin(log1p((double)gamma * x), (double)beta) / (double)beta;
+  const double q = floor(u * qmax);
   return q >= qmax ? (uint32_t)qmax : (uint32_t)q;
 }
 
+/* The value code q stands for, (e^(beta q / qmax) - 1) / gamma, in FP64 and
+ * rounded once to binary32. */
 float orc_pack_decode(uint32_t q, float beta, float gamma, int32_t bits) {
-  const float qmax = (float)((1u << bits) - 1u);
-  float u = (float)q / qmax;
-  return (orc_exp32(beta * u) - 1.0f) / gamma;
+  const double qmax = (double)((1u << bits) - 1u);
+  return (float)(expm1((double)beta * ((double)q / qmax)) / (double)gamma);
 }
 
 void orc_packed_blend(int32_t count, const int32_t* n, const int64_t* ray_base, const float* rec,

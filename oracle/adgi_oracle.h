@@ -195,14 +195,13 @@ double orc_blend_alpha(int32_t n, double hysteresis);
 double orc_round_half(double x);
 
 /* ---- packed 32-bit texels (eq. rgbEnc; Sec. 4.6; App. B) ----------------
- * The quantised codes are decisions of the paper's FP32 shader arithmetic, so
- * this part computes in IEEE binary32 (every operation written out, fused
- * multiply-adds explicit, no contraction) with its own ln and exp. */
-float orc_ln32(float y);            /* natural log, y >= 1                    */
-float orc_exp32(float x);           /* e^x, 0 <= x <= 16                      */
-/* floor(min(ln(gamma v + 1), beta) / beta * (2^bits - 1)) for v >= 0 */
+ * The texel values are binary32 (the paper's shader arithmetic: the moving
+ * average runs in binary32, fused multiply-adds explicit); the codes are the
+ * exact eq. rgbEnc of those binary32 values and the decoded values the exact
+ * ones rounded once to binary32, both through FP64 libm. */
+/* floor(min(ln(gamma v + 1), beta) / beta * (2^bits - 1)) for v >= 0, exact */
 uint32_t orc_pack_encode(float v, float beta, float gamma, int32_t bits);
-/* (exp(beta q / (2^bits - 1)) - 1) / gamma */
+/* (exp(beta q / (2^bits - 1)) - 1) / gamma, rounded to binary32 */
 float orc_pack_decode(uint32_t q, float beta, float gamma, int32_t bits);
 /* Moving average of Alg. MovingAvgUpdate on packed words, samples of each
  * probe applied in ray order: irradiance word = R9 | G9 << 9 | B8 << 18 |

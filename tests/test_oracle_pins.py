@@ -839,26 +839,74 @@ def test_pin8_allocation_properties():
 
 # ---------------------------------------------------------------- packed texels
 # The packed words of eq. rgbEnc / App. B (R9 G9 B8 + N6; two 13-bit depth
-# channels + N6) are computed in FP32 with the oracle's own ln/exp. Pins: the
-# library log/exp, the closed form of the encoding, the round-down property
-# the paper states for its quantisation (dark samples drive a texel to zero),
-# the fixed point of the quantised moving average, and the count field.
+# channels + N6): binary32 moving averages, exact codes, decoded values
+# rounded once to binary32. Pins: every code boundary and every decoded value
+# of the four channel types against 50-digit arithmetic, the closed form of
+# the encoding, the round-down property the paper states for its
+# quantisation (dark samples drive a texel to zero), the fixed point of the
+# quantised moving average, and the count field.
 
-def test_packed_exp_ln_against_libm():
-    L = oracle.lib()
-    xs = np.linspace(0.0, 16.0, 4001).astype(np.float32)
-    e = np.array([L.orc_exp32(float(x)) for x in xs], np.float64)
-    ref = np.exp(xs.astype(np.float64))
-    assert np.max(np.abs(e - ref) / np.spacing(ref.astype(np.float32)).astype(np.float64)) <= 1.0
-    ys = np.exp(np.linspace(0.0, 20.0, 4001)).astype(np.float32)
-    ln = np.array([L.orc_ln32(float(y)) for y in ys], np.float64)
-    ref = np.log(ys.astype(np.float64))
-    ulp = np.spacing(np.maximum(np.abs(ref), 1e-3).astype(np.float32)).astype(np.float64)
-    assert np.max(np.abs(ln - ref) / ulp) <= 3.0
+PACK_CHANNELS = [(5.0, 15.0, 9), (5.0, 15.0, 8), (5.0, 15.0, 13), (8.0, 20.0, 13)]
 
 
-@pytest.mark.parametrize("beta,gamma,bits", [(5.0, 15.0, 9), (5.0, 15.0, 8), (5.0, 15.0, 13),
-                                             (8.0, 20.0, 13)])
+def _f32_up(f):
+    return np.nextafter(np.float32(f), np.float32(np.inf))
+
+
+def _f32_down(f):
+    return np.nextafter(np.float32(f), np.float32(0.0))
+
+
+@pytest.mark.parametrize("beta,gamma,bits", PACK_CHANNELS)
+def test_packed_codes_exact_at_every_boundary(beta, gamma, bits):
+    """Code k begins at t_k = (e^(beta k / qmax) - 1) / gamma. For every k the
+    binary32 value just above t_k encodes to k and the one just below to
+    k - 1, and both lie farther from the boundary (in code units, 50-digit
+    arithmetic) than any FP64 rounding could reach; so the encoder is the
+    exact floor for every binary32 input."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    qmax = (1 << bits) - 1
+    B, G = Decimal(beta), Decimal(gamma)
+    min_margin = Decimal(1)
+    for k in range(1, qmax + 1):
+        t = ((B * k / qmax).exp() - 1) / G
+        f = np.float32(float(t))
+        while Decimal(float(f)) < t:
+            f = _f32_up(f)
+        while Decimal(float(_f32_down(f))) >= t:
+            f = _f32_down(f)
+        lo = _f32_down(f)
+        assert oracle.pack_encode(float(f), beta, gamma, bits) == k, (k, float(f))
+        assert oracle.pack_encode(float(lo), beta, gamma, bits) == k - 1, (k, float(lo))
+        for x, side in ((f, 1), (lo, -1)):
+            u = (G * Decimal(float(x)) + 1).ln() / B * qmax
+            min_margin = min(min_margin, side * (u - k))
+    # FP64 evaluation errs by a few ulps of log1p (<= 5) scaled by qmax / beta
+    # (<= 1639) plus the rounding of the product: below 5e-12 code units;
+    # the nearest binary32 input to any boundary is 3.7e-10 away (13 bits)
+    assert min_margin > Decimal("1e-10"), min_margin
+    # saturation: everything at or above t_qmax is qmax
+    assert oracle.pack_encode(3.0e38, beta, gamma, bits) == qmax
+    assert oracle.pack_encode(0.0, beta, gamma, bits) == 0
+    assert oracle.pack_encode(-1.0, beta, gamma, bits) == 0
+
+
+@pytest.mark.parametrize("beta,gamma,bits", PACK_CHANNELS)
+def test_packed_decode_is_the_rounded_exact_value(beta, gamma, bits):
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    qmax = (1 << bits) - 1
+    B, G = Decimal(beta), Decimal(gamma)
+    for q in range(qmax + 1):
+        d = ((B * q / qmax).exp() - 1) / G
+        f = np.float32(float(d))
+        cands = [_f32_down(f), f, _f32_up(f)]
+        best = min(cands, key=lambda c: (abs(Decimal(float(c)) - d), int(np.float32(c).view(np.uint32)) & 1))
+        assert oracle.pack_decode(q, beta, gamma, bits) == float(best), (q, float(best))
+
+
+@pytest.mark.parametrize("beta,gamma,bits", PACK_CHANNELS)
 def test_packed_encode_closed_form(beta, gamma, bits):
     qmax = (1 << bits) - 1
     rng = np.random.default_rng(bits)
