@@ -133,61 +133,29 @@ __device__ __forceinline__ void border_source(int X, int Y, int r, int& sx, int&
 }
 
 // ------------------------------------------------------- packed texels
-// The 32-bit texel words of eq. rgbEnc store floor decisions on binary32
-// values, so ln and exp are written out here from IEEE operations alone
-// (explicit fmaf, correctly rounded division), not taken from a math library
-// whose last bits may change: ln by m 2^e reduction and the atanh series of
-// ln m to s^11; exp by Cody-Waite reduction to |r| <= ln2/2 and the Taylor
-// series to r^7; ln 2 split into a 16-bit head and a tail.
-constexpr float kPkLn2Hi = 0.693145751953125f;
-constexpr float kPkLn2Lo = 1.42860682030941723212e-6f;
-
-__device__ __forceinline__ float pk_ln(float y) {  // y >= 1
-  const uint32_t b = __float_as_uint(y);
-  int e = (int)((b >> 23) & 0xFFu) - 127;
-  float m = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
-  if (m > 1.41421356f) {
-    m = m * 0.5f;
-    e = e + 1;
-  }
-  const float s = (m - 1.0f) / (m + 1.0f);
-  const float s2 = s * s;
-  float p = fmaf(s2, 1.0f / 11.0f, 1.0f / 9.0f);
-  p = fmaf(s2, p, 1.0f / 7.0f);
-  p = fmaf(s2, p, 1.0f / 5.0f);
-  p = fmaf(s2, p, 1.0f / 3.0f);
-  p = fmaf(s2, p, 1.0f);
-  const float lnm = 2.0f * s * p;
-  const float fe = (float)e;
-  return fmaf(fe, kPkLn2Hi, fmaf(fe, kPkLn2Lo, lnm));
-}
-
-__device__ __forceinline__ float pk_exp(float x) {  // 0 <= x <= 16
-  const float k = rintf(x * 1.44269504f);
-  float r = fmaf(-k, kPkLn2Hi, x);
-  r = fmaf(-k, kPkLn2Lo, r);
-  float p = fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
-  p = fmaf(r, p, 1.0f / 120.0f);
-  p = fmaf(r, p, 1.0f / 24.0f);
-  p = fmaf(r, p, 1.0f / 6.0f);
-  p = fmaf(r, p, 0.5f);
-  p = fmaf(r, p, 1.0f);
-  p = fmaf(r, p, 1.0f);
-  return p * __uint_as_float((uint32_t)((int)k + 127) << 23);
-}
-
-// code = floor(min(ln(gamma v + 1), beta) / beta * (2^bits - 1)), v >= 0
-__device__ __forceinline__ uint32_t pk_encode(float v, float beta, float gamma, int bits) {
-  const float qmax = (float)((1u << bits) - 1u);
+// Code of a binary32 value x >= 0 in a channel of eq. rgbEnc (beta, gamma,
+// qmax = 2^bits - 1): floor(qmax min(ln(gamma x + 1), beta) / beta), the
+// exact floor (App. B rounds down). Code k begins at t_k = (e^(beta k /
+// qmax) - 1) / gamma, and the decoded value D_k is t_k rounded to nearest,
+// so x >= t_k exactly when x > D_k, or x == D_k and D_k was rounded up (one
+// bit per code, `up`). With k the estimate qmax log2(gamma x + 1) ln 2 /
+// beta (hardware base-2 log, 1 ulp: within 2e-3 code units) rounded to the
+// nearest integer, the exact code is k or k - 1, and that one comparison
+// decides. dec and up are indexed by base + k (the channel's table).
+template <int BITS>
+__device__ __forceinline__ uint32_t pk_encode(float v, float beta, float gamma, const float* dec, const uint32_t* up,
+                                              int base) {
+  constexpr uint32_t qmax = (1u << BITS) - 1u;
   const float x = v > 0.0f ? v : 0.0f;
-  const float u = fminf(pk_ln(fmaf(gamma, x, 1.0f)), beta) / beta;
-  const float q = floorf(u * qmax);
-  return q >= qmax ? (uint32_t)qmax : (uint32_t)q;
-}
-
-__device__ __forceinline__ float pk_decode(uint32_t q, float beta, float gamma, int bits) {
-  const float qmax = (float)((1u << bits) - 1u);
-  return (pk_exp(beta * ((float)q / qmax)) - 1.0f) / gamma;
+  // qmax ln 2 / beta, rounded once (beta is a literal of the channel)
+  const float scale = (float)((double)qmax * 0.69314718055994530942 / (double)beta);
+  const float kr = rintf(__builtin_amdgcn_logf(fmaf(gamma, x, 1.0f)) * scale);
+  const uint32_t k = kr < 0.5f ? 0u : kr > (float)qmax ? qmax : (uint32_t)kr;
+  const int t = base + (int)k;
+  const float d = dec[t];
+  const bool rounded_up = (up[t >> 5] >> (t & 31)) & 1u;
+  const bool reached = x > d || (x == d && rounded_up);  // code 0: D_0 = 0, rounded up
+  return reached ? k : k - 1u;
 }
 
 // ------------------------------------------------------------ ray tests

@@ -65,18 +65,20 @@ struct BlendIO {
   uint8_t* irr_n_out;
   uint8_t* dep_n_out;
 };
+// Once per volume before its first blend (ADGI_PACKED raises the packed
+// kernel's dynamic LDS limit).
+hipError_t blend_prepare(int irr_res, int dep_res, int storage);
 // chunk = 0 selects the wave-per-probe kernel (tile sizes 8/16 and 16/16) with
 // `grid` workgroups walking the allocation's probe order; otherwise one
 // workgroup per probe with `chunk` rays staged per step.
-// storage: ADGI_FP32, ADGI_FP16 or ADGI_PACKED (wave kernel only)
+// storage: ADGI_FP32, ADGI_FP16 or ADGI_PACKED (wave kernel only; packed:
+// `grid` workgroups of 16 waves, one per CU)
 // chain: the lists are chain samples (wave kernel; not with ADGI_PACKED)
 // gather: DDGI's cosine-weighted gather instead of the per-sample update
 // (wave kernel; not with ADGI_PACKED or chain frames)
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,
                         int grid = 0, bool chain = false, bool gather = false);
 bool blend_wave_supported(const VolumeView& v);
-// Fills the table of decoded values of every packed code (v.pk_dec).
-hipError_t launch_packed_decode_table(float* dec, hipStream_t s);
 size_t blend_lds_bytes(const VolumeView& v, int chunk);
 
 // refit.hip

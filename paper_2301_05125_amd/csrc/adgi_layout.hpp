@@ -24,6 +24,7 @@ constexpr int kOrderBuckets = 32;               // blend order: 64-ray chunks pe
 constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
 constexpr int kPkDecIrr9 = 0, kPkDecIrr8 = 512, kPkDecTau = 768, kPkDecTau2 = 768 + 8192;
 constexpr int kPkDecSize = 768 + 2 * 8192;      // decoded values of all packed codes
+constexpr int kPkUpWords = (kPkDecSize + 31) / 32;  // one bit per code: decoded value rounded up
 constexpr float kShadowOffset = 1e-4f;          // shadow origin offset, units of s
 constexpr float kShadowShorten = 1e-6f;         // relative shortening of shadow rays
 
@@ -167,6 +168,7 @@ struct VolumeView {
   int32_t pdx, pdy, pdz;      // proxy grid
   uint8_t* dbg_accept;        // [C][steps] (debug)
   const float* pk_dec;        // packed storage: decoded value of every code
+  const uint32_t* pk_up;      // packed storage: bit k set if pk_dec[k] >= the exact value
                               // [irr 9-bit 512 | irr 8-bit 256 | tau 8192 | tau^2 8192]
   // trace / blend
   float4* rec;                // [max_rays] radiance RGB, t

@@ -863,70 +863,45 @@ __global__ __launch_bounds__(256) void blend_gather_kernel(VolumeView v, BlendIO
 }
 
 // ---------------------------------------------------------------------------
-// Packed 32-bit texels: the same wave-per-probe walk, with each interior
-// texel's word in its owner lane's registers. A sample decodes the word,
-// applies the moving average in binary32 and re-encodes it (the paper's
-// per-sample update of Alg. AtomicMovingAvg; a probe belongs to one wave, so
-// no compare-and-swap is needed). Counts saturate at 63 (6 bits).
-// Decoding goes through tables of pk_decode over every code (built once per
-// volume, bitwise the same values); the irradiance tables sit in LDS.
-__global__ void packed_decode_table_kernel(float* dec) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kPkDecSize) return;
-  float v;
-  if (k < kPkDecIrr8) v = pk_decode((uint32_t)k, 5.0f, 15.0f, 9);
-  else if (k < kPkDecTau) v = pk_decode((uint32_t)(k - kPkDecIrr8), 5.0f, 15.0f, 8);
-  else if (k < kPkDecTau2) v = pk_decode((uint32_t)(k - kPkDecTau), 5.0f, 15.0f, 13);
-  else v = pk_decode((uint32_t)(k - kPkDecTau2), 8.0f, 20.0f, 13);
-  dec[k] = v;
-}
-
-hipError_t launch_packed_decode_table(float* dec, hipStream_t s) {
-  hipLaunchKernelGGL(packed_decode_table_kernel, dim3((kPkDecSize + 255) / 256), dim3(256), 0, s, dec);
-  return hipGetLastError();
-}
-
-__device__ __forceinline__ uint32_t packed_rgb(uint32_t w, float4 r, const float* alpha, const float* dec_irr) {
-  uint32_t N = w >> 26;
-  const float al = alpha[N];
-  const float o0 = dec_irr[kPkDecIrr9 + (w & 0x1FFu)];
-  const float o1 = dec_irr[kPkDecIrr9 + ((w >> 9) & 0x1FFu)];
-  const float o2 = dec_irr[kPkDecIrr8 + ((w >> 18) & 0xFFu)];
-  const uint32_t c0 = pk_encode(fmaf(al, r.x - o0, o0), 5.0f, 15.0f, 9);
-  const uint32_t c1 = pk_encode(fmaf(al, r.y - o1, o1), 5.0f, 15.0f, 9);
-  const uint32_t c2 = pk_encode(fmaf(al, r.z - o2, o2), 5.0f, 15.0f, 8);
-  N = N < 63u ? N + 1u : 63u;
-  return c0 | (c1 << 9) | (c2 << 18) | (N << 26);
-}
-
-__device__ __forceinline__ uint32_t packed_tau(uint32_t w, float t, float inv_s, float tmax, const float* alpha,
-                                               const float* __restrict__ dec) {
-  uint32_t N = w >> 26;
-  const float al = alpha[N];
-  const float tau = fminf(t * inv_s, tmax);
-  const float p0 = dec[kPkDecTau + (w & 0x1FFFu)];
-  const float p1 = dec[kPkDecTau2 + ((w >> 13) & 0x1FFFu)];
-  const uint32_t d0 = pk_encode(fmaf(al, tau - p0, p0), 5.0f, 15.0f, 13);
-  const uint32_t d1 = pk_encode(fmaf(al, tau * tau - p1, p1), 8.0f, 20.0f, 13);
-  N = N < 63u ? N + 1u : 63u;
-  return d0 | (d1 << 13) | (N << 26);
-}
+// Packed 32-bit texels (eq. rgbEnc, App. B): one wave per probe as in the
+// binary32 kernel, the probe's interior words staged in LDS and each chunk's
+// samples applied in rounds by rank. A sample decodes its texel's word,
+// applies the moving average in binary32 with the step of the word's count
+// and re-encodes it (the per-sample update of Alg. AtomicMovingAvg; a probe
+// belongs to one wave, so no compare-and-swap is needed). Counts saturate at
+// 63 (6 bits). The decoded value of every code (68.6 KB, exact values rounded
+// once, built on the host) and its rounding direction sit in LDS, so one
+// workgroup of kPkWaves waves holds a CU.
+constexpr int kPkWaves = 16;
 
 template <int RI, int RD>
-__device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i, uint8_t* wbase,
-                                   const uint16_t* tab, const float* alpha, const float* dec_irr) {
-  using W = WaveTile<RI, RD>;
-  constexpr int NI = W::NI, ND = W::ND, SI = W::SI, SD = W::SD, GI = W::GI, GD = W::GD;
+struct PackedTile {
+  static constexpr int NI = RI * RI, ND = RD * RD, NT = NI + ND, GI = RI + 2, GD = RD + 2;
+  // per wave: the interior words (irradiance, then depth), then one 64-bit
+  // lane mask per interior texel
+  static constexpr size_t kMasks = (4 * (size_t)NT + 7) & ~(size_t)7;
+  static constexpr size_t kWaveBytes = kMasks + 8 * (size_t)NT;
+  static constexpr size_t kTabBytes = (2 * (GI * GI * 3 + GD * GD * 2) + 15) & ~(size_t)15;
+  static constexpr size_t kBlockBytes =
+      kPkWaves * kWaveBytes + kTabBytes + 64 * 4 + 4 * (size_t)kPkDecSize + 4 * (size_t)kPkUpWords;
+};
+
+template <int RI, int RD>
+__device__ __forceinline__ void packed_probe(const VolumeView& v, const BlendIO& io, int i, uint32_t off,
+                                             uint32_t n, uint8_t* wbase, const uint16_t* tab, const float* alpha,
+                                             const float* dec, const uint32_t* up, float inv_s, float tmax) {
+  using PT = PackedTile<RI, RD>;
+  constexpr int NI = PT::NI, ND = PT::ND, GI = PT::GI, GD = PT::GD;
+  constexpr int SI = (NI + 63) / 64, SD = (ND + 63) / 64;
   const int lane = threadIdx.x & 63;
-  float4* rec_s = (float4*)wbase;
-  unsigned long long* mask = (unsigned long long*)(wbase + 64 * 16);  // [NI | ND]
+  uint32_t* words = (uint32_t*)wbase;
+  uint64_t* mk = (uint64_t*)(wbase + PT::kMasks);
   const uint32_t* irr_in = (const uint32_t*)io.irr_in + (size_t)i * GI * GI;
   const uint32_t* dep_in = (const uint32_t*)io.dep_in + (size_t)i * GD * GD;
   uint32_t wi[SI], wd[SD];
 #pragma unroll
   for (int s = 0; s < SI; ++s) {
     const int k = lane + 64 * s;
-    wi[s] = 0u;
     if (k < NI) {
       const int iy = k / RI, ix = k - iy * RI;
       wi[s] = irr_in[(iy + 1) * GI + ix + 1];
@@ -935,92 +910,132 @@ __device__ void blend_probe_packed(const VolumeView& v, const BlendIO& io, int i
 #pragma unroll
   for (int s = 0; s < SD; ++s) {
     const int k = lane + 64 * s;
-    wd[s] = 0u;
     if (k < ND) {
       const int iy = k / RD, ix = k - iy * RD;
       wd[s] = dep_in[(iy + 1) * GD + ix + 1];
     }
   }
-  const uint32_t off = v.offsets[i];
-  const uint32_t n = v.offsets[i + 1] - off;
-  const float inv_s = 1.0f / v.s_diag;
-  const float tmax = v.tau_max;
   float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-  if ((uint32_t)lane < n) nxt = v.rec[off + lane];
+  uint32_t nbin = 0u;
+  if ((uint32_t)lane < n) {
+    nxt = v.rec[off + lane];
+    nbin = v.ray_bins[off + lane];
+  }
+#pragma unroll
+  for (int s = 0; s < SI; ++s)
+    if (lane + 64 * s < NI) words[lane + 64 * s] = wi[s];
+#pragma unroll
+  for (int s = 0; s < SD; ++s)
+    if (lane + 64 * s < ND) words[NI + lane + 64 * s] = wd[s];
+  wave_sync();
   for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
     const uint32_t m = min(64u, n - c0);
     const float4 cur = nxt;
-    if (c0 + 64u + (uint32_t)lane < n) nxt = v.rec[off + c0 + 64u + lane];
-    for (int k = lane; k < NI + ND; k += 64) mask[k] = 0ull;
-    wave_sync();
-    if ((uint32_t)lane < m) {
-      const uint32_t j = c0 + (uint32_t)lane;
-      rec_s[lane] = cur;
-      const uint32_t bins = v.ray_bins[off + j];
-      atomicOr(&mask[bins & 0xFFFFu], 1ull << lane);
-      atomicOr(&mask[NI + (bins >> 16)], 1ull << lane);
+    const uint32_t cbin = nbin;
+    if (c0 + 64u + (uint32_t)lane < n) {
+      nxt = v.rec[off + c0 + 64u + lane];
+      nbin = v.ray_bins[off + c0 + 64u + lane];
+    }
+    const bool act = (uint32_t)lane < m;
+    const uint32_t bI = cbin & 0xFFFFu, bD = NI + (cbin >> 16);
+    // the chunk's lanes in this lane's texels (as in the binary32 kernel)
+    uint64_t mI = 0ull, mD = 0ull;
+    if (act) {
+      atomicOr((unsigned long long*)&mk[bI], 1ull << lane);
+      atomicOr((unsigned long long*)&mk[bD], 1ull << lane);
     }
     wave_sync();
-#pragma unroll
-    for (int s = 0; s < SI; ++s) {
-      const int k = lane + 64 * s;
-      unsigned long long mk = k < NI ? mask[k] : 0ull;
-      while (mk) {
-        const int j = __ffsll((long long)mk) - 1;
-        mk &= mk - 1ull;
-        wi[s] = packed_rgb(wi[s], rec_s[j], alpha, dec_irr);
+    if (act) {
+      mI = mk[bI];
+      mD = mk[bD];
+    }
+    wave_sync();
+    if (act) {
+      mk[bI] = 0ull;
+      mk[bD] = 0ull;
+    }
+    const uint32_t rI = lanes_below(mI), rD = lanes_below(mD);
+    const uint32_t rmax = act ? max(rI, rD) : 0u;
+    const float tau = fminf(cur.w * inv_s, tmax);
+    const float tau2 = tau * tau;
+    for (uint32_t r = 0;; ++r) {
+      if (act && rI == r) {
+        const uint32_t w = words[bI];
+        const uint32_t N = w >> 26;
+        const float al = alpha[N];
+        const float o0 = dec[kPkDecIrr9 + (w & 0x1FFu)];
+        const float o1 = dec[kPkDecIrr9 + ((w >> 9) & 0x1FFu)];
+        const float o2 = dec[kPkDecIrr8 + ((w >> 18) & 0xFFu)];
+        const uint32_t q0 = pk_encode<9>(fmaf(al, cur.x - o0, o0), 5.0f, 15.0f, dec, up, kPkDecIrr9);
+        const uint32_t q1 = pk_encode<9>(fmaf(al, cur.y - o1, o1), 5.0f, 15.0f, dec, up, kPkDecIrr9);
+        const uint32_t q2 = pk_encode<8>(fmaf(al, cur.z - o2, o2), 5.0f, 15.0f, dec, up, kPkDecIrr8);
+        words[bI] = q0 | (q1 << 9) | (q2 << 18) | (min(N + 1u, 63u) << 26);
       }
-    }
-#pragma unroll
-    for (int s = 0; s < SD; ++s) {
-      const int k = lane + 64 * s;
-      unsigned long long mk = k < ND ? mask[NI + k] : 0ull;
-      while (mk) {
-        const int j = __ffsll((long long)mk) - 1;
-        mk &= mk - 1ull;
-        wd[s] = packed_tau(wd[s], rec_s[j].w, inv_s, tmax, alpha, v.pk_dec);
+      if (act && rD == r) {
+        const uint32_t w = words[bD];
+        const uint32_t N = w >> 26;
+        const float al = alpha[N];
+        const float p0 = dec[kPkDecTau + (w & 0x1FFFu)];
+        const float p1 = dec[kPkDecTau2 + ((w >> 13) & 0x1FFFu)];
+        const uint32_t d0 = pk_encode<13>(fmaf(al, tau - p0, p0), 5.0f, 15.0f, dec, up, kPkDecTau);
+        const uint32_t d1 = pk_encode<13>(fmaf(al, tau2 - p1, p1), 8.0f, 20.0f, dec, up, kPkDecTau2);
+        words[bD] = d0 | (d1 << 13) | (min(N + 1u, 63u) << 26);
       }
+      wave_sync();
+      if (ballot(rmax > r) == 0ull) break;
     }
-    wave_sync();
   }
-  // stage the interior words, then write both tiles with the border fold
-  uint32_t* stW = (uint32_t*)wbase;
-#pragma unroll
-  for (int s = 0; s < SI; ++s) {
-    const int k = lane + 64 * s;
-    if (k < NI) stW[k] = wi[s];
-  }
-#pragma unroll
-  for (int s = 0; s < SD; ++s) {
-    const int k = lane + 64 * s;
-    if (k < ND) stW[NI + k] = wd[s];
-  }
-  wave_sync();
+  // both tiles with the border fold (channel 0 of a tile texel names its
+  // interior texel)
   uint32_t* irr_out = (uint32_t*)io.irr_out + (size_t)i * GI * GI;
   uint32_t* dep_out = (uint32_t*)io.dep_out + (size_t)i * GD * GD;
-  // the fold table maps tile channel elements to interior channel elements;
-  // channel 0 of a texel gives its interior texel
-  for (int f = lane; f < GI * GI; f += 64) irr_out[f] = stW[tab[3 * f] / 3];
-  for (int f = lane; f < GD * GD; f += 64) dep_out[f] = stW[NI + tab[GI * GI * 3 + 2 * f] / 2];
+  for (int f = lane; f < GI * GI; f += 64) irr_out[f] = words[tab[3 * f] / 3];
+  for (int f = lane; f < GD * GD; f += 64) dep_out[f] = words[NI + tab[GI * GI * 3 + 2 * f] / 2];
   wave_sync();
 }
 
 template <int RI, int RD>
-__global__ __launch_bounds__(256) void blend_packed_kernel(VolumeView v, BlendIO io) {
-  using W = WaveTile<RI, RD>;
+__global__ __launch_bounds__(kPkWaves * 64) void blend_packed_kernel(VolumeView v, BlendIO io,
+                                                                    const int32_t* __restrict__ order,
+                                                                    const uint32_t* __restrict__ offsets) {
+  using PT = PackedTile<RI, RD>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  uint16_t* tab = (uint16_t*)(smem + 4 * W::kWaveBytes);
-  float* alpha = (float*)(smem + 4 * W::kWaveBytes + W::kTabBytes);
+  uint16_t* tab = (uint16_t*)(smem + kPkWaves * PT::kWaveBytes);
+  float* alpha = (float*)(smem + kPkWaves * PT::kWaveBytes + PT::kTabBytes);
+  float* dec = alpha + 64;
+  uint32_t* up = (uint32_t*)(dec + kPkDecSize);
   build_fold_tables<RI, RD>(tab);
-  float* dec_irr = alpha + 256;  // kPkDecTau floats
-  for (int k = threadIdx.x; k < 256; k += blockDim.x)
-    alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
-  for (int k = threadIdx.x; k < kPkDecTau; k += blockDim.x) dec_irr[k] = v.pk_dec[k];
+  // step weight of Alg. MovingAvgUpdate by the word's count N <= 63
+  for (int k = threadIdx.x; k < 64; k += blockDim.x) alpha[k] = fmaxf(1.0f / (float)(k + 1), v.one_minus_h);
+  for (int k = threadIdx.x; k < kPkDecSize; k += blockDim.x) dec[k] = v.pk_dec[k];
+  for (int k = threadIdx.x; k < kPkUpWords; k += blockDim.x) up[k] = v.pk_up[k];
+  uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * PT::kWaveBytes;
+  const int lane = threadIdx.x & 63;
+  for (int k = lane; k < PT::NT; k += 64) ((uint64_t*)(wbase + PT::kMasks))[k] = 0ull;
   __syncthreads();
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  uint8_t* wbase = smem + (size_t)(threadIdx.x >> 6) * W::kWaveBytes;
-  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < (uint32_t)v.P; q += waves)
-    blend_probe_packed<RI, RD>(v, io, v.order[q], wbase, tab, alpha, dec_irr);
+  const uint32_t P = (uint32_t)v.P;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (first >= P) return;
+  const uint32_t nq = (P - first + waves - 1u) / waves;
+  const float inv_s = 1.0f / v.s_diag;
+  const float tmax = v.tau_max;
+  for (uint32_t base = 0; base < nq; base += 64u) {
+    const uint32_t k = base + (uint32_t)lane;
+    int ik = 0;
+    uint32_t ok = 0u, ek = 0u;
+    if (k < nq) {
+      ik = order[first + k * waves];
+      ok = offsets[ik];
+      ek = offsets[ik + 1];
+    }
+    const uint32_t cnt = min(64u, nq - base);
+    for (uint32_t kk = 0; kk < cnt; ++kk) {
+      const uint32_t off = __builtin_amdgcn_readlane(ok, kk);
+      packed_probe<RI, RD>(v, io, __builtin_amdgcn_readlane(ik, kk), off, __builtin_amdgcn_readlane(ek, kk) - off,
+                           wbase, tab, alpha, dec, up, inv_s, tmax);
+    }
+  }
 }
 
 bool blend_wave_supported(const VolumeView& v) {
@@ -1035,7 +1050,7 @@ template <int RI, int RD>
 static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int grid,
                          bool chain, bool gather) {
   using W = WaveTile<RI, RD>;
-  const size_t lds = W::kBlockBytes;
+  const size_t lds = W::kBlockBytes, lds_pk = PackedTile<RI, RD>::kBlockBytes;
   if (gather && storage == ADGI_FP16)
     hipLaunchKernelGGL((blend_gather_kernel<RI, RD, true>), dim3(grid), dim3(256), lds, s, v, io);
   else if (gather)
@@ -1045,11 +1060,26 @@ static void launch_sched(const VolumeView& v, const BlendIO& io, hipStream_t s, 
   else if (chain)
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, true>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
   else if (storage == ADGI_PACKED)
-    hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(256), lds + 4 * kPkDecTau, s, v, io);
+    hipLaunchKernelGGL((blend_packed_kernel<RI, RD>), dim3(grid), dim3(kPkWaves * 64), lds_pk, s, v, io, v.order,
+                       v.offsets);
   else if (storage == ADGI_FP16)
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, true, false>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
   else
     hipLaunchKernelGGL((blend_wave_kernel<RI, RD, false, false>), dim3(grid), dim3(256), lds, s, v, io, v.order, v.offsets);
+}
+
+// The packed kernel's workgroup takes more LDS than the default dynamic
+// limit: raised once per tile shape, before any launch (and outside graph
+// capture).
+hipError_t blend_prepare(int irr_res, int dep_res, int storage) {
+  if (storage != ADGI_PACKED) return hipSuccess;
+  if (irr_res == 8 && dep_res == 16)
+    return hipFuncSetAttribute((const void*)blend_packed_kernel<6, 14>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)PackedTile<6, 14>::kBlockBytes);
+  if (irr_res == 16 && dep_res == 16)
+    return hipFuncSetAttribute((const void*)blend_packed_kernel<14, 14>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)PackedTile<14, 14>::kBlockBytes);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_blend(const VolumeView& v, const BlendIO& io, hipStream_t s, int storage, int chunk,

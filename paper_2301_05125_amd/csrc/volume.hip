@@ -237,8 +237,9 @@ hipError_t enqueue_blend(adgi_volume* vol, int mode, hipStream_t s) {
   const bool chain = mode == ADGI_MODE_CHAIN;
   BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
   const bool gather = vol->desc.blend_mode == ADGI_BLEND_GATHER;
-  return launch_blend(vol->v, io, s, vol->desc.storage, chain || gather ? 0 : t.blend_chunk,
-                      vol->num_cus * t.blend_blocks_per_cu, chain, gather);
+  // the packed kernel runs one workgroup per CU (its decode tables fill the LDS)
+  const int grid = vol->desc.storage == ADGI_PACKED ? vol->num_cus : vol->num_cus * t.blend_blocks_per_cu;
+  return launch_blend(vol->v, io, s, vol->desc.storage, chain || gather ? 0 : t.blend_chunk, grid, chain, gather);
 }
 
 bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
@@ -492,11 +493,34 @@ size_t dep_tile_bytes(const adgi_volume_desc& d) {
   return d.storage == ADGI_PACKED ? g * 4 : g * 2 * (d.storage == ADGI_FP16 ? 2 : 4);
 }
 
-// Host decode of a packed channel, (exp(beta q / qmax) - 1) / gamma, for the
-// FP32 readback view (the words themselves are the state).
+// The value packed code q stands for, (e^(beta q / qmax) - 1) / gamma (eq.
+// rgbEnc), in FP64 and rounded once to binary32.
 float packed_decode_host(uint32_t q, float beta, float gamma, int bits) {
   const double qmax = (double)((1u << bits) - 1u);
-  return (float)((std::exp((double)beta * (double)q / qmax) - 1.0) / (double)gamma);
+  return (float)(std::expm1((double)beta * ((double)q / qmax)) / (double)gamma);
+}
+
+// Decoded values of every code of the four packed channels, in the order of
+// the device table (R/G 9 bits, B 8 bits, tau and tau^2 13 bits), and after
+// them one bit per code, set where the decoded value was rounded up from the
+// exact one (so it is also the first binary32 value of its code); built once
+// and kept for the process.
+const std::vector<uint32_t>& packed_decode_table() {
+  static const std::vector<uint32_t> tab = [] {
+    std::vector<uint32_t> t(kPkDecSize + kPkUpWords, 0u);
+    for (int k = 0; k < kPkDecSize; ++k) {
+      const int c = k < kPkDecIrr8 ? 0 : k < kPkDecTau ? 1 : k < kPkDecTau2 ? 2 : 3;
+      const int q = k - (c == 0 ? 0 : c == 1 ? kPkDecIrr8 : c == 2 ? kPkDecTau : kPkDecTau2);
+      const double beta = c == 3 ? 8.0 : 5.0, gamma = c == 3 ? 20.0 : 15.0;
+      const double qmax = (double)((1u << (c == 0 ? 9 : c == 1 ? 8 : 13)) - 1u);
+      const double exact = std::expm1(beta * ((double)q / qmax)) / gamma;
+      const float d = (float)exact;
+      std::memcpy(&t[k], &d, 4);
+      if ((double)d >= exact) t[kPkDecSize + k / 32] |= 1u << (k % 32);
+    }
+    return t;
+  }();
+  return tab;
 }
 
 bool finite3(const float* x) { return std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]); }
@@ -775,7 +799,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   if (!(d->flags & ADGI_STATIC_SCRATCH))
     frame_scratch_each(v, (size_t)P, R, std::max(R, (size_t)P * 8),
                        [&](void** p, size_t bytes) { reqs.push_back({p, bytes}); });
-  if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)kPkDecSize * 4});
+  if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)(kPkDecSize + kPkUpWords) * 4});
   if (d->max_chains > 0) {
     const size_t C = (size_t)d->max_chains, Smax = R / 2;
     vol->sort_temp_bytes = chain_sort_temp_bytes((uint32_t)Smax, (int)P);
@@ -821,7 +845,12 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   }
   CREATE_TRY(hipEventRecord(vol->ev_traced, vol->stream));
   CREATE_TRY(hipEventRecord(vol->ev_refit, vol->stream));
-  if (d->storage == ADGI_PACKED) CREATE_TRY(launch_packed_decode_table((float*)v.pk_dec, vol->stream));
+  CREATE_TRY(blend_prepare(d->irr_res, d->depth_res, d->storage));
+  if (d->storage == ADGI_PACKED) {
+    const std::vector<uint32_t>& dec = packed_decode_table();  // lives for the process
+    CREATE_TRY(hipMemcpyAsync((void*)v.pk_dec, dec.data(), dec.size() * 4, hipMemcpyHostToDevice, vol->stream));
+    v.pk_up = (const uint32_t*)v.pk_dec + kPkDecSize;
+  }
   // Every reader of the zero-filled buffers runs on the volume's stream or
   // waits for it, so creation returns without waiting for the fill (which
   // may queue behind other volumes' work). The chain tables go after the
