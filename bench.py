@@ -416,6 +416,54 @@ def run_quality(adgi, torch, sc, cfg, tuning, frames=40, every=8, ref_rays=2304)
             "frames": frames, "every": every, "samplers": summary}
 
 
+def run_colour_slices(adgi, torch, n=256, scales=(1 / 256, 1 / 64, 1 / 16, 1 / 4, 1.0, 4.0, 8.0)):
+    """The packed irradiance encoding (R9 G9 B8, log, rounded down; through
+    the library's own encoder, adgi_pack_channel) against FP16 storage
+    (round to nearest) on slices of RGB space across the dynamic range, each
+    against the FP32 colours: at intensity scale s, the n x n slice
+    s (r, g, b0) over r, g in [0, 1] for b0 in {0, 1/2, 1}, and likewise
+    s (r0, g, b) for r0 in {0, 1/2, 1}. Errors as the paper's encoding
+    comparison reports them: luminance error, the r.m.s. difference of the
+    Rec. 709 luminance maps (also relative to the mean reference luminance),
+    and colour correlation, the normalised dot product of the flattened
+    colour maps."""
+    dev = torch.device("cuda")
+    t = torch.linspace(0.0, 1.0, n, device=dev, dtype=torch.float32)
+    a, b = torch.meshgrid(t, t, indexing="ij")
+    w = torch.tensor([0.2126, 0.7152, 0.0722], device=dev, dtype=torch.float64)
+    rows = {"packed_r9g9b8": [], "fp16": []}
+    for s in scales:
+        acc = {k: {"se": 0.0, "lum": 0.0, "dot": 0.0, "n_enc": 0.0, "n_ref": 0.0, "count": 0} for k in rows}
+        for fixed in (0.0, 0.5, 1.0):
+            c = torch.full_like(a, fixed)
+            for rgb in (torch.stack([a, b, c], -1), torch.stack([c, a, b], -1)):
+                ref = (rgb * s).contiguous()
+                _, d_rg = adgi.pack_channel(ref[..., :2].contiguous(), adgi.ADGI_PACK_RG9)
+                _, d_b = adgi.pack_channel(ref[..., 2].contiguous(), adgi.ADGI_PACK_B8)
+                enc = {"packed_r9g9b8": torch.cat([d_rg, d_b[..., None]], -1),
+                       "fp16": ref.half().float()}
+                r64 = ref.double()
+                y_ref = r64 @ w
+                for k, e in enc.items():
+                    e64 = e.double()
+                    dy = e64 @ w - y_ref
+                    A = acc[k]
+                    A["se"] += float((dy * dy).sum())
+                    A["lum"] += float(y_ref.sum())
+                    A["dot"] += float((e64 * r64).sum())
+                    A["n_enc"] += float((e64 * e64).sum())
+                    A["n_ref"] += float((r64 * r64).sum())
+                    A["count"] += int(dy.numel())
+        for k, A in acc.items():
+            rms = (A["se"] / A["count"]) ** 0.5
+            rows[k].append({"scale": s, "lum_rms": rms, "lum_rms_rel": rms / (A["lum"] / A["count"]),
+                            "colour_correlation": A["dot"] / ((A["n_enc"] * A["n_ref"]) ** 0.5)})
+    torch.cuda.synchronize()
+    return {"slices": f"{n}x{n} RGB slices s(r, g, b0) and s(r0, g, b), b0, r0 in {{0, 1/2, 1}}, "
+                      f"scales {list(scales)} (the packed range ends at (e^5 - 1)/15 = 9.83)",
+            "reference": "FP32 colours", **rows}
+
+
 def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
     """The oracle as it stands, on the host cores, on a bounded sample of the
     adaptive frame: the scene update, all pilot rays, detection and allocation
@@ -620,8 +668,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving mix and print its JSON (the bench runs it so, as a child)")
-    ap.add_argument("--quality", action="store_true",
-                    help="texel error against a converged reference: adaptive vs uniform vs chains")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the texel error against a converged reference (adaptive vs uniform vs chains)")
     ap.add_argument("--chains", default=",".join(CHAIN_CONFIGS),
                     help="comma-separated chain-frame configurations to run (none: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -805,7 +853,10 @@ def main():
             "roofline": {"bound": "alu", "achieved": gops / (stages_g[5] * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
                          "unit": "TFLOP/s", "frac": gops / (stages_g[5] * 1e-3) / 1e12 / VALU_PEAK_TOPS}}
         print("[bench] gather blend done", file=sys.stderr, flush=True)
-    if args.quality:
+    if not args.no_configs:
+        out["colour_slices"] = run_colour_slices(adgi, torch)
+        print("[bench] colour slices done", file=sys.stderr, flush=True)
+    if not args.no_quality:
         out["quality"] = run_quality(adgi, torch, sc, cfg, tuning)
         print("[bench] quality done", file=sys.stderr, flush=True)
     chain_names = [c for c in args.chains.split(",") if c and c != "none"]

@@ -405,6 +405,24 @@ typedef struct {
                                  azimuth order); 0 = index order                  */
 } adgi_tuning;
 
+/* ---- packed texel channels (eq. rgbEnc, App. B) ---------------------------
+ * Round trip of `count` binary32 values through one channel of the packed
+ * 32-bit texels, with the encoder and decode tables of the packed blend:
+ * codes[i] = floor(qmax min(ln(gamma x + 1), beta) / beta) (qmax = 2^bits - 1,
+ * the exact floor; x < 0 counts as 0) and decoded[i] = (e^(beta code / qmax)
+ * - 1) / gamma rounded to binary32. Channels: ADGI_PACK_RG9 (irradiance R and
+ * G, 9 bits, beta 5, gamma 15), ADGI_PACK_B8 (B, 8 bits, 5, 15),
+ * ADGI_PACK_TAU13 (mean distance, 13 bits, 5, 15), ADGI_PACK_TAU2_13 (mean
+ * squared distance, 13 bits, 8, 20). values, codes, decoded: device memory
+ * of `count` elements, owned by the caller; codes or decoded may be NULL.
+ * Enqueued on hip_stream (NULL: the default stream) on the current device,
+ * asynchronous; the first call on a device uploads the tables (68.6 KB,
+ * kept for the process). Errors: ADGI_ERR_INVALID_ARG (count < 0, unknown
+ * channel, NULL arrays), ADGI_ERR_DEVICE. */
+enum { ADGI_PACK_RG9 = 0, ADGI_PACK_B8 = 1, ADGI_PACK_TAU13 = 2, ADGI_PACK_TAU2_13 = 3 };
+adgi_status adgi_pack_channel(const float* values, int64_t count, int32_t channel, uint32_t* codes,
+                              float* decoded, void* hip_stream);
+
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);
 adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t);
 /* Time candidate launch shapes on the current scene and frame parameters

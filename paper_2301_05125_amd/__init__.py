@@ -182,6 +182,8 @@ def lib():
         L.adgi_update_scene.argtypes = [P, P]
         L.adgi_update_probes.argtypes = [P, P, P]
         L.adgi_update_probes_static.argtypes = [P, P, P]
+        L.adgi_pack_channel.argtypes = [P, C.c_int64, C.c_int32, P, P, P]
+        L.adgi_pack_channel.restype = C.c_int
         L.adgi_read_probes.argtypes = [P, P]
         L.adgi_destroy_volume.argtypes = [P]
         L.adgi_destroy_volume.restype = None
@@ -527,6 +529,23 @@ class Volume:
 
     def device_bytes(self) -> int:
         return int(lib().adgi_device_bytes(self.h))
+
+
+ADGI_PACK_RG9, ADGI_PACK_B8, ADGI_PACK_TAU13, ADGI_PACK_TAU2_13 = 0, 1, 2, 3
+
+
+def pack_channel(values, channel):
+    """Packed round trip of a CUDA float32 tensor through one channel
+    (adgi_pack_channel): returns (codes int32 tensor, decoded float32 tensor)."""
+    import torch
+    x = values.contiguous()
+    assert x.is_cuda and x.dtype == torch.float32
+    codes = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    dec = torch.empty_like(x)
+    _check(lib().adgi_pack_channel(C.c_void_p(x.data_ptr()), C.c_int64(x.numel()), C.c_int32(int(channel)),
+                                   C.c_void_p(codes.data_ptr()), C.c_void_p(dec.data_ptr()),
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return codes, dec
 
 
 def volume_for_scene(scene, storage=ADGI_FP32, max_rays=None, seed=1, debug=False,

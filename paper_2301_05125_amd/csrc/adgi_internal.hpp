@@ -65,6 +65,11 @@ struct BlendIO {
   uint8_t* irr_n_out;
   uint8_t* dep_n_out;
 };
+// Packed round trip of n device values through channel 0..3 (R/G 9 bits, B 8
+// bits, tau 13 bits, tau^2 13 bits); dec/up: the decode table and its
+// rounding bits (kPkDecSize floats, then kPkUpWords words).
+hipError_t launch_pack_channel(const float* x, int64_t n, int channel, const float* dec, const uint32_t* up,
+                               uint32_t* codes, float* decoded, hipStream_t s);
 // Once per volume before its first blend (ADGI_PACKED raises the packed
 // kernel's dynamic LDS limit).
 hipError_t blend_prepare(int irr_res, int dep_res, int storage);

@@ -1038,6 +1038,41 @@ __global__ __launch_bounds__(kPkWaves * 64) void blend_packed_kernel(VolumeView 
   }
 }
 
+// Round trip of n binary32 values through one packed channel with the
+// blend's encoder and tables: the code of each value and the value it
+// decodes to.
+__global__ void pack_channel_kernel(const float* __restrict__ x, int64_t n, int channel,
+                                    const float* __restrict__ dec, const uint32_t* __restrict__ up,
+                                    uint32_t* __restrict__ codes, float* __restrict__ decoded) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = x[i];
+  uint32_t q;
+  int base;
+  if (channel == 0) {
+    q = pk_encode<9>(v, 5.0f, 15.0f, dec, up, kPkDecIrr9);
+    base = kPkDecIrr9;
+  } else if (channel == 1) {
+    q = pk_encode<8>(v, 5.0f, 15.0f, dec, up, kPkDecIrr8);
+    base = kPkDecIrr8;
+  } else if (channel == 2) {
+    q = pk_encode<13>(v, 5.0f, 15.0f, dec, up, kPkDecTau);
+    base = kPkDecTau;
+  } else {
+    q = pk_encode<13>(v, 8.0f, 20.0f, dec, up, kPkDecTau2);
+    base = kPkDecTau2;
+  }
+  if (codes) codes[i] = q;
+  if (decoded) decoded[i] = dec[base + q];
+}
+
+hipError_t launch_pack_channel(const float* x, int64_t n, int channel, const float* dec, const uint32_t* up,
+                               uint32_t* codes, float* decoded, hipStream_t s) {
+  const int64_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(pack_channel_kernel, dim3((uint32_t)g), dim3(256), 0, s, x, n, channel, dec, up, codes, decoded);
+  return hipGetLastError();
+}
+
 bool blend_wave_supported(const VolumeView& v) {
   return (v.irr_res == 8 && v.dep_res == 16) || (v.irr_res == 16 && v.dep_res == 16);
 }

@@ -1715,6 +1715,44 @@ adgi_status adgi_query_irradiance(adgi_volume* vol, const float* points, const f
   return order_user_after(vol);
 }
 
+adgi_status adgi_pack_channel(const float* values, int64_t count, int32_t channel, uint32_t* codes, float* decoded,
+                              void* hip_stream) {
+  if (count < 0) return fail(ADGI_ERR_INVALID_ARG, "count must be >= 0");
+  if (channel < ADGI_PACK_RG9 || channel > ADGI_PACK_TAU2_13)
+    return fail(ADGI_ERR_INVALID_ARG, "channel must be ADGI_PACK_RG9, _B8, _TAU13 or _TAU2_13");
+  if (count > 0 && (!values || (!codes && !decoded))) return fail(ADGI_ERR_INVALID_ARG, "NULL array");
+  if (count > ((int64_t)1 << 40)) return fail(ADGI_ERR_INVALID_ARG, "count too large");
+  if (count == 0) return ADGI_OK;
+  // the decode table and rounding bits, one device copy per device for the
+  // process (uploaded on the first call on that device)
+  static std::mutex mu;
+  static std::map<int, void*> tables;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ADGI_ERR_DEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+  void* tab = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = tables.find(dev);
+    if (it == tables.end()) {
+      const std::vector<uint32_t>& host = packed_decode_table();
+      e = hipMalloc(&tab, host.size() * 4);
+      if (e == hipSuccess) e = hipMemcpy(tab, host.data(), host.size() * 4, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        if (tab) (void)hipFree(tab);
+        return fail(ADGI_ERR_DEVICE, "packed table upload failed: %s", hipGetErrorString(e));
+      }
+      tables[dev] = tab;
+    } else {
+      tab = it->second;
+    }
+  }
+  e = launch_pack_channel(values, count, channel, (const float*)tab, (const uint32_t*)tab + kPkDecSize, codes,
+                          decoded, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(ADGI_ERR_DEVICE, "pack_channel launch failed: %s", hipGetErrorString(e));
+  return ADGI_OK;
+}
+
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out) {
   if (!vol || !out) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
   *out = vol->tun;

@@ -71,3 +71,15 @@ def test_null_arguments():
     assert L.adgi_read_probes(None, None) == -1
     L.adgi_destroy_volume(None)  # no-op
     assert L.adgi_state_size(None) == 0
+
+
+def test_pack_channel_argument_checks():
+    """adgi_pack_channel validates before any device call; count 0 is a no-op."""
+    L = adgi.lib()
+    x = C.c_void_p(16)  # never dereferenced: every call here returns first
+    assert L.adgi_pack_channel(x, C.c_int64(-1), 0, x, x, None) == adgi.ADGI_ERR_INVALID_ARG
+    assert L.adgi_pack_channel(x, C.c_int64(4), 4, x, x, None) == adgi.ADGI_ERR_INVALID_ARG
+    assert L.adgi_pack_channel(x, C.c_int64(4), -1, x, x, None) == adgi.ADGI_ERR_INVALID_ARG
+    assert L.adgi_pack_channel(None, C.c_int64(4), 0, x, x, None) == adgi.ADGI_ERR_INVALID_ARG
+    assert L.adgi_pack_channel(x, C.c_int64(4), 0, None, None, None) == adgi.ADGI_ERR_INVALID_ARG
+    assert L.adgi_pack_channel(None, C.c_int64(0), 3, None, None, None) == adgi.ADGI_OK
