@@ -557,9 +557,10 @@ def run_serving_child(duration_s):
     line's top-level "errors"."""
     import subprocess
     try:
+        # ADGI_CRASH_TRACE: a fault there prints the library's native stack too
         r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
                             "--serve-seconds", str(duration_s)], capture_output=True, text=True,
-                           timeout=240 + 40 * duration_s)
+                           timeout=240 + 40 * duration_s, env=dict(os.environ, ADGI_CRASH_TRACE="1"))
     except subprocess.TimeoutExpired:
         return {"error": "serving process timed out"}
     sys.stderr.write(r.stderr[-3000:])

@@ -24,7 +24,9 @@ SOURCES = ["volume.hip", "trace.hip", "detect.hip", "alloc.hip", "blend.hip", "r
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
+# -Xarch_host -g1: line tables for the host code only, so that a native stack
+# printed at a fault (ADGI_CRASH_TRACE) maps to source lines
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off", "-Xarch_host", "-g1",
          "-Wall", "-Wno-unused-function",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          f"-I{os.path.join(ROOT, 'include')}"]

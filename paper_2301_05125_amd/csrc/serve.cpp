@@ -22,8 +22,14 @@
 // keeps its memory until its state copy has landed.
 #include <hip/hip_runtime.h>
 
+#include <execinfo.h>
+#include <signal.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <mutex>
 #include <atomic>
 #include <chrono>
 #include <cstring>
@@ -71,6 +77,38 @@ struct Pool {
   std::map<void*, size_t> size_of;
   int64_t held = 0;
 };
+
+// With ADGI_CRASH_TRACE set in the environment, a segmentation fault in a
+// process that created a server prints the native stack (symbols, or offsets
+// into the library for addr2line) to stderr, then hands the signal to the
+// handler installed before (Python's faulthandler, or the default action).
+struct sigaction g_prev_segv;
+
+void crash_trace(int sig, siginfo_t*, void*) {
+  void* frames[64];
+  const int n = backtrace(frames, 64);
+  static const char msg[] = "adgi: native stack at the fault:\n";
+  if (write(2, msg, sizeof(msg) - 1) < 0) {
+  }
+  backtrace_symbols_fd(frames, n, 2);
+  sigaction(SIGSEGV, &g_prev_segv, nullptr);
+  raise(sig);
+}
+
+void install_crash_trace() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    if (!std::getenv("ADGI_CRASH_TRACE")) return;
+    void* warm[1];
+    (void)backtrace(warm, 1);  // loads the unwinder now, not inside the handler
+    struct sigaction sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.sa_sigaction = crash_trace;
+    sa.sa_flags = SA_SIGINFO;
+    sigemptyset(&sa.sa_mask);
+    sigaction(SIGSEGV, &sa, &g_prev_segv);
+  });
+}
 
 void* pool_alloc(size_t bytes, void* ctx) {
   Pool* p = static_cast<Pool*>(ctx);
@@ -450,6 +488,7 @@ int64_t adgi_server_now_ns(void) { return now_ns(); }
 const char* adgi_server_last_error(void) { return g_serve_err; }
 
 adgi_status adgi_server_create(const adgi_server_desc* desc, const adgi_allocator* alloc, adgi_server** out) {
+  install_crash_trace();
   if (!desc || !out) return sfail(ADGI_ERR_INVALID_ARG, "desc and out must not be NULL");
   if (desc->hbm_budget_bytes <= 0 || desc->max_inflight < 1 || desc->max_inflight > 64)
     return sfail(ADGI_ERR_INVALID_ARG, "need hbm_budget_bytes > 0 and max_inflight in [1, 64]");

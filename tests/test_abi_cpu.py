@@ -83,3 +83,22 @@ def test_pack_channel_argument_checks():
     assert L.adgi_pack_channel(None, C.c_int64(4), 0, x, x, None) == adgi.ADGI_ERR_INVALID_ARG
     assert L.adgi_pack_channel(x, C.c_int64(4), 0, None, None, None) == adgi.ADGI_ERR_INVALID_ARG
     assert L.adgi_pack_channel(None, C.c_int64(0), 3, None, None, None) == adgi.ADGI_OK
+
+
+def test_crash_trace_prints_the_native_stack():
+    """With ADGI_CRASH_TRACE set, a process that created a server (here with
+    NULL arguments: no device call at all) prints the native stack on a
+    segmentation fault and then hands the signal on (Python's faulthandler
+    prints its stack, the process dies of SIGSEGV). The fault is a host-side
+    read of address 0 in a CPU-only child process."""
+    import subprocess
+    import sys
+    code = ("import sys, ctypes as C, faulthandler; faulthandler.enable(); "
+            f"sys.path.insert(0, {ROOT!r}); import paper_2301_05125_amd as adgi; "
+            "assert adgi.lib().adgi_server_create(None, None, None) == adgi.ADGI_ERR_INVALID_ARG; "
+            "C.string_at(0)")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       env=dict(os.environ, ADGI_CRASH_TRACE="1"))
+    assert r.returncode in (-11, 139), (r.returncode, r.stderr[-2000:])
+    assert "adgi: native stack at the fault" in r.stderr and "libadgi.so" in r.stderr, r.stderr[-2000:]
+    assert "Segmentation fault" in r.stderr
