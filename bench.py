@@ -498,7 +498,37 @@ def cpu_baseline(sc, budget, n_min, n_max, sample_probes=4096, frames=2):
             "extrapolated_ms_per_frame": frame_s * 1e3,
             "seconds": wall,
             "host": host_info(),
+            "box_field_fp16_storage": cpu_box_field_variants(oracle, sc, probes, budget, n_min, n_max),
             "other_workloads": cpu_small_workloads(oracle)}
+
+
+def cpu_box_field_variants(oracle, sc, probes, budget, n_min, n_max):
+    """The box field's FP16-storage frame (the texels rounded to binary16 after
+    every update, as the GPU's FP16 storage) on all threads, and its probe rays
+    on one thread, each on a bounded sample of probes: 1,024 probes for two
+    adaptive FP16 frames (probe-ray phase only, scaled to all B rays), 256
+    probes for one uniform frame of 128 rays per probe on one thread."""
+    out = {}
+    v16 = oracle.OracleVolume(sc, seed=7, fp16=True, probes=probes[:1024])
+    probes_s = 0.0
+    sample_rays = full_rays = 0
+    for f in range(2):
+        o = v16.update(f, adaptive=True, budget=budget, n_min=n_min, n_max=n_max)
+        probes_s += o["seconds"]["probes"]
+        sample_rays += o["counts"]["rays"]
+        full_rays += int(o["n"].sum())
+    out["fp16_probe_rays_per_s"] = sample_rays / max(probes_s, 1e-9)
+    out["fp16_sample"] = f"probe rays of 1024 sampled probes over 2 adaptive frames, {sample_rays} rays"
+    v1 = oracle.OracleVolume(sc, seed=7, probes=probes[:256])
+    nthreads = int(oracle.lib().orc_num_threads())
+    oracle.lib().orc_set_threads(1)
+    try:
+        o = v1.update(0, adaptive=False, n_uniform=128)
+    finally:
+        oracle.lib().orc_set_threads(nthreads)
+    out["one_thread_probe_rays_per_s"] = o["counts"]["rays"] / max(o["seconds"]["probes"], 1e-9)
+    out["one_thread_sample"] = f"probe rays of 256 sampled probes, 128 each, one thread, {o['counts']['rays']} rays"
+    return out
 
 
 def host_info():
