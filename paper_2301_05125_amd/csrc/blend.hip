@@ -37,6 +37,15 @@ struct Store<true> {
   __device__ static void store(T* p, float x) { *p = __float2half_rn(x); }
 };
 
+// The binary16 value in the low 16 bits of w, and two values rounded to
+// binary16 (nearest even) packed low | high << 16.
+__device__ __forceinline__ float half_bits(uint32_t w) {
+  return __half2float(__ushort_as_half((unsigned short)(w & 0xFFFFu)));
+}
+__device__ __forceinline__ uint32_t half_word(float lo, float hi) {
+  return (uint32_t)__half_as_ushort(__float2half_rn(lo)) | ((uint32_t)__half_as_ushort(__float2half_rn(hi)) << 16);
+}
+
 __device__ uint32_t block_scan_u32(uint32_t x, uint32_t* sm, uint32_t& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   uint32_t v = x;
@@ -380,9 +389,14 @@ __device__ __forceinline__ void plane_tau(float* sD, uint32_t k, float tau, floa
 template <int RI, int RD, bool HALF, bool CHAIN>
 struct ProbeRegs {
   using W = WaveTile<RI, RD>;
-  static constexpr int LI = (3 * W::NI + 63) / 64, LD = (2 * W::ND + 63) / 64;
+  // FP32: the interior channel values, row by row; FP16: 32-bit words of
+  // two halves, the whole irradiance tile (its rows start at odd halves) and
+  // the interior depth texels (one word each)
+  static constexpr int kIrrWords = W::GI * W::GI * 3 / 2;
+  static constexpr int LI = HALF ? (kIrrWords + 63) / 64 : (3 * W::NI + 63) / 64;
+  static constexpr int LD = HALF ? (W::ND + 63) / 64 : (2 * W::ND + 63) / 64;
   static constexpr int CI = (W::NI / 4 + 63) / 64, CD = (W::ND / 4 + 63) / 64;
-  float ti[LI], td[LD];
+  uint32_t ti[LI], td[LD];
   uint32_t ci[CI], cd[CD];
   float4 rec;
   uint32_t bins;  // budgeted frames: irradiance texel | depth texel << 16
@@ -413,22 +427,38 @@ __device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& i
   using G = ProbeRegs<RI, RD, HALF, CHAIN>;
   constexpr int NI = W::NI, ND = W::ND, GI = W::GI, GD = W::GD;
   const int lane = threadIdx.x & 63;
-  const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
-  const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
+  if constexpr (HALF) {
+    const uint32_t* irr_w = (const uint32_t*)io.irr_in + (size_t)i * G::kIrrWords;
+    const uint32_t* dep_w = (const uint32_t*)io.dep_in + (size_t)i * GD * GD;
 #pragma unroll
-  for (int s = 0; s < G::LI; ++s) {
-    const int f = lane + 64 * s;
-    if (f < 3 * NI) {
-      const int row = f / (3 * RI), col = f - row * (3 * RI);
-      g.ti[s] = S::load(irr_in + ((row + 1) * GI + 1) * 3 + col);
+    for (int s = 0; s < G::LI; ++s)
+      if (lane + 64 * s < G::kIrrWords) g.ti[s] = irr_w[lane + 64 * s];
+#pragma unroll
+    for (int s = 0; s < G::LD; ++s) {
+      const int k = lane + 64 * s;
+      if (k < ND) {
+        const int row = k / RD, col = k - row * RD;
+        g.td[s] = dep_w[(row + 1) * GD + col + 1];
+      }
     }
-  }
+  } else {
+    const T* irr_in = (const T*)io.irr_in + (size_t)i * GI * GI * 3;
+    const T* dep_in = (const T*)io.dep_in + (size_t)i * GD * GD * 2;
 #pragma unroll
-  for (int s = 0; s < G::LD; ++s) {
-    const int f = lane + 64 * s;
-    if (f < 2 * ND) {
-      const int row = f / (2 * RD), col = f - row * (2 * RD);
-      g.td[s] = S::load(dep_in + ((row + 1) * GD + 1) * 2 + col);
+    for (int s = 0; s < G::LI; ++s) {
+      const int f = lane + 64 * s;
+      if (f < 3 * NI) {
+        const int row = f / (3 * RI), col = f - row * (3 * RI);
+        g.ti[s] = __float_as_uint(S::load(irr_in + ((row + 1) * GI + 1) * 3 + col));
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < G::LD; ++s) {
+      const int f = lane + 64 * s;
+      if (f < 2 * ND) {
+        const int row = f / (2 * RD), col = f - row * (2 * RD);
+        g.td[s] = __float_as_uint(S::load(dep_in + ((row + 1) * GD + 1) * 2 + col));
+      }
     }
   }
   const uint32_t* ni_in = (const uint32_t*)(io.irr_n_in + (size_t)i * NI);
@@ -456,18 +486,42 @@ __device__ __forceinline__ void stage_probe(const ProbeRegs<RI, RD, HALF, CHAIN>
   float* sD = (float*)(wbase + W::kStD);
   uint32_t* nI = (uint32_t*)(sI + 3 * NI);
   uint32_t* nD = (uint32_t*)(sD + 2 * ND);
+  if constexpr (HALF) {
+    constexpr int GI = W::GI;
 #pragma unroll
-  for (int s = 0; s < G::LI; ++s) {
-    const int f = lane + 64 * s;
-    if (f < 3 * NI) {
-      const int k = f / 3;
-      sI[(f - 3 * k) * NI + k] = g.ti[s];
+    for (int s = 0; s < G::LI; ++s) {
+      const int w = lane + 64 * s;
+      if (w < G::kIrrWords) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int h = 2 * w + b, t = h / 3, c = h - 3 * t, Y = t / GI, X = t - Y * GI;
+          if (X >= 1 && X <= RI && Y >= 1 && Y <= RI)
+            sI[c * NI + (Y - 1) * RI + (X - 1)] = half_bits(g.ti[s] >> (16 * b));
+        }
+      }
     }
-  }
 #pragma unroll
-  for (int s = 0; s < G::LD; ++s) {
-    const int f = lane + 64 * s;
-    if (f < 2 * ND) sD[(f & 1) * ND + (f >> 1)] = g.td[s];
+    for (int s = 0; s < G::LD; ++s) {
+      const int k = lane + 64 * s;
+      if (k < ND) {
+        sD[k] = half_bits(g.td[s]);
+        sD[ND + k] = half_bits(g.td[s] >> 16);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < G::LI; ++s) {
+      const int f = lane + 64 * s;
+      if (f < 3 * NI) {
+        const int k = f / 3;
+        sI[(f - 3 * k) * NI + k] = __uint_as_float(g.ti[s]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < G::LD; ++s) {
+      const int f = lane + 64 * s;
+      if (f < 2 * ND) sD[(f & 1) * ND + (f >> 1)] = __uint_as_float(g.td[s]);
+    }
   }
   // counts: word w holds the counts of texels 4w .. 4w+3
 #pragma unroll
@@ -637,10 +691,20 @@ __device__ __forceinline__ void store_probe(const BlendIO& io, int i, const uint
   const int lane = threadIdx.x & 63;
   const float* sI = (const float*)(wbase + W::kStI);
   const float* sD = (const float*)(wbase + W::kStD);
-  T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
-  T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
-  for (int f = lane; f < GI * GI * 3; f += 64) S::store(irr_out + f, sI[tab[f]]);
-  for (int f = lane; f < GD * GD * 2; f += 64) S::store(dep_out + f, sD[tab[GI * GI * 3 + f]]);
+  if constexpr (HALF) {
+    // two halves per 32-bit store
+    uint32_t* irr_w = (uint32_t*)io.irr_out + (size_t)i * (GI * GI * 3 / 2);
+    uint32_t* dep_w = (uint32_t*)io.dep_out + (size_t)i * GD * GD;
+    for (int w = lane; w < GI * GI * 3 / 2; w += 64)
+      irr_w[w] = half_word(sI[tab[2 * w]], sI[tab[2 * w + 1]]);
+    for (int w = lane; w < GD * GD; w += 64)
+      dep_w[w] = half_word(sD[tab[GI * GI * 3 + 2 * w]], sD[tab[GI * GI * 3 + 2 * w + 1]]);
+  } else {
+    T* irr_out = (T*)io.irr_out + (size_t)i * GI * GI * 3;
+    T* dep_out = (T*)io.dep_out + (size_t)i * GD * GD * 2;
+    for (int f = lane; f < GI * GI * 3; f += 64) S::store(irr_out + f, sI[tab[f]]);
+    for (int f = lane; f < GD * GD * 2; f += 64) S::store(dep_out + f, sD[tab[GI * GI * 3 + f]]);
+  }
   uint32_t* ni_out = (uint32_t*)(io.irr_n_out + (size_t)i * NI);
   uint32_t* nd_out = (uint32_t*)(io.dep_n_out + (size_t)i * ND);
   const uint32_t* nI = (const uint32_t*)(sI + 3 * NI);

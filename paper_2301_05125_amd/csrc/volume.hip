@@ -1955,7 +1955,7 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   struct BlendCand {
     int chunk, bpc;
   };
-  const BlendCand bcands[] = {{0, 4}, {0, 8}, {0, 16}, {128, 8}, {256, 8}, {512, 8}};
+  const BlendCand bcands[] = {{0, 4}, {0, 5}, {0, 6}, {0, 8}, {0, 16}, {128, 8}, {256, 8}, {512, 8}};
   for (const BlendCand& bc : bcands) {
     if (err != hipSuccess) break;
     if (bc.chunk == 0 && !blend_wave_supported(vol->v)) continue;
