@@ -389,14 +389,15 @@ __device__ __forceinline__ void plane_tau(float* sD, uint32_t k, float tau, floa
 template <int RI, int RD, bool HALF, bool CHAIN>
 struct ProbeRegs {
   using W = WaveTile<RI, RD>;
-  // FP32: the interior channel values, row by row; FP16: 32-bit words of
-  // two halves, the whole irradiance tile (its rows start at odd halves) and
-  // the interior depth texels (one word each)
+  // FP32: the interior irradiance values row by row, and each interior
+  // depth texel's (tau, tau^2) as one 8-byte value (td, td2); FP16: 32-bit
+  // words of two halves, the whole irradiance tile (its rows start at odd
+  // halves) and the interior depth texels (one word each)
   static constexpr int kIrrWords = W::GI * W::GI * 3 / 2;
   static constexpr int LI = HALF ? (kIrrWords + 63) / 64 : (3 * W::NI + 63) / 64;
-  static constexpr int LD = HALF ? (W::ND + 63) / 64 : (2 * W::ND + 63) / 64;
+  static constexpr int LD = (W::ND + 63) / 64;
   static constexpr int CI = (W::NI / 4 + 63) / 64, CD = (W::ND / 4 + 63) / 64;
-  uint32_t ti[LI], td[LD];
+  uint32_t ti[LI], td[LD], td2[HALF ? 1 : LD];
   uint32_t ci[CI], cd[CD];
   float4 rec;
   uint32_t bins;  // budgeted frames: irradiance texel | depth texel << 16
@@ -452,12 +453,15 @@ __device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& i
         g.ti[s] = __float_as_uint(S::load(irr_in + ((row + 1) * GI + 1) * 3 + col));
       }
     }
+    const float2* dep2 = (const float2*)dep_in;
 #pragma unroll
     for (int s = 0; s < G::LD; ++s) {
-      const int f = lane + 64 * s;
-      if (f < 2 * ND) {
-        const int row = f / (2 * RD), col = f - row * (2 * RD);
-        g.td[s] = __float_as_uint(S::load(dep_in + ((row + 1) * GD + 1) * 2 + col));
+      const int k = lane + 64 * s;
+      if (k < ND) {
+        const int row = k / RD, col = k - row * RD;
+        const float2 m = dep2[(row + 1) * GD + col + 1];
+        g.td[s] = __float_as_uint(m.x);
+        g.td2[s] = __float_as_uint(m.y);
       }
     }
   }
@@ -519,8 +523,11 @@ __device__ __forceinline__ void stage_probe(const ProbeRegs<RI, RD, HALF, CHAIN>
     }
 #pragma unroll
     for (int s = 0; s < G::LD; ++s) {
-      const int f = lane + 64 * s;
-      if (f < 2 * ND) sD[(f & 1) * ND + (f >> 1)] = __uint_as_float(g.td[s]);
+      const int k = lane + 64 * s;
+      if (k < ND) {
+        sD[k] = __uint_as_float(g.td[s]);
+        sD[ND + k] = __uint_as_float(g.td2[s]);
+      }
     }
   }
   // counts: word w holds the counts of texels 4w .. 4w+3
