@@ -528,7 +528,9 @@ __device__ __forceinline__ void flush_stats(const VolumeView& v, const Work& w, 
 }
 
 // ---- closest-hit kernel
-// A wave owns 64 consecutive rays (batch b = rays [64b, 64b + 64)); a
+// A wave owns a batch of consecutive rays (batch b = rays [B b, B b + B),
+// B = v.batch_rays: 64, or 32 / 16 for a pass too small to give every CU
+// several waves, which then ends sooner with fewer rays per wave); a
 // persistent launch walks the batches with a grid stride, so no wave ever
 // waits on a shared counter. Every ray finds its closest hit. A miss, a back
 // face, a distance-only ray or a lit hit with no light on its front side is
@@ -541,14 +543,14 @@ template <int KIND, bool COUNT, bool W4>
 __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32_t b, uint32_t total, Work& w,
                                           uint32_t& shadow) {
   const SceneParams& sc = *v.scene;
-  const uint32_t lane = lane_id();
-  const uint32_t r = b * 64u + lane;
-  const bool active = r < total;
+  const uint32_t lane = lane_id(), br = v.batch_rays;
+  const uint32_t r = b * br + lane;
+  const bool active = lane < br && r < total;
   float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
   bool shade = true;
   uint32_t dst = r;
   // probe of the batch's first ray (the same in every lane)
-  const int i0 = KIND == KIND_PRIMARY ? probe_of_ray(v.offsets, v.P, b * 64u) : 0;
+  const int i0 = KIND == KIND_PRIMARY ? probe_of_ray(v.offsets, v.P, b * br) : 0;
   if (active) gen_ray<KIND>(v, r, i0, o, d, shade, dst);
   if (KIND == KIND_PILOT && active && v.fp->pilot_reuse) {
     const float2 uv = oct_encode(d);
@@ -622,7 +624,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_hit_kernel(Volu
   st.lds = (lds_u64*)smem + wave * (64 * kStackLds) + lane_id();
   st.sp = 0;
   const uint32_t total = ray_total<KIND>(v);
-  const uint32_t nbatch = (total + 63u) / 64u;
+  const uint32_t nbatch = (total + v.batch_rays - 1u) / v.batch_rays;
   const uint32_t waves = blockDim.x >> 6;
   const uint32_t first = blockIdx.x * waves + (uint32_t)wave;
   const uint32_t stride = persistent ? gridDim.x * waves : nbatch;
@@ -753,7 +755,7 @@ __device__ __forceinline__ void shade_batch(const VolumeView& v, Stack& st, uint
   }
   const uint32_t b = lo;
   const uint32_t e = v.pairs[(size_t)b * kPairsPerBatch + (p - v.pair_off[b])];
-  const uint32_t r = b * 64u + (e & 63u), l = e >> 6;
+  const uint32_t r = b * v.batch_rays + (e & 63u), l = e >> 6;
   const float4 pos = v.hit_pos[r], nrm = v.hit_nrm[r];
   const float off_len = kShadowOffset * v.s_diag;
   const float3 so = make_float3(fmaf(off_len, nrm.x, pos.x), fmaf(off_len, nrm.y, pos.y),

@@ -246,6 +246,18 @@ bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
   return t.bvh_width == 4 && vol->d_nodes4 != nullptr;
 }
 
+// Rays per wave of the pilot pass (8 P rays): 64, or 32 / 16 while 64 would
+// give the CUs fewer than 8 waves each and the pair lists have room for the
+// extra batches. Which lane traces which ray changes no result.
+uint32_t pilot_batch_rays(const adgi_volume* vol) {
+  const uint64_t total = 8ull * (uint64_t)vol->P, cap = ((uint64_t)vol->v.hit_cap + 63u) / 64u;
+  uint32_t br = 64u;
+  while (br > 16u && (total + br - 1u) / br < 8ull * (uint64_t)vol->num_cus &&
+         (total + br / 2u - 1u) / (br / 2u) <= cap)
+    br /= 2u;
+  return br;
+}
+
 // Stage boundaries recorded into ev[0..7] when ev is non-null (eager only):
 // 0 start, 1 frame_begin, 2 pilot trace, 3 detect | chains, 4 allocate |
 // blend order, 5 probe trace, 6 blend; 7 between the probe trace's
@@ -269,10 +281,16 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
   if ((e = mark(0)) != hipSuccess) return e;
   if ((e = launch_frame_begin(v, s)) != hipSuccess) return e;
   if ((e = mark(1)) != hipSuccess) return e;
+  const uint32_t pbr = pilot_batch_rays(vol);
+  // waves (64 threads each) that cover the pilot batches when not persistent
+  const int pilot_grid =
+      (int)(((8ull * (uint64_t)vol->P + pbr - 1u) / pbr * 64u + (uint64_t)t.trace_block - 1u) / (uint64_t)t.trace_block);
   if (chain && !count_work) {
-    int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
-    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, pgrid, false, w4)) != hipSuccess)
-      return e;
+    int grid = t.persistent ? pgrid : pilot_grid;
+    v.batch_rays = pbr;
+    e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, pgrid, false, w4);
+    v.batch_rays = 64u;
+    if (e != hipSuccess) return e;
     // detection keeps triggers and scores current (odd frames); the dynamic
     // chains read the box sums on every frame
     if (vol->frame_now & 1) {
@@ -296,9 +314,11 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
     if ((e = mark(2)) != hipSuccess) return e;
     if ((e = mark(3)) != hipSuccess) return e;
   } else if (adaptive) {
-    int grid = t.persistent ? pgrid : (8 * vol->P + t.trace_block - 1) / t.trace_block;
-    if ((e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, pgrid, false, w4)) != hipSuccess)
-      return e;
+    int grid = t.persistent ? pgrid : pilot_grid;
+    v.batch_rays = pbr;
+    e = launch_trace(v, s, true, t.persistent != 0, t.trace_block, grid, pgrid, false, w4);
+    v.batch_rays = 64u;
+    if (e != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_detect(v, s)) != hipSuccess) return e;
     if ((e = mark(3)) != hipSuccess) return e;
@@ -886,6 +906,7 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   v.tau_max = d->tau_max;
   v.max_rays = (uint32_t)R;
   v.hit_cap = (uint32_t)std::max(R, (size_t)P * 8);
+  v.batch_rays = 64u;
   if (blend_wave_supported(v)) vol->tun.blend_chunk = 0;
   if (d->blend_mode == ADGI_BLEND_GATHER) vol->tun.blend_chunk = 0;
   *out = vol;
