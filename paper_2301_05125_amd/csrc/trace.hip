@@ -26,8 +26,6 @@
 // Traversal is a while-while loop over the BVH2 or its 4-wide collapse, with
 // a short per-lane stack in LDS (deeper entries in private memory); a few
 // very large triangles sit outside the tree and every ray tests them first.
-#include <type_traits>
-
 #include "adgi_internal.hpp"
 
 namespace adgi {
@@ -44,17 +42,14 @@ enum { KIND_PRIMARY = 0, KIND_PILOT = 1, KIND_CHAIN = 2 };
 // inside theirs) with the same comparison.
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 
-// REGS: the deeper entries sit in an array of the kernel's own and the
-// struct holds a pointer, so sp stays in a register (with the array as a
-// member the whole struct, sp included, lives in private memory and every
-// push stores sp there). The closest-hit kernel is 7.5% faster that way; the
-// shading kernel keeps the member array: with sp in a register the compiler
-// merged its node and leaf loops into one and it ran 30% slower.
-template <bool REGS>
-struct StackT {
+// The deeper entries sit in an array of the kernel's own (private memory)
+// and the struct holds a pointer to it, so sp stays in a register: with the
+// array as a member the whole struct, sp included, lived in private memory
+// and every push stored sp there.
+struct Stack {
   lds_u64* lds;   // this lane's entry 0; an entry is (t bits << 32) | node
   int sp;
-  std::conditional_t<REGS, uint64_t*, uint64_t[kStackMax - kStackLds]> deep;
+  uint64_t* deep;
   __device__ __forceinline__ void push(int node, float t) {
     const uint64_t e = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)node;
     if (sp < kStackLds) {
@@ -87,9 +82,6 @@ struct StackT {
     return false;
   }
 };
-
-using HitStack = StackT<true>;
-using ShadeStack = StackT<false>;
 
 struct NodeData {
   float4 a, b, c;
@@ -149,9 +141,9 @@ __device__ __forceinline__ bool any_big(const VolumeView& v, const Ray& ray, flo
 
 // Closest hit: smallest t in (0, inf); equal t resolves to the lowest
 // original triangle index. Returns the triangle slot or -1.
-template <bool COUNT, class ST>
+template <bool COUNT>
 __device__ int closest_hit(const VolumeView& v, const Ray& ray,
-                           ST& st, float& t_best, bool& front_best, int& id_best, Work& w) {
+                           Stack& st, float& t_best, bool& front_best, int& id_best, Work& w) {
   t_best = INFINITY;
   id_best = 0x7fffffff;
   int slot_best = -1;
@@ -204,49 +196,59 @@ __device__ int closest_hit(const VolumeView& v, const Ray& ray,
   }
 }
 
-// Any hit on (0, tmax].
-template <bool COUNT, class ST>
+// Any hit on (0, tmax]: a while-while traversal with wave-wide loop exits
+// (the node phase runs until no lane needs another node, then the lanes
+// holding a leaf test its triangles).
+template <bool COUNT>
 __device__ bool any_hit(const VolumeView& v, const Ray& ray,
-                        float tmax, ST& st, Work& w) {
+                        float tmax, Stack& st, Work& w) {
   if (COUNT) w.tris += v.scene->num_big;
-  if (any_big(v, ray, tmax)) return true;
+  const bool big = any_big(v, ray, tmax);
   st.sp = 0;
   int node = 0;
+  bool more = !big, hit = big;
   for (;;) {
-    while (node >= 0) {
-      NodeData nd = fetch_node(v.nodes, node);
-      if (COUNT) {
-        ++w.nodes;
-        w.boxes += 2u;
+    for (;;) {
+      if (more && node >= 0) {
+        NodeData nd = fetch_node(v.nodes, node);
+        if (COUNT) {
+          ++w.nodes;
+          w.boxes += 2u;
+        }
+        float tl, tr;
+        bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
+        bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
+        if (hl && hr) {
+          bool lf = tl <= tr;
+          st.push(lf ? nd.right : nd.left, lf ? tr : tl);
+          node = lf ? nd.left : nd.right;
+        } else if (hl) {
+          node = nd.left;
+        } else if (hr) {
+          node = nd.right;
+        } else {
+          more = st.sp > 0;
+          if (more) node = st.pop_node();
+        }
       }
-      float tl, tr;
-      bool hl = box_hit(ray, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, 0.0f, tmax, tl);
-      bool hr = box_hit(ray, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, 0.0f, tmax, tr);
-      if (hl && hr) {
-        bool lf = tl <= tr;
-        st.push(lf ? nd.right : nd.left, lf ? tr : tl);
-        node = lf ? nd.left : nd.right;
-      } else if (hl) {
-        node = nd.left;
-      } else if (hr) {
-        node = nd.right;
-      } else {
-        if (st.sp == 0) return false;
-        node = st.pop_node();
+      if (ballot(more && node >= 0) == 0ull) break;
+    }
+    if (more) {
+      const int code = ~node;
+      const int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+      for (int k = 0; k < count && !hit; ++k) {
+        const float4* tp = v.tris + 3 * (size_t)(first + k);
+        float t;
+        bool fr;
+        if (COUNT) ++w.tris;
+        hit = tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr);
       }
+      more = !hit && st.sp > 0;
+      if (more) node = st.pop_node();
     }
-    int code = ~node;
-    int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
-    for (int k = 0; k < count; ++k) {
-      const float4* tp = v.tris + 3 * (size_t)(first + k);
-      float t;
-      bool fr;
-      if (COUNT) ++w.tris;
-      if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
-    }
-    if (st.sp == 0) return false;
-    node = st.pop_node();
+    if (ballot(more) == 0ull) break;
   }
+  return hit;
 }
 
 
@@ -264,9 +266,9 @@ __device__ __forceinline__ void order2(float& ka, int& ca, float& kb, int& cb) {
   ca = c;
 }
 
-template <bool COUNT, class ST>
+template <bool COUNT>
 __device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int idx, const Ray& ray,
-                                          float lim, ST& st, int& next, Work& w) {
+                                          float lim, Stack& st, int& next, Work& w) {
   const float4* src = nodes4 + 8 * (size_t)idx;
   const float4 lx = src[0], ly = src[1], lz = src[2], hx = src[3], hy = src[4], hz = src[5], cf = src[6];
   int c0 = __float_as_int(cf.x), c1 = __float_as_int(cf.y), c2 = __float_as_int(cf.z),
@@ -298,8 +300,8 @@ __device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int
 }
 
 
-template <bool COUNT, class ST>
-__device__ int closest_hit4(const VolumeView& v, const Ray& ray, ST& st, float& t_best, bool& front_best,
+template <bool COUNT>
+__device__ int closest_hit4(const VolumeView& v, const Ray& ray, Stack& st, float& t_best, bool& front_best,
                             int& id_best, Work& w) {
   t_best = INFINITY;
   id_best = 0x7fffffff;
@@ -340,34 +342,45 @@ __device__ int closest_hit4(const VolumeView& v, const Ray& ray, ST& st, float& 
   }
 }
 
-template <bool COUNT, class ST>
-__device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, ST& st, Work& w) {
+template <bool COUNT>
+__device__ bool any_hit4(const VolumeView& v, const Ray& ray, float tmax, Stack& st, Work& w) {
   if (COUNT) w.tris += v.scene->num_big;
-  if (any_big(v, ray, tmax)) return true;
+  const bool big = any_big(v, ray, tmax);
   st.sp = 0;
+  // while-while with wave-wide loop exits: the node phase runs until no lane
+  // needs another node (each lane then holds a leaf or is done), then the
+  // lanes holding a leaf test its triangles
   int node = 0;
+  bool more = !big, hit = big;
   for (;;) {
-    while (node >= 0) {
-      int next;
-      if (node4_step<COUNT>(v.nodes4, node, ray, tmax, st, next, w) > 0) {
-        node = next;
-      } else {
-        if (st.sp == 0) return false;
-        node = st.pop_node();
+    for (;;) {
+      if (more && node >= 0) {
+        int next;
+        if (node4_step<COUNT>(v.nodes4, node, ray, tmax, st, next, w) > 0) {
+          node = next;
+        } else {
+          more = st.sp > 0;
+          if (more) node = st.pop_node();
+        }
       }
+      if (ballot(more && node >= 0) == 0ull) break;
     }
-    int code = ~node;
-    int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
-    for (int k = 0; k < count; ++k) {
-      const float4* tp = v.tris + 3 * (size_t)(first + k);
-      float t;
-      bool fr;
-      if (COUNT) ++w.tris;
-      if (tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr)) return true;
+    if (more) {
+      const int code = ~node;
+      const int first = code >> kLeafShift, count = (code & (kLeafMaxTris - 1)) + 1;
+      for (int k = 0; k < count && !hit; ++k) {
+        const float4* tp = v.tris + 3 * (size_t)(first + k);
+        float t;
+        bool fr;
+        if (COUNT) ++w.tris;
+        hit = tri_hit(ray, tp[0], tp[1], tp[2], 0.0f, tmax, t, fr);
+      }
+      more = !hit && st.sp > 0;
+      if (more) node = st.pop_node();
     }
-    if (st.sp == 0) return false;
-    node = st.pop_node();
+    if (ballot(more) == 0ull) break;
   }
+  return hit;
 }
 
 
@@ -552,7 +565,7 @@ __device__ __forceinline__ void flush_stats(const VolumeView& v, const Work& w, 
 // per such light into the batch's pair segment, all pairs of light 0 first,
 // then light 1, and so on (neighbouring shadow rays mostly share a light).
 template <int KIND, bool COUNT, bool W4>
-__device__ __forceinline__ void hit_batch(const VolumeView& v, HitStack& st, uint32_t b, uint32_t total, Work& w,
+__device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32_t b, uint32_t total, Work& w,
                                           uint32_t& shadow) {
   const SceneParams& sc = *v.scene;
   const uint32_t lane = lane_id(), br = v.batch_rays;
@@ -633,7 +646,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_hit_kernel(Volu
   extern __shared__ uint64_t smem[];
   const int wave = threadIdx.x >> 6;
   uint64_t deep[kStackMax - kStackLds];
-  HitStack st;
+  Stack st;
   st.lds = (lds_u64*)smem + wave * (64 * kStackLds) + lane_id();
   st.sp = 0;
   st.deep = deep;
@@ -756,7 +769,7 @@ __global__ __launch_bounds__(1024) void pair_scan_single_kernel(VolumeView v) {
 // the ray's last shadow ray shades it: rho/pi times the sum over its visible
 // lights of I_l cos / d^2, the lights taken in index order.
 template <int KIND, bool COUNT, bool W4>
-__device__ __forceinline__ void shade_batch(const VolumeView& v, ShadeStack& st, uint32_t q, uint32_t T, uint32_t nb,
+__device__ __forceinline__ void shade_batch(const VolumeView& v, Stack& st, uint32_t q, uint32_t T, uint32_t nb,
                                             Work& w) {
   const SceneParams& sc = *v.scene;
   const uint32_t p = q * 64u + lane_id();
@@ -807,9 +820,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_shade_kernel(Vo
   extern __shared__ uint64_t smem[];
   const int wave = threadIdx.x >> 6;
   const uint32_t waves = blockDim.x >> 6;
-  ShadeStack st;
+  uint64_t deep[kStackMax - kStackLds];
+  Stack st;
   st.lds = (lds_u64*)smem + wave * (64 * kStackLds) + lane_id();
   st.sp = 0;
+  st.deep = deep;
   const uint32_t T = v.stats->pair_total, nb = v.stats->pair_batches;
   const uint32_t nq = (T + 63u) / 64u;
   Work w;
