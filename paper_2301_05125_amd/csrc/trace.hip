@@ -50,15 +50,10 @@ struct Stack {
   lds_u64* lds;   // this lane's entry 0; an entry is (t bits << 32) | node
   int sp;
   uint64_t* deep;
-  __device__ __forceinline__ void push(int node, float t) {
-    const uint64_t e = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)node;
-    if (sp < kStackLds) {
-      lds[sp << 6] = e;
-    } else {
-      deep[sp - kStackLds] = e;
-    }
-    ++sp;
+  static __device__ __forceinline__ uint64_t entry(int node, float t) {
+    return ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)node;
   }
+  __device__ __forceinline__ void push(int node, float t) { push_entry(entry(node, t)); }
   __device__ __forceinline__ uint64_t pop() {
     --sp;
     uint64_t e;
@@ -68,6 +63,32 @@ struct Stack {
       e = deep[sp - kStackLds];
     }
     return e;
+  }
+  // The hit children after the nearest of a 4-wide visit, sorted near to far
+  // (e1 <= e2 <= e3 by distance), nh hits in all (2..4): pushed farthest
+  // first, so they pop nearest first. While three more entries fit in LDS,
+  // the three slots above sp are written whatever nh is (a slot above the new
+  // top holds nothing live), with no branch per entry.
+  __device__ __forceinline__ void push_after_nearest(int nh, uint64_t e1, uint64_t e2, uint64_t e3) {
+    if (sp + 3 <= kStackLds) {
+      lds_u64* p = lds + (sp << 6);
+      p[0] = nh >= 4 ? e3 : nh == 3 ? e2 : e1;
+      p[64] = nh >= 4 ? e2 : e1;
+      p[128] = e1;
+      sp += nh - 1;
+    } else {
+      if (nh >= 4) push_entry(e3);
+      if (nh >= 3) push_entry(e2);
+      push_entry(e1);
+    }
+  }
+  __device__ __forceinline__ void push_entry(uint64_t e) {
+    if (sp < kStackLds) {
+      lds[sp << 6] = e;
+    } else {
+      deep[sp - kStackLds] = e;
+    }
+    ++sp;
   }
   __device__ __forceinline__ int pop_node() { return (int)(uint32_t)pop(); }
   // Next entry whose box may hold a hit at t <= tmax; false when none is left.
@@ -283,18 +304,17 @@ __device__ __forceinline__ int node4_step(const float4* __restrict__ nodes4, int
   const bool h1 = box_hit(ray, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, 0.0f, lim, t1) && c1 != kEmptyChild;
   const bool h2 = box_hit(ray, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, 0.0f, lim, t2) && c2 != kEmptyChild;
   const bool h3 = box_hit(ray, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, 0.0f, lim, t3) && c3 != kEmptyChild;
-  // hits sort before misses: finite keys for hits, +inf for misses
-  float k0 = h0 ? fminf(t0, 3.0e38f) : INFINITY, k1 = h1 ? fminf(t1, 3.0e38f) : INFINITY;
-  float k2 = h2 ? fminf(t2, 3.0e38f) : INFINITY, k3 = h3 ? fminf(t3, 3.0e38f) : INFINITY;
+  // hits sort before misses: a hit's entry distance is finite (padded bounds
+  // are finite and |1/d| <= 1e20), a miss keys +inf
+  float k0 = h0 ? t0 : INFINITY, k1 = h1 ? t1 : INFINITY;
+  float k2 = h2 ? t2 : INFINITY, k3 = h3 ? t3 : INFINITY;
   order2(k0, c0, k1, c1);
   order2(k2, c2, k3, c3);
   order2(k0, c0, k2, c2);
   order2(k1, c1, k3, c3);
   order2(k1, c1, k2, c2);
   const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
-  if (nh >= 4) st.push(c3, k3);
-  if (nh >= 3) st.push(c2, k2);
-  if (nh >= 2) st.push(c1, k1);
+  if (nh >= 2) st.push_after_nearest(nh, Stack::entry(c1, k1), Stack::entry(c2, k2), Stack::entry(c3, k3));
   next = c0;
   return nh;
 }
