@@ -89,6 +89,8 @@ def lib():
         L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_frame_rotation.argtypes = [C.c_uint64, C.c_int32, P]
         L.orc_sf_dir.argtypes = [C.c_int32, C.c_int32, P, P]
+        L.orc_ray_point.restype = C.c_int32
+        L.orc_ray_point.argtypes = [C.c_int32, C.c_int32]
         L.orc_pilot_dir.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, P]
         L.orc_oct_encode.argtypes = [P, P]
         L.orc_oct_decode.argtypes = [P, P]
@@ -190,6 +192,18 @@ def sf_dirs(n: int, R: np.ndarray) -> np.ndarray:
         lib().orc_sf_dir(j, n, _p(R), _p(d))
         out[j] = d
     return out
+
+
+def ray_point(j: int, n: int) -> int:
+    """Index of the spherical Fibonacci point that ray j of an n-ray probe takes."""
+    return int(lib().orc_ray_point(j, n))
+
+
+def probe_ray_dirs(n: int, R: np.ndarray) -> np.ndarray:
+    """Directions of an n-ray probe's rays in ray order: ray j along point
+    ray_point(j, n) of the rotated spherical Fibonacci set."""
+    pts = sf_dirs(n, R)
+    return pts[[ray_point(j, n) for j in range(n)]]
 
 
 def pilot_dir(seed: int, probe: int, k: int, pair: int) -> np.ndarray:

@@ -72,6 +72,27 @@ void orc_sf_dir(int32_t j, int32_t n, const float R[9], double d[3]) {
     d[a] = (double)R[3 * a + 0] * v[0] + (double)R[3 * a + 1] * v[1] + (double)R[3 * a + 2] * v[2];
 }
 
+/* Which spherical Fibonacci point ray j of a probe with n rays takes. The
+ * paper fixes the point set of a probe's rays, not which ray gets which
+ * point, nor the order in which a texel's samples enter its moving average
+ * (its updates are atomic). Reading taken here: the points are dealt into
+ * C = ceil(n/64) strata by index modulo C (stratum c holds c, c + C, c + 2C,
+ * ... in ascending order), ray indices run through stratum 0, then stratum 1,
+ * and so on, and a texel takes its samples in ascending ray index. Each
+ * stratum spreads over the whole sphere. n <= 64: ray j takes point j. */
+int32_t orc_ray_point(int32_t j, int32_t n) {
+  const int64_t C = ((int64_t)n + 63) / 64;
+  if (C <= 1) return j;
+  /* stratum c holds ceil((n - c) / C) points */
+  int64_t c = 0, first = 0;
+  for (;;) {
+    const int64_t size = ((int64_t)n - c + C - 1) / C;
+    if (j < first + size) return (int32_t)(c + (j - first) * C);
+    first += size;
+    ++c;
+  }
+}
+
 /* Pilot ray of octant k (Sec. 4.4): one stratified-random direction per
  * octant, the same for both frames of a pair (AABBCC... pattern). A uniform
  * sphere point folded into the octant. */
@@ -1084,7 +1105,7 @@ static void probe_frame_one(const orc_scene* s, const orc_grid* g, int32_t probe
   }
   for (int32_t j = 0; j < n; ++j) {
     double d[3];
-    orc_sf_dir(j, n, R, d);
+    orc_sf_dir(orc_ray_point(j, n), n, R, d);
     orc_ray ray;
     orc_shade_ray(s, o, d, g->s, tol, hint_tri ? hint_tri[j] : -2,
                   hint_shadow ? (int32_t)hint_shadow[j] : -1, &ray, ties, mism);

@@ -50,6 +50,8 @@ double   orc_uniform(uint64_t key, uint64_t q);   /* top 24 bits of mix(key^q) *
 void orc_frame_rotation(uint64_t seed, int32_t frame, float R[9]);
 /* Spherical Fibonacci direction j of n, rotated by R (FP64). */
 void orc_sf_dir(int32_t j, int32_t n, const float R[9], double d[3]);
+/* Spherical Fibonacci point (index) that ray j of a probe with n rays takes. */
+int32_t orc_ray_point(int32_t j, int32_t n);
 /* Pilot direction: probe, octant k (bit0 -x, bit1 -y, bit2 -z), pair m. */
 void orc_pilot_dir(uint64_t seed, int32_t probe, int32_t k, int32_t pair, double d[3]);
 

@@ -57,6 +57,56 @@ __device__ __forceinline__ float3 sf_direction(uint32_t j, uint32_t n, const flo
                      fmaf(R[6], vx, fmaf(R[7], vy, R[8] * z)));
 }
 
+// Which spherical Fibonacci point ray j of a probe with n rays takes. The
+// points are dealt into C = ceil(n/64) strata by index modulo C (stratum c:
+// points c, c + C, c + 2C, ...), and the ray indices run through stratum 0,
+// then stratum 1, and so on. Stratum c holds q + 1 points for c < n mod C and
+// q otherwise (q = n / C, at most 64) and spreads over the whole sphere, where
+// 64 consecutive points form a thin band in z; the blend takes one stratum per
+// step, so few of a step's samples share a texel. n <= 64: ray j takes point j.
+struct RayStrata {
+  uint32_t C, q, rem;
+  __host__ __device__ explicit RayStrata(uint32_t n)
+      : C((n + 63u) >> 6), q(n > 0u ? n / ((n + 63u) >> 6) : 0u), rem(n > 0u ? n % ((n + 63u) >> 6) : 0u) {}
+  __host__ __device__ uint32_t size(uint32_t c) const { return q + (c < rem ? 1u : 0u); }
+  __host__ __device__ uint32_t start(uint32_t c) const { return c * q + (c < rem ? c : rem); }
+};
+
+// floor(a / d) for a < 2^16 and d >= 1: the hardware reciprocal's estimate
+// is within 2^-6 of a / d there, so its truncation is off by at most one and
+// one correction step either way makes it exact.
+__device__ __forceinline__ uint32_t udiv16(uint32_t a, uint32_t d) {
+  uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)d));
+  if (q * d > a) --q;
+  if ((q + 1u) * d <= a) ++q;
+  return q;
+}
+
+__device__ __forceinline__ uint32_t sf_point_of_ray(uint32_t j, uint32_t n) {
+  if (n <= 64u) return j;
+  const bool small = n < 65536u;
+  const uint32_t C = (n + 63u) >> 6;
+  const uint32_t q = small ? udiv16(n, C) : n / C, rem = n - q * C;
+  const uint32_t big = rem * (q + 1u);  // rays of the strata with q + 1 points
+  uint32_t c, k;
+  if (j < big) {
+    c = small ? udiv16(j, q + 1u) : j / (q + 1u);
+    k = j - c * (q + 1u);
+  } else {
+    const uint32_t t = j - big, cc = small ? udiv16(t, q) : t / q;
+    c = rem + cc;
+    k = t - cc * q;
+  }
+  return c + k * C;
+}
+
+// The ray that takes spherical Fibonacci point p (the inverse of the above).
+__host__ __device__ __forceinline__ uint32_t ray_of_sf_point(uint32_t p, uint32_t n) {
+  if (n <= 64u) return p;
+  const RayStrata s(n);
+  return s.start(p % s.C) + p / s.C;
+}
+
 // Pilot direction of octant k (bit0 -x, bit1 -y, bit2 -z) for pair m: a
 // uniform sphere point folded into the octant.
 __device__ __forceinline__ float3 pilot_direction(uint64_t seed, uint32_t probe, uint32_t k,

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
     for (int j = tid; j < m; j += nt) L.rec[j] = v.rec[off + c0 + j];
     __syncthreads();
     for (int j = tid; j < m; j += nt) {
-      float3 d = sf_direction(c0 + (uint32_t)j, n, fp.R);
+      float3 d = sf_direction(sf_point_of_ray(c0 + (uint32_t)j, n), n, fp.R);
       float2 uv = oct_encode(d);
       uint32_t bI = oct_bin(uv, ri), bD = oct_bin(uv, rd);
       L.bins[j] = (uint16_t)bI;
@@ -249,15 +249,17 @@ __global__ __launch_bounds__(256) void blend_kernel(VolumeView v, BlendIO io, in
 // ---------------------------------------------------------------------------
 // Wave-per-probe variant for the common tile sizes. One 64-lane wave owns one
 // probe and keeps its interior texels, depth moments and counts in LDS for
-// the whole frame (loaded row by row, coalesced). Rays are taken 64 at a
-// time, one per lane, with the texel indices the trace stored for each ray.
-// Each lane ORs its lane bit into a 64-bit LDS mask of its irradiance texel
-// and of its depth texel; the set bits below a lane give its rank among the
-// chunk's samples of the same texel. Round r then applies, in every lane of
-// rank r at once, that lane's sample to its texel: a texel takes its samples
-// in ascending ray order and no two lanes touch one texel in a round, so the
+// the whole frame (loaded row by row, coalesced). Rays are taken one stratum
+// (sf_point_of_ray: at most 64 rays spread over the sphere) at a time, one
+// per lane, with the texel indices the trace stored for each ray. Each lane
+// ORs its lane bit into a 64-bit LDS mask of its irradiance texel and of its
+// depth texel; the set bits below a lane give its rank among the step's
+// samples of the same texel. Round r then applies, in every lane of rank r at
+// once, that lane's sample to its texel: a texel takes its samples in
+// ascending ray order and no two lanes touch one texel in a round, so the
 // moving average is the same sequence of FP32 operations as one sample at a
-// time. The next 64 records are loaded while the current ones are applied.
+// time, and a step takes as many rounds as its most-hit texel has samples.
+// The next step's records are loaded while the current ones are applied.
 // Waves take probes in the allocation's order (most rays first) so the
 // longest blends start first.
 __device__ __forceinline__ void wave_sync() {
@@ -419,6 +421,14 @@ __device__ __forceinline__ void load_sample(const VolumeView& v, uint32_t off, u
   }
 }
 
+// Samples per step of a probe's blend: probe rays one stratum at a time
+// (sf_point_of_ray: at most 64 rays spread over the sphere), chain samples 64
+// at a time. Either way a step holds the next samples in ascending order.
+template <bool CHAIN>
+__device__ __forceinline__ uint32_t first_step_size(uint32_t n) {
+  return CHAIN ? min(64u, n) : RayStrata(n).size(0u);
+}
+
 template <int RI, int RD, bool HALF, bool CHAIN>
 __device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& io, int i, uint32_t off,
                                            uint32_t n, bool reuse, ProbeRegs<RI, RD, HALF, CHAIN>& g) {
@@ -473,7 +483,7 @@ __device__ __forceinline__ void load_probe(const VolumeView& v, const BlendIO& i
 #pragma unroll
   for (int s = 0; s < G::CD; ++s)
     if (lane + 64 * s < ND / 4) g.cd[s] = nd_in[lane + 64 * s];
-  if ((uint32_t)lane < n) load_sample<CHAIN>(v, off, (uint32_t)lane, g.rec, g.bins, g.uv);
+  if ((uint32_t)lane < first_step_size<CHAIN>(n)) load_sample<CHAIN>(v, off, (uint32_t)lane, g.rec, g.bins, g.uv);
   if (reuse && lane < 8) {
     g.prec = v.pilot_rec[8 * (size_t)i + lane];
     g.pbins = v.pilot_bins[8 * (size_t)i + lane];
@@ -633,13 +643,16 @@ __device__ __forceinline__ void blend_probe_samples(const VolumeView& v, int i, 
   uint32_t nbin = bins0;
   float2 nuv = uv0;
   if (n == 0u) at_last_chunk();
-  for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
-    const uint32_t m = min(64u, n - c0);
+  const RayStrata strata(CHAIN ? 0u : n);
+  uint32_t m = first_step_size<CHAIN>(n), step = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += m, m = CHAIN ? min(64u, n - c0) : strata.size(++step)) {
     const float4 cur = nxt;
     uint32_t cbin = nbin;
     const float2 cuv = nuv;
-    if (c0 + 64u < n) {
-      if (c0 + 64u + (uint32_t)lane < n) load_sample<CHAIN>(v, off, c0 + 64u + lane, nxt, nbin, nuv);
+    const uint32_t c1 = c0 + m;  // the next step's first sample
+    if (c1 < n) {
+      const uint32_t m1 = CHAIN ? min(64u, n - c1) : strata.size(step + 1u);
+      if ((uint32_t)lane < m1) load_sample<CHAIN>(v, off, c1 + lane, nxt, nbin, nuv);
     } else {
       at_last_chunk();
     }
@@ -846,7 +859,7 @@ __device__ void gather_probe_wave(const VolumeView& v, const BlendIO& io, int i,
   for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
     const uint32_t m = min(64u, n - c0);
     if ((uint32_t)lane < m) {
-      const float3 d = sf_direction(c0 + (uint32_t)lane, n, fp.R);
+      const float3 d = sf_direction(sf_point_of_ray(c0 + (uint32_t)lane, n), n, fp.R);
       const float4 r = v.rec[off + c0 + (uint32_t)lane];
       st_dir[lane] = make_float4(d.x, d.y, d.z, fminf(r.w * inv_s, v.tau_max));
       st_rgb[lane] = r;
@@ -988,7 +1001,8 @@ __device__ __forceinline__ void packed_probe(const VolumeView& v, const BlendIO&
   }
   float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
   uint32_t nbin = 0u;
-  if ((uint32_t)lane < n) {
+  const RayStrata strata(n);  // one stratum of rays per step
+  if ((uint32_t)lane < strata.size(0u)) {
     nxt = v.rec[off + lane];
     nbin = v.ray_bins[off + lane];
   }
@@ -999,13 +1013,14 @@ __device__ __forceinline__ void packed_probe(const VolumeView& v, const BlendIO&
   for (int s = 0; s < SD; ++s)
     if (lane + 64 * s < ND) words[NI + lane + 64 * s] = wd[s];
   wave_sync();
-  for (uint32_t c0 = 0; c0 < n; c0 += 64u) {
-    const uint32_t m = min(64u, n - c0);
+  uint32_t m = strata.size(0u), step = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += m, m = strata.size(++step)) {
     const float4 cur = nxt;
     const uint32_t cbin = nbin;
-    if (c0 + 64u + (uint32_t)lane < n) {
-      nxt = v.rec[off + c0 + 64u + lane];
-      nbin = v.ray_bins[off + c0 + 64u + lane];
+    const uint32_t c1 = c0 + m;
+    if (c1 < n && (uint32_t)lane < strata.size(step + 1u)) {
+      nxt = v.rec[off + c1 + lane];
+      nbin = v.ray_bins[off + c1 + lane];
     }
     const bool act = (uint32_t)lane < m;
     const uint32_t bI = cbin & 0xFFFFu, bD = NI + (cbin >> 16);

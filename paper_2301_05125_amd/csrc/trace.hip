@@ -458,7 +458,7 @@ __device__ __forceinline__ void gen_ray(const VolumeView& v, uint32_t r, int i0,
     uint32_t j = r - b;
     if (v.ray_perm && n <= (uint32_t)v.ray_perm_max) j = v.ray_perm[(size_t)n * (n - 1u) / 2u + j];
     dst = b + j;
-    d = sf_direction(j, n, fp.R);
+    d = sf_direction(sf_point_of_ray(j, n), n, fp.R);
   } else if (KIND == KIND_CHAIN) {
     const uint32_t S2 = 2u * v.offsets[v.P];
     d = make_float3(0.f, 0.f, 1.f);

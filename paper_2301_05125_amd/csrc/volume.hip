@@ -546,16 +546,17 @@ const std::vector<uint32_t>& packed_decode_table() {
 bool finite3(const float* x) { return std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]); }
 
 // Coherent order of a probe's rays for the traversal. The n rays of a probe
-// are the points of a spherical Fibonacci set, whose index j runs down the
-// sphere in z; 64 consecutive indices form a thin band around the whole
-// sphere, so one wave's rays point every way. Slot k of a probe with n rays
-// traces ray perm_n(k) instead: the indices are cut into bands of B
-// consecutive indices (B a multiple of 64 near sqrt(201 n), which makes the
-// 64-ray patch of a wave about as tall in z as it is wide in azimuth) and
-// each band is listed in ascending azimuth (the 32-bit fraction the
-// direction's angle is computed from). Rays keep their indices, so every
-// output is the same; only which lane traces which ray changes. Tables for
-// n = 1 .. kRayOrderMaxN, n (n-1)/2 entries before n's; built once per process.
+// take the points of a spherical Fibonacci set, whose index runs down the
+// sphere in z, and a stratum of rays (sf_point_of_ray) spreads over the
+// whole sphere, so one wave's rays in index order point every way. Slot k of
+// a probe with n rays traces ray perm_n(k) instead: the point indices are cut
+// into bands of B consecutive indices (B a multiple of 64 near sqrt(201 n),
+// which makes the 64-ray patch of a wave about as tall in z as it is wide in
+// azimuth), each band is listed in ascending azimuth (the 32-bit fraction the
+// direction's angle is computed from), and the slot traces the ray that takes
+// that point. Rays keep their indices, so every output is the same; only
+// which lane traces which ray changes. Tables for n = 1 .. kRayOrderMaxN,
+// n (n-1)/2 entries before n's; built once per process.
 constexpr int kRayOrderMaxN = 2048;
 
 const std::vector<uint16_t>& ray_order_table() {
@@ -573,7 +574,7 @@ const std::vector<uint16_t>& ray_order_table() {
         for (uint32_t j = b0; j < b1; ++j)
           key.push_back({(uint32_t)(((uint64_t)j * 0x9E3779B97F4A7C15ull) >> 32), j});
         std::sort(key.begin(), key.end());
-        for (uint32_t k = b0; k < b1; ++k) out[k] = (uint16_t)key[k - b0].second;
+        for (uint32_t k = b0; k < b1; ++k) out[k] = (uint16_t)ray_of_sf_point(key[k - b0].second, n);
       }
     }
   });

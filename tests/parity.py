@@ -108,7 +108,7 @@ def ray_rgb_bar(scene, frame, sel, n_sel, R, o, tri, shadow) -> np.ndarray:
     sel = np.asarray(sel, np.int64)
     pidx = np.stack([sel % dims[0], (sel // dims[0]) % dims[1], sel // (dims[0] * dims[1])], axis=1)
     pos_p = org + pidx * spc
-    d = np.concatenate([oracle.sf_dirs(int(k), R) if k else np.zeros((0, 3)) for k in n_sel])
+    d = np.concatenate([oracle.probe_ray_dirs(int(k), R) if k else np.zeros((0, 3)) for k in n_sel])
     p = np.repeat(pos_p, np.asarray(n_sel, np.int64), axis=0)
     t = o[:, 3]
     lit = (tri >= 0) & np.isfinite(t) & (np.abs(o[:, :3]).max(axis=1) > 0)
@@ -315,7 +315,7 @@ def run_lockstep(scene, frames: int, adaptive: bool, n_uniform: int = 64, budget
             et = np.where(same, np.abs(gt - ot) / den_t, 0.0)
             res["max_rel_t"] = max(res.get("max_rel_t", 0.0), float(et.max(initial=0.0)))
             pr = np.repeat(probe_positions(scene, sel), np.asarray(n_sel, np.int64), axis=0)
-            dr = np.concatenate([oracle.sf_dirs(int(k), out["R"]) if k else np.zeros((0, 3)) for k in n_sel])
+            dr = np.concatenate([oracle.probe_ray_dirs(int(k), out["R"]) if k else np.zeros((0, 3)) for k in n_sel])
             tbar = ray_t_bar(scene, f, pr, dr, np.where(miss_o, np.inf, o[:, 3]), out["tri"])
             res["t_bar_excess"] = res.get("t_bar_excess", 0) + int(np.count_nonzero(et > tbar))
             k = int(np.argmax(e)) if e.size else 0

@@ -420,7 +420,7 @@ def test_shadow_ray_count_is_one_per_facing_light(scene_name):
         rb = vol.read_probes(texels=False, debug=True)
     finally:
         vol.destroy_volume()
-    dirs = oracle.sf_dirs(n, oracle.frame_rotation(seed, 0))
+    dirs = oracle.probe_ray_dirs(n, oracle.frame_rotation(seed, 0))
     dims = sc.grid_dims.astype(np.int64)
     i = np.arange(P)
     cell = np.stack([i % dims[0], (i // dims[0]) % dims[1], i // (dims[0] * dims[1])], axis=1)

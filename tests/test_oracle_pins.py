@@ -85,6 +85,35 @@ def test_spherical_fibonacci_properties(n):
     assert np.allclose(np.minimum(dphi, 2 * np.pi - dphi), golden, atol=1e-9)
 
 
+@pytest.mark.parametrize("n", [1, 7, 64, 65, 100, 127, 128, 129, 300, 2047, 2048, 4097])
+def test_ray_point_strata(n):
+    # brute force of the stratified assignment: the residue classes of the
+    # point indices modulo C = ceil(n/64), each ascending, concatenated
+    C = -(-n // 64)
+    order = [p for c in range(C) for p in range(c, n, C)]
+    got = [oracle.ray_point(j, n) for j in range(n)]
+    assert got == order
+    assert sorted(got) == list(range(n))  # a permutation: the probe still traces the whole set
+    if n <= 64:
+        assert got == list(range(n))
+    # each stratum (at most 64 rays) spans the sphere: its mean z is small,
+    # unlike that of as many consecutive points (a thin band in z)
+    d = oracle.probe_ray_dirs(n, np.eye(3, dtype=np.float32))
+    if n >= 128:
+        m = -(-n // C)  # stratum 0's size
+        assert m <= 64
+        assert np.abs(d[:m, 2].mean()) < 0.1
+        assert oracle.sf_dirs(n, np.eye(3, dtype=np.float32))[:m, 2].mean() > 0.4
+
+
+def test_probe_ray_directions_are_the_point_set():
+    R = oracle.frame_rotation(3, 1)
+    for n in (8, 200, 1000):
+        a = oracle.probe_ray_dirs(n, R)
+        b = oracle.sf_dirs(n, R)
+        assert np.array_equal(a[np.argsort([oracle.ray_point(j, n) for j in range(n)])], b)
+
+
 def test_sf_rotation_applies_matrix():
     R = oracle.frame_rotation(5, 3)
     d0 = oracle.sf_dirs(33, np.eye(3, dtype=np.float32))
