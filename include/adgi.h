@@ -426,9 +426,10 @@ adgi_status adgi_pack_channel(const float* values, int64_t count, int32_t channe
 adgi_status adgi_get_tuning(const adgi_volume* vol, adgi_tuning* out);
 adgi_status adgi_set_tuning(adgi_volume* vol, const adgi_tuning* t);
 /* Time candidate launch shapes on the current scene and frame parameters
- * and keep the fastest. Runs the traversal and the blend several times on
- * scratch copies: the volume's state is unchanged. The choice is cached per
- * (device, shape class) in memory for the process. */
+ * and keep the fastest. Runs one frame, then the traversal and the blend
+ * several times each, in place, and restores the volume's state from a
+ * snapshot taken first: the state afterwards is bit-identical. The choice is
+ * cached per (device, shape class) in memory for the process. */
 adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* params, adgi_tuning* chosen);
 
 /* ---- traversal work (for rooflines) --------------------------------------

@@ -1891,22 +1891,6 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     vol->tun = saved;
     return st;
   }
-  // scratch outputs so the blend candidates leave the state alone
-  const size_t P = vol->P, gi = vol->desc.irr_res, gd = vol->desc.depth_res;
-  std::vector<void*> scratch;
-  void* so_irr = vol_alloc(vol, P * irr_tile_bytes(vol->desc), &scratch);
-  void* so_dep = vol_alloc(vol, P * dep_tile_bytes(vol->desc), &scratch);
-  void* so_in = vol_alloc(vol, P * (gi - 2) * (gi - 2), &scratch);
-  void* so_dn = vol_alloc(vol, P * (gd - 2) * (gd - 2), &scratch);
-  auto cleanup = [&]() {
-    for (void* x : scratch) vol_free(vol, x);
-  };
-  if (!so_irr || !so_dep || !so_in || !so_dn) {
-    cleanup();
-    vol->tun = saved;
-    (void)adgi_restore_state(vol, snap.data(), snap.size());
-    return fail(ADGI_ERR_OUT_OF_MEMORY, "allocator returned NULL for tuning scratch");
-  }
   hipStream_t s = vol->stream;
   auto time_trace = [&](const adgi_tuning& c, float& best) -> hipError_t {
     best = INFINITY;
@@ -1983,9 +1967,11 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     if (bc.chunk == 0 && !blend_wave_supported(vol->v)) continue;
     if (bc.chunk != 0 && blend_lds_bytes(vol->v, bc.chunk) > 65536) continue;
     if (bc.chunk != 0 && (vol->desc.storage == ADGI_PACKED || vol->desc.blend_mode == ADGI_BLEND_GATHER)) continue;
-    BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, so_irr, so_dep, (uint8_t*)so_in, (uint8_t*)so_dn};
+    // in place, as the frame runs it (the snapshot restores the texels at
+    // the end): out-of-place timings ranked the grids differently
+    BlendIO io{vol->irr, vol->dep, vol->irr_n, vol->dep_n, vol->irr, vol->dep, vol->irr_n, vol->dep_n};
     float bm = INFINITY;
-    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+    for (int rep = 0; rep < 5 && err == hipSuccess; ++rep) {
       if ((err = hipEventRecord(vol->ev_t0, s)) != hipSuccess) break;
       if ((err = launch_blend(vol->v, io, s, vol->desc.storage, bc.chunk, vol->num_cus * bc.bpc, false,
                               vol->desc.blend_mode == ADGI_BLEND_GATHER)) != hipSuccess)
@@ -2007,7 +1993,6 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
     return fail(ADGI_ERR_DEVICE, "autotune kernel failed: %s", hipGetErrorString(err));
   }
   (void)hipStreamSynchronize(s);
-  cleanup();
   best_t.use_graph = saved.use_graph;
   vol->tun = saved;
   st = adgi_restore_state(vol, snap.data(), snap.size());
