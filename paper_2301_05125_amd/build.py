@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libadgi.so")
 
 SOURCES = ["volume.hip", "trace.hip", "detect.hip", "alloc.hip", "blend.hip", "refit.hip",
-           "chain.hip", "query.hip", "bvh_build.cpp", "serve.cpp"]
+           "chain.hip", "sort.hip", "query.hip", "bvh_build.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -25,18 +25,24 @@ hipError_t launch_trace(const VolumeView& v, hipStream_t s, bool pilot, bool per
 // sample ranges). samples = chains * (steps - burn_in - 1). lanes: 1 (one
 // thread per chain) or 4 / 8 / 16 (prefetching groups); chain_lanes_auto
 // picks one from the chain count.
-size_t chain_sort_temp_bytes(uint32_t max_samples, int P);
-size_t chain_sort_needed_bytes(uint32_t samples, int P);
 int chain_lanes_auto(int chains);
 // alloc.hip: blend order (most 64-entry chunks first) from counts already in v.n
 hipError_t launch_blend_order(const VolumeView& v, hipStream_t s);
 hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int chains, int lanes, uint32_t samples,
-                         void* sort_temp, size_t sort_temp_bytes, hipStream_t s);
+                         void* sort_temp, uint32_t sample_cap, hipStream_t s);
 // chain.hip: F per (proxy, octant) from f_d (needs the box sums in box_a),
 // one frame of the dynamic chains (marks), per-probe dynamic ray counts and
 // their scan into v.dyn_off.
-hipError_t launch_dyn_chains(const VolumeView& v, int chains, int lanes, void* scan_temp, size_t scan_temp_bytes,
+hipError_t launch_dyn_chains(const VolumeView& v, int chains, int lanes, void* scan_temp, uint32_t sample_cap,
                              hipStream_t s);
+// sort.hip: the chain samples (v.smp_probe_raw / v.smp_uv_raw, S of them)
+// sorted by probe, stably, into v.smp_probe / v.smp_uv; exclusive scan of P
+// counts into offsets[0..P] (offsets[P] the total). Both use a workspace of
+// sort_temp_bytes(cap, P) bytes for up to cap samples.
+size_t sort_temp_bytes(uint32_t cap, int P);
+hipError_t launch_sample_sort(const VolumeView& v, uint32_t S, uint32_t cap, void* temp, hipStream_t s);
+hipError_t launch_offsets_scan(const uint32_t* counts, int P, uint32_t* offsets, uint32_t cap, void* temp,
+                               hipStream_t s);
 // detect.hip: the three 5-tap passes of the box sum into box_a, whatever the
 // frame (the dynamic chains read them on even frames too)
 hipError_t launch_box_sums(const VolumeView& v, hipStream_t s);

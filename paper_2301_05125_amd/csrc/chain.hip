@@ -26,7 +26,6 @@
 #include <algorithm>
 #include <cstring>
 
-#include <rocprim/rocprim.hpp>
 
 #include "adgi_internal.hpp"
 
@@ -433,44 +432,6 @@ __global__ void dyn_count_kernel(VolumeView v) {
   v.dyn_n[i] = n;
 }
 
-static int probe_key_bits(int P) {
-  int bits = 1;
-  while ((1ll << bits) < (long long)P) ++bits;
-  return bits;
-}
-
-// Onesweep above one block of keys: the merge-sort path rocprim takes by
-// default below 2^20 keys launches about twice as many kernels here.
-using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                              rocprim::default_config, 0>;
-
-static size_t sort_bytes_for(uint32_t samples, int P) {
-  size_t bytes = 0;
-  (void)rocprim::radix_sort_pairs<SortConfig>(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                              (uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)samples, 0,
-                                              probe_key_bits(P), (hipStream_t)0);
-  return bytes;
-}
-
-static size_t scan_bytes_for(int P) {
-  size_t bytes = 0;
-  (void)rocprim::inclusive_scan(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)P,
-                                rocprim::plus<uint32_t>(), (hipStream_t)0);
-  return bytes;
-}
-
-// The sort may pick another algorithm for fewer keys: the workspace covers
-// every power of two up to max_samples, max_samples itself and the scans.
-size_t chain_sort_temp_bytes(uint32_t max_samples, int P) {
-  size_t bytes = std::max(sort_bytes_for(max_samples, P), scan_bytes_for(P));
-  for (uint64_t n = 1; n < max_samples; n <<= 1) bytes = std::max(bytes, sort_bytes_for((uint32_t)n, P));
-  return bytes;
-}
-
-size_t chain_sort_needed_bytes(uint32_t samples, int P) {
-  return std::max(sort_bytes_for(samples, P), scan_bytes_for(P));
-}
-
 int chain_lanes_auto(int chains) {
   // measured on the 65,536-probe box field: 16 lanes up to 16k chains, 4 at
   // 64k (the rounds' extra target evaluations then cost more than the latency
@@ -509,7 +470,7 @@ static hipError_t launch_chain_kernel(const VolumeView& v, int chains, int lanes
 }
 
 hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int chains, int lanes, uint32_t samples,
-                         void* sort_temp, size_t sort_temp_bytes, hipStream_t s) {
+                         void* sort_temp, uint32_t sample_cap, hipStream_t s) {
   hipLaunchKernelGGL(chain_clear_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, v);
   const int m = (v.irr_res - 2) / 2;
   const long long cells = (long long)v.P * m * m;
@@ -519,31 +480,21 @@ hipError_t launch_chains(const VolumeView& v, bool fp16, const void* irr, int ch
     hipLaunchKernelGGL(chain_lum_kernel<false>, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, v, irr);
   hipError_t e = launch_chain_kernel<StaticChain>(v, chains, lanes, s);
   if (e != hipSuccess) return e;
-  // stable LSD radix sort of (probe, uv) by probe: a probe's samples stay in
-  // chain-major order
-  size_t tb = sort_temp_bytes;
-  e = rocprim::radix_sort_pairs<SortConfig>(sort_temp, tb, v.smp_probe_raw, v.smp_probe, (uint64_t*)v.smp_uv_raw,
-                                            (uint64_t*)v.smp_uv, (size_t)samples, 0, probe_key_bits(v.P), s);
+  // stable sort of (probe, uv) by probe: a probe's samples stay in
+  // chain-major order; then the per-probe offsets
+  e = launch_sample_sort(v, samples, sample_cap, sort_temp, s);
   if (e != hipSuccess) return e;
-  tb = sort_temp_bytes;
-  e = rocprim::inclusive_scan(sort_temp, tb, (const uint32_t*)v.n, v.offsets + 1, (size_t)v.P,
-                              rocprim::plus<uint32_t>(), s);
-  if (e != hipSuccess) return e;
-  return hipGetLastError();
+  return launch_offsets_scan((const uint32_t*)v.n, v.P, v.offsets, sample_cap, sort_temp, s);
 }
 
-hipError_t launch_dyn_chains(const VolumeView& v, int chains, int lanes, void* scan_temp, size_t scan_temp_bytes,
+hipError_t launch_dyn_chains(const VolumeView& v, int chains, int lanes, void* scan_temp, uint32_t sample_cap,
                              hipStream_t s) {
   const int Pp = v.pdx * v.pdy * v.pdz;
   hipLaunchKernelGGL(dyn_proxy_kernel, dim3((8 * Pp + 255) / 256), dim3(256), 0, s, v);
   hipError_t e = launch_chain_kernel<DynamicChain>(v, chains, lanes, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dyn_count_kernel, dim3((v.P + 255) / 256), dim3(256), 0, s, v);
-  size_t tb = scan_temp_bytes;
-  e = rocprim::inclusive_scan(scan_temp, tb, (const uint32_t*)v.dyn_n, v.dyn_off + 1, (size_t)v.P,
-                              rocprim::plus<uint32_t>(), s);
-  if (e != hipSuccess) return e;
-  return hipGetLastError();
+  return launch_offsets_scan((const uint32_t*)v.dyn_n, v.P, v.dyn_off, sample_cap, scan_temp, s);
 }
 
 }  // namespace adgi

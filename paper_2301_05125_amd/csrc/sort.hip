@@ -1,0 +1,282 @@
+// sort.hip - exclusive scans and the stable sort of chain samples by probe.
+//
+// A chain frame's samples come out in sample order (chain-major) with their
+// probe; the blend wants them grouped by probe, each probe's samples still in
+// sample order, and the per-probe ray offsets. Both are built here from
+// fixed-size launches (sizes known on the host), so a chain frame can be
+// captured in a graph like a budgeted one:
+//  * exclusive scan of n 32-bit counts: per-block sums of 1024 entries, one
+//    workgroup scanning the block sums, then per-block local scans plus the
+//    block's offset;
+//  * least-significant-digit radix sort of the probe keys with 8-bit digits
+//    (ceil(key bits / 8) passes), the sample index as the value: per tile of
+//    1024 keys a digit histogram, an exclusive scan of the histograms in
+//    digit-major order (so a digit's keys from earlier tiles come first), and
+//    a scatter in which each key's rank within its tile comes from wave-wide
+//    digit matches, taken 256 keys at a time in index order. Every pass is
+//    stable, so a probe's samples keep their sample order. A final gather
+//    writes the sorted probes and looks up each sample's octahedral uv.
+#include <algorithm>
+
+#include "adgi_internal.hpp"
+
+namespace adgi {
+
+constexpr int kScanBlock = 256, kScanPer = 4, kScanTile = kScanBlock * kScanPer;  // 1024 entries per block
+constexpr int kSortBlock = 256, kSortRounds = 4, kSortTile = kSortBlock * kSortRounds;  // 1024 keys per tile
+constexpr int kRadix = 256, kSortWaves = kSortBlock / 64;
+
+static inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ---- exclusive scan
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, (unsigned)off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan across a workgroup of blockDim.x (a multiple of 64) threads;
+// sm holds blockDim.x / 64 + 1 words. Returns this thread's exclusive prefix
+// and the workgroup total.
+__device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_t* sm, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(x);
+  if (lane == 63) sm[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0u;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t t = sm[w];
+      sm[w] = acc;
+      acc += t;
+    }
+    sm[nw] = acc;
+  }
+  __syncthreads();
+  total = sm[nw];
+  const uint32_t out = inc - x + sm[wave];
+  __syncthreads();
+  return out;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(const uint32_t* __restrict__ in, uint32_t n,
+                                                               uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t sm[kScanBlock / 64 + 1];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0u;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const uint64_t i = base + (uint64_t)k * kScanBlock + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t total;
+  (void)block_exclusive_scan_u32(s, sm, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the nb block sums in place, 1024 at a time
+// with a running carry; the grand total to *total_out when given.
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* __restrict__ bsum, uint32_t nb,
+                                                           uint32_t* __restrict__ total_out) {
+  __shared__ uint32_t sm[1024 / 64 + 1];
+  uint32_t carry = 0u;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024u) {
+    const uint32_t i = b0 + threadIdx.x;
+    const uint32_t x = i < nb ? bsum[i] : 0u;
+    uint32_t total;
+    const uint32_t e = block_exclusive_scan_u32(x, sm, total);
+    if (i < nb) bsum[i] = carry + e;
+    carry += total;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+// Block b: the exclusive scan of its 1024 entries plus the block's offset.
+// in and out may be the same array (each block reads its entries before it
+// writes them, and touches no other block's).
+__global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const uint32_t* in, uint32_t n,
+                                                                const uint32_t* __restrict__ bsum, uint32_t* out) {
+  __shared__ uint32_t sm[kScanBlock / 64 + 1];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+  uint32_t x[kScanPer];
+  uint32_t s = 0u;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const uint64_t i = base + k;
+    x[k] = i < n ? in[i] : 0u;
+    s += x[k];
+  }
+  uint32_t total;
+  uint32_t acc = block_exclusive_scan_u32(s, sm, total) + bsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const uint64_t i = base + k;
+    if (i < n) out[i] = acc;
+    acc += x[k];
+  }
+}
+
+size_t scan_temp_words(uint64_t n) { return div_up(n, kScanTile) + 1u; }
+
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* total_out,
+                                 uint32_t* bsum, hipStream_t s) {
+  if (n == 0u) return hipSuccess;
+  const uint32_t nb = div_up(n, kScanTile);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(nb), dim3(kScanBlock), 0, s, in, n, bsum);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, bsum, nb, total_out);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kScanBlock), 0, s, in, n, (const uint32_t*)bsum, out);
+  return hipGetLastError();
+}
+
+// ---- radix sort
+// Key index of round r, thread t of tile b: b * 1024 + r * 256 + t (ascending
+// in (r, t), the order the scatter ranks keys in).
+__global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n,
+                                                                int shift, uint32_t ntiles,
+                                                                uint32_t* __restrict__ hist) {
+  __shared__ uint32_t cnt[kRadix];
+  cnt[threadIdx.x] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)r * kSortBlock + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// hist: the digit-major exclusive scan, i.e. where digit d of tile b starts.
+// vals_in NULL: the values are the key indices.
+__global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
+                                                                   const uint32_t* __restrict__ vals_in, uint32_t n,
+                                                                   int shift, uint32_t ntiles,
+                                                                   const uint32_t* __restrict__ hist,
+                                                                   uint32_t* __restrict__ keys_out,
+                                                                   uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t base[kRadix];             // next position of each digit
+  __shared__ uint32_t cnt[kSortWaves][kRadix];  // this round's keys per wave and digit
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  base[t] = hist[(size_t)t * ntiles + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) cnt[w][t] = 0u;
+  __syncthreads();
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)r * kSortBlock + t;
+    const bool valid = i < n;
+    const uint32_t key = valid ? keys_in[i] : 0u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    // lanes of this wave with the same digit: agree bit by bit
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t ones = ballot(valid && bit);
+      peers &= bit ? ones : ~ones;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & below);
+    if (valid && rank == 0u) cnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += cnt[w][d];
+      keys_out[pos] = key;
+      vals_out[pos] = vals_in ? vals_in[i] : (uint32_t)i;
+    }
+    __syncthreads();
+    uint32_t add = 0u;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      add += cnt[w][t];
+      cnt[w][t] = 0u;
+    }
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+// Sorted probes, and each sorted sample's uv looked up by its sample index.
+__global__ __launch_bounds__(256) void sample_gather_kernel(const uint32_t* __restrict__ keys,
+                                                            const uint32_t* __restrict__ idx, uint32_t n,
+                                                            const float2* __restrict__ uv_raw,
+                                                            uint32_t* __restrict__ probe_out,
+                                                            float2* __restrict__ uv_out) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  probe_out[i] = keys[i];
+  uv_out[i] = uv_raw[idx[i]];
+}
+
+int sort_key_bits(int P) {
+  int bits = 1;
+  while ((1ll << bits) < (long long)P) ++bits;
+  return bits;
+}
+
+// Workspace layout (32-bit words) for up to `cap` samples: keys and values
+// twice over, the tiles' digit histograms, and the scans' block sums.
+struct SortSpace {
+  uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *bsum;
+};
+
+static size_t align_words(size_t w) { return (w + 63u) & ~(size_t)63u; }
+
+static SortSpace carve(void* temp, uint32_t cap) {
+  uint32_t* p = (uint32_t*)temp;
+  SortSpace sp;
+  const size_t s = align_words(cap);
+  sp.keys_a = p;
+  sp.vals_a = p + s;
+  sp.keys_b = p + 2 * s;
+  sp.vals_b = p + 3 * s;
+  sp.hist = p + 4 * s;
+  sp.bsum = sp.hist + align_words((size_t)kRadix * div_up(cap, kSortTile));
+  return sp;
+}
+
+size_t sort_temp_bytes(uint32_t cap, int P) {
+  const size_t s = align_words(cap), ntiles = div_up(cap, kSortTile);
+  const size_t hist = align_words((size_t)kRadix * ntiles);
+  const size_t bsum = align_words(std::max<size_t>(scan_temp_words((uint64_t)kRadix * ntiles),
+                                                   scan_temp_words((uint64_t)P + 1u)));
+  return 4 * (4 * s + hist + bsum);
+}
+
+hipError_t launch_sample_sort(const VolumeView& v, uint32_t S, uint32_t cap, void* temp, hipStream_t s) {
+  if (S == 0u) return hipSuccess;
+  if (S > cap) return hipErrorInvalidValue;
+  const SortSpace sp = carve(temp, cap);
+  const uint32_t ntiles = div_up(S, kSortTile);
+  const int passes = (sort_key_bits(v.P) + 7) / 8;
+  const uint32_t* kin = v.smp_probe_raw;
+  const uint32_t* vin = nullptr;
+  uint32_t* kout = sp.keys_a;
+  uint32_t* vout = sp.vals_a;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(kSortBlock), 0, s, kin, S, shift, ntiles, sp.hist);
+    hipError_t e = launch_exclusive_scan(sp.hist, kRadix * ntiles, sp.hist, nullptr, sp.bsum, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(kSortBlock), 0, s, kin, vin, S, shift, ntiles,
+                       (const uint32_t*)sp.hist, kout, vout);
+    kin = kout;
+    vin = vout;
+    kout = kout == sp.keys_a ? sp.keys_b : sp.keys_a;
+    vout = vout == sp.vals_a ? sp.vals_b : sp.vals_a;
+  }
+  hipLaunchKernelGGL(sample_gather_kernel, dim3(div_up(S, 256)), dim3(256), 0, s, kin, vin, S,
+                     (const float2*)v.smp_uv_raw, v.smp_probe, v.smp_uv);
+  return hipGetLastError();
+}
+
+hipError_t launch_offsets_scan(const uint32_t* counts, int P, uint32_t* offsets, uint32_t cap, void* temp,
+                               hipStream_t s) {
+  const SortSpace sp = carve(temp, cap);
+  return launch_exclusive_scan(counts, (uint32_t)P, offsets, offsets + P, sp.bsum, s);
+}
+
+}  // namespace adgi

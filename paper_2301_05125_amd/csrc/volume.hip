@@ -181,6 +181,7 @@ struct adgi_volume {
   void* d_sort_temp = nullptr;
   uint16_t* d_ray_perm = nullptr;  // coherent ray order tables (ray_order_table)
   size_t sort_temp_bytes = 0;
+  uint32_t sample_cap = 0;  // chain samples the sort workspace holds
   int32_t chain_count = 0, chain_steps = 0;  // of the last chain frame (0: chains not started)
   int64_t num_samples = 0;
   int32_t dyn_count = 0, dyn_steps = 0;      // dynamic chains of the last chain frame
@@ -301,11 +302,11 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
     if ((e = mark(2)) != hipSuccess) return e;
     const int lanes = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->chain_count);
     if ((e = launch_chains(v, vol->desc.storage == ADGI_FP16, vol->irr, vol->chain_count, lanes,
-                           (uint32_t)vol->num_samples, vol->d_sort_temp, vol->sort_temp_bytes, s)) != hipSuccess)
+                           (uint32_t)vol->num_samples, vol->d_sort_temp, vol->sample_cap, s)) != hipSuccess)
       return e;
     if (vol->dyn_last) {
       const int dl = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->dyn_count);
-      if ((e = launch_dyn_chains(v, vol->dyn_count, dl, vol->d_sort_temp, vol->sort_temp_bytes, s)) != hipSuccess)
+      if ((e = launch_dyn_chains(v, vol->dyn_count, dl, vol->d_sort_temp, vol->sample_cap, s)) != hipSuccess)
         return e;
     }
     if ((e = mark(3)) != hipSuccess) return e;
@@ -823,7 +824,8 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   if (d->storage == ADGI_PACKED) reqs.push_back({(void**)&v.pk_dec, (size_t)(kPkDecSize + kPkUpWords) * 4});
   if (d->max_chains > 0) {
     const size_t C = (size_t)d->max_chains, Smax = R / 2;
-    vol->sort_temp_bytes = chain_sort_temp_bytes((uint32_t)Smax, (int)P);
+    vol->sample_cap = (uint32_t)Smax;
+    vol->sort_temp_bytes = sort_temp_bytes((uint32_t)Smax, (int)P);
     reqs.push_back({(void**)&v.chain_state, C * 32});
     reqs.push_back({(void**)&v.smp_probe_raw, Smax * 4});
     reqs.push_back({(void**)&v.smp_uv_raw, Smax * 8});
@@ -1395,7 +1397,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
     if (2 * samples + dyn_rays > cap)
       return fail(ADGI_ERR_BUDGET, "2 * chain samples (%lld) + dynamic rays (up to %lld) exceed max_rays_per_frame",
                   (long long)(2 * samples), (long long)dyn_rays);
-    if (chain_sort_needed_bytes((uint32_t)samples, vol->P) > vol->sort_temp_bytes)
+    if (samples > (int64_t)vol->sample_cap)
       return fail(ADGI_ERR_INVALID_ARG, "sort workspace too small for %lld samples", (long long)samples);
   } else if (mode == ADGI_MODE_ADAPTIVE) {
     if (p->n_min < 1 || p->n_max < p->n_min) return fail(ADGI_ERR_BUDGET, "need 1 <= n_min <= n_max");
