@@ -255,8 +255,8 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
     """Chain frames: two warm uniform frames give the guide an irradiance,
     then `warmup` untimed and `steps` timed chain frames (scene update
     included, as in the budgeted steps), then synchronous frames for latency
-    and per-stage times (chain frames launch eagerly, stage events between
-    the kernels)."""
+    (captured frame graphs, as in the timed frames), then a few eager frames
+    with stage events between the kernels for the per-stage times."""
     P = sc.num_probes
     S = steps_per_chain - burn_in - 1
     Sd = dyn_steps - dyn_burn_in - 1 if dyn_chains else 0
@@ -295,9 +295,17 @@ def run_chains(adgi, torch, sc, storage, tuning, steps, warmup, latency_frames, 
         rays_seen.append(st["primary_rays"])
         if dyn_chains:
             marks.append(int(vol.read_probes(texels=False)["dyn_mark"].sum()))
-        for k in range(6):
-            stage[k] += st["ms_stage"][k] / latency_frames
         f += 1
+    tun = vol.get_tuning()
+    vol.set_tuning(use_graph=0)
+    stage_frames = 6  # both frame parities
+    for _ in range(stage_frames):
+        step_scene(vol, sc, f, adgi)
+        st = vol.update_chains(f, sync=True, **kw)
+        for k in range(6):
+            stage[k] += st["ms_stage"][k] / stage_frames
+        f += 1
+    vol.set_tuning(use_graph=tun["use_graph"])
     tw = vol.measure_chain_trace_work(f, **kw)
     rb = vol.read_probes(texels=False)
     n = rb["rays_per_probe"]

@@ -113,6 +113,18 @@ std::map<TuneKey, adgi_tuning> g_tune_cache;
 
 }  // namespace
 
+// What a chain frame's launches depend on besides the tuning and the scene
+// (the frame parameters themselves are read on the device): a captured chain
+// frame is replayed only for the same shape.
+struct ChainShape {
+  int parity = -1, chains = 0, lanes = 0, dyn = 0, dyn_lanes = 0;
+  int64_t samples = 0;
+  bool operator==(const ChainShape& o) const {
+    return parity == o.parity && chains == o.chains && lanes == o.lanes && dyn == o.dyn &&
+           dyn_lanes == o.dyn_lanes && samples == o.samples;
+  }
+};
+
 struct adgi_volume {
   adgi_volume_desc desc{};
   adgi_allocator alloc{};
@@ -172,7 +184,10 @@ struct adgi_volume {
   int bvh_depth = 0;
   double last_build_ms = 0.0;
   // frame
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // frame graphs: uniform, budgeted, and chain frames of even and odd frames
+  // (odd ones run detection), each chain graph for the shape it was taken at
+  hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  ChainShape chain_shape[2];
   adgi_tuning tun{};
   bool tuned = false;
   int32_t last_frame = -1, last_adaptive = 0;
@@ -1504,8 +1519,27 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
       vol->sticky = true;
       return fail(ADGI_ERR_DEVICE, "static-scratch frame failed: %s", hipGetErrorString(e));
     }
-  } else if (vol->tun.use_graph && mode != ADGI_MODE_CHAIN) {
-    if (!vol->exec[mode]) {
+  } else if (vol->tun.use_graph) {
+    int gslot = mode;
+    if (mode == ADGI_MODE_CHAIN) {
+      const adgi_tuning& t = vol->tun;
+      ChainShape sh;
+      sh.parity = vol->frame_now & 1;
+      sh.chains = vol->chain_count;
+      sh.lanes = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->chain_count);
+      sh.samples = vol->num_samples;
+      if (vol->dyn_last) {
+        sh.dyn = vol->dyn_count;
+        sh.dyn_lanes = t.chain_lanes ? t.chain_lanes : chain_lanes_auto(vol->dyn_count);
+      }
+      gslot = 2 + sh.parity;
+      if (vol->exec[gslot] && !(vol->chain_shape[sh.parity] == sh)) {
+        (void)hipGraphExecDestroy(vol->exec[gslot]);
+        vol->exec[gslot] = nullptr;
+      }
+      vol->chain_shape[sh.parity] = sh;
+    }
+    if (!vol->exec[gslot]) {
       // the frame up to the probe trace and its blend, captured apart and
       // composed with the event node that frees the scene between them
       hipGraph_t part[2] = {nullptr, nullptr}, graph = nullptr;
@@ -1520,7 +1554,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
       if (e == hipSuccess) e = hipGraphAddChildGraphNode(&na, graph, nullptr, 0, part[0]);
       if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ne, graph, &na, 1, vol->ev_traced);
       if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nb, graph, &na, 1, part[1]);
-      if (e == hipSuccess) e = hipGraphInstantiate(&vol->exec[mode], graph, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = hipGraphInstantiate(&vol->exec[gslot], graph, nullptr, nullptr, 0);
       for (hipGraph_t g : {part[0], part[1], graph})
         if (g) (void)hipGraphDestroy(g);
       if (e != hipSuccess || e2 != hipSuccess) {
@@ -1528,7 +1562,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
         return fail(ADGI_ERR_DEVICE, "frame graph failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
       }
     }
-    HIP_TRY(vol, hipGraphLaunch(vol->exec[mode], vol->stream));
+    HIP_TRY(vol, hipGraphLaunch(vol->exec[gslot], vol->stream));
   } else {
     HIP_TRY(vol, enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr, false, vol->ev_traced));
   }
@@ -1559,7 +1593,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
       float ms = 0.f;
       HIP_TRY(vol, hipEventElapsedTime(&ms, vol->ev_t0, vol->ev_t1));
       stats->ms_total = ms;
-      if (use_static || !vol->tun.use_graph || mode == ADGI_MODE_CHAIN) {
+      if (use_static || !vol->tun.use_graph) {
         for (int k = 0; k < 6; ++k)
           HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[k], vol->ev_k[k], vol->ev_k[k + 1]));
         HIP_TRY(vol, hipEventElapsedTime(&stats->ms_stage[6], vol->ev_k[4], vol->ev_k[7]));

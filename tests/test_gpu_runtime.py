@@ -246,6 +246,7 @@ def _same_chain(a, b):
 
 
 @pytest.mark.parametrize("tuning", [
+    {"use_graph": 0},
     {"persistent": 0},
     {"trace_block": 256, "trace_waves_per_cu": 16},
     {"bvh_width": 4},
@@ -256,7 +257,8 @@ def _same_chain(a, b):
     {"chain_lanes": 32},
 ])
 def test_chain_launch_shape_does_not_change_results(tuning):
-    """Every launch shape, and the one-thread-per-chain kernel against the
+    """Every launch shape, eager frames against the captured frame graphs
+    (the default), and the one-thread-per-chain kernel against the
     prefetching groups (16 lanes for 768 chains by default), give the same
     chains and texels bit for bit."""
     sc = _small_field()
@@ -275,6 +277,32 @@ def test_chain_snapshot_resumes_bit_identically():
     got = _chain_run(sc, 2, vol=vol2, start=3)
     vol2.destroy_volume()
     _same_chain(ref, got)
+
+
+def test_chain_graph_follows_shape_changes():
+    """A chain frame graph is taken per frame parity and replayed only for the
+    shape it was taken at: changing the chain count, the samples per chain
+    and switching dynamic chains on and off between frames gives the same
+    chains and texels as eager frames, bit for bit."""
+    sc = _small_field()
+    seq = [(512, 20, 3, 0), (512, 20, 3, 0), (768, 20, 3, 0), (768, 24, 3, 64), (768, 24, 3, 64),
+           (512, 20, 3, 0), (512, 20, 3, 0)]
+
+    def run(use_graph):
+        vol = adgi.volume_for_scene(sc, max_rays=2 * 768 * 24 + sc.num_probes * 232, seed=4, max_chains=768)
+        vol.set_tuning(use_graph=use_graph)
+        vol.update_probes(0, adaptive=False, n_uniform=32, sync=True)
+        for f, (c, m, k, dyn) in enumerate(seq, start=1):
+            vol.update_scene(sc.positions_at(f), light_pos=sc.light_positions(f),
+                             light_intensity=sc.light_intensity, sky=sc.sky,
+                             mode=adgi.ADGI_SCENE_REFIT, refit_range=(0, sc.anim_vertices))
+            kw = dict(dyn_chains=dyn, dyn_steps=12, dyn_burn_in=2) if dyn else {}
+            vol.update_chains(f, c, m, k, sync=True, **kw)
+        rb = vol.read_probes()
+        vol.destroy_volume()
+        return rb
+
+    _same_chain(run(0), run(1))
 
 
 def test_chain_and_budgeted_frames_interleave():
@@ -353,7 +381,7 @@ def _same_dyn(a, b):
         assert np.array_equal(a[k], b[k]), (k, int(np.count_nonzero(a[k] != b[k])))
 
 
-@pytest.mark.parametrize("tuning", [{"chain_lanes": 1}, {"persistent": 0}, {"bvh_width": 4}])
+@pytest.mark.parametrize("tuning", [{"use_graph": 0}, {"chain_lanes": 1}, {"persistent": 0}, {"bvh_width": 4}])
 def test_dynamic_chain_launch_shape_does_not_change_results(tuning):
     sc = _small_field()
     a = _dyn_run(sc, 5)
