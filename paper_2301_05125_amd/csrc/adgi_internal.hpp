@@ -107,7 +107,8 @@ struct RefitView {
   int32_t cut, subtrees, deep_levels;
   const int32_t* leaf_slots;   // RefitPlan::leaf_slots on the device
   int32_t num_leaf_slots;
-  float* tri_box;              // [T][6] scratch: each triangle slot's box
+  float* tri_box;              // [T][6] each triangle slot's box, kept from refit to refit
+  const int32_t* range;        // [2] on the device: the vertex range this refit moves
 };
 // Refit plan of a BVH2: the internal nodes at depth >= cut are grouped, in
 // every level, by their ancestor at depth `cut` (one subtree per workgroup,

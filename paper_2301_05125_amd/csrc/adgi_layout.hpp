@@ -58,6 +58,9 @@ struct SceneParams {
   int32_t num_tris;
   int32_t num_nodes;
   int32_t num_big;    // triangle slots [0, num_big) are tested by every ray before the tree
+  // vertices the current refit moves: the refit rebuilds the records and
+  // boxes of the triangles that touch [refit_vb, refit_ve) only
+  int32_t refit_vb, refit_ve;
 };
 
 struct FrameParams {

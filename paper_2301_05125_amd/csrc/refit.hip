@@ -27,13 +27,17 @@ __device__ __forceinline__ void write_tri(const RefitView& r, int s, int t, cons
   r.tris[3 * (size_t)s + 2] = make_float4(v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2], 0.f);
 }
 
-// Record of triangle slot s and its box (min xyz, max xyz of its vertices).
+// Record of triangle slot s and its box (min xyz, max xyz of its vertices),
+// for the triangles with a vertex in this refit's range; the others did not
+// move, and their records and boxes from an earlier refit or the build stand.
 __global__ void refit_tris_kernel(RefitView r) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= r.num_tris) return;
   const int t = r.tri_order[s];
-  const float* p[3] = {r.positions + 3 * (size_t)r.indices[3 * t], r.positions + 3 * (size_t)r.indices[3 * t + 1],
-                       r.positions + 3 * (size_t)r.indices[3 * t + 2]};
+  const int i0 = r.indices[3 * t], i1 = r.indices[3 * t + 1], i2 = r.indices[3 * t + 2];
+  const int vb = r.range[0], ve = r.range[1];
+  if (!((i0 >= vb && i0 < ve) || (i1 >= vb && i1 < ve) || (i2 >= vb && i2 < ve))) return;
+  const float* p[3] = {r.positions + 3 * (size_t)i0, r.positions + 3 * (size_t)i1, r.positions + 3 * (size_t)i2};
   write_tri(r, s, t, p[0], p[1], p[2]);
   float* b = r.tri_box + 6 * (size_t)s;
   for (int a = 0; a < 3; ++a) {

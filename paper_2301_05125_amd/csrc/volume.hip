@@ -172,6 +172,7 @@ struct adgi_volume {
   float* d_tri_box = nullptr;                        // refit scratch: triangle boxes
   int32_t refit_cut = 0, refit_subtrees = 0, refit_deep = 0, num_leaf_slots = 0;
   hipGraphExec_t refit_exec = nullptr;
+  bool refit_all = true;  // the next refit rebuilds every triangle (none since the build)
   float4* d_nodes = nullptr;
   float4* d_nodes4 = nullptr;   // BVH4 collapse (null when its stack bound does not fit)
   int32_t* d_src4 = nullptr;    // BVH4 slot -> BVH2 slot, for the refit gather
@@ -1116,25 +1117,33 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     hp.num_nodes = nn;
     hp.num_big = bvh.num_big;
     vol->num_big = bvh.num_big;
+    // the build leaves no triangle boxes: the first refit computes them all
+    vol->refit_all = true;
+    HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice, ss));
   } else {
     hp.num_nodes = vol->num_nodes;
     hp.num_big = vol->num_big;
+    hp.refit_vb = vol->refit_all ? 0 : (int32_t)vb;
+    hp.refit_ve = vol->refit_all ? vol->nv : (int32_t)ve;
     const size_t cnt = (size_t)(ve - vb) * 3;
     if (cnt) {
       std::memcpy(vol->h_stage + 3 * vb, sc->positions + 3 * vb, cnt * 4);
       HIP_TRY(vol, hipMemcpyAsync(vol->d_pos + 3 * vb, vol->h_stage + 3 * vb, cnt * 4,
                                   hipMemcpyHostToDevice, ss));
     }
-    // the positions are read by the refit alone; triangles, nodes and lights
-    // change only after the queued work that reads them
+    // the positions are read by the refit alone; triangles, nodes, lights and
+    // the scene constants change only after the queued work that reads them
     HIP_TRY(vol, hipStreamWaitEvent(ss, vol->ev_traced, 0));
+    // the constants first: the refit reads its vertex range from them
+    HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice, ss));
     if (cnt) {
       // the refit is captured once per build
       if (!vol->refit_exec) {
         RefitView r{vol->d_pos,   vol->d_idx,     vol->d_order,         vol->d_tris,
                     vol->d_nodes, vol->d_levels,  vol->nt,              vol->num_nodes,
                     vol->pad_abs, vol->d_refit_tab, vol->refit_cut, vol->refit_subtrees,
-                    vol->refit_deep,  vol->d_leaf_slots, vol->num_leaf_slots, vol->d_tri_box};
+                    vol->refit_deep,  vol->d_leaf_slots, vol->num_leaf_slots, vol->d_tri_box,
+                    &vol->v.scene->refit_vb};
         hipGraph_t graph = nullptr;
         HIP_TRY(vol, hipStreamBeginCapture(ss, hipStreamCaptureModeRelaxed));
         hipError_t e = launch_refit(r, vol->level_offsets, ss);
@@ -1155,9 +1164,9 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
         }
       }
       HIP_TRY(vol, hipGraphLaunch(vol->refit_exec, ss));
+      vol->refit_all = false;
     }
   }
-  HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice, ss));
   HIP_TRY(vol, hipEventRecord(vol->ev_stage, ss));
   // every later use of the volume's stream follows the new scene
   HIP_TRY(vol, hipEventRecord(vol->ev_refit, ss));

@@ -101,6 +101,47 @@ def test_launch_shape_does_not_change_results(tuning):
     _same(_run(sc, 4, **kw), _run(sc, 4, tuning=tuning, **kw))
 
 
+def test_refit_of_a_vertex_range_matches_a_full_refit():
+    """A REFIT that names the moved vertices rebuilds only the triangles that
+    touch them; frames after it match those after refits of every vertex, bit
+    for bit (ray records and hit triangles included), also when the range
+    changes from frame to frame and right after a REBUILD."""
+    sc = _small_field()
+    P = sc.num_probes
+
+    def refit(vol, f, rng):
+        vol.update_scene(sc.positions_at(f), light_pos=sc.light_positions(f),
+                         light_intensity=sc.light_intensity, sky=sc.sky,
+                         mode=adgi.ADGI_SCENE_REFIT, refit_range=rng)
+
+    def run(ranged):
+        vol = adgi.volume_for_scene(sc, max_rays=P * 64, seed=3, debug=True)
+        out = []
+        for f in range(6):
+            if f == 3:  # a REBUILD mid-way: the next refit must redo every triangle
+                vol.update_scene(sc.positions_at(f), sc.indices, albedo=sc.albedo,
+                                 light_pos=sc.light_positions(f), light_intensity=sc.light_intensity,
+                                 sky=sc.sky, mode=adgi.ADGI_SCENE_REBUILD)
+            if not ranged:
+                refit(vol, f, (0, sc.positions.shape[0]))
+            elif f == 2:  # half the moving vertices, then the rest
+                refit(vol, f, (0, sc.anim_vertices // 2))
+                refit(vol, f, (sc.anim_vertices // 2, sc.anim_vertices))
+            else:
+                refit(vol, f, (0, sc.anim_vertices))
+            vol.update_probes(f, adaptive=False, n_uniform=64, sync=True)
+            rb = vol.read_probes(debug=True)
+            out.append([rb[k].copy() for k in ("irradiance", "depth", "hit_tri", "ray_record")])
+        vol.destroy_volume()
+        return out
+
+    assert sc.anim_vertices > 0
+    a, b = run(True), run(False)
+    for fa, fb in zip(a, b):
+        for x, y in zip(fa, fb):
+            assert np.array_equal(x, y)
+
+
 def test_autotune_keeps_state_and_results():
     sc = _small_field()
     kw = dict(adaptive=True, budget=sc.num_probes * 40, n_min=8, n_max=256)
