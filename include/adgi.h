@@ -136,7 +136,11 @@ typedef struct {
   float sky[3];               /* radiance of rays that leave the scene            */
   int32_t mode;               /* REBUILD: new triangles, host SAH build.
                                  REFIT: same V and T, positions[vbegin, vend)
-                                 changed; boxes are refitted on the device.       */
+                                 changed (only they are uploaded; the others keep
+                                 their last uploaded values); the triangles that
+                                 touch the range are rebuilt and the boxes refitted
+                                 on the device (every triangle on the first REFIT
+                                 after a REBUILD).                                */
   int32_t refit_vertex_begin; /* REFIT only; [0, V]                                */
   int32_t refit_vertex_end;   /* REFIT only; [begin, V]                            */
 } adgi_scene_desc;
