@@ -45,6 +45,10 @@ WORKLOADS = {
 }
 
 
+# committed counter summary of the blend kernel of each texel storage
+BLEND_PROFILE = {"fp32": "blend_boxfield", "fp16": "blend_fp16_boxfield", "packed": "blend_packed_boxfield"}
+
+
 def blend_bytes(P, R, storage):
     """Algorithmic HBM bytes of one blend launch: per probe read the interior
     texels (36 x 12 + 196 x 8 B FP32), write full tiles (64 x 12 + 256 x 8 B),
@@ -224,6 +228,8 @@ def run_config(adgi, torch, sc, cfg, storage_name, tuning, steps, warmup, latenc
                                               "blend", "probe_trace_hit", "probe_trace_shade"], stages))},
            "roofline_blend": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK_GBS, "ms": stages[5], "algorithmic_bytes": bbytes,
+                              "traffic": read_profile(BLEND_PROFILE[storage_name],
+                                                      source_hash("blend.hip", "adgi_device.hpp")).get("traffic"),
                               "target_ms_at_half_peak": bbytes / (0.5 * HBM_PEAK_GBS * 1e9) * 1e3}}
     for n in uniform:
         v2 = adgi.volume_for_scene(sc, storage=storage, max_rays=max_rays, seed=11)
@@ -794,7 +800,7 @@ def main():
     blend_gbs = bbytes / (blend_ms * 1e-3) / 1e9
     h_trace = source_hash("trace.hip", "adgi_device.hpp", "adgi_layout.hpp", "bvh_build.cpp")
     h_blend = source_hash("blend.hip", "adgi_device.hpp")
-    prof_blend = read_profile("blend_boxfield", h_blend)
+    prof_blend = read_profile(BLEND_PROFILE[args.storage], h_blend)
     width = 4 if tuning.get("bvh_width") == 4 else 2
 
     def trace_roof(kernel, ms, nodes, boxes, tris, rays, prof_key):
