@@ -148,8 +148,9 @@ __device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d) {
   return peers;
 }
 
-// Per tile, the count of each digit (LDS atomics: counting per wave with
-// ballots first measured slower, 16.1 against 13.8 us for 4 M keys).
+// Per tile, the count of each digit, with LDS atomics (counting per wave with
+// ballots, as the scatter ranks, measured slower: 16.1 against 13.8 us for
+// 4 M keys).
 __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n,
                                                                 int shift, uint32_t ntiles,
                                                                 uint32_t* __restrict__ hist) {

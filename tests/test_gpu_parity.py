@@ -264,6 +264,23 @@ def test_chains_flat_box_field_lockstep():
     _assert_chain_parity(res)
 
 
+def test_chains_many_probes_lockstep():
+    """More than 2^16 probes (96 x 8 x 96): the probe keys take 17 bits, so
+    the sample sort runs three radix passes; samples, their order within each
+    probe and the texels still match the oracle. Four static boxes on a
+    20 x 20 field keep every probe at least 0.01 from a surface: with 73,728
+    probes among 64 boxes some probe lies within 1e-5 of a face, where the
+    FP32 ray origin alone moves a depth sample by more than the texel bar
+    (the budgeted lockstep holds such rays to per-ray bars instead)."""
+    from tests.parity import run_chain_lockstep
+    sc = scenes.box_field(seed=scenes.SEED_BASE + 310, lattice=2, pitch=10.0, dims=(96, 8, 96), n_lights=1,
+                          frames=4, anim_fraction=0.0)
+    assert sc.num_probes > 65536
+    res = run_chain_lockstep(sc, frames=2, chains=512, steps=14, burn_in=3, n_uniform=8)
+    print({k: v for k, v in res.items() if not isinstance(v, np.ndarray)})
+    _assert_chain_parity(res)
+
+
 def test_chains_box_field_ragged_lockstep():
     """Box field, 8 x 2 x 8 probes, 1000 chains (not a multiple of the wave)
     x 23 steps (burn-in 4), FP16 texels against the binary16-emulating oracle."""
