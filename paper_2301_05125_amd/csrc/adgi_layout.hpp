@@ -179,6 +179,7 @@ struct VolumeView {
   uint32_t* pilot_bins;       // [8P] pilot irradiance texel | depth texel << 16
   int32_t* dbg_ptri;          // [8P] pilot closest triangle (debug)
   uint8_t* dbg_pshadow;       // [8P] pilot shadow bits (debug)
+  uint32_t* batch_probe;      // [max_rays / 64] budgeted frames: the probe of ray 64 b
   uint32_t* ray_bins;         // [max_rays] probe rays: interior irradiance texel
                               // | interior depth texel << 16 of the direction
   // lit hits waiting for their shadow rays (the pilot and probe passes of a

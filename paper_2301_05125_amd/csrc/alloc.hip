@@ -268,6 +268,8 @@ __global__ __launch_bounds__(256) void alloc_write_kernel(VolumeView v) {
     v.n[i] = n;
     v.offsets[i] = (uint32_t)off;
     nmin = nmax = n;
+    // the 64-ray trace batches that start among this probe's rays
+    for (int64_t r = (off + 63) & ~(int64_t)63; r < off + n; r += 64) v.batch_probe[r >> 6] = (uint32_t)i;
   }
   count_buckets(v, i < v.P, n, hist);
   // block minimum and maximum, then one atomic each per block (a per-wave

@@ -594,8 +594,11 @@ __device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32
   float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
   bool shade = true;
   uint32_t dst = r;
-  // probe of the batch's first ray (the same in every lane)
-  const int i0 = KIND == KIND_PRIMARY ? probe_of_ray(v.offsets, v.P, b * br) : 0;
+  // probe of the batch's first ray (the same in every lane): budgeted frames
+  // list it per 64-ray batch with the allocation, uniform ones divide
+  int i0 = 0;
+  if (KIND == KIND_PRIMARY)
+    i0 = v.fp->adaptive ? (int)v.batch_probe[b] : (int)(b * br / (uint32_t)v.fp->n_uniform);
   if (active) gen_ray<KIND>(v, r, i0, o, d, shade, dst);
   if (KIND == KIND_PILOT && active && v.fp->pilot_reuse) {
     const float2 uv = oct_encode(d);

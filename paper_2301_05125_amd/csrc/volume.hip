@@ -683,6 +683,7 @@ void frame_scratch_each(VolumeView& v, size_t P, size_t R, size_t H, F&& f) {
   f((void**)&v.blk_off, pb * 4);
   f((void**)&v.order, P * 4);
   f((void**)&v.ray_bins, R * 4);
+  f((void**)&v.batch_probe, ((R + 63) / 64) * 4);
   f((void**)&v.hit_pos, H * 16);
   f((void**)&v.hit_nrm, H * 16);
   f((void**)&v.hit_vis, H * 4);
