@@ -173,8 +173,10 @@ typedef struct {
    * traces two rays from its probe's centre: d(uv), shaded with direct light
    * and blended into the irradiance texel of d, and -d, whose distance only
    * is blended into the depth texel of -d. Per-probe lists are the samples
-   * in chain-major order. Pilots run as in ADAPTIVE; detection and
-   * allocation are skipped. Chain frames run eagerly (no graph). */
+   * in chain-major order. Pilots run as in ADAPTIVE and detection on odd
+   * frames; the budget split is skipped. With use_graph, chain frames are
+   * captured as graphs too, one per frame parity, captured again when the
+   * chain count, lanes, samples or dynamic chain count change. */
   int32_t chain_count;        /* C, 1..max_chains                                  */
   int32_t chain_steps;        /* M, 2..ADGI_CHAIN_MAX_STEPS                        */
   int32_t chain_burn_in;      /* K, 0 <= K <= M - 2                                */
