@@ -200,7 +200,7 @@ struct VolumeView {
   uint32_t* pair_off;         // [ceil(hit_cap/64) + 1] exclusive scan of pair_cnt
   uint32_t* pair_blk;         // [ceil(hit_cap/64)/kPairScanPer + 1] scan block totals
   uint32_t hit_cap;           // max(max_rays, 8 P)
-  uint32_t batch_rays;        // rays per wave batch of a trace pass: 64, or 32 / 16 for small pilot passes
+  uint32_t batch_rays;        // rays per wave batch of a trace pass: 64, or 32 .. 1 for small pilot passes
   int32_t* dbg_tri;           // [max_rays] or null
   uint8_t* dbg_shadow;
   uint16_t* dbg_ibin;

@@ -572,95 +572,127 @@ __device__ __forceinline__ void flush_stats(const VolumeView& v, const Work& w, 
   }
 }
 
-// ---- closest-hit kernel
-// A wave owns a batch of consecutive rays (batch b = rays [B b, B b + B),
-// B = v.batch_rays: 64, or 32 / 16 for a pass too small to give every CU
-// several waves, which then ends sooner with fewer rays per wave); a
-// persistent launch walks the batches with a grid stride, so no wave ever
-// waits on a shared counter. Every ray finds its closest hit. A miss, a back
-// face, a distance-only ray or a lit hit with no light on its front side is
-// final and is written at once; a lit hit with lights on its front side
-// keeps its hit point, t, normal and triangle at its own index, its pending
-// shadow-ray count in its visibility word, and puts one (lane, light) pair
-// per such light into the batch's pair segment, all pairs of light 0 first,
-// then light 1, and so on (neighbouring shadow rays mostly share a light).
+// One lane's ray of a batch after its closest hit: x and n the hit point and
+// unit face normal, need the lights on the front side of a lit hit (0 for a
+// miss, a back face, a distance-only ray or a hit no light faces).
+struct BatchHit {
+  bool active;
+  uint32_t dst;
+  float3 x, n;
+  float t;
+  int id, slot;
+  uint32_t need;
+};
+
 template <int KIND, bool COUNT, bool W4>
-__device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32_t b, uint32_t total, Work& w,
-                                          uint32_t& shadow) {
+__device__ __forceinline__ BatchHit closest_of_batch(const VolumeView& v, Stack& st, uint32_t b, uint32_t total,
+                                                     Work& w) {
   const SceneParams& sc = *v.scene;
   const uint32_t lane = lane_id(), br = v.batch_rays;
   const uint32_t r = b * br + lane;
-  const bool active = lane < br && r < total;
+  BatchHit h;
+  h.active = lane < br && r < total;
   float3 o = make_float3(0.f, 0.f, 0.f), d = make_float3(0.f, 0.f, 1.f);
   bool shade = true;
-  uint32_t dst = r;
+  h.dst = r;
   // probe of the batch's first ray (the same in every lane): budgeted frames
   // list it per 64-ray batch with the allocation, uniform ones divide
   int i0 = 0;
   if (KIND == KIND_PRIMARY)
     i0 = v.fp->adaptive ? (int)v.batch_probe[b] : (int)(b * br / (uint32_t)v.fp->n_uniform);
-  if (active) gen_ray<KIND>(v, r, i0, o, d, shade, dst);
-  if (KIND == KIND_PILOT && active && v.fp->pilot_reuse) {
+  if (h.active) gen_ray<KIND>(v, r, i0, o, d, shade, h.dst);
+  if (KIND == KIND_PILOT && h.active && v.fp->pilot_reuse) {
     const float2 uv = oct_encode(d);
     v.pilot_bins[r] = oct_bin(uv, v.irr_res - 2) | (oct_bin(uv, v.dep_res - 2) << 16);
   }
-  if (KIND == KIND_PRIMARY && active) {
+  if (KIND == KIND_PRIMARY && h.active) {
     // the interior irradiance and depth texels the ray's direction falls in,
     // for the blend (one 4-byte word per ray instead of regenerating the
     // direction there)
     const float2 uv = oct_encode(d);
     const uint32_t bI = oct_bin(uv, v.irr_res - 2), bD = oct_bin(uv, v.dep_res - 2);
-    v.ray_bins[dst] = bI | (bD << 16);
+    v.ray_bins[h.dst] = bI | (bD << 16);
     if (v.fp->debug) {
-      v.dbg_ibin[dst] = (uint16_t)bI;
-      v.dbg_dbin[dst] = (uint16_t)bD;
+      v.dbg_ibin[h.dst] = (uint16_t)bI;
+      v.dbg_dbin[h.dst] = (uint16_t)bD;
     }
   }
-  float t = INFINITY;
+  h.t = INFINITY;
   bool front = false;
-  int id = -1, slot = -1;
-  if (active && sc.num_tris > 0) {
+  h.id = -1;
+  h.slot = -1;
+  if (h.active && sc.num_tris > 0) {
     Ray ray = make_ray(o, d);
-    slot = W4 ? closest_hit4<COUNT>(v, ray, st, t, front, id, w) : closest_hit<COUNT>(v, ray, st, t, front, id, w);
-    if (slot < 0) {
-      id = -1;
-      t = INFINITY;
+    h.slot = W4 ? closest_hit4<COUNT>(v, ray, st, h.t, front, h.id, w)
+                : closest_hit<COUNT>(v, ray, st, h.t, front, h.id, w);
+    if (h.slot < 0) {
+      h.id = -1;
+      h.t = INFINITY;
     }
   }
-  const bool lit = active && slot >= 0 && front && shade;
-  uint32_t need = 0u;
-  if (lit) {
-    const float4* tp = v.tris + 3 * (size_t)slot;
+  h.need = 0u;
+  h.x = h.n = make_float3(0.f, 0.f, 0.f);
+  if (h.active && h.slot >= 0 && front && shade) {
+    const float4* tp = v.tris + 3 * (size_t)h.slot;
     const float4 tb = tp[1], tc = tp[2];
     const float nx = tb.y * tc.z - tb.z * tc.y, ny = tb.z * tc.x - tb.x * tc.z, nz = tb.x * tc.y - tb.y * tc.x;
     const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
-    const float3 nrm = make_float3(nx * inv, ny * inv, nz * inv);
-    const float3 x = make_float3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
-    need = lights_facing(sc, x, nrm);
-    if (need) {
-      v.hit_pos[r] = make_float4(x.x, x.y, x.z, t);
-      v.hit_nrm[r] = make_float4(nrm.x, nrm.y, nrm.z, __int_as_float(id));
-      v.hit_vis[r] = (uint32_t)__popc(need) << 8;
-      if (KIND == KIND_PRIMARY) v.hit_dst[r] = dst;
-    }
+    h.n = make_float3(nx * inv, ny * inv, nz * inv);
+    h.x = make_float3(fmaf(h.t, d.x, o.x), fmaf(h.t, d.y, o.y), fmaf(h.t, d.z, o.z));
+    h.need = lights_facing(sc, h.x, h.n);
+  }
+  return h;
+}
+
+// The final output of a ray with no shadow ray to wait for: the sky for a
+// miss, black for any hit.
+template <int KIND>
+__device__ __forceinline__ void emit_unshadowed(const VolumeView& v, const BatchHit& h) {
+  const SceneParams& sc = *v.scene;
+  const float3 L = h.slot < 0 ? make_float3(sc.sky[0], sc.sky[1], sc.sky[2]) : make_float3(0.f, 0.f, 0.f);
+  emit_ray<KIND>(v, h.dst, L, h.t, h.id, 0u);
+}
+
+// ---- closest-hit kernel
+// A wave owns a batch of consecutive rays (batch b = rays [B b, B b + B),
+// B = v.batch_rays = 64; the fused pilot pass below takes fewer when the pass
+// is too small to fill the launch's waves); a persistent launch walks the
+// batches with a grid stride, so no wave ever waits on a shared counter.
+// Every ray finds its closest hit. A miss, a back face, a distance-only ray
+// or a lit hit with no light on its front side is final and is written at
+// once; a lit hit with lights on its front side keeps its hit point, t,
+// normal and triangle at its own index, its pending shadow-ray count in its
+// visibility word, and puts one (lane, light) pair per such light into the
+// batch's pair segment, all pairs of light 0 first, then light 1, and so on
+// (neighbouring shadow rays mostly share a light).
+template <int KIND, bool COUNT, bool W4>
+__device__ __forceinline__ void hit_batch(const VolumeView& v, Stack& st, uint32_t b, uint32_t total, Work& w,
+                                          uint32_t& shadow) {
+  const SceneParams& sc = *v.scene;
+  const uint32_t lane = lane_id();
+  const uint32_t r = b * v.batch_rays + lane;
+  const BatchHit h = closest_of_batch<KIND, COUNT, W4>(v, st, b, total, w);
+  if (h.need) {
+    v.hit_pos[r] = make_float4(h.x.x, h.x.y, h.x.z, h.t);
+    v.hit_nrm[r] = make_float4(h.n.x, h.n.y, h.n.z, __int_as_float(h.id));
+    v.hit_vis[r] = (uint32_t)__popc(h.need) << 8;
+    if (KIND == KIND_PRIMARY) v.hit_dst[r] = h.dst;
   }
   uint16_t* seg = v.pairs + (size_t)b * kPairsPerBatch;
   uint32_t n = 0u;
   for (int l = 0; l < sc.num_lights; ++l) {
-    const bool p = (need >> l) & 1u;
+    const bool p = (h.need >> l) & 1u;
     const uint64_t m = ballot(p);
     if (p) seg[n + lanes_below(m)] = (uint16_t)(lane | ((uint32_t)l << 6));
     n += (uint32_t)__popcll(m);
   }
   if (lane == 0) v.pair_cnt[b] = n;
   shadow += n;
-  if (active && !need) {
-    const bool miss = slot < 0;
-    const float3 L = miss ? make_float3(sc.sky[0], sc.sky[1], sc.sky[2]) : make_float3(0.f, 0.f, 0.f);
-    emit_ray<KIND>(v, dst, L, t, id, 0u);
-  } else if (active && v.fp->debug) {
-    if (KIND == KIND_PILOT) v.dbg_ptri[dst] = id;
-    else v.dbg_tri[dst] = id;
+  if (h.active && !h.need) {
+    emit_unshadowed<KIND>(v, h);
+  } else if (h.active && v.fp->debug) {
+    if (KIND == KIND_PILOT) v.dbg_ptri[h.dst] = h.id;
+    else v.dbg_tri[h.dst] = h.id;
   }
 }
 
@@ -782,6 +814,43 @@ __global__ __launch_bounds__(1024) void pair_scan_single_kernel(VolumeView v) {
   }
 }
 
+// Whether light l is blocked from the hit point pos (normal nrm): any hit on
+// the segment from pos offset along the normal to the light, shortened.
+template <bool COUNT, bool W4>
+__device__ __forceinline__ bool shadow_blocked(const VolumeView& v, const SceneParams& sc, float4 pos, float4 nrm,
+                                               uint32_t l, Stack& st, Work& w) {
+  const float off_len = kShadowOffset * v.s_diag;
+  const float3 so = make_float3(fmaf(off_len, nrm.x, pos.x), fmaf(off_len, nrm.y, pos.y),
+                                fmaf(off_len, nrm.z, pos.z));
+  const float gx = sc.lpos[l][0] - so.x, gy = sc.lpos[l][1] - so.y, gz = sc.lpos[l][2] - so.z;
+  const float len = sqrtf(gx * gx + gy * gy + gz * gz);
+  const float il = 1.0f / len;
+  const Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
+  const float smax = len * (1.0f - kShadowShorten);
+  return W4 ? any_hit4<COUNT>(v, sray, smax, st, w) : any_hit<COUNT>(v, sray, smax, st, w);
+}
+
+// Radiance leaving a lit hit (Lambertian, albedo of triangle id): rho/pi
+// times the sum over the visible lights `bits` of I_l cos / d^2, the lights
+// taken in index order.
+__device__ __forceinline__ float3 lit_radiance(const VolumeView& v, const SceneParams& sc, float4 pos, float4 nrm,
+                                               int id, uint32_t bits) {
+  float er = 0.f, eg = 0.f, eb = 0.f;
+  for (int k = 0; k < sc.num_lights; ++k) {
+    if (!((bits >> k) & 1u)) continue;
+    const float lx = sc.lpos[k][0] - pos.x, ly = sc.lpos[k][1] - pos.y, lz = sc.lpos[k][2] - pos.z;
+    const float d2 = lx * lx + ly * ly + lz * lz;
+    const float cs = (nrm.x * lx + nrm.y * ly + nrm.z * lz) / sqrtf(d2);
+    const float wl = fmaxf(cs, 0.0f) / d2;
+    er = fmaf(sc.lint[k][0], wl, er);
+    eg = fmaf(sc.lint[k][1], wl, eg);
+    eb = fmaf(sc.lint[k][2], wl, eb);
+  }
+  const float4 rho = v.albedo[id];
+  const float inv_pi = 0.318309886183790671538f;
+  return make_float3(rho.x * inv_pi * er, rho.y * inv_pi * eg, rho.z * inv_pi * eb);
+}
+
 // ---- shadow and shading kernel
 // Wave-batch q takes pairs [64q, 64q + 64) of the frame's pair list (the
 // batches' segments end to end): lane p finds its batch by binary search in
@@ -807,35 +876,14 @@ __device__ __forceinline__ void shade_batch(const VolumeView& v, Stack& st, uint
   const uint32_t e = v.pairs[(size_t)b * kPairsPerBatch + (p - v.pair_off[b])];
   const uint32_t r = b * v.batch_rays + (e & 63u), l = e >> 6;
   const float4 pos = v.hit_pos[r], nrm = v.hit_nrm[r];
-  const float off_len = kShadowOffset * v.s_diag;
-  const float3 so = make_float3(fmaf(off_len, nrm.x, pos.x), fmaf(off_len, nrm.y, pos.y),
-                                fmaf(off_len, nrm.z, pos.z));
-  const float gx = sc.lpos[l][0] - so.x, gy = sc.lpos[l][1] - so.y, gz = sc.lpos[l][2] - so.z;
-  const float len = sqrtf(gx * gx + gy * gy + gz * gz);
-  const float il = 1.0f / len;
-  const Ray sray = make_ray(so, make_float3(gx * il, gy * il, gz * il));
-  const float smax = len * (1.0f - kShadowShorten);
-  const bool blocked = W4 ? any_hit4<COUNT>(v, sray, smax, st, w) : any_hit<COUNT>(v, sray, smax, st, w);
+  const bool blocked = shadow_blocked<COUNT, W4>(v, sc, pos, nrm, l, st, w);
   const uint32_t mine = blocked ? 0u : 1u << l;
   const uint32_t old = atomicAdd(&v.hit_vis[r], mine - 256u);
   if ((old >> 8) != 1u) return;
   const uint32_t bits = (old & 0xffu) | mine;
-  float er = 0.f, eg = 0.f, eb = 0.f;
-  for (int k = 0; k < sc.num_lights; ++k) {
-    if (!((bits >> k) & 1u)) continue;
-    const float lx = sc.lpos[k][0] - pos.x, ly = sc.lpos[k][1] - pos.y, lz = sc.lpos[k][2] - pos.z;
-    const float d2 = lx * lx + ly * ly + lz * lz;
-    const float cs = (nrm.x * lx + nrm.y * ly + nrm.z * lz) / sqrtf(d2);
-    const float wl = fmaxf(cs, 0.0f) / d2;
-    er = fmaf(sc.lint[k][0], wl, er);
-    eg = fmaf(sc.lint[k][1], wl, eg);
-    eb = fmaf(sc.lint[k][2], wl, eb);
-  }
   const int id = __float_as_int(nrm.w);
-  const float4 rho = v.albedo[id];
-  const float inv_pi = 0.318309886183790671538f;
-  const float3 L = make_float3(rho.x * inv_pi * er, rho.y * inv_pi * eg, rho.z * inv_pi * eb);
-  emit_ray<KIND>(v, KIND == KIND_PRIMARY ? v.hit_dst[r] : r, L, pos.w, id, bits);
+  emit_ray<KIND>(v, KIND == KIND_PRIMARY ? v.hit_dst[r] : r, lit_radiance(v, sc, pos, nrm, id, bits), pos.w, id,
+                 bits);
 }
 
 template <int KIND, bool COUNT, bool W4>
@@ -854,6 +902,93 @@ __global__ __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_shade_kernel(Vo
   for (uint32_t q = blockIdx.x * waves + (uint32_t)wave; q < nq; q += gridDim.x * waves)
     shade_batch<KIND, COUNT, W4>(v, st, q, T, nb, w);
   flush_stats<COUNT, true>(v, w, 0u);
+}
+
+// ---- fused pilot kernel
+// Pilot passes are small (8 rays per probe) and their waves end unevenly, so
+// a wave traces a batch's shadow rays itself, right after the batch's
+// closest hits, with no pair list in global memory, no scan and no second
+// launch. The batch's (ray, light) pairs go to the wave's LDS in the order
+// the two-kernel form lists them (all pairs of light 0 in lane order, then
+// light 1, ...); pair k is traced by lane k mod 64 in round k / 64 and ORs
+// its light's bit into its ray's LDS visibility word when unblocked. A ray's
+// outputs are those of the two-kernel form: the same hit, the same shadow
+// rays, the same light order in its radiance sum. One wave per workgroup;
+// its LDS holds the traversal stack, then the pair list (64 kMaxLights
+// 16-bit entries), then the 64 visibility words.
+constexpr size_t kPilotLdsWave = (size_t)kStackLds * 64 * 8 + 64 * kMaxLights * 2 + 64 * 4;
+
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int KIND, bool COUNT, bool W4>
+__device__ __forceinline__ void fused_batch(const VolumeView& v, Stack& st, lds_u16* pairs, lds_u32* vis, uint32_t b,
+                                            uint32_t total, Work& w, Work& ws, uint32_t& shadow) {
+  const SceneParams& sc = *v.scene;
+  const uint32_t lane = lane_id(), r0 = b * v.batch_rays;
+  uint32_t need, dst;
+  {
+    const BatchHit h = closest_of_batch<KIND, COUNT, W4>(v, st, b, total, w);
+    need = h.need;
+    dst = h.dst;
+    if (need) {
+      v.hit_pos[r0 + lane] = make_float4(h.x.x, h.x.y, h.x.z, h.t);
+      v.hit_nrm[r0 + lane] = make_float4(h.n.x, h.n.y, h.n.z, __int_as_float(h.id));
+    } else if (h.active) {
+      emit_unshadowed<KIND>(v, h);
+    }
+  }
+  vis[lane] = 0u;
+  uint32_t n = 0u;
+  for (int l = 0; l < sc.num_lights; ++l) {
+    const bool p = (need >> l) & 1u;
+    const uint64_t m = ballot(p);
+    if (p) pairs[n + lanes_below(m)] = (uint16_t)(lane | ((uint32_t)l << 6));
+    n += (uint32_t)__popcll(m);
+  }
+  shadow += n;
+  wave_sync();
+  for (uint32_t k = lane; k < n; k += 64u) {
+    const uint32_t e = pairs[k];
+    const uint32_t r = r0 + (e & 63u), l = e >> 6;
+    if (!shadow_blocked<COUNT, W4>(v, sc, v.hit_pos[r], v.hit_nrm[r], l, st, ws)) atomicOr((uint32_t*)&vis[e & 63u], 1u << l);
+  }
+  wave_sync();
+  const uint32_t bits = vis[lane];
+  wave_sync();  // the next batch rewrites the pair list and the words
+  if (!need) return;
+  const uint32_t r = r0 + lane;
+  const float4 pos = v.hit_pos[r], nrm = v.hit_nrm[r];
+  const int id = __float_as_int(nrm.w);
+  emit_ray<KIND>(v, dst, lit_radiance(v, sc, pos, nrm, id, bits), pos.w, id, bits);
+}
+
+template <int KIND, bool COUNT, bool W4>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_fused_kernel(VolumeView v,
+                                                                                                  int persistent) {
+  extern __shared__ uint64_t smem[];
+  uint64_t deep[kStackMax - kStackLds];
+  Stack st;
+  st.lds = (lds_u64*)smem + lane_id();
+  st.sp = 0;
+  st.deep = deep;
+  lds_u16* pairs = (lds_u16*)((lds_u64*)smem + 64 * kStackLds);
+  lds_u32* vis = (lds_u32*)(pairs + 64 * kMaxLights);
+  const uint32_t total = ray_total<KIND>(v);
+  const uint32_t nbatch = (total + v.batch_rays - 1u) / v.batch_rays;
+  const uint32_t stride = persistent ? gridDim.x : nbatch;
+  Work w, ws;
+  uint32_t shadow = 0u;
+  for (uint32_t b = blockIdx.x; b < nbatch; b += stride)
+    fused_batch<KIND, COUNT, W4>(v, st, pairs, vis, b, total, w, ws, shadow);
+  flush_stats<COUNT, false>(v, w, shadow);
+  flush_stats<COUNT, true>(v, ws, 0u);
 }
 
 size_t trace_lds_bytes(int block) { return (size_t)kStackLds * block * 8; }
@@ -886,8 +1021,12 @@ static hipError_t launch_trace_w(const VolumeView& v, hipStream_t s, bool pilot,
                                  int shade_grid, bool count, bool chain, hipEvent_t between) {
   if (chain && count) return launch_kind<KIND_CHAIN, true, W4>(v, s, pers, block, grid, shade_grid, between);
   if (chain) return launch_kind<KIND_CHAIN, false, W4>(v, s, pers, block, grid, shade_grid, between);
-  if (pilot && count) return launch_kind<KIND_PILOT, true, W4>(v, s, pers, block, grid, shade_grid, between);
-  if (pilot) return launch_kind<KIND_PILOT, false, W4>(v, s, pers, block, grid, shade_grid, between);
+  if (pilot) {  // one wave per workgroup, as many waves as the closest-hit launch would have
+    const dim3 waves((unsigned)grid * (unsigned)(block / 64));
+    if (count) hipLaunchKernelGGL((trace_fused_kernel<KIND_PILOT, true, W4>), waves, dim3(64), kPilotLdsWave, s, v, pers);
+    else hipLaunchKernelGGL((trace_fused_kernel<KIND_PILOT, false, W4>), waves, dim3(64), kPilotLdsWave, s, v, pers);
+    return hipGetLastError();
+  }
   if (count) return launch_kind<KIND_PRIMARY, true, W4>(v, s, pers, block, grid, shade_grid, between);
   return launch_kind<KIND_PRIMARY, false, W4>(v, s, pers, block, grid, shade_grid, between);
 }

@@ -263,15 +263,16 @@ bool use_bvh4(const adgi_volume* vol, const adgi_tuning& t) {
   return t.bvh_width == 4 && vol->d_nodes4 != nullptr;
 }
 
-// Rays per wave of the pilot pass (8 P rays): 64, or 32 / 16 while 64 would
-// give the CUs fewer than 8 waves each and the pair lists have room for the
-// extra batches. Which lane traces which ray changes no result.
+// Rays per wave of the pilot pass (8 P rays): 64, halved while the pass
+// would have fewer batches than the trace launch has resident waves (down to
+// one ray per wave). A small pilot pass lasts as long as its slowest wave, so
+// it is spread over every wave the launch holds. Which lane traces which ray
+// changes no result.
 uint32_t pilot_batch_rays(const adgi_volume* vol) {
-  const uint64_t total = 8ull * (uint64_t)vol->P, cap = ((uint64_t)vol->v.hit_cap + 63u) / 64u;
+  const uint64_t total = 8ull * (uint64_t)vol->P;
+  const uint64_t waves = (uint64_t)vol->num_cus * (uint64_t)std::max(1, vol->tun.trace_waves_per_cu);
   uint32_t br = 64u;
-  while (br > 16u && (total + br - 1u) / br < 8ull * (uint64_t)vol->num_cus &&
-         (total + br / 2u - 1u) / (br / 2u) <= cap)
-    br /= 2u;
+  while (br > 1u && (total + br - 1u) / br < waves) br /= 2u;
   return br;
 }
 
