@@ -109,6 +109,8 @@ struct RefitView {
   int32_t num_leaf_slots;
   float* tri_box;              // [T][6] each triangle slot's box, kept from refit to refit
   const int32_t* range;        // [2] on the device: the vertex range this refit moves
+  int2* slot_vrange;           // [T] least and greatest vertex index of each triangle slot
+  int2* leaf_vrange;           // [num_leaf_slots] the same over each leaf slot's triangles
 };
 // Refit plan of a BVH2: the internal nodes at depth >= cut are grouped, in
 // every level, by their ancestor at depth `cut` (one subtree per workgroup,
@@ -124,6 +126,9 @@ struct RefitPlan {
 };
 // level_offsets[d] .. level_offsets[d+1] index level_nodes for depth d
 hipError_t launch_refit(const RefitView& r, const std::vector<int32_t>& level_offsets, hipStream_t s);
+// The vertex-index ranges of the triangle and leaf slots, once per build
+// (indices and tri_order uploaded, in stream order).
+hipError_t launch_refit_ranges(const RefitView& r, hipStream_t s);
 // Copy refitted BVH2 child boxes into the BVH4 nodes (one thread per slot).
 hipError_t launch_bvh4_gather(float4* nodes4, const int32_t* src, int num_nodes4, const float4* nodes2,
                               hipStream_t s);

@@ -1,9 +1,12 @@
 // refit.hip - device BVH refit after vertex motion (same topology).
 //
-// 1. Every triangle record (v0, e1, e2) and triangle box is rebuilt from the
-//    current positions (a thread per triangle), then every leaf child slot
-//    gets the (padded) union of its leaf's triangle boxes (a thread per leaf
-//    slot; a leaf's triangles are contiguous).
+// 1. Every triangle record (v0, e1, e2) and triangle box with a vertex in
+//    the moved range is rebuilt from the current positions (a thread per
+//    triangle slot), then every leaf child slot holding such a triangle gets
+//    the (padded) union of its leaf's triangle boxes (a thread per leaf slot;
+//    a leaf's triangles are contiguous). The least and greatest vertex index
+//    of every triangle slot and leaf slot, set once per build, rule out the
+//    others without reading their triangles.
 // 2. The internal child slots, from the deepest internal nodes to the root:
 //    the union of the child's two slots, which a deeper level finished. The
 //    levels below a cut depth run in one launch, one workgroup per subtree
@@ -15,6 +18,7 @@
 #include "adgi_internal.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 
 namespace adgi {
@@ -27,15 +31,22 @@ __device__ __forceinline__ void write_tri(const RefitView& r, int s, int t, cons
   r.tris[3 * (size_t)s + 2] = make_float4(v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2], 0.f);
 }
 
+// Whether [lo, hi] (a slot's vertex indices lie in it) meets the moved range
+// [vb, ve); when it does not, no vertex of the slot moved.
+__device__ __forceinline__ bool range_meets(int2 vr, int vb, int ve) { return vr.y >= vb && vr.x < ve; }
+
 // Record of triangle slot s and its box (min xyz, max xyz of its vertices),
 // for the triangles with a vertex in this refit's range; the others did not
 // move, and their records and boxes from an earlier refit or the build stand.
+// The slot's vertex-index range, read in slot order, rules out most of them
+// before the triangle's own indices are gathered.
 __global__ void refit_tris_kernel(RefitView r) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= r.num_tris) return;
+  const int vb = r.range[0], ve = r.range[1];
+  if (!range_meets(r.slot_vrange[s], vb, ve)) return;
   const int t = r.tri_order[s];
   const int i0 = r.indices[3 * t], i1 = r.indices[3 * t + 1], i2 = r.indices[3 * t + 2];
-  const int vb = r.range[0], ve = r.range[1];
   if (!((i0 >= vb && i0 < ve) || (i1 >= vb && i1 < ve) || (i2 >= vb && i2 < ve))) return;
   const float* p[3] = {r.positions + 3 * (size_t)i0, r.positions + 3 * (size_t)i1, r.positions + 3 * (size_t)i2};
   write_tri(r, s, t, p[0], p[1], p[2]);
@@ -96,13 +107,47 @@ __device__ __forceinline__ void refit_node(const RefitView& r, int g) {
   }
 }
 
-// Every leaf child slot (entry 2g + side of leaf_slots), all independent.
+// Every leaf child slot (entry 2g + side of leaf_slots) with a triangle that
+// has a vertex in the moved range, all independent; the others keep their
+// bounds, which their unchanged triangle boxes would give again.
 __global__ void refit_leaves_kernel(RefitView r) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < r.num_leaf_slots) {
+  if (q < r.num_leaf_slots && range_meets(r.leaf_vrange[q], r.range[0], r.range[1])) {
     const int e = r.leaf_slots[q];
     refit_leaf_slot(r, e >> 1, e & 1);
   }
+}
+
+__global__ void slot_vrange_kernel(RefitView r) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= r.num_tris) return;
+  const int t = r.tri_order[s];
+  const int i0 = r.indices[3 * t], i1 = r.indices[3 * t + 1], i2 = r.indices[3 * t + 2];
+  r.slot_vrange[s] = make_int2(min(min(i0, i1), i2), max(max(i0, i1), i2));
+}
+
+__global__ void leaf_vrange_kernel(RefitView r) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= r.num_leaf_slots) return;
+  const int e = r.leaf_slots[q];
+  const int* meta = (const int*)(r.nodes + 4 * (size_t)(e >> 1) + 3);
+  const int code = ~meta[e & 1];
+  const int first = code >> kLeafShift, count_t = (code & (kLeafMaxTris - 1)) + 1;
+  int2 vr = make_int2(INT_MAX, -1);
+  for (int k = 0; k < count_t; ++k) {
+    const int2 t = r.slot_vrange[first + k];
+    vr.x = min(vr.x, t.x);
+    vr.y = max(vr.y, t.y);
+  }
+  r.leaf_vrange[q] = vr;
+}
+
+hipError_t launch_refit_ranges(const RefitView& r, hipStream_t s) {
+  if (r.num_tris == 0) return hipSuccess;
+  hipLaunchKernelGGL(slot_vrange_kernel, dim3((r.num_tris + 255) / 256), dim3(256), 0, s, r);
+  if (r.num_leaf_slots > 0)
+    hipLaunchKernelGGL(leaf_vrange_kernel, dim3((r.num_leaf_slots + 255) / 256), dim3(256), 0, s, r);
+  return hipGetLastError();
 }
 
 __global__ void refit_level_kernel(RefitView r, const int32_t* __restrict__ nodes_of_level, int count) {

@@ -170,6 +170,8 @@ struct adgi_volume {
   int32_t* d_refit_tab = nullptr;                    // RefitPlan::tab
   int32_t* d_leaf_slots = nullptr;                   // RefitPlan::leaf_slots
   float* d_tri_box = nullptr;                        // refit scratch: triangle boxes
+  int2* d_slot_vr = nullptr;                         // vertex-index range per triangle slot
+  int2* d_leaf_vr = nullptr;                         // vertex-index range per leaf slot
   int32_t refit_cut = 0, refit_subtrees = 0, refit_deep = 0, num_leaf_slots = 0;
   hipGraphExec_t refit_exec = nullptr;
   bool refit_all = true;  // the next refit rebuilds every triangle (none since the build)
@@ -479,6 +481,7 @@ void free_scene(adgi_volume* vol) {
   vol->d_pos = nullptr;
   vol->d_idx = vol->d_order = vol->d_levels = vol->d_refit_tab = vol->d_leaf_slots = nullptr;
   vol->d_tri_box = nullptr;
+  vol->d_slot_vr = vol->d_leaf_vr = nullptr;
   vol->level_offsets.clear();
   vol->refit_cut = vol->refit_subtrees = vol->refit_deep = vol->num_leaf_slots = 0;
   vol->d_nodes = vol->d_tris = vol->d_albedo = nullptr;
@@ -966,6 +969,16 @@ bool build_scene(const adgi_volume_desc& d, const adgi_scene_desc* sc, BuiltScen
   return true;
 }
 
+// The refit's view of the volume's scene buffers (its moved vertex range is
+// read from the scene constants on the device).
+RefitView refit_view(adgi_volume* vol) {
+  return RefitView{vol->d_pos,       vol->d_idx,        vol->d_order,          vol->d_tris,
+                   vol->d_nodes,     vol->d_levels,     vol->nt,               vol->num_nodes,
+                   vol->pad_abs,     vol->d_refit_tab,  vol->refit_cut,        vol->refit_subtrees,
+                   vol->refit_deep,  vol->d_leaf_slots, vol->num_leaf_slots,   vol->d_tri_box,
+                   &vol->v.scene->refit_vb, vol->d_slot_vr, vol->d_leaf_vr};
+}
+
 adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const BuiltScene* prebuilt) {
   if (!vol || !sc) return fail(ADGI_ERR_INVALID_ARG, "volume and scene must not be NULL");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
@@ -1052,6 +1065,8 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     vol->d_refit_tab = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.tab.size(), 1) * 4, &g);
     vol->d_leaf_slots = (int32_t*)vol_alloc(vol, std::max<size_t>(plan.leaf_slots.size(), 1) * 4, &g);
     vol->d_tri_box = (float*)vol_alloc(vol, (size_t)std::max(nt, 1) * 24, &g);
+    vol->d_slot_vr = (int2*)vol_alloc(vol, (size_t)std::max(nt, 1) * 8, &g);
+    vol->d_leaf_vr = (int2*)vol_alloc(vol, std::max<size_t>(plan.leaf_slots.size(), 1) * 8, &g);
     vol->d_nodes = (float4*)vol_alloc(vol, bvh.nodes.size() * 16, &g);
     vol->d_tris = (float4*)vol_alloc(vol, std::max<size_t>(bvh.tris.size(), 3) * 16, &g);
     vol->d_albedo = (float4*)vol_alloc(vol, (size_t)std::max(nt, 1) * 16, &g);
@@ -1060,7 +1075,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
       vol->d_src4 = (int32_t*)vol_alloc(vol, bvh4.src.size() * 4, &g);
     }
     if (!vol->d_pos || !vol->d_idx || !vol->d_order || !vol->d_levels || !vol->d_refit_tab ||
-        !vol->d_leaf_slots || !vol->d_tri_box || !vol->d_nodes ||
+        !vol->d_leaf_slots || !vol->d_tri_box || !vol->d_slot_vr || !vol->d_leaf_vr || !vol->d_nodes ||
         !vol->d_tris || !vol->d_albedo || (fits4 && (!vol->d_nodes4 || !vol->d_src4))) {
       free_scene(vol);
       vol->has_scene = false;
@@ -1121,6 +1136,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     vol->num_big = bvh.num_big;
     // the build leaves no triangle boxes: the first refit computes them all
     vol->refit_all = true;
+    HIP_TRY(vol, launch_refit_ranges(refit_view(vol), ss));
     HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.scene, vol->h_scene, sizeof(SceneParams), hipMemcpyHostToDevice, ss));
   } else {
     hp.num_nodes = vol->num_nodes;
@@ -1141,11 +1157,7 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
     if (cnt) {
       // the refit is captured once per build
       if (!vol->refit_exec) {
-        RefitView r{vol->d_pos,   vol->d_idx,     vol->d_order,         vol->d_tris,
-                    vol->d_nodes, vol->d_levels,  vol->nt,              vol->num_nodes,
-                    vol->pad_abs, vol->d_refit_tab, vol->refit_cut, vol->refit_subtrees,
-                    vol->refit_deep,  vol->d_leaf_slots, vol->num_leaf_slots, vol->d_tri_box,
-                    &vol->v.scene->refit_vb};
+        const RefitView r = refit_view(vol);
         hipGraph_t graph = nullptr;
         HIP_TRY(vol, hipStreamBeginCapture(ss, hipStreamCaptureModeRelaxed));
         hipError_t e = launch_refit(r, vol->level_offsets, ss);
