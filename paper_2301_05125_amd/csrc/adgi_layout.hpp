@@ -19,6 +19,7 @@ constexpr int kPairsPerBatch = 64 * kMaxLights;  // shadow pairs of one 64-ray b
 constexpr int kPairScanPer = 1024;               // batches per block of the pair-count scan
 constexpr int kAllocCandidates = 256;           // per k-ary search pass (m = 1..255)
 constexpr int kAllocPasses = 4;                 // 2^31+1 -> 1 in four 256-ary steps
+constexpr int kLamLine = 16;                    // lambda-pass sums: one per 128-byte line (uint64 stride)
 constexpr int kStackLds = 7;                    // traversal stack entries kept in LDS
 constexpr int kOrderBuckets = 32;               // blend order: 64-ray chunks per probe, capped
 constexpr int kStackMax = 64;                   // BVH depth bound enforced by the builder
@@ -114,7 +115,6 @@ struct FrameStats {
   int64_t remainder;        // R = B' - sum e_i(lambda*)
   uint32_t bucket_count[kOrderBuckets];   // probes per ray-chunk bucket
   uint32_t bucket_cursor[kOrderBuckets];  // scatter cursors
-  uint64_t sums[4][kAllocCandidates];
 };
 
 // Everything a kernel needs, passed by value.
@@ -180,6 +180,7 @@ struct VolumeView {
   int32_t* dbg_ptri;          // [8P] pilot closest triangle (debug)
   uint8_t* dbg_pshadow;       // [8P] pilot shadow bits (debug)
   uint32_t* batch_probe;      // [max_rays / 64] budgeted frames: the probe of ray 64 b
+  uint64_t* lam_sums;         // [kAllocPasses][kAllocCandidates] candidate sums, kLamLine apart
   uint32_t* ray_bins;         // [max_rays] probe rays: interior irradiance texel
                               // | interior depth texel << 16 of the direction
   // lit hits waiting for their shadow rays (the pilot and probe passes of a

@@ -34,14 +34,14 @@ __device__ __forceinline__ uint32_t extra_rays(uint32_t lambda, uint32_t w, uint
 // a pass is kept when it lies in the interval and its sum fits the budget,
 // and since the sums grow with m the kept candidates are m = 1..m_best, so
 // m_best is their count.
-__device__ void replay_interval(const FrameStats* st, int passes, int64_t Bp, uint32_t& lo, uint32_t& hi) {
+__device__ void replay_interval(const uint64_t* sums, int passes, int64_t Bp, uint32_t& lo, uint32_t& hi) {
   lo = 0u;
   hi = 1u << 31;
   const int m = (int)threadIdx.x;
   for (int p = 0; p < passes; ++p) {
     const uint32_t step = (uint32_t)(((uint64_t)hi - lo + 1 + kAllocCandidates - 1) / kAllocCandidates);
     const uint64_t c = (uint64_t)lo + (uint64_t)m * step;
-    const bool keep = m >= 1 && m < kAllocCandidates && c <= hi && (int64_t)st->sums[p][m] <= Bp;
+    const bool keep = m >= 1 && m < kAllocCandidates && c <= hi && (int64_t)sums[(p * kAllocCandidates + m) * kLamLine] <= Bp;
     const int m_best = __syncthreads_count(keep);
     const uint64_t nlo = (uint64_t)lo + (uint64_t)m_best * step;
     const uint64_t nxt = nlo + step;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void lambda_pass_kernel(VolumeView v, int pass
   const int64_t Bp = fp.budget - (int64_t)v.P * fp.n_min;
   const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
   uint32_t lo, hi;
-  replay_interval(v.stats, pass, Bp, lo, hi);
+  replay_interval(v.lam_sums, pass, Bp, lo, hi);
   const uint64_t maxs = v.stats->max_score;
   const int i = blockIdx.x * 256 + threadIdx.x;
   w_s[threadIdx.x] = i < v.P ? weight_of((uint64_t)v.score[i], maxs) : 0u;
@@ -88,7 +88,9 @@ __global__ __launch_bounds__(256) void lambda_pass_kernel(VolumeView v, int pass
   uint32_t sum = 0;
   const int cnt = min(256, v.P - blockIdx.x * 256);
   for (int k = 0; k < cnt; ++k) sum += extra_rays(lam, w_s[k], E);
-  if (sum) atomicAdd((unsigned long long*)&v.stats->sums[pass][m], (unsigned long long)sum);
+  // each candidate's sum on a cache line of its own: the blocks' atomics on
+  // neighbouring candidates do not queue on one line
+  if (sum) atomicAdd((unsigned long long*)&v.lam_sums[(pass * kAllocCandidates + m) * kLamLine], (unsigned long long)sum);
 }
 
 // Block-wide exclusive scan (blockDim multiple of 64, <= 1024).
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void alloc_blocks_kernel(VolumeView v) {
   const int64_t Bp = fp.budget - (int64_t)v.P * fp.n_min;
   const uint32_t E = (uint32_t)(fp.n_max - fp.n_min);
   uint32_t lam, hi;
-  replay_interval(v.stats, kAllocPasses, Bp, lam, hi);
+  replay_interval(v.lam_sums, kAllocPasses, Bp, lam, hi);
   const int i = blockIdx.x * 256 + threadIdx.x;
   int64_t e0 = 0;
   uint32_t el = 0;

@@ -18,7 +18,7 @@ namespace adgi {
 __global__ void frame_begin_kernel(VolumeView v) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   FrameStats* st = v.stats;
-  if (tid < 4 * kAllocCandidates) (&st->sums[0][0])[tid] = 0ull;
+  if (tid < kAllocPasses * kAllocCandidates) v.lam_sums[(size_t)tid * kLamLine] = 0ull;
   if (tid < kOrderBuckets) {
     st->bucket_count[tid] = 0u;
     st->bucket_cursor[tid] = 0u;

@@ -679,6 +679,7 @@ template <class F>
 void frame_scratch_each(VolumeView& v, size_t P, size_t R, size_t H, F&& f) {
   const size_t pb = (P + 255) / 256, nb = (H + 63) / 64;
   f((void**)&v.stats, sizeof(FrameStats));
+  f((void**)&v.lam_sums, (size_t)kAllocPasses * kAllocCandidates * kLamLine * 8);
   f((void**)&v.box_a, P * 64);
   f((void**)&v.box_b, P * 64);
   f((void**)&v.blk_e, pb * 8);
