@@ -387,10 +387,13 @@ const char* adgi_last_error(void);
 typedef struct {
   int32_t use_graph;          /* 1: capture the frame as a hipGraph; 0: eager     */
   int32_t persistent;         /* 1: persistent traversal, a fixed grid whose waves
-                                 take 64-ray batches by grid stride (no shared
-                                 counter); 0: one thread per ray, grid sized to
-                                 the rays                                         */
-  int32_t trace_block;        /* threads per traversal workgroup: 64..1024, x64   */
+                                 take ray batches by grid stride (no shared
+                                 counter): 64 rays, fewer in a pilot pass too
+                                 small to fill the grid; 0: one thread per ray,
+                                 grid sized to the rays                           */
+  int32_t trace_block;        /* threads per traversal workgroup: 64..1024, x64
+                                 (the fused pilot kernel runs the same number of
+                                 waves, one per workgroup)                        */
   int32_t trace_waves_per_cu; /* persistent grid = CUs * this / (block/64), 1..32 */
   int32_t blend_chunk;        /* 0: wave-per-probe blend (tiles 8/16 or 16/16),
                                  probes taken in most-rays-first order;
