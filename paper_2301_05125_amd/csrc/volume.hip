@@ -801,9 +801,11 @@ adgi_status adgi_create_volume(const adgi_volume_desc* d, const adgi_allocator* 
   vol->stream = vol->own_stream;
   vol->scene_stream = vol->own_scene;
   for (auto& e : vol->ev_bind) CREATE_TRY(take_event(false, &e));
-  for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_t0, &vol->ev_t1, &vol->ev_stage})
-    CREATE_TRY(take_event(true, e));
-  for (hipEvent_t* e : {&vol->ev_traced, &vol->ev_refit}) CREATE_TRY(take_event(false, e));
+  // events that only order work carry no timestamps (a timing event's record
+  // is a heavier packet, and a wait on one across queues starts later)
+  for (hipEvent_t* e : {&vol->ev_t0, &vol->ev_t1}) CREATE_TRY(take_event(true, e));
+  for (hipEvent_t* e : {&vol->ev_user, &vol->ev_done, &vol->ev_stage, &vol->ev_traced, &vol->ev_refit})
+    CREATE_TRY(take_event(false, e));
   for (auto& e : vol->ev_slot) CREATE_TRY(take_event(false, &e));
   for (auto& e : vol->ev_k) CREATE_TRY(take_event(true, &e));
   CREATE_TRY(pinned_alloc((void**)&vol->h_fp, sizeof(FrameParams) * kParamSlots));
@@ -1524,7 +1526,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
   vol->frame_now = p->frame;
   HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.fp, &fp, sizeof(FrameParams), hipMemcpyHostToDevice, vol->stream));
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
-  HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));
+  if (p->sync) HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));  // ms_total
   if (use_static) {
     // one static frame at a time per device: each waits on the GPU for the
     // previous one's blend, so frames of different volumes never share the
@@ -1590,7 +1592,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
   } else {
     HIP_TRY(vol, enqueue_frame(vol, mode, p->sync ? vol->ev_k : nullptr, false, vol->ev_traced));
   }
-  HIP_TRY(vol, hipEventRecord(vol->ev_t1, vol->stream));
+  if (p->sync) HIP_TRY(vol, hipEventRecord(vol->ev_t1, vol->stream));
   vol->last_frame = p->frame;
   vol->last_adaptive = p->adaptive;
   std::memcpy(vol->last_R, fp.R, sizeof(vol->last_R));
