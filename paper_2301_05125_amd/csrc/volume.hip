@@ -175,6 +175,7 @@ struct adgi_volume {
   int32_t refit_cut = 0, refit_subtrees = 0, refit_deep = 0, num_leaf_slots = 0;
   hipGraphExec_t refit_exec = nullptr;
   bool refit_all = true;  // the next refit rebuilds every triangle (none since the build)
+  bool scene_pending = false;  // the frame stream has not yet been made to wait for ev_refit
   float4* d_nodes = nullptr;
   float4* d_nodes4 = nullptr;   // BVH4 collapse (null when its stack bound does not fit)
   int32_t* d_src4 = nullptr;    // BVH4 slot -> BVH2 slot, for the refit gather
@@ -363,13 +364,26 @@ hipError_t enqueue_frame(adgi_volume* vol, int mode, hipEvent_t* ev = nullptr,
   return mark(6);
 }
 
-adgi_status order_after_user(adgi_volume* vol) {
+// A scene update leaves the frame stream's wait for its refit to the next
+// call that reads the scene there. A frame adds it after its parameter
+// upload, which reads no scene data, so the upload is not held behind the
+// refit's completion on the other queue (a wait across queues starts tens of
+// microseconds after the event).
+adgi_status follow_scene(adgi_volume* vol) {
+  if (vol->scene_pending) {
+    HIP_TRY(vol, hipStreamWaitEvent(vol->stream, vol->ev_refit, 0));
+    vol->scene_pending = false;
+  }
+  return ADGI_OK;
+}
+
+adgi_status order_after_user(adgi_volume* vol, bool scene = true) {
   if (vol->user_stream) {
     HIP_TRY(vol, hipEventRecord(vol->ev_user, vol->user_stream));
     HIP_TRY(vol, hipStreamWaitEvent(vol->stream, vol->ev_user, 0));
     HIP_TRY(vol, hipStreamWaitEvent(vol->scene_stream, vol->ev_user, 0));
   }
-  return ADGI_OK;
+  return scene ? follow_scene(vol) : ADGI_OK;
 }
 
 // `scene_free`: everything queued so far may read the scene, so a later
@@ -1187,7 +1201,10 @@ adgi_status update_scene_impl(adgi_volume* vol, const adgi_scene_desc* sc, const
   HIP_TRY(vol, hipEventRecord(vol->ev_stage, ss));
   // every later use of the volume's stream follows the new scene
   HIP_TRY(vol, hipEventRecord(vol->ev_refit, ss));
-  HIP_TRY(vol, hipStreamWaitEvent(vol->stream, vol->ev_refit, 0));
+  // every later call that reads the scene on the frame stream waits for it
+  // (follow_scene); the caller's stream waits for it now
+  vol->scene_pending = true;
+  if (vol->user_stream) HIP_TRY(vol, hipStreamWaitEvent(vol->user_stream, vol->ev_refit, 0));
   vol->has_scene = true;
   return order_user_after(vol);
 }
@@ -1476,7 +1493,7 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
     sview.hit_cap = (uint32_t)Hc;
   }
 
-  adgi_status st = order_after_user(vol);
+  adgi_status st = order_after_user(vol, false);  // the scene is followed after the parameter upload
   if (st != ADGI_OK) return st;
   // parameter block into the next pinned slot
   const int slot = vol->slot;
@@ -1525,6 +1542,8 @@ adgi_status update_impl(adgi_volume* vol, const adgi_update_params* p, adgi_upda
   }
   vol->frame_now = p->frame;
   HIP_TRY(vol, hipMemcpyAsync((void*)vol->v.fp, &fp, sizeof(FrameParams), hipMemcpyHostToDevice, vol->stream));
+  st = follow_scene(vol);
+  if (st != ADGI_OK) return st;
   HIP_TRY(vol, hipEventRecord(vol->ev_slot[slot], vol->stream));
   if (p->sync) HIP_TRY(vol, hipEventRecord(vol->ev_t0, vol->stream));  // ms_total
   if (use_static) {
@@ -1885,6 +1904,7 @@ adgi_status adgi_measure_trace_work(adgi_volume* vol, const adgi_update_params* 
   if (!vol || !p || !out) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "measure before update_scene");
+  if (follow_scene(vol) != ADGI_OK) return ADGI_ERR_DEVICE;
   std::vector<uint8_t> snap(adgi_state_size(vol));
   adgi_status st = adgi_save_state(vol, snap.data(), snap.size());
   if (st != ADGI_OK) return st;
@@ -1924,6 +1944,7 @@ adgi_status adgi_autotune(adgi_volume* vol, const adgi_update_params* p, adgi_tu
   if (!vol || !p) return fail(ADGI_ERR_INVALID_ARG, "NULL argument");
   if (vol->sticky) return fail(ADGI_ERR_DEVICE, "volume has a sticky device error");
   if (!vol->has_scene) return fail(ADGI_ERR_NO_SCENE, "autotune before update_scene");
+  if (follow_scene(vol) != ADGI_OK) return ADGI_ERR_DEVICE;
   if (p->adaptive == ADGI_MODE_CHAIN)
     return fail(ADGI_ERR_INVALID_ARG, "autotune takes a uniform or budgeted frame (chain frames reuse its shapes)");
   const TuneKey key{vol->device, 32 - __builtin_clz((unsigned)vol->P), vol->desc.irr_res * 64 + vol->desc.depth_res,
